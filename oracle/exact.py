@@ -1,0 +1,192 @@
+"""Pure-Python exact checkers for the F2M optimum (Sec. 4).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+* brute_force_opt2: enumerates every x in {0, 1/2, 1}^E with all degrees
+  equal to 2 (backtracking with degree pruning), valid because some optimal
+  vertex of F2M is half-integral (Sec. 4, Edmonds).  Practical for n <= 7.
+* simplex_opt2: exact-rational bounded-variable primal simplex (Bland's rule)
+  on   min c.x  s.t.  sum_{e in delta(v)} x_e = 2,  0 <= x <= 1,
+  with a phase 1 on artificial variables.  Practical for n <= ~40.
+
+Both return 2 * optimum as an int (the optimum is a multiple of 1/2) and use
+math.isqrt for the EUC_2D length, independently of the C oracle.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+
+def euc2d(xy, u, v) -> int:
+    """nint(sqrt(D)): the k with (2k-1)^2 <= 4D < (2k+1)^2."""
+    dx = int(xy[u][0]) - int(xy[v][0])
+    dy = int(xy[u][1]) - int(xy[v][1])
+    D = dx * dx + dy * dy
+    r = math.isqrt(4 * D)          # floor(2 sqrt D)
+    return (r + 1) // 2
+
+
+def edges_of(n):
+    return [(u, v) for u in range(n) for v in range(u + 1, n)]
+
+
+def brute_force_opt2(xy):
+    """2 * min c.x over x in {0,1/2,1}^E with every degree 2; None if none."""
+    n = len(xy)
+    E = edges_of(n)
+    c = [euc2d(xy, u, v) for (u, v) in E]
+    deg = [0] * n              # doubled degrees so far
+    left = [n - 1] * n         # undecided incident edges per node
+    best = [None]
+    # order edges so each node's edges close early: already lexicographic
+
+    def rec(i, acc):
+        if best[0] is not None and acc >= best[0]:
+            return
+        if i == len(E):
+            if all(d == 4 for d in deg):
+                best[0] = acc
+            return
+        u, v = E[i]
+        left[u] -= 1; left[v] -= 1
+        for x2 in (0, 1, 2):
+            du, dv = deg[u] + x2, deg[v] + x2
+            if du > 4 or dv > 4:
+                continue
+            if du + 2 * left[u] < 4 or dv + 2 * left[v] < 4:
+                continue
+            deg[u], deg[v] = du, dv
+            rec(i + 1, acc + x2 * c[i])
+            deg[u] -= x2; deg[v] -= x2
+        left[u] += 1; left[v] += 1
+
+    rec(0, 0)
+    return best[0]
+
+
+def simplex_opt2(xy, max_pivots=200000):
+    """Exact optimum * 2 by a bounded-variable simplex over Fractions.
+
+    Standard form: rows A x = b (one per node, b = 2), 0 <= x <= 1.  Phase 1
+    adds one artificial per row (x_a >= 0, no upper bound) and minimises
+    their sum; phase 2 minimises c.x.  Nonbasic variables sit at 0 or at
+    their upper bound; entering/leaving by Bland's rule (smallest index)."""
+    n = len(xy)
+    E = edges_of(n)
+    m = len(E)
+    cost = [Fraction(euc2d(xy, u, v)) for (u, v) in E]
+    nv = m + n                     # structural + artificial
+    INF = None
+    ub = [Fraction(1)] * m + [INF] * n
+    # dense tableau rows: B^-1 A, and B^-1 b, kept explicitly
+    A = [[Fraction(0)] * nv for _ in range(n)]
+    for j, (u, v) in enumerate(E):
+        A[u][j] = Fraction(1)
+        A[v][j] = Fraction(1)
+    for i in range(n):
+        A[i][m + i] = Fraction(1)
+    basis = [m + i for i in range(n)]
+    at_upper = [False] * nv
+    xB = [Fraction(2)] * n           # values of basic variables
+
+    def run(obj, allowed):
+        pivots = 0
+        while True:
+            # reduced costs d_j = obj_j - obj_B . column_j
+            cb = [obj[b] for b in basis]
+            entering, direction = None, 0
+            inbasis = set(basis)
+            for j in range(allowed):
+                if j in inbasis:
+                    continue
+                d = obj[j] - sum(cb[i] * A[i][j] for i in range(n) if A[i][j] != 0)
+                if not at_upper[j] and d < 0:
+                    entering, direction = j, +1
+                    break
+                if at_upper[j] and d > 0:
+                    entering, direction = j, -1
+                    break
+            if entering is None:
+                return
+            j = entering
+            # ratio test: moving x_j by t*direction changes x_B by -t*direction*col
+            tmax = ub[j] if ub[j] is not None else None
+            leave, leave_to_upper = None, False
+            for i in range(n):
+                a = A[i][j] * direction
+                if a > 0:            # x_B[i] decreases to 0
+                    t = xB[i] / a
+                    cand = (t, basis[i], i, False)
+                elif a < 0 and ub[basis[i]] is not None:   # increases to its bound
+                    t = (ub[basis[i]] - xB[i]) / (-a)
+                    cand = (t, basis[i], i, True)
+                else:
+                    continue
+                if tmax is None or cand[0] < tmax or (cand[0] == tmax and leave is not None and cand[1] < leave[1]):
+                    tmax = cand[0]
+                    leave = cand
+            if tmax is None:
+                raise RuntimeError("unbounded")
+            t = tmax
+            for i in range(n):
+                xB[i] -= t * direction * A[i][j]
+            if leave is None:          # bound flip of the entering variable
+                at_upper[j] = not at_upper[j]
+            else:
+                _, _, r, to_upper = leave
+                old = basis[r]
+                newval = t if direction > 0 else ub[j] - t
+                piv = A[r][j]
+                A[r] = [a / piv for a in A[r]]
+                for i in range(n):
+                    if i != r and A[i][j] != 0:
+                        f = A[i][j]
+                        A[i] = [a - f * b for a, b in zip(A[i], A[r])]
+                basis[r] = j
+                xB[r] = newval
+                at_upper[j] = False
+                at_upper[old] = to_upper
+            pivots += 1
+            if pivots > max_pivots:
+                raise RuntimeError("pivot limit")
+
+    run([Fraction(0)] * m + [Fraction(1)] * n, nv)
+    art = sum(xB[i] for i in range(n) if basis[i] >= m) + \
+        sum(ub[j] for j in range(m, nv) if at_upper[j] and ub[j] is not None)
+    if art != 0:
+        return None
+    # phase 2: artificials never enter again; a degenerate basic artificial
+    # (value 0) gets upper bound 0 so that it leaves rather than grows
+    for i in range(n):
+        ub[m + i] = Fraction(0)
+    run(cost + [Fraction(0)] * n, m)
+    x = [Fraction(0)] * m
+    for j in range(m):
+        if at_upper[j]:
+            x[j] = Fraction(1)
+    for i, b in enumerate(basis):
+        if b < m:
+            x[b] = xB[i]
+    val = sum(ci * xi for ci, xi in zip(cost, x))
+    assert (2 * val).denominator == 1
+    return int(2 * val)
+
+
+def highs_opt2(xy):
+    """2 * optimum from scipy's HiGHS LP solver (a library cross-check;
+    the optimum is a half-integer, recovered by rounding 2*fun)."""
+    from scipy.optimize import linprog
+    from scipy.sparse import coo_matrix
+    n = len(xy)
+    E = edges_of(n)
+    c = np.array([euc2d(xy, u, v) for (u, v) in E], dtype=float)
+    m = len(E)
+    rows = np.array([u for u, v in E] + [v for u, v in E])
+    cols = np.concatenate([np.arange(m), np.arange(m)])
+    A = coo_matrix((np.ones(2 * m), (rows, cols)), shape=(n, m)).tocsr()
+    r = linprog(c, A_eq=A, b_eq=2 * np.ones(n), bounds=(0, 1), method="highs")
+    assert r.status == 0
+    return int(round(2 * r.fun))
