@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Benchmark of libf2m on one MI355X: time to a certified F2M optimum and
+pair evaluations per second on the complete graph of n = 100,000 cities with
+integer coordinates uniform in [0, 10^6)^2 (seeded, synthetic).
+
+One step = one full solve on the GPU: the GDP loop (scan, selection, degree
+counts, Lam update, device-side stop test), the exact finish when the
+trivial x does not certify, and the certificate.  Coordinates are resident
+in HBM before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "time-to-certified F2M optimum (s) + pair-evals/s at n=100k; warm vs cold"
+# gfx950 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one fp32 op per lane
+# per clock without packed math
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# the scan's float filter: 3 FMAs and 1 min per ordered pair
+OPS_PER_PAIR = 4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(xy, lam, budget_s):
+    """The oracle's plain per-row GDP pass on a sample of rows of the same
+    instance, scaled to unordered pair evaluations per second."""
+    from oracle import core
+    n = len(xy)
+    rng = np.random.default_rng(0)
+    rows = rng.permutation(n)
+    done, t_used, take = 0, 0.0, 16
+    while t_used < budget_s and done < n:
+        chunk = rows[done:done + take]
+        t0 = time.perf_counter()
+        core.gdp_rows(xy, lam, chunk)
+        t_used += time.perf_counter() - t0
+        done += len(chunk)
+        rate = done / max(t_used, 1e-9)
+        take = int(min(max(16, rate * (budget_s - t_used) * 0.9), n - done)) if t_used < budget_s else 0
+        if take <= 0:
+            break
+    per_iter_s = t_used * n / done
+    pairs = n * (n - 1) / 2
+    return {"value": pairs / per_iter_s, "unit": "pair-evals/s", "cores": core.num_threads(),
+            "kind": "oracle",
+            "sample": "%d of %d rows of one GDP iteration (each row scans all n-1 columns), %.1f s, "
+                      "scaled to a full iteration" % (done, n, t_used)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a device copy of known size (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X and has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel(), "copies": 3}))
+        return
+
+    from paper_2011_08170_amd import f2m, instances
+
+    n = args.n
+    xy = instances.uniform(n, 1_000_000, args.seed)
+    ctx = f2m.Context(0)
+    xy_dev = torch.from_numpy(xy).cuda()
+    torch.cuda.synchronize()
+    log("workload: n=%d uniform [0,1e6)^2 seed=%d; warmup %d, steps %d" % (n, args.seed, args.warmup, args.steps))
+    for i in range(args.warmup):
+        r = ctx.solve(xy_dev)
+        log("warmup %d: %s, %d iterations, %.3f s" % (i, r["status"], r["iterations"], r["seconds"]["total"]))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        r = ctx.solve(xy_dev, time_kernels=True)
+        runs.append(r)
+        log("step %d: %s stop=%s iterations=%d total=%.3f s (gdp %.3f, finish %.3f, certify %.3f)" % (
+            i, r["status"], r["stop"], r["iterations"], r["seconds"]["total"], r["seconds"]["gdp"],
+            r["seconds"]["finish"], r["seconds"]["certify"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    pairs = n * (n - 1) / 2
+    iters = sum(r["iterations"] for r in runs)
+    scan_ms = sum(r["scan_ms"] for r in runs)
+    launches = sum(r["scan_launches"] for r in runs)
+    avg_ms = scan_ms / max(launches, 1)
+    ops = OPS_PER_PAIR * n * (n - 1)
+    achieved = ops / (avg_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": iters * pairs / elapsed,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "F2M GDP, complete graph, n=%d cities uniform integer in [0,10^6)^2, seed %d, "
+                               "cold start" % (n, args.seed),
+                   "n": n, "graph": "complete", "start": "cold"},
+        "time_to_certified_s": elapsed / args.steps,
+        "certified": all(r["certified"] for r in runs),
+        "iterations": [r["iterations"] for r in runs],
+        "stop": [r["stop"] for r in runs],
+        "objective2": runs[-1]["primal2"],
+        "phase_s": {k: float(np.mean([r["seconds"][k] for r in runs])) for k in ("setup", "gdp", "finish", "certify")},
+        "scan_pair_evals_per_s": pairs / (avg_ms * 1e-3),
+        "roofline": {"bound": "alu", "kernel": "k_scan<%d>" % runs[-1]["scan_rows"], "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
+                     "ops_per_launch": ops, "slices": runs[-1]["scan_slices"]},
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(xy, runs[-1]["lambda2_gdp"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * f2m.h -- C ABI of libf2m: the gradient descent procedure (GDP) for the
+ * fractional 2-matching (F2M) LP relaxation of Euclidean TSP, on one
+ * MI355X (gfx950) GPU.
+ *
+ * Method: Antonov, "Gradient descent procedure for solving linear
+ * programming relaxations of combinatorial optimization problems in
+ * parallel mode on extra large scale", arXiv 2011.08170.
+ *   - F2M LP: min c.x, sum_{e in delta(v)} x_e = 2 for every node v,
+ *     0 <= x <= 1 (Sec. 4).
+ *   - Adjusted length v^e = c_e - lambda_u - lambda_v (eq. 9).
+ *   - Gradient of lambda_v from the 2nd and 3rd shortest adjusted edges at
+ *     v (eq. 10); all nodes in parallel (Sec. 5.1).
+ *   - Trivial solution: x_e = 1, 1/2, 0 for v^e <0, =0, >0 (eq. 7, Sec. 4).
+ *   - Output: edges with value 1 and edges with value 1/2 (Sec. 5.1).
+ *
+ * Number formats used throughout:
+ *   coordinates  int32 pairs (x, y), city i at [2i], [2i+1]; each axis span
+ *                must be below 2^20.
+ *   c_e          TSPLIB EUC_2D length nint(sqrt(dx^2 + dy^2)), exact.
+ *   Lam          2*lambda as int64 ("lambda2"); |Lam| must stay below 2^38.
+ *   Z_e          2c_e - Lam_u - Lam_v = twice the adjusted length (eq. 9).
+ *   x2           2*x_e in {1, 2} (1 = one half, 2 = one).
+ *   primal2      2*c.x;  dual2 = 2*L(lambda) = 2*sum Lam + sum_{u<v} min(0, Z).
+ *
+ * GDP rule (rule_version 1, a reading of eq. 10 and Sec. 3): per node
+ *   s = Z_(2) + Z_(3) over the node's edges (2nd and 3rd smallest),
+ *   dLam = sign(s) * floor((|s| + 2) / 4)  (midpoint move damped by 1/2,
+ *   rounded half away from zero), every node from the same Lam (Jacobi).
+ * The loop stops when every trivial degree is 2 ("trivial"), when every
+ * step is 0 ("fixed"), when Lam_k equals Lam_{k-2} by hash ("cycle"), or at
+ * max_iters ("cap").
+ *
+ * Ownership: the caller owns every input.  Host arrays inside f2m_result
+ * are allocated by the library and released by f2m_result_free.  No
+ * exception or abort crosses this ABI; on error the outputs are left
+ * untouched and f2m_last_error(ctx) holds a message.
+ *
+ * Pointers: "device" arguments are HIP device pointers on the context's
+ * device; "host" arguments are ordinary host memory.  Calls on one context
+ * are not thread safe; use one context per host thread.
+ */
+#ifndef F2M_H
+#define F2M_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct f2m_ctx f2m_ctx;
+
+typedef enum f2m_status {
+    F2M_OK = 0,
+    F2M_NOT_CERTIFIED = 1,   /* soft: result returned, optimality not proven */
+    F2M_ERR_ARG = -1,        /* null pointer, bad size, bad option */
+    F2M_ERR_RANGE = -2,      /* coordinate span >= 2^20 on an axis */
+    F2M_ERR_INFEASIBLE = -3, /* n < 3: no degree-2 solution exists */
+    F2M_ERR_NOMEM = -4,      /* host or device allocation failed */
+    F2M_ERR_DEVICE = -5,     /* HIP runtime error */
+    F2M_ERR_CAPACITY = -6,   /* caller buffer too small */
+    F2M_ERR_OVERFLOW = -7    /* |Lam| reached 2^38 */
+} f2m_status;
+
+enum { F2M_GRAPH_COMPLETE = 0 };
+enum { F2M_WARM_COLD = 0, F2M_WARM_USER = 1 };
+enum { F2M_FINISH_NONE = 0, F2M_FINISH_EXACT = 1 };
+enum { F2M_STOP_TRIVIAL = 1, F2M_STOP_FIXED = 2, F2M_STOP_CYCLE = 3, F2M_STOP_CAP = 4 };
+
+/* Per-iteration record, F2M_TRACE_W int64 per iteration k:
+ *   [0] k  [1] dual2 at Lam_k  [2] #nodes with Z_(2) > 0 or Z_(3) < 0
+ *   [3] #nodes whose trivial doubled degree is not 4  [4] max |dLam|
+ *   [5] #nonzero steps  [6] order-free hash of Lam_k (uint64 bits)
+ *   [7] sum of Lam_k */
+#define F2M_TRACE_W 8
+
+typedef struct f2m_opts {
+    uint32_t struct_size;         /* sizeof(f2m_opts) */
+    uint32_t rule_version;        /* must be 1 */
+    int32_t graph;                /* F2M_GRAPH_COMPLETE */
+    int32_t warm;                 /* F2M_WARM_COLD (Lam0 = 0) or F2M_WARM_USER */
+    const int64_t *lambda2_init;  /* host, n entries, read when warm == USER */
+    int64_t max_iters;            /* iteration cap (>= 0) */
+    int32_t finish;               /* F2M_FINISH_EXACT: make the result exact
+                                     when the trivial x does not certify */
+    int32_t coords_on_device;     /* coords_xy argument is a device pointer */
+    int32_t record_trace;         /* fill f2m_result.trace */
+    int32_t chunk;                /* iterations queued between host checks (0: auto) */
+    int32_t time_kernels;         /* time every scan launch with HIP events */
+    void *hip_stream;             /* hipStream_t to run on; NULL: the context's stream */
+} f2m_opts;
+
+typedef struct f2m_result {
+    int64_t n;
+    int64_t iterations;     /* GDP iterations evaluated (records) */
+    int64_t kstar;          /* index of the GDP iterate the finish started from */
+    int32_t stop;           /* F2M_STOP_* */
+    int32_t certified;      /* primal2 == dual2 with a feasible x (complete graph) */
+    int64_t *lambda2;       /* host, n: the final Lam (the certificate's duals) */
+    int64_t *lambda2_gdp;   /* host, n: the GDP iterate Lam_kstar */
+    int64_t n_edges;
+    int32_t *edge_u;        /* host, n_edges, edge_u < edge_v */
+    int32_t *edge_v;
+    uint8_t *edge_x2;       /* 2 = value 1, 1 = value 1/2 */
+    int64_t primal2;        /* 2 c.x of the returned x */
+    int64_t dual2;          /* 2 L(lambda2) on the complete graph */
+    int64_t dual2_gdp;      /* 2 L(lambda2_gdp) */
+    int64_t finish_paths;   /* augmenting paths used by the exact finish */
+    int64_t finish_rounds;  /* pricing rounds of the exact finish */
+    int64_t trace_len;
+    int64_t *trace;         /* host, trace_len * F2M_TRACE_W, or NULL */
+    double seconds[6];      /* setup, (unused), gdp, finish, certify, total */
+    double scan_ms;         /* summed duration of the scan launches (time_kernels) */
+    int64_t scan_launches;  /* scan launches timed */
+    int32_t scan_rows;      /* scan launch shape: rows per lane */
+    int32_t pad0;
+    int64_t scan_slices;    /* scan launch shape: column slices */
+} f2m_result;
+
+/* Fills opts with the defaults: rule 1, complete graph, cold start,
+ * max_iters 100000, exact finish, host coords, no trace, auto chunk. */
+void f2m_opts_default(f2m_opts *opts);
+
+/* Creates a context on HIP device `device` with its own stream. */
+f2m_status f2m_create(f2m_ctx **ctx, int device);
+void f2m_destroy(f2m_ctx *ctx);
+
+/* Full solve of F2M on the complete graph of n cities (Sec. 4, 5.1):
+ * GDP loop, then the trivial x (eq. 7) when every trivial degree is 2, else
+ * (finish == EXACT) a primal-dual finish on the bipartite double cover
+ * started from the GDP multipliers, then the certificate.
+ *   coords_xy  host (or device, see opts) int32[2n]
+ *   out        receives library-allocated host arrays
+ * Returns F2M_OK when certified, F2M_NOT_CERTIFIED when the result holds
+ * a valid bound but no proof (finish == NONE), or an error. n == 3 is
+ * solved in closed form; n < 3 returns F2M_ERR_INFEASIBLE. */
+f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
+                     const f2m_opts *opts, f2m_result *out);
+
+/* One GDP iteration (eq. 9, eq. 10, Jacobi) on device buffers, n >= 4:
+ *   coords_xy   device int32[2n]
+ *   lambda2_in  device int64[n]  (Lam_k)
+ *   lambda2_out device int64[n]  (Lam_k + dLam), may not alias lambda2_in
+ *   z4, i4      device int64[4n], int32[4n] or NULL: the four smallest
+ *               (Z, u) of each row in (Z, u) order, entry j of node v at
+ *               [4v + j]
+ *   neg, zero   device int32[n] or NULL: #{Z < 0}, #{Z == 0} per node
+ *   step        device int64[n] or NULL: dLam
+ *   rec         host int64[F2M_TRACE_W]: the iteration record (k = 0)
+ * Runs on the context's stream and waits for it. */
+f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
+                        const int64_t *lambda2_in, int64_t *lambda2_out,
+                        int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
+                        int64_t *step, int64_t rec[F2M_TRACE_W]);
+
+/* Certificate on the complete graph (weak/strong duality of Sec. 2):
+ *   coords_xy device int32[2n]; lambda2 device int64[n];
+ *   eu, ev, ex2 device arrays of m edges.
+ *   out host int64[4]: primal2, dual2, feasible (every x2 in {1,2}, u != v,
+ *   endpoints in range, no repeated pair, every doubled degree 4),
+ *   certified (feasible and primal2 == dual2). */
+f2m_status f2m_certify(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
+                       const int64_t *lambda2, int64_t m, const int32_t *eu,
+                       const int32_t *ev, const uint8_t *ex2, int64_t out[4]);
+
+void f2m_result_free(f2m_result *res);
+const char *f2m_status_str(f2m_status s);
+const char *f2m_last_error(const f2m_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* F2M_H */

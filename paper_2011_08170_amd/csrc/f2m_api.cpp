@@ -1,0 +1,690 @@
+// Host runtime of libf2m: contexts, device workspaces, the GDP loop with its
+// device-side stop test, the finish and the certificate, behind the C ABI
+// declared in include/f2m.h.
+#include "f2m.h"
+#include "f2m_finish.h"
+#include "f2m_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace f2m;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct f2m_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<DevBuf *> bufs;
+    // workspace
+    DevBuf xy, col, lam[2], lam_best, pz, pi, pneg, pzero, prowneg, z4, i4, seed, ctrl, trace, minmax, xy2max;
+    DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
+    // certificate workspace
+    DevBuf c_col, c_ctrl, c_xy2max, c_deg, c_cnt, c_nb, c_acc, c_minmax, c_lam, c_eu, c_ev, c_ex;
+    DevBuf p_lam, p_pairs, p_count;
+    Ctrl *ctrl_host = nullptr;   // pinned
+    int64_t *scratch_host = nullptr;   // pinned, 16 entries
+
+    f2m_ctx()
+    {
+        DevBuf *all[] = {&xy, &col, &lam[0], &lam[1], &lam_best, &pz, &pi, &pneg, &pzero, &prowneg, &z4, &i4,
+                         &seed, &ctrl, &trace, &minmax, &xy2max, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
+                         &btmp, &count, &c_col, &c_ctrl, &c_xy2max, &c_deg, &c_cnt, &c_nb, &c_acc, &c_minmax,
+                         &c_lam, &c_eu, &c_ev, &c_ex, &p_lam, &p_pairs, &p_count};
+        bufs.assign(std::begin(all), std::end(all));
+    }
+};
+
+namespace {
+
+struct Fail {
+    f2m_status st;
+};
+
+void fail(f2m_ctx *ctx, f2m_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    throw Fail{st};
+}
+
+void ck(f2m_ctx *ctx, hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        fail(ctx, e == hipErrorOutOfMemory ? F2M_ERR_NOMEM : F2M_ERR_DEVICE,
+             std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+template <typename T>
+T *grow(f2m_ctx *ctx, DevBuf &b, size_t count)
+{
+    const size_t need = std::max<size_t>(count * sizeof(T), 256);
+    if (b.bytes < need) {
+        if (b.p) (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        ck(ctx, hipMalloc(&b.p, need), "hipMalloc");
+        b.bytes = need;
+    }
+    return static_cast<T *>(b.p);
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Scan launch shape: rows per lane and column slices, from n.
+struct ScanShape {
+    int rows;          // rows per thread
+    int64_t slices;
+    int64_t slice_len;
+};
+
+ScanShape scan_shape(int64_t n)
+{
+    ScanShape s;
+    s.rows = n >= 65536 ? 4 : (n >= 8192 ? 2 : 1);
+    const int64_t row_blocks = (n + 256 * s.rows - 1) / (256 * s.rows);
+    const int64_t target = 2048;
+    int64_t sl = (target + row_blocks - 1) / row_blocks;
+    const int64_t max_sl = std::max<int64_t>(1, n / 64);
+    sl = std::max<int64_t>(1, std::min(sl, max_sl));
+    s.slice_len = (n + sl - 1) / sl;
+    s.slices = (n + s.slice_len - 1) / s.slice_len;
+    return s;
+}
+
+hipStream_t pick_stream(f2m_ctx *ctx, const f2m_opts *o)
+{
+    return (o && o->hip_stream) ? static_cast<hipStream_t>(o->hip_stream) : ctx->stream;
+}
+
+// Validates coordinates already on the device; returns the centre.
+void check_and_centre(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, DevBuf &mm, hipStream_t st,
+                      int32_t *cx, int32_t *cy)
+{
+    int32_t *m4 = grow<int32_t>(ctx, mm, 4);
+    ck(ctx, launch_minmax(xy_dev, n, m4, st), "minmax");
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, m4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    const int32_t *h = reinterpret_cast<const int32_t *>(ctx->scratch_host);
+    const int64_t spanx = (int64_t)h[1] - h[0], spany = (int64_t)h[3] - h[2];
+    if (spanx >= (1 << 20) || spany >= (1 << 20))
+        fail(ctx, F2M_ERR_RANGE, "coordinate span must be below 2^20 on each axis");
+    *cx = (int32_t)(((int64_t)h[0] + h[1]) >> 1);
+    *cy = (int32_t)(((int64_t)h[2] + h[3]) >> 1);
+}
+
+int64_t cost_host(const int32_t *xy, int64_t u, int64_t v)
+{
+    const int64_t dx = (int64_t)xy[2 * u] - xy[2 * v], dy = (int64_t)xy[2 * u + 1] - xy[2 * v + 1];
+    return nint_sqrt_host(dx * dx + dy * dy);
+}
+
+char *host_alloc(f2m_ctx *ctx, size_t bytes)
+{
+    char *p = static_cast<char *>(std::malloc(bytes ? bytes : 1));
+    if (!p) fail(ctx, F2M_ERR_NOMEM, "host allocation failed");
+    return p;
+}
+
+// Certificate of (lam, edges) on device buffers; returns out[4].
+void certify_dev(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam, int64_t m, const int32_t *eu,
+                 const int32_t *ev, const uint8_t *ex, hipStream_t st, int64_t out[4])
+{
+    int32_t cx, cy;
+    check_and_centre(ctx, xy, n, ctx->c_minmax, st, &cx, &cy);
+    float4 *col = grow<float4>(ctx, ctx->c_col, n);
+    float *x2m = grow<float>(ctx, ctx->c_xy2max, 1);
+    Ctrl *cc = grow<Ctrl>(ctx, ctx->c_ctrl, 1);
+    int32_t *deg = grow<int32_t>(ctx, ctx->c_deg, n);
+    int32_t *cnt = grow<int32_t>(ctx, ctx->c_cnt, n);
+    int32_t *nb = grow<int32_t>(ctx, ctx->c_nb, kTop * n);
+    unsigned long long *acc = grow<unsigned long long>(ctx, ctx->c_acc, 4);
+    ck(ctx, launch_prep(xy, n, cx, cy, col, x2m, st), "prep");
+    ck(ctx, launch_ctrl_init(cc, 0, 0, st), "ctrl");
+    ck(ctx, launch_set_lam(lam, n, col, cc, st), "set_lam");
+    ck(ctx, hipMemsetAsync(deg, 0, n * sizeof(int32_t), st), "memset");
+    ck(ctx, hipMemsetAsync(cnt, 0, n * sizeof(int32_t), st), "memset");
+    ck(ctx, hipMemsetAsync(acc, 0, 4 * sizeof(unsigned long long), st), "memset");
+    // the xy2max bound is read by value: fetch it
+    float x2host = 0.0f;
+    ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    const ScanShape sh = scan_shape(n);
+    CertScanArgs ca{n, sh.slice_len, col, lam, cc, x2host, acc};
+    ck(ctx, launch_cert_scan(ca, sh.slices, st), "cert_scan");
+    ck(ctx, launch_cert_edges(xy, n, m, eu, ev, ex, deg, cnt, nb, acc, st), "cert_edges");
+    ck(ctx, launch_cert_nodes(lam, n, deg, cnt, nb, acc, st), "cert_nodes");
+    unsigned long long h[4];
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, acc, sizeof(h), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    std::memcpy(h, ctx->scratch_host, sizeof(h));
+    const int64_t rowneg = (int64_t)h[0], primal2 = (int64_t)h[1], viol = (int64_t)h[2], sl = (int64_t)h[3];
+    out[0] = primal2;
+    out[1] = 2 * sl + rowneg / 2;
+    out[2] = viol == 0 ? 1 : 0;
+    out[3] = (viol == 0 && out[0] == out[1]) ? 1 : 0;
+}
+
+// Candidate pairs for the exact finish from GPU scans of the complete graph.
+class GpuPairs : public PairSource {
+public:
+    GpuPairs(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int32_t *seed_dev, hipStream_t st)
+        : ctx_(ctx), xy_(xy_dev), n_(n), seed_(seed_dev), st_(st)
+    {
+    }
+    bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) override
+    {
+        return run(lam, seed_, 0, slack, out, err);
+    }
+    bool negative(const int64_t *lam, PairList &out, std::string &err) override
+    {
+        return run(lam, nullptr, -1, 0, out, err);
+    }
+
+private:
+    bool run(const int64_t *lam_host, const int32_t *seed, int64_t theta, int64_t slack, PairList &out,
+             std::string &err)
+    {
+        try {
+            f2m_ctx *ctx = ctx_;
+            const int64_t n = n_;
+            int32_t cx, cy;
+            check_and_centre(ctx, xy_, n, ctx->c_minmax, st_, &cx, &cy);
+            float4 *col = grow<float4>(ctx, ctx->c_col, n);
+            float *x2m = grow<float>(ctx, ctx->c_xy2max, 1);
+            Ctrl *cc = grow<Ctrl>(ctx, ctx->c_ctrl, 1);
+            int64_t *lam = grow<int64_t>(ctx, ctx->p_lam, n);
+            unsigned long long *cnt = grow<unsigned long long>(ctx, ctx->p_count, 1);
+            ck(ctx, hipMemcpyAsync(lam, lam_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st_), "copy");
+            ck(ctx, launch_prep(xy_, n, cx, cy, col, x2m, st_), "prep");
+            ck(ctx, launch_ctrl_init(cc, 0, 0, st_), "ctrl");
+            ck(ctx, launch_set_lam(lam, n, col, cc, st_), "set_lam");
+            float x2host = 0.0f;
+            ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st_), "copy");
+            ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cc, sizeof(Ctrl), hipMemcpyDeviceToHost, st_), "copy");
+            ck(ctx, hipStreamSynchronize(st_), "sync");
+            if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| reached 2^38");
+            const ScanShape sh = scan_shape(n);
+            int64_t cap = std::max<int64_t>(cap_, 8 * n);
+            for (;;) {
+                int2 *pairs = grow<int2>(ctx, ctx->p_pairs, cap);
+                ck(ctx, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st_), "memset");
+                CollectArgs ca{n, sh.slice_len, col, lam, seed, cc, x2host, theta, slack, cnt, pairs, cap};
+                ck(ctx, launch_collect(ca, sh.slices, st_), "collect");
+                ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st_), "copy");
+                ck(ctx, hipStreamSynchronize(st_), "sync");
+                const int64_t found = ctx->scratch_host[0];
+                if (found > cap) { cap = found + found / 4; continue; }
+                std::vector<int2> h(found);
+                if (found)
+                    ck(ctx, hipMemcpyAsync(h.data(), pairs, found * sizeof(int2), hipMemcpyDeviceToHost, st_), "copy");
+                ck(ctx, hipStreamSynchronize(st_), "sync");
+                out.clear();
+                out.reserve(found);
+                for (const int2 &p : h) out.emplace_back(p.x, p.y);
+                std::sort(out.begin(), out.end());
+                out.erase(std::unique(out.begin(), out.end()), out.end());
+                cap_ = cap;
+                return true;
+            }
+        } catch (const Fail &) {
+            err = ctx_->err;
+            return false;
+        }
+    }
+
+    f2m_ctx *ctx_;
+    const int32_t *xy_;
+    int64_t n_;
+    const int32_t *seed_;
+    hipStream_t st_;
+    int64_t cap_ = 0;
+};
+
+// GDP loop on device buffers.  Returns the final control block.
+struct LoopOut {
+    Ctrl c;
+    double scan_ms = 0.0;
+    int64_t scan_launches = 0;
+    ScanShape shape;
+    int64_t *lam_star;     // device pointer holding Lam_kstar
+    int64_t *lam_last;     // device pointer holding Lam_klast
+};
+
+LoopOut gdp_loop(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int64_t *lam0_host, int64_t max_iters,
+                 int32_t chunk_opt, bool want_trace, bool time_kernels, hipStream_t st)
+{
+    LoopOut o;
+    int32_t cx, cy;
+    check_and_centre(ctx, xy_dev, n, ctx->minmax, st, &cx, &cy);
+    const ScanShape sh = scan_shape(n);
+    float4 *col = grow<float4>(ctx, ctx->col, n);
+    float *x2m = grow<float>(ctx, ctx->xy2max, 1);
+    int64_t *lam[2] = {grow<int64_t>(ctx, ctx->lam[0], n), grow<int64_t>(ctx, ctx->lam[1], n)};
+    int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
+    int64_t *pz = grow<int64_t>(ctx, ctx->pz, sh.slices * kTop * n);
+    int32_t *pi = grow<int32_t>(ctx, ctx->pi, sh.slices * kTop * n);
+    int32_t *pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
+    int32_t *pzero = grow<int32_t>(ctx, ctx->pzero, sh.slices * n);
+    int64_t *prn = grow<int64_t>(ctx, ctx->prowneg, sh.slices * n);
+    int64_t *z4 = grow<int64_t>(ctx, ctx->z4, kTop * n);
+    int32_t *i4 = grow<int32_t>(ctx, ctx->i4, kTop * n);
+    int32_t *seed = grow<int32_t>(ctx, ctx->seed, kTop * n);
+    Ctrl *cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
+    const int64_t trace_cap = want_trace ? max_iters + 1 : 0;
+    int64_t *trace = want_trace ? grow<int64_t>(ctx, ctx->trace, kTraceW * trace_cap) : nullptr;
+
+    ck(ctx, launch_prep(xy_dev, n, cx, cy, col, x2m, st), "prep");
+    if (lam0_host)
+        ck(ctx, hipMemcpyAsync(lam[0], lam0_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+    else
+        ck(ctx, hipMemsetAsync(lam[0], 0, n * sizeof(int64_t), st), "memset");
+    ck(ctx, launch_ctrl_init(cd, max_iters, trace_cap, st), "ctrl_init");
+    ck(ctx, launch_set_lam(lam[0], n, col, cd, st), "set_lam");
+    float x2host = 0.0f;
+    ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2_init| must be below 2^38");
+
+    const int chunk = chunk_opt > 0 ? chunk_opt : (n >= 50000 ? 4 : (n >= 5000 ? 16 : 64));
+    std::vector<hipEvent_t> evs;
+    if (time_kernels) {
+        evs.resize(2 * chunk);
+        for (auto &e : evs) ck(ctx, hipEventCreate(&e), "hipEventCreate");
+    }
+    struct EvGuard {
+        std::vector<hipEvent_t> &v;
+        ~EvGuard() { for (auto e : v) (void)hipEventDestroy(e); }
+    } guard{evs};
+    int64_t k = 0;
+    for (;;) {
+        int issued = 0;
+        for (int j = 0; j < chunk && k <= max_iters; ++j, ++k, ++issued) {
+            ScanArgs sa{n, sh.slice_len, col, lam[k & 1], k > 0 ? seed : nullptr, cd, x2host,
+                        pz, pi, pneg, pzero, prn};
+            if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
+            ck(ctx, launch_scan(sa, sh.slices, sh.rows, st), "scan");
+            if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
+            UpdateArgs ua{n, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
+                          z4, i4, seed, nullptr, nullptr, nullptr, cd, trace};
+            ck(ctx, launch_update(ua, st), "update");
+        }
+        ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        if (time_kernels) {
+            // iterations after the stop exit at once; count the ones that ran
+            const int64_t k0 = k - issued;
+            const int64_t ran = std::min<int64_t>(issued, ctx->ctrl_host->k_last + 1 - k0);
+            for (int64_t j = 0; j < ran; ++j) {
+                float ms = 0.0f;
+                ck(ctx, hipEventElapsedTime(&ms, evs[2 * j], evs[2 * j + 1]), "hipEventElapsedTime");
+                o.scan_ms += ms;
+                ++o.scan_launches;
+            }
+        }
+        if (ctx->ctrl_host->done) break;
+        if (k > max_iters) fail(ctx, F2M_ERR_DEVICE, "GDP loop passed the cap without stopping");
+    }
+    o.shape = sh;
+    o.c = *ctx->ctrl_host;
+    if (o.c.overflow) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| reached 2^38");
+    o.lam_last = lam[o.c.k_last & 1];
+    o.lam_star = (o.c.kstar == o.c.k_last) ? o.lam_last : best;
+    return o;
+}
+
+f2m_status solve_n3(f2m_ctx *ctx, const int32_t *xy, f2m_result *out)
+{
+    // the triangle is the only degree-2 solution; lambda from c_uv = lambda_u + lambda_v
+    const int64_t c01 = cost_host(xy, 0, 1), c02 = cost_host(xy, 0, 2), c12 = cost_host(xy, 1, 2);
+    out->n = 3;
+    out->lambda2 = reinterpret_cast<int64_t *>(host_alloc(ctx, 3 * sizeof(int64_t)));
+    out->lambda2_gdp = reinterpret_cast<int64_t *>(host_alloc(ctx, 3 * sizeof(int64_t)));
+    out->lambda2[0] = c01 + c02 - c12;
+    out->lambda2[1] = c01 + c12 - c02;
+    out->lambda2[2] = c02 + c12 - c01;
+    std::memcpy(out->lambda2_gdp, out->lambda2, 3 * sizeof(int64_t));
+    out->n_edges = 3;
+    out->edge_u = reinterpret_cast<int32_t *>(host_alloc(ctx, 3 * sizeof(int32_t)));
+    out->edge_v = reinterpret_cast<int32_t *>(host_alloc(ctx, 3 * sizeof(int32_t)));
+    out->edge_x2 = reinterpret_cast<uint8_t *>(host_alloc(ctx, 3));
+    const int32_t us[3] = {0, 0, 1}, vs[3] = {1, 2, 2};
+    for (int e = 0; e < 3; ++e) { out->edge_u[e] = us[e]; out->edge_v[e] = vs[e]; out->edge_x2[e] = 2; }
+    out->primal2 = 2 * (c01 + c02 + c12);
+    out->dual2 = out->dual2_gdp = out->primal2;   // every Z is 0
+    out->certified = 1;
+    out->stop = F2M_STOP_TRIVIAL;
+    return F2M_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void f2m_opts_default(f2m_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(f2m_opts);
+    o->rule_version = 1;
+    o->graph = F2M_GRAPH_COMPLETE;
+    o->warm = F2M_WARM_COLD;
+    o->max_iters = 100000;
+    o->finish = F2M_FINISH_EXACT;
+}
+
+f2m_status f2m_create(f2m_ctx **out, int device)
+{
+    if (!out) return F2M_ERR_ARG;
+    *out = nullptr;
+    f2m_ctx *ctx = new (std::nothrow) f2m_ctx();
+    if (!ctx) return F2M_ERR_NOMEM;
+    ctx->device = device;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        delete ctx;
+        return F2M_ERR_DEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->scratch_host, 16 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+        f2m_destroy(ctx);
+        return F2M_ERR_DEVICE;
+    }
+    *out = ctx;
+    return F2M_OK;
+}
+
+void f2m_destroy(f2m_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (DevBuf *b : ctx->bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->ctrl_host) (void)hipHostFree(ctx->ctrl_host);
+    if (ctx->scratch_host) (void)hipHostFree(ctx->scratch_host);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+void f2m_result_free(f2m_result *r)
+{
+    if (!r) return;
+    std::free(r->lambda2);
+    std::free(r->lambda2_gdp);
+    std::free(r->edge_u);
+    std::free(r->edge_v);
+    std::free(r->edge_x2);
+    std::free(r->trace);
+    std::memset(r, 0, sizeof(*r));
+}
+
+const char *f2m_status_str(f2m_status s)
+{
+    switch (s) {
+    case F2M_OK: return "ok";
+    case F2M_NOT_CERTIFIED: return "not certified";
+    case F2M_ERR_ARG: return "invalid argument";
+    case F2M_ERR_RANGE: return "coordinate span out of range";
+    case F2M_ERR_INFEASIBLE: return "infeasible (n < 3)";
+    case F2M_ERR_NOMEM: return "out of memory";
+    case F2M_ERR_DEVICE: return "device error";
+    case F2M_ERR_CAPACITY: return "buffer too small";
+    case F2M_ERR_OVERFLOW: return "multiplier overflow";
+    }
+    return "unknown status";
+}
+
+const char *f2m_last_error(const f2m_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam_in, int64_t *lam_out,
+                        int64_t *z4_out, int32_t *i4_out, int32_t *neg, int32_t *zero, int64_t *step,
+                        int64_t rec[F2M_TRACE_W])
+{
+    if (!ctx) return F2M_ERR_ARG;
+    try {
+        if (!xy || !lam_in || !lam_out || !rec || n < 4 || lam_in == lam_out)
+            fail(ctx, F2M_ERR_ARG, "gdp_step needs n >= 4, coords, distinct lambda2_in/out and rec");
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        hipStream_t st = ctx->stream;
+        int32_t cx, cy;
+        check_and_centre(ctx, xy, n, ctx->minmax, st, &cx, &cy);
+        const ScanShape sh = scan_shape(n);
+        float4 *col = grow<float4>(ctx, ctx->col, n);
+        float *x2m = grow<float>(ctx, ctx->xy2max, 1);
+        int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
+        int64_t *pz = grow<int64_t>(ctx, ctx->pz, sh.slices * kTop * n);
+        int32_t *pi = grow<int32_t>(ctx, ctx->pi, sh.slices * kTop * n);
+        int32_t *pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
+        int32_t *pzero = grow<int32_t>(ctx, ctx->pzero, sh.slices * n);
+        int64_t *prn = grow<int64_t>(ctx, ctx->prowneg, sh.slices * n);
+        int64_t *z4 = z4_out ? z4_out : grow<int64_t>(ctx, ctx->z4, kTop * n);
+        int32_t *i4 = i4_out ? i4_out : grow<int32_t>(ctx, ctx->i4, kTop * n);
+        int32_t *seed = grow<int32_t>(ctx, ctx->seed, kTop * n);
+        Ctrl *cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
+        int64_t *trace = grow<int64_t>(ctx, ctx->trace, kTraceW);
+        ck(ctx, launch_prep(xy, n, cx, cy, col, x2m, st), "prep");
+        ck(ctx, launch_ctrl_init(cd, INT64_MAX, 1, st), "ctrl_init");
+        ck(ctx, launch_set_lam(lam_in, n, col, cd, st), "set_lam");
+        float x2host = 0.0f;
+        ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| must be below 2^38");
+        ScanArgs sa{n, sh.slice_len, col, lam_in, nullptr, cd, x2host, pz, pi, pneg, pzero, prn};
+        ck(ctx, launch_scan(sa, sh.slices, sh.rows, st), "scan");
+        UpdateArgs ua{n, sh.slices, 0, pz, pi, pneg, pzero, prn, lam_in, lam_out, best, col,
+                      z4, i4, seed, neg, zero, step, cd, trace};
+        ck(ctx, launch_update(ua, st), "update");
+        ck(ctx, hipMemcpyAsync(ctx->scratch_host, trace, kTraceW * sizeof(int64_t), hipMemcpyDeviceToHost, st),
+           "copy");
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        std::memcpy(rec, ctx->scratch_host, kTraceW * sizeof(int64_t));
+        return F2M_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+f2m_status f2m_certify(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam, int64_t m,
+                       const int32_t *eu, const int32_t *ev, const uint8_t *ex2, int64_t out[4])
+{
+    if (!ctx) return F2M_ERR_ARG;
+    try {
+        if (!xy || !lam || !out || n < 3 || m < 0 || (m > 0 && (!eu || !ev || !ex2)))
+            fail(ctx, F2M_ERR_ARG, "certify needs n >= 3, coords, lambda2 and the edge arrays");
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        certify_dev(ctx, xy, n, lam, m, eu, ev, ex2, ctx->stream, out);
+        return F2M_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_opts *opts, f2m_result *out)
+{
+    if (!ctx) return F2M_ERR_ARG;
+    f2m_result res;
+    std::memset(&res, 0, sizeof(res));
+    try {
+        f2m_opts o;
+        f2m_opts_default(&o);
+        if (opts) {
+            if (opts->struct_size != sizeof(f2m_opts)) fail(ctx, F2M_ERR_ARG, "opts.struct_size mismatch");
+            o = *opts;
+        }
+        if (!coords || !out) fail(ctx, F2M_ERR_ARG, "null coords or result");
+        if (o.rule_version != 1) fail(ctx, F2M_ERR_ARG, "only rule_version 1 exists");
+        if (o.graph != F2M_GRAPH_COMPLETE) fail(ctx, F2M_ERR_ARG, "unknown graph kind");
+        if (o.max_iters < 0) fail(ctx, F2M_ERR_ARG, "max_iters < 0");
+        if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
+        if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER) fail(ctx, F2M_ERR_ARG, "unknown warm mode");
+        if (n < 3) fail(ctx, F2M_ERR_INFEASIBLE, "F2M needs n >= 3");
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        hipStream_t st = pick_stream(ctx, &o);
+        const double t0 = now_s();
+
+        // coordinates on the device and on the host (the finish and n == 3 need them)
+        std::vector<int32_t> xy_host;
+        const int32_t *xy_dev;
+        if (o.coords_on_device) {
+            xy_dev = coords;
+            xy_host.resize(2 * n);
+            ck(ctx, hipMemcpyAsync(xy_host.data(), coords, 2 * n * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+               "copy");
+            ck(ctx, hipStreamSynchronize(st), "sync");
+        } else {
+            xy_host.assign(coords, coords + 2 * n);
+            int32_t *d = grow<int32_t>(ctx, ctx->xy, 2 * n);
+            ck(ctx, hipMemcpyAsync(d, coords, 2 * n * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+            xy_dev = d;
+        }
+        if (n == 3) {
+            int64_t mn[2] = {xy_host[0], xy_host[1]}, mx[2] = {xy_host[0], xy_host[1]};
+            for (int i = 1; i < 3; ++i)
+                for (int a = 0; a < 2; ++a) {
+                    mn[a] = std::min<int64_t>(mn[a], xy_host[2 * i + a]);
+                    mx[a] = std::max<int64_t>(mx[a], xy_host[2 * i + a]);
+                }
+            if (mx[0] - mn[0] >= (1 << 20) || mx[1] - mn[1] >= (1 << 20))
+                fail(ctx, F2M_ERR_RANGE, "coordinate span must be below 2^20 on each axis");
+            f2m_status s = solve_n3(ctx, xy_host.data(), &res);
+            res.seconds[5] = now_s() - t0;
+            *out = res;
+            return s;
+        }
+        const double t1 = now_s();
+        LoopOut lo = gdp_loop(ctx, xy_dev, n, o.warm == F2M_WARM_USER ? o.lambda2_init : nullptr, o.max_iters,
+                              o.chunk, o.record_trace != 0, o.time_kernels != 0, st);
+        const double t2 = now_s();
+        res.n = n;
+        res.iterations = lo.c.k_last + 1;
+        res.kstar = lo.c.kstar;
+        res.stop = (int32_t)lo.c.stop;
+        res.lambda2_gdp = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
+        ck(ctx, hipMemcpyAsync(res.lambda2_gdp, lo.lam_star, n * sizeof(int64_t), hipMemcpyDeviceToHost, st),
+           "copy");
+        if (o.record_trace) {
+            res.trace_len = res.iterations;
+            res.trace = reinterpret_cast<int64_t *>(host_alloc(ctx, res.trace_len * kTraceW * sizeof(int64_t)));
+            ck(ctx, hipMemcpyAsync(res.trace, ctx->trace.p, res.trace_len * kTraceW * sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, st), "copy");
+        }
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        res.dual2_gdp = (lo.c.kstar == lo.c.k_last) ? lo.c.dual2_last : lo.c.best_dual2;
+
+        int32_t *eu = nullptr, *ev = nullptr;
+        uint8_t *ex = nullptr;
+        int64_t m = 0;
+        const int64_t *lam_final_dev = lo.lam_star;
+        std::vector<int64_t> lam_final_host;
+        const double t3 = now_s();
+        if (lo.c.stop == F2M_STOP_TRIVIAL) {
+            const int64_t ns = kTop * n;
+            int32_t *su = grow<int32_t>(ctx, ctx->slot_u, ns);
+            int32_t *sv = grow<int32_t>(ctx, ctx->slot_v, ns);
+            uint8_t *sx = grow<uint8_t>(ctx, ctx->slot_x, ns);
+            eu = grow<int32_t>(ctx, ctx->eu, ns);
+            ev = grow<int32_t>(ctx, ctx->ev, ns);
+            ex = grow<uint8_t>(ctx, ctx->ex, ns);
+            int32_t *bt = grow<int32_t>(ctx, ctx->btmp, compact_block_tmp_len(ns));
+            int64_t *cnt = grow<int64_t>(ctx, ctx->count, 1);
+            ck(ctx, launch_extract_trivial((const int64_t *)ctx->z4.p, (const int32_t *)ctx->i4.p, n, su, sv, sx, st),
+               "extract");
+            ck(ctx, launch_compact(su, sv, sx, ns, eu, ev, ex, cnt, bt, st), "compact");
+            ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+            ck(ctx, hipStreamSynchronize(st), "sync");
+            m = ctx->scratch_host[0];
+        } else if (o.finish == F2M_FINISH_EXACT) {
+            FinishResult fr;
+            GpuPairs src(ctx, xy_dev, n, (const int32_t *)ctx->seed.p, st);
+            finish_exact(xy_host.data(), n, res.lambda2_gdp, src, &fr);
+            res.finish_paths = fr.paths;
+            res.finish_rounds = fr.rounds;
+            if (!fr.ok) fail(ctx, F2M_ERR_DEVICE, "exact finish failed: " + fr.msg);
+            m = (int64_t)fr.eu.size();
+            lam_final_host = fr.lam;
+            int64_t *ld = grow<int64_t>(ctx, ctx->c_lam, n);
+            eu = grow<int32_t>(ctx, ctx->c_eu, std::max<int64_t>(m, 1));
+            ev = grow<int32_t>(ctx, ctx->c_ev, std::max<int64_t>(m, 1));
+            ex = grow<uint8_t>(ctx, ctx->c_ex, std::max<int64_t>(m, 1));
+            ck(ctx, hipMemcpyAsync(ld, fr.lam.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+            if (m) {
+                ck(ctx, hipMemcpyAsync(eu, fr.eu.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+                ck(ctx, hipMemcpyAsync(ev, fr.ev.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+                ck(ctx, hipMemcpyAsync(ex, fr.ex2.data(), m * sizeof(uint8_t), hipMemcpyHostToDevice, st), "copy");
+            }
+            lam_final_dev = ld;
+        }
+        const double t4 = now_s();
+        int64_t cert[4] = {0, 0, 0, 0};
+        if (m > 0 || lo.c.stop == F2M_STOP_TRIVIAL || o.finish == F2M_FINISH_EXACT) {
+            certify_dev(ctx, xy_dev, n, lam_final_dev, m, eu, ev, ex, st, cert);
+        }
+        const double t5 = now_s();
+        res.n_edges = m;
+        res.edge_u = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
+        res.edge_v = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
+        res.edge_x2 = reinterpret_cast<uint8_t *>(host_alloc(ctx, std::max<int64_t>(m, 1)));
+        res.lambda2 = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
+        if (m) {
+            ck(ctx, hipMemcpyAsync(res.edge_u, eu, m * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+            ck(ctx, hipMemcpyAsync(res.edge_v, ev, m * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+            ck(ctx, hipMemcpyAsync(res.edge_x2, ex, m * sizeof(uint8_t), hipMemcpyDeviceToHost, st), "copy");
+        }
+        ck(ctx, hipMemcpyAsync(res.lambda2, lam_final_dev, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        res.primal2 = cert[0];
+        res.dual2 = cert[1];
+        res.certified = (int32_t)cert[3];
+        res.scan_ms = lo.scan_ms;
+        res.scan_launches = lo.scan_launches;
+        res.scan_rows = lo.shape.rows;
+        res.scan_slices = lo.shape.slices;
+        res.seconds[0] = t1 - t0;
+        res.seconds[2] = t2 - t1;
+        res.seconds[3] = t4 - t3;
+        res.seconds[4] = t5 - t4;
+        res.seconds[5] = now_s() - t0;
+        *out = res;
+        return res.certified ? F2M_OK : F2M_NOT_CERTIFIED;
+    } catch (const Fail &f) {
+        f2m_result_free(&res);
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        f2m_result_free(&res);
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+// Exact finish: primal-dual min-cost flow on the bipartite double cover of
+// a candidate graph, warm-started from the GDP multipliers, with pricing on
+// the complete graph.  See f2m_finish.h.
+#include "f2m_finish.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <queue>
+#include <unordered_set>
+
+namespace f2m {
+
+int64_t nint_sqrt_host(int64_t D)
+{
+    int64_t k = (int64_t)std::llround(std::sqrt((double)D));
+    const int64_t d4 = 4 * D;
+    while ((2 * k + 1) * (2 * k + 1) <= d4) ++k;
+    while (k > 0 && (2 * k - 1) * (2 * k - 1) > d4) --k;
+    return k;
+}
+
+namespace {
+
+constexpr int64_t kInf = std::numeric_limits<int64_t>::max() / 4;
+
+int64_t floor_half(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
+
+// Node ids: left copy v' -> v, right copy u'' -> n + u.
+// Arc 2i is a_i' -> b_i'', arc 2i+1 is b_i' -> a_i'' for candidate edge i.
+class DoubleCover {
+public:
+    DoubleCover(const int32_t *xy, int64_t n, const int64_t *lam) : xy_(xy), n_(n), alpha_(n), beta_(n), ex_(2 * n, 0)
+    {
+        for (int64_t v = 0; v < n; ++v) {
+            alpha_[v] = floor_half(lam[v]);
+            beta_[v] = lam[v] - alpha_[v];
+            ex_[v] = 2;        // left copies supply 2
+            ex_[n + v] = -2;   // right copies demand 2
+        }
+    }
+
+    int64_t edges() const { return (int64_t)ea_.size(); }
+
+    // Adds new candidate edges; arcs of negative reduced cost start saturated.
+    void add(const PairList &pl)
+    {
+        for (const auto &p : pl) {
+            int32_t a = std::min(p.first, p.second), b = std::max(p.first, p.second);
+            if (a == b || a < 0 || b >= n_) continue;
+            const uint64_t key = (uint64_t)a * (uint64_t)n_ + (uint64_t)b;
+            if (!have_.insert(key).second) continue;
+            const int64_t dx = (int64_t)xy_[2 * a] - xy_[2 * b], dy = (int64_t)xy_[2 * a + 1] - xy_[2 * b + 1];
+            const int64_t c = nint_sqrt_host(dx * dx + dy * dy);
+            ea_.push_back(a);
+            eb_.push_back(b);
+            ec_.push_back(c);
+            for (int d = 0; d < 2; ++d) {
+                const int64_t k = 2 * ((int64_t)ea_.size() - 1) + d;
+                const bool neg = red(k) < 0;
+                y_.push_back(neg ? 1 : 0);
+                if (neg) { --ex_[tail(k)]; ++ex_[n_ + head(k)]; }
+            }
+        }
+        build_adjacency();
+    }
+
+    // Min-cost flow on the current candidates; false when some excess
+    // cannot reach a deficit (the candidate graph is too small).
+    bool solve(int64_t &paths, int64_t &phases)
+    {
+        std::vector<int64_t> dist(2 * n_, kInf);
+        std::vector<int32_t> seen(2 * n_, 0), dead(2 * n_, 0);
+        int32_t stamp = 0;
+        std::vector<int64_t> touched;
+        for (;;) {
+            bool any = false;
+            for (int64_t x = 0; x < 2 * n_; ++x) if (ex_[x] > 0) { any = true; break; }
+            if (!any) return true;
+            // Dijkstra from every excess node on reduced costs
+            using Item = std::pair<int64_t, int64_t>;
+            std::priority_queue<Item, std::vector<Item>, std::greater<Item>> pq;
+            for (int64_t x : touched) dist[x] = kInf;
+            touched.clear();
+            for (int64_t x = 0; x < 2 * n_; ++x)
+                if (ex_[x] > 0) { dist[x] = 0; touched.push_back(x); pq.push({0, x}); }
+            int64_t D = -1;
+            while (!pq.empty()) {
+                const auto [d, x] = pq.top();
+                pq.pop();
+                if (d != dist[x]) continue;
+                if (ex_[x] < 0) { D = d; break; }
+                relax_from(x, d, dist, touched, pq);
+            }
+            if (D < 0) return false;
+            ++phases;
+            // potentials: p(x) -= min(dist(x), D); p(v') = alpha_v, p(u'') = -beta_u
+            for (int64_t v = 0; v < n_; ++v) {
+                alpha_[v] -= std::min(dist[v], D);
+                beta_[v] += std::min(dist[n_ + v], D);
+            }
+            // unit augmentations along zero-reduced-cost paths
+            ++stamp;
+            for (int64_t s = 0; s < 2 * n_; ++s) {
+                while (ex_[s] > 0 && seen[s] != stamp) {
+                    if (!augment_from(s, stamp, seen)) break;
+                    ++paths;
+                }
+            }
+            (void)dead;
+        }
+    }
+
+    void lam(std::vector<int64_t> &out) const
+    {
+        out.resize(n_);
+        for (int64_t v = 0; v < n_; ++v) out[v] = alpha_[v] + beta_[v];
+    }
+
+    void x(std::vector<int32_t> &eu, std::vector<int32_t> &ev, std::vector<uint8_t> &ex2) const
+    {
+        std::vector<int64_t> order;
+        for (int64_t i = 0; i < (int64_t)ea_.size(); ++i)
+            if (y_[2 * i] + y_[2 * i + 1] > 0) order.push_back(i);
+        std::sort(order.begin(), order.end(), [&](int64_t p, int64_t q) {
+            return ea_[p] != ea_[q] ? ea_[p] < ea_[q] : eb_[p] < eb_[q];
+        });
+        eu.clear(); ev.clear(); ex2.clear();
+        for (int64_t i : order) {
+            eu.push_back(ea_[i]);
+            ev.push_back(eb_[i]);
+            ex2.push_back((uint8_t)(y_[2 * i] + y_[2 * i + 1]));
+        }
+    }
+
+private:
+    int64_t tail(int64_t k) const { return (k & 1) ? eb_[k >> 1] : ea_[k >> 1]; }
+    int64_t head(int64_t k) const { return (k & 1) ? ea_[k >> 1] : eb_[k >> 1]; }
+    int64_t red(int64_t k) const { return ec_[k >> 1] - alpha_[tail(k)] - beta_[head(k)]; }
+
+    void build_adjacency()
+    {
+        const int64_t m = 2 * (int64_t)ea_.size();
+        lstart_.assign(n_ + 1, 0);
+        rstart_.assign(n_ + 1, 0);
+        for (int64_t k = 0; k < m; ++k) { ++lstart_[tail(k) + 1]; ++rstart_[head(k) + 1]; }
+        for (int64_t v = 0; v < n_; ++v) { lstart_[v + 1] += lstart_[v]; rstart_[v + 1] += rstart_[v]; }
+        larc_.assign(m, 0);
+        rarc_.assign(m, 0);
+        std::vector<int64_t> lp(lstart_.begin(), lstart_.end() - 1), rp(rstart_.begin(), rstart_.end() - 1);
+        for (int64_t k = 0; k < m; ++k) { larc_[lp[tail(k)]++] = k; rarc_[rp[head(k)]++] = k; }
+    }
+
+    template <typename PQ>
+    void relax_from(int64_t x, int64_t d, std::vector<int64_t> &dist, std::vector<int64_t> &touched, PQ &pq)
+    {
+        if (x < n_) {   // left copy: arcs with y = 0, forward
+            for (int64_t p = lstart_[x]; p < lstart_[x + 1]; ++p) {
+                const int64_t k = larc_[p];
+                if (y_[k]) continue;
+                const int64_t to = n_ + head(k);
+                const int64_t nd = d + red(k);
+                if (nd < dist[to]) { if (dist[to] == kInf) touched.push_back(to); dist[to] = nd; pq.push({nd, to}); }
+            }
+        } else {        // right copy: arcs with y = 1, backward
+            const int64_t u = x - n_;
+            for (int64_t p = rstart_[u]; p < rstart_[u + 1]; ++p) {
+                const int64_t k = rarc_[p];
+                if (!y_[k]) continue;
+                const int64_t to = tail(k);
+                const int64_t nd = d - red(k);
+                if (nd < dist[to]) { if (dist[to] == kInf) touched.push_back(to); dist[to] = nd; pq.push({nd, to}); }
+            }
+        }
+    }
+
+    // Depth-first search from s over zero-reduced-cost residual arcs to a
+    // node with a deficit; flips the arcs of the path found.
+    bool augment_from(int64_t s, int32_t stamp, std::vector<int32_t> &seen)
+    {
+        struct Frame { int64_t x, p, via; };
+        std::vector<Frame> st;
+        seen[s] = stamp;
+        st.push_back({s, s < n_ ? lstart_[s] : rstart_[s - n_], -1});
+        while (!st.empty()) {
+            Frame &f = st.back();
+            const int64_t x = f.x;
+            if (x != s && ex_[x] < 0) {
+                // flip the path
+                for (size_t i = 1; i < st.size(); ++i) y_[st[i].via] ^= 1;
+                --ex_[s];
+                ++ex_[x];
+                return true;
+            }
+            bool pushed = false;
+            if (x < n_) {
+                for (; f.p < lstart_[x + 1]; ++f.p) {
+                    const int64_t k = larc_[f.p];
+                    if (y_[k] || red(k) != 0) continue;
+                    const int64_t to = n_ + head(k);
+                    if (seen[to] == stamp) continue;
+                    seen[to] = stamp;
+                    ++f.p;
+                    st.push_back({to, rstart_[head(k)], k});
+                    pushed = true;
+                    break;
+                }
+            } else {
+                const int64_t u = x - n_;
+                for (; f.p < rstart_[u + 1]; ++f.p) {
+                    const int64_t k = rarc_[f.p];
+                    if (!y_[k] || red(k) != 0) continue;
+                    const int64_t to = tail(k);
+                    if (seen[to] == stamp) continue;
+                    seen[to] = stamp;
+                    ++f.p;
+                    st.push_back({to, lstart_[to], k});
+                    pushed = true;
+                    break;
+                }
+            }
+            if (!pushed) st.pop_back();
+        }
+        return false;
+    }
+
+    const int32_t *xy_;
+    int64_t n_;
+    std::vector<int64_t> alpha_, beta_;
+    std::vector<int64_t> ex_;
+    std::vector<int32_t> ea_, eb_;
+    std::vector<int64_t> ec_;
+    std::vector<uint8_t> y_;
+    std::unordered_set<uint64_t> have_;
+    std::vector<int64_t> lstart_, rstart_, larc_, rarc_;
+};
+
+}  // namespace
+
+void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out)
+{
+    FinishResult &r = *out;
+    r = FinishResult();
+    DoubleCover g(xy, n, lam0);
+    std::string err;
+    PairList pl;
+    int64_t slack = 16;
+    if (!src.near(lam0, slack, pl, err)) { r.msg = err; return; }
+    g.add(pl);
+    std::vector<int64_t> lam;
+    for (int round = 0; round < 64; ++round) {
+        ++r.rounds;
+        if (!g.solve(r.paths, r.phases)) {
+            // too few candidates for a degree-2 flow: widen around the current duals
+            slack *= 4;
+            g.lam(lam);
+            pl.clear();
+            if (!src.near(lam.data(), slack, pl, err)) { r.msg = err; return; }
+            g.add(pl);
+            continue;
+        }
+        g.lam(lam);
+        pl.clear();
+        if (!src.negative(lam.data(), pl, err)) { r.msg = err; return; }
+        const int64_t before = g.edges();
+        g.add(pl);
+        if (g.edges() == before) {
+            r.ok = true;
+            r.lam = lam;
+            g.x(r.eu, r.ev, r.ex2);
+            r.candidates = g.edges();
+            return;
+        }
+    }
+    r.msg = "pricing did not converge in 64 rounds";
+}
+
+}  // namespace f2m

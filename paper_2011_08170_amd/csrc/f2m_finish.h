@@ -1,0 +1,56 @@
+// Exact finish of the GDP (host C++): from the GDP multipliers to a
+// certified F2M optimum.
+//
+// The GDP's fixed points are stationary for every single multiplier but
+// need not be optimal (degenerate cases, Sec. 3 of arXiv 2011.08170).  The
+// finish solves F2M exactly as a min-cost flow on the bipartite double
+// cover (left copy v', right copy v'', arc v'->u'' of cost c_uv and
+// capacity 1, every copy of degree 2; its optimum is twice the F2M optimum
+// and x_e = (y_u'v'' + y_v'u'')/2), by a primal-dual method: Dijkstra on
+// reduced costs from every node with excess, a potential update, then unit
+// augmentations along zero-reduced-cost paths.  It starts from the GDP's
+// Lam: alpha_v = floor(Lam_v / 2), beta_v = Lam_v - alpha_v, and the flow
+// y = 1 exactly on the arcs of negative reduced cost.  The arc set is a
+// candidate set of near-tight pairs; pricing asks the caller for every pair
+// of the complete graph whose Z is negative under the finished
+// Lam = alpha + beta and repeats until there is none, which makes the
+// result optimal on the complete graph (dual2 == primal2).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace f2m {
+
+// exact nint(sqrt(D)) on the host
+int64_t nint_sqrt_host(int64_t D);
+
+using PairList = std::vector<std::pair<int32_t, int32_t>>;   // (u, v), u < v
+
+// Candidate pairs for the finish, supplied by the caller (the library
+// uses GPU scans).
+struct PairSource {
+    virtual ~PairSource() = default;
+    // pairs {u, v} with Z_uv(lam) <= max(0, 4th smallest Z at u or v) + slack
+    virtual bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) = 0;
+    // pairs {u, v} with Z_uv(lam) < 0
+    virtual bool negative(const int64_t *lam, PairList &out, std::string &err) = 0;
+};
+
+struct FinishResult {
+    bool ok = false;
+    std::string msg;
+    std::vector<int64_t> lam;       // Lam = alpha + beta
+    std::vector<int32_t> eu, ev;    // edges of x, eu < ev
+    std::vector<uint8_t> ex2;       // 2x in {1, 2}
+    int64_t paths = 0;              // unit augmentations
+    int64_t rounds = 0;             // pricing rounds
+    int64_t phases = 0;             // Dijkstra phases
+    int64_t candidates = 0;         // candidate pairs at the end
+};
+
+void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out);
+
+}  // namespace f2m

@@ -1,0 +1,897 @@
+// HIP kernels of libf2m for gfx950 (MI355X): the complete-graph GDP scan,
+// the per-node update with its device-side stop test, trivial-x extraction
+// and the certificate.
+//
+// Notation (arXiv 2011.08170): c_e is the edge length, lambda_v the node
+// multiplier, v^e = c_e - lambda_u - lambda_v the adjusted length (eq. 9).
+// Fixed point: Lam = 2*lambda (int64), Z_uv = 2c_uv - Lam_u - Lam_v.
+//
+// The scan.  For every ordered pair (v, u) the GDP needs Z_vu only when it
+// can change node v's statistics: the four smallest (Z, u) of the row and
+// the counts of Z < 0, Z == 0 and the sum of the negative Z.  With theta_v
+// an upper bound on the row's 4th smallest Z (seeded from the previous
+// iteration's top-4 columns, tightened as the lane's own list fills) and
+// theta_v >= 0, a pair matters only if Z <= theta_v, i.e.
+//     2c <= R := theta_v + Lam_v + Lam_u.
+// Since c = nint(sqrt D) >= sqrt(D) - 1/2, that needs sqrt(D) < (R+1)/2 = h,
+// i.e.  E = D - h^2 < 0.  With h = hv + hu (hv per row, hu = Lam_u/2 per
+// column) and centred coordinates,
+//     E = K_v + q_u + (-2x_v) x_u + (-2y_v) y_u + (-2hv) hu,
+//     K_v = x_v^2 + y_v^2 - hv^2,   q_u = x_u^2 + y_u^2 - hu^2,
+// three FMAs per pair in float.  Every rounding in that chain is bounded by
+// 2^-24 of M_v = 2(x_v^2 + y_v^2 + hv^2 + max_u(x_u^2 + y_u^2) + max_u hu^2),
+// so a pair is skipped only when the float value exceeds K_v by more than
+// 2^-18 M_v; everything else is re-evaluated exactly in int64 (exact D,
+// nint(sqrt D) from sqrtf corrected by integer tests).  The filter is
+// conservative: it never drops a pair with Z <= theta_v.
+#include "f2m_internal.h"
+
+#include <float.h>
+#include <limits.h>
+
+namespace f2m {
+
+constexpr int kBlock = 256;   // threads per workgroup (4 waves of 64)
+constexpr int kTile = 256;    // columns staged in LDS per tile
+constexpr int kGroup = 8;     // columns per filter test
+constexpr int32_t kNoIdx = INT32_MAX;
+
+// ---------------------------------------------------------------------------
+// exact arithmetic helpers
+// ---------------------------------------------------------------------------
+
+// nint(sqrt(D)) exactly: the k with (2k-1)^2 <= 4D < (2k+1)^2 (TSPLIB
+// EUC_2D rounding).  sqrtf gives k within one; the loops make it exact.
+__device__ __forceinline__ int64_t nint_sqrt(int64_t D)
+{
+    const float f = sqrtf((float)D);
+    int64_t k = (int64_t)(f + 0.5f);
+    const int64_t d4 = 4 * D;
+    while ((2 * k + 1) * (2 * k + 1) <= d4) ++k;
+    while (k > 0 && (2 * k - 1) * (2 * k - 1) > d4) --k;
+    return k;
+}
+
+// Z_vu from centred float coordinates (exact integers, |.| <= 2^19).
+__device__ __forceinline__ int64_t exact_z(float xv, float yv, int64_t lamv, float xu, float yu,
+                                           int64_t lamu)
+{
+    const int32_t dx = (int32_t)(xv - xu);
+    const int32_t dy = (int32_t)(yv - yu);
+    const int64_t D = (int64_t)dx * dx + (int64_t)dy * dy;
+    return 2 * nint_sqrt(D) - lamv - lamu;
+}
+
+__device__ __forceinline__ bool key_less(int64_t za, int32_t ua, int64_t zb, int32_t ub)
+{
+    return za < zb || (za == zb && ua < ub);
+}
+
+// dLam = sign(s) * floor((|s| + 2) / 4)
+__device__ __forceinline__ int64_t gdp_step(int64_t s)
+{
+    if (s > 0) return (s + 2) >> 2;
+    if (s < 0) return -((-s + 2) >> 2);
+    return 0;
+}
+
+// SplitMix64 output finaliser (Steele, Lea, Flood 2014)
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// per-row scan state
+// ---------------------------------------------------------------------------
+
+struct Top4 {
+    int64_t z[kTop];
+    int32_t id[kTop];
+
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int j = 0; j < kTop; ++j) { z[j] = INT64_MAX; id[j] = kNoIdx; }
+    }
+    // keeps the four smallest keys in increasing (Z, u) order
+    __device__ __forceinline__ void insert(int64_t zz, int32_t u)
+    {
+        if (!key_less(zz, u, z[3], id[3])) return;
+        z[3] = zz; id[3] = u;
+#pragma unroll
+        for (int j = 3; j > 0; --j) {
+            if (key_less(z[j], id[j], z[j - 1], id[j - 1])) {
+                const int64_t tz = z[j]; z[j] = z[j - 1]; z[j - 1] = tz;
+                const int32_t ti = id[j]; id[j] = id[j - 1]; id[j - 1] = ti;
+            }
+        }
+    }
+};
+
+struct Row {
+    float a, b, c, thr;   // filter: skip when a*xu + b*yu + c*hu + qu > thr
+    float xv, yv;
+    int64_t lamv, theta;
+    int64_t v;
+};
+
+// Recomputes the filter of a row from theta (see the header comment).
+__device__ __forceinline__ void set_filter(Row &r, float colmax)
+{
+    const float hv = (float)(0.5 * (double)(r.theta + r.lamv + 1));
+    r.a = -2.0f * r.xv;
+    r.b = -2.0f * r.yv;
+    r.c = -2.0f * hv;
+    const float K = fmaf(r.xv, r.xv, fmaf(r.yv, r.yv, -hv * hv));
+    const float M = 2.0f * (r.xv * r.xv + r.yv * r.yv + hv * hv + colmax);
+    r.thr = M * 0x1p-18f - K;
+}
+
+__device__ __forceinline__ float filter_value(const Row &r, float4 cd)
+{
+    return fmaf(r.c, cd.z, fmaf(r.b, cd.y, fmaf(r.a, cd.x, cd.w)));
+}
+
+// max over columns of x^2 + y^2 plus the square of an upper bound on |hu|
+__device__ __forceinline__ float col_bound(float xy2max, long long maxabs_lam)
+{
+    const float hu = (float)(maxabs_lam / 2 + 1);
+    return xy2max + hu * hu;
+}
+
+// ---------------------------------------------------------------------------
+// scan: rows x column slices -> partial top-4 and counts
+// ---------------------------------------------------------------------------
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_scan(ScanArgs a)
+{
+    if (a.ctrl->done) return;
+    __shared__ float4 sc[kTile];
+    const int t = threadIdx.x;
+    const int64_t n = a.n;
+    const int64_t sl = blockIdx.y;
+    const int64_t c0 = sl * a.slice_len;
+    const int64_t c1 = min(n, c0 + a.slice_len);
+    const float colmax = col_bound(a.xy2max, a.ctrl->maxabs_lam);
+
+    Row rw[R];
+    Top4 top[R];
+    int32_t neg[R], zero[R];
+    int64_t rn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t v = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + t;
+        rw[r].v = v;
+        top[r].clear();
+        neg[r] = 0; zero[r] = 0; rn[r] = 0;
+        if (v < n) {
+            const float4 cv = a.col[v];
+            rw[r].xv = cv.x; rw[r].yv = cv.y;
+            rw[r].lamv = a.lam[v];
+            int64_t th = kThetaNone;
+            if (a.seed) {
+                int64_t mx = INT64_MIN;
+                int cnt = 0;
+#pragma unroll
+                for (int j = 0; j < kTop; ++j) {
+                    const int32_t u = a.seed[j * n + v];
+                    if (u >= 0 && u < n && u != v) {
+                        const float4 cu = a.col[u];
+                        const int64_t z = exact_z(cv.x, cv.y, rw[r].lamv, cu.x, cu.y, a.lam[u]);
+                        mx = z > mx ? z : mx;
+                        ++cnt;
+                    }
+                }
+                if (cnt == kTop) th = mx > 0 ? mx : 0;
+            }
+            rw[r].theta = th;
+            set_filter(rw[r], colmax);
+        } else {
+            rw[r].xv = rw[r].yv = 0.0f;
+            rw[r].lamv = 0; rw[r].theta = 0;
+            rw[r].a = rw[r].b = rw[r].c = 0.0f;
+            rw[r].thr = -INFINITY;   // never passes
+        }
+    }
+
+    for (int64_t tile = c0; tile < c1; tile += kTile) {
+        __syncthreads();
+        const int64_t cc = tile + t;
+        sc[t] = (cc < c1) ? a.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        __syncthreads();
+        const int64_t ntile = min((int64_t)kTile, c1 - tile);
+        for (int g = 0; g < ntile; g += kGroup) {
+            float m[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) m[r] = INFINITY;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const float4 cd = sc[g + q];
+#pragma unroll
+                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (m[r] <= rw[r].thr) {
+                    // exact pass over the group for this row
+                    for (int q = 0; q < kGroup; ++q) {
+                        const int64_t u = tile + g + q;
+                        if (u >= c1 || u == rw[r].v) continue;
+                        const float4 cd = sc[g + q];
+                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
+                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lam[u]);
+                        if (z > rw[r].theta) continue;
+                        if (z < 0) { ++neg[r]; rn[r] += z; }
+                        else if (z == 0) ++zero[r];
+                        top[r].insert(z, (int32_t)u);
+                        if (top[r].id[3] != kNoIdx) {
+                            const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
+                            if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t v = rw[r].v;
+        if (v >= n) continue;
+#pragma unroll
+        for (int j = 0; j < kTop; ++j) {
+            a.pz[(sl * kTop + j) * n + v] = top[r].z[j];
+            a.pi[(sl * kTop + j) * n + v] = top[r].id[j];
+        }
+        a.pneg[sl * n + v] = neg[r];
+        a.pzero[sl * n + v] = zero[r];
+        a.prowneg[sl * n + v] = rn[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// block reductions
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const T y = __shfl_xor(x, o, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Sums (or maxes) one value per thread over the block; result valid in
+// thread 0.  `buf` holds kBlock/64 entries.
+template <typename T, bool kMax>
+__device__ __forceinline__ T block_reduce(T x, T *buf)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x = kMax ? wave_max(x) : wave_sum(x);
+    __syncthreads();
+    if (lane == 0) buf[w] = x;
+    __syncthreads();
+    T r = buf[0];
+    for (int i = 1; i < kBlock / 64; ++i) r = kMax ? (buf[i] > r ? buf[i] : r) : r + buf[i];
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// update: merge slices, step Lam, reduce, stop test
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
+{
+    Ctrl *ctrl = a.ctrl;
+    if (ctrl->done) return;
+    __shared__ unsigned long long red[kBlock / 64];
+    __shared__ int s_last;
+    const int64_t n = a.n;
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // Lam_{k-1} sits in lam_out until it is overwritten below
+    const bool copy_best = a.k > 0 && ctrl->best_k == a.k - 1;
+
+    unsigned long long sumlam = 0, rowneg = 0, unsat = 0, bad = 0, nonzero = 0, hsh = 0;
+    long long maxstep = 0, maxabs = 0;
+    if (v < n) {
+        Top4 top;
+        top.clear();
+        int64_t cn = 0, cz = 0, rn = 0;
+        for (int64_t sl = 0; sl < a.nslices; ++sl) {
+#pragma unroll
+            for (int j = 0; j < kTop; ++j)
+                top.insert(a.pz[(sl * kTop + j) * n + v], a.pi[(sl * kTop + j) * n + v]);
+            cn += a.pneg[sl * n + v];
+            cz += a.pzero[sl * n + v];
+            rn += a.prowneg[sl * n + v];
+        }
+        const int64_t lamv = a.lam_in[v];
+        const int64_t st = gdp_step(top.z[1] + top.z[2]);   // eq. 10: 2nd and 3rd shortest
+        const int64_t nxt = lamv + st;
+        if (copy_best) a.lam_best[v] = a.lam_out[v];
+        a.lam_out[v] = nxt;
+        float4 cv = a.col[v];
+        const float h = (float)(0.5 * (double)nxt);
+        cv.z = h;
+        cv.w = fmaf(cv.x, cv.x, fmaf(cv.y, cv.y, -h * h));
+        a.col[v] = cv;
+#pragma unroll
+        for (int j = 0; j < kTop; ++j) {
+            const int32_t id = top.id[j] == kNoIdx ? -1 : top.id[j];
+            a.z4[kTop * v + j] = top.z[j];
+            a.i4[kTop * v + j] = id;
+            a.seed[j * n + v] = id;
+        }
+        const int64_t deg2 = 2 * cn + cz;
+        if (a.neg) a.neg[v] = (int32_t)cn;
+        if (a.zero) a.zero[v] = (int32_t)cz;
+        if (a.step) a.step[v] = st;
+        sumlam = (unsigned long long)lamv;
+        rowneg = (unsigned long long)rn;
+        unsat = (top.z[1] > 0 || top.z[2] < 0) ? 1 : 0;
+        bad = deg2 != 4 ? 1 : 0;
+        nonzero = st != 0 ? 1 : 0;
+        maxstep = st < 0 ? -st : st;
+        maxabs = nxt < 0 ? -nxt : nxt;
+        hsh = mix64((uint64_t)lamv ^ (0x9E3779B97F4A7C15ULL * (uint64_t)(v + 1)));
+    }
+    sumlam = block_reduce<unsigned long long, false>(sumlam, red);
+    rowneg = block_reduce<unsigned long long, false>(rowneg, red);
+    unsat = block_reduce<unsigned long long, false>(unsat, red);
+    bad = block_reduce<unsigned long long, false>(bad, red);
+    nonzero = block_reduce<unsigned long long, false>(nonzero, red);
+    hsh = block_reduce<unsigned long long, false>(hsh, red);
+    maxstep = (long long)block_reduce<unsigned long long, true>((unsigned long long)maxstep, red);
+    maxabs = (long long)block_reduce<unsigned long long, true>((unsigned long long)maxabs, red);
+    if (threadIdx.x == 0) {
+        atomicAdd(&ctrl->acc_sumlam, sumlam);
+        atomicAdd(&ctrl->acc_rowneg, rowneg);
+        atomicAdd(&ctrl->acc_unsat, unsat);
+        atomicAdd(&ctrl->acc_bad, bad);
+        atomicAdd(&ctrl->acc_nonzero, nonzero);
+        atomicAdd(&ctrl->acc_hash, hsh);
+        atomicMax((unsigned long long *)&ctrl->acc_maxstep, (unsigned long long)maxstep);
+        atomicMax((unsigned long long *)&ctrl->acc_maxabs_next, (unsigned long long)maxabs);
+        __threadfence();
+        const unsigned prev = atomicAdd(&ctrl->blocks_done, 1u);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last || threadIdx.x != 0) return;
+
+    // last block: every other block's atomics are visible
+    __threadfence();
+    const long long k = a.k;
+    const long long sl = (long long)atomicAdd(&ctrl->acc_sumlam, 0ULL);
+    const long long rnsum = (long long)atomicAdd(&ctrl->acc_rowneg, 0ULL);
+    const long long un = (long long)atomicAdd(&ctrl->acc_unsat, 0ULL);
+    const long long bd = (long long)atomicAdd(&ctrl->acc_bad, 0ULL);
+    const long long nz = (long long)atomicAdd(&ctrl->acc_nonzero, 0ULL);
+    const unsigned long long hh = atomicAdd(&ctrl->acc_hash, 0ULL);
+    const long long ms = (long long)atomicAdd((unsigned long long *)&ctrl->acc_maxstep, 0ULL);
+    const long long mx = (long long)atomicAdd((unsigned long long *)&ctrl->acc_maxabs_next, 0ULL);
+    // each unordered pair sits in two rows
+    const long long dual2 = 2 * sl + rnsum / 2;
+    if (a.trace && k < ctrl->trace_cap) {
+        long long *rec = (long long *)a.trace + kTraceW * k;
+        rec[0] = k; rec[1] = dual2; rec[2] = un; rec[3] = bd;
+        rec[4] = ms; rec[5] = nz; rec[6] = (long long)hh; rec[7] = sl;
+    }
+    if (ctrl->best_k < 0 || dual2 > ctrl->best_dual2) { ctrl->best_dual2 = dual2; ctrl->best_k = k; }
+    long long stop = 0;
+    if (bd == 0) stop = 1;                              // trivial
+    else if (nz == 0) stop = 2;                         // fixed
+    else if (k >= 2 && hh == ctrl->h2) stop = 3;        // cycle
+    else if (k >= ctrl->max_iters) stop = 4;            // cap
+    else if (mx >= kLamLimit) { stop = 4; ctrl->overflow = 1; }
+    ctrl->k_last = k;
+    ctrl->dual2_last = dual2;
+    if (stop) {
+        ctrl->stop = stop;
+        ctrl->kstar = (stop == 1 || stop == 2) ? k : ctrl->best_k;
+        ctrl->done = 1;
+    } else {
+        ctrl->h2 = ctrl->h1;
+        ctrl->h1 = hh;
+    }
+    ctrl->maxabs_lam = mx;
+    atomicExch(&ctrl->acc_sumlam, 0ULL);
+    atomicExch(&ctrl->acc_rowneg, 0ULL);
+    atomicExch(&ctrl->acc_unsat, 0ULL);
+    atomicExch(&ctrl->acc_bad, 0ULL);
+    atomicExch(&ctrl->acc_nonzero, 0ULL);
+    atomicExch(&ctrl->acc_hash, 0ULL);
+    atomicExch((unsigned long long *)&ctrl->acc_maxstep, 0ULL);
+    atomicExch((unsigned long long *)&ctrl->acc_maxabs_next, 0ULL);
+    __threadfence();
+    atomicExch(&ctrl->blocks_done, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_minmax_init(int32_t *out4)
+{
+    if (threadIdx.x == 0) { out4[0] = INT_MAX; out4[1] = INT_MIN; out4[2] = INT_MAX; out4[3] = INT_MIN; }
+}
+
+__global__ __launch_bounds__(kBlock) void k_minmax(const int32_t *xy, int64_t n, int32_t *out4)
+{
+    int32_t mnx = INT_MAX, mxx = INT_MIN, mny = INT_MAX, mxy = INT_MIN;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const int32_t x = xy[2 * i], y = xy[2 * i + 1];
+        mnx = min(mnx, x); mxx = max(mxx, x); mny = min(mny, y); mxy = max(mxy, y);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mnx = min(mnx, __shfl_xor(mnx, o, 64)); mxx = max(mxx, __shfl_xor(mxx, o, 64));
+        mny = min(mny, __shfl_xor(mny, o, 64)); mxy = max(mxy, __shfl_xor(mxy, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&out4[0], mnx); atomicMax(&out4[1], mxx);
+        atomicMin(&out4[2], mny); atomicMax(&out4[3], mxy);
+    }
+}
+
+// centred float coordinates; q and h filled by k_set_lam
+__global__ __launch_bounds__(kBlock) void k_prep(const int32_t *xy, int64_t n, int32_t cx, int32_t cy,
+                                                 float4 *col, unsigned int *xy2max_bits)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    float r2 = 0.0f;
+    if (i < n) {
+        const float x = (float)(xy[2 * i] - cx), y = (float)(xy[2 * i + 1] - cy);
+        col[i] = make_float4(x, y, 0.0f, x * x + y * y);
+        r2 = fmaf(x, x, y * y);
+        // round the bound up by a relative 2^-22 so it is >= the exact value
+        r2 = r2 * (1.0f + 0x1p-22f) + 1.0f;
+    }
+    for (int o = 32; o > 0; o >>= 1) r2 = fmaxf(r2, __shfl_xor(r2, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(xy2max_bits, __float_as_uint(r2));
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_lam(const int64_t *lam, int64_t n, float4 *col, Ctrl *ctrl)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long ab = 0;
+    if (i < n) {
+        const int64_t l = lam[i];
+        float4 cv = col[i];
+        const float h = (float)(0.5 * (double)l);
+        cv.z = h;
+        cv.w = fmaf(cv.x, cv.x, fmaf(cv.y, cv.y, -h * h));
+        col[i] = cv;
+        ab = (unsigned long long)(l < 0 ? -l : l);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(ab, o, 64);
+        ab = y > ab ? y : ab;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long *)&ctrl->maxabs_lam, ab);
+}
+
+__global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap)
+{
+    if (threadIdx.x != 0) return;
+    Ctrl c;
+    unsigned char *p = (unsigned char *)&c;
+    for (size_t i = 0; i < sizeof(Ctrl); ++i) p[i] = 0;
+    c.best_k = -1;
+    c.best_dual2 = LLONG_MIN;
+    c.kstar = -1;
+    c.k_last = -1;
+    c.max_iters = max_iters;
+    c.trace_cap = trace_cap;
+    *ctrl = c;
+}
+
+// ---------------------------------------------------------------------------
+// trivial x (eq. 7) and compaction
+// ---------------------------------------------------------------------------
+
+// slot (v, j): edge {v, u} of v's j-th smallest entry when Z <= 0 and v < u
+// (each such edge is in the top-4 of both endpoints once every trivial
+// degree is 2, so the lower endpoint emits it exactly once)
+__global__ __launch_bounds__(kBlock) void k_extract_trivial(const int64_t *z4, const int32_t *i4, int64_t n,
+                                                            int32_t *su, int32_t *sv, uint8_t *sx)
+{
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= kTop * n) return;
+    const int64_t v = s / kTop;
+    const int64_t z = z4[s];
+    const int32_t u = i4[s];
+    if (u > v && u < n && z <= 0) { su[s] = (int32_t)v; sv[s] = u; sx[s] = z < 0 ? 2 : 1; }
+    else { su[s] = -1; sv[s] = -1; sx[s] = 0; }
+}
+
+__device__ __forceinline__ int block_excl_scan(int flag, int *wbuf, int *total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long bal = __ballot(flag);
+    const int below = __popcll(bal & ((1ULL << lane) - 1ULL));
+    if (lane == 0) wbuf[w] = __popcll(bal);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < kBlock / 64; ++i) { if (i < w) off += wbuf[i]; tot += wbuf[i]; }
+    *total = tot;
+    return off + below;
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_count(const int32_t *su, int64_t ns, int32_t *bcount)
+{
+    __shared__ int wbuf[kBlock / 64];
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int flag = (s < ns && su[s] >= 0) ? 1 : 0;
+    int tot;
+    block_excl_scan(flag, wbuf, &tot);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+}
+
+// exclusive scan of nb block counts in one block; total to *count
+__global__ __launch_bounds__(1024) void k_compact_scan(int32_t *bcount, int64_t nb, int64_t *count)
+{
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = min(nb, b0 + per);
+    int64_t s = 0;
+    for (int64_t b = b0; b < b1; ++b) s += bcount[b];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < 1024; ++i) { const int64_t x = part[i]; part[i] = acc; acc += x; }
+        *count = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int64_t b = b0; b < b1; ++b) { const int32_t x = bcount[b]; bcount[b] = (int32_t)acc; acc += x; }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact_scatter(const int32_t *su, const int32_t *sv, const uint8_t *sx,
+                                                            int64_t ns, const int32_t *boff, int32_t *eu,
+                                                            int32_t *ev, uint8_t *ex)
+{
+    __shared__ int wbuf[kBlock / 64];
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int flag = (s < ns && su[s] >= 0) ? 1 : 0;
+    int tot;
+    const int pos = block_excl_scan(flag, wbuf, &tot);
+    if (flag) {
+        const int64_t o = (int64_t)boff[blockIdx.x] + pos;
+        eu[o] = su[s]; ev[o] = sv[s]; ex[o] = sx[s];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// certificate
+// ---------------------------------------------------------------------------
+
+// sum over ordered pairs of min(0, Z) (theta = 0: only Z <= 0 matters)
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_cert_scan(CertScanArgs a)
+{
+    __shared__ float4 sc[kTile];
+    __shared__ unsigned long long red[kBlock / 64];
+    const int t = threadIdx.x;
+    const int64_t n = a.n;
+    const int64_t c0 = (int64_t)blockIdx.y * a.slice_len;
+    const int64_t c1 = min(n, c0 + a.slice_len);
+    const float colmax = col_bound(a.xy2max, a.ctrl->maxabs_lam);
+    Row rw[R];
+    int64_t rn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t v = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + t;
+        rw[r].v = v;
+        rn[r] = 0;
+        if (v < n) {
+            const float4 cv = a.col[v];
+            rw[r].xv = cv.x; rw[r].yv = cv.y;
+            rw[r].lamv = a.lam[v];
+            rw[r].theta = 0;
+            set_filter(rw[r], colmax);
+        } else {
+            rw[r].xv = rw[r].yv = 0.0f; rw[r].lamv = 0; rw[r].theta = 0;
+            rw[r].a = rw[r].b = rw[r].c = 0.0f; rw[r].thr = -INFINITY;
+        }
+    }
+    for (int64_t tile = c0; tile < c1; tile += kTile) {
+        __syncthreads();
+        const int64_t cc = tile + t;
+        sc[t] = (cc < c1) ? a.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        __syncthreads();
+        const int64_t ntile = min((int64_t)kTile, c1 - tile);
+        for (int g = 0; g < ntile; g += kGroup) {
+            float m[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) m[r] = INFINITY;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const float4 cd = sc[g + q];
+#pragma unroll
+                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (m[r] <= rw[r].thr) {
+                    for (int q = 0; q < kGroup; ++q) {
+                        const int64_t u = tile + g + q;
+                        if (u >= c1 || u == rw[r].v) continue;
+                        const float4 cd = sc[g + q];
+                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
+                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lam[u]);
+                        if (z < 0) rn[r] += z;
+                    }
+                }
+            }
+        }
+    }
+    int64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) s += rn[r];
+    const unsigned long long tot = block_reduce<unsigned long long, false>((unsigned long long)s, red);
+    if (threadIdx.x == 0 && tot != 0) atomicAdd(&a.acc[0], tot);
+}
+
+// every pair (v, u) with Z_vu <= theta_v, reported as (min, max)
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_collect(CollectArgs a)
+{
+    __shared__ float4 sc[kTile];
+    const int t = threadIdx.x;
+    const int64_t n = a.n;
+    const int64_t c0 = (int64_t)blockIdx.y * a.slice_len;
+    const int64_t c1 = min(n, c0 + a.slice_len);
+    const float colmax = col_bound(a.xy2max, a.ctrl->maxabs_lam);
+    Row rw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t v = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + t;
+        rw[r].v = v;
+        if (v < n) {
+            const float4 cv = a.col[v];
+            rw[r].xv = cv.x; rw[r].yv = cv.y;
+            rw[r].lamv = a.lam[v];
+            int64_t th = a.theta;
+            if (a.seed) {
+                int64_t mx = INT64_MIN;
+                int cnt = 0;
+#pragma unroll
+                for (int j = 0; j < kTop; ++j) {
+                    const int32_t u = a.seed[j * n + v];
+                    if (u >= 0 && u < n && u != v) {
+                        const float4 cu = a.col[u];
+                        const int64_t z = exact_z(cv.x, cv.y, rw[r].lamv, cu.x, cu.y, a.lam[u]);
+                        mx = z > mx ? z : mx;
+                        ++cnt;
+                    }
+                }
+                if (cnt == kTop) th = (mx > 0 ? mx : 0) + a.slack;
+            }
+            rw[r].theta = th;
+            set_filter(rw[r], colmax);
+        } else {
+            rw[r].xv = rw[r].yv = 0.0f; rw[r].lamv = 0; rw[r].theta = 0;
+            rw[r].a = rw[r].b = rw[r].c = 0.0f; rw[r].thr = -INFINITY;
+        }
+    }
+    for (int64_t tile = c0; tile < c1; tile += kTile) {
+        __syncthreads();
+        const int64_t cc = tile + t;
+        sc[t] = (cc < c1) ? a.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        __syncthreads();
+        const int64_t ntile = min((int64_t)kTile, c1 - tile);
+        for (int g = 0; g < ntile; g += kGroup) {
+            float m[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) m[r] = INFINITY;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const float4 cd = sc[g + q];
+#pragma unroll
+                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (m[r] <= rw[r].thr) {
+                    for (int q = 0; q < kGroup; ++q) {
+                        const int64_t u = tile + g + q;
+                        if (u >= c1 || u == rw[r].v) continue;
+                        const float4 cd = sc[g + q];
+                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
+                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lam[u]);
+                        if (z > rw[r].theta) continue;
+                        const unsigned long long slot = atomicAdd(a.count, 1ULL);
+                        if ((int64_t)slot < a.cap) {
+                            const int32_t lo = (int32_t)min(rw[r].v, u), hi = (int32_t)max(rw[r].v, u);
+                            a.out[slot] = make_int2(lo, hi);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// acc: [0] sum min(0,Z) ordered, [1] primal2, [2] #violations, [3] sum Lam
+__global__ __launch_bounds__(kBlock) void k_cert_edges(const int32_t *xy, int64_t n, int64_t m, const int32_t *eu,
+                                                       const int32_t *ev, const uint8_t *ex2, int32_t *deg,
+                                                       int32_t *cnt, int32_t *nb, unsigned long long *acc)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= m) return;
+    const int64_t u = eu[e], v = ev[e];
+    const int x2 = ex2[e];
+    if (u < 0 || v < 0 || u >= n || v >= n || u == v || (x2 != 1 && x2 != 2)) {
+        atomicAdd(&acc[2], 1ULL);
+        return;
+    }
+    const int64_t dx = (int64_t)xy[2 * u] - xy[2 * v];
+    const int64_t dy = (int64_t)xy[2 * u + 1] - xy[2 * v + 1];
+    const int64_t c = nint_sqrt(dx * dx + dy * dy);
+    atomicAdd(&acc[1], (unsigned long long)(c * x2));
+    atomicAdd(&deg[u], x2);
+    atomicAdd(&deg[v], x2);
+    const int su = atomicAdd(&cnt[u], 1);
+    if (su < kTop) nb[kTop * u + su] = (int32_t)v;
+    const int sv = atomicAdd(&cnt[v], 1);
+    if (sv < kTop) nb[kTop * v + sv] = (int32_t)u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cert_nodes(const int64_t *lam, int64_t n, const int32_t *deg,
+                                                       const int32_t *cnt, const int32_t *nb,
+                                                       unsigned long long *acc)
+{
+    __shared__ unsigned long long red[kBlock / 64];
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long bad = 0, sl = 0;
+    if (v < n) {
+        sl = (unsigned long long)lam[v];
+        const int c = cnt[v];
+        if (deg[v] != 4 || c > kTop) bad = 1;
+        else {
+            for (int i = 0; i < c; ++i)
+                for (int j = i + 1; j < c; ++j)
+                    if (nb[kTop * v + i] == nb[kTop * v + j]) bad = 1;
+        }
+    }
+    bad = block_reduce<unsigned long long, false>(bad, red);
+    sl = block_reduce<unsigned long long, false>(sl, red);
+    if (threadIdx.x == 0) {
+        if (bad) atomicAdd(&acc[2], bad);
+        atomicAdd(&acc[3], sl);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_minmax(const int32_t *xy, int64_t n, int32_t *out4, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(64), 0, st, out4);
+    unsigned nb = blocks_for(n, kBlock);
+    if (nb > 1024) nb = 1024;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(k_minmax, dim3(nb), dim3(kBlock), 0, st, xy, n, out4);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const int32_t *xy, int64_t n, int32_t cx, int32_t cy, float4 *col, float *xy2max_dev,
+                       hipStream_t st)
+{
+    hipError_t e = hipMemsetAsync(xy2max_dev, 0, sizeof(float), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prep, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, xy, n, cx, cy, col,
+                       (unsigned int *)xy2max_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_lam(const int64_t *lam, int64_t n, float4 *col, Ctrl *ctrl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_lam, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam, n, col, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, max_iters, trace_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const ScanArgs &a, int64_t nslices, int rows_per_thread, hipStream_t st)
+{
+    const unsigned gy = (unsigned)nslices;
+    switch (rows_per_thread) {
+    case 1:
+        hipLaunchKernelGGL(k_scan<1>, dim3(blocks_for(a.n, kBlock), gy), dim3(kBlock), 0, st, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_scan<2>, dim3(blocks_for(a.n, 2 * kBlock), gy), dim3(kBlock), 0, st, a);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_scan<4>, dim3(blocks_for(a.n, 4 * kBlock), gy), dim3(kBlock), 0, st, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_update, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_trivial(const int64_t *z4, const int32_t *i4, int64_t n, int32_t *su, int32_t *sv,
+                                  uint8_t *sx, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_extract_trivial, dim3(blocks_for(kTop * n, kBlock)), dim3(kBlock), 0, st, z4, i4, n, su,
+                       sv, sx);
+    return hipGetLastError();
+}
+
+int64_t compact_block_tmp_len(int64_t nslots) { return (nslots + kBlock - 1) / kBlock; }
+
+hipError_t launch_compact(const int32_t *su, const int32_t *sv, const uint8_t *sx, int64_t ns, int32_t *eu,
+                          int32_t *ev, uint8_t *ex, int64_t *count_dev, int32_t *btmp, hipStream_t st)
+{
+    const unsigned nb = blocks_for(ns, kBlock);
+    if (nb == 0) return hipMemsetAsync(count_dev, 0, sizeof(int64_t), st);
+    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, st, su, ns, btmp);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, btmp, (int64_t)nb, count_dev);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, st, su, sv, sx, ns, btmp, eu, ev, ex);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect(const CollectArgs &a, int64_t nslices, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_collect<2>, dim3(blocks_for(a.n, 2 * kBlock), (unsigned)nslices), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cert_scan(const CertScanArgs &a, int64_t nslices, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cert_scan<2>, dim3(blocks_for(a.n, 2 * kBlock), (unsigned)nslices), dim3(kBlock), 0, st,
+                       a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cert_edges(const int32_t *xy, int64_t n, int64_t m, const int32_t *eu, const int32_t *ev,
+                             const uint8_t *ex2, int32_t *deg, int32_t *cnt, int32_t *nb, unsigned long long *acc,
+                             hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cert_edges, dim3(blocks_for(m, kBlock)), dim3(kBlock), 0, st, xy, n, m, eu, ev, ex2, deg,
+                       cnt, nb, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cert_nodes(const int64_t *lam, int64_t n, const int32_t *deg, const int32_t *cnt,
+                             const int32_t *nb, unsigned long long *acc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cert_nodes, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam, n, deg, cnt, nb, acc);
+    return hipGetLastError();
+}
+
+}  // namespace f2m

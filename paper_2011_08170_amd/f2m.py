@@ -1,0 +1,205 @@
+"""ctypes binding of libf2m (include/f2m.h): argument marshalling only.
+
+Every computation runs in libf2m.so (HIP kernels for gfx950 plus its host
+runtime).  There is no fallback: if the library is missing or no GPU is
+present, the calls raise.  Device arrays are passed as torch CUDA tensors
+(torch provides device memory only) or raw device pointers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libf2m.so")
+
+OK, NOT_CERTIFIED = 0, 1
+STATUS = {0: "ok", 1: "not certified", -1: "invalid argument", -2: "coordinate span out of range",
+          -3: "infeasible (n < 3)", -4: "out of memory", -5: "device error", -6: "buffer too small",
+          -7: "multiplier overflow"}
+STOP_NAMES = {0: "none", 1: "trivial", 2: "fixed", 3: "cycle", 4: "cap"}
+FINISH = {"none": 0, "exact": 1}
+TRACE_W = 8
+TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
+SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
+           "f2m_result_free", "f2m_status_str", "f2m_last_error")
+
+
+class F2MError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class Opts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("rule_version", C.c_uint32), ("graph", C.c_int32),
+                ("warm", C.c_int32), ("lambda2_init", C.c_void_p), ("max_iters", C.c_int64),
+                ("finish", C.c_int32), ("coords_on_device", C.c_int32), ("record_trace", C.c_int32),
+                ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("hip_stream", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("n", C.c_int64), ("iterations", C.c_int64), ("kstar", C.c_int64), ("stop", C.c_int32),
+                ("certified", C.c_int32), ("lambda2", C.POINTER(C.c_int64)),
+                ("lambda2_gdp", C.POINTER(C.c_int64)), ("n_edges", C.c_int64),
+                ("edge_u", C.POINTER(C.c_int32)), ("edge_v", C.POINTER(C.c_int32)),
+                ("edge_x2", C.POINTER(C.c_uint8)), ("primal2", C.c_int64), ("dual2", C.c_int64),
+                ("dual2_gdp", C.c_int64), ("finish_paths", C.c_int64), ("finish_rounds", C.c_int64),
+                ("trace_len", C.c_int64), ("trace", C.POINTER(C.c_int64)), ("seconds", C.c_double * 6),
+                ("scan_ms", C.c_double), ("scan_launches", C.c_int64), ("scan_rows", C.c_int32),
+                ("pad0", C.c_int32), ("scan_slices", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libf2m.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libf2m.so is not built: run `python -m paper_2011_08170_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        p, i64 = C.c_void_p, C.c_int64
+        L.f2m_opts_default.restype = None
+        L.f2m_opts_default.argtypes = [C.POINTER(Opts)]
+        L.f2m_create.restype = C.c_int
+        L.f2m_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
+        L.f2m_destroy.restype = None
+        L.f2m_destroy.argtypes = [p]
+        L.f2m_solve.restype = C.c_int
+        L.f2m_solve.argtypes = [p, p, i64, C.POINTER(Opts), C.POINTER(Result)]
+        L.f2m_gdp_step.restype = C.c_int
+        L.f2m_gdp_step.argtypes = [p, p, i64, p, p, p, p, p, p, p, p]
+        L.f2m_certify.restype = C.c_int
+        L.f2m_certify.argtypes = [p, p, i64, p, i64, p, p, p, p]
+        L.f2m_result_free.restype = None
+        L.f2m_result_free.argtypes = [C.POINTER(Result)]
+        L.f2m_status_str.restype = C.c_char_p
+        L.f2m_status_str.argtypes = [C.c_int]
+        L.f2m_last_error.restype = C.c_char_p
+        L.f2m_last_error.argtypes = [p]
+        _lib = L
+    return _lib
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or an int), None for None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Context:
+    """One libf2m context (device + stream)."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        st = lib().f2m_create(C.byref(self._h), int(device))
+        if st != OK:
+            raise F2MError(st, "f2m_create(device=%d) failed" % device)
+
+    def close(self):
+        if self._h:
+            lib().f2m_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st):
+        if st < 0:
+            raise F2MError(st, lib().f2m_last_error(self._h).decode())
+        return st
+
+    def solve(self, coords, *, max_iters=100000, finish="exact", lambda2_init=None, trace=False,
+              chunk=0, stream=None, time_kernels=False):
+        """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
+        array on the host or a contiguous int32 device tensor."""
+        o = Opts()
+        lib().f2m_opts_default(C.byref(o))
+        o.max_iters = int(max_iters)
+        o.finish = FINISH[finish]
+        o.record_trace = 1 if trace else 0
+        o.chunk = int(chunk)
+        o.time_kernels = 1 if time_kernels else 0
+        keep = []
+        if lambda2_init is not None:
+            l0 = _np(lambda2_init, np.int64)
+            keep.append(l0)
+            o.warm = 1
+            o.lambda2_init = l0.ctypes.data
+        if stream is not None:
+            o.hip_stream = stream
+        if hasattr(coords, "is_cuda") and coords.is_cuda:
+            o.coords_on_device = 1
+            n = coords.shape[0]
+            ptr = _dptr(coords)
+        else:
+            xy = _np(coords, np.int32)
+            keep.append(xy)
+            n = xy.shape[0]
+            ptr = xy.ctypes.data
+        res = Result()
+        st = self._check(lib().f2m_solve(self._h, ptr, n, C.byref(o), C.byref(res)))
+        try:
+            m = res.n_edges
+            out = dict(
+                status=STATUS[st], certified=bool(res.certified), stop=STOP_NAMES.get(res.stop, "?"),
+                iterations=res.iterations, kstar=res.kstar, primal2=res.primal2, dual2=res.dual2,
+                dual2_gdp=res.dual2_gdp, finish_paths=res.finish_paths, finish_rounds=res.finish_rounds,
+                lambda2=np.ctypeslib.as_array(res.lambda2, (n,)).copy(),
+                lambda2_gdp=np.ctypeslib.as_array(res.lambda2_gdp, (n,)).copy(),
+                edge_u=np.ctypeslib.as_array(res.edge_u, (max(m, 1),))[:m].copy(),
+                edge_v=np.ctypeslib.as_array(res.edge_v, (max(m, 1),))[:m].copy(),
+                edge_x2=np.ctypeslib.as_array(res.edge_x2, (max(m, 1),))[:m].copy(),
+                seconds=dict(zip(("setup", "warm", "gdp", "finish", "certify", "total"), list(res.seconds))),
+                scan_ms=res.scan_ms, scan_launches=res.scan_launches, scan_rows=res.scan_rows,
+                scan_slices=res.scan_slices,
+            )
+            if res.trace_len:
+                out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(
+                    res.trace_len, TRACE_W).copy()
+        finally:
+            lib().f2m_result_free(C.byref(res))
+        return out
+
+    def gdp_step(self, coords, lam_in, lam_out, z4=None, i4=None, neg=None, zero=None, step=None):
+        """One GDP iteration on device tensors; returns the record dict."""
+        n = coords.shape[0]
+        rec = np.zeros(TRACE_W, np.int64)
+        self._check(lib().f2m_gdp_step(self._h, _dptr(coords), n, _dptr(lam_in), _dptr(lam_out), _dptr(z4),
+                                       _dptr(i4), _dptr(neg), _dptr(zero), _dptr(step),
+                                       rec.ctypes.data_as(C.c_void_p)))
+        r = dict(zip(TRACE_FIELDS, (int(x) for x in rec)))
+        r["hash"] &= (1 << 64) - 1
+        return r
+
+    def certify(self, coords, lam, eu, ev, ex2):
+        """Certificate on device tensors: dict(primal2, dual2, feasible, certified)."""
+        n = coords.shape[0]
+        m = eu.shape[0]
+        out = np.zeros(4, np.int64)
+        self._check(lib().f2m_certify(self._h, _dptr(coords), n, _dptr(lam), m, _dptr(eu) if m else None,
+                                      _dptr(ev) if m else None, _dptr(ex2) if m else None,
+                                      out.ctypes.data_as(C.c_void_p)))
+        return dict(primal2=int(out[0]), dual2=int(out[1]), feasible=bool(out[2]), certified=bool(out[3]))

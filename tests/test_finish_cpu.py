@@ -1,0 +1,55 @@
+"""The host exact finish of libf2m (f2m_finish.cpp), run on the CPU with a
+brute-force pair source, against the oracle's exact optimum.  The result
+must be a certificate (primal2 == dual2 on the complete graph) from any
+starting Lam: zero, random, or a GDP fixed point."""
+import numpy as np
+import pytest
+
+from oracle import core
+from paper_2011_08170_amd import instances as I
+from tests.native import harness
+
+
+@pytest.fixture(scope="module")
+def L(tmp_path_factory):
+    return harness.build(tmp_path_factory.mktemp("finish"))
+
+
+def check(L, xy, lam0):
+    lam, eu, ev, ex, st = harness.finish(L, xy, lam0)
+    c = core.certify(xy, lam, eu, ev, ex)
+    assert c["certified"], (c, st)
+    assert c["primal2"] == core.exact_opt2(xy)
+    assert np.all(eu < ev)
+    return st
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 7, 12])
+def test_small_from_zero(L, n):
+    for seed in range(3):
+        xy = I.uniform(n, 300, 10 * n + seed)
+        check(L, xy, np.zeros(n, np.int64))
+
+
+def test_from_gdp_fixed_point(L):
+    for seed in (1, 2, 3):
+        xy = I.uniform(200, 100000, seed)
+        r = core.gdp_solve(xy)
+        st = check(L, xy, r["lam"])
+        assert st["rounds"] <= 4
+
+
+def test_from_random_and_ties(L):
+    rnd = np.random.default_rng(4)
+    for xy in (I.lattice_jitter(8, 9, 20, 2, 1), I.with_duplicates(60, 400, 8, 2), I.lattice(6, 6, 5),
+               I.clustered(150, 100000, 3, centres=4)):
+        n = len(xy)
+        check(L, xy, rnd.integers(-50, 200, n).astype(np.int64))
+        check(L, xy, core.gdp_solve(xy)["lam"])
+
+
+def test_odd_lattice_half_values(L):
+    # 3x3 lattice: odd n, so no all-integer 2-factor of unit edges fits
+    # every node; the optimum has half values or longer edges
+    xy = I.lattice(3, 3, 10)
+    check(L, xy, np.zeros(9, np.int64))

@@ -1,0 +1,161 @@
+"""GPU parity: libf2m (HIP, gfx950) against the CPU oracle, bit for bit.
+
+Every comparison is exact: the method is integer arithmetic throughout
+(Lam = 2*lambda int64, exact EUC_2D lengths), so the tolerance is zero."""
+import numpy as np
+import pytest
+
+from oracle import core
+from paper_2011_08170_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2011_08170_amd import f2m
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = f2m.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def gpu_step(ctx, xy, lam):
+    n = len(xy)
+    out = dict(lam=torch.empty(n, dtype=torch.int64, device="cuda"),
+               z4=torch.empty(4 * n, dtype=torch.int64, device="cuda"),
+               i4=torch.empty(4 * n, dtype=torch.int32, device="cuda"),
+               neg=torch.empty(n, dtype=torch.int32, device="cuda"),
+               zero=torch.empty(n, dtype=torch.int32, device="cuda"),
+               step=torch.empty(n, dtype=torch.int64, device="cuda"))
+    rec = ctx.gdp_step(dev(xy, np.int32), dev(lam, np.int64), out["lam"], out["z4"], out["i4"], out["neg"],
+                       out["zero"], out["step"])
+    h = {k: v.cpu().numpy() for k, v in out.items()}
+    h["z4"] = h["z4"].reshape(n, 4)
+    h["i4"] = h["i4"].reshape(n, 4)
+    return rec, h
+
+
+CASES = [
+    ("n4", lambda: I.uniform(4, 1000, 1)),
+    ("n5", lambda: I.uniform(5, 1000, 2)),
+    ("n257", lambda: I.uniform(257, 100000, 3)),
+    ("c1_1000", lambda: I.uniform(1000, 100000, 1)),
+    ("ragged_3001", lambda: I.uniform(3001, 1000000, 4)),
+    ("ties_lattice", lambda: I.lattice_jitter(30, 33, 50, 3, 5)),
+    ("dups", lambda: I.with_duplicates(700, 5000, 60, 6)),
+    ("clustered_2000", lambda: I.clustered(2000, 1000000, 7)),
+    ("full_span", lambda: np.array(I.uniform(600, 1 << 20, 8), dtype=np.int32) - (1 << 19)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_gdp_step_matches_oracle(ctx, name, make):
+    xy = make()
+    n = len(xy)
+    rnd = np.random.default_rng(n)
+    for lam in (np.zeros(n, np.int64), rnd.integers(-3000, 9000, n).astype(np.int64)):
+        rec, g = gpu_step(ctx, xy, lam)
+        o = core.gdp_iter(xy, lam)
+        assert np.array_equal(g["z4"], o["z4"]), name
+        assert np.array_equal(g["i4"], np.where(o["i4"] < 0, -1, o["i4"])), name
+        assert np.array_equal(g["neg"], o["neg"]) and np.array_equal(g["zero"], o["zero"])
+        assert np.array_equal(g["step"], o["step"])
+        assert np.array_equal(g["lam"], lam + o["step"])
+        for f in ("dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam"):
+            assert rec[f] == o["rec"][f], (name, f)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_solve_trajectory_c1(ctx, seed):
+    # n = 1000, uniform in [0, 10^5)^2: the trajectory, the stop and Lam*
+    xy = I.uniform(1000, 100000, seed)
+    o = core.gdp_solve(xy)
+    g = ctx.solve(xy, trace=True, finish="none")
+    assert g["iterations"] == o["iters"] and g["stop"] == o["stop"] and g["kstar"] == o["kstar"]
+    assert np.array_equal(g["trace"], o["trace"])
+    assert np.array_equal(g["lambda2_gdp"], o["lam"])
+
+
+@pytest.mark.parametrize("name,make", [("square", lambda: I.square4()), ("tri3", lambda: I.triangles(3)),
+                                       ("c1", lambda: I.uniform(1000, 100000, 1)),
+                                       ("lattice", lambda: I.lattice_jitter(20, 21, 40, 2, 3)),
+                                       ("clustered", lambda: I.clustered(800, 1000000, 2, centres=20))])
+def test_solve_certified_optimum(ctx, name, make):
+    xy = make()
+    g = ctx.solve(xy, trace=True)
+    assert g["certified"] and g["status"] == "ok", g["status"]
+    assert g["primal2"] == g["dual2"] == core.exact_opt2(xy)
+    c = core.certify(xy, g["lambda2"], g["edge_u"], g["edge_v"], g["edge_x2"])
+    assert c["certified"] and c["primal2"] == g["primal2"]
+    o = core.gdp_solve(xy)
+    assert np.array_equal(g["trace"], o["trace"])
+
+
+def test_certify_kernel_matches_oracle(ctx):
+    rnd = np.random.default_rng(0)
+    for n, seed in [(50, 1), (333, 2), (900, 3)]:
+        xy = I.uniform(n, 20000, seed)
+        opt2, x2, lam = core.exact_opt2(xy, want_x=True)
+        eu, ev, ex = core.dense_to_edges(x2)
+        variants = [(lam, eu, ev, ex), (lam + rnd.integers(-5, 6, n), eu, ev, ex),
+                    (lam, eu[1:], ev[1:], ex[1:]), (lam, eu, ev, np.where(np.arange(len(ex)) == 0, 3 - ex, ex))]
+        for lv, a, b, x in variants:
+            o = core.certify(xy, lv, a, b, x)
+            g = ctx.certify(dev(xy, np.int32), dev(lv, np.int64), dev(a, np.int32), dev(b, np.int32),
+                            dev(x, np.uint8))
+            assert g == o
+
+
+def test_n3_and_errors(ctx):
+    from paper_2011_08170_amd import f2m
+    g = ctx.solve(np.array([[0, 0], [30, 0], [0, 40]], np.int32))
+    assert g["certified"] and g["primal2"] == 240
+    with pytest.raises(f2m.F2MError) as e:
+        ctx.solve(np.array([[0, 0], [1, 1]], np.int32))
+    assert e.value.status == -3
+    with pytest.raises(f2m.F2MError) as e:
+        ctx.solve(np.array([[0, 0], [1 << 20, 0], [5, 5], [7, 7]], np.int32))
+    assert e.value.status == -2
+
+
+def test_device_coords_same_as_host(ctx):
+    xy = I.uniform(600, 100000, 9)
+    a = ctx.solve(xy, trace=True)
+    b = ctx.solve(dev(xy, np.int32), trace=True)
+    for k in ("trace", "lambda2", "edge_u", "edge_v", "edge_x2"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_repeat_bitwise(ctx):
+    xy = I.clustered(1500, 1000000, 4)
+    a = ctx.solve(xy, trace=True)
+    b = ctx.solve(xy, trace=True)
+    for k in ("trace", "lambda2", "edge_u", "edge_v", "edge_x2"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_c2_shape_sampled_rows(ctx):
+    # n = 100000 uniform in [0, 10^6)^2, the benchmark's launch shape:
+    # sampled rows of one iteration at a cold and a perturbed Lam
+    xy = I.uniform(100000, 1000000, 1)
+    n = len(xy)
+    rows = np.random.default_rng(1).choice(n, 96, replace=False)
+    rows = np.concatenate([rows, [0, n - 1]])
+    rnd = np.random.default_rng(2)
+    for lam in (np.zeros(n, np.int64), rnd.integers(0, 6000, n).astype(np.int64)):
+        rec, g = gpu_step(ctx, xy, lam)
+        o = core.gdp_rows(xy, lam, rows)
+        assert np.array_equal(g["z4"][rows], o["z4"])
+        assert np.array_equal(g["i4"][rows], o["i4"])
+        assert np.array_equal(g["neg"][rows], o["neg"]) and np.array_equal(g["zero"][rows], o["zero"])
+        assert np.array_equal(g["step"][rows], o["step"])
+        assert rec["sum_lam"] == int(lam.sum())
+        assert rec["hash"] == core.lam_hash(lam)
