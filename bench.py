@@ -26,8 +26,9 @@ METRIC = "time-to-certified F2M optimum (s) + pair-evals/s at n=100k; warm vs co
 # gfx950 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one fp32 op per lane
 # per clock without packed math
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# the scan's float filter: 3 FMAs and 1 min per ordered pair
-OPS_PER_PAIR = 4
+# the scan's float filter per ordered pair: 3 FMAs and half a v_min3 (two
+# comparisons folded into one instruction)
+OPS_PER_PAIR = 3.5
 
 
 def log(*a):
