@@ -27,9 +27,11 @@
  *   s = Z_(2) + Z_(3) over the node's edges (2nd and 3rd smallest),
  *   dLam = sign(s) * floor((|s| + 2) / 4)  (midpoint move damped by 1/2,
  *   rounded half away from zero), every node from the same Lam (Jacobi).
- * The loop stops when every trivial degree is 2 ("trivial"), when every
- * step is 0 ("fixed"), when Lam_k equals Lam_{k-2} by hash ("cycle"), or at
- * max_iters ("cap").
+ * At iteration k the loop stops, tested in this order, when every trivial
+ * degree is 2 ("trivial"); when handoff_div > 0 and (#nodes with
+ * Z_(2) > 0 or Z_(3) < 0) * handoff_div <= n ("handoff": the rest is left to
+ * the exact finish); when every step is 0 ("fixed"); when Lam_k equals
+ * Lam_{k-2} by hash ("cycle"); at k == max_iters ("cap").
  *
  * Ownership: the caller owns every input.  Host arrays inside f2m_result
  * are allocated by the library and released by f2m_result_free.  No
@@ -67,7 +69,8 @@ typedef enum f2m_status {
 enum { F2M_GRAPH_COMPLETE = 0 };
 enum { F2M_WARM_COLD = 0, F2M_WARM_USER = 1 };
 enum { F2M_FINISH_NONE = 0, F2M_FINISH_EXACT = 1 };
-enum { F2M_STOP_TRIVIAL = 1, F2M_STOP_FIXED = 2, F2M_STOP_CYCLE = 3, F2M_STOP_CAP = 4 };
+enum { F2M_STOP_TRIVIAL = 1, F2M_STOP_FIXED = 2, F2M_STOP_CYCLE = 3, F2M_STOP_CAP = 4,
+       F2M_STOP_HANDOFF = 5 };
 
 /* Per-iteration record, F2M_TRACE_W int64 per iteration k:
  *   [0] k  [1] dual2 at Lam_k  [2] #nodes with Z_(2) > 0 or Z_(3) < 0
@@ -83,6 +86,7 @@ typedef struct f2m_opts {
     int32_t warm;                 /* F2M_WARM_COLD (Lam0 = 0) or F2M_WARM_USER */
     const int64_t *lambda2_init;  /* host, n entries, read when warm == USER */
     int64_t max_iters;            /* iteration cap (>= 0) */
+    int64_t handoff_div;          /* hand-off stop (see above); 0 disables it */
     int32_t finish;               /* F2M_FINISH_EXACT: make the result exact
                                      when the trivial x does not certify */
     int32_t coords_on_device;     /* coords_xy argument is a device pointer */
@@ -120,7 +124,8 @@ typedef struct f2m_result {
 } f2m_result;
 
 /* Fills opts with the defaults: rule 1, complete graph, cold start,
- * max_iters 100000, exact finish, host coords, no trace, auto chunk. */
+ * max_iters 100000, handoff_div 300, exact finish, host coords, no trace,
+ * auto chunk. */
 void f2m_opts_default(f2m_opts *opts);
 
 /* Creates a context on HIP device `device` with its own stream. */

@@ -16,8 +16,8 @@ import numpy as np
 
 from . import build as _build
 
-STOP_TRIVIAL, STOP_FIXED, STOP_CYCLE, STOP_CAP = 1, 2, 3, 4
-STOP_NAMES = {1: "trivial", 2: "fixed", 3: "cycle", 4: "cap"}
+STOP_TRIVIAL, STOP_FIXED, STOP_CYCLE, STOP_CAP, STOP_HANDOFF = 1, 2, 3, 4, 5
+STOP_NAMES = {1: "trivial", 2: "fixed", 3: "cycle", 4: "cap", 5: "handoff"}
 TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
 
@@ -43,7 +43,7 @@ def lib():
         L.or_gdp_iter.restype = C.c_int
         L.or_gdp_iter.argtypes = [i64, p, p, p, p, p, p, p, p]
         L.or_gdp_solve.restype = C.c_int
-        L.or_gdp_solve.argtypes = [i64, p, p, i64, p, p, p, p, p, p, p, p]
+        L.or_gdp_solve.argtypes = [i64, p, p, i64, i64, p, p, p, p, p, p, p, p]
         L.or_certify.restype = C.c_int
         L.or_certify.argtypes = [i64, p, p, i64, p, p, p, p]
         L.or_trivial_x.restype = i64
@@ -131,8 +131,9 @@ def gdp_iter(xy, lam):
     return dict(z4=z4, i4=i4, neg=neg, zero=zero, step=st, rec=r)
 
 
-def gdp_solve(xy, lam0=None, max_iters=100000):
-    """GDP rule loop.  Returns dict: lam (Lam*), stop (name), iters,
+def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0):
+    """GDP rule loop (handoff_div > 0: stop once #unsatisfied*div <= n).
+    Returns dict: lam (Lam*), stop (name), iters,
     kstar, trace (iters x TRACE_W int64), z4/i4/neg/zero at the last
     evaluated iterate."""
     xy = _coords(xy)
@@ -142,7 +143,7 @@ def gdp_solve(xy, lam0=None, max_iters=100000):
     iters = C.c_int64(0); stop = C.c_int32(0); kstar = C.c_int64(0)
     z4 = np.empty((n, 4), np.int64); i4 = np.empty((n, 4), np.int32)
     neg = np.empty(n, np.int32); zero = np.empty(n, np.int32)
-    rc = lib().or_gdp_solve(n, _ptr(xy), _ptr(lam), int(max_iters), _ptr(trace), C.byref(iters),
+    rc = lib().or_gdp_solve(n, _ptr(xy), _ptr(lam), int(max_iters), int(handoff_div), _ptr(trace), C.byref(iters),
                             C.byref(stop), C.byref(kstar), _ptr(z4), _ptr(i4), _ptr(neg), _ptr(zero))
     if rc:
         raise RuntimeError("or_gdp_solve failed: %d" % rc)

@@ -57,6 +57,7 @@
 #define OR_STOP_FIXED 2     /* every step is zero */
 #define OR_STOP_CYCLE 3     /* hash of Lam_k equals hash of Lam_{k-2} */
 #define OR_STOP_CAP 4       /* iteration cap reached */
+#define OR_STOP_HANDOFF 5   /* few unsatisfied nodes left: hand over to an exact finish */
 
 /* ------------------------------------------------------------------ */
 /* integer square root and the exact EUC_2D length                     */
@@ -221,16 +222,19 @@ int or_gdp_iter(int64_t n, const int32_t *xy, const int64_t *lam,
 }
 
 /* GDP loop from lam (in/out).  On return lam holds Lam*, the iterate the
- * loop stops on:  the current one for TRIVIAL and FIXED, the iterate with
- * the largest dual2 (earliest on ties) for CYCLE and CAP.
+ * loop stops on:  the current one for TRIVIAL, HANDOFF and FIXED, the
+ * iterate with the largest dual2 (earliest on ties) for CYCLE and CAP.
+ *   handoff_div > 0 stops at the first k with #unsatisfied * handoff_div <= n
+ *   (checked right after the trivial test); 0 disables it.
  *   trace: max_iters+1 rows of OR_TRACE_W (may be NULL); *iters = number of
  *   iterations evaluated (records written); *stop = reason; *kstar = index
  *   of Lam*.  z4/i4/neg/zero describe Lam_k of the last evaluated k. */
 int or_gdp_solve(int64_t n, const int32_t *xy, int64_t *lam, int64_t max_iters,
+                 int64_t handoff_div,
                  int64_t *trace, int64_t *iters, int32_t *stop, int64_t *kstar,
                  int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero)
 {
-    if (n < 4 || max_iters < 0 || !lam) return OR_ERR_ARG;
+    if (n < 4 || max_iters < 0 || handoff_div < 0 || !lam) return OR_ERR_ARG;
     int rc = or_check_coords(xy, n);
     if (rc) return rc;
     int64_t *step = malloc(sizeof(int64_t) * (size_t)n);
@@ -252,6 +256,7 @@ int or_gdp_solve(int64_t n, const int32_t *xy, int64_t *lam, int64_t max_iters,
         }
         uint64_t h = (uint64_t)rec[6];
         if (rec[3] == 0) { why = OR_STOP_TRIVIAL; break; }
+        if (handoff_div > 0 && rec[2] * handoff_div <= n) { why = OR_STOP_HANDOFF; break; }
         if (rec[5] == 0) { why = OR_STOP_FIXED; break; }
         if (k >= 2 && h == h2) { why = OR_STOP_CYCLE; break; }
         if (k >= max_iters) { why = OR_STOP_CAP; break; }

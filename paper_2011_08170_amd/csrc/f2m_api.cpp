@@ -157,7 +157,7 @@ void certify_dev(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam,
     int32_t *nb = grow<int32_t>(ctx, ctx->c_nb, kTop * n);
     unsigned long long *acc = grow<unsigned long long>(ctx, ctx->c_acc, 4);
     ck(ctx, launch_prep(xy, n, cx, cy, col, x2m, st), "prep");
-    ck(ctx, launch_ctrl_init(cc, 0, 0, st), "ctrl");
+    ck(ctx, launch_ctrl_init(cc, 0, 0, 0, st), "ctrl");
     ck(ctx, launch_set_lam(lam, n, col, cc, st), "set_lam");
     ck(ctx, hipMemsetAsync(deg, 0, n * sizeof(int32_t), st), "memset");
     ck(ctx, hipMemsetAsync(cnt, 0, n * sizeof(int32_t), st), "memset");
@@ -214,7 +214,7 @@ private:
             unsigned long long *cnt = grow<unsigned long long>(ctx, ctx->p_count, 1);
             ck(ctx, hipMemcpyAsync(lam, lam_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st_), "copy");
             ck(ctx, launch_prep(xy_, n, cx, cy, col, x2m, st_), "prep");
-            ck(ctx, launch_ctrl_init(cc, 0, 0, st_), "ctrl");
+            ck(ctx, launch_ctrl_init(cc, 0, 0, 0, st_), "ctrl");
             ck(ctx, launch_set_lam(lam, n, col, cc, st_), "set_lam");
             float x2host = 0.0f;
             ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st_), "copy");
@@ -269,7 +269,7 @@ struct LoopOut {
 };
 
 LoopOut gdp_loop(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int64_t *lam0_host, int64_t max_iters,
-                 int32_t chunk_opt, bool want_trace, bool time_kernels, hipStream_t st)
+                 int64_t handoff_div, int32_t chunk_opt, bool want_trace, bool time_kernels, hipStream_t st)
 {
     LoopOut o;
     int32_t cx, cy;
@@ -296,7 +296,7 @@ LoopOut gdp_loop(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int64_t *
         ck(ctx, hipMemcpyAsync(lam[0], lam0_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
     else
         ck(ctx, hipMemsetAsync(lam[0], 0, n * sizeof(int64_t), st), "memset");
-    ck(ctx, launch_ctrl_init(cd, max_iters, trace_cap, st), "ctrl_init");
+    ck(ctx, launch_ctrl_init(cd, max_iters, trace_cap, handoff_div, st), "ctrl_init");
     ck(ctx, launch_set_lam(lam[0], n, col, cd, st), "set_lam");
     float x2host = 0.0f;
     ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
@@ -392,6 +392,7 @@ void f2m_opts_default(f2m_opts *o)
     o->graph = F2M_GRAPH_COMPLETE;
     o->warm = F2M_WARM_COLD;
     o->max_iters = 100000;
+    o->handoff_div = 300;
     o->finish = F2M_FINISH_EXACT;
 }
 
@@ -487,7 +488,7 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
         Ctrl *cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
         int64_t *trace = grow<int64_t>(ctx, ctx->trace, kTraceW);
         ck(ctx, launch_prep(xy, n, cx, cy, col, x2m, st), "prep");
-        ck(ctx, launch_ctrl_init(cd, INT64_MAX, 1, st), "ctrl_init");
+        ck(ctx, launch_ctrl_init(cd, INT64_MAX, 1, 0, st), "ctrl_init");
         ck(ctx, launch_set_lam(lam_in, n, col, cd, st), "set_lam");
         float x2host = 0.0f;
         ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
@@ -546,6 +547,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         if (o.rule_version != 1) fail(ctx, F2M_ERR_ARG, "only rule_version 1 exists");
         if (o.graph != F2M_GRAPH_COMPLETE) fail(ctx, F2M_ERR_ARG, "unknown graph kind");
         if (o.max_iters < 0) fail(ctx, F2M_ERR_ARG, "max_iters < 0");
+        if (o.handoff_div < 0) fail(ctx, F2M_ERR_ARG, "handoff_div < 0");
         if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
         if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER) fail(ctx, F2M_ERR_ARG, "unknown warm mode");
         if (n < 3) fail(ctx, F2M_ERR_INFEASIBLE, "F2M needs n >= 3");
@@ -584,7 +586,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         }
         const double t1 = now_s();
         LoopOut lo = gdp_loop(ctx, xy_dev, n, o.warm == F2M_WARM_USER ? o.lambda2_init : nullptr, o.max_iters,
-                              o.chunk, o.record_trace != 0, o.time_kernels != 0, st);
+                              o.handoff_div, o.chunk, o.record_trace != 0, o.time_kernels != 0, st);
         const double t2 = now_s();
         res.n = n;
         res.iterations = lo.c.k_last + 1;

@@ -43,7 +43,7 @@ struct Ctrl {
     long long overflow;    // 1 if |Lam_{k+1}| reached kLamLimit
     long long trace_cap;
     long long dual2_last;  // dual2 of Lam_{k_last}
-    long long pad1;
+    long long handoff_div; // hand-off stop: #unsat * div <= n (0: off)
 };
 
 // Column record of the scan, one per city: centred coordinates, half of
@@ -119,7 +119,8 @@ hipError_t launch_minmax(const int32_t *xy, int64_t n, int32_t *out4, hipStream_
 hipError_t launch_prep(const int32_t *xy, int64_t n, int32_t cx, int32_t cy, float4 *col,
                        float *xy2max_dev, hipStream_t st);
 hipError_t launch_set_lam(const int64_t *lam, int64_t n, float4 *col, Ctrl *ctrl, hipStream_t st);
-hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, hipStream_t st);
+hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div,
+                            hipStream_t st);
 hipError_t launch_scan(const ScanArgs &a, int64_t nslices, int rows_per_thread, hipStream_t st);
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
 hipError_t launch_extract_trivial(const int64_t *z4, const int32_t *i4, int64_t n,

@@ -395,6 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
     if (ctrl->best_k < 0 || dual2 > ctrl->best_dual2) { ctrl->best_dual2 = dual2; ctrl->best_k = k; }
     long long stop = 0;
     if (bd == 0) stop = 1;                              // trivial
+    else if (ctrl->handoff_div > 0 && un * ctrl->handoff_div <= a.n) stop = 5;   // handoff
     else if (nz == 0) stop = 2;                         // fixed
     else if (k >= 2 && hh == ctrl->h2) stop = 3;        // cycle
     else if (k >= ctrl->max_iters) stop = 4;            // cap
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
     ctrl->dual2_last = dual2;
     if (stop) {
         ctrl->stop = stop;
-        ctrl->kstar = (stop == 1 || stop == 2) ? k : ctrl->best_k;
+        ctrl->kstar = (stop == 3 || stop == 4) ? ctrl->best_k : k;
         ctrl->done = 1;
     } else {
         ctrl->h2 = ctrl->h1;
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_set_lam(const int64_t *lam, int64_t 
     if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long *)&ctrl->maxabs_lam, ab);
 }
 
-__global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap)
+__global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div)
 {
     if (threadIdx.x != 0) return;
     Ctrl c;
@@ -498,6 +499,7 @@ __global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap)
     c.k_last = -1;
     c.max_iters = max_iters;
     c.trace_cap = trace_cap;
+    c.handoff_div = handoff_div;
     *ctrl = c;
 }
 
@@ -812,9 +814,10 @@ hipError_t launch_set_lam(const int64_t *lam, int64_t n, float4 *col, Ctrl *ctrl
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, hipStream_t st)
+hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div,
+                            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, max_iters, trace_cap);
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, max_iters, trace_cap, handoff_div);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ OK, NOT_CERTIFIED = 0, 1
 STATUS = {0: "ok", 1: "not certified", -1: "invalid argument", -2: "coordinate span out of range",
           -3: "infeasible (n < 3)", -4: "out of memory", -5: "device error", -6: "buffer too small",
           -7: "multiplier overflow"}
-STOP_NAMES = {0: "none", 1: "trivial", 2: "fixed", 3: "cycle", 4: "cap"}
+STOP_NAMES = {0: "none", 1: "trivial", 2: "fixed", 3: "cycle", 4: "cap", 5: "handoff"}
 FINISH = {"none": 0, "exact": 1}
 TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
@@ -36,6 +36,7 @@ class F2MError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("rule_version", C.c_uint32), ("graph", C.c_int32),
                 ("warm", C.c_int32), ("lambda2_init", C.c_void_p), ("max_iters", C.c_int64),
+                ("handoff_div", C.c_int64),
                 ("finish", C.c_int32), ("coords_on_device", C.c_int32), ("record_trace", C.c_int32),
                 ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("hip_stream", C.c_void_p)]
 
@@ -131,13 +132,14 @@ class Context:
             raise F2MError(st, lib().f2m_last_error(self._h).decode())
         return st
 
-    def solve(self, coords, *, max_iters=100000, finish="exact", lambda2_init=None, trace=False,
-              chunk=0, stream=None, time_kernels=False):
+    def solve(self, coords, *, max_iters=100000, handoff_div=300, finish="exact", lambda2_init=None,
+              trace=False, chunk=0, stream=None, time_kernels=False):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
         array on the host or a contiguous int32 device tensor."""
         o = Opts()
         lib().f2m_opts_default(C.byref(o))
         o.max_iters = int(max_iters)
+        o.handoff_div = int(handoff_div)
         o.finish = FINISH[finish]
         o.record_trace = 1 if trace else 0
         o.chunk = int(chunk)

@@ -39,6 +39,14 @@ def test_from_gdp_fixed_point(L):
         assert st["rounds"] <= 4
 
 
+def test_from_gdp_handoff(L):
+    for seed in (4, 5):
+        xy = I.uniform(300, 100000, seed)
+        r = core.gdp_solve(xy, handoff_div=30)
+        assert r["stop"] == "handoff"
+        check(L, xy, r["lam"])
+
+
 def test_from_random_and_ties(L):
     rnd = np.random.default_rng(4)
     for xy in (I.lattice_jitter(8, 9, 20, 2, 1), I.with_duplicates(60, 400, 8, 2), I.lattice(6, 6, 5),

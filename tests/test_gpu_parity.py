@@ -73,12 +73,12 @@ def test_gdp_step_matches_oracle(ctx, name, make):
             assert rec[f] == o["rec"][f], (name, f)
 
 
-@pytest.mark.parametrize("seed", [1, 2, 3])
-def test_solve_trajectory_c1(ctx, seed):
+@pytest.mark.parametrize("seed,div", [(1, 0), (2, 0), (3, 0), (1, 300), (2, 50)])
+def test_solve_trajectory_c1(ctx, seed, div):
     # n = 1000, uniform in [0, 10^5)^2: the trajectory, the stop and Lam*
     xy = I.uniform(1000, 100000, seed)
-    o = core.gdp_solve(xy)
-    g = ctx.solve(xy, trace=True, finish="none")
+    o = core.gdp_solve(xy, handoff_div=div)
+    g = ctx.solve(xy, trace=True, finish="none", handoff_div=div)
     assert g["iterations"] == o["iters"] and g["stop"] == o["stop"] and g["kstar"] == o["kstar"]
     assert np.array_equal(g["trace"], o["trace"])
     assert np.array_equal(g["lambda2_gdp"], o["lam"])
@@ -91,11 +91,12 @@ def test_solve_trajectory_c1(ctx, seed):
 def test_solve_certified_optimum(ctx, name, make):
     xy = make()
     g = ctx.solve(xy, trace=True)
+    assert g["stop"] in ("trivial", "handoff", "fixed", "cycle")
     assert g["certified"] and g["status"] == "ok", g["status"]
     assert g["primal2"] == g["dual2"] == core.exact_opt2(xy)
     c = core.certify(xy, g["lambda2"], g["edge_u"], g["edge_v"], g["edge_x2"])
     assert c["certified"] and c["primal2"] == g["primal2"]
-    o = core.gdp_solve(xy)
+    o = core.gdp_solve(xy, handoff_div=300)
     assert np.array_equal(g["trace"], o["trace"])
 
 

@@ -193,3 +193,18 @@ def test_certificate_rejects_negative_edge_outside_x():
     lam2 = lam.copy(); lam2[v] += bump
     c = core.certify(xy, lam2, eu, ev, ex2)
     assert c["feasible"] and not c["certified"] and c["dual2"] < c["primal2"]
+
+
+def test_handoff_stop():
+    # stops at the first iterate with #unsatisfied * div <= n; every earlier
+    # record has more unsatisfied nodes; the records up to it are the plain
+    # run's records
+    xy = I.uniform(400, 100000, 3)
+    full = core.gdp_solve(xy)
+    for div in (20, 100, 400):
+        r = core.gdp_solve(xy, handoff_div=div)
+        k = r["iters"] - 1
+        assert r["stop"] == "handoff" and r["kstar"] == k
+        assert r["trace"][k, 2] * div <= 400
+        assert np.all(r["trace"][:k, 2] * div > 400)
+        assert np.array_equal(r["trace"], full["trace"][:k + 1])
