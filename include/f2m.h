@@ -69,6 +69,10 @@ typedef enum f2m_status {
 enum { F2M_GRAPH_COMPLETE = 0 };
 enum { F2M_WARM_COLD = 0, F2M_WARM_USER = 1 };
 enum { F2M_FINISH_NONE = 0, F2M_FINISH_EXACT = 1 };
+/* Scan over the complete graph: F2M_SCAN_CULLED skips column tiles whose
+ * bounding box is provably too far for any pair to matter (exact: same
+ * results); F2M_SCAN_FULL tests every ordered pair. */
+enum { F2M_SCAN_CULLED = 0, F2M_SCAN_FULL = 1 };
 enum { F2M_STOP_TRIVIAL = 1, F2M_STOP_FIXED = 2, F2M_STOP_CYCLE = 3, F2M_STOP_CAP = 4,
        F2M_STOP_HANDOFF = 5 };
 
@@ -93,6 +97,7 @@ typedef struct f2m_opts {
     int32_t record_trace;         /* fill f2m_result.trace */
     int32_t chunk;                /* iterations queued between host checks (0: auto) */
     int32_t time_kernels;         /* time every scan launch with HIP events */
+    int32_t scan_mode;            /* F2M_SCAN_CULLED (default) or F2M_SCAN_FULL */
     void *hip_stream;             /* hipStream_t to run on; NULL: the context's stream */
 } f2m_opts;
 

@@ -30,21 +30,25 @@ struct f2m_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     std::vector<DevBuf *> bufs;
-    // workspace
-    DevBuf xy, col, lam[2], lam_best, pz, pi, pneg, pzero, prowneg, z4, i4, seed, ctrl, trace, minmax, xy2max;
+    // geometry of the current instance (sorted order)
+    DevBuf xy, minmax, keys, keys_alt, ids, orig, pos, box, xy2max, sort_temp;
+    // GDP loop state
+    DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, z4, i4, seed, ctrl, trace;
+    // trivial x
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
-    // certificate workspace
-    DevBuf c_col, c_ctrl, c_xy2max, c_deg, c_cnt, c_nb, c_acc, c_minmax, c_lam, c_eu, c_ev, c_ex;
-    DevBuf p_lam, p_pairs, p_count;
+    // certificate / pair collection state
+    DevBuf c_col, c_lam, c_tile_hmax, c_ctrl, c_deg, c_cnt, c_nb, c_acc, c_lam_label, c_eu, c_ev, c_ex;
+    DevBuf p_pairs, p_count;
     Ctrl *ctrl_host = nullptr;   // pinned
     int64_t *scratch_host = nullptr;   // pinned, 16 entries
 
     f2m_ctx()
     {
-        DevBuf *all[] = {&xy, &col, &lam[0], &lam[1], &lam_best, &pz, &pi, &pneg, &pzero, &prowneg, &z4, &i4,
-                         &seed, &ctrl, &trace, &minmax, &xy2max, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
-                         &btmp, &count, &c_col, &c_ctrl, &c_xy2max, &c_deg, &c_cnt, &c_nb, &c_acc, &c_minmax,
-                         &c_lam, &c_eu, &c_ev, &c_ex, &p_lam, &p_pairs, &p_count};
+        DevBuf *all[] = {&xy, &minmax, &keys, &keys_alt, &ids, &orig, &pos, &box, &xy2max, &sort_temp,
+                         &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
+                         &prowneg, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
+                         &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
+                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count};
         bufs.assign(std::begin(all), std::end(all));
     }
 };
@@ -88,23 +92,32 @@ double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Scan launch shape: rows per lane and column slices, from n.
+int64_t ntiles_of(int64_t n) { return (n + kTileCols - 1) / kTileCols; }
+
+// Scan launch shape: rows per lane and column slices (slice length a
+// multiple of the tile width).  Results never depend on it.
 struct ScanShape {
     int rows;          // rows per thread
     int64_t slices;
     int64_t slice_len;
 };
 
-ScanShape scan_shape(int64_t n)
+ScanShape scan_shape(int64_t n, bool cull)
 {
     ScanShape s;
-    s.rows = n >= 65536 ? 4 : (n >= 8192 ? 2 : 1);
-    const int64_t row_blocks = (n + 256 * s.rows - 1) / (256 * s.rows);
-    const int64_t target = 2048;
-    int64_t sl = (target + row_blocks - 1) / row_blocks;
-    const int64_t max_sl = std::max<int64_t>(1, n / 64);
-    sl = std::max<int64_t>(1, std::min(sl, max_sl));
-    s.slice_len = (n + sl - 1) / sl;
+    const int64_t nt = ntiles_of(n);
+    if (cull) {
+        s.rows = 1;
+        const int64_t sl = std::max<int64_t>(1, std::min<int64_t>(nt, 8));
+        s.slice_len = ((nt + sl - 1) / sl) * kTileCols;
+    } else {
+        s.rows = n >= 65536 ? 4 : (n >= 8192 ? 2 : 1);
+        const int64_t row_blocks = (n + 256 * s.rows - 1) / (256 * s.rows);
+        const int64_t target = 2048;
+        int64_t sl = (target + row_blocks - 1) / row_blocks;
+        sl = std::max<int64_t>(1, std::min(sl, nt));
+        s.slice_len = ((nt + sl - 1) / sl) * kTileCols;
+    }
     s.slices = (n + s.slice_len - 1) / s.slice_len;
     return s;
 }
@@ -112,22 +125,6 @@ ScanShape scan_shape(int64_t n)
 hipStream_t pick_stream(f2m_ctx *ctx, const f2m_opts *o)
 {
     return (o && o->hip_stream) ? static_cast<hipStream_t>(o->hip_stream) : ctx->stream;
-}
-
-// Validates coordinates already on the device; returns the centre.
-void check_and_centre(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, DevBuf &mm, hipStream_t st,
-                      int32_t *cx, int32_t *cy)
-{
-    int32_t *m4 = grow<int32_t>(ctx, mm, 4);
-    ck(ctx, launch_minmax(xy_dev, n, m4, st), "minmax");
-    ck(ctx, hipMemcpyAsync(ctx->scratch_host, m4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-    ck(ctx, hipStreamSynchronize(st), "sync");
-    const int32_t *h = reinterpret_cast<const int32_t *>(ctx->scratch_host);
-    const int64_t spanx = (int64_t)h[1] - h[0], spany = (int64_t)h[3] - h[2];
-    if (spanx >= (1 << 20) || spany >= (1 << 20))
-        fail(ctx, F2M_ERR_RANGE, "coordinate span must be below 2^20 on each axis");
-    *cx = (int32_t)(((int64_t)h[0] + h[1]) >> 1);
-    *cy = (int32_t)(((int64_t)h[2] + h[3]) >> 1);
 }
 
 int64_t cost_host(const int32_t *xy, int64_t u, int64_t v)
@@ -143,34 +140,87 @@ char *host_alloc(f2m_ctx *ctx, size_t bytes)
     return p;
 }
 
-// Certificate of (lam, edges) on device buffers; returns out[4].
-void certify_dev(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam, int64_t m, const int32_t *eu,
+// Geometry of the instance on the device: span check, centre, Morton
+// order, tile boxes.  The GDP column records are prepared in ctx->col.
+struct GeoHost {
+    Geo g;
+    const int32_t *xy;   // device coordinates (labels)
+    int32_t cx, cy;
+};
+
+GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st)
+{
+    GeoHost gh;
+    int32_t *m4 = grow<int32_t>(ctx, ctx->minmax, 4);
+    ck(ctx, launch_minmax(xy_dev, n, m4, st), "minmax");
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, m4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    int32_t h[4];
+    std::memcpy(h, ctx->scratch_host, sizeof(h));
+    if ((int64_t)h[1] - h[0] >= (1 << 20) || (int64_t)h[3] - h[2] >= (1 << 20))
+        fail(ctx, F2M_ERR_RANGE, "coordinate span must be below 2^20 on each axis");
+    gh.cx = (int32_t)(((int64_t)h[0] + h[1]) >> 1);
+    gh.cy = (int32_t)(((int64_t)h[2] + h[3]) >> 1);
+    gh.xy = xy_dev;
+    const size_t tb = sort_temp_bytes(n);
+    uint32_t *keys = grow<uint32_t>(ctx, ctx->keys, n);
+    uint32_t *keys2 = grow<uint32_t>(ctx, ctx->keys_alt, n);
+    int32_t *ids = grow<int32_t>(ctx, ctx->ids, n);
+    int32_t *orig = grow<int32_t>(ctx, ctx->orig, n);
+    int32_t *pos = grow<int32_t>(ctx, ctx->pos, n);
+    void *temp = grow<char>(ctx, ctx->sort_temp, tb);
+    ck(ctx, launch_sort(xy_dev, n, h[0], h[2], keys, keys2, ids, orig, pos, temp, tb, st), "sort");
+    float4 *col = grow<float4>(ctx, ctx->col, n);
+    float4 *box = grow<float4>(ctx, ctx->box, ntiles_of(n));
+    float *x2m = grow<float>(ctx, ctx->xy2max, 1);
+    ck(ctx, launch_prep(xy_dev, orig, n, gh.cx, gh.cy, col, box, x2m, st), "prep");
+    float x2host = 0.0f;
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    std::memcpy(&x2host, ctx->scratch_host, sizeof(float));
+    gh.g = Geo{n, orig, pos, box, x2host};
+    return gh;
+}
+
+// A Lam placed on the certificate / collection state: sorted Lam, column
+// records and tile maxima; lam_label_dev is in label order.
+LamView place_lam(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label_dev, hipStream_t st)
+{
+    const int64_t n = gh.g.n;
+    float4 *col = grow<float4>(ctx, ctx->c_col, n);
+    int64_t *ls = grow<int64_t>(ctx, ctx->c_lam, n);
+    float *th = grow<float>(ctx, ctx->c_tile_hmax, ntiles_of(n));
+    Ctrl *cc = grow<Ctrl>(ctx, ctx->c_ctrl, 1);
+    float *x2m = grow<float>(ctx, ctx->xy2max, 1);
+    ck(ctx, launch_prep(gh.xy, gh.g.orig, n, gh.cx, gh.cy, col, (float4 *)ctx->box.p, x2m, st), "prep");
+    ck(ctx, launch_ctrl_init(cc, 0, 0, 0, st), "ctrl");
+    ck(ctx, launch_set_lam(lam_label_dev, gh.g.orig, n, ls, col, th, cc, st), "set_lam");
+    return LamView{col, ls, th, cc};
+}
+
+// Certificate of (lam, edges); lam and the edges are device arrays by label.
+void certify_dev(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label, int64_t m, const int32_t *eu,
                  const int32_t *ev, const uint8_t *ex, hipStream_t st, int64_t out[4])
 {
-    int32_t cx, cy;
-    check_and_centre(ctx, xy, n, ctx->c_minmax, st, &cx, &cy);
-    float4 *col = grow<float4>(ctx, ctx->c_col, n);
-    float *x2m = grow<float>(ctx, ctx->c_xy2max, 1);
-    Ctrl *cc = grow<Ctrl>(ctx, ctx->c_ctrl, 1);
+    const int64_t n = gh.g.n;
+    LamView lv = place_lam(ctx, gh, lam_label, st);
     int32_t *deg = grow<int32_t>(ctx, ctx->c_deg, n);
     int32_t *cnt = grow<int32_t>(ctx, ctx->c_cnt, n);
     int32_t *nb = grow<int32_t>(ctx, ctx->c_nb, kTop * n);
     unsigned long long *acc = grow<unsigned long long>(ctx, ctx->c_acc, 4);
-    ck(ctx, launch_prep(xy, n, cx, cy, col, x2m, st), "prep");
-    ck(ctx, launch_ctrl_init(cc, 0, 0, 0, st), "ctrl");
-    ck(ctx, launch_set_lam(lam, n, col, cc, st), "set_lam");
     ck(ctx, hipMemsetAsync(deg, 0, n * sizeof(int32_t), st), "memset");
     ck(ctx, hipMemsetAsync(cnt, 0, n * sizeof(int32_t), st), "memset");
     ck(ctx, hipMemsetAsync(acc, 0, 4 * sizeof(unsigned long long), st), "memset");
-    // the xy2max bound is read by value: fetch it
-    float x2host = 0.0f;
-    ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
-    ck(ctx, hipStreamSynchronize(st), "sync");
-    const ScanShape sh = scan_shape(n);
-    CertScanArgs ca{n, sh.slice_len, col, lam, cc, x2host, acc};
-    ck(ctx, launch_cert_scan(ca, sh.slices, st), "cert_scan");
-    ck(ctx, launch_cert_edges(xy, n, m, eu, ev, ex, deg, cnt, nb, acc, st), "cert_edges");
-    ck(ctx, launch_cert_nodes(lam, n, deg, cnt, nb, acc, st), "cert_nodes");
+    const ScanShape sh = scan_shape(n, true);
+    ScanArgs sa{};
+    sa.g = gh.g;
+    sa.lv = lv;
+    sa.slice_len = sh.slice_len;
+    sa.cull = 1;
+    sa.acc = acc;
+    ck(ctx, launch_scan(sa, kModeCert, sh.slices, sh.rows, st), "cert_scan");
+    ck(ctx, launch_cert_edges(gh.xy, n, m, eu, ev, ex, deg, cnt, nb, acc, st), "cert_edges");
+    ck(ctx, launch_cert_nodes(lam_label, n, deg, cnt, nb, acc, st), "cert_nodes");
     unsigned long long h[4];
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, acc, sizeof(h), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
@@ -185,8 +235,8 @@ void certify_dev(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam,
 // Candidate pairs for the exact finish from GPU scans of the complete graph.
 class GpuPairs : public PairSource {
 public:
-    GpuPairs(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int32_t *seed_dev, hipStream_t st)
-        : ctx_(ctx), xy_(xy_dev), n_(n), seed_(seed_dev), st_(st)
+    GpuPairs(f2m_ctx *ctx, const GeoHost &gh, const int32_t *seed_dev, hipStream_t st)
+        : ctx_(ctx), gh_(gh), seed_(seed_dev), st_(st)
     {
     }
     bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) override
@@ -204,30 +254,28 @@ private:
     {
         try {
             f2m_ctx *ctx = ctx_;
-            const int64_t n = n_;
-            int32_t cx, cy;
-            check_and_centre(ctx, xy_, n, ctx->c_minmax, st_, &cx, &cy);
-            float4 *col = grow<float4>(ctx, ctx->c_col, n);
-            float *x2m = grow<float>(ctx, ctx->c_xy2max, 1);
-            Ctrl *cc = grow<Ctrl>(ctx, ctx->c_ctrl, 1);
-            int64_t *lam = grow<int64_t>(ctx, ctx->p_lam, n);
+            const int64_t n = gh_.g.n;
+            int64_t *lam = grow<int64_t>(ctx, ctx->c_lam_label, n);
             unsigned long long *cnt = grow<unsigned long long>(ctx, ctx->p_count, 1);
             ck(ctx, hipMemcpyAsync(lam, lam_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st_), "copy");
-            ck(ctx, launch_prep(xy_, n, cx, cy, col, x2m, st_), "prep");
-            ck(ctx, launch_ctrl_init(cc, 0, 0, 0, st_), "ctrl");
-            ck(ctx, launch_set_lam(lam, n, col, cc, st_), "set_lam");
-            float x2host = 0.0f;
-            ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st_), "copy");
-            ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cc, sizeof(Ctrl), hipMemcpyDeviceToHost, st_), "copy");
-            ck(ctx, hipStreamSynchronize(st_), "sync");
-            if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| reached 2^38");
-            const ScanShape sh = scan_shape(n);
+            LamView lv = place_lam(ctx, gh_, lam, st_);
+            const ScanShape sh = scan_shape(n, true);
             int64_t cap = std::max<int64_t>(cap_, 8 * n);
             for (;;) {
                 int2 *pairs = grow<int2>(ctx, ctx->p_pairs, cap);
                 ck(ctx, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st_), "memset");
-                CollectArgs ca{n, sh.slice_len, col, lam, seed, cc, x2host, theta, slack, cnt, pairs, cap};
-                ck(ctx, launch_collect(ca, sh.slices, st_), "collect");
+                ScanArgs sa{};
+                sa.g = gh_.g;
+                sa.lv = lv;
+                sa.slice_len = sh.slice_len;
+                sa.cull = 1;
+                sa.seed = seed;
+                sa.theta = theta;
+                sa.slack = slack;
+                sa.count = cnt;
+                sa.out = pairs;
+                sa.cap = cap;
+                ck(ctx, launch_scan(sa, kModeCollect, sh.slices, sh.rows, st_), "collect");
                 ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st_), "copy");
                 ck(ctx, hipStreamSynchronize(st_), "sync");
                 const int64_t found = ctx->scratch_host[0];
@@ -251,34 +299,34 @@ private:
     }
 
     f2m_ctx *ctx_;
-    const int32_t *xy_;
-    int64_t n_;
+    GeoHost gh_;
     const int32_t *seed_;
     hipStream_t st_;
     int64_t cap_ = 0;
 };
 
-// GDP loop on device buffers.  Returns the final control block.
 struct LoopOut {
     Ctrl c;
     double scan_ms = 0.0;
     int64_t scan_launches = 0;
     ScanShape shape;
-    int64_t *lam_star;     // device pointer holding Lam_kstar
-    int64_t *lam_last;     // device pointer holding Lam_klast
+    int64_t *lam_star;     // device, sorted: Lam_kstar
 };
 
-LoopOut gdp_loop(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int64_t *lam0_host, int64_t max_iters,
-                 int64_t handoff_div, int32_t chunk_opt, bool want_trace, bool time_kernels, hipStream_t st)
+// The GDP loop on device buffers.  lam0_label_dev: device Lam_0 by label
+// (null: zero).
+LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev, int64_t max_iters,
+                 int64_t handoff_div, int32_t chunk_opt, bool want_trace, bool time_kernels, bool cull,
+                 hipStream_t st)
 {
     LoopOut o;
-    int32_t cx, cy;
-    check_and_centre(ctx, xy_dev, n, ctx->minmax, st, &cx, &cy);
-    const ScanShape sh = scan_shape(n);
-    float4 *col = grow<float4>(ctx, ctx->col, n);
-    float *x2m = grow<float>(ctx, ctx->xy2max, 1);
+    const int64_t n = gh.g.n;
+    const ScanShape sh = scan_shape(n, cull);
+    float4 *col = static_cast<float4 *>(ctx->col.p);
     int64_t *lam[2] = {grow<int64_t>(ctx, ctx->lam[0], n), grow<int64_t>(ctx, ctx->lam[1], n)};
     int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
+    int64_t *l0 = grow<int64_t>(ctx, ctx->lam_label, n);
+    float *thm = grow<float>(ctx, ctx->tile_hmax, ntiles_of(n));
     int64_t *pz = grow<int64_t>(ctx, ctx->pz, sh.slices * kTop * n);
     int32_t *pi = grow<int32_t>(ctx, ctx->pi, sh.slices * kTop * n);
     int32_t *pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
@@ -291,15 +339,13 @@ LoopOut gdp_loop(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int64_t *
     const int64_t trace_cap = want_trace ? max_iters + 1 : 0;
     int64_t *trace = want_trace ? grow<int64_t>(ctx, ctx->trace, kTraceW * trace_cap) : nullptr;
 
-    ck(ctx, launch_prep(xy_dev, n, cx, cy, col, x2m, st), "prep");
-    if (lam0_host)
-        ck(ctx, hipMemcpyAsync(lam[0], lam0_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+    if (lam0_label_dev)
+        ck(ctx, hipMemcpyAsync(l0, lam0_label_dev, n * sizeof(int64_t), hipMemcpyDeviceToDevice, st), "copy");
     else
-        ck(ctx, hipMemsetAsync(lam[0], 0, n * sizeof(int64_t), st), "memset");
+        ck(ctx, hipMemsetAsync(l0, 0, n * sizeof(int64_t), st), "memset");
     ck(ctx, launch_ctrl_init(cd, max_iters, trace_cap, handoff_div, st), "ctrl_init");
-    ck(ctx, launch_set_lam(lam[0], n, col, cd, st), "set_lam");
-    float x2host = 0.0f;
-    ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, launch_set_lam(l0, gh.g.orig, n, lam[0], col, thm, cd, st), "set_lam");
+    ck(ctx, launch_seed_neighbours(n, seed, st), "seed");
     ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2_init| must be below 2^38");
@@ -318,13 +364,19 @@ LoopOut gdp_loop(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int64_t *
     for (;;) {
         int issued = 0;
         for (int j = 0; j < chunk && k <= max_iters; ++j, ++k, ++issued) {
-            ScanArgs sa{n, sh.slice_len, col, lam[k & 1], k > 0 ? seed : nullptr, cd, x2host,
-                        pz, pi, pneg, pzero, prn};
+            ScanArgs sa{};
+            sa.g = gh.g;
+            sa.lv = LamView{col, lam[k & 1], thm, cd};
+            sa.slice_len = sh.slice_len;
+            sa.cull = cull ? 1 : 0;
+            sa.check_done = 1;
+            sa.seed = seed;
+            sa.pz = pz; sa.pi = pi; sa.pneg = pneg; sa.pzero = pzero; sa.prowneg = prn;
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
-            ck(ctx, launch_scan(sa, sh.slices, sh.rows, st), "scan");
+            ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
-            UpdateArgs ua{n, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
-                          z4, i4, seed, nullptr, nullptr, nullptr, cd, trace};
+            UpdateArgs ua{gh.g, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
+                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace};
             ck(ctx, launch_update(ua, st), "update");
         }
         ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
@@ -346,8 +398,8 @@ LoopOut gdp_loop(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, const int64_t *
     o.shape = sh;
     o.c = *ctx->ctrl_host;
     if (o.c.overflow) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| reached 2^38");
-    o.lam_last = lam[o.c.k_last & 1];
-    o.lam_star = (o.c.kstar == o.c.k_last) ? o.lam_last : best;
+    int64_t *last = lam[o.c.k_last & 1];
+    o.lam_star = (o.c.kstar == o.c.k_last) ? last : best;
     return o;
 }
 
@@ -471,12 +523,14 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
             fail(ctx, F2M_ERR_ARG, "gdp_step needs n >= 4, coords, distinct lambda2_in/out and rec");
         ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
         hipStream_t st = ctx->stream;
-        int32_t cx, cy;
-        check_and_centre(ctx, xy, n, ctx->minmax, st, &cx, &cy);
-        const ScanShape sh = scan_shape(n);
-        float4 *col = grow<float4>(ctx, ctx->col, n);
-        float *x2m = grow<float>(ctx, ctx->xy2max, 1);
+        const GeoHost gh = setup_geo(ctx, xy, n, st);
+        const bool cull = true;
+        const ScanShape sh = scan_shape(n, cull);
+        float4 *col = static_cast<float4 *>(ctx->col.p);
+        int64_t *ls = grow<int64_t>(ctx, ctx->lam[0], n);
+        int64_t *lo = grow<int64_t>(ctx, ctx->lam[1], n);
         int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
+        float *thm = grow<float>(ctx, ctx->tile_hmax, ntiles_of(n));
         int64_t *pz = grow<int64_t>(ctx, ctx->pz, sh.slices * kTop * n);
         int32_t *pi = grow<int32_t>(ctx, ctx->pi, sh.slices * kTop * n);
         int32_t *pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
@@ -487,19 +541,25 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
         int32_t *seed = grow<int32_t>(ctx, ctx->seed, kTop * n);
         Ctrl *cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
         int64_t *trace = grow<int64_t>(ctx, ctx->trace, kTraceW);
-        ck(ctx, launch_prep(xy, n, cx, cy, col, x2m, st), "prep");
         ck(ctx, launch_ctrl_init(cd, INT64_MAX, 1, 0, st), "ctrl_init");
-        ck(ctx, launch_set_lam(lam_in, n, col, cd, st), "set_lam");
-        float x2host = 0.0f;
-        ck(ctx, hipMemcpyAsync(&x2host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, launch_set_lam(lam_in, gh.g.orig, n, ls, col, thm, cd, st), "set_lam");
+        ck(ctx, launch_seed_neighbours(n, seed, st), "seed");
         ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
         ck(ctx, hipStreamSynchronize(st), "sync");
         if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| must be below 2^38");
-        ScanArgs sa{n, sh.slice_len, col, lam_in, nullptr, cd, x2host, pz, pi, pneg, pzero, prn};
-        ck(ctx, launch_scan(sa, sh.slices, sh.rows, st), "scan");
-        UpdateArgs ua{n, sh.slices, 0, pz, pi, pneg, pzero, prn, lam_in, lam_out, best, col,
+        ScanArgs sa{};
+        sa.g = gh.g;
+        sa.lv = LamView{col, ls, thm, cd};
+        sa.slice_len = sh.slice_len;
+        sa.cull = cull ? 1 : 0;
+        sa.check_done = 1;
+        sa.seed = seed;
+        sa.pz = pz; sa.pi = pi; sa.pneg = pneg; sa.pzero = pzero; sa.prowneg = prn;
+        ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
+        UpdateArgs ua{gh.g, sh.slices, 0, pz, pi, pneg, pzero, prn, ls, lo, best, col, thm,
                       z4, i4, seed, neg, zero, step, cd, trace};
         ck(ctx, launch_update(ua, st), "update");
+        ck(ctx, launch_unpermute(lo, gh.g.orig, n, lam_out, st), "unpermute");
         ck(ctx, hipMemcpyAsync(ctx->scratch_host, trace, kTraceW * sizeof(int64_t), hipMemcpyDeviceToHost, st),
            "copy");
         ck(ctx, hipStreamSynchronize(st), "sync");
@@ -521,7 +581,8 @@ f2m_status f2m_certify(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t
         if (!xy || !lam || !out || n < 3 || m < 0 || (m > 0 && (!eu || !ev || !ex2)))
             fail(ctx, F2M_ERR_ARG, "certify needs n >= 3, coords, lambda2 and the edge arrays");
         ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-        certify_dev(ctx, xy, n, lam, m, eu, ev, ex2, ctx->stream, out);
+        const GeoHost gh = setup_geo(ctx, xy, n, ctx->stream);
+        certify_dev(ctx, gh, lam, m, eu, ev, ex2, ctx->stream, out);
         return F2M_OK;
     } catch (const Fail &f) {
         return f.st;
@@ -551,21 +612,21 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
         if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER) fail(ctx, F2M_ERR_ARG, "unknown warm mode");
         if (n < 3) fail(ctx, F2M_ERR_INFEASIBLE, "F2M needs n >= 3");
+        if (n >= (int64_t)1 << 30) fail(ctx, F2M_ERR_ARG, "n must be below 2^30");
         ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
         hipStream_t st = pick_stream(ctx, &o);
         const double t0 = now_s();
 
         // coordinates on the device and on the host (the finish and n == 3 need them)
-        std::vector<int32_t> xy_host;
+        std::vector<int32_t> xy_host(2 * n);
         const int32_t *xy_dev;
         if (o.coords_on_device) {
             xy_dev = coords;
-            xy_host.resize(2 * n);
             ck(ctx, hipMemcpyAsync(xy_host.data(), coords, 2 * n * sizeof(int32_t), hipMemcpyDeviceToHost, st),
                "copy");
             ck(ctx, hipStreamSynchronize(st), "sync");
         } else {
-            xy_host.assign(coords, coords + 2 * n);
+            std::memcpy(xy_host.data(), coords, 2 * n * sizeof(int32_t));
             int32_t *d = grow<int32_t>(ctx, ctx->xy, 2 * n);
             ck(ctx, hipMemcpyAsync(d, coords, 2 * n * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
             xy_dev = d;
@@ -584,17 +645,25 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             *out = res;
             return s;
         }
+        const GeoHost gh = setup_geo(ctx, xy_dev, n, st);
+        const int64_t *lam0_dev = nullptr;
+        if (o.warm == F2M_WARM_USER) {
+            int64_t *d = grow<int64_t>(ctx, ctx->c_lam_label, n);
+            ck(ctx, hipMemcpyAsync(d, o.lambda2_init, n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+            lam0_dev = d;
+        }
         const double t1 = now_s();
-        LoopOut lo = gdp_loop(ctx, xy_dev, n, o.warm == F2M_WARM_USER ? o.lambda2_init : nullptr, o.max_iters,
-                              o.handoff_div, o.chunk, o.record_trace != 0, o.time_kernels != 0, st);
+        LoopOut lo = gdp_loop(ctx, gh, lam0_dev, o.max_iters, o.handoff_div, o.chunk, o.record_trace != 0,
+                              o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, st);
         const double t2 = now_s();
         res.n = n;
         res.iterations = lo.c.k_last + 1;
         res.kstar = lo.c.kstar;
         res.stop = (int32_t)lo.c.stop;
+        int64_t *lstar = grow<int64_t>(ctx, ctx->lam_label, n);
+        ck(ctx, launch_unpermute(lo.lam_star, gh.g.orig, n, lstar, st), "unpermute");
         res.lambda2_gdp = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
-        ck(ctx, hipMemcpyAsync(res.lambda2_gdp, lo.lam_star, n * sizeof(int64_t), hipMemcpyDeviceToHost, st),
-           "copy");
+        ck(ctx, hipMemcpyAsync(res.lambda2_gdp, lstar, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
         if (o.record_trace) {
             res.trace_len = res.iterations;
             res.trace = reinterpret_cast<int64_t *>(host_alloc(ctx, res.trace_len * kTraceW * sizeof(int64_t)));
@@ -607,9 +676,9 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         int32_t *eu = nullptr, *ev = nullptr;
         uint8_t *ex = nullptr;
         int64_t m = 0;
-        const int64_t *lam_final_dev = lo.lam_star;
-        std::vector<int64_t> lam_final_host;
+        const int64_t *lam_final_dev = lstar;
         const double t3 = now_s();
+        bool have_x = false;
         if (lo.c.stop == F2M_STOP_TRIVIAL) {
             const int64_t ns = kTop * n;
             int32_t *su = grow<int32_t>(ctx, ctx->slot_u, ns);
@@ -626,32 +695,35 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
             ck(ctx, hipStreamSynchronize(st), "sync");
             m = ctx->scratch_host[0];
+            have_x = true;
         } else if (o.finish == F2M_FINISH_EXACT) {
             FinishResult fr;
-            GpuPairs src(ctx, xy_dev, n, (const int32_t *)ctx->seed.p, st);
+            GpuPairs src(ctx, gh, (const int32_t *)ctx->seed.p, st);
             finish_exact(xy_host.data(), n, res.lambda2_gdp, src, &fr);
             res.finish_paths = fr.paths;
             res.finish_rounds = fr.rounds;
             if (!fr.ok) fail(ctx, F2M_ERR_DEVICE, "exact finish failed: " + fr.msg);
             m = (int64_t)fr.eu.size();
-            lam_final_host = fr.lam;
-            int64_t *ld = grow<int64_t>(ctx, ctx->c_lam, n);
+            int64_t *ld = grow<int64_t>(ctx, ctx->c_lam_label, n);
             eu = grow<int32_t>(ctx, ctx->c_eu, std::max<int64_t>(m, 1));
             ev = grow<int32_t>(ctx, ctx->c_ev, std::max<int64_t>(m, 1));
             ex = grow<uint8_t>(ctx, ctx->c_ex, std::max<int64_t>(m, 1));
-            ck(ctx, hipMemcpyAsync(ld, fr.lam.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+            // the GDP multipliers stay available in lstar; the certificate's
+            // duals go to their own buffer
+            int64_t *lf = grow<int64_t>(ctx, ctx->lam_best, n);
+            ck(ctx, hipMemcpyAsync(lf, fr.lam.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+            (void)ld;
             if (m) {
                 ck(ctx, hipMemcpyAsync(eu, fr.eu.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
                 ck(ctx, hipMemcpyAsync(ev, fr.ev.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
                 ck(ctx, hipMemcpyAsync(ex, fr.ex2.data(), m * sizeof(uint8_t), hipMemcpyHostToDevice, st), "copy");
             }
-            lam_final_dev = ld;
+            lam_final_dev = lf;
+            have_x = true;
         }
         const double t4 = now_s();
         int64_t cert[4] = {0, 0, 0, 0};
-        if (m > 0 || lo.c.stop == F2M_STOP_TRIVIAL || o.finish == F2M_FINISH_EXACT) {
-            certify_dev(ctx, xy_dev, n, lam_final_dev, m, eu, ev, ex, st, cert);
-        }
+        if (have_x) certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert);
         const double t5 = now_s();
         res.n_edges = m;
         res.edge_u = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
@@ -666,7 +738,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         ck(ctx, hipMemcpyAsync(res.lambda2, lam_final_dev, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
         ck(ctx, hipStreamSynchronize(st), "sync");
         res.primal2 = cert[0];
-        res.dual2 = cert[1];
+        res.dual2 = have_x ? cert[1] : res.dual2_gdp;
         res.certified = (int32_t)cert[3];
         res.scan_ms = lo.scan_ms;
         res.scan_launches = lo.scan_launches;

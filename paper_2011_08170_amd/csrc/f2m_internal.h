@@ -1,5 +1,11 @@
 // Internal interface between the HIP kernels (f2m_kernels.hip) and the host
 // runtime (f2m_api.cpp).  Not part of the public ABI.
+//
+// Internal order.  Cities are relabelled by a Morton (Z-order) sort of their
+// coordinates; "position" p in [0, n) is the sorted index, orig[p] the
+// caller's label.  Scans run over positions (spatially compact row blocks
+// and column tiles), while every tie-break, output and hash uses labels, so
+// results do not depend on the order.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -14,6 +20,8 @@ constexpr int64_t kThetaNone = int64_t(1) << 40;
 constexpr int kTraceW = 8;
 // Entries kept per row: the four smallest (Z, u).
 constexpr int kTop = 4;
+// Columns per LDS tile; also the alignment of row blocks and slices.
+constexpr int kTileCols = 256;
 
 // Device-resident control block of the GDP loop.  The update kernel's
 // last block reads the accumulators, writes the iteration record, takes
@@ -46,28 +54,51 @@ struct Ctrl {
     long long handoff_div; // hand-off stop: #unsat * div <= n (0: off)
 };
 
-// Column record of the scan, one per city: centred coordinates, half of
-// Lam and q = x^2 + y^2 - h^2 (all float; x, y exact integers).
-// float4 {x, y, h, q}.
+// Static geometry of an instance in sorted order.
+struct Geo {
+    int64_t n;
+    const int32_t *orig;        // position -> label
+    const int32_t *pos;         // label -> position
+    const float4 *box;          // per tile: xmin, xmax, ymin, ymax (centred)
+    float xy2max;               // >= max over cities of x^2 + y^2 (centred)
+};
+
+// Column records, one per position: centred coordinates, h = Lam/2 and
+// q = x^2 + y^2 - h^2 (float4 {x, y, h, q}), plus the per-tile maximum of h.
+struct LamView {
+    const float4 *col;
+    const int64_t *lam;         // Lam in sorted order
+    const float *tile_hmax;     // per tile: max h
+    const Ctrl *ctrl;           // maxabs_lam (and done for the GDP loop)
+};
+
+enum ScanMode { kModeGdp = 0, kModeCert = 1, kModeCollect = 2 };
 
 struct ScanArgs {
-    int64_t n;
-    int64_t slice_len;          // columns per slice (blockIdx.y)
-    const float4 *col;          // n
-    const int64_t *lam;         // Lam_k, n
-    const int32_t *seed;        // previous top-4 indices [4n] or null
-    const Ctrl *ctrl;           // done flag, maxabs_lam
-    float xy2max;               // max over cities of x^2 + y^2 (centred)
-    // partial results per (slice, row), structure of arrays
+    Geo g;
+    LamView lv;
+    int64_t slice_len;          // columns per slice (blockIdx.y), multiple of kTileCols
+    int cull;                   // skip column tiles that cannot hold a passing pair
+    int check_done;             // GDP loop: exit at once when ctrl->done
+    const int32_t *seed;        // [j][n] positions bounding the 4th smallest Z, or null
+    // GDP mode: partial results per (slice, position), structure of arrays
     int64_t *pz;                // [slice][4][n]
-    int32_t *pi;                // [slice][4][n]
+    int32_t *pi;                // [slice][4][n]  (labels)
     int32_t *pneg;              // [slice][n]
     int32_t *pzero;             // [slice][n]
     int64_t *prowneg;           // [slice][n]
+    // certificate mode
+    unsigned long long *acc;    // [0] += sum of min(0, Z) over ordered pairs
+    // collect mode: pairs (label, label), lo < hi, with Z <= theta_row
+    int64_t theta;              // threshold when no seed bound exists
+    int64_t slack;              // added to the seeded bound
+    unsigned long long *count;
+    int2 *out;
+    int64_t cap;
 };
 
 struct UpdateArgs {
-    int64_t n;
+    Geo g;
     int64_t nslices;
     int64_t k;                  // iteration index
     const int64_t *pz;
@@ -75,53 +106,40 @@ struct UpdateArgs {
     const int32_t *pneg;
     const int32_t *pzero;
     const int64_t *prowneg;
-    const int64_t *lam_in;      // Lam_k
-    int64_t *lam_out;           // Lam_{k+1}; holds Lam_{k-1} on entry
-    int64_t *lam_best;          // copy of the best-dual iterate
+    const int64_t *lam_in;      // Lam_k, sorted
+    int64_t *lam_out;           // Lam_{k+1}, sorted; holds Lam_{k-1} on entry
+    int64_t *lam_best;          // sorted copy of the best-dual iterate
     float4 *col;                // h, q rewritten for Lam_{k+1}
-    int64_t *z4;                // [4n] node-major (4v + j)
-    int32_t *i4;                // [4n] node-major
-    int32_t *seed;              // [j][n] top-4 indices for the next scan
-    int32_t *neg;               // [n] or null
-    int32_t *zero;              // [n] or null
-    int64_t *step;              // [n] or null
+    float *tile_hmax;           // per tile max h of Lam_{k+1}
+    int64_t *z4;                // [4n] by label (4v + j)
+    int32_t *i4;                // [4n] by label, entries are labels
+    int32_t *seed;              // [j][n] positions of the top-4, for the next scan
+    int32_t *neg;               // [n] by label, or null
+    int32_t *zero;              // [n] by label, or null
+    int64_t *step;              // [n] by label, or null
     Ctrl *ctrl;
     int64_t *trace;             // [trace_cap][8] or null
 };
 
-struct CollectArgs {
-    int64_t n;
-    int64_t slice_len;
-    const float4 *col;
-    const int64_t *lam;
-    const int32_t *seed;        // [j][n] column indices bounding the 4th smallest Z, or null
-    const Ctrl *ctrl;           // maxabs_lam
-    float xy2max;
-    int64_t theta;              // row threshold when seed is null (or a seed is missing)
-    int64_t slack;              // added to the seeded threshold
-    unsigned long long *count;  // pairs found (may exceed cap)
-    int2 *out;                  // (u, v), u < v; both rows may report a pair
-    int64_t cap;
-};
-
-struct CertScanArgs {
-    int64_t n;
-    int64_t slice_len;
-    const float4 *col;
-    const int64_t *lam;
-    const Ctrl *ctrl;           // maxabs_lam
-    float xy2max;
-    unsigned long long *acc;    // [0] sum of min(0, Z) over ordered pairs
-};
-
 // Launchers (f2m_kernels.hip).  All run on `st`; none synchronises.
 hipError_t launch_minmax(const int32_t *xy, int64_t n, int32_t *out4, hipStream_t st);
-hipError_t launch_prep(const int32_t *xy, int64_t n, int32_t cx, int32_t cy, float4 *col,
-                       float *xy2max_dev, hipStream_t st);
-hipError_t launch_set_lam(const int64_t *lam, int64_t n, float4 *col, Ctrl *ctrl, hipStream_t st);
+// Morton order: fills orig (position -> label) and pos (label -> position).
+size_t sort_temp_bytes(int64_t n);
+hipError_t launch_sort(const int32_t *xy, int64_t n, int32_t minx, int32_t miny, uint32_t *keys,
+                       uint32_t *keys_alt, int32_t *ids, int32_t *orig, int32_t *pos, void *temp,
+                       size_t temp_bytes, hipStream_t st);
+// centred float coordinates in sorted order, tile boxes, xy2max
+hipError_t launch_prep(const int32_t *xy, const int32_t *orig, int64_t n, int32_t cx, int32_t cy, float4 *col,
+                       float4 *box, float *xy2max_dev, hipStream_t st);
+// Lam (labels) -> sorted Lam, h and q, tile maxima of h, max |Lam|
+hipError_t launch_set_lam(const int64_t *lam_label, const int32_t *orig, int64_t n, int64_t *lam_sorted,
+                          float4 *col, float *tile_hmax, Ctrl *ctrl, hipStream_t st);
+hipError_t launch_unpermute(const int64_t *lam_sorted, const int32_t *orig, int64_t n, int64_t *lam_label,
+                            hipStream_t st);
+hipError_t launch_seed_neighbours(int64_t n, int32_t *seed, hipStream_t st);
 hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div,
                             hipStream_t st);
-hipError_t launch_scan(const ScanArgs &a, int64_t nslices, int rows_per_thread, hipStream_t st);
+hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_per_thread, hipStream_t st);
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
 hipError_t launch_extract_trivial(const int64_t *z4, const int32_t *i4, int64_t n,
                                   int32_t *slot_u, int32_t *slot_v, uint8_t *slot_x2,
@@ -130,8 +148,6 @@ hipError_t launch_compact(const int32_t *slot_u, const int32_t *slot_v, const ui
                           int64_t nslots, int32_t *eu, int32_t *ev, uint8_t *ex2,
                           int64_t *count_dev, int32_t *block_tmp, hipStream_t st);
 int64_t compact_block_tmp_len(int64_t nslots);
-hipError_t launch_collect(const CollectArgs &a, int64_t nslices, hipStream_t st);
-hipError_t launch_cert_scan(const CertScanArgs &a, int64_t nslices, hipStream_t st);
 hipError_t launch_cert_edges(const int32_t *xy, int64_t n, int64_t m, const int32_t *eu,
                              const int32_t *ev, const uint8_t *ex2, int32_t *deg, int32_t *cnt,
                              int32_t *nb, unsigned long long *acc, hipStream_t st);

@@ -29,10 +29,12 @@
 #include <float.h>
 #include <limits.h>
 
+#include <hipcub/hipcub.hpp>
+
 namespace f2m {
 
 constexpr int kBlock = 256;   // threads per workgroup (4 waves of 64)
-constexpr int kTile = 256;    // columns staged in LDS per tile
+constexpr int kTile = kTileCols;   // columns staged in LDS per tile
 constexpr int kGroup = 8;     // columns per filter test
 constexpr int32_t kNoIdx = INT32_MAX;
 
@@ -143,117 +145,6 @@ __device__ __forceinline__ float col_bound(float xy2max, long long maxabs_lam)
 }
 
 // ---------------------------------------------------------------------------
-// scan: rows x column slices -> partial top-4 and counts
-// ---------------------------------------------------------------------------
-
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_scan(ScanArgs a)
-{
-    if (a.ctrl->done) return;
-    __shared__ float4 sc[kTile];
-    const int t = threadIdx.x;
-    const int64_t n = a.n;
-    const int64_t sl = blockIdx.y;
-    const int64_t c0 = sl * a.slice_len;
-    const int64_t c1 = min(n, c0 + a.slice_len);
-    const float colmax = col_bound(a.xy2max, a.ctrl->maxabs_lam);
-
-    Row rw[R];
-    Top4 top[R];
-    int32_t neg[R], zero[R];
-    int64_t rn[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t v = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + t;
-        rw[r].v = v;
-        top[r].clear();
-        neg[r] = 0; zero[r] = 0; rn[r] = 0;
-        if (v < n) {
-            const float4 cv = a.col[v];
-            rw[r].xv = cv.x; rw[r].yv = cv.y;
-            rw[r].lamv = a.lam[v];
-            int64_t th = kThetaNone;
-            if (a.seed) {
-                int64_t mx = INT64_MIN;
-                int cnt = 0;
-#pragma unroll
-                for (int j = 0; j < kTop; ++j) {
-                    const int32_t u = a.seed[j * n + v];
-                    if (u >= 0 && u < n && u != v) {
-                        const float4 cu = a.col[u];
-                        const int64_t z = exact_z(cv.x, cv.y, rw[r].lamv, cu.x, cu.y, a.lam[u]);
-                        mx = z > mx ? z : mx;
-                        ++cnt;
-                    }
-                }
-                if (cnt == kTop) th = mx > 0 ? mx : 0;
-            }
-            rw[r].theta = th;
-            set_filter(rw[r], colmax);
-        } else {
-            rw[r].xv = rw[r].yv = 0.0f;
-            rw[r].lamv = 0; rw[r].theta = 0;
-            rw[r].a = rw[r].b = rw[r].c = 0.0f;
-            rw[r].thr = -INFINITY;   // never passes
-        }
-    }
-
-    for (int64_t tile = c0; tile < c1; tile += kTile) {
-        __syncthreads();
-        const int64_t cc = tile + t;
-        sc[t] = (cc < c1) ? a.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
-        __syncthreads();
-        const int64_t ntile = min((int64_t)kTile, c1 - tile);
-        for (int g = 0; g < ntile; g += kGroup) {
-            float m[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) m[r] = INFINITY;
-#pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const float4 cd = sc[g + q];
-#pragma unroll
-                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (m[r] <= rw[r].thr) {
-                    // exact pass over the group for this row
-                    for (int q = 0; q < kGroup; ++q) {
-                        const int64_t u = tile + g + q;
-                        if (u >= c1 || u == rw[r].v) continue;
-                        const float4 cd = sc[g + q];
-                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
-                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lam[u]);
-                        if (z > rw[r].theta) continue;
-                        if (z < 0) { ++neg[r]; rn[r] += z; }
-                        else if (z == 0) ++zero[r];
-                        top[r].insert(z, (int32_t)u);
-                        if (top[r].id[3] != kNoIdx) {
-                            const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
-                            if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
-                        }
-                    }
-                }
-            }
-        }
-    }
-
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t v = rw[r].v;
-        if (v >= n) continue;
-#pragma unroll
-        for (int j = 0; j < kTop; ++j) {
-            a.pz[(sl * kTop + j) * n + v] = top[r].z[j];
-            a.pi[(sl * kTop + j) * n + v] = top[r].id[j];
-        }
-        a.pneg[sl * n + v] = neg[r];
-        a.pzero[sl * n + v] = zero[r];
-        a.prowneg[sl * n + v] = rn[r];
-    }
-}
-
-// ---------------------------------------------------------------------------
 // block reductions
 // ---------------------------------------------------------------------------
 
@@ -276,8 +167,19 @@ __device__ __forceinline__ T wave_max(T x)
     return x;
 }
 
-// Sums (or maxes) one value per thread over the block; result valid in
-// thread 0.  `buf` holds kBlock/64 entries.
+template <typename T>
+__device__ __forceinline__ T wave_min(T x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const T y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// Sums (or maxes) one value per thread over the block; the result is
+// returned to every thread.  `buf` holds kBlock/64 entries.
 template <typename T, bool kMax>
 __device__ __forceinline__ T block_reduce(T x, T *buf)
 {
@@ -292,6 +194,190 @@ __device__ __forceinline__ T block_reduce(T x, T *buf)
 }
 
 // ---------------------------------------------------------------------------
+// row scan: rows x column slices over the sorted order
+// ---------------------------------------------------------------------------
+
+// Upper bound of the 4th smallest Z of row p from four seed columns
+// (positions): any four distinct columns bound the 4th order statistic.
+// Returns false when fewer than four usable seeds exist.
+__device__ __forceinline__ bool seeded_bound(const ScanArgs &a, int64_t p, float xv, float yv, int64_t lamv,
+                                             int64_t *out)
+{
+    const int64_t n = a.g.n;
+    int64_t mx = INT64_MIN;
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) {
+        const int32_t u = a.seed[j * n + p];
+        if (u >= 0 && u < n && u != p) {
+            const float4 cu = a.lv.col[u];
+            const int64_t z = exact_z(xv, yv, lamv, cu.x, cu.y, a.lv.lam[u]);
+            mx = z > mx ? z : mx;
+            ++cnt;
+        }
+    }
+    *out = mx;
+    return cnt == kTop;
+}
+
+// MODE kModeGdp: per row the four smallest (Z, label), #Z<0, #Z==0 and the
+// sum of the negative Z over the slice's columns, written as partials.
+// MODE kModeCert: the sum over the slice of min(0, Z) (theta = 0), added to
+// acc[0].  MODE kModeCollect: every pair with Z <= theta_row.
+template <int R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
+{
+    if (a.check_done && a.lv.ctrl->done) return;
+    __shared__ float4 sc[kTile];
+    __shared__ float redf[kBlock / 64];
+    __shared__ unsigned long long redu[kBlock / 64];
+    const int t = threadIdx.x;
+    const int64_t n = a.g.n;
+    const int64_t sl = blockIdx.y;
+    const int64_t c0 = sl * a.slice_len;
+    const int64_t c1 = min(n, c0 + a.slice_len);
+    const float colmax = col_bound(a.g.xy2max, a.lv.ctrl->maxabs_lam);
+
+    Row rw[R];
+    Top4 top[R];
+    int32_t neg[R], zero[R];
+    int64_t rn[R];
+    float hvmax = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + t;
+        rw[r].v = p;
+        top[r].clear();
+        neg[r] = 0; zero[r] = 0; rn[r] = 0;
+        if (p < n) {
+            const float4 cv = a.lv.col[p];
+            rw[r].xv = cv.x; rw[r].yv = cv.y;
+            rw[r].lamv = a.lv.lam[p];
+            int64_t th;
+            if (MODE == kModeCert) {
+                th = 0;
+            } else {
+                int64_t mx;
+                const bool ok = a.seed && seeded_bound(a, p, cv.x, cv.y, rw[r].lamv, &mx);
+                if (MODE == kModeGdp) th = ok ? (mx > 0 ? mx : 0) : kThetaNone;
+                else th = ok ? (mx > 0 ? mx : 0) + a.slack : a.theta;
+            }
+            rw[r].theta = th;
+            set_filter(rw[r], colmax);
+            hvmax = fmaxf(hvmax, -0.5f * rw[r].c);
+        } else {
+            rw[r].xv = rw[r].yv = 0.0f;
+            rw[r].lamv = 0; rw[r].theta = 0;
+            rw[r].a = rw[r].b = rw[r].c = 0.0f;
+            rw[r].thr = -INFINITY;   // never passes
+        }
+    }
+
+    // culling data: the largest row half-radius and the row block's box
+    float4 rbox = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+    if (a.cull) {
+        hvmax = block_reduce<float, true>(hvmax, redf);
+        const int64_t ntiles = (n + kTile - 1) / kTile;
+        for (int r = 0; r < R; ++r) {
+            const int64_t ti = (int64_t)blockIdx.x * R + r;
+            if (ti < ntiles) {
+                const float4 b = a.g.box[ti];
+                rbox.x = fminf(rbox.x, b.x); rbox.y = fmaxf(rbox.y, b.y);
+                rbox.z = fminf(rbox.z, b.z); rbox.w = fmaxf(rbox.w, b.w);
+            }
+        }
+    }
+
+    for (int64_t tile = c0; tile < c1; tile += kTile) {
+        if (a.cull) {
+            // every pair of the tile has D >= d2; it can pass only if
+            // D < (hv + hu)^2 for some row and column: uniform over the block
+            const int64_t ti = tile / kTile;
+            const float4 b = a.g.box[ti];
+            const float hu = a.lv.tile_hmax[ti];
+            const double dx = fmax(0.0, fmax((double)b.x - rbox.y, (double)rbox.x - b.y));
+            const double dy = fmax(0.0, fmax((double)b.z - rbox.w, (double)rbox.z - b.w));
+            const double d2 = dx * dx + dy * dy;
+            double hs = (double)hvmax + (double)hu;
+            hs += 1e-6 * (fabs((double)hvmax) + fabs((double)hu)) + 1.0;
+            if (hs <= 0.0 || d2 > hs * hs) continue;
+        }
+        __syncthreads();
+        const int64_t cc = tile + t;
+        sc[t] = (cc < c1) ? a.lv.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        __syncthreads();
+        const int64_t ntile = min((int64_t)kTile, c1 - tile);
+        for (int g = 0; g < ntile; g += kGroup) {
+            float m[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) m[r] = INFINITY;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const float4 cd = sc[g + q];
+#pragma unroll
+                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (m[r] <= rw[r].thr) {
+                    // exact pass over the group for this row
+                    for (int q = 0; q < kGroup; ++q) {
+                        const int64_t u = tile + g + q;
+                        if (u >= c1 || u == rw[r].v) continue;
+                        const float4 cd = sc[g + q];
+                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
+                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lv.lam[u]);
+                        if (MODE == kModeCert) {
+                            if (z < 0) rn[r] += z;
+                            continue;
+                        }
+                        if (z > rw[r].theta) continue;
+                        if (MODE == kModeCollect) {
+                            const unsigned long long slot = atomicAdd(a.count, 1ULL);
+                            if ((int64_t)slot < a.cap) {
+                                const int32_t lv = a.g.orig[rw[r].v], lu = a.g.orig[u];
+                                a.out[slot] = make_int2(min(lv, lu), max(lv, lu));
+                            }
+                            continue;
+                        }
+                        if (z < 0) { ++neg[r]; rn[r] += z; }
+                        else if (z == 0) ++zero[r];
+                        top[r].insert(z, a.g.orig[u]);
+                        if (top[r].id[3] != kNoIdx) {
+                            const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
+                            if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if (MODE == kModeGdp) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t p = rw[r].v;
+            if (p >= n) continue;
+#pragma unroll
+            for (int j = 0; j < kTop; ++j) {
+                a.pz[(sl * kTop + j) * n + p] = top[r].z[j];
+                a.pi[(sl * kTop + j) * n + p] = top[r].id[j];
+            }
+            a.pneg[sl * n + p] = neg[r];
+            a.pzero[sl * n + p] = zero[r];
+            a.prowneg[sl * n + p] = rn[r];
+        }
+    }
+    if (MODE == kModeCert) {
+        int64_t s = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s += rn[r];
+        const unsigned long long tot = block_reduce<unsigned long long, false>((unsigned long long)s, redu);
+        if (threadIdx.x == 0 && tot != 0) atomicAdd(&a.acc[0], tot);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // update: merge slices, step Lam, reduce, stop test
 // ---------------------------------------------------------------------------
 
@@ -300,42 +386,46 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
     Ctrl *ctrl = a.ctrl;
     if (ctrl->done) return;
     __shared__ unsigned long long red[kBlock / 64];
+    __shared__ float redf[kBlock / 64];
     __shared__ int s_last;
-    const int64_t n = a.n;
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t n = a.g.n;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     // Lam_{k-1} sits in lam_out until it is overwritten below
     const bool copy_best = a.k > 0 && ctrl->best_k == a.k - 1;
 
     unsigned long long sumlam = 0, rowneg = 0, unsat = 0, bad = 0, nonzero = 0, hsh = 0;
     long long maxstep = 0, maxabs = 0;
-    if (v < n) {
+    float hmax = -INFINITY;
+    if (p < n) {
+        const int64_t v = a.g.orig[p];
         Top4 top;
         top.clear();
         int64_t cn = 0, cz = 0, rn = 0;
         for (int64_t sl = 0; sl < a.nslices; ++sl) {
 #pragma unroll
             for (int j = 0; j < kTop; ++j)
-                top.insert(a.pz[(sl * kTop + j) * n + v], a.pi[(sl * kTop + j) * n + v]);
-            cn += a.pneg[sl * n + v];
-            cz += a.pzero[sl * n + v];
-            rn += a.prowneg[sl * n + v];
+                top.insert(a.pz[(sl * kTop + j) * n + p], a.pi[(sl * kTop + j) * n + p]);
+            cn += a.pneg[sl * n + p];
+            cz += a.pzero[sl * n + p];
+            rn += a.prowneg[sl * n + p];
         }
-        const int64_t lamv = a.lam_in[v];
+        const int64_t lamv = a.lam_in[p];
         const int64_t st = gdp_step(top.z[1] + top.z[2]);   // eq. 10: 2nd and 3rd shortest
         const int64_t nxt = lamv + st;
-        if (copy_best) a.lam_best[v] = a.lam_out[v];
-        a.lam_out[v] = nxt;
-        float4 cv = a.col[v];
+        if (copy_best) a.lam_best[p] = a.lam_out[p];
+        a.lam_out[p] = nxt;
+        float4 cv = a.col[p];
         const float h = (float)(0.5 * (double)nxt);
         cv.z = h;
         cv.w = fmaf(cv.x, cv.x, fmaf(cv.y, cv.y, -h * h));
-        a.col[v] = cv;
+        a.col[p] = cv;
+        hmax = h;
 #pragma unroll
         for (int j = 0; j < kTop; ++j) {
-            const int32_t id = top.id[j] == kNoIdx ? -1 : top.id[j];
+            const bool ok = top.id[j] != kNoIdx;
             a.z4[kTop * v + j] = top.z[j];
-            a.i4[kTop * v + j] = id;
-            a.seed[j * n + v] = id;
+            a.i4[kTop * v + j] = ok ? top.id[j] : -1;
+            a.seed[j * n + p] = ok ? a.g.pos[top.id[j]] : -1;
         }
         const int64_t deg2 = 2 * cn + cz;
         if (a.neg) a.neg[v] = (int32_t)cn;
@@ -350,6 +440,9 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
         maxabs = nxt < 0 ? -nxt : nxt;
         hsh = mix64((uint64_t)lamv ^ (0x9E3779B97F4A7C15ULL * (uint64_t)(v + 1)));
     }
+    // a block of kBlock positions is one column tile
+    hmax = block_reduce<float, true>(hmax, redf);
+    if (threadIdx.x == 0) a.tile_hmax[blockIdx.x] = hmax;
     sumlam = block_reduce<unsigned long long, false>(sumlam, red);
     rowneg = block_reduce<unsigned long long, false>(rowneg, red);
     unsat = block_reduce<unsigned long long, false>(unsat, red);
@@ -394,11 +487,11 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
     }
     if (ctrl->best_k < 0 || dual2 > ctrl->best_dual2) { ctrl->best_dual2 = dual2; ctrl->best_k = k; }
     long long stop = 0;
-    if (bd == 0) stop = 1;                              // trivial
-    else if (ctrl->handoff_div > 0 && un * ctrl->handoff_div <= a.n) stop = 5;   // handoff
-    else if (nz == 0) stop = 2;                         // fixed
-    else if (k >= 2 && hh == ctrl->h2) stop = 3;        // cycle
-    else if (k >= ctrl->max_iters) stop = 4;            // cap
+    if (bd == 0) stop = 1;                                                      // trivial
+    else if (ctrl->handoff_div > 0 && un * ctrl->handoff_div <= n) stop = 5;    // handoff
+    else if (nz == 0) stop = 2;                                                 // fixed
+    else if (k >= 2 && hh == ctrl->h2) stop = 3;                                // cycle
+    else if (k >= ctrl->max_iters) stop = 4;                                    // cap
     else if (mx >= kLamLimit) { stop = 4; ctrl->overflow = 1; }
     ctrl->k_last = k;
     ctrl->dual2_last = dual2;
@@ -450,41 +543,109 @@ __global__ __launch_bounds__(kBlock) void k_minmax(const int32_t *xy, int64_t n,
     }
 }
 
-// centred float coordinates; q and h filled by k_set_lam
-__global__ __launch_bounds__(kBlock) void k_prep(const int32_t *xy, int64_t n, int32_t cx, int32_t cy,
-                                                 float4 *col, unsigned int *xy2max_bits)
+// spread the low 16 bits of x to the even bit positions
+__device__ __forceinline__ uint32_t spread16(uint32_t x)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    float r2 = 0.0f;
-    if (i < n) {
-        const float x = (float)(xy[2 * i] - cx), y = (float)(xy[2 * i + 1] - cy);
-        col[i] = make_float4(x, y, 0.0f, x * x + y * y);
-        r2 = fmaf(x, x, y * y);
-        // round the bound up by a relative 2^-22 so it is >= the exact value
-        r2 = r2 * (1.0f + 0x1p-22f) + 1.0f;
-    }
-    for (int o = 32; o > 0; o >>= 1) r2 = fmaxf(r2, __shfl_xor(r2, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(xy2max_bits, __float_as_uint(r2));
+    x &= 0xffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
 }
 
-__global__ __launch_bounds__(kBlock) void k_set_lam(const int64_t *lam, int64_t n, float4 *col, Ctrl *ctrl)
+// Morton key of the top 16 bits of each (span < 2^20) coordinate offset
+__global__ __launch_bounds__(kBlock) void k_morton(const int32_t *xy, int64_t n, int32_t minx, int32_t miny,
+                                                   uint32_t *keys, int32_t *ids)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t x = (uint32_t)(xy[2 * i] - minx) >> 4, y = (uint32_t)(xy[2 * i + 1] - miny) >> 4;
+    keys[i] = spread16(x) | (spread16(y) << 1);
+    ids[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_inverse(const int32_t *orig, int64_t n, int32_t *pos)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) pos[orig[p]] = (int32_t)p;
+}
+
+// centred float coordinates in sorted order; one block is one tile
+__global__ __launch_bounds__(kBlock) void k_prep(const int32_t *xy, const int32_t *orig, int64_t n, int32_t cx,
+                                                 int32_t cy, float4 *col, float4 *box, unsigned int *xy2max_bits)
+{
+    __shared__ float redf[kBlock / 64];
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    float r2 = 0.0f, x = 0.0f, y = 0.0f;
+    const bool ok = p < n;
+    if (ok) {
+        const int64_t v = orig[p];
+        x = (float)(xy[2 * v] - cx);
+        y = (float)(xy[2 * v + 1] - cy);
+        col[p] = make_float4(x, y, 0.0f, x * x + y * y);
+        // round the bound up by a relative 2^-22 so it is >= the exact value
+        r2 = fmaf(x, x, y * y) * (1.0f + 0x1p-22f) + 1.0f;
+    }
+    const float mnx = -block_reduce<float, true>(ok ? -x : -INFINITY, redf);
+    const float mxx = block_reduce<float, true>(ok ? x : -INFINITY, redf);
+    const float mny = -block_reduce<float, true>(ok ? -y : -INFINITY, redf);
+    const float mxy = block_reduce<float, true>(ok ? y : -INFINITY, redf);
+    r2 = block_reduce<float, true>(r2, redf);
+    if (threadIdx.x == 0) {
+        box[blockIdx.x] = make_float4(mnx, mxx, mny, mxy);
+        atomicMax(xy2max_bits, __float_as_uint(r2));
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_lam(const int64_t *lam_label, const int32_t *orig, int64_t n,
+                                                    int64_t *lam_sorted, float4 *col, float *tile_hmax, Ctrl *ctrl)
+{
+    __shared__ float redf[kBlock / 64];
+    __shared__ unsigned long long redu[kBlock / 64];
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     unsigned long long ab = 0;
-    if (i < n) {
-        const int64_t l = lam[i];
-        float4 cv = col[i];
-        const float h = (float)(0.5 * (double)l);
+    float h = -INFINITY;
+    if (p < n) {
+        const int64_t l = lam_label[orig[p]];
+        lam_sorted[p] = l;
+        float4 cv = col[p];
+        h = (float)(0.5 * (double)l);
         cv.z = h;
         cv.w = fmaf(cv.x, cv.x, fmaf(cv.y, cv.y, -h * h));
-        col[i] = cv;
+        col[p] = cv;
         ab = (unsigned long long)(l < 0 ? -l : l);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long y = __shfl_xor(ab, o, 64);
-        ab = y > ab ? y : ab;
+    h = block_reduce<float, true>(h, redf);
+    ab = block_reduce<unsigned long long, true>(ab, redu);
+    if (threadIdx.x == 0) {
+        tile_hmax[blockIdx.x] = h;
+        atomicMax((unsigned long long *)&ctrl->maxabs_lam, ab);
     }
-    if ((threadIdx.x & 63) == 0) atomicMax((unsigned long long *)&ctrl->maxabs_lam, ab);
+}
+
+__global__ __launch_bounds__(kBlock) void k_unpermute(const int64_t *lam_sorted, const int32_t *orig, int64_t n,
+                                                      int64_t *lam_label)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) lam_label[orig[p]] = lam_sorted[p];
+}
+
+// four positions next to p in the sorted order (spatial neighbours): the
+// first iteration's threshold seeds
+__global__ __launch_bounds__(kBlock) void k_seed_neighbours(int64_t n, int32_t *seed)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    if (n < 5) {
+        for (int j = 0; j < kTop; ++j) seed[j * n + p] = -1;
+        return;
+    }
+    int64_t lo = p - 2;
+    lo = lo < 0 ? 0 : (lo > n - 5 ? n - 5 : lo);
+    int j = 0;
+    for (int64_t q = lo; q < lo + 5; ++q)
+        if (q != p) seed[(j++) * n + p] = (int32_t)q;
 }
 
 __global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div)
@@ -582,155 +743,8 @@ __global__ __launch_bounds__(kBlock) void k_compact_scatter(const int32_t *su, c
 }
 
 // ---------------------------------------------------------------------------
-// certificate
+// certificate: primal side
 // ---------------------------------------------------------------------------
-
-// sum over ordered pairs of min(0, Z) (theta = 0: only Z <= 0 matters)
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_cert_scan(CertScanArgs a)
-{
-    __shared__ float4 sc[kTile];
-    __shared__ unsigned long long red[kBlock / 64];
-    const int t = threadIdx.x;
-    const int64_t n = a.n;
-    const int64_t c0 = (int64_t)blockIdx.y * a.slice_len;
-    const int64_t c1 = min(n, c0 + a.slice_len);
-    const float colmax = col_bound(a.xy2max, a.ctrl->maxabs_lam);
-    Row rw[R];
-    int64_t rn[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t v = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + t;
-        rw[r].v = v;
-        rn[r] = 0;
-        if (v < n) {
-            const float4 cv = a.col[v];
-            rw[r].xv = cv.x; rw[r].yv = cv.y;
-            rw[r].lamv = a.lam[v];
-            rw[r].theta = 0;
-            set_filter(rw[r], colmax);
-        } else {
-            rw[r].xv = rw[r].yv = 0.0f; rw[r].lamv = 0; rw[r].theta = 0;
-            rw[r].a = rw[r].b = rw[r].c = 0.0f; rw[r].thr = -INFINITY;
-        }
-    }
-    for (int64_t tile = c0; tile < c1; tile += kTile) {
-        __syncthreads();
-        const int64_t cc = tile + t;
-        sc[t] = (cc < c1) ? a.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
-        __syncthreads();
-        const int64_t ntile = min((int64_t)kTile, c1 - tile);
-        for (int g = 0; g < ntile; g += kGroup) {
-            float m[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) m[r] = INFINITY;
-#pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const float4 cd = sc[g + q];
-#pragma unroll
-                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (m[r] <= rw[r].thr) {
-                    for (int q = 0; q < kGroup; ++q) {
-                        const int64_t u = tile + g + q;
-                        if (u >= c1 || u == rw[r].v) continue;
-                        const float4 cd = sc[g + q];
-                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
-                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lam[u]);
-                        if (z < 0) rn[r] += z;
-                    }
-                }
-            }
-        }
-    }
-    int64_t s = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) s += rn[r];
-    const unsigned long long tot = block_reduce<unsigned long long, false>((unsigned long long)s, red);
-    if (threadIdx.x == 0 && tot != 0) atomicAdd(&a.acc[0], tot);
-}
-
-// every pair (v, u) with Z_vu <= theta_v, reported as (min, max)
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_collect(CollectArgs a)
-{
-    __shared__ float4 sc[kTile];
-    const int t = threadIdx.x;
-    const int64_t n = a.n;
-    const int64_t c0 = (int64_t)blockIdx.y * a.slice_len;
-    const int64_t c1 = min(n, c0 + a.slice_len);
-    const float colmax = col_bound(a.xy2max, a.ctrl->maxabs_lam);
-    Row rw[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t v = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + t;
-        rw[r].v = v;
-        if (v < n) {
-            const float4 cv = a.col[v];
-            rw[r].xv = cv.x; rw[r].yv = cv.y;
-            rw[r].lamv = a.lam[v];
-            int64_t th = a.theta;
-            if (a.seed) {
-                int64_t mx = INT64_MIN;
-                int cnt = 0;
-#pragma unroll
-                for (int j = 0; j < kTop; ++j) {
-                    const int32_t u = a.seed[j * n + v];
-                    if (u >= 0 && u < n && u != v) {
-                        const float4 cu = a.col[u];
-                        const int64_t z = exact_z(cv.x, cv.y, rw[r].lamv, cu.x, cu.y, a.lam[u]);
-                        mx = z > mx ? z : mx;
-                        ++cnt;
-                    }
-                }
-                if (cnt == kTop) th = (mx > 0 ? mx : 0) + a.slack;
-            }
-            rw[r].theta = th;
-            set_filter(rw[r], colmax);
-        } else {
-            rw[r].xv = rw[r].yv = 0.0f; rw[r].lamv = 0; rw[r].theta = 0;
-            rw[r].a = rw[r].b = rw[r].c = 0.0f; rw[r].thr = -INFINITY;
-        }
-    }
-    for (int64_t tile = c0; tile < c1; tile += kTile) {
-        __syncthreads();
-        const int64_t cc = tile + t;
-        sc[t] = (cc < c1) ? a.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
-        __syncthreads();
-        const int64_t ntile = min((int64_t)kTile, c1 - tile);
-        for (int g = 0; g < ntile; g += kGroup) {
-            float m[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) m[r] = INFINITY;
-#pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const float4 cd = sc[g + q];
-#pragma unroll
-                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (m[r] <= rw[r].thr) {
-                    for (int q = 0; q < kGroup; ++q) {
-                        const int64_t u = tile + g + q;
-                        if (u >= c1 || u == rw[r].v) continue;
-                        const float4 cd = sc[g + q];
-                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
-                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lam[u]);
-                        if (z > rw[r].theta) continue;
-                        const unsigned long long slot = atomicAdd(a.count, 1ULL);
-                        if ((int64_t)slot < a.cap) {
-                            const int32_t lo = (int32_t)min(rw[r].v, u), hi = (int32_t)max(rw[r].v, u);
-                            a.out[slot] = make_int2(lo, hi);
-                        }
-                    }
-                }
-            }
-        }
-    }
-}
 
 // acc: [0] sum min(0,Z) ordered, [1] primal2, [2] #violations, [3] sum Lam
 __global__ __launch_bounds__(kBlock) void k_cert_edges(const int32_t *xy, int64_t n, int64_t m, const int32_t *eu,
@@ -798,51 +812,88 @@ hipError_t launch_minmax(const int32_t *xy, int64_t n, int32_t *out4, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const int32_t *xy, int64_t n, int32_t cx, int32_t cy, float4 *col, float *xy2max_dev,
-                       hipStream_t st)
+size_t sort_temp_bytes(int64_t n)
+{
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                             (const int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 32);
+    return bytes;
+}
+
+hipError_t launch_sort(const int32_t *xy, int64_t n, int32_t minx, int32_t miny, uint32_t *keys, uint32_t *keys_alt,
+                       int32_t *ids, int32_t *orig, int32_t *pos, void *temp, size_t temp_bytes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_morton, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, xy, n, minx, miny, keys, ids);
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys, keys_alt, ids, orig, (int)n, 0, 32, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_inverse, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, orig, n, pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const int32_t *xy, const int32_t *orig, int64_t n, int32_t cx, int32_t cy, float4 *col,
+                       float4 *box, float *xy2max_dev, hipStream_t st)
 {
     hipError_t e = hipMemsetAsync(xy2max_dev, 0, sizeof(float), st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_prep, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, xy, n, cx, cy, col,
+    hipLaunchKernelGGL(k_prep, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, xy, orig, n, cx, cy, col, box,
                        (unsigned int *)xy2max_dev);
     return hipGetLastError();
 }
 
-hipError_t launch_set_lam(const int64_t *lam, int64_t n, float4 *col, Ctrl *ctrl, hipStream_t st)
+hipError_t launch_set_lam(const int64_t *lam_label, const int32_t *orig, int64_t n, int64_t *lam_sorted, float4 *col,
+                          float *tile_hmax, Ctrl *ctrl, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_set_lam, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam, n, col, ctrl);
+    hipLaunchKernelGGL(k_set_lam, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam_label, orig, n, lam_sorted,
+                       col, tile_hmax, ctrl);
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div,
+hipError_t launch_unpermute(const int64_t *lam_sorted, const int32_t *orig, int64_t n, int64_t *lam_label,
                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unpermute, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam_sorted, orig, n, lam_label);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_neighbours(int64_t n, int32_t *seed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seed_neighbours, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, n, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div, hipStream_t st)
 {
     hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, max_iters, trace_cap, handoff_div);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const ScanArgs &a, int64_t nslices, int rows_per_thread, hipStream_t st)
+template <int MODE>
+static hipError_t launch_scan_mode(const ScanArgs &a, int64_t nslices, int R, hipStream_t st)
 {
     const unsigned gy = (unsigned)nslices;
-    switch (rows_per_thread) {
-    case 1:
-        hipLaunchKernelGGL(k_scan<1>, dim3(blocks_for(a.n, kBlock), gy), dim3(kBlock), 0, st, a);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_scan<2>, dim3(blocks_for(a.n, 2 * kBlock), gy), dim3(kBlock), 0, st, a);
-        break;
-    case 4:
-        hipLaunchKernelGGL(k_scan<4>, dim3(blocks_for(a.n, 4 * kBlock), gy), dim3(kBlock), 0, st, a);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    switch (R) {
+    case 1: hipLaunchKernelGGL((k_rowscan<1, MODE>), dim3(blocks_for(a.g.n, kBlock), gy), dim3(kBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_rowscan<2, MODE>), dim3(blocks_for(a.g.n, 2 * kBlock), gy), dim3(kBlock), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_rowscan<4, MODE>), dim3(blocks_for(a.g.n, 4 * kBlock), gy), dim3(kBlock), 0, st, a); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_per_thread, hipStream_t st)
+{
+    if (a.slice_len % kTile != 0) return hipErrorInvalidValue;
+    switch (mode) {
+    case kModeGdp: return launch_scan_mode<kModeGdp>(a, nslices, rows_per_thread, st);
+    case kModeCert: return launch_scan_mode<kModeCert>(a, nslices, rows_per_thread, st);
+    case kModeCollect: return launch_scan_mode<kModeCollect>(a, nslices, rows_per_thread, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_update, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_update, dim3(blocks_for(a.g.n, kBlock)), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
@@ -864,19 +915,6 @@ hipError_t launch_compact(const int32_t *su, const int32_t *sv, const uint8_t *s
     hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kBlock), 0, st, su, ns, btmp);
     hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, btmp, (int64_t)nb, count_dev);
     hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(kBlock), 0, st, su, sv, sx, ns, btmp, eu, ev, ex);
-    return hipGetLastError();
-}
-
-hipError_t launch_collect(const CollectArgs &a, int64_t nslices, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_collect<2>, dim3(blocks_for(a.n, 2 * kBlock), (unsigned)nslices), dim3(kBlock), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_cert_scan(const CertScanArgs &a, int64_t nslices, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_cert_scan<2>, dim3(blocks_for(a.n, 2 * kBlock), (unsigned)nslices), dim3(kBlock), 0, st,
-                       a);
     return hipGetLastError();
 }
 

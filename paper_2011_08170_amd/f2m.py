@@ -21,6 +21,7 @@ STATUS = {0: "ok", 1: "not certified", -1: "invalid argument", -2: "coordinate s
           -7: "multiplier overflow"}
 STOP_NAMES = {0: "none", 1: "trivial", 2: "fixed", 3: "cycle", 4: "cap", 5: "handoff"}
 FINISH = {"none": 0, "exact": 1}
+SCAN = {"culled": 0, "full": 1}
 TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
 SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
@@ -38,7 +39,8 @@ class Opts(C.Structure):
                 ("warm", C.c_int32), ("lambda2_init", C.c_void_p), ("max_iters", C.c_int64),
                 ("handoff_div", C.c_int64),
                 ("finish", C.c_int32), ("coords_on_device", C.c_int32), ("record_trace", C.c_int32),
-                ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("hip_stream", C.c_void_p)]
+                ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("scan_mode", C.c_int32),
+                ("hip_stream", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -133,7 +135,7 @@ class Context:
         return st
 
     def solve(self, coords, *, max_iters=100000, handoff_div=300, finish="exact", lambda2_init=None,
-              trace=False, chunk=0, stream=None, time_kernels=False):
+              trace=False, chunk=0, stream=None, time_kernels=False, scan="culled"):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
         array on the host or a contiguous int32 device tensor."""
         o = Opts()
@@ -144,6 +146,7 @@ class Context:
         o.record_trace = 1 if trace else 0
         o.chunk = int(chunk)
         o.time_kernels = 1 if time_kernels else 0
+        o.scan_mode = SCAN[scan]
         keep = []
         if lambda2_init is not None:
             l0 = _np(lambda2_init, np.int64)

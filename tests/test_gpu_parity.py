@@ -73,12 +73,13 @@ def test_gdp_step_matches_oracle(ctx, name, make):
             assert rec[f] == o["rec"][f], (name, f)
 
 
-@pytest.mark.parametrize("seed,div", [(1, 0), (2, 0), (3, 0), (1, 300), (2, 50)])
-def test_solve_trajectory_c1(ctx, seed, div):
+@pytest.mark.parametrize("seed,div,scan", [(1, 0, "culled"), (2, 0, "culled"), (3, 0, "full"), (1, 300, "full"),
+                                           (2, 50, "culled")])
+def test_solve_trajectory_c1(ctx, seed, div, scan):
     # n = 1000, uniform in [0, 10^5)^2: the trajectory, the stop and Lam*
     xy = I.uniform(1000, 100000, seed)
     o = core.gdp_solve(xy, handoff_div=div)
-    g = ctx.solve(xy, trace=True, finish="none", handoff_div=div)
+    g = ctx.solve(xy, trace=True, finish="none", handoff_div=div, scan=scan)
     assert g["iterations"] == o["iters"] and g["stop"] == o["stop"] and g["kstar"] == o["kstar"]
     assert np.array_equal(g["trace"], o["trace"])
     assert np.array_equal(g["lambda2_gdp"], o["lam"])
@@ -125,6 +126,20 @@ def test_n3_and_errors(ctx):
     with pytest.raises(f2m.F2MError) as e:
         ctx.solve(np.array([[0, 0], [1 << 20, 0], [5, 5], [7, 7]], np.int32))
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("name,make", [("clustered_5000", lambda: I.clustered(5000, 1000000, 11)),
+                                       ("uniform_12289", lambda: I.uniform(12289, 1000000, 12))])
+def test_full_and_culled_scans_agree_with_oracle(ctx, name, make):
+    # the full scan (every ordered pair) and the culled scan give the same
+    # bits; both equal the oracle's first iterations
+    xy = make()
+    a = ctx.solve(xy, trace=True, finish="none", max_iters=6, scan="full")
+    b = ctx.solve(xy, trace=True, finish="none", max_iters=6, scan="culled")
+    assert np.array_equal(a["trace"], b["trace"]) and np.array_equal(a["lambda2_gdp"], b["lambda2_gdp"])
+    o = core.gdp_solve(xy, max_iters=6)
+    assert np.array_equal(a["trace"], o["trace"])
+    assert np.array_equal(a["lambda2_gdp"], o["lam"])
 
 
 def test_device_coords_same_as_host(ctx):
