@@ -126,6 +126,7 @@ typedef struct f2m_result {
     int32_t scan_rows;      /* scan launch shape: rows per lane */
     int32_t pad0;
     int64_t scan_slices;    /* scan launch shape: column slices */
+    int64_t scan_pairs;     /* ordered pairs the GDP scans evaluated (culled tiles excluded) */
 } f2m_result;
 
 /* Fills opts with the defaults: rule 1, complete graph, cold start,

@@ -370,6 +370,7 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             sa.slice_len = sh.slice_len;
             sa.cull = cull ? 1 : 0;
             sa.check_done = 1;
+            sa.tested = &cd->pairs_tested;
             sa.seed = seed;
             sa.pz = pz; sa.pi = pi; sa.pneg = pneg; sa.pzero = pzero; sa.prowneg = prn;
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
@@ -740,6 +741,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         res.primal2 = cert[0];
         res.dual2 = have_x ? cert[1] : res.dual2_gdp;
         res.certified = (int32_t)cert[3];
+        res.scan_pairs = (int64_t)lo.c.pairs_tested;
         res.scan_ms = lo.scan_ms;
         res.scan_launches = lo.scan_launches;
         res.scan_rows = lo.shape.rows;

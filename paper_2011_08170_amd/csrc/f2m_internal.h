@@ -52,6 +52,7 @@ struct Ctrl {
     long long trace_cap;
     long long dual2_last;  // dual2 of Lam_{k_last}
     long long handoff_div; // hand-off stop: #unsat * div <= n (0: off)
+    unsigned long long pairs_tested;   // ordered pairs the GDP scans evaluated (all iterations)
 };
 
 // Static geometry of an instance in sorted order.
@@ -80,6 +81,7 @@ struct ScanArgs {
     int64_t slice_len;          // columns per slice (blockIdx.y), multiple of kTileCols
     int cull;                   // skip column tiles that cannot hold a passing pair
     int check_done;             // GDP loop: exit at once when ctrl->done
+    unsigned long long *tested; // if set: += ordered pairs evaluated (culled tiles excluded)
     const int32_t *seed;        // [j][n] positions bounding the 4th smallest Z, or null
     // GDP mode: partial results per (slice, position), structure of arrays
     int64_t *pz;                // [slice][4][n]

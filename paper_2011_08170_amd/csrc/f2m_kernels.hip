@@ -288,6 +288,10 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
         }
     }
 
+    // rows of this block: positions [rb0, rb1)
+    const int64_t rb0 = (int64_t)blockIdx.x * (kBlock * R);
+    const int64_t rb1 = min(n, rb0 + (int64_t)kBlock * R);
+    unsigned long long tested = 0;
     for (int64_t tile = c0; tile < c1; tile += kTile) {
         if (a.cull) {
             // every pair of the tile has D >= d2; it can pass only if
@@ -307,6 +311,9 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
         sc[t] = (cc < c1) ? a.lv.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
         __syncthreads();
         const int64_t ntile = min((int64_t)kTile, c1 - tile);
+        // ordered pairs of this tile, the diagonal excluded
+        tested += (unsigned long long)((rb1 - rb0) * ntile -
+                                       max((int64_t)0, min(rb1, tile + ntile) - max(rb0, tile)));
         for (int g = 0; g < ntile; g += kGroup) {
             float m[R];
 #pragma unroll
@@ -353,6 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
         }
     }
 
+    if (a.tested && threadIdx.x == 0 && tested) atomicAdd(a.tested, tested);
     if (MODE == kModeGdp) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {

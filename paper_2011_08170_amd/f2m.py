@@ -52,7 +52,7 @@ class Result(C.Structure):
                 ("dual2_gdp", C.c_int64), ("finish_paths", C.c_int64), ("finish_rounds", C.c_int64),
                 ("trace_len", C.c_int64), ("trace", C.POINTER(C.c_int64)), ("seconds", C.c_double * 6),
                 ("scan_ms", C.c_double), ("scan_launches", C.c_int64), ("scan_rows", C.c_int32),
-                ("pad0", C.c_int32), ("scan_slices", C.c_int64)]
+                ("pad0", C.c_int32), ("scan_slices", C.c_int64), ("scan_pairs", C.c_int64)]
 
 
 _lib = None
@@ -179,7 +179,7 @@ class Context:
                 edge_x2=np.ctypeslib.as_array(res.edge_x2, (max(m, 1),))[:m].copy(),
                 seconds=dict(zip(("setup", "warm", "gdp", "finish", "certify", "total"), list(res.seconds))),
                 scan_ms=res.scan_ms, scan_launches=res.scan_launches, scan_rows=res.scan_rows,
-                scan_slices=res.scan_slices,
+                scan_slices=res.scan_slices, scan_pairs=res.scan_pairs,
             )
             if res.trace_len:
                 out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(

@@ -137,6 +137,9 @@ def test_full_and_culled_scans_agree_with_oracle(ctx, name, make):
     a = ctx.solve(xy, trace=True, finish="none", max_iters=6, scan="full")
     b = ctx.solve(xy, trace=True, finish="none", max_iters=6, scan="culled")
     assert np.array_equal(a["trace"], b["trace"]) and np.array_equal(a["lambda2_gdp"], b["lambda2_gdp"])
+    n = len(xy)
+    assert a["scan_pairs"] == a["iterations"] * n * (n - 1)
+    assert 0 < b["scan_pairs"] < a["scan_pairs"]
     o = core.gdp_solve(xy, max_iters=6)
     assert np.array_equal(a["trace"], o["trace"])
     assert np.array_equal(a["lambda2_gdp"], o["lam"])
