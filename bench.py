@@ -151,6 +151,10 @@ def main():
         "stop": [r["stop"] for r in runs],
         "objective2": runs[-1]["primal2"],
         "phase_s": {k: float(np.mean([r["seconds"][k] for r in runs])) for k in ("setup", "gdp", "finish", "certify")},
+        "finish_detail": {"seconds": {k: float(np.mean([r["finish_seconds"][k] for r in runs]))
+                                      for k in ("collect", "build", "flow")},
+                          "paths": runs[-1]["finish_paths"], "phases": runs[-1]["finish_phases"],
+                          "rounds": runs[-1]["finish_rounds"], "candidates": runs[-1]["finish_candidates"]},
         "scan_pair_evals_per_s": pairs / (avg_ms * 1e-3),
         "roofline": {"bound": "alu", "kernel": "k_rowscan<%d,gdp>" % runs[-1]["scan_rows"], "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,

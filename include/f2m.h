@@ -127,6 +127,9 @@ typedef struct f2m_result {
     int32_t pad0;
     int64_t scan_slices;    /* scan launch shape: column slices */
     int64_t scan_pairs;     /* ordered pairs the GDP scans evaluated (culled tiles excluded) */
+    int64_t finish_phases;      /* Dijkstra phases of the exact finish */
+    int64_t finish_candidates;  /* candidate pairs of the exact finish at the end */
+    double finish_seconds[3];   /* exact finish: pair collection (GPU), candidate build, flow */
 } f2m_result;
 
 /* Fills opts with the defaults: rule 1, complete graph, cold start,

@@ -703,6 +703,11 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             finish_exact(xy_host.data(), n, res.lambda2_gdp, src, &fr);
             res.finish_paths = fr.paths;
             res.finish_rounds = fr.rounds;
+            res.finish_phases = fr.phases;
+            res.finish_candidates = fr.candidates;
+            res.finish_seconds[0] = fr.t_collect;
+            res.finish_seconds[1] = fr.t_build;
+            res.finish_seconds[2] = fr.t_flow;
             if (!fr.ok) fail(ctx, F2M_ERR_DEVICE, "exact finish failed: " + fr.msg);
             m = (int64_t)fr.eu.size();
             int64_t *ld = grow<int64_t>(ctx, ctx->c_lam_label, n);

@@ -7,7 +7,8 @@
 #include <cmath>
 #include <limits>
 #include <queue>
-#include <unordered_set>
+#include <chrono>
+#include <iterator>
 
 namespace f2m {
 
@@ -37,19 +38,38 @@ public:
             beta_[v] = lam[v] - alpha_[v];
             ex_[v] = 2;        // left copies supply 2
             ex_[n + v] = -2;   // right copies demand 2
+            src_.push_back(v);
         }
     }
 
     int64_t edges() const { return (int64_t)ea_.size(); }
 
-    // Adds new candidate edges; arcs of negative reduced cost start saturated.
+    // Adds new candidate edges (a sorted list of distinct pairs); arcs of
+    // negative reduced cost start saturated.
     void add(const PairList &pl)
     {
+        std::vector<uint64_t> fresh;
+        fresh.reserve(pl.size());
+        size_t j = 0;
         for (const auto &p : pl) {
-            int32_t a = std::min(p.first, p.second), b = std::max(p.first, p.second);
+            const int32_t a = std::min(p.first, p.second), b = std::max(p.first, p.second);
             if (a == b || a < 0 || b >= n_) continue;
             const uint64_t key = (uint64_t)a * (uint64_t)n_ + (uint64_t)b;
-            if (!have_.insert(key).second) continue;
+            while (j < keys_.size() && keys_[j] < key) ++j;
+            if (j < keys_.size() && keys_[j] == key) continue;
+            if (!fresh.empty() && fresh.back() >= key) {
+                if (fresh.back() == key) continue;
+                // unsorted input: fall back to a sorted copy
+                std::vector<std::pair<int32_t, int32_t>> cp(pl.begin(), pl.end());
+                std::sort(cp.begin(), cp.end());
+                cp.erase(std::unique(cp.begin(), cp.end()), cp.end());
+                add(cp);
+                return;
+            }
+            fresh.push_back(key);
+        }
+        for (uint64_t key : fresh) {
+            const int32_t a = (int32_t)(key / (uint64_t)n_), b = (int32_t)(key % (uint64_t)n_);
             const int64_t dx = (int64_t)xy_[2 * a] - xy_[2 * b], dy = (int64_t)xy_[2 * a + 1] - xy_[2 * b + 1];
             const int64_t c = nint_sqrt_host(dx * dx + dy * dy);
             ea_.push_back(a);
@@ -59,8 +79,18 @@ public:
                 const int64_t k = 2 * ((int64_t)ea_.size() - 1) + d;
                 const bool neg = red(k) < 0;
                 y_.push_back(neg ? 1 : 0);
-                if (neg) { --ex_[tail(k)]; ++ex_[n_ + head(k)]; }
+                if (neg) {
+                    --ex_[tail(k)];
+                    const int64_t h = n_ + head(k);
+                    if (++ex_[h] == 1) src_.push_back(h);
+                }
             }
+        }
+        if (!fresh.empty()) {
+            std::vector<uint64_t> merged;
+            merged.reserve(keys_.size() + fresh.size());
+            std::merge(keys_.begin(), keys_.end(), fresh.begin(), fresh.end(), std::back_inserter(merged));
+            keys_.swap(merged);
         }
         build_adjacency();
     }
@@ -69,21 +99,26 @@ public:
     // cannot reach a deficit (the candidate graph is too small).
     bool solve(int64_t &paths, int64_t &phases)
     {
-        std::vector<int64_t> dist(2 * n_, kInf);
-        std::vector<int32_t> seen(2 * n_, 0), dead(2 * n_, 0);
+        std::vector<int64_t> &dist = dist_;
+        dist.assign(2 * n_, kInf);
+        std::vector<int32_t> seen(2 * n_, 0);
         int32_t stamp = 0;
         std::vector<int64_t> touched;
         for (;;) {
-            bool any = false;
-            for (int64_t x = 0; x < 2 * n_; ++x) if (ex_[x] > 0) { any = true; break; }
-            if (!any) return true;
+            // the excess nodes (the list only shrinks while solving)
+            size_t w = 0;
+            for (size_t i = 0; i < src_.size(); ++i)
+                if (ex_[src_[i]] > 0) src_[w++] = src_[i];
+            src_.resize(w);
+            std::sort(src_.begin(), src_.end());
+            src_.erase(std::unique(src_.begin(), src_.end()), src_.end());
+            if (src_.empty()) return true;
             // Dijkstra from every excess node on reduced costs
             using Item = std::pair<int64_t, int64_t>;
             std::priority_queue<Item, std::vector<Item>, std::greater<Item>> pq;
             for (int64_t x : touched) dist[x] = kInf;
             touched.clear();
-            for (int64_t x = 0; x < 2 * n_; ++x)
-                if (ex_[x] > 0) { dist[x] = 0; touched.push_back(x); pq.push({0, x}); }
+            for (int64_t x : src_) { dist[x] = 0; touched.push_back(x); pq.push({0, x}); }
             int64_t D = -1;
             while (!pq.empty()) {
                 const auto [d, x] = pq.top();
@@ -94,27 +129,32 @@ public:
             }
             if (D < 0) return false;
             ++phases;
-            // potentials: p(x) -= min(dist(x), D); p(v') = alpha_v, p(u'') = -beta_u
-            for (int64_t v = 0; v < n_; ++v) {
-                alpha_[v] -= std::min(dist[v], D);
-                beta_[v] += std::min(dist[n_ + v], D);
+            // potentials: p(x) -= min(dist(x), D) with p(v') = alpha_v,
+            // p(u'') = -beta_u; only nodes closer than D move relative to
+            // the global offsets
+            for (int64_t x : touched) {
+                const int64_t d = dist[x];
+                if (d >= D) continue;
+                if (x < n_) alpha_[x] += D - d;
+                else beta_[x - n_] -= D - d;
             }
+            A_ -= D;
+            B_ += D;
             // unit augmentations along zero-reduced-cost paths
             ++stamp;
-            for (int64_t s = 0; s < 2 * n_; ++s) {
+            for (int64_t s : src_) {
                 while (ex_[s] > 0 && seen[s] != stamp) {
                     if (!augment_from(s, stamp, seen)) break;
                     ++paths;
                 }
             }
-            (void)dead;
         }
     }
 
     void lam(std::vector<int64_t> &out) const
     {
         out.resize(n_);
-        for (int64_t v = 0; v < n_; ++v) out[v] = alpha_[v] + beta_[v];
+        for (int64_t v = 0; v < n_; ++v) out[v] = alpha_[v] + A_ + beta_[v] + B_;
     }
 
     void x(std::vector<int32_t> &eu, std::vector<int32_t> &ev, std::vector<uint8_t> &ex2) const
@@ -136,7 +176,8 @@ public:
 private:
     int64_t tail(int64_t k) const { return (k & 1) ? eb_[k >> 1] : ea_[k >> 1]; }
     int64_t head(int64_t k) const { return (k & 1) ? ea_[k >> 1] : eb_[k >> 1]; }
-    int64_t red(int64_t k) const { return ec_[k >> 1] - alpha_[tail(k)] - beta_[head(k)]; }
+    // alpha, beta are stored relative to the global offsets A_, B_
+    int64_t red(int64_t k) const { return ec_[k >> 1] - alpha_[tail(k)] - beta_[head(k)] - A_ - B_; }
 
     void build_adjacency()
     {
@@ -227,43 +268,66 @@ private:
     const int32_t *xy_;
     int64_t n_;
     std::vector<int64_t> alpha_, beta_;
+    int64_t A_ = 0, B_ = 0;          // global offsets of alpha and beta
     std::vector<int64_t> ex_;
+    std::vector<int64_t> src_;       // nodes with excess (may hold stale entries)
+    std::vector<int64_t> dist_;
+    std::vector<uint64_t> keys_;     // sorted keys a*n+b of the candidate edges
     std::vector<int32_t> ea_, eb_;
     std::vector<int64_t> ec_;
     std::vector<uint8_t> y_;
-    std::unordered_set<uint64_t> have_;
     std::vector<int64_t> lstart_, rstart_, larc_, rarc_;
 };
 
 }  // namespace
 
+static double secs()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out)
 {
     FinishResult &r = *out;
     r = FinishResult();
+    double t = secs();
     DoubleCover g(xy, n, lam0);
     std::string err;
     PairList pl;
     int64_t slack = 16;
     if (!src.near(lam0, slack, pl, err)) { r.msg = err; return; }
+    r.t_collect += secs() - t;
+    t = secs();
     g.add(pl);
+    r.t_build += secs() - t;
     std::vector<int64_t> lam;
     for (int round = 0; round < 64; ++round) {
         ++r.rounds;
-        if (!g.solve(r.paths, r.phases)) {
+        t = secs();
+        const bool ok = g.solve(r.paths, r.phases);
+        r.t_flow += secs() - t;
+        if (!ok) {
             // too few candidates for a degree-2 flow: widen around the current duals
             slack *= 4;
             g.lam(lam);
             pl.clear();
+            t = secs();
             if (!src.near(lam.data(), slack, pl, err)) { r.msg = err; return; }
+            r.t_collect += secs() - t;
+            t = secs();
             g.add(pl);
+            r.t_build += secs() - t;
             continue;
         }
         g.lam(lam);
         pl.clear();
+        t = secs();
         if (!src.negative(lam.data(), pl, err)) { r.msg = err; return; }
+        r.t_collect += secs() - t;
         const int64_t before = g.edges();
+        t = secs();
         g.add(pl);
+        r.t_build += secs() - t;
         if (g.edges() == before) {
             r.ok = true;
             r.lam = lam;

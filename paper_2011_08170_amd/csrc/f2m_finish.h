@@ -49,6 +49,9 @@ struct FinishResult {
     int64_t rounds = 0;             // pricing rounds
     int64_t phases = 0;             // Dijkstra phases
     int64_t candidates = 0;         // candidate pairs at the end
+    double t_collect = 0.0;         // seconds in the pair source
+    double t_build = 0.0;           // seconds adding candidates
+    double t_flow = 0.0;            // seconds in the flow phases
 };
 
 void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out);

@@ -52,7 +52,8 @@ class Result(C.Structure):
                 ("dual2_gdp", C.c_int64), ("finish_paths", C.c_int64), ("finish_rounds", C.c_int64),
                 ("trace_len", C.c_int64), ("trace", C.POINTER(C.c_int64)), ("seconds", C.c_double * 6),
                 ("scan_ms", C.c_double), ("scan_launches", C.c_int64), ("scan_rows", C.c_int32),
-                ("pad0", C.c_int32), ("scan_slices", C.c_int64), ("scan_pairs", C.c_int64)]
+                ("pad0", C.c_int32), ("scan_slices", C.c_int64), ("scan_pairs", C.c_int64),
+                ("finish_phases", C.c_int64), ("finish_candidates", C.c_int64), ("finish_seconds", C.c_double * 3)]
 
 
 _lib = None
@@ -180,6 +181,8 @@ class Context:
                 seconds=dict(zip(("setup", "warm", "gdp", "finish", "certify", "total"), list(res.seconds))),
                 scan_ms=res.scan_ms, scan_launches=res.scan_launches, scan_rows=res.scan_rows,
                 scan_slices=res.scan_slices, scan_pairs=res.scan_pairs,
+                finish_phases=res.finish_phases, finish_candidates=res.finish_candidates,
+                finish_seconds=dict(zip(("collect", "build", "flow"), list(res.finish_seconds))),
             )
             if res.trace_len:
                 out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(
