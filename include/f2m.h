@@ -66,7 +66,11 @@ typedef enum f2m_status {
     F2M_ERR_OVERFLOW = -7    /* |Lam| reached 2^38 */
 } f2m_status;
 
-enum { F2M_GRAPH_COMPLETE = 0 };
+/* F2M_GRAPH_KNN: the candidate graph of Sec. 5.3 -- every node joined to
+ * its knn_k nearest neighbours by (squared distance, index), union-
+ * symmetrised; the GDP, the finish and the certificate run on that graph,
+ * and the result is also checked against the complete graph. */
+enum { F2M_GRAPH_COMPLETE = 0, F2M_GRAPH_KNN = 1 };
 enum { F2M_WARM_COLD = 0, F2M_WARM_USER = 1 };
 enum { F2M_FINISH_NONE = 0, F2M_FINISH_EXACT = 1 };
 /* Scan over the complete graph: F2M_SCAN_CULLED skips column tiles whose
@@ -86,7 +90,8 @@ enum { F2M_STOP_TRIVIAL = 1, F2M_STOP_FIXED = 2, F2M_STOP_CYCLE = 3, F2M_STOP_CA
 typedef struct f2m_opts {
     uint32_t struct_size;         /* sizeof(f2m_opts) */
     uint32_t rule_version;        /* must be 1 */
-    int32_t graph;                /* F2M_GRAPH_COMPLETE */
+    int32_t graph;                /* F2M_GRAPH_COMPLETE or F2M_GRAPH_KNN */
+    int32_t knn_k;                /* neighbours per node for F2M_GRAPH_KNN: 10 or 16 */
     int32_t warm;                 /* F2M_WARM_COLD (Lam0 = 0) or F2M_WARM_USER */
     const int64_t *lambda2_init;  /* host, n entries, read when warm == USER */
     int64_t max_iters;            /* iteration cap (>= 0) */
@@ -106,7 +111,7 @@ typedef struct f2m_result {
     int64_t iterations;     /* GDP iterations evaluated (records) */
     int64_t kstar;          /* index of the GDP iterate the finish started from */
     int32_t stop;           /* F2M_STOP_* */
-    int32_t certified;      /* primal2 == dual2 with a feasible x (complete graph) */
+    int32_t certified;      /* primal2 == dual2 with a feasible x on the solved graph */
     int64_t *lambda2;       /* host, n: the final Lam (the certificate's duals) */
     int64_t *lambda2_gdp;   /* host, n: the GDP iterate Lam_kstar */
     int64_t n_edges;
@@ -130,11 +135,15 @@ typedef struct f2m_result {
     int64_t finish_phases;      /* Dijkstra phases of the exact finish */
     int64_t finish_candidates;  /* candidate pairs of the exact finish at the end */
     double finish_seconds[3];   /* exact finish: pair collection (GPU), candidate build, flow */
+    int64_t dual2_complete;     /* 2 L(lambda2) on the complete graph */
+    int32_t certified_complete; /* x is also optimal for the complete graph */
+    int32_t pad1;
+    int64_t graph_nnz;          /* directed entries of the candidate graph (F2M_GRAPH_KNN) */
 } f2m_result;
 
 /* Fills opts with the defaults: rule 1, complete graph, cold start,
- * max_iters 100000, handoff_div 300, exact finish, host coords, no trace,
- * auto chunk. */
+ * knn_k 10, max_iters 100000, handoff_div 300, exact finish, host coords,
+ * no trace, auto chunk, culled scan. */
 void f2m_opts_default(f2m_opts *opts);
 
 /* Creates a context on HIP device `device` with its own stream. */
@@ -178,6 +187,15 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
 f2m_status f2m_certify(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
                        const int64_t *lambda2, int64_t m, const int32_t *eu,
                        const int32_t *ev, const uint8_t *ex2, int64_t out[4]);
+
+/* The candidate graph of F2M_GRAPH_KNN as CSR over labels: row v lists
+ * every u with u among the k nearest neighbours of v or v among those of u
+ * (k nearest by squared distance, then index), columns increasing.
+ *   coords_xy device int32[2n]; k is 10 or 16; n > k.
+ *   rowptr device int32[n+1]; col device int32[cap]; *nnz (host) receives
+ *   the entry count.  F2M_ERR_CAPACITY (nnz set) when cap < nnz. */
+f2m_status f2m_knn_graph(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n, int32_t k,
+                         int32_t *rowptr, int32_t *col, int64_t cap, int64_t *nnz);
 
 void f2m_result_free(f2m_result *res);
 const char *f2m_status_str(f2m_status s);

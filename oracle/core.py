@@ -39,17 +39,21 @@ def lib():
         L.or_hash.restype = C.c_uint64; L.or_hash.argtypes = [i64, p]
         L.or_check_coords.restype = C.c_int; L.or_check_coords.argtypes = [p, i64]
         L.or_gdp_rows.restype = None
-        L.or_gdp_rows.argtypes = [i64, p, p, i64, p, p, p, p, p, p, p]
+        L.or_gdp_rows.argtypes = [i64, p, p, p, p, i64, p, p, p, p, p, p, p]
         L.or_gdp_iter.restype = C.c_int
-        L.or_gdp_iter.argtypes = [i64, p, p, p, p, p, p, p, p]
+        L.or_gdp_iter.argtypes = [i64, p, p, p, p, p, p, p, p, p, p]
         L.or_gdp_solve.restype = C.c_int
-        L.or_gdp_solve.argtypes = [i64, p, p, i64, i64, p, p, p, p, p, p, p, p]
+        L.or_gdp_solve.argtypes = [i64, p, p, p, p, i64, i64, p, p, p, p, p, p, p, p]
         L.or_certify.restype = C.c_int
-        L.or_certify.argtypes = [i64, p, p, i64, p, p, p, p]
+        L.or_certify.argtypes = [i64, p, p, p, p, i64, p, p, p, p]
+        L.or_knn.restype = C.c_int
+        L.or_knn.argtypes = [i64, p, i64, p]
+        L.or_knn_rows.restype = C.c_int
+        L.or_knn_rows.argtypes = [i64, p, i64, i64, p, p]
         L.or_trivial_x.restype = i64
         L.or_trivial_x.argtypes = [i64, p, p, i64, p, p, p]
         L.or_exact_opt2.restype = C.c_int
-        L.or_exact_opt2.argtypes = [i64, p, p, p, p]
+        L.or_exact_opt2.argtypes = [i64, p, p, p, p, p, p]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -57,6 +61,14 @@ def lib():
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _graph(graph):
+    """(rowptr int64, col int32) or (None, None) for the complete graph."""
+    if graph is None:
+        return None, None
+    rowptr, col = graph
+    return np.ascontiguousarray(rowptr, dtype=np.int64), np.ascontiguousarray(col, dtype=np.int32)
 
 
 def _coords(xy):
@@ -96,8 +108,9 @@ def check_coords(xy) -> int:
     return int(lib().or_check_coords(_ptr(xy), xy.shape[0]))
 
 
-def gdp_rows(xy, lam, rows):
-    """Per-row GDP quantities at Lam for the listed rows.
+def gdp_rows(xy, lam, rows, graph=None):
+    """Per-row GDP quantities at Lam for the listed rows (on `graph`, a
+    (rowptr, col) CSR candidate graph, or the complete graph).
     Returns dict: z4 (r,4) int64, i4 (r,4) int32, neg, zero (int32),
     rowneg, step (int64)."""
     xy = _coords(xy)
@@ -108,12 +121,13 @@ def gdp_rows(xy, lam, rows):
     out = dict(z4=np.empty((r, 4), np.int64), i4=np.empty((r, 4), np.int32),
                neg=np.empty(r, np.int32), zero=np.empty(r, np.int32),
                rowneg=np.empty(r, np.int64), step=np.empty(r, np.int64))
-    lib().or_gdp_rows(n, _ptr(xy), _ptr(lam), r, _ptr(rows), _ptr(out["z4"]), _ptr(out["i4"]),
+    rp, cl = _graph(graph)
+    lib().or_gdp_rows(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), r, _ptr(rows), _ptr(out["z4"]), _ptr(out["i4"]),
                       _ptr(out["neg"]), _ptr(out["zero"]), _ptr(out["rowneg"]), _ptr(out["step"]))
     return out
 
 
-def gdp_iter(xy, lam):
+def gdp_iter(xy, lam, graph=None):
     """One full GDP evaluation at Lam: per-node arrays plus the record
     (dict keyed by TRACE_FIELDS; 'k' is 0)."""
     xy = _coords(xy)
@@ -122,7 +136,8 @@ def gdp_iter(xy, lam):
     z4 = np.empty((n, 4), np.int64); i4 = np.empty((n, 4), np.int32)
     neg = np.empty(n, np.int32); zero = np.empty(n, np.int32); st = np.empty(n, np.int64)
     rec = np.zeros(TRACE_W, np.int64)
-    rc = lib().or_gdp_iter(n, _ptr(xy), _ptr(lam), _ptr(z4), _ptr(i4), _ptr(neg), _ptr(zero),
+    rp, cl = _graph(graph)
+    rc = lib().or_gdp_iter(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), _ptr(z4), _ptr(i4), _ptr(neg), _ptr(zero),
                            _ptr(st), _ptr(rec))
     if rc:
         raise RuntimeError("or_gdp_iter failed: %d" % rc)
@@ -131,7 +146,7 @@ def gdp_iter(xy, lam):
     return dict(z4=z4, i4=i4, neg=neg, zero=zero, step=st, rec=r)
 
 
-def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0):
+def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0, graph=None):
     """GDP rule loop (handoff_div > 0: stop once #unsatisfied*div <= n).
     Returns dict: lam (Lam*), stop (name), iters,
     kstar, trace (iters x TRACE_W int64), z4/i4/neg/zero at the last
@@ -143,7 +158,9 @@ def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0):
     iters = C.c_int64(0); stop = C.c_int32(0); kstar = C.c_int64(0)
     z4 = np.empty((n, 4), np.int64); i4 = np.empty((n, 4), np.int32)
     neg = np.empty(n, np.int32); zero = np.empty(n, np.int32)
-    rc = lib().or_gdp_solve(n, _ptr(xy), _ptr(lam), int(max_iters), int(handoff_div), _ptr(trace), C.byref(iters),
+    rp, cl = _graph(graph)
+    rc = lib().or_gdp_solve(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), int(max_iters), int(handoff_div),
+                            _ptr(trace), C.byref(iters),
                             C.byref(stop), C.byref(kstar), _ptr(z4), _ptr(i4), _ptr(neg), _ptr(zero))
     if rc:
         raise RuntimeError("or_gdp_solve failed: %d" % rc)
@@ -152,8 +169,9 @@ def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0):
                 trace=trace[:k].copy(), z4=z4, i4=i4, neg=neg, zero=zero)
 
 
-def certify(xy, lam, eu, ev, ex2):
-    """Returns dict(primal2, dual2, feasible, certified) on the complete graph."""
+def certify(xy, lam, eu, ev, ex2, graph=None):
+    """Returns dict(primal2, dual2, feasible, certified) on `graph` (the
+    complete graph by default)."""
     xy = _coords(xy)
     n = xy.shape[0]
     lam = np.ascontiguousarray(lam, dtype=np.int64)
@@ -161,7 +179,9 @@ def certify(xy, lam, eu, ev, ex2):
     ev = np.ascontiguousarray(ev, dtype=np.int32)
     ex2 = np.ascontiguousarray(ex2, dtype=np.uint8)
     out = np.zeros(4, np.int64)
-    rc = lib().or_certify(n, _ptr(xy), _ptr(lam), eu.size, _ptr(eu), _ptr(ev), _ptr(ex2), _ptr(out))
+    rp, cl = _graph(graph)
+    rc = lib().or_certify(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), eu.size, _ptr(eu), _ptr(ev), _ptr(ex2),
+                          _ptr(out))
     if rc:
         raise RuntimeError("or_certify failed: %d" % rc)
     return dict(primal2=int(out[0]), dual2=int(out[1]), feasible=bool(out[2]), certified=bool(out[3]))
@@ -180,7 +200,7 @@ def trivial_x(xy, lam, cap=None):
     return eu[:m].copy(), ev[:m].copy(), ex2[:m].copy()
 
 
-def exact_opt2(xy, want_x=False):
+def exact_opt2(xy, want_x=False, graph=None):
     """2 * F2M optimum by min-cost flow on the double cover.  With want_x,
     returns (opt2, x2, lam): the optimal x as a dense (n, n) uint8 matrix of
     x2 = 2x and an optimal Lam = 2*lambda from the flow's potentials."""
@@ -189,7 +209,8 @@ def exact_opt2(xy, want_x=False):
     out = C.c_int64(0)
     x2 = np.zeros((n, n), np.uint8) if want_x else None
     lam = np.zeros(n, np.int64) if want_x else None
-    rc = lib().or_exact_opt2(n, _ptr(xy), C.byref(out), _ptr(x2), _ptr(lam))
+    rp, cl = _graph(graph)
+    rc = lib().or_exact_opt2(n, _ptr(xy), _ptr(rp), _ptr(cl), C.byref(out), _ptr(x2), _ptr(lam))
     if rc:
         raise RuntimeError("or_exact_opt2 failed: %d" % rc)
     return (out.value, x2, lam) if want_x else out.value
@@ -199,3 +220,42 @@ def dense_to_edges(x2):
     """(n, n) symmetric x2 matrix -> edge list (u < v, x2 > 0)."""
     u, v = np.nonzero(np.triu(x2, 1))
     return u.astype(np.int32), v.astype(np.int32), x2[u, v].astype(np.uint8)
+
+
+def knn(xy, k):
+    """The k nearest neighbours of every node by (D, index): (n, k) int32."""
+    xy = _coords(xy)
+    n = xy.shape[0]
+    idx = np.empty((n, k), np.int32)
+    rc = lib().or_knn(n, _ptr(xy), int(k), _ptr(idx))
+    if rc:
+        raise RuntimeError("or_knn failed: %d" % rc)
+    return idx
+
+
+def knn_rows(xy, k, rows):
+    """The k nearest neighbours of the listed rows: (len(rows), k) int32."""
+    xy = _coords(xy)
+    n = xy.shape[0]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    idx = np.empty((rows.size, k), np.int32)
+    rc = lib().or_knn_rows(n, _ptr(xy), int(k), rows.size, _ptr(rows), _ptr(idx))
+    if rc:
+        raise RuntimeError("or_knn_rows failed: %d" % rc)
+    return idx
+
+
+def knn_graph(xy, k):
+    """Union-symmetrised k-nearest-neighbour graph as CSR (rowptr int64,
+    col int32), each row's columns increasing."""
+    idx = knn(xy, k)
+    n = idx.shape[0]
+    a = np.repeat(np.arange(n), k)
+    b = idx.ravel().astype(np.int64)
+    u = np.concatenate([a, b])
+    v = np.concatenate([b, a])
+    key = np.unique(u * n + v)
+    rows, cols = key // n, key % n
+    rowptr = np.zeros(n + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    return np.cumsum(rowptr), cols.astype(np.int32)

@@ -33,13 +33,24 @@ def edges_of(n):
     return [(u, v) for u in range(n) for v in range(u + 1, n)]
 
 
-def brute_force_opt2(xy):
+def graph_edges(graph, n):
+    """Edge list (u < v) of a CSR graph (rowptr, col); all pairs if None."""
+    if graph is None:
+        return edges_of(n)
+    rowptr, col = graph
+    return [(u, int(v)) for u in range(n) for v in col[rowptr[u]:rowptr[u + 1]] if u < v]
+
+
+def brute_force_opt2(xy, graph=None):
     """2 * min c.x over x in {0,1/2,1}^E with every degree 2; None if none."""
     n = len(xy)
-    E = edges_of(n)
+    E = graph_edges(graph, n)
     c = [euc2d(xy, u, v) for (u, v) in E]
     deg = [0] * n              # doubled degrees so far
-    left = [n - 1] * n         # undecided incident edges per node
+    left = [0] * n             # undecided incident edges per node
+    for (u, v) in E:
+        left[u] += 1
+        left[v] += 1
     best = [None]
     # order edges so each node's edges close early: already lexicographic
 
@@ -175,13 +186,13 @@ def simplex_opt2(xy, max_pivots=200000):
     return int(2 * val)
 
 
-def highs_opt2(xy):
+def highs_opt2(xy, graph=None):
     """2 * optimum from scipy's HiGHS LP solver (a library cross-check;
     the optimum is a half-integer, recovered by rounding 2*fun)."""
     from scipy.optimize import linprog
     from scipy.sparse import coo_matrix
     n = len(xy)
-    E = edges_of(n)
+    E = graph_edges(graph, n)
     c = np.array([euc2d(xy, u, v) for (u, v) in E], dtype=float)
     m = len(E)
     rows = np.array([u for u, v in E] + [v for u, v in E])

@@ -30,6 +30,12 @@
  * units  dual2 = 2*L = 2*sum Lam + sum_{u<v} min(0, Z_uv).  For any feasible
  * x, c.x >= L (weak duality); equality certifies optimality.
  *
+ * Candidate graphs (Sec. 5.3: "the top N closest neighbors for each node"):
+ * every routine takes an optional CSR graph (rowptr[n+1], col[]), symmetric,
+ * no self loops; NULL means the complete graph.  On a graph, a row's
+ * statistics run over its neighbours only, the dual bound sums over its
+ * edges and the exact optimum uses its edges only.
+ *
  * The exact optimum (used to pin the GDP and the finisher) comes from the
  * bipartite double cover: left copy v', right copy v'', arc v'->u'' of cost
  * c_uv and capacity 1 for every ordered pair; every copy has degree 2.
@@ -134,8 +140,8 @@ int64_t or_step(int64_t s)
  * smallest (Z, u) in order, count Z < 0 and Z == 0, sum min(0, Z), and form
  * the step.  Outputs are indexed by position in `rows`.  z4/i4 hold four
  * entries per row (unused slots: Z = INT64_MAX, u = -1).  Requires n >= 2. */
-void or_gdp_rows(int64_t n, const int32_t *xy, const int64_t *lam,
-                 int64_t nrows, const int64_t *rows,
+void or_gdp_rows(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
+                 const int64_t *lam, int64_t nrows, const int64_t *rows,
                  int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
                  int64_t *rowneg, int64_t *step)
 {
@@ -145,7 +151,9 @@ void or_gdp_rows(int64_t n, const int32_t *xy, const int64_t *lam,
         int64_t bz[4] = {INT64_MAX, INT64_MAX, INT64_MAX, INT64_MAX};
         int64_t bu[4] = {-1, -1, -1, -1};
         int64_t cn = 0, cz = 0, rn = 0;
-        for (int64_t u = 0; u < n; u++) {
+        const int64_t m = rowptr ? rowptr[v + 1] - rowptr[v] : n;
+        for (int64_t e = 0; e < m; e++) {
+            const int64_t u = rowptr ? col[rowptr[v] + e] : e;
             if (u == v) continue;
             int64_t z = 2 * or_cost(xy, u, v) - lam[u] - lam[v];     /* eq. 9, doubled */
             if (z < 0) { cn++; rn += z; }
@@ -164,8 +172,8 @@ void or_gdp_rows(int64_t n, const int32_t *xy, const int64_t *lam,
         zero[r] = (int32_t)cz;
         rowneg[r] = rn;
         /* eq. 10: second and third shortest adjusted edges (positions 1, 2 of
-         * the sorted list, counting from 0).  n == 3 has no third edge. */
-        step[r] = (n >= 4) ? or_step(bz[1] + bz[2]) : 0;
+         * the sorted list, counting from 0).  A row needs a third edge. */
+        step[r] = (bu[2] >= 0) ? or_step(bz[1] + bz[2]) : 0;
     }
 }
 
@@ -193,15 +201,15 @@ uint64_t or_hash(int64_t n, const int64_t *lam)
 
 /* Full GDP iteration at Lam: all rows, then the global statistics.
  * Outputs per node: z4, i4, neg, zero, step (n rows); rec[OR_TRACE_W]. */
-int or_gdp_iter(int64_t n, const int32_t *xy, const int64_t *lam,
-                int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
+int or_gdp_iter(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
+                const int64_t *lam, int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
                 int64_t *step, int64_t *rec)
 {
     int64_t *rows = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int64_t *rowneg = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     if (!rows || !rowneg) { free(rows); free(rowneg); return OR_ERR_NOMEM; }
     for (int64_t v = 0; v < n; v++) rows[v] = v;
-    or_gdp_rows(n, xy, lam, n, rows, z4, i4, neg, zero, rowneg, step);
+    or_gdp_rows(n, xy, rowptr, col, lam, n, rows, z4, i4, neg, zero, rowneg, step);
     int64_t sl = 0, sneg = 0, unsat = 0, bad = 0, mx = 0, nz = 0;
     for (int64_t v = 0; v < n; v++) {
         sl += lam[v];
@@ -229,8 +237,8 @@ int or_gdp_iter(int64_t n, const int32_t *xy, const int64_t *lam,
  *   trace: max_iters+1 rows of OR_TRACE_W (may be NULL); *iters = number of
  *   iterations evaluated (records written); *stop = reason; *kstar = index
  *   of Lam*.  z4/i4/neg/zero describe Lam_k of the last evaluated k. */
-int or_gdp_solve(int64_t n, const int32_t *xy, int64_t *lam, int64_t max_iters,
-                 int64_t handoff_div,
+int or_gdp_solve(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
+                 int64_t *lam, int64_t max_iters, int64_t handoff_div,
                  int64_t *trace, int64_t *iters, int32_t *stop, int64_t *kstar,
                  int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero)
 {
@@ -246,7 +254,7 @@ int or_gdp_solve(int64_t n, const int32_t *xy, int64_t *lam, int64_t max_iters,
     int64_t k = 0;
     int32_t why = 0;
     for (;; k++) {
-        rc = or_gdp_iter(n, xy, lam, z4, i4, neg, zero, step, rec);
+        rc = or_gdp_iter(n, xy, rowptr, col, lam, z4, i4, neg, zero, step, rec);
         if (rc) break;
         rec[0] = k;
         if (trace) memcpy(trace + OR_TRACE_W * k, rec, sizeof(rec));
@@ -293,7 +301,8 @@ static int cmp_pair(const void *a, const void *b)
  *   out[2] feasible: endpoints valid, u != v, x2 in {1,2}, no repeated
  *          pair, every node's sum of x2 equal to 4 (degree 2)
  *   out[3] certified = feasible && primal2 == dual2 */
-int or_certify(int64_t n, const int32_t *xy, const int64_t *lam, int64_t m,
+int or_certify(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
+               const int64_t *lam, int64_t m,
                const int32_t *eu, const int32_t *ev, const uint8_t *ex2,
                int64_t *out)
 {
@@ -310,6 +319,11 @@ int or_certify(int64_t n, const int32_t *xy, const int64_t *lam, int64_t m,
         if (u < 0 || v < 0 || u >= n || v >= n || u == v || (ex2[e] != 1 && ex2[e] != 2)) {
             feas = 0; keys[e] = -1 - e; continue;
         }
+        if (rowptr) {
+            int found = 0;
+            for (int64_t q = rowptr[u]; q < rowptr[u + 1]; q++) if (col[q] == v) found = 1;
+            if (!found) feas = 0;
+        }
         primal += or_cost(xy, u, v) * ex2[e];
         deg[u] += ex2[e]; deg[v] += ex2[e];
         int64_t a = u < v ? u : v, b = u < v ? v : u;
@@ -321,11 +335,15 @@ int or_certify(int64_t n, const int32_t *xy, const int64_t *lam, int64_t m,
     int64_t sl = 0, sneg = 0;
     for (int64_t v = 0; v < n; v++) sl += lam[v];
 #pragma omp parallel for reduction(+ : sneg) schedule(dynamic, 16)
-    for (int64_t v = 0; v < n; v++)
-        for (int64_t u = v + 1; u < n; u++) {
+    for (int64_t v = 0; v < n; v++) {
+        const int64_t deg = rowptr ? rowptr[v + 1] - rowptr[v] : n;
+        for (int64_t e = 0; e < deg; e++) {
+            const int64_t u = rowptr ? col[rowptr[v] + e] : e;
+            if (u <= v) continue;
             int64_t z = 2 * or_cost(xy, u, v) - lam[u] - lam[v];
             if (z < 0) sneg += z;
         }
+    }
     out[0] = primal;
     out[1] = 2 * sl + sneg;
     out[2] = feas;
@@ -364,7 +382,8 @@ int64_t or_trivial_x(int64_t n, const int32_t *xy, const int64_t *lam, int64_t c
  * alpha_v = -pot(v'), beta_v = pot(v'') optimal duals of the double cover,
  * lambda = (alpha + beta)/2 is optimal for F2M by the symmetry of the cover,
  * so Lam_v = pot(v'') - pot(v').  x2 and lam may be NULL. */
-int or_exact_opt2(int64_t n, const int32_t *xy, int64_t *opt2, uint8_t *x2, int64_t *lam)
+int or_exact_opt2(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
+                  int64_t *opt2, uint8_t *x2, int64_t *lam)
 {
     if (n < 3 || !xy || !opt2) return OR_ERR_ARG;
     int rc = or_check_coords(xy, n);
@@ -383,13 +402,16 @@ int or_exact_opt2(int64_t n, const int32_t *xy, int64_t *opt2, uint8_t *x2, int6
     }
     const int64_t INF = INT64_MAX / 4;
     for (int64_t v = 0; v < n; v++)
-        for (int64_t u = 0; u < n; u++) c[v * n + u] = (u == v) ? INF : or_cost(xy, u, v);
+        for (int64_t u = 0; u < n; u++) c[v * n + u] = (u == v || rowptr) ? INF : or_cost(xy, u, v);
+    if (rowptr)
+        for (int64_t v = 0; v < n; v++)
+            for (int64_t q = rowptr[v]; q < rowptr[v + 1]; q++) c[v * n + col[q]] = or_cost(xy, col[q], v);
     /* potentials: pot(v') = 0, pot(u'') = min_v c_vu, so every reduced cost
      * c_vu + pot(v') - pot(u'') is >= 0 */
     for (int64_t u = 0; u < n; u++) {
         int64_t mn = INF;
         for (int64_t v = 0; v < n; v++) if (c[v * n + u] < mn) mn = c[v * n + u];
-        pot[n + u] = mn;
+        pot[n + u] = mn < INF ? mn : 0;
     }
     for (int64_t v = 0; v < n; v++) { exl[v] = 2; dfr[v] = 2; }
     int64_t total = 0;
@@ -406,7 +428,7 @@ int or_exact_opt2(int64_t n, const int32_t *xy, int64_t *opt2, uint8_t *x2, int6
             if (a >= n && dfr[a - n] > 0) { target = a; break; }
             if (a < n) {                      /* forward arcs a' -> u'' with y = 0 */
                 for (int64_t u = 0; u < n; u++) {
-                    if (u == a || y[a * n + u]) continue;
+                    if (u == a || y[a * n + u] || c[a * n + u] >= INF) continue;
                     int64_t rcst = c[a * n + u] + pot[a] - pot[n + u];
                     int64_t d = dist[a] + rcst;
                     if (d < dist[n + u]) { dist[n + u] = d; prev[n + u] = a; }
@@ -438,6 +460,7 @@ int or_exact_opt2(int64_t n, const int32_t *xy, int64_t *opt2, uint8_t *x2, int6
     }
     for (int64_t v = 0; v < n; v++)
         for (int64_t u = 0; u < n; u++) if (y[v * n + u]) total += c[v * n + u];
+    (void)0;
     *opt2 = total;   /* = 2 * F2M optimum (sum over both copies) */
     if (lam)
         for (int64_t v = 0; v < n; v++) lam[v] = pot[n + v] - pot[v];
@@ -447,6 +470,42 @@ int or_exact_opt2(int64_t n, const int32_t *xy, int64_t *opt2, uint8_t *x2, int6
                 x2[v * n + u] = (u == v) ? 0 : (uint8_t)(y[v * n + u] + y[u * n + v]);
 out:
     free(c); free(y); free(pot); free(dist); free(prev); free(done); free(exl); free(dfr);
+    return rc;
+}
+
+/* k nearest neighbours of every node: the k smallest (D_uv, u), u != v,
+ * in that order.  idx[k*v + j]. */
+int or_knn_rows(int64_t n, const int32_t *xy, int64_t k, int64_t nrows, const int64_t *rows, int32_t *idx)
+{
+    if (n < 2 || k < 1 || k > n - 1 || k > 64 || !xy || !idx || !rows) return OR_ERR_ARG;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; r++) {
+        const int64_t v = rows[r];
+        int64_t bd[64], bu[64];
+        for (int64_t j = 0; j < k; j++) { bd[j] = INT64_MAX; bu[j] = -1; }
+        for (int64_t u = 0; u < n; u++) {
+            if (u == v) continue;
+            int64_t d = sq_dist(xy, u, v);
+            if (!(d < bd[k - 1] || (d == bd[k - 1] && u < bu[k - 1])) && bu[k - 1] >= 0) continue;
+            int64_t j = k - 1;
+            while (j > 0 && (bu[j - 1] < 0 || d < bd[j - 1] || (d == bd[j - 1] && u < bu[j - 1]))) {
+                bd[j] = bd[j - 1]; bu[j] = bu[j - 1]; j--;
+            }
+            bd[j] = d; bu[j] = u;
+        }
+        for (int64_t j = 0; j < k; j++) idx[k * r + j] = (int32_t)bu[j];
+    }
+    return OR_OK;
+}
+
+int or_knn(int64_t n, const int32_t *xy, int64_t k, int32_t *idx)
+{
+    if (n < 2 || !idx) return OR_ERR_ARG;
+    int64_t *rows = malloc(sizeof(int64_t) * (size_t)n);
+    if (!rows) return OR_ERR_NOMEM;
+    for (int64_t v = 0; v < n; v++) rows[v] = v;
+    int rc = or_knn_rows(n, xy, k, n, rows, idx);
+    free(rows);
     return rc;
 }
 

@@ -39,6 +39,8 @@ struct f2m_ctx {
     // certificate / pair collection state
     DevBuf c_col, c_lam, c_tile_hmax, c_ctrl, c_deg, c_cnt, c_nb, c_acc, c_lam_label, c_eu, c_ev, c_ex;
     DevBuf p_pairs, p_count;
+    // candidate graph
+    DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
     Ctrl *ctrl_host = nullptr;   // pinned
     int64_t *scratch_host = nullptr;   // pinned, 16 entries
 
@@ -48,7 +50,8 @@ struct f2m_ctx {
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
                          &prowneg, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
-                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count};
+                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &knn_nbr, &csr_keys,
+                         &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz};
         bufs.assign(std::begin(all), std::end(all));
     }
 };
@@ -305,6 +308,113 @@ private:
     int64_t cap_ = 0;
 };
 
+// The candidate graph (k nearest neighbours, union-symmetrised) as CSR
+// over positions.
+Csr build_graph(f2m_ctx *ctx, const GeoHost &gh, int K, hipStream_t st)
+{
+    const int64_t n = gh.g.n;
+    if (K != 10 && K != 16) fail(ctx, F2M_ERR_ARG, "knn_k must be 10 or 16");
+    if (n < K + 1) fail(ctx, F2M_ERR_ARG, "the candidate graph needs n > knn_k");
+    const int64_t nk = n * K;
+    int32_t *nbr = grow<int32_t>(ctx, ctx->knn_nbr, nk);
+    uint64_t *keys = grow<uint64_t>(ctx, ctx->csr_keys, nk);
+    uint64_t *keys2 = grow<uint64_t>(ctx, ctx->csr_keys2, nk);
+    int32_t *deg = grow<int32_t>(ctx, ctx->csr_deg, n + 1);
+    int32_t *rowptr = grow<int32_t>(ctx, ctx->csr_rowptr, n + 1);
+    int32_t *col = grow<int32_t>(ctx, ctx->csr_col, 2 * nk);
+    int32_t *cost = grow<int32_t>(ctx, ctx->csr_cost, 2 * nk);
+    int64_t *nnz_dev = grow<int64_t>(ctx, ctx->csr_nnz, 1);
+    const size_t tb = csr_temp_bytes(n, K);
+    void *temp = grow<char>(ctx, ctx->csr_temp, tb);
+    ck(ctx, hipMemsetAsync(nnz_dev, 0, sizeof(int64_t), st), "memset");
+    ck(ctx, launch_knn(gh.g, static_cast<const float4 *>(ctx->col.p), K, nbr, nullptr, st), "knn");
+    ck(ctx, launch_build_csr(gh.g, gh.xy, n, K, nbr, keys, keys2, deg, rowptr, col, cost, nnz_dev, temp, tb, 2 * nk,
+                             st), "csr");
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, nnz_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    return Csr{rowptr, col, cost, ctx->scratch_host[0]};
+}
+
+// Certificate of (lam, edges) restricted to the candidate graph.
+void certify_graph_dev(f2m_ctx *ctx, const GeoHost &gh, const Csr &csr, const int64_t *lam_label, int64_t m,
+                       const int32_t *eu, const int32_t *ev, const uint8_t *ex, hipStream_t st, int64_t out[4])
+{
+    const int64_t n = gh.g.n;
+    LamView lv = place_lam(ctx, gh, lam_label, st);
+    int32_t *deg = grow<int32_t>(ctx, ctx->c_deg, n);
+    int32_t *cnt = grow<int32_t>(ctx, ctx->c_cnt, n);
+    int32_t *nb = grow<int32_t>(ctx, ctx->c_nb, kTop * n);
+    unsigned long long *acc = grow<unsigned long long>(ctx, ctx->c_acc, 4);
+    ck(ctx, hipMemsetAsync(deg, 0, n * sizeof(int32_t), st), "memset");
+    ck(ctx, hipMemsetAsync(cnt, 0, n * sizeof(int32_t), st), "memset");
+    ck(ctx, hipMemsetAsync(acc, 0, 4 * sizeof(unsigned long long), st), "memset");
+    ck(ctx, launch_graph_dual(gh.g, csr, lv.lam, acc, st), "graph_dual");
+    ck(ctx, launch_cert_edges(gh.xy, n, m, eu, ev, ex, deg, cnt, nb, acc, st), "cert_edges");
+    ck(ctx, launch_graph_membership(gh.g, csr, m, eu, ev, acc, st), "membership");
+    ck(ctx, launch_cert_nodes(lam_label, n, deg, cnt, nb, acc, st), "cert_nodes");
+    unsigned long long h[4];
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, acc, sizeof(h), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    std::memcpy(h, ctx->scratch_host, sizeof(h));
+    const int64_t rowneg = (int64_t)h[0], primal2 = (int64_t)h[1], viol = (int64_t)h[2], sl = (int64_t)h[3];
+    out[0] = primal2;
+    out[1] = 2 * sl + rowneg / 2;
+    out[2] = viol == 0 ? 1 : 0;
+    out[3] = (viol == 0 && out[0] == out[1]) ? 1 : 0;
+}
+
+// Candidate pairs for the exact finish on the candidate graph.
+class GpuGraphPairs : public PairSource {
+public:
+    GpuGraphPairs(f2m_ctx *ctx, const GeoHost &gh, const Csr &csr, hipStream_t st)
+        : ctx_(ctx), gh_(gh), csr_(csr), st_(st)
+    {
+    }
+    bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) override
+    {
+        return run(lam, slack < 0 ? 0 : slack, out, err);
+    }
+    bool negative(const int64_t *lam, PairList &out, std::string &err) override { return run(lam, -1, out, err); }
+
+private:
+    bool run(const int64_t *lam_host, int64_t slack, PairList &out, std::string &err)
+    {
+        try {
+            f2m_ctx *ctx = ctx_;
+            const int64_t n = gh_.g.n;
+            int64_t *lam = grow<int64_t>(ctx, ctx->c_lam_label, n);
+            unsigned long long *cnt = grow<unsigned long long>(ctx, ctx->p_count, 1);
+            ck(ctx, hipMemcpyAsync(lam, lam_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st_), "copy");
+            LamView lv = place_lam(ctx, gh_, lam, st_);
+            const int64_t cap = csr_.nnz + 1;
+            int2 *pairs = grow<int2>(ctx, ctx->p_pairs, cap);
+            ck(ctx, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st_), "memset");
+            ck(ctx, launch_graph_collect(gh_.g, csr_, lv.lam, slack, cnt, pairs, cap, st_), "graph_collect");
+            ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st_), "copy");
+            ck(ctx, hipStreamSynchronize(st_), "sync");
+            const int64_t found = std::min<int64_t>(ctx->scratch_host[0], cap);
+            std::vector<int2> h(found);
+            if (found)
+                ck(ctx, hipMemcpyAsync(h.data(), pairs, found * sizeof(int2), hipMemcpyDeviceToHost, st_), "copy");
+            ck(ctx, hipStreamSynchronize(st_), "sync");
+            out.clear();
+            out.reserve(found);
+            for (const int2 &p : h) out.emplace_back(p.x, p.y);
+            std::sort(out.begin(), out.end());
+            out.erase(std::unique(out.begin(), out.end()), out.end());
+            return true;
+        } catch (const Fail &) {
+            err = ctx_->err;
+            return false;
+        }
+    }
+
+    f2m_ctx *ctx_;
+    GeoHost gh_;
+    Csr csr_;
+    hipStream_t st_;
+};
+
 struct LoopOut {
     Ctrl c;
     double scan_ms = 0.0;
@@ -317,11 +427,12 @@ struct LoopOut {
 // (null: zero).
 LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev, int64_t max_iters,
                  int64_t handoff_div, int32_t chunk_opt, bool want_trace, bool time_kernels, bool cull,
-                 hipStream_t st)
+                 const Csr *csr, hipStream_t st)
 {
     LoopOut o;
     const int64_t n = gh.g.n;
-    const ScanShape sh = scan_shape(n, cull);
+    // on the candidate graph the step is one fused kernel and needs no partials
+    const ScanShape sh = csr ? ScanShape{1, 1, ((n + kTileCols - 1) / kTileCols) * kTileCols} : scan_shape(n, cull);
     float4 *col = static_cast<float4 *>(ctx->col.p);
     int64_t *lam[2] = {grow<int64_t>(ctx, ctx->lam[0], n), grow<int64_t>(ctx, ctx->lam[1], n)};
     int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
@@ -364,6 +475,14 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     for (;;) {
         int issued = 0;
         for (int j = 0; j < chunk && k <= max_iters; ++j, ++k, ++issued) {
+            if (csr) {
+                GraphStepArgs ga{gh.g, *csr, k, lam[k & 1], lam[(k + 1) & 1], best, z4, i4, nullptr, nullptr,
+                                 nullptr, cd, trace};
+                if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
+                ck(ctx, launch_graph_step(ga, st), "graph_step");
+                if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
+                continue;
+            }
             ScanArgs sa{};
             sa.g = gh.g;
             sa.lv = LamView{col, lam[k & 1], thm, cd};
@@ -446,6 +565,7 @@ void f2m_opts_default(f2m_opts *o)
     o->warm = F2M_WARM_COLD;
     o->max_iters = 100000;
     o->handoff_div = 300;
+    o->knn_k = 10;
     o->finish = F2M_FINISH_EXACT;
 }
 
@@ -574,6 +694,30 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
     }
 }
 
+f2m_status f2m_knn_graph(f2m_ctx *ctx, const int32_t *xy, int64_t n, int32_t k, int32_t *rowptr, int32_t *col,
+                         int64_t cap, int64_t *nnz)
+{
+    if (!ctx) return F2M_ERR_ARG;
+    try {
+        if (!xy || !rowptr || !col || !nnz || cap < 0) fail(ctx, F2M_ERR_ARG, "knn_graph needs coords and outputs");
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        hipStream_t st = ctx->stream;
+        const GeoHost gh = setup_geo(ctx, xy, n, st);
+        const Csr csr = build_graph(ctx, gh, k, st);
+        *nnz = csr.nnz;
+        if (cap < csr.nnz) fail(ctx, F2M_ERR_CAPACITY, "col capacity below the entry count");
+        int32_t *deg = grow<int32_t>(ctx, ctx->c_deg, n + 1);
+        ck(ctx, launch_csr_to_labels(gh.g, csr, rowptr, col, deg, st), "csr_to_labels");
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        return F2M_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
 f2m_status f2m_certify(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam, int64_t m,
                        const int32_t *eu, const int32_t *ev, const uint8_t *ex2, int64_t out[4])
 {
@@ -607,7 +751,8 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         }
         if (!coords || !out) fail(ctx, F2M_ERR_ARG, "null coords or result");
         if (o.rule_version != 1) fail(ctx, F2M_ERR_ARG, "only rule_version 1 exists");
-        if (o.graph != F2M_GRAPH_COMPLETE) fail(ctx, F2M_ERR_ARG, "unknown graph kind");
+        if (o.graph != F2M_GRAPH_COMPLETE && o.graph != F2M_GRAPH_KNN) fail(ctx, F2M_ERR_ARG, "unknown graph kind");
+        const bool on_graph = o.graph == F2M_GRAPH_KNN;
         if (o.max_iters < 0) fail(ctx, F2M_ERR_ARG, "max_iters < 0");
         if (o.handoff_div < 0) fail(ctx, F2M_ERR_ARG, "handoff_div < 0");
         if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
@@ -653,9 +798,14 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             ck(ctx, hipMemcpyAsync(d, o.lambda2_init, n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
             lam0_dev = d;
         }
+        Csr csr{};
+        if (on_graph) {
+            csr = build_graph(ctx, gh, o.knn_k, st);
+            res.graph_nnz = csr.nnz;
+        }
         const double t1 = now_s();
         LoopOut lo = gdp_loop(ctx, gh, lam0_dev, o.max_iters, o.handoff_div, o.chunk, o.record_trace != 0,
-                              o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, st);
+                              o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, on_graph ? &csr : nullptr, st);
         const double t2 = now_s();
         res.n = n;
         res.iterations = lo.c.k_last + 1;
@@ -699,8 +849,13 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             have_x = true;
         } else if (o.finish == F2M_FINISH_EXACT) {
             FinishResult fr;
-            GpuPairs src(ctx, gh, (const int32_t *)ctx->seed.p, st);
-            finish_exact(xy_host.data(), n, res.lambda2_gdp, src, &fr);
+            if (on_graph) {
+                GpuGraphPairs src(ctx, gh, csr, st);
+                finish_exact(xy_host.data(), n, res.lambda2_gdp, src, &fr);
+            } else {
+                GpuPairs src(ctx, gh, (const int32_t *)ctx->seed.p, st);
+                finish_exact(xy_host.data(), n, res.lambda2_gdp, src, &fr);
+            }
             res.finish_paths = fr.paths;
             res.finish_rounds = fr.rounds;
             res.finish_phases = fr.phases;
@@ -728,8 +883,16 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             have_x = true;
         }
         const double t4 = now_s();
-        int64_t cert[4] = {0, 0, 0, 0};
-        if (have_x) certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert);
+        int64_t cert[4] = {0, 0, 0, 0}, cert_full[4] = {0, 0, 0, 0};
+        if (have_x) {
+            if (on_graph) {
+                certify_graph_dev(ctx, gh, csr, lam_final_dev, m, eu, ev, ex, st, cert);
+                certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert_full);
+            } else {
+                certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert);
+                std::memcpy(cert_full, cert, sizeof(cert));
+            }
+        }
         const double t5 = now_s();
         res.n_edges = m;
         res.edge_u = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
@@ -746,6 +909,8 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         res.primal2 = cert[0];
         res.dual2 = have_x ? cert[1] : res.dual2_gdp;
         res.certified = (int32_t)cert[3];
+        res.dual2_complete = have_x ? cert_full[1] : 0;
+        res.certified_complete = (int32_t)cert_full[3];
         res.scan_pairs = (int64_t)lo.c.pairs_tested;
         res.scan_ms = lo.scan_ms;
         res.scan_launches = lo.scan_launches;

@@ -123,7 +123,52 @@ struct UpdateArgs {
     int64_t *trace;             // [trace_cap][8] or null
 };
 
+// Candidate graph (k nearest neighbours, union-symmetrised) in CSR over
+// positions: rowptr[n+1], col (positions, increasing within a row), cost.
+struct Csr {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const int32_t *cost;
+    int64_t nnz;
+};
+
+struct GraphStepArgs {
+    Geo g;
+    Csr csr;
+    int64_t k;
+    const int64_t *lam_in;      // sorted
+    int64_t *lam_out;           // sorted; holds Lam_{k-1} on entry
+    int64_t *lam_best;
+    int64_t *z4;                // [4n] by label
+    int32_t *i4;                // [4n] by label
+    int32_t *neg, *zero;        // by label, or null
+    int64_t *step;              // by label, or null
+    Ctrl *ctrl;
+    int64_t *trace;
+};
+
 // Launchers (f2m_kernels.hip).  All run on `st`; none synchronises.
+// k nearest neighbours (K in {10, 16}) by (D, label): nbr[p*K + j] positions
+hipError_t launch_knn(const Geo &g, const float4 *col, int K, int32_t *nbr, int64_t *nbr_d, hipStream_t st);
+// CSR of the union-symmetrised graph; returns nnz through nnz_dev
+size_t csr_temp_bytes(int64_t n, int K);
+hipError_t launch_build_csr(const Geo &g, const int32_t *xy, int64_t n, int K, const int32_t *nbr, uint64_t *keys,
+                            uint64_t *keys_alt, int32_t *deg, int32_t *rowptr, int32_t *col, int32_t *cost,
+                            int64_t *nnz_dev, void *temp, size_t temp_bytes, int64_t cap, hipStream_t st);
+hipError_t launch_graph_step(const GraphStepArgs &a, hipStream_t st);
+// graph certificate dual side: acc[0] += sum over CSR entries of min(0, Z)
+hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_sorted, unsigned long long *acc,
+                             hipStream_t st);
+// pairs (labels, lo < hi) of CSR edges with Z <= theta_row (theta_row =
+// max(0, 4th smallest Z of the row) + slack when slack >= 0, else -1)
+hipError_t launch_graph_collect(const Geo &g, const Csr &csr, const int64_t *lam_sorted, int64_t slack,
+                                unsigned long long *count, int2 *out, int64_t cap, hipStream_t st);
+// labels: edges of x must be edges of the graph; acc[2] += violations
+hipError_t launch_graph_membership(const Geo &g, const Csr &csr, int64_t m, const int32_t *eu, const int32_t *ev,
+                                   unsigned long long *acc, hipStream_t st);
+// CSR in label space (rows by label, columns labels increasing)
+hipError_t launch_csr_to_labels(const Geo &g, const Csr &csr, int32_t *rowptr_l, int32_t *col_l, int32_t *deg_tmp,
+                                hipStream_t st);
 hipError_t launch_minmax(const int32_t *xy, int64_t n, int32_t *out4, hipStream_t st);
 // Morton order: fills orig (position -> label) and pos (label -> position).
 size_t sort_temp_bytes(int64_t n);

@@ -386,79 +386,81 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// update: merge slices, step Lam, reduce, stop test
+// per-node step, iteration record and stop test (shared by the complete-graph
+// update and the candidate-graph step)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
-{
-    Ctrl *ctrl = a.ctrl;
-    if (ctrl->done) return;
-    __shared__ unsigned long long red[kBlock / 64];
-    __shared__ float redf[kBlock / 64];
-    __shared__ int s_last;
-    const int64_t n = a.g.n;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    // Lam_{k-1} sits in lam_out until it is overwritten below
-    const bool copy_best = a.k > 0 && ctrl->best_k == a.k - 1;
-
+struct RowOut {
     unsigned long long sumlam = 0, rowneg = 0, unsat = 0, bad = 0, nonzero = 0, hsh = 0;
     long long maxstep = 0, maxabs = 0;
     float hmax = -INFINITY;
-    if (p < n) {
-        const int64_t v = a.g.orig[p];
-        Top4 top;
-        top.clear();
-        int64_t cn = 0, cz = 0, rn = 0;
-        for (int64_t sl = 0; sl < a.nslices; ++sl) {
-#pragma unroll
-            for (int j = 0; j < kTop; ++j)
-                top.insert(a.pz[(sl * kTop + j) * n + p], a.pi[(sl * kTop + j) * n + p]);
-            cn += a.pneg[sl * n + p];
-            cz += a.pzero[sl * n + p];
-            rn += a.prowneg[sl * n + p];
-        }
-        const int64_t lamv = a.lam_in[p];
-        const int64_t st = gdp_step(top.z[1] + top.z[2]);   // eq. 10: 2nd and 3rd shortest
-        const int64_t nxt = lamv + st;
-        if (copy_best) a.lam_best[p] = a.lam_out[p];
-        a.lam_out[p] = nxt;
-        float4 cv = a.col[p];
+};
+
+// Step of the row at position p from its merged statistics: eq. 10 on the
+// 2nd and 3rd smallest Z; writes Lam_{k+1} and the per-node outputs.
+__device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &top, int64_t cn, int64_t cz,
+                                         int64_t rn, int64_t lamv, bool copy_best, int64_t *lam_out,
+                                         int64_t *lam_best, int64_t *z4, int32_t *i4, int32_t *seed,
+                                         int32_t *neg, int32_t *zero, int64_t *step, float4 *col, RowOut &o)
+{
+    const int64_t n = g.n;
+    const int64_t v = g.orig[p];
+    // a row needs a third edge (n >= 4 on the complete graph)
+    const int64_t st = top.id[2] != kNoIdx ? gdp_step(top.z[1] + top.z[2]) : 0;
+    const int64_t nxt = lamv + st;
+    if (copy_best) lam_best[p] = lam_out[p];
+    lam_out[p] = nxt;
+    if (col) {
+        float4 cv = col[p];
         const float h = (float)(0.5 * (double)nxt);
         cv.z = h;
         cv.w = fmaf(cv.x, cv.x, fmaf(cv.y, cv.y, -h * h));
-        a.col[p] = cv;
-        hmax = h;
-#pragma unroll
-        for (int j = 0; j < kTop; ++j) {
-            const bool ok = top.id[j] != kNoIdx;
-            a.z4[kTop * v + j] = top.z[j];
-            a.i4[kTop * v + j] = ok ? top.id[j] : -1;
-            a.seed[j * n + p] = ok ? a.g.pos[top.id[j]] : -1;
-        }
-        const int64_t deg2 = 2 * cn + cz;
-        if (a.neg) a.neg[v] = (int32_t)cn;
-        if (a.zero) a.zero[v] = (int32_t)cz;
-        if (a.step) a.step[v] = st;
-        sumlam = (unsigned long long)lamv;
-        rowneg = (unsigned long long)rn;
-        unsat = (top.z[1] > 0 || top.z[2] < 0) ? 1 : 0;
-        bad = deg2 != 4 ? 1 : 0;
-        nonzero = st != 0 ? 1 : 0;
-        maxstep = st < 0 ? -st : st;
-        maxabs = nxt < 0 ? -nxt : nxt;
-        hsh = mix64((uint64_t)lamv ^ (0x9E3779B97F4A7C15ULL * (uint64_t)(v + 1)));
+        col[p] = cv;
+        o.hmax = h;
     }
-    // a block of kBlock positions is one column tile
-    hmax = block_reduce<float, true>(hmax, redf);
-    if (threadIdx.x == 0) a.tile_hmax[blockIdx.x] = hmax;
-    sumlam = block_reduce<unsigned long long, false>(sumlam, red);
-    rowneg = block_reduce<unsigned long long, false>(rowneg, red);
-    unsat = block_reduce<unsigned long long, false>(unsat, red);
-    bad = block_reduce<unsigned long long, false>(bad, red);
-    nonzero = block_reduce<unsigned long long, false>(nonzero, red);
-    hsh = block_reduce<unsigned long long, false>(hsh, red);
-    maxstep = (long long)block_reduce<unsigned long long, true>((unsigned long long)maxstep, red);
-    maxabs = (long long)block_reduce<unsigned long long, true>((unsigned long long)maxabs, red);
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) {
+        const bool ok = top.id[j] != kNoIdx;
+        z4[kTop * v + j] = top.z[j];
+        i4[kTop * v + j] = ok ? top.id[j] : -1;
+        if (seed) seed[j * n + p] = ok ? g.pos[top.id[j]] : -1;
+    }
+    const int64_t deg2 = 2 * cn + cz;
+    if (neg) neg[v] = (int32_t)cn;
+    if (zero) zero[v] = (int32_t)cz;
+    if (step) step[v] = st;
+    o.sumlam = (unsigned long long)lamv;
+    o.rowneg = (unsigned long long)rn;
+    o.unsat = (top.z[1] > 0 || top.z[2] < 0) ? 1 : 0;
+    o.bad = deg2 != 4 ? 1 : 0;
+    o.nonzero = st != 0 ? 1 : 0;
+    o.maxstep = st < 0 ? -st : st;
+    o.maxabs = nxt < 0 ? -nxt : nxt;
+    o.hsh = mix64((uint64_t)lamv ^ (0x9E3779B97F4A7C15ULL * (uint64_t)(v + 1)));
+}
+
+// Block reductions of the rows' records, then the last block of the grid
+// writes the iteration record, takes the stop decision and clears the
+// accumulators.  Called by every thread of the block.
+__device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t k, Ctrl *ctrl, int64_t *trace,
+                                                   float *tile_hmax)
+{
+    __shared__ unsigned long long red[kBlock / 64];
+    __shared__ float redf[kBlock / 64];
+    __shared__ int s_last;
+    if (tile_hmax) {
+        // a block of kBlock positions is one column tile
+        const float hm = block_reduce<float, true>(o.hmax, redf);
+        if (threadIdx.x == 0) tile_hmax[blockIdx.x] = hm;
+    }
+    const unsigned long long sumlam = block_reduce<unsigned long long, false>(o.sumlam, red);
+    const unsigned long long rowneg = block_reduce<unsigned long long, false>(o.rowneg, red);
+    const unsigned long long unsat = block_reduce<unsigned long long, false>(o.unsat, red);
+    const unsigned long long bad = block_reduce<unsigned long long, false>(o.bad, red);
+    const unsigned long long nonzero = block_reduce<unsigned long long, false>(o.nonzero, red);
+    const unsigned long long hsh = block_reduce<unsigned long long, false>(o.hsh, red);
+    const unsigned long long maxstep = block_reduce<unsigned long long, true>((unsigned long long)o.maxstep, red);
+    const unsigned long long maxabs = block_reduce<unsigned long long, true>((unsigned long long)o.maxabs, red);
     if (threadIdx.x == 0) {
         atomicAdd(&ctrl->acc_sumlam, sumlam);
         atomicAdd(&ctrl->acc_rowneg, rowneg);
@@ -466,8 +468,8 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
         atomicAdd(&ctrl->acc_bad, bad);
         atomicAdd(&ctrl->acc_nonzero, nonzero);
         atomicAdd(&ctrl->acc_hash, hsh);
-        atomicMax((unsigned long long *)&ctrl->acc_maxstep, (unsigned long long)maxstep);
-        atomicMax((unsigned long long *)&ctrl->acc_maxabs_next, (unsigned long long)maxabs);
+        atomicMax((unsigned long long *)&ctrl->acc_maxstep, maxstep);
+        atomicMax((unsigned long long *)&ctrl->acc_maxabs_next, maxabs);
         __threadfence();
         const unsigned prev = atomicAdd(&ctrl->blocks_done, 1u);
         s_last = (prev == gridDim.x - 1);
@@ -477,7 +479,6 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
 
     // last block: every other block's atomics are visible
     __threadfence();
-    const long long k = a.k;
     const long long sl = (long long)atomicAdd(&ctrl->acc_sumlam, 0ULL);
     const long long rnsum = (long long)atomicAdd(&ctrl->acc_rowneg, 0ULL);
     const long long un = (long long)atomicAdd(&ctrl->acc_unsat, 0ULL);
@@ -488,8 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
     const long long mx = (long long)atomicAdd((unsigned long long *)&ctrl->acc_maxabs_next, 0ULL);
     // each unordered pair sits in two rows
     const long long dual2 = 2 * sl + rnsum / 2;
-    if (a.trace && k < ctrl->trace_cap) {
-        long long *rec = (long long *)a.trace + kTraceW * k;
+    if (trace && k < ctrl->trace_cap) {
+        long long *rec = (long long *)trace + kTraceW * k;
         rec[0] = k; rec[1] = dual2; rec[2] = un; rec[3] = bd;
         rec[4] = ms; rec[5] = nz; rec[6] = (long long)hh; rec[7] = sl;
     }
@@ -522,6 +523,287 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
     atomicExch((unsigned long long *)&ctrl->acc_maxabs_next, 0ULL);
     __threadfence();
     atomicExch(&ctrl->blocks_done, 0u);
+}
+
+// complete graph: merge the slices' partials, step, reduce, stop test
+__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
+{
+    Ctrl *ctrl = a.ctrl;
+    if (ctrl->done) return;
+    const int64_t n = a.g.n;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // Lam_{k-1} sits in lam_out until it is overwritten
+    const bool copy_best = a.k > 0 && ctrl->best_k == a.k - 1;
+    RowOut o;
+    if (p < n) {
+        Top4 top;
+        top.clear();
+        int64_t cn = 0, cz = 0, rn = 0;
+        for (int64_t sl = 0; sl < a.nslices; ++sl) {
+#pragma unroll
+            for (int j = 0; j < kTop; ++j)
+                top.insert(a.pz[(sl * kTop + j) * n + p], a.pi[(sl * kTop + j) * n + p]);
+            cn += a.pneg[sl * n + p];
+            cz += a.pzero[sl * n + p];
+            rn += a.prowneg[sl * n + p];
+        }
+        step_row(a.g, p, top, cn, cz, rn, a.lam_in[p], copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
+                 a.neg, a.zero, a.step, a.col, o);
+    }
+    reduce_and_control(o, n, a.k, ctrl, a.trace, a.tile_hmax);
+}
+
+// candidate graph: one fused pass per iteration over the CSR rows
+__global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
+{
+    Ctrl *ctrl = a.ctrl;
+    if (ctrl->done) return;
+    const int64_t n = a.g.n;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool copy_best = a.k > 0 && ctrl->best_k == a.k - 1;
+    RowOut o;
+    if (p < n) {
+        Top4 top;
+        top.clear();
+        int64_t cn = 0, cz = 0, rn = 0;
+        const int64_t lamv = a.lam_in[p];
+        const int32_t e1 = a.csr.rowptr[p + 1];
+        for (int32_t e = a.csr.rowptr[p]; e < e1; ++e) {
+            const int32_t u = a.csr.col[e];
+            const int64_t z = 2 * (int64_t)a.csr.cost[e] - lamv - a.lam_in[u];   // eq. 9, doubled
+            if (z < 0) { ++cn; rn += z; }
+            else if (z == 0) ++cz;
+            top.insert(z, a.g.orig[u]);
+        }
+        step_row(a.g, p, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, nullptr,
+                 a.neg, a.zero, a.step, nullptr, o);
+    }
+    reduce_and_control(o, n, a.k, ctrl, a.trace, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// candidate graph: k nearest neighbours and the CSR
+// ---------------------------------------------------------------------------
+
+// K smallest (D, label) per row over every column, by tiles, culled by the
+// block's largest current threshold.  Thresholds start at the largest D of
+// K + 1 neighbouring positions (any K distinct columns bound the K-th
+// smallest D); the float test keeps every pair with D <= thr exactly.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_t *nbr, int64_t *nbr_d)
+{
+    __shared__ float2 sc[kTile];
+    __shared__ double redd[kBlock / 64];
+    const int t = threadIdx.x;
+    const int64_t n = g.n;
+    const int64_t p = (int64_t)blockIdx.x * kBlock + t;
+    const bool valid = p < n;
+    float xv = 0.0f, yv = 0.0f;
+    int64_t bd[K];
+    int32_t bl[K], bp[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) { bd[j] = INT64_MAX; bl[j] = kNoIdx; bp[j] = -1; }
+    int64_t thr = INT64_MAX;
+    int32_t lv = 0;
+    if (valid) {
+        const float4 cv = col[p];
+        xv = cv.x; yv = cv.y;
+        lv = g.orig[p];
+        int64_t lo = p - K / 2;
+        lo = lo < 0 ? 0 : (lo > n - K - 1 ? n - K - 1 : lo);
+        int64_t mx = 0;
+        for (int64_t q = lo; q < lo + K + 1; ++q) {
+            if (q == p) continue;
+            const float4 cu = col[q];
+            const int32_t dx = (int32_t)(xv - cu.x), dy = (int32_t)(yv - cu.y);
+            const int64_t D = (int64_t)dx * dx + (int64_t)dy * dy;
+            mx = D > mx ? D : mx;
+        }
+        thr = mx;
+    }
+    float thrf = valid ? (float)thr * (1.0f + 0x1p-20f) + 1.0f : -INFINITY;
+    const double thrmax = block_reduce<double, true>(valid ? (double)thr : -1.0, redd);
+    const float4 rbox = g.box[blockIdx.x];
+    for (int64_t tile = 0; tile < n; tile += kTile) {
+        const float4 b = g.box[tile / kTile];
+        const double dx = fmax(0.0, fmax((double)b.x - rbox.y, (double)rbox.x - b.y));
+        const double dy = fmax(0.0, fmax((double)b.z - rbox.w, (double)rbox.z - b.w));
+        if (dx * dx + dy * dy > thrmax) continue;   // uniform over the block
+        __syncthreads();
+        const int64_t cc = tile + t;
+        if (cc < n) { const float4 c4 = col[cc]; sc[t] = make_float2(c4.x, c4.y); }
+        else sc[t] = make_float2(INFINITY, INFINITY);
+        __syncthreads();
+        const int64_t ntile = min((int64_t)kTile, n - tile);
+        for (int j = 0; j < ntile; ++j) {
+            const float2 cu = sc[j];
+            const float ddx = xv - cu.x, ddy = yv - cu.y;
+            const float df = fmaf(ddx, ddx, ddy * ddy);
+            if (!(df <= thrf)) continue;
+            const int64_t u = tile + j;
+            if (u == p) continue;
+            const int32_t ix = (int32_t)ddx, iy = (int32_t)ddy;
+            const int64_t D = (int64_t)ix * ix + (int64_t)iy * iy;
+            const int32_t lu = g.orig[u];
+            if (!(D < bd[K - 1] || (D == bd[K - 1] && lu < bl[K - 1]))) continue;
+            bd[K - 1] = D; bl[K - 1] = lu; bp[K - 1] = (int32_t)u;
+#pragma unroll
+            for (int q = K - 1; q > 0; --q) {
+                if (bd[q] < bd[q - 1] || (bd[q] == bd[q - 1] && bl[q] < bl[q - 1])) {
+                    const int64_t td = bd[q]; bd[q] = bd[q - 1]; bd[q - 1] = td;
+                    const int32_t tl = bl[q]; bl[q] = bl[q - 1]; bl[q - 1] = tl;
+                    const int32_t tp = bp[q]; bp[q] = bp[q - 1]; bp[q - 1] = tp;
+                }
+            }
+            if (bp[K - 1] >= 0 && bd[K - 1] < thr) {
+                thr = bd[K - 1];
+                thrf = (float)thr * (1.0f + 0x1p-20f) + 1.0f;
+            }
+        }
+    }
+    (void)lv;
+    if (valid) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            nbr[p * K + j] = bp[j];
+            if (nbr_d) nbr_d[p * K + j] = bd[j];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pair_keys(const int32_t *nbr, int64_t nk, int K, uint64_t *keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nk) return;
+    const uint64_t p = (uint64_t)(i / K), q = (uint64_t)(uint32_t)nbr[i];
+    keys[i] = p < q ? (p << 32) | q : (q << 32) | p;
+}
+
+// counts distinct undirected edges per endpoint (keys sorted)
+__global__ __launch_bounds__(kBlock) void k_edge_count(const uint64_t *keys, int64_t nk, int32_t *deg)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nk || (i > 0 && keys[i] == keys[i - 1])) return;
+    atomicAdd(&deg[keys[i] >> 32], 1);
+    atomicAdd(&deg[keys[i] & 0xffffffffULL], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_edge_fill(const uint64_t *keys, int64_t nk, const int32_t *rowptr,
+                                                      int32_t *cursor, int32_t *col)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nk || (i > 0 && keys[i] == keys[i - 1])) return;
+    const int32_t a = (int32_t)(keys[i] >> 32), b = (int32_t)(keys[i] & 0xffffffffULL);
+    col[rowptr[a] + atomicAdd(&cursor[a], 1)] = b;
+    col[rowptr[b] + atomicAdd(&cursor[b], 1)] = a;
+}
+
+// sorts each row's columns (insertion sort: rows are short) and fills the
+// exact costs
+__global__ __launch_bounds__(kBlock) void k_row_finish(const int32_t *xy, const int32_t *orig, int64_t n,
+                                                       const int32_t *rowptr, int32_t *col, int32_t *cost)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const int32_t e0 = rowptr[p], e1 = rowptr[p + 1];
+    for (int32_t e = e0 + 1; e < e1; ++e) {
+        const int32_t x = col[e];
+        int32_t f = e - 1;
+        while (f >= e0 && col[f] > x) { col[f + 1] = col[f]; --f; }
+        col[f + 1] = x;
+    }
+    const int64_t v = orig[p];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int64_t u = orig[col[e]];
+        const int64_t dx = (int64_t)xy[2 * v] - xy[2 * u], dy = (int64_t)xy[2 * v + 1] - xy[2 * u + 1];
+        cost[e] = (int32_t)nint_sqrt(dx * dx + dy * dy);
+    }
+}
+
+// sum over CSR entries of min(0, Z)
+__global__ __launch_bounds__(kBlock) void k_graph_dual(Geo g, Csr csr, const int64_t *lam, unsigned long long *acc)
+{
+    __shared__ unsigned long long red[kBlock / 64];
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t s = 0;
+    if (p < g.n) {
+        const int64_t lv = lam[p];
+        for (int32_t e = csr.rowptr[p]; e < csr.rowptr[p + 1]; ++e) {
+            const int64_t z = 2 * (int64_t)csr.cost[e] - lv - lam[csr.col[e]];
+            if (z < 0) s += z;
+        }
+    }
+    const unsigned long long tot = block_reduce<unsigned long long, false>((unsigned long long)s, red);
+    if (threadIdx.x == 0 && tot) atomicAdd(&acc[0], tot);
+}
+
+__global__ __launch_bounds__(kBlock) void k_graph_collect(Geo g, Csr csr, const int64_t *lam, int64_t slack,
+                                                          unsigned long long *count, int2 *out, int64_t cap)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= g.n) return;
+    const int64_t lv = lam[p];
+    const int32_t e0 = csr.rowptr[p], e1 = csr.rowptr[p + 1];
+    int64_t th = -1;
+    if (slack >= 0) {
+        int64_t b[kTop] = {INT64_MAX, INT64_MAX, INT64_MAX, INT64_MAX};
+        for (int32_t e = e0; e < e1; ++e) {
+            int64_t z = 2 * (int64_t)csr.cost[e] - lv - lam[csr.col[e]];
+#pragma unroll
+            for (int j = 0; j < kTop; ++j) if (z < b[j]) { const int64_t tt = b[j]; b[j] = z; z = tt; }
+        }
+        th = b[3] == INT64_MAX ? INT64_MAX / 4 : (b[3] > 0 ? b[3] : 0) + slack;
+    }
+    const int32_t lp = g.orig[p];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t u = csr.col[e];
+        const int64_t z = 2 * (int64_t)csr.cost[e] - lv - lam[u];
+        if (z > th) continue;
+        const unsigned long long slot = atomicAdd(count, 1ULL);
+        if ((int64_t)slot < cap) {
+            const int32_t lu = g.orig[u];
+            out[slot] = make_int2(min(lp, lu), max(lp, lu));
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_graph_membership(Geo g, Csr csr, int64_t m, const int32_t *eu,
+                                                             const int32_t *ev, unsigned long long *acc)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= m) return;
+    const int64_t u = eu[e], v = ev[e];
+    if (u < 0 || v < 0 || u >= g.n || v >= g.n) return;   // counted by the edge check
+    const int32_t pu = g.pos[u], pv = g.pos[v];
+    int32_t lo = csr.rowptr[pu], hi = csr.rowptr[pu + 1];
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (csr.col[mid] < pv) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= csr.rowptr[pu + 1] || csr.col[lo] != pv) atomicAdd(&acc[2], 1ULL);
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_degrees(Geo g, Csr csr, int32_t *deg)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= g.n) return;
+    const int32_t p = g.pos[v];
+    deg[v] = csr.rowptr[p + 1] - csr.rowptr[p];
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_rows(Geo g, Csr csr, const int32_t *rowptr_l, int32_t *col_l)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= g.n) return;
+    const int32_t p = g.pos[v];
+    const int32_t o = rowptr_l[v];
+    const int32_t e0 = csr.rowptr[p], e1 = csr.rowptr[p + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t x = g.orig[csr.col[e]];
+        int32_t f = o + (e - e0) - 1;
+        while (f >= o && col_l[f] > x) { col_l[f + 1] = col_l[f]; --f; }
+        col_l[f + 1] = x;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -902,6 +1184,96 @@ hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_pe
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_update, dim3(blocks_for(a.g.n, kBlock)), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_step(const GraphStepArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_graph_step, dim3(blocks_for(a.g.n, kBlock)), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn(const Geo &g, const float4 *col, int K, int32_t *nbr, int64_t *nbr_d, hipStream_t st)
+{
+    if (g.n < K + 1) return hipErrorInvalidValue;
+    switch (K) {
+    case 10: hipLaunchKernelGGL(k_knn<10>, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, col, nbr, nbr_d); break;
+    case 16: hipLaunchKernelGGL(k_knn<16>, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, col, nbr, nbr_d); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+size_t csr_temp_bytes(int64_t n, int K)
+{
+    size_t a = 0, b = 0;
+    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                            (int)(n * K), 0, 64);
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int32_t *)nullptr, (int32_t *)nullptr, (int)(n + 1));
+    return a > b ? a : b;
+}
+
+hipError_t launch_build_csr(const Geo &g, const int32_t *xy, int64_t n, int K, const int32_t *nbr, uint64_t *keys,
+                            uint64_t *keys_alt, int32_t *deg, int32_t *rowptr, int32_t *col, int32_t *cost,
+                            int64_t *nnz_dev, void *temp, size_t temp_bytes, int64_t cap, hipStream_t st)
+{
+    const int64_t nk = n * K;
+    hipLaunchKernelGGL(k_pair_keys, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, nbr, nk, K, keys);
+    size_t tb = temp_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, tb, keys, keys_alt, (int)nk, 0, 64, st);
+    if (e != hipSuccess) return e;
+    if ((e = hipMemsetAsync(deg, 0, (n + 1) * sizeof(int32_t), st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_edge_count, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, keys_alt, nk, deg);
+    tb = temp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(temp, tb, deg, rowptr, (int)(n + 1), st);
+    if (e != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(nnz_dev, rowptr + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+    (void)cap;   // 2*n*K >= nnz always
+    if ((e = hipMemsetAsync(deg, 0, (n + 1) * sizeof(int32_t), st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_edge_fill, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, keys_alt, nk, rowptr, deg, col);
+    hipLaunchKernelGGL(k_row_finish, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, xy, g.orig, n, rowptr, col,
+                       cost);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_sorted, unsigned long long *acc,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_graph_dual, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, csr, lam_sorted, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_collect(const Geo &g, const Csr &csr, const int64_t *lam_sorted, int64_t slack,
+                                unsigned long long *count, int2 *out, int64_t cap, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_graph_collect, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, csr, lam_sorted,
+                       slack, count, out, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_membership(const Geo &g, const Csr &csr, int64_t m, const int32_t *eu, const int32_t *ev,
+                                   unsigned long long *acc, hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_graph_membership, dim3(blocks_for(m, kBlock)), dim3(kBlock), 0, st, g, csr, m, eu, ev, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_to_labels(const Geo &g, const Csr &csr, int32_t *rowptr_l, int32_t *col_l, int32_t *deg_tmp,
+                                hipStream_t st)
+{
+    // rows by label: degrees, exclusive sum (host-sized scan in one block), fill
+    hipLaunchKernelGGL(k_label_degrees, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, csr, deg_tmp);
+    size_t tb = 0;
+    hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, tb, deg_tmp, rowptr_l, (int)(g.n + 1), st);
+    if (e != hipSuccess) return e;
+    void *temp = nullptr;
+    if ((e = hipMallocAsync(&temp, tb, st)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(deg_tmp + g.n, 0, sizeof(int32_t), st)) != hipSuccess) return e;
+    e = hipcub::DeviceScan::ExclusiveSum(temp, tb, deg_tmp, rowptr_l, (int)(g.n + 1), st);
+    (void)hipFreeAsync(temp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_label_rows, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, csr, rowptr_l, col_l);
     return hipGetLastError();
 }
 

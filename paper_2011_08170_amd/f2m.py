@@ -25,7 +25,8 @@ SCAN = {"culled": 0, "full": 1}
 TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
 SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
-           "f2m_result_free", "f2m_status_str", "f2m_last_error")
+           "f2m_knn_graph", "f2m_result_free", "f2m_status_str", "f2m_last_error")
+GRAPH = {"complete": 0, "knn": 1}
 
 
 class F2MError(RuntimeError):
@@ -36,7 +37,7 @@ class F2MError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("rule_version", C.c_uint32), ("graph", C.c_int32),
-                ("warm", C.c_int32), ("lambda2_init", C.c_void_p), ("max_iters", C.c_int64),
+                ("knn_k", C.c_int32), ("warm", C.c_int32), ("lambda2_init", C.c_void_p), ("max_iters", C.c_int64),
                 ("handoff_div", C.c_int64),
                 ("finish", C.c_int32), ("coords_on_device", C.c_int32), ("record_trace", C.c_int32),
                 ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("scan_mode", C.c_int32),
@@ -53,7 +54,9 @@ class Result(C.Structure):
                 ("trace_len", C.c_int64), ("trace", C.POINTER(C.c_int64)), ("seconds", C.c_double * 6),
                 ("scan_ms", C.c_double), ("scan_launches", C.c_int64), ("scan_rows", C.c_int32),
                 ("pad0", C.c_int32), ("scan_slices", C.c_int64), ("scan_pairs", C.c_int64),
-                ("finish_phases", C.c_int64), ("finish_candidates", C.c_int64), ("finish_seconds", C.c_double * 3)]
+                ("finish_phases", C.c_int64), ("finish_candidates", C.c_int64), ("finish_seconds", C.c_double * 3),
+                ("dual2_complete", C.c_int64), ("certified_complete", C.c_int32), ("pad1", C.c_int32),
+                ("graph_nnz", C.c_int64)]
 
 
 _lib = None
@@ -79,6 +82,8 @@ def lib():
         L.f2m_gdp_step.argtypes = [p, p, i64, p, p, p, p, p, p, p, p]
         L.f2m_certify.restype = C.c_int
         L.f2m_certify.argtypes = [p, p, i64, p, i64, p, p, p, p]
+        L.f2m_knn_graph.restype = C.c_int
+        L.f2m_knn_graph.argtypes = [p, p, i64, C.c_int32, p, p, i64, p]
         L.f2m_result_free.restype = None
         L.f2m_result_free.argtypes = [C.POINTER(Result)]
         L.f2m_status_str.restype = C.c_char_p
@@ -136,7 +141,7 @@ class Context:
         return st
 
     def solve(self, coords, *, max_iters=100000, handoff_div=300, finish="exact", lambda2_init=None,
-              trace=False, chunk=0, stream=None, time_kernels=False, scan="culled"):
+              trace=False, chunk=0, stream=None, time_kernels=False, scan="culled", graph="complete", knn_k=10):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
         array on the host or a contiguous int32 device tensor."""
         o = Opts()
@@ -148,6 +153,8 @@ class Context:
         o.chunk = int(chunk)
         o.time_kernels = 1 if time_kernels else 0
         o.scan_mode = SCAN[scan]
+        o.graph = GRAPH[graph]
+        o.knn_k = int(knn_k)
         keep = []
         if lambda2_init is not None:
             l0 = _np(lambda2_init, np.int64)
@@ -183,6 +190,8 @@ class Context:
                 scan_slices=res.scan_slices, scan_pairs=res.scan_pairs,
                 finish_phases=res.finish_phases, finish_candidates=res.finish_candidates,
                 finish_seconds=dict(zip(("collect", "build", "flow"), list(res.finish_seconds))),
+                dual2_complete=res.dual2_complete, certified_complete=bool(res.certified_complete),
+                graph_nnz=res.graph_nnz,
             )
             if res.trace_len:
                 out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(
@@ -211,3 +220,17 @@ class Context:
                                       _dptr(ev) if m else None, _dptr(ex2) if m else None,
                                       out.ctypes.data_as(C.c_void_p)))
         return dict(primal2=int(out[0]), dual2=int(out[1]), feasible=bool(out[2]), certified=bool(out[3]))
+
+
+def knn_graph(ctx, coords, k=10):
+    """CSR (rowptr, col) of the candidate graph over labels, from a device
+    coordinate tensor; returns numpy arrays."""
+    import torch
+    n = coords.shape[0]
+    rowptr = torch.empty(n + 1, dtype=torch.int32, device=coords.device)
+    cap = 2 * k * n
+    col = torch.empty(cap, dtype=torch.int32, device=coords.device)
+    nnz = C.c_int64(0)
+    ctx._check(lib().f2m_knn_graph(ctx._h, _dptr(coords), n, int(k), _dptr(rowptr), _dptr(col), cap,
+                                   C.byref(nnz)))
+    return rowptr.cpu().numpy().astype(np.int64), col[:nnz.value].cpu().numpy()
