@@ -675,7 +675,9 @@ __global__ __launch_bounds__(kBlock) void k_pair_keys(const int32_t *nbr, int64_
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nk) return;
-    const uint64_t p = (uint64_t)(i / K), q = (uint64_t)(uint32_t)nbr[i];
+    const int32_t qq = nbr[i];
+    if (qq < 0) { keys[i] = ~0ULL; return; }   // unfilled slot: sorts last, never used
+    const uint64_t p = (uint64_t)(i / K), q = (uint64_t)qq;
     keys[i] = p < q ? (p << 32) | q : (q << 32) | p;
 }
 
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_keys(const int32_t *nbr, int64_
 __global__ __launch_bounds__(kBlock) void k_edge_count(const uint64_t *keys, int64_t nk, int32_t *deg)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= nk || (i > 0 && keys[i] == keys[i - 1])) return;
+    if (i >= nk || keys[i] == ~0ULL || (i > 0 && keys[i] == keys[i - 1])) return;
     atomicAdd(&deg[keys[i] >> 32], 1);
     atomicAdd(&deg[keys[i] & 0xffffffffULL], 1);
 }
@@ -692,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_fill(const uint64_t *keys, int6
                                                       int32_t *cursor, int32_t *col)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= nk || (i > 0 && keys[i] == keys[i - 1])) return;
+    if (i >= nk || keys[i] == ~0ULL || (i > 0 && keys[i] == keys[i - 1])) return;
     const int32_t a = (int32_t)(keys[i] >> 32), b = (int32_t)(keys[i] & 0xffffffffULL);
     col[rowptr[a] + atomicAdd(&cursor[a], 1)] = b;
     col[rowptr[b] + atomicAdd(&cursor[b], 1)] = a;
