@@ -70,6 +70,11 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--instance", choices=("uniform", "clustered"), default="uniform",
+                    help="uniform: integer coordinates uniform in [0,10^6)^2; clustered: 200 Gaussian centres, "
+                         "sigma 2%% of the side")
+    ap.add_argument("--graph", choices=("complete", "knn"), default="complete",
+                    help="complete graph, or the 10-nearest-neighbour candidate graph")
     ap.add_argument("--scan", choices=("culled", "full"), default="culled",
                     help="culled: skip column tiles that provably hold no relevant pair (default); "
                          "full: test every ordered pair")
@@ -99,20 +104,24 @@ def main():
     from paper_2011_08170_amd import f2m, instances
 
     n = args.n
-    xy = instances.uniform(n, 1_000_000, args.seed)
+    if args.instance == "uniform":
+        xy = instances.uniform(n, 1_000_000, args.seed)
+    else:
+        xy = instances.clustered(n, 1_000_000, args.seed)
     ctx = f2m.Context(0)
     xy_dev = torch.from_numpy(xy).cuda()
     torch.cuda.synchronize()
-    log("workload: n=%d uniform [0,1e6)^2 seed=%d; warmup %d, steps %d" % (n, args.seed, args.warmup, args.steps))
+    log("workload: n=%d %s [0,1e6)^2 seed=%d graph=%s; warmup %d, steps %d" % (
+        n, args.instance, args.seed, args.graph, args.warmup, args.steps))
     for i in range(args.warmup):
-        r = ctx.solve(xy_dev, scan=args.scan)
+        r = ctx.solve(xy_dev, scan=args.scan, graph=args.graph)
         log("warmup %d: %s, %d iterations, %.3f s" % (i, r["status"], r["iterations"], r["seconds"]["total"]))
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
     for i in range(args.steps):
-        r = ctx.solve(xy_dev, time_kernels=True, scan=args.scan)
+        r = ctx.solve(xy_dev, time_kernels=True, scan=args.scan, graph=args.graph)
         runs.append(r)
         log("step %d: %s stop=%s iterations=%d total=%.3f s (gdp %.3f, finish %.3f, certify %.3f)" % (
             i, r["status"], r["stop"], r["iterations"], r["seconds"]["total"], r["seconds"]["gdp"],
@@ -125,14 +134,33 @@ def main():
     scan_ms = sum(r["scan_ms"] for r in runs)
     launches = sum(r["scan_launches"] for r in runs)
     avg_ms = scan_ms / max(launches, 1)
-    # ordered pairs the scan evaluated per launch (culled tiles excluded)
-    tested = sum(r["scan_pairs"] for r in runs) / max(launches, 1)
-    ops = OPS_PER_PAIR * tested
-    achieved = ops / (avg_ms * 1e-3) / 1e12
+    if args.graph == "complete":
+        # ordered pairs the scan evaluated per launch (culled tiles excluded)
+        tested = sum(r["scan_pairs"] for r in runs) / max(launches, 1)
+        ops = OPS_PER_PAIR * tested
+        achieved = ops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_rowscan<%d,gdp>" % runs[-1]["scan_rows"], "achieved": achieved,
+                "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
+                "pairs_tested_per_launch": tested, "ops_per_launch": ops,
+                "slices": runs[-1]["scan_slices"]}
+        value = iters * pairs / elapsed
+        unit = "pair-evals/s"
+    else:
+        nnz = runs[-1]["graph_nnz"]
+        # per row: rowptr 4, own label 4, Lam in 8, Lam out 8, top-4 Z 32 and labels 16;
+        # per entry: column 4, cost 4, Lam 8, label 4
+        nbytes = n * 72 + nnz * 20
+        achieved = nbytes / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "k_graph_step", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                "frac": achieved / 8000.0, "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
+                "bytes_per_launch": nbytes, "nnz": nnz}
+        value = iters * nnz / 2 / elapsed
+        unit = "edge-evals/s"
     out = {
         "metric": METRIC,
-        "value": iters * pairs / elapsed,
-        "unit": "pair-evals/s",
+        "value": value,
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -142,11 +170,13 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "F2M GDP, complete graph, n=%d cities uniform integer in [0,10^6)^2, seed %d, "
-                               "cold start, %s scan" % (n, args.seed, args.scan),
-                   "n": n, "graph": "complete", "start": "cold", "scan": args.scan},
+        "config": {"workload": "F2M GDP, %s graph, n=%d cities %s integer in [0,10^6)^2, seed %d, cold start, %s" % (
+                       args.graph, n, args.instance, args.seed,
+                       "%s scan" % args.scan if args.graph == "complete" else "k=10"),
+                   "n": n, "instance": args.instance, "graph": args.graph, "start": "cold", "scan": args.scan},
         "time_to_certified_s": elapsed / args.steps,
         "certified": all(r["certified"] for r in runs),
+        "certified_complete": all(r["certified_complete"] for r in runs),
         "iterations": [r["iterations"] for r in runs],
         "stop": [r["stop"] for r in runs],
         "objective2": runs[-1]["primal2"],
@@ -155,13 +185,10 @@ def main():
                                       for k in ("collect", "build", "flow")},
                           "paths": runs[-1]["finish_paths"], "phases": runs[-1]["finish_phases"],
                           "rounds": runs[-1]["finish_rounds"], "candidates": runs[-1]["finish_candidates"]},
-        "scan_pair_evals_per_s": pairs / (avg_ms * 1e-3),
-        "roofline": {"bound": "alu", "kernel": "k_rowscan<%d,gdp>" % runs[-1]["scan_rows"], "achieved": achieved,
-                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
-                     "pairs_tested_per_launch": tested, "ops_per_launch": ops,
-                     "slices": runs[-1]["scan_slices"]},
+        "roofline": roof,
     }
+    if args.graph == "complete":
+        out["scan_pair_evals_per_s"] = pairs / (avg_ms * 1e-3)
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
