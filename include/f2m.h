@@ -162,6 +162,21 @@ void f2m_destroy(f2m_ctx *ctx);
 f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
                      const f2m_opts *opts, f2m_result *out);
 
+/* Many independent instances in one batched GDP loop: every iteration is
+ * one scan launch and one update launch over all instances (work items
+ * instance x row block x column slice, a control block and stop test per
+ * instance), a chunk of iterations is captured once as a HIP graph and
+ * replayed until every instance has stopped; then each instance gets its
+ * finish and certificate.  Results equal independent f2m_solve calls.
+ *   coords   host int32, instance i at coords[2*offsets[i] .. 2*offsets[i+1])
+ *   offsets  host int64[n_inst+1], offsets[0] = 0, every size >= 3
+ *   opts     as for f2m_solve (complete graph, host coordinates); a
+ *            USER warm start reads lambda2_init[offsets[i] + v]
+ *   outs     host array of n_inst results (free each with f2m_result_free)
+ * Returns F2M_OK when every instance is certified. */
+f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *offsets, int32_t n_inst,
+                           const f2m_opts *opts, f2m_result *outs);
+
 /* One GDP iteration (eq. 9, eq. 10, Jacobi) on device buffers, n >= 4:
  *   coords_xy   device int32[2n]
  *   lambda2_in  device int64[n]  (Lam_k)

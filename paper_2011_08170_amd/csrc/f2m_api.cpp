@@ -41,6 +41,9 @@ struct f2m_ctx {
     DevBuf p_pairs, p_count;
     // candidate graph
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
+    // batched solve pools
+    DevBuf b_xy, b_orig, b_pos, b_col, b_box, b_x2m, b_lam0, b_lam1, b_best, b_lamlabel, b_thm, b_pz, b_pi, b_pneg,
+        b_pzero, b_prn, b_z4, b_i4, b_seed, b_ctrl, b_trace, b_sargs, b_uargs, b_sitems, b_uitems, b_nblk, b_active;
     Ctrl *ctrl_host = nullptr;   // pinned
     int64_t *scratch_host = nullptr;   // pinned, 16 entries
 
@@ -51,7 +54,10 @@ struct f2m_ctx {
                          &prowneg, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
                          &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &knn_nbr, &csr_keys,
-                         &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz};
+                         &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
+                         &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
+                         &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
+                         &b_sargs, &b_uargs, &b_sitems, &b_uitems, &b_nblk, &b_active};
         bufs.assign(std::begin(all), std::end(all));
     }
 };
@@ -149,7 +155,28 @@ struct GeoHost {
     Geo g;
     const int32_t *xy;   // device coordinates (labels)
     int32_t cx, cy;
+    float4 *col;         // GDP column records
 };
+
+struct GeoBufs {
+    int32_t *orig, *pos;
+    float4 *col, *box;
+    float *xy2max;
+};
+
+// Morton order, centred column records and tile boxes for one instance
+// whose extents are known; enqueued on st without synchronising.
+void enqueue_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, int32_t minx, int32_t miny, int32_t cx, int32_t cy,
+                 const GeoBufs &b, hipStream_t st)
+{
+    const size_t tb = sort_temp_bytes(n);
+    uint32_t *keys = grow<uint32_t>(ctx, ctx->keys, n);
+    uint32_t *keys2 = grow<uint32_t>(ctx, ctx->keys_alt, n);
+    int32_t *ids = grow<int32_t>(ctx, ctx->ids, n);
+    void *temp = grow<char>(ctx, ctx->sort_temp, tb);
+    ck(ctx, launch_sort(xy_dev, n, minx, miny, keys, keys2, ids, b.orig, b.pos, temp, tb, st), "sort");
+    ck(ctx, launch_prep(xy_dev, b.orig, n, cx, cy, b.col, b.box, b.xy2max, st), "prep");
+}
 
 GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st)
 {
@@ -165,23 +192,15 @@ GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st
     gh.cx = (int32_t)(((int64_t)h[0] + h[1]) >> 1);
     gh.cy = (int32_t)(((int64_t)h[2] + h[3]) >> 1);
     gh.xy = xy_dev;
-    const size_t tb = sort_temp_bytes(n);
-    uint32_t *keys = grow<uint32_t>(ctx, ctx->keys, n);
-    uint32_t *keys2 = grow<uint32_t>(ctx, ctx->keys_alt, n);
-    int32_t *ids = grow<int32_t>(ctx, ctx->ids, n);
-    int32_t *orig = grow<int32_t>(ctx, ctx->orig, n);
-    int32_t *pos = grow<int32_t>(ctx, ctx->pos, n);
-    void *temp = grow<char>(ctx, ctx->sort_temp, tb);
-    ck(ctx, launch_sort(xy_dev, n, h[0], h[2], keys, keys2, ids, orig, pos, temp, tb, st), "sort");
-    float4 *col = grow<float4>(ctx, ctx->col, n);
-    float4 *box = grow<float4>(ctx, ctx->box, ntiles_of(n));
-    float *x2m = grow<float>(ctx, ctx->xy2max, 1);
-    ck(ctx, launch_prep(xy_dev, orig, n, gh.cx, gh.cy, col, box, x2m, st), "prep");
+    GeoBufs b{grow<int32_t>(ctx, ctx->orig, n), grow<int32_t>(ctx, ctx->pos, n), grow<float4>(ctx, ctx->col, n),
+              grow<float4>(ctx, ctx->box, ntiles_of(n)), grow<float>(ctx, ctx->xy2max, 1)};
+    enqueue_geo(ctx, xy_dev, n, h[0], h[2], gh.cx, gh.cy, b, st);
     float x2host = 0.0f;
-    ck(ctx, hipMemcpyAsync(ctx->scratch_host, x2m, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, b.xy2max, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     std::memcpy(&x2host, ctx->scratch_host, sizeof(float));
-    gh.g = Geo{n, orig, pos, box, x2host};
+    gh.g = Geo{n, b.orig, b.pos, b.box, x2host};
+    gh.col = b.col;
     return gh;
 }
 
@@ -195,7 +214,7 @@ LamView place_lam(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label_dev,
     float *th = grow<float>(ctx, ctx->c_tile_hmax, ntiles_of(n));
     Ctrl *cc = grow<Ctrl>(ctx, ctx->c_ctrl, 1);
     float *x2m = grow<float>(ctx, ctx->xy2max, 1);
-    ck(ctx, launch_prep(gh.xy, gh.g.orig, n, gh.cx, gh.cy, col, (float4 *)ctx->box.p, x2m, st), "prep");
+    ck(ctx, launch_prep(gh.xy, gh.g.orig, n, gh.cx, gh.cy, col, const_cast<float4 *>(gh.g.box), x2m, st), "prep");
     ck(ctx, launch_ctrl_init(cc, 0, 0, 0, st), "ctrl");
     ck(ctx, launch_set_lam(lam_label_dev, gh.g.orig, n, ls, col, th, cc, st), "set_lam");
     return LamView{col, ls, th, cc};
@@ -327,7 +346,7 @@ Csr build_graph(f2m_ctx *ctx, const GeoHost &gh, int K, hipStream_t st)
     const size_t tb = csr_temp_bytes(n, K);
     void *temp = grow<char>(ctx, ctx->csr_temp, tb);
     ck(ctx, hipMemsetAsync(nnz_dev, 0, sizeof(int64_t), st), "memset");
-    ck(ctx, launch_knn(gh.g, static_cast<const float4 *>(ctx->col.p), K, nbr, nullptr, st), "knn");
+    ck(ctx, launch_knn(gh.g, gh.col, K, nbr, nullptr, st), "knn");
     ck(ctx, launch_build_csr(gh.g, gh.xy, n, K, nbr, keys, keys2, deg, rowptr, col, cost, nnz_dev, temp, tb, 2 * nk,
                              st), "csr");
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, nnz_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
@@ -433,7 +452,7 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     const int64_t n = gh.g.n;
     // on the candidate graph the step is one fused kernel and needs no partials
     const ScanShape sh = csr ? ScanShape{1, 1, ((n + kTileCols - 1) / kTileCols) * kTileCols} : scan_shape(n, cull);
-    float4 *col = static_cast<float4 *>(ctx->col.p);
+    float4 *col = gh.col;
     int64_t *lam[2] = {grow<int64_t>(ctx, ctx->lam[0], n), grow<int64_t>(ctx, ctx->lam[1], n)};
     int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
     int64_t *l0 = grow<int64_t>(ctx, ctx->lam_label, n);
@@ -547,6 +566,133 @@ f2m_status solve_n3(f2m_ctx *ctx, const int32_t *xy, f2m_result *out)
     return F2M_OK;
 }
 
+// Everything after the GDP loop for one instance: Lam* by label, the
+// trivial x or the exact finish, the certificate(s) and the host copies.
+struct InstanceState {
+    GeoHost gh;
+    Ctrl c;
+    const int64_t *lam_star;   // device, sorted
+    const int64_t *z4;         // device, by label
+    const int32_t *i4;
+    const int32_t *seed;       // device, positions
+    const int64_t *trace;      // device or null
+    const Csr *csr;            // candidate graph or null
+};
+
+void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, const int32_t *xy_host, hipStream_t st,
+                     f2m_result &res)
+{
+    const int64_t n = is.gh.g.n;
+    const GeoHost &gh = is.gh;
+    const Ctrl &c = is.c;
+    res.n = n;
+    res.iterations = c.k_last + 1;
+    res.kstar = c.kstar;
+    res.stop = (int32_t)c.stop;
+    int64_t *lstar = grow<int64_t>(ctx, ctx->lam_label, n);
+    ck(ctx, launch_unpermute(is.lam_star, gh.g.orig, n, lstar, st), "unpermute");
+    res.lambda2_gdp = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
+    ck(ctx, hipMemcpyAsync(res.lambda2_gdp, lstar, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+    if (is.trace) {
+        res.trace_len = std::min<int64_t>(res.iterations, c.trace_cap);
+        res.trace = reinterpret_cast<int64_t *>(host_alloc(ctx, res.trace_len * kTraceW * sizeof(int64_t)));
+        ck(ctx, hipMemcpyAsync(res.trace, is.trace, res.trace_len * kTraceW * sizeof(int64_t),
+                               hipMemcpyDeviceToHost, st), "copy");
+    }
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    res.dual2_gdp = (c.kstar == c.k_last) ? c.dual2_last : c.best_dual2;
+
+    int32_t *eu = nullptr, *ev = nullptr;
+    uint8_t *ex = nullptr;
+    int64_t m = 0;
+    const int64_t *lam_final_dev = lstar;
+    const double t3 = now_s();
+    bool have_x = false;
+    if (c.stop == F2M_STOP_TRIVIAL) {
+        const int64_t ns = kTop * n;
+        int32_t *su = grow<int32_t>(ctx, ctx->slot_u, ns);
+        int32_t *sv = grow<int32_t>(ctx, ctx->slot_v, ns);
+        uint8_t *sx = grow<uint8_t>(ctx, ctx->slot_x, ns);
+        eu = grow<int32_t>(ctx, ctx->eu, ns);
+        ev = grow<int32_t>(ctx, ctx->ev, ns);
+        ex = grow<uint8_t>(ctx, ctx->ex, ns);
+        int32_t *bt = grow<int32_t>(ctx, ctx->btmp, compact_block_tmp_len(ns));
+        int64_t *cnt = grow<int64_t>(ctx, ctx->count, 1);
+        ck(ctx, launch_extract_trivial(is.z4, is.i4, n, su, sv, sx, st), "extract");
+        ck(ctx, launch_compact(su, sv, sx, ns, eu, ev, ex, cnt, bt, st), "compact");
+        ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        m = ctx->scratch_host[0];
+        have_x = true;
+    } else if (o.finish == F2M_FINISH_EXACT) {
+        FinishResult fr;
+        if (is.csr) {
+            GpuGraphPairs src(ctx, gh, *is.csr, st);
+            finish_exact(xy_host, n, res.lambda2_gdp, src, &fr);
+        } else {
+            GpuPairs src(ctx, gh, is.seed, st);
+            finish_exact(xy_host, n, res.lambda2_gdp, src, &fr);
+        }
+        res.finish_paths = fr.paths;
+        res.finish_rounds = fr.rounds;
+        res.finish_phases = fr.phases;
+        res.finish_candidates = fr.candidates;
+        res.finish_seconds[0] = fr.t_collect;
+        res.finish_seconds[1] = fr.t_build;
+        res.finish_seconds[2] = fr.t_flow;
+        if (!fr.ok) fail(ctx, F2M_ERR_DEVICE, "exact finish failed: " + fr.msg);
+        m = (int64_t)fr.eu.size();
+        int64_t *ld = grow<int64_t>(ctx, ctx->c_lam_label, n);
+        eu = grow<int32_t>(ctx, ctx->c_eu, std::max<int64_t>(m, 1));
+        ev = grow<int32_t>(ctx, ctx->c_ev, std::max<int64_t>(m, 1));
+        ex = grow<uint8_t>(ctx, ctx->c_ex, std::max<int64_t>(m, 1));
+        // the GDP multipliers stay available in lstar; the certificate's
+        // duals go to their own buffer
+        int64_t *lf = grow<int64_t>(ctx, ctx->lam_best, n);
+        ck(ctx, hipMemcpyAsync(lf, fr.lam.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+        (void)ld;
+        if (m) {
+            ck(ctx, hipMemcpyAsync(eu, fr.eu.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+            ck(ctx, hipMemcpyAsync(ev, fr.ev.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+            ck(ctx, hipMemcpyAsync(ex, fr.ex2.data(), m * sizeof(uint8_t), hipMemcpyHostToDevice, st), "copy");
+        }
+        lam_final_dev = lf;
+        have_x = true;
+    }
+    const double t4 = now_s();
+    int64_t cert[4] = {0, 0, 0, 0}, cert_full[4] = {0, 0, 0, 0};
+    if (have_x) {
+        if (is.csr) {
+            certify_graph_dev(ctx, gh, *is.csr, lam_final_dev, m, eu, ev, ex, st, cert);
+            certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert_full);
+        } else {
+            certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert);
+            std::memcpy(cert_full, cert, sizeof(cert));
+        }
+    }
+    const double t5 = now_s();
+    res.n_edges = m;
+    res.edge_u = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
+    res.edge_v = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
+    res.edge_x2 = reinterpret_cast<uint8_t *>(host_alloc(ctx, std::max<int64_t>(m, 1)));
+    res.lambda2 = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
+    if (m) {
+        ck(ctx, hipMemcpyAsync(res.edge_u, eu, m * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(res.edge_v, ev, m * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(res.edge_x2, ex, m * sizeof(uint8_t), hipMemcpyDeviceToHost, st), "copy");
+    }
+    ck(ctx, hipMemcpyAsync(res.lambda2, lam_final_dev, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    res.primal2 = cert[0];
+    res.dual2 = have_x ? cert[1] : res.dual2_gdp;
+    res.certified = (int32_t)cert[3];
+    res.dual2_complete = have_x ? cert_full[1] : 0;
+    res.certified_complete = (int32_t)cert_full[3];
+    res.scan_pairs = (int64_t)c.pairs_tested;
+    res.seconds[3] = t4 - t3;
+    res.seconds[4] = t5 - t4;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -647,7 +793,7 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
         const GeoHost gh = setup_geo(ctx, xy, n, st);
         const bool cull = true;
         const ScanShape sh = scan_shape(n, cull);
-        float4 *col = static_cast<float4 *>(ctx->col.p);
+        float4 *col = gh.col;
         int64_t *ls = grow<int64_t>(ctx, ctx->lam[0], n);
         int64_t *lo = grow<int64_t>(ctx, ctx->lam[1], n);
         int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
@@ -807,119 +953,17 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         LoopOut lo = gdp_loop(ctx, gh, lam0_dev, o.max_iters, o.handoff_div, o.chunk, o.record_trace != 0,
                               o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, on_graph ? &csr : nullptr, st);
         const double t2 = now_s();
-        res.n = n;
-        res.iterations = lo.c.k_last + 1;
-        res.kstar = lo.c.kstar;
-        res.stop = (int32_t)lo.c.stop;
-        int64_t *lstar = grow<int64_t>(ctx, ctx->lam_label, n);
-        ck(ctx, launch_unpermute(lo.lam_star, gh.g.orig, n, lstar, st), "unpermute");
-        res.lambda2_gdp = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
-        ck(ctx, hipMemcpyAsync(res.lambda2_gdp, lstar, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
-        if (o.record_trace) {
-            res.trace_len = res.iterations;
-            res.trace = reinterpret_cast<int64_t *>(host_alloc(ctx, res.trace_len * kTraceW * sizeof(int64_t)));
-            ck(ctx, hipMemcpyAsync(res.trace, ctx->trace.p, res.trace_len * kTraceW * sizeof(int64_t),
-                                   hipMemcpyDeviceToHost, st), "copy");
-        }
-        ck(ctx, hipStreamSynchronize(st), "sync");
-        res.dual2_gdp = (lo.c.kstar == lo.c.k_last) ? lo.c.dual2_last : lo.c.best_dual2;
-
-        int32_t *eu = nullptr, *ev = nullptr;
-        uint8_t *ex = nullptr;
-        int64_t m = 0;
-        const int64_t *lam_final_dev = lstar;
-        const double t3 = now_s();
-        bool have_x = false;
-        if (lo.c.stop == F2M_STOP_TRIVIAL) {
-            const int64_t ns = kTop * n;
-            int32_t *su = grow<int32_t>(ctx, ctx->slot_u, ns);
-            int32_t *sv = grow<int32_t>(ctx, ctx->slot_v, ns);
-            uint8_t *sx = grow<uint8_t>(ctx, ctx->slot_x, ns);
-            eu = grow<int32_t>(ctx, ctx->eu, ns);
-            ev = grow<int32_t>(ctx, ctx->ev, ns);
-            ex = grow<uint8_t>(ctx, ctx->ex, ns);
-            int32_t *bt = grow<int32_t>(ctx, ctx->btmp, compact_block_tmp_len(ns));
-            int64_t *cnt = grow<int64_t>(ctx, ctx->count, 1);
-            ck(ctx, launch_extract_trivial((const int64_t *)ctx->z4.p, (const int32_t *)ctx->i4.p, n, su, sv, sx, st),
-               "extract");
-            ck(ctx, launch_compact(su, sv, sx, ns, eu, ev, ex, cnt, bt, st), "compact");
-            ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
-            ck(ctx, hipStreamSynchronize(st), "sync");
-            m = ctx->scratch_host[0];
-            have_x = true;
-        } else if (o.finish == F2M_FINISH_EXACT) {
-            FinishResult fr;
-            if (on_graph) {
-                GpuGraphPairs src(ctx, gh, csr, st);
-                finish_exact(xy_host.data(), n, res.lambda2_gdp, src, &fr);
-            } else {
-                GpuPairs src(ctx, gh, (const int32_t *)ctx->seed.p, st);
-                finish_exact(xy_host.data(), n, res.lambda2_gdp, src, &fr);
-            }
-            res.finish_paths = fr.paths;
-            res.finish_rounds = fr.rounds;
-            res.finish_phases = fr.phases;
-            res.finish_candidates = fr.candidates;
-            res.finish_seconds[0] = fr.t_collect;
-            res.finish_seconds[1] = fr.t_build;
-            res.finish_seconds[2] = fr.t_flow;
-            if (!fr.ok) fail(ctx, F2M_ERR_DEVICE, "exact finish failed: " + fr.msg);
-            m = (int64_t)fr.eu.size();
-            int64_t *ld = grow<int64_t>(ctx, ctx->c_lam_label, n);
-            eu = grow<int32_t>(ctx, ctx->c_eu, std::max<int64_t>(m, 1));
-            ev = grow<int32_t>(ctx, ctx->c_ev, std::max<int64_t>(m, 1));
-            ex = grow<uint8_t>(ctx, ctx->c_ex, std::max<int64_t>(m, 1));
-            // the GDP multipliers stay available in lstar; the certificate's
-            // duals go to their own buffer
-            int64_t *lf = grow<int64_t>(ctx, ctx->lam_best, n);
-            ck(ctx, hipMemcpyAsync(lf, fr.lam.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
-            (void)ld;
-            if (m) {
-                ck(ctx, hipMemcpyAsync(eu, fr.eu.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
-                ck(ctx, hipMemcpyAsync(ev, fr.ev.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
-                ck(ctx, hipMemcpyAsync(ex, fr.ex2.data(), m * sizeof(uint8_t), hipMemcpyHostToDevice, st), "copy");
-            }
-            lam_final_dev = lf;
-            have_x = true;
-        }
-        const double t4 = now_s();
-        int64_t cert[4] = {0, 0, 0, 0}, cert_full[4] = {0, 0, 0, 0};
-        if (have_x) {
-            if (on_graph) {
-                certify_graph_dev(ctx, gh, csr, lam_final_dev, m, eu, ev, ex, st, cert);
-                certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert_full);
-            } else {
-                certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert);
-                std::memcpy(cert_full, cert, sizeof(cert));
-            }
-        }
-        const double t5 = now_s();
-        res.n_edges = m;
-        res.edge_u = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
-        res.edge_v = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
-        res.edge_x2 = reinterpret_cast<uint8_t *>(host_alloc(ctx, std::max<int64_t>(m, 1)));
-        res.lambda2 = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
-        if (m) {
-            ck(ctx, hipMemcpyAsync(res.edge_u, eu, m * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-            ck(ctx, hipMemcpyAsync(res.edge_v, ev, m * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-            ck(ctx, hipMemcpyAsync(res.edge_x2, ex, m * sizeof(uint8_t), hipMemcpyDeviceToHost, st), "copy");
-        }
-        ck(ctx, hipMemcpyAsync(res.lambda2, lam_final_dev, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipStreamSynchronize(st), "sync");
-        res.primal2 = cert[0];
-        res.dual2 = have_x ? cert[1] : res.dual2_gdp;
-        res.certified = (int32_t)cert[3];
-        res.dual2_complete = have_x ? cert_full[1] : 0;
-        res.certified_complete = (int32_t)cert_full[3];
-        res.scan_pairs = (int64_t)lo.c.pairs_tested;
+        InstanceState is{gh, lo.c, lo.lam_star, static_cast<const int64_t *>(ctx->z4.p),
+                         static_cast<const int32_t *>(ctx->i4.p), static_cast<const int32_t *>(ctx->seed.p),
+                         o.record_trace ? static_cast<const int64_t *>(ctx->trace.p) : nullptr,
+                         on_graph ? &csr : nullptr};
+        complete_result(ctx, is, o, xy_host.data(), st, res);
         res.scan_ms = lo.scan_ms;
         res.scan_launches = lo.scan_launches;
         res.scan_rows = lo.shape.rows;
         res.scan_slices = lo.shape.slices;
         res.seconds[0] = t1 - t0;
         res.seconds[2] = t2 - t1;
-        res.seconds[3] = t4 - t3;
-        res.seconds[4] = t5 - t4;
         res.seconds[5] = now_s() - t0;
         *out = res;
         return res.certified ? F2M_OK : F2M_NOT_CERTIFIED;
@@ -928,6 +972,258 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         return f.st;
     } catch (const std::bad_alloc &) {
         f2m_result_free(&res);
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+
+f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *offsets, int32_t n_inst,
+                           const f2m_opts *opts, f2m_result *outs)
+{
+    if (!ctx) return F2M_ERR_ARG;
+    std::vector<f2m_result> res;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct GraphGuard {
+        hipGraph_t &g;
+        hipGraphExec_t &e;
+        ~GraphGuard()
+        {
+            if (e) (void)hipGraphExecDestroy(e);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    } gguard{graph, exec};
+    try {
+        f2m_opts o;
+        f2m_opts_default(&o);
+        if (opts) {
+            if (opts->struct_size != sizeof(f2m_opts)) fail(ctx, F2M_ERR_ARG, "opts.struct_size mismatch");
+            o = *opts;
+        }
+        if (!coords || !offsets || !outs || n_inst <= 0) fail(ctx, F2M_ERR_ARG, "null inputs or no instances");
+        if (o.rule_version != 1) fail(ctx, F2M_ERR_ARG, "only rule_version 1 exists");
+        if (o.graph != F2M_GRAPH_COMPLETE) fail(ctx, F2M_ERR_ARG, "batched solves run on the complete graph");
+        if (o.coords_on_device) fail(ctx, F2M_ERR_ARG, "batched solves take host coordinates");
+        if (o.max_iters < 0 || o.handoff_div < 0) fail(ctx, F2M_ERR_ARG, "bad max_iters or handoff_div");
+        if (o.warm != F2M_WARM_COLD && !(o.warm == F2M_WARM_USER && o.lambda2_init))
+            fail(ctx, F2M_ERR_ARG, "bad warm start");
+        if (offsets[0] != 0) fail(ctx, F2M_ERR_ARG, "offsets[0] must be 0");
+        for (int32_t i = 0; i < n_inst; ++i) {
+            if (offsets[i + 1] - offsets[i] < 3) fail(ctx, F2M_ERR_INFEASIBLE, "every instance needs n >= 3");
+            if (offsets[i + 1] - offsets[i] >= (int64_t)1 << 30) fail(ctx, F2M_ERR_ARG, "instance too large");
+        }
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        hipStream_t st = pick_stream(ctx, &o);
+        const double t0 = now_s();
+        res.assign(n_inst, f2m_result{});
+        const int64_t total = offsets[n_inst];
+        const bool cull = o.scan_mode != F2M_SCAN_FULL;
+
+        // layout: positions and tiles 256-aligned per instance
+        std::vector<int64_t> P(n_inst + 1, 0), T(n_inst + 1, 0), PZ(n_inst + 1, 0), PS(n_inst + 1, 0);
+        std::vector<ScanShape> shp(n_inst);
+        std::vector<int32_t> cxs(n_inst), cys(n_inst), mnx(n_inst), mny(n_inst);
+        std::vector<int> active;   // instances with n >= 4
+        for (int32_t i = 0; i < n_inst; ++i) {
+            const int64_t n = offsets[i + 1] - offsets[i];
+            const int32_t *xy = coords + 2 * offsets[i];
+            int64_t lo[2] = {xy[0], xy[1]}, hi[2] = {xy[0], xy[1]};
+            for (int64_t v = 1; v < n; ++v)
+                for (int a = 0; a < 2; ++a) {
+                    lo[a] = std::min<int64_t>(lo[a], xy[2 * v + a]);
+                    hi[a] = std::max<int64_t>(hi[a], xy[2 * v + a]);
+                }
+            if (hi[0] - lo[0] >= (1 << 20) || hi[1] - lo[1] >= (1 << 20))
+                fail(ctx, F2M_ERR_RANGE, "coordinate span must be below 2^20 on each axis");
+            mnx[i] = (int32_t)lo[0]; mny[i] = (int32_t)lo[1];
+            cxs[i] = (int32_t)((lo[0] + hi[0]) >> 1); cys[i] = (int32_t)((lo[1] + hi[1]) >> 1);
+            const int64_t nt = ntiles_of(n);
+            // one row per lane for the whole launch; the batch itself fills
+            // the GPU, so culled scans take one slice and full scans a few
+            shp[i].rows = 1;
+            const int64_t sl = cull ? 1 : std::min<int64_t>(nt, 4);
+            shp[i].slice_len = ((nt + sl - 1) / sl) * kTileCols;
+            shp[i].slices = (n + shp[i].slice_len - 1) / shp[i].slice_len;
+            P[i + 1] = P[i] + nt * kTileCols;
+            T[i + 1] = T[i] + nt;
+            PZ[i + 1] = PZ[i] + shp[i].slices * n;
+            if (n >= 4) active.push_back(i);
+        }
+        const int64_t trace_cap = o.record_trace ? std::min<int64_t>(o.max_iters + 1, 8192) : 0;
+
+        // pools
+        int32_t *xy = grow<int32_t>(ctx, ctx->b_xy, 2 * total);
+        int32_t *orig = grow<int32_t>(ctx, ctx->b_orig, P[n_inst]);
+        int32_t *pos = grow<int32_t>(ctx, ctx->b_pos, total);
+        float4 *col = grow<float4>(ctx, ctx->b_col, P[n_inst]);
+        float4 *box = grow<float4>(ctx, ctx->b_box, T[n_inst]);
+        float *x2m = grow<float>(ctx, ctx->b_x2m, n_inst);
+        int64_t *lam0 = grow<int64_t>(ctx, ctx->b_lam0, P[n_inst]);
+        int64_t *lam1 = grow<int64_t>(ctx, ctx->b_lam1, P[n_inst]);
+        int64_t *best = grow<int64_t>(ctx, ctx->b_best, P[n_inst]);
+        int64_t *lamlabel = grow<int64_t>(ctx, ctx->b_lamlabel, total);
+        float *thm = grow<float>(ctx, ctx->b_thm, T[n_inst]);
+        int64_t *pz = grow<int64_t>(ctx, ctx->b_pz, kTop * PZ[n_inst]);
+        int32_t *pi = grow<int32_t>(ctx, ctx->b_pi, kTop * PZ[n_inst]);
+        int32_t *pneg = grow<int32_t>(ctx, ctx->b_pneg, PZ[n_inst]);
+        int32_t *pzero = grow<int32_t>(ctx, ctx->b_pzero, PZ[n_inst]);
+        int64_t *prn = grow<int64_t>(ctx, ctx->b_prn, PZ[n_inst]);
+        int64_t *z4 = grow<int64_t>(ctx, ctx->b_z4, kTop * total);
+        int32_t *i4 = grow<int32_t>(ctx, ctx->b_i4, kTop * total);
+        int32_t *seed = grow<int32_t>(ctx, ctx->b_seed, kTop * total);
+        Ctrl *ctrl = grow<Ctrl>(ctx, ctx->b_ctrl, n_inst);
+        int64_t *trace = trace_cap ? grow<int64_t>(ctx, ctx->b_trace, (int64_t)n_inst * trace_cap * kTraceW) : nullptr;
+        int64_t *nblk = grow<int64_t>(ctx, ctx->b_nblk, n_inst);
+        int32_t *act = grow<int32_t>(ctx, ctx->b_active, 1);
+
+        ck(ctx, hipMemcpyAsync(xy, coords, 2 * total * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
+        if (o.warm == F2M_WARM_USER)
+            ck(ctx, hipMemcpyAsync(lamlabel, o.lambda2_init, total * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+        else
+            ck(ctx, hipMemsetAsync(lamlabel, 0, total * sizeof(int64_t), st), "memset");
+        std::vector<int64_t> nb_host(n_inst, 0);
+        for (int32_t i : active) {
+            const int64_t n = offsets[i + 1] - offsets[i], X = offsets[i];
+            GeoBufs b{orig + P[i], pos + X, col + P[i], box + T[i], x2m + i};
+            enqueue_geo(ctx, xy + 2 * X, n, mnx[i], mny[i], cxs[i], cys[i], b, st);
+            ck(ctx, launch_ctrl_init(ctrl + i, o.max_iters, trace_cap, o.handoff_div, st), "ctrl_init");
+            ck(ctx, launch_set_lam(lamlabel + X, orig + P[i], n, lam0 + P[i], col + P[i], thm + T[i], ctrl + i, st),
+               "set_lam");
+            ck(ctx, launch_seed_neighbours(n, seed + kTop * X, st), "seed");
+            nb_host[i] = ntiles_of(n);
+        }
+        ck(ctx, hipMemcpyAsync(nblk, nb_host.data(), n_inst * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+        ck(ctx, launch_ctrl_nblocks(ctrl, nblk, n_inst, st), "nblocks");
+        std::vector<float> x2h(n_inst);
+        std::vector<Ctrl> ch(n_inst);
+        ck(ctx, hipMemcpyAsync(x2h.data(), x2m, n_inst * sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(ch.data(), ctrl, n_inst * sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        for (int32_t i : active)
+            if (ch[i].maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2_init| must be below 2^38");
+
+        // per-instance argument tables and work items
+        std::vector<ScanArgs> sa(n_inst);
+        std::vector<UpdateArgs> ua(n_inst);
+        std::vector<BatchScanItem> sitems;
+        std::vector<BatchTileItem> uitems;
+        for (int32_t i : active) {
+            const int64_t n = offsets[i + 1] - offsets[i], X = offsets[i];
+            const Geo g{n, orig + P[i], pos + X, box + T[i], x2h[i]};
+            ScanArgs &a = sa[i];
+            a = ScanArgs{};
+            a.g = g;
+            a.lv = LamView{col + P[i], lam0 + P[i], thm + T[i], ctrl + i};
+            a.lam_odd = lam1 + P[i];
+            a.slice_len = shp[i].slice_len;
+            a.cull = cull ? 1 : 0;
+            a.check_done = 1;
+            a.tested = &ctrl[i].pairs_tested;
+            a.seed = seed + kTop * X;
+            a.pz = pz + kTop * PZ[i]; a.pi = pi + kTop * PZ[i];
+            a.pneg = pneg + PZ[i]; a.pzero = pzero + PZ[i]; a.prowneg = prn + PZ[i];
+            ua[i] = UpdateArgs{g, shp[i].slices, 0, a.pz, a.pi, a.pneg, a.pzero, a.prowneg, lam0 + P[i], lam1 + P[i],
+                               best + P[i], col + P[i], thm + T[i], z4 + kTop * X, i4 + kTop * X, seed + kTop * X,
+                               nullptr, nullptr, nullptr, ctrl + i,
+                               trace ? trace + (int64_t)i * trace_cap * kTraceW : nullptr};
+            const int64_t rb = ntiles_of(n);
+            for (int64_t r = 0; r < rb; ++r)
+                for (int64_t sl = 0; sl < shp[i].slices; ++sl)
+                    sitems.push_back(BatchScanItem{i, (int32_t)r, (int32_t)sl, 0});
+            for (int64_t b = 0; b < rb; ++b) uitems.push_back(BatchTileItem{i, (int32_t)b});
+        }
+        ScanArgs *sa_d = grow<ScanArgs>(ctx, ctx->b_sargs, n_inst);
+        UpdateArgs *ua_d = grow<UpdateArgs>(ctx, ctx->b_uargs, n_inst);
+        BatchScanItem *si_d = grow<BatchScanItem>(ctx, ctx->b_sitems, std::max<size_t>(sitems.size(), 1));
+        BatchTileItem *ui_d = grow<BatchTileItem>(ctx, ctx->b_uitems, std::max<size_t>(uitems.size(), 1));
+        ck(ctx, hipMemcpyAsync(sa_d, sa.data(), n_inst * sizeof(ScanArgs), hipMemcpyHostToDevice, st), "copy");
+        ck(ctx, hipMemcpyAsync(ua_d, ua.data(), n_inst * sizeof(UpdateArgs), hipMemcpyHostToDevice, st), "copy");
+        if (!sitems.empty()) {
+            ck(ctx, hipMemcpyAsync(si_d, sitems.data(), sitems.size() * sizeof(BatchScanItem), hipMemcpyHostToDevice, st),
+               "copy");
+            ck(ctx, hipMemcpyAsync(ui_d, uitems.data(), uitems.size() * sizeof(BatchTileItem), hipMemcpyHostToDevice, st),
+               "copy");
+        }
+        ck(ctx, hipStreamSynchronize(st), "sync");
+        const double t1 = now_s();
+
+        // the loop: a chunk of iterations captured once as a graph and
+        // replayed until every instance has stopped
+        if (!active.empty()) {
+            const int chunk = o.chunk > 0 ? 2 * ((o.chunk + 1) / 2) : 8;
+            ck(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            for (int j = 0; j < chunk; ++j) {
+                hipError_t e1 = launch_scan_batch(sa_d, si_d, (int64_t)sitems.size(), 1, st);
+                hipError_t e2 = launch_update_batch(ua_d, ui_d, (int64_t)uitems.size(), st);
+                if (e1 != hipSuccess || e2 != hipSuccess) {
+                    hipGraph_t g2 = nullptr;
+                    (void)hipStreamEndCapture(st, &g2);
+                    if (g2) (void)hipGraphDestroy(g2);
+                    ck(ctx, e1 != hipSuccess ? e1 : e2, "batched launch");
+                }
+            }
+            ck(ctx, hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+            ck(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            const int64_t max_replays = o.max_iters / chunk + 2;
+            int64_t replays = 0;
+            for (;;) {
+                ck(ctx, hipGraphLaunch(exec, st), "hipGraphLaunch");
+                ++replays;
+                ck(ctx, launch_count_active(ctrl, n_inst, act, st), "count_active");
+                ck(ctx, hipMemcpyAsync(ctx->scratch_host, act, sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+                ck(ctx, hipStreamSynchronize(st), "sync");
+                int32_t left;
+                std::memcpy(&left, ctx->scratch_host, sizeof(int32_t));
+                // instances of n = 3 never start: count only the others
+                int32_t idle = 0;
+                for (int32_t i = 0; i < n_inst; ++i) idle += (offsets[i + 1] - offsets[i] < 4) ? 1 : 0;
+                if (left - idle <= 0) break;
+                if (replays > max_replays) fail(ctx, F2M_ERR_DEVICE, "batched GDP loop passed the cap");
+            }
+        }
+        const double t2 = now_s();
+        ck(ctx, hipMemcpyAsync(ch.data(), ctrl, n_inst * sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipStreamSynchronize(st), "sync");
+
+        // per-instance finish and certificate
+        for (int32_t i = 0; i < n_inst; ++i) {
+            const int64_t n = offsets[i + 1] - offsets[i], X = offsets[i];
+            const double ti = now_s();
+            if (n == 3) {
+                (void)solve_n3(ctx, coords + 2 * X, &res[i]);
+                continue;
+            }
+            if (ch[i].overflow) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| reached 2^38");
+            GeoHost gh;
+            gh.g = Geo{n, orig + P[i], pos + X, box + T[i], x2h[i]};
+            gh.xy = xy + 2 * X;
+            gh.cx = cxs[i];
+            gh.cy = cys[i];
+            gh.col = col + P[i];
+            const Ctrl &c = ch[i];
+            const int64_t *last = (c.k_last & 1) ? lam1 + P[i] : lam0 + P[i];
+            const int64_t *lstar = (c.kstar == c.k_last) ? last : best + P[i];
+            InstanceState is{gh, c, lstar, z4 + kTop * X, i4 + kTop * X, seed + kTop * X,
+                             trace ? trace + (int64_t)i * trace_cap * kTraceW : nullptr, nullptr};
+            complete_result(ctx, is, o, coords + 2 * X, st, res[i]);
+            res[i].scan_rows = 1;
+            res[i].scan_slices = shp[i].slices;
+            res[i].seconds[2] = t2 - t1;
+            res[i].seconds[5] = now_s() - ti;
+        }
+        for (int32_t i = 0; i < n_inst; ++i) {
+            res[i].seconds[0] = t1 - t0;
+            outs[i] = res[i];
+        }
+        bool all = true;
+        for (int32_t i = 0; i < n_inst; ++i) all = all && res[i].certified;
+        return all ? F2M_OK : F2M_NOT_CERTIFIED;
+    } catch (const Fail &f) {
+        for (auto &r : res) f2m_result_free(&r);
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        for (auto &r : res) f2m_result_free(&r);
         ctx->err = "host allocation failed";
         return F2M_ERR_NOMEM;
     }

@@ -53,6 +53,8 @@ struct Ctrl {
     long long dual2_last;  // dual2 of Lam_{k_last}
     long long handoff_div; // hand-off stop: #unsat * div <= n (0: off)
     unsigned long long pairs_tested;   // ordered pairs the GDP scans evaluated (all iterations)
+    long long k_next;      // iteration the next update evaluates (batched, graph-replayed loops)
+    long long nblocks;     // blocks of this instance's update launch (batched loops)
 };
 
 // Static geometry of an instance in sorted order.
@@ -81,6 +83,7 @@ struct ScanArgs {
     int64_t slice_len;          // columns per slice (blockIdx.y), multiple of kTileCols
     int cull;                   // skip column tiles that cannot hold a passing pair
     int check_done;             // GDP loop: exit at once when ctrl->done
+    const int64_t *lam_odd;     // batched loop: Lam_k for odd k (lv.lam holds even k)
     unsigned long long *tested; // if set: += ordered pairs evaluated (culled tiles excluded)
     const int32_t *seed;        // [j][n] positions bounding the 4th smallest Z, or null
     // GDP mode: partial results per (slice, position), structure of arrays
@@ -146,6 +149,25 @@ struct GraphStepArgs {
     Ctrl *ctrl;
     int64_t *trace;
 };
+
+// Batched loop: one launch covers every instance.  Work items are tables in
+// device memory; per-instance argument structs live in device memory too.
+struct BatchScanItem {
+    int32_t inst, row_block, slice, pad;
+};
+struct BatchTileItem {
+    int32_t inst, block;   // update block `block` of instance `inst`
+};
+// Single-instance ScanArgs/UpdateArgs pointers are rebased per instance; the
+// iteration index of a batched update comes from the instance's Ctrl.
+hipError_t launch_scan_batch(const ScanArgs *args_dev, const BatchScanItem *items, int64_t nitems, int rows,
+                             hipStream_t st);
+hipError_t launch_update_batch(const UpdateArgs *args_dev, const BatchTileItem *items, int64_t nitems,
+                               hipStream_t st);
+// ctrls[i].nblocks = nblocks[i]
+hipError_t launch_ctrl_nblocks(Ctrl *ctrls, const int64_t *nblocks, int64_t ninst, hipStream_t st);
+// out[0] = number of instances not yet done
+hipError_t launch_count_active(const Ctrl *ctrls, int64_t ninst, int32_t *out, hipStream_t st);
 
 // Launchers (f2m_kernels.hip).  All run on `st`; none synchronises.
 // k nearest neighbours (K in {10, 16}) by (D, label): nbr[p*K + j] positions

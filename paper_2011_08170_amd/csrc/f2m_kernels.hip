@@ -225,7 +225,7 @@ __device__ __forceinline__ bool seeded_bound(const ScanArgs &a, int64_t p, float
 // MODE kModeCert: the sum over the slice of min(0, Z) (theta = 0), added to
 // acc[0].  MODE kModeCollect: every pair with Z <= theta_row.
 template <int R, int MODE>
-__global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
+__device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rblk, const int64_t sl)
 {
     if (a.check_done && a.lv.ctrl->done) return;
     __shared__ float4 sc[kTile];
@@ -233,7 +233,6 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
     __shared__ unsigned long long redu[kBlock / 64];
     const int t = threadIdx.x;
     const int64_t n = a.g.n;
-    const int64_t sl = blockIdx.y;
     const int64_t c0 = sl * a.slice_len;
     const int64_t c1 = min(n, c0 + a.slice_len);
     const float colmax = col_bound(a.g.xy2max, a.lv.ctrl->maxabs_lam);
@@ -245,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
     float hvmax = -INFINITY;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t p = (int64_t)blockIdx.x * (kBlock * R) + r * kBlock + t;
+        const int64_t p = rblk * (kBlock * R) + r * kBlock + t;
         rw[r].v = p;
         top[r].clear();
         neg[r] = 0; zero[r] = 0; rn[r] = 0;
@@ -279,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
         hvmax = block_reduce<float, true>(hvmax, redf);
         const int64_t ntiles = (n + kTile - 1) / kTile;
         for (int r = 0; r < R; ++r) {
-            const int64_t ti = (int64_t)blockIdx.x * R + r;
+            const int64_t ti = rblk * R + r;
             if (ti < ntiles) {
                 const float4 b = a.g.box[ti];
                 rbox.x = fminf(rbox.x, b.x); rbox.y = fmaxf(rbox.y, b.y);
@@ -289,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
     }
 
     // rows of this block: positions [rb0, rb1)
-    const int64_t rb0 = (int64_t)blockIdx.x * (kBlock * R);
+    const int64_t rb0 = rblk * (kBlock * R);
     const int64_t rb1 = min(n, rb0 + (int64_t)kBlock * R);
     unsigned long long tested = 0;
     for (int64_t tile = c0; tile < c1; tile += kTile) {
@@ -385,6 +384,22 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
     }
 }
 
+template <int R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
+{
+    rowscan_body<R, MODE>(a, blockIdx.x, blockIdx.y);
+}
+
+// batched GDP scan: one block per (instance, row block, slice)
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_rowscan_batch(const ScanArgs *args, const BatchScanItem *items)
+{
+    const BatchScanItem w = items[blockIdx.x];
+    ScanArgs a = args[w.inst];
+    if (a.lv.ctrl->k_next & 1) a.lv.lam = a.lam_odd;
+    rowscan_body<R, kModeGdp>(a, w.row_block, w.slice);
+}
+
 // ---------------------------------------------------------------------------
 // per-node step, iteration record and stop test (shared by the complete-graph
 // update and the candidate-graph step)
@@ -443,7 +458,7 @@ __device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &to
 // writes the iteration record, takes the stop decision and clears the
 // accumulators.  Called by every thread of the block.
 __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t k, Ctrl *ctrl, int64_t *trace,
-                                                   float *tile_hmax)
+                                                   float *tile_hmax, int64_t blk, int64_t nblk)
 {
     __shared__ unsigned long long red[kBlock / 64];
     __shared__ float redf[kBlock / 64];
@@ -451,7 +466,7 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
     if (tile_hmax) {
         // a block of kBlock positions is one column tile
         const float hm = block_reduce<float, true>(o.hmax, redf);
-        if (threadIdx.x == 0) tile_hmax[blockIdx.x] = hm;
+        if (threadIdx.x == 0) tile_hmax[blk] = hm;
     }
     const unsigned long long sumlam = block_reduce<unsigned long long, false>(o.sumlam, red);
     const unsigned long long rowneg = block_reduce<unsigned long long, false>(o.rowneg, red);
@@ -472,7 +487,7 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
         atomicMax((unsigned long long *)&ctrl->acc_maxabs_next, maxabs);
         __threadfence();
         const unsigned prev = atomicAdd(&ctrl->blocks_done, 1u);
-        s_last = (prev == gridDim.x - 1);
+        s_last = (prev == (unsigned)(nblk - 1));
     }
     __syncthreads();
     if (!s_last || threadIdx.x != 0) return;
@@ -511,6 +526,7 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
     } else {
         ctrl->h2 = ctrl->h1;
         ctrl->h1 = hh;
+        ctrl->k_next = k + 1;
     }
     ctrl->maxabs_lam = mx;
     atomicExch(&ctrl->acc_sumlam, 0ULL);
@@ -526,14 +542,14 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
 }
 
 // complete graph: merge the slices' partials, step, reduce, stop test
-__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
+__device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k, const int64_t blk,
+                                            const int64_t nblk)
 {
     Ctrl *ctrl = a.ctrl;
-    if (ctrl->done) return;
     const int64_t n = a.g.n;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t p = blk * kBlock + threadIdx.x;
     // Lam_{k-1} sits in lam_out until it is overwritten
-    const bool copy_best = a.k > 0 && ctrl->best_k == a.k - 1;
+    const bool copy_best = k > 0 && ctrl->best_k == k - 1;
     RowOut o;
     if (p < n) {
         Top4 top;
@@ -550,7 +566,47 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
         step_row(a.g, p, top, cn, cz, rn, a.lam_in[p], copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
                  a.neg, a.zero, a.step, a.col, o);
     }
-    reduce_and_control(o, n, a.k, ctrl, a.trace, a.tile_hmax);
+    reduce_and_control(o, n, k, ctrl, a.trace, a.tile_hmax, blk, nblk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
+{
+    if (a.ctrl->done) return;
+    update_body(a, a.k, blockIdx.x, gridDim.x);
+}
+
+// batched update: the instance's iteration index lives in its Ctrl; the
+// lam buffers swap with its parity (the argument struct holds k even)
+__global__ __launch_bounds__(kBlock) void k_update_batch(const UpdateArgs *args, const BatchTileItem *items)
+{
+    const BatchTileItem w = items[blockIdx.x];
+    UpdateArgs a = args[w.inst];
+    if (a.ctrl->done) return;
+    const int64_t k = a.ctrl->k_next;
+    if (k & 1) {
+        const int64_t *t = a.lam_in;
+        a.lam_in = a.lam_out;
+        a.lam_out = const_cast<int64_t *>(t);
+    }
+    update_body(a, k, w.block, a.ctrl->nblocks);
+}
+
+__global__ void k_ctrl_nblocks(Ctrl *ctrls, const int64_t *nb, int64_t ninst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ninst) ctrls[i].nblocks = nb[i];
+}
+
+__global__ void k_count_active(const Ctrl *ctrls, int64_t ninst, int32_t *out)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int c = 0;
+    for (int64_t i = threadIdx.x; i < ninst; i += blockDim.x) c += ctrls[i].done ? 0 : 1;
+    atomicAdd(&cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = cnt;
 }
 
 // candidate graph: one fused pass per iteration over the CSR rows
@@ -578,7 +634,7 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
         step_row(a.g, p, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, nullptr,
                  a.neg, a.zero, a.step, nullptr, o);
     }
-    reduce_and_control(o, n, a.k, ctrl, a.trace, nullptr);
+    reduce_and_control(o, n, a.k, ctrl, a.trace, nullptr, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1186,6 +1242,38 @@ hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_pe
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_update, dim3(blocks_for(a.g.n, kBlock)), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_batch(const ScanArgs *args_dev, const BatchScanItem *items, int64_t nitems, int rows,
+                             hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    switch (rows) {
+    case 1: hipLaunchKernelGGL(k_rowscan_batch<1>, dim3((unsigned)nitems), dim3(kBlock), 0, st, args_dev, items); break;
+    case 2: hipLaunchKernelGGL(k_rowscan_batch<2>, dim3((unsigned)nitems), dim3(kBlock), 0, st, args_dev, items); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update_batch(const UpdateArgs *args_dev, const BatchTileItem *items, int64_t nitems,
+                               hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_batch, dim3((unsigned)nitems), dim3(kBlock), 0, st, args_dev, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_nblocks(Ctrl *ctrls, const int64_t *nblocks, int64_t ninst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctrl_nblocks, dim3(blocks_for(ninst, kBlock)), dim3(kBlock), 0, st, ctrls, nblocks, ninst);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_active(const Ctrl *ctrls, int64_t ninst, int32_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, st, ctrls, ninst, out);
     return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ SCAN = {"culled": 0, "full": 1}
 TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
 SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
-           "f2m_knn_graph", "f2m_result_free", "f2m_status_str", "f2m_last_error")
+           "f2m_knn_graph", "f2m_solve_batch", "f2m_result_free", "f2m_status_str", "f2m_last_error")
 GRAPH = {"complete": 0, "knn": 1}
 
 
@@ -82,6 +82,8 @@ def lib():
         L.f2m_gdp_step.argtypes = [p, p, i64, p, p, p, p, p, p, p, p]
         L.f2m_certify.restype = C.c_int
         L.f2m_certify.argtypes = [p, p, i64, p, i64, p, p, p, p]
+        L.f2m_solve_batch.restype = C.c_int
+        L.f2m_solve_batch.argtypes = [p, p, p, C.c_int32, C.POINTER(Opts), p]
         L.f2m_knn_graph.restype = C.c_int
         L.f2m_knn_graph.argtypes = [p, p, i64, C.c_int32, p, p, i64, p]
         L.f2m_result_free.restype = None
@@ -107,6 +109,31 @@ def _dptr(t):
 
 def _np(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _result_dict(res, n, st):
+    m = res.n_edges
+    out = dict(
+        status=STATUS[st], certified=bool(res.certified), stop=STOP_NAMES.get(res.stop, "?"),
+        iterations=res.iterations, kstar=res.kstar, primal2=res.primal2, dual2=res.dual2,
+        dual2_gdp=res.dual2_gdp, finish_paths=res.finish_paths, finish_rounds=res.finish_rounds,
+        lambda2=np.ctypeslib.as_array(res.lambda2, (n,)).copy(),
+        lambda2_gdp=np.ctypeslib.as_array(res.lambda2_gdp, (n,)).copy(),
+        edge_u=np.ctypeslib.as_array(res.edge_u, (max(m, 1),))[:m].copy(),
+        edge_v=np.ctypeslib.as_array(res.edge_v, (max(m, 1),))[:m].copy(),
+        edge_x2=np.ctypeslib.as_array(res.edge_x2, (max(m, 1),))[:m].copy(),
+        seconds=dict(zip(("setup", "warm", "gdp", "finish", "certify", "total"), list(res.seconds))),
+        scan_ms=res.scan_ms, scan_launches=res.scan_launches, scan_rows=res.scan_rows,
+        scan_slices=res.scan_slices, scan_pairs=res.scan_pairs,
+        finish_phases=res.finish_phases, finish_candidates=res.finish_candidates,
+        finish_seconds=dict(zip(("collect", "build", "flow"), list(res.finish_seconds))),
+        dual2_complete=res.dual2_complete, certified_complete=bool(res.certified_complete),
+        graph_nnz=res.graph_nnz,
+    )
+    if res.trace_len:
+        out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(
+            res.trace_len, TRACE_W).copy()
+    return out
 
 
 class Context:
@@ -175,30 +202,42 @@ class Context:
         res = Result()
         st = self._check(lib().f2m_solve(self._h, ptr, n, C.byref(o), C.byref(res)))
         try:
-            m = res.n_edges
-            out = dict(
-                status=STATUS[st], certified=bool(res.certified), stop=STOP_NAMES.get(res.stop, "?"),
-                iterations=res.iterations, kstar=res.kstar, primal2=res.primal2, dual2=res.dual2,
-                dual2_gdp=res.dual2_gdp, finish_paths=res.finish_paths, finish_rounds=res.finish_rounds,
-                lambda2=np.ctypeslib.as_array(res.lambda2, (n,)).copy(),
-                lambda2_gdp=np.ctypeslib.as_array(res.lambda2_gdp, (n,)).copy(),
-                edge_u=np.ctypeslib.as_array(res.edge_u, (max(m, 1),))[:m].copy(),
-                edge_v=np.ctypeslib.as_array(res.edge_v, (max(m, 1),))[:m].copy(),
-                edge_x2=np.ctypeslib.as_array(res.edge_x2, (max(m, 1),))[:m].copy(),
-                seconds=dict(zip(("setup", "warm", "gdp", "finish", "certify", "total"), list(res.seconds))),
-                scan_ms=res.scan_ms, scan_launches=res.scan_launches, scan_rows=res.scan_rows,
-                scan_slices=res.scan_slices, scan_pairs=res.scan_pairs,
-                finish_phases=res.finish_phases, finish_candidates=res.finish_candidates,
-                finish_seconds=dict(zip(("collect", "build", "flow"), list(res.finish_seconds))),
-                dual2_complete=res.dual2_complete, certified_complete=bool(res.certified_complete),
-                graph_nnz=res.graph_nnz,
-            )
-            if res.trace_len:
-                out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(
-                    res.trace_len, TRACE_W).copy()
+            return _result_dict(res, n, st)
         finally:
             lib().f2m_result_free(C.byref(res))
-        return out
+
+    def solve_batch(self, coords, offsets, *, max_iters=100000, handoff_div=300, finish="exact", trace=False,
+                    chunk=0, scan="culled", lambda2_init=None):
+        """Solves many instances in one batched loop.  coords: int32 (sum n, 2)
+        on the host; offsets: int64 (n_inst + 1).  Returns (status, [dict])."""
+        o = Opts()
+        lib().f2m_opts_default(C.byref(o))
+        o.max_iters = int(max_iters)
+        o.handoff_div = int(handoff_div)
+        o.finish = FINISH[finish]
+        o.record_trace = 1 if trace else 0
+        o.chunk = int(chunk)
+        o.scan_mode = SCAN[scan]
+        xy = _np(coords, np.int32)
+        off = _np(offsets, np.int64)
+        keep = [xy, off]
+        if lambda2_init is not None:
+            l0 = _np(lambda2_init, np.int64)
+            keep.append(l0)
+            o.warm = 1
+            o.lambda2_init = l0.ctypes.data
+        k = off.size - 1
+        arr = (Result * k)()
+        st = self._check(lib().f2m_solve_batch(self._h, xy.ctypes.data, off.ctypes.data, k, C.byref(o),
+                                               C.cast(arr, C.c_void_p)))
+        out = []
+        try:
+            for i in range(k):
+                out.append(_result_dict(arr[i], int(off[i + 1] - off[i]), 0 if arr[i].certified else 1))
+        finally:
+            for i in range(k):
+                lib().f2m_result_free(C.byref(arr[i]))
+        return STATUS[st], out
 
     def gdp_step(self, coords, lam_in, lam_out, z4=None, i4=None, neg=None, zero=None, step=None):
         """One GDP iteration on device tensors; returns the record dict."""

@@ -1,0 +1,63 @@
+"""Batched GDP (many uneven instances, one graph-captured loop) against the
+oracle and against independent solves, bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import core
+from paper_2011_08170_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2011_08170_amd import f2m
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    c = f2m.Context(0)
+    yield c
+    c.close()
+
+
+def small_batch():
+    # sizes log-uniform in [200, 3000], half uniform, half clustered, plus
+    # the degenerate sizes 3 and 4 and a ragged 257
+    xy, off = I.batch(14, 200, 3000, 7)
+    parts = [xy[off[i]:off[i + 1]] for i in range(14)]
+    parts += [I.uniform(3, 1000, 1), I.uniform(4, 1000, 2), I.uniform(257, 100000, 3)]
+    offs = np.zeros(len(parts) + 1, np.int64)
+    offs[1:] = np.cumsum([len(p) for p in parts])
+    return np.concatenate(parts), offs, parts
+
+
+def test_batch_matches_oracle(ctx):
+    xy, off, parts = small_batch()
+    st, res = ctx.solve_batch(xy, off, trace=True)
+    assert st == "ok"
+    for part, r in zip(parts, res):
+        assert r["certified"]
+        if len(part) == 3:
+            assert r["primal2"] == core.exact_opt2(part)
+            continue
+        o = core.gdp_solve(part, handoff_div=300)
+        assert r["iterations"] == o["iters"] and r["stop"] == o["stop"] and r["kstar"] == o["kstar"]
+        assert np.array_equal(r["trace"], o["trace"])
+        assert np.array_equal(r["lambda2_gdp"], o["lam"])
+        if len(part) <= 1500:
+            assert r["primal2"] == core.exact_opt2(part)
+        c = core.certify(part, r["lambda2"], r["edge_u"], r["edge_v"], r["edge_x2"])
+        assert c["certified"] and c["primal2"] == r["primal2"]
+
+
+def test_batch_equals_independent_solves(ctx):
+    xy, off = I.batch(10, 1000, 8000, 11)
+    for scan in ("culled", "full"):
+        st, res = ctx.solve_batch(xy, off, trace=True, scan=scan)
+        assert st == "ok"
+        for i, r in enumerate(res):
+            s = ctx.solve(xy[off[i]:off[i + 1]], trace=True)
+            for k in ("trace", "lambda2_gdp", "lambda2", "edge_u", "edge_v", "edge_x2"):
+                assert np.array_equal(r[k], s[k]), (scan, i, k)
+            assert r["primal2"] == s["primal2"] and r["certified"]
