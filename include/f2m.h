@@ -103,6 +103,9 @@ typedef struct f2m_opts {
     int32_t chunk;                /* iterations queued between host checks (0: auto) */
     int32_t time_kernels;         /* time every scan launch with HIP events */
     int32_t scan_mode;            /* F2M_SCAN_CULLED (default) or F2M_SCAN_FULL */
+    int32_t scan_rows;            /* launch shape: rows per lane, 1, 2 or 4 (0: built-in choice) */
+    int32_t scan_slices;          /* launch shape: column slices >= 1 (0: built-in choice);
+                                     the shape never changes a result, only the time */
     void *hip_stream;             /* hipStream_t to run on; NULL: the context's stream */
 } f2m_opts;
 

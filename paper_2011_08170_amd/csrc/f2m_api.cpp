@@ -111,7 +111,22 @@ struct ScanShape {
     int64_t slice_len;
 };
 
-ScanShape scan_shape(int64_t n, bool cull)
+ScanShape scan_shape_auto(int64_t n, bool cull);
+
+ScanShape scan_shape(int64_t n, bool cull, int rows_override = 0, int64_t slices_override = 0)
+{
+    ScanShape s = scan_shape_auto(n, cull);
+    const int64_t nt = ntiles_of(n);
+    if (rows_override == 1 || rows_override == 2 || rows_override == 4) s.rows = rows_override;
+    if (slices_override > 0) {
+        const int64_t sl = std::min<int64_t>(slices_override, nt);
+        s.slice_len = ((nt + sl - 1) / sl) * kTileCols;
+        s.slices = (n + s.slice_len - 1) / s.slice_len;
+    }
+    return s;
+}
+
+ScanShape scan_shape_auto(int64_t n, bool cull)
 {
     ScanShape s;
     const int64_t nt = ntiles_of(n);
@@ -446,12 +461,13 @@ struct LoopOut {
 // (null: zero).
 LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev, int64_t max_iters,
                  int64_t handoff_div, int32_t chunk_opt, bool want_trace, bool time_kernels, bool cull,
-                 const Csr *csr, hipStream_t st)
+                 const Csr *csr, int rows_override, int64_t slices_override, hipStream_t st)
 {
     LoopOut o;
     const int64_t n = gh.g.n;
     // on the candidate graph the step is one fused kernel and needs no partials
-    const ScanShape sh = csr ? ScanShape{1, 1, ((n + kTileCols - 1) / kTileCols) * kTileCols} : scan_shape(n, cull);
+    const ScanShape sh = csr ? ScanShape{1, 1, ((n + kTileCols - 1) / kTileCols) * kTileCols}
+                             : scan_shape(n, cull, rows_override, slices_override);
     float4 *col = gh.col;
     int64_t *lam[2] = {grow<int64_t>(ctx, ctx->lam[0], n), grow<int64_t>(ctx, ctx->lam[1], n)};
     int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
@@ -901,6 +917,9 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         const bool on_graph = o.graph == F2M_GRAPH_KNN;
         if (o.max_iters < 0) fail(ctx, F2M_ERR_ARG, "max_iters < 0");
         if (o.handoff_div < 0) fail(ctx, F2M_ERR_ARG, "handoff_div < 0");
+        if (o.scan_rows != 0 && o.scan_rows != 1 && o.scan_rows != 2 && o.scan_rows != 4)
+            fail(ctx, F2M_ERR_ARG, "scan_rows must be 0, 1, 2 or 4");
+        if (o.scan_slices < 0) fail(ctx, F2M_ERR_ARG, "scan_slices < 0");
         if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
         if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER) fail(ctx, F2M_ERR_ARG, "unknown warm mode");
         if (n < 3) fail(ctx, F2M_ERR_INFEASIBLE, "F2M needs n >= 3");
@@ -951,7 +970,8 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         }
         const double t1 = now_s();
         LoopOut lo = gdp_loop(ctx, gh, lam0_dev, o.max_iters, o.handoff_div, o.chunk, o.record_trace != 0,
-                              o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, on_graph ? &csr : nullptr, st);
+                              o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, on_graph ? &csr : nullptr,
+                              o.scan_rows, o.scan_slices, st);
         const double t2 = now_s();
         InstanceState is{gh, lo.c, lo.lam_star, static_cast<const int64_t *>(ctx->z4.p),
                          static_cast<const int32_t *>(ctx->i4.p), static_cast<const int32_t *>(ctx->seed.p),
@@ -1042,7 +1062,8 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             // one row per lane for the whole launch; the batch itself fills
             // the GPU, so culled scans take one slice and full scans a few
             shp[i].rows = 1;
-            const int64_t sl = cull ? 1 : std::min<int64_t>(nt, 4);
+            const int64_t sl = o.scan_slices > 0 ? std::min<int64_t>(nt, o.scan_slices)
+                                                 : (cull ? 1 : std::min<int64_t>(nt, 4));
             shp[i].slice_len = ((nt + sl - 1) / sl) * kTileCols;
             shp[i].slices = (n + shp[i].slice_len - 1) / shp[i].slice_len;
             P[i + 1] = P[i] + nt * kTileCols;
@@ -1108,7 +1129,12 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         std::vector<UpdateArgs> ua(n_inst);
         std::vector<BatchScanItem> sitems;
         std::vector<BatchTileItem> uitems;
-        for (int32_t i : active) {
+        // longest processing time first: larger instances' blocks launch first
+        std::vector<int> order(active);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+        });
+        for (int32_t i : order) {
             const int64_t n = offsets[i + 1] - offsets[i], X = offsets[i];
             const Geo g{n, orig + P[i], pos + X, box + T[i], x2h[i]};
             ScanArgs &a = sa[i];

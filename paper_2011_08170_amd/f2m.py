@@ -41,7 +41,7 @@ class Opts(C.Structure):
                 ("handoff_div", C.c_int64),
                 ("finish", C.c_int32), ("coords_on_device", C.c_int32), ("record_trace", C.c_int32),
                 ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("scan_mode", C.c_int32),
-                ("hip_stream", C.c_void_p)]
+                ("scan_rows", C.c_int32), ("scan_slices", C.c_int32), ("hip_stream", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -168,7 +168,8 @@ class Context:
         return st
 
     def solve(self, coords, *, max_iters=100000, handoff_div=300, finish="exact", lambda2_init=None,
-              trace=False, chunk=0, stream=None, time_kernels=False, scan="culled", graph="complete", knn_k=10):
+              trace=False, chunk=0, stream=None, time_kernels=False, scan="culled", graph="complete", knn_k=10,
+              shape=None):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
         array on the host or a contiguous int32 device tensor."""
         o = Opts()
@@ -182,6 +183,8 @@ class Context:
         o.scan_mode = SCAN[scan]
         o.graph = GRAPH[graph]
         o.knn_k = int(knn_k)
+        if shape is not None:
+            o.scan_rows, o.scan_slices = int(shape[0]), int(shape[1])
         keep = []
         if lambda2_init is not None:
             l0 = _np(lambda2_init, np.int64)
@@ -207,7 +210,7 @@ class Context:
             lib().f2m_result_free(C.byref(res))
 
     def solve_batch(self, coords, offsets, *, max_iters=100000, handoff_div=300, finish="exact", trace=False,
-                    chunk=0, scan="culled", lambda2_init=None):
+                    chunk=0, scan="culled", lambda2_init=None, slices=0):
         """Solves many instances in one batched loop.  coords: int32 (sum n, 2)
         on the host; offsets: int64 (n_inst + 1).  Returns (status, [dict])."""
         o = Opts()
@@ -218,6 +221,7 @@ class Context:
         o.record_trace = 1 if trace else 0
         o.chunk = int(chunk)
         o.scan_mode = SCAN[scan]
+        o.scan_slices = int(slices)
         xy = _np(coords, np.int32)
         off = _np(offsets, np.int64)
         keep = [xy, off]
