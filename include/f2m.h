@@ -71,7 +71,10 @@ typedef enum f2m_status {
  * symmetrised; the GDP, the finish and the certificate run on that graph,
  * and the result is also checked against the complete graph. */
 enum { F2M_GRAPH_COMPLETE = 0, F2M_GRAPH_KNN = 1 };
-enum { F2M_WARM_COLD = 0, F2M_WARM_USER = 1 };
+/* F2M_WARM_MLP: Lam_0 from the warm-start network (see f2m_mlp_forward),
+ * parameters in opts.mlp_theta; the GDP, the finish and the certificate
+ * are unchanged, so the certified optimum equals the cold start's. */
+enum { F2M_WARM_COLD = 0, F2M_WARM_USER = 1, F2M_WARM_MLP = 2 };
 enum { F2M_FINISH_NONE = 0, F2M_FINISH_EXACT = 1 };
 /* Scan over the complete graph: F2M_SCAN_CULLED skips column tiles whose
  * bounding box is provably too far for any pair to matter (exact: same
@@ -94,6 +97,7 @@ typedef struct f2m_opts {
     int32_t knn_k;                /* neighbours per node for F2M_GRAPH_KNN: 10 or 16 */
     int32_t warm;                 /* F2M_WARM_COLD (Lam0 = 0) or F2M_WARM_USER */
     const int64_t *lambda2_init;  /* host, n entries, read when warm == USER */
+    const float *mlp_theta;       /* device, F2M_MLP_PARAMS floats, read when warm == MLP */
     int64_t max_iters;            /* iteration cap (>= 0) */
     int64_t handoff_div;          /* hand-off stop (see above); 0 disables it */
     int32_t finish;               /* F2M_FINISH_EXACT: make the result exact
@@ -214,6 +218,30 @@ f2m_status f2m_certify(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
  *   the entry count.  F2M_ERR_CAPACITY (nnz set) when cap < nnz. */
 f2m_status f2m_knn_graph(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n, int32_t k,
                          int32_t *rowptr, int32_t *col, int64_t cap, int64_t *nnz);
+
+/* Warm-start network (not in the paper): per node v the features
+ * x_v = (d_1, ..., d_16) / s, d_j the distance to the j-th nearest
+ * neighbour (by squared distance, then index) and s the median of all
+ * n*16 such distances; an MLP 16 -> 128 -> 128 -> 1 with ReLU, BF16
+ * operands on the matrix cores and FP32 accumulation, predicts
+ * y_v ~ lambda_v / s; Lam_0,v = round-half-even(2 s y_v).
+ * Parameters: FP32 vector of F2M_MLP_PARAMS entries, in this order:
+ * W1[128][16], b1[128], W2[128][128], b2[128], w3[128], b3. */
+#define F2M_MLP_PARAMS 18817
+
+/* coords_xy device int32[2n], n >= 17; feat device uint16[16n] (bf16,
+ * row v = label v); *scale (host) receives s. */
+f2m_status f2m_features(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n, uint16_t *feat, float *scale);
+/* theta, feat, y device arrays; y[v] = network output for row v. */
+f2m_status f2m_mlp_forward(f2m_ctx *ctx, const float *theta, const uint16_t *feat, int64_t n, float *y);
+/* Gradient of the mean squared error mean_v (y_v - target_v)^2 over the n
+ * rows: grad (device, F2M_MLP_PARAMS floats), *loss (host). */
+f2m_status f2m_mlp_grad(f2m_ctx *ctx, const float *theta, const uint16_t *feat, const float *target, int64_t n,
+                        float *grad, double *loss);
+/* One AdamW step (beta1 0.9, beta2 0.999, eps 1e-8, decoupled decay wd)
+ * on device arrays of F2M_MLP_PARAMS floats; step counts from 1. */
+f2m_status f2m_mlp_adamw(f2m_ctx *ctx, float *theta, const float *grad, float *m, float *v, int64_t step, float lr,
+                         float wd);
 
 void f2m_result_free(f2m_result *res);
 const char *f2m_status_str(f2m_status s);

@@ -19,7 +19,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I", os.
           "-I", CSRC]
 # device code: gfx950 only; no packed fp32 instructions
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("f2m_kernels.hip", True), ("f2m_api.cpp", False), ("f2m_finish.cpp", False)]
+SOURCES = [("f2m_kernels.hip", True), ("f2m_mlp.hip", True), ("f2m_api.cpp", False), ("f2m_finish.cpp", False)]
 
 
 def _compile(src, device):
@@ -33,7 +33,7 @@ def _compile(src, device):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=3) as ex:
+    with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(lambda s: _compile(*s), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs

@@ -4,6 +4,7 @@
 #include "f2m.h"
 #include "f2m_finish.h"
 #include "f2m_internal.h"
+#include "f2m_mlp.h"
 
 #include <algorithm>
 #include <chrono>
@@ -41,6 +42,9 @@ struct f2m_ctx {
     DevBuf p_pairs, p_count;
     // candidate graph
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
+    // warm-start network
+    DevBuf m_nbr, m_nbrd, m_sorted, m_temp, m_scale, m_feat, m_w1b, m_w2b, m_z1, m_h1b, m_z2, m_h2, m_y, m_dy, m_g2b,
+        m_g2f, m_pre1, m_g1b, m_g1f, m_sq, m_part, m_lam0;
     // batched solve pools
     DevBuf b_xy, b_orig, b_pos, b_col, b_box, b_x2m, b_lam0, b_lam1, b_best, b_lamlabel, b_thm, b_pz, b_pi, b_pneg,
         b_pzero, b_prn, b_z4, b_i4, b_seed, b_ctrl, b_trace, b_sargs, b_uargs, b_sitems, b_uitems, b_nblk, b_active;
@@ -57,7 +61,9 @@ struct f2m_ctx {
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
                          &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
-                         &b_sargs, &b_uargs, &b_sitems, &b_uitems, &b_nblk, &b_active};
+                         &b_sargs, &b_uargs, &b_sitems, &b_uitems, &b_nblk, &b_active, &m_nbr, &m_nbrd, &m_sorted,
+                         &m_temp, &m_scale, &m_feat, &m_w1b, &m_w2b, &m_z1, &m_h1b, &m_z2, &m_h2, &m_y, &m_dy, &m_g2b,
+                         &m_g2f, &m_pre1, &m_g1b, &m_g1f, &m_sq, &m_part, &m_lam0};
         bufs.assign(std::begin(all), std::end(all));
     }
 };
@@ -582,6 +588,97 @@ f2m_status solve_n3(f2m_ctx *ctx, const int32_t *xy, f2m_result *out)
     return F2M_OK;
 }
 
+// Features of every node (by label) and the scale, on device.
+void features_dev(f2m_ctx *ctx, const GeoHost &gh, uint16_t *feat, float *scale_dev, hipStream_t st)
+{
+    const int64_t n = gh.g.n;
+    if (n < kMlpIn + 1) fail(ctx, F2M_ERR_ARG, "features need n >= 17");
+    int32_t *nbr = grow<int32_t>(ctx, ctx->m_nbr, n * kMlpIn);
+    int64_t *nbrd = grow<int64_t>(ctx, ctx->m_nbrd, n * kMlpIn);
+    uint64_t *sorted = grow<uint64_t>(ctx, ctx->m_sorted, n * kMlpIn);
+    const size_t tb = median_temp_bytes(n * kMlpIn);
+    void *temp = grow<char>(ctx, ctx->m_temp, tb);
+    ck(ctx, launch_knn(gh.g, gh.col, kMlpIn, nbr, nbrd, st), "knn16");
+    ck(ctx, launch_features(nbrd, gh.g.orig, n, sorted, temp, tb, scale_dev, feat, st), "features");
+}
+
+// Network forward over n rows; keeps h1 (bf16) and h2 (fp32) in the
+// workspace for a following backward pass.
+void mlp_forward_dev(f2m_ctx *ctx, const float *theta, const uint16_t *feat, int64_t n, float *y, hipStream_t st)
+{
+    uint16_t *w1b = grow<uint16_t>(ctx, ctx->m_w1b, kMlpH * kMlpIn);
+    uint16_t *w2b = grow<uint16_t>(ctx, ctx->m_w2b, kMlpH * kMlpH);
+    float *z1 = grow<float>(ctx, ctx->m_z1, n * kMlpH);
+    uint16_t *h1b = grow<uint16_t>(ctx, ctx->m_h1b, n * kMlpH);
+    float *z2 = grow<float>(ctx, ctx->m_z2, n * kMlpH);
+    float *h2 = grow<float>(ctx, ctx->m_h2, n * kMlpH);
+    ck(ctx, launch_to_bf16(theta + kMlpW1, kMlpH * kMlpIn, w1b, st), "bf16");
+    ck(ctx, launch_to_bf16(theta + kMlpW2, kMlpH * kMlpH, w2b, st), "bf16");
+    // z1 = x W1^T, h1 = relu(z1 + b1)
+    ck(ctx, launch_gemm_bf16(GemmArgs{feat, w1b, z1, n, kMlpH, kMlpIn, kMlpIn, kMlpIn, 1, 1, kMlpIn}, st), "gemm1");
+    ck(ctx, launch_bias_relu(z1, theta + kMlpB1, n, kMlpH, h1b, nullptr, st), "relu1");
+    // z2 = h1 W2^T, y = relu(z2 + b2) . w3 + b3
+    ck(ctx, launch_gemm_bf16(GemmArgs{h1b, w2b, z2, n, kMlpH, kMlpH, kMlpH, kMlpH, 1, 1, kMlpH}, st), "gemm2");
+    ck(ctx, launch_out(z2, theta, n, y, h2, st), "out");
+}
+
+// MSE gradient over n rows (forward included); loss to the host.
+void mlp_grad_dev(f2m_ctx *ctx, const float *theta, const uint16_t *feat, const float *target, int64_t n, float *grad,
+                  double *loss, hipStream_t st)
+{
+    float *y = grow<float>(ctx, ctx->m_y, n);
+    mlp_forward_dev(ctx, theta, feat, n, y, st);
+    const uint16_t *w2b = static_cast<const uint16_t *>(ctx->m_w2b.p);
+    const uint16_t *h1b = static_cast<const uint16_t *>(ctx->m_h1b.p);
+    const float *h2 = static_cast<const float *>(ctx->m_h2.p);
+    float *dy = grow<float>(ctx, ctx->m_dy, n);
+    uint16_t *g2b = grow<uint16_t>(ctx, ctx->m_g2b, n * kMlpH);
+    float *g2f = grow<float>(ctx, ctx->m_g2f, n * kMlpH);
+    float *pre1 = grow<float>(ctx, ctx->m_pre1, n * kMlpH);
+    uint16_t *g1b = grow<uint16_t>(ctx, ctx->m_g1b, n * kMlpH);
+    float *g1f = grow<float>(ctx, ctx->m_g1f, n * kMlpH);
+    float *sq = grow<float>(ctx, ctx->m_sq, n);
+    const int64_t kchunk = 4096;
+    const int64_t chunks = (n + kchunk - 1) / kchunk;
+    const int64_t nparts = std::max<int64_t>(1, std::min<int64_t>(256, (n + 255) / 256));
+    float *part = grow<float>(ctx, ctx->m_part, std::max<int64_t>(chunks * kMlpH * kMlpH, nparts * kMlpH));
+    ck(ctx, launch_out_grad(y, target, h2, theta, n, 1.0f / (float)n, dy, g2b, g2f, sq, st), "out_grad");
+    ck(ctx, launch_col_sums(h2, dy, n, kMlpH, part, grad + kMlpW3, nparts, st), "dw3");
+    ck(ctx, launch_col_sums(dy, nullptr, n, 1, part, grad + kMlpB3, nparts, st), "db3");
+    ck(ctx, launch_col_sums(g2f, nullptr, n, kMlpH, part, grad + kMlpB2, nparts, st), "db2");
+    // dW2[j][i] = sum_v g2[v][j] h1[v][i]
+    ck(ctx, launch_gemm_bf16(GemmArgs{g2b, h1b, part, kMlpH, kMlpH, n, kchunk, 1, kMlpH, kMlpH, 1}, st), "dW2");
+    ck(ctx, launch_sum_chunks(part, chunks, kMlpH * kMlpH, grad + kMlpW2, st), "dW2 sum");
+    // g1 = (g2 W2) * [h1 > 0]
+    ck(ctx, launch_gemm_bf16(GemmArgs{g2b, w2b, pre1, n, kMlpH, kMlpH, kMlpH, kMlpH, 1, kMlpH, 1}, st), "g1");
+    ck(ctx, launch_mask_bf16(pre1, h1b, n * kMlpH, g1b, g1f, st), "mask1");
+    ck(ctx, launch_col_sums(g1f, nullptr, n, kMlpH, part, grad + kMlpB1, nparts, st), "db1");
+    // dW1[j][f] = sum_v g1[v][j] x[v][f]
+    ck(ctx, launch_gemm_bf16(GemmArgs{g1b, feat, part, kMlpH, kMlpIn, n, kchunk, 1, kMlpH, kMlpIn, 1}, st), "dW1");
+    ck(ctx, launch_sum_chunks(part, chunks, kMlpH * kMlpIn, grad + kMlpW1, st), "dW1 sum");
+    float *ls = y;   // y is no longer needed: reuse for the loss sum
+    ck(ctx, launch_col_sums(sq, nullptr, n, 1, part, ls, nparts, st), "loss");
+    float lh = 0.0f;
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, ls, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    std::memcpy(&lh, ctx->scratch_host, sizeof(float));
+    *loss = (double)lh / (double)n;
+}
+
+// Lam_0 by label from the network (features, forward, rounding).
+const int64_t *mlp_lam0_dev(f2m_ctx *ctx, const GeoHost &gh, const float *theta, hipStream_t st)
+{
+    const int64_t n = gh.g.n;
+    uint16_t *feat = grow<uint16_t>(ctx, ctx->m_feat, n * kMlpIn);
+    float *scale = grow<float>(ctx, ctx->m_scale, 1);
+    float *y = grow<float>(ctx, ctx->m_y, n);
+    int64_t *lam0 = grow<int64_t>(ctx, ctx->m_lam0, n);
+    features_dev(ctx, gh, feat, scale, st);
+    mlp_forward_dev(ctx, theta, feat, n, y, st);
+    ck(ctx, launch_lam_from_pred(y, scale, n, kLamLimit / 2, lam0, st), "lam0");
+    return lam0;
+}
+
 // Everything after the GDP loop for one instance: Lam* by label, the
 // trivial x or the exact finish, the certificate(s) and the host copies.
 struct InstanceState {
@@ -856,6 +953,67 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
     }
 }
 
+#define F2M_GUARD_BEGIN \
+    if (!ctx) return F2M_ERR_ARG; \
+    try {
+#define F2M_GUARD_END \
+    } catch (const Fail &f) { \
+        return f.st; \
+    } catch (const std::bad_alloc &) { \
+        ctx->err = "host allocation failed"; \
+        return F2M_ERR_NOMEM; \
+    }
+
+f2m_status f2m_features(f2m_ctx *ctx, const int32_t *xy, int64_t n, uint16_t *feat, float *scale)
+{
+    F2M_GUARD_BEGIN
+    if (!xy || !feat || !scale) fail(ctx, F2M_ERR_ARG, "features need coords, feat and scale");
+    ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = ctx->stream;
+    const GeoHost gh = setup_geo(ctx, xy, n, st);
+    float *sd = grow<float>(ctx, ctx->m_scale, 1);
+    features_dev(ctx, gh, feat, sd, st);
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, sd, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    std::memcpy(scale, ctx->scratch_host, sizeof(float));
+    return F2M_OK;
+    F2M_GUARD_END
+}
+
+f2m_status f2m_mlp_forward(f2m_ctx *ctx, const float *theta, const uint16_t *feat, int64_t n, float *y)
+{
+    F2M_GUARD_BEGIN
+    if (!theta || !feat || !y || n < 1) fail(ctx, F2M_ERR_ARG, "mlp_forward needs theta, feat, y and n >= 1");
+    ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    mlp_forward_dev(ctx, theta, feat, n, y, ctx->stream);
+    ck(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    return F2M_OK;
+    F2M_GUARD_END
+}
+
+f2m_status f2m_mlp_grad(f2m_ctx *ctx, const float *theta, const uint16_t *feat, const float *target, int64_t n,
+                        float *grad, double *loss)
+{
+    F2M_GUARD_BEGIN
+    if (!theta || !feat || !target || !grad || !loss || n < 1) fail(ctx, F2M_ERR_ARG, "mlp_grad needs every array");
+    ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    mlp_grad_dev(ctx, theta, feat, target, n, grad, loss, ctx->stream);
+    return F2M_OK;
+    F2M_GUARD_END
+}
+
+f2m_status f2m_mlp_adamw(f2m_ctx *ctx, float *theta, const float *grad, float *m, float *v, int64_t step, float lr,
+                         float wd)
+{
+    F2M_GUARD_BEGIN
+    if (!theta || !grad || !m || !v || step < 1) fail(ctx, F2M_ERR_ARG, "mlp_adamw needs every array and step >= 1");
+    ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    ck(ctx, launch_adamw(theta, grad, m, v, kMlpParams, lr, 0.9f, 0.999f, 1e-8f, wd, step, ctx->stream), "adamw");
+    ck(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    return F2M_OK;
+    F2M_GUARD_END
+}
+
 f2m_status f2m_knn_graph(f2m_ctx *ctx, const int32_t *xy, int64_t n, int32_t k, int32_t *rowptr, int32_t *col,
                          int64_t cap, int64_t *nnz)
 {
@@ -921,7 +1079,9 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             fail(ctx, F2M_ERR_ARG, "scan_rows must be 0, 1, 2 or 4");
         if (o.scan_slices < 0) fail(ctx, F2M_ERR_ARG, "scan_slices < 0");
         if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
-        if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER) fail(ctx, F2M_ERR_ARG, "unknown warm mode");
+        if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER && o.warm != F2M_WARM_MLP)
+            fail(ctx, F2M_ERR_ARG, "unknown warm mode");
+        if (o.warm == F2M_WARM_MLP && !o.mlp_theta) fail(ctx, F2M_ERR_ARG, "warm start without mlp_theta");
         if (n < 3) fail(ctx, F2M_ERR_INFEASIBLE, "F2M needs n >= 3");
         if (n >= (int64_t)1 << 30) fail(ctx, F2M_ERR_ARG, "n must be below 2^30");
         ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
@@ -968,7 +1128,13 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             csr = build_graph(ctx, gh, o.knn_k, st);
             res.graph_nnz = csr.nnz;
         }
+        const double tw = now_s();
+        if (o.warm == F2M_WARM_MLP) {
+            lam0_dev = mlp_lam0_dev(ctx, gh, o.mlp_theta, st);
+            ck(ctx, hipStreamSynchronize(st), "sync");
+        }
         const double t1 = now_s();
+        res.seconds[1] = t1 - tw;
         LoopOut lo = gdp_loop(ctx, gh, lam0_dev, o.max_iters, o.handoff_div, o.chunk, o.record_trace != 0,
                               o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, on_graph ? &csr : nullptr,
                               o.scan_rows, o.scan_slices, st);
@@ -982,7 +1148,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         res.scan_launches = lo.scan_launches;
         res.scan_rows = lo.shape.rows;
         res.scan_slices = lo.shape.slices;
-        res.seconds[0] = t1 - t0;
+        res.seconds[0] = tw - t0;
         res.seconds[2] = t2 - t1;
         res.seconds[5] = now_s() - t0;
         *out = res;

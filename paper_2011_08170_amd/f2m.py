@@ -25,7 +25,10 @@ SCAN = {"culled": 0, "full": 1}
 TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
 SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
-           "f2m_knn_graph", "f2m_solve_batch", "f2m_result_free", "f2m_status_str", "f2m_last_error")
+           "f2m_knn_graph", "f2m_solve_batch", "f2m_features", "f2m_mlp_forward", "f2m_mlp_grad", "f2m_mlp_adamw",
+           "f2m_result_free", "f2m_status_str", "f2m_last_error")
+MLP_PARAMS = 18817
+WARM = {"cold": 0, "user": 1, "mlp": 2}
 GRAPH = {"complete": 0, "knn": 1}
 
 
@@ -37,7 +40,8 @@ class F2MError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("rule_version", C.c_uint32), ("graph", C.c_int32),
-                ("knn_k", C.c_int32), ("warm", C.c_int32), ("lambda2_init", C.c_void_p), ("max_iters", C.c_int64),
+                ("knn_k", C.c_int32), ("warm", C.c_int32), ("lambda2_init", C.c_void_p), ("mlp_theta", C.c_void_p),
+                ("max_iters", C.c_int64),
                 ("handoff_div", C.c_int64),
                 ("finish", C.c_int32), ("coords_on_device", C.c_int32), ("record_trace", C.c_int32),
                 ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("scan_mode", C.c_int32),
@@ -82,6 +86,14 @@ def lib():
         L.f2m_gdp_step.argtypes = [p, p, i64, p, p, p, p, p, p, p, p]
         L.f2m_certify.restype = C.c_int
         L.f2m_certify.argtypes = [p, p, i64, p, i64, p, p, p, p]
+        L.f2m_features.restype = C.c_int
+        L.f2m_features.argtypes = [p, p, i64, p, C.POINTER(C.c_float)]
+        L.f2m_mlp_forward.restype = C.c_int
+        L.f2m_mlp_forward.argtypes = [p, p, p, i64, p]
+        L.f2m_mlp_grad.restype = C.c_int
+        L.f2m_mlp_grad.argtypes = [p, p, p, p, i64, p, C.POINTER(C.c_double)]
+        L.f2m_mlp_adamw.restype = C.c_int
+        L.f2m_mlp_adamw.argtypes = [p, p, p, p, p, i64, C.c_float, C.c_float]
         L.f2m_solve_batch.restype = C.c_int
         L.f2m_solve_batch.argtypes = [p, p, p, C.c_int32, C.POINTER(Opts), p]
         L.f2m_knn_graph.restype = C.c_int
@@ -169,7 +181,7 @@ class Context:
 
     def solve(self, coords, *, max_iters=100000, handoff_div=300, finish="exact", lambda2_init=None,
               trace=False, chunk=0, stream=None, time_kernels=False, scan="culled", graph="complete", knn_k=10,
-              shape=None):
+              shape=None, mlp_theta=None):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
         array on the host or a contiguous int32 device tensor."""
         o = Opts()
@@ -193,6 +205,9 @@ class Context:
             o.lambda2_init = l0.ctypes.data
         if stream is not None:
             o.hip_stream = stream
+        if mlp_theta is not None:
+            o.warm = WARM["mlp"]
+            o.mlp_theta = _dptr(mlp_theta)
         if hasattr(coords, "is_cuda") and coords.is_cuda:
             o.coords_on_device = 1
             n = coords.shape[0]
@@ -253,6 +268,26 @@ class Context:
         r = dict(zip(TRACE_FIELDS, (int(x) for x in rec)))
         r["hash"] &= (1 << 64) - 1
         return r
+
+    def features(self, coords, feat):
+        """Warm-start features into feat (uint16 bf16 [n, 16] device tensor,
+        viewed as int16 in torch); returns the scale."""
+        sc = C.c_float(0.0)
+        self._check(lib().f2m_features(self._h, _dptr(coords), coords.shape[0], _dptr(feat), C.byref(sc)))
+        return sc.value
+
+    def mlp_forward(self, theta, feat, y):
+        self._check(lib().f2m_mlp_forward(self._h, _dptr(theta), _dptr(feat), y.shape[0], _dptr(y)))
+
+    def mlp_grad(self, theta, feat, target, grad):
+        loss = C.c_double(0.0)
+        self._check(lib().f2m_mlp_grad(self._h, _dptr(theta), _dptr(feat), _dptr(target), target.shape[0],
+                                       _dptr(grad), C.byref(loss)))
+        return loss.value
+
+    def mlp_adamw(self, theta, grad, m, v, step, lr, wd=0.0):
+        self._check(lib().f2m_mlp_adamw(self._h, _dptr(theta), _dptr(grad), _dptr(m), _dptr(v), int(step),
+                                        float(lr), float(wd)))
 
     def certify(self, coords, lam, eu, ev, ex2):
         """Certificate on device tensors: dict(primal2, dual2, feasible, certified)."""
