@@ -841,6 +841,12 @@ __global__ __launch_bounds__(kBlock) void k_graph_membership(Geo g, Csr csr, int
     if (lo >= csr.rowptr[pu + 1] || csr.col[lo] != pv) atomicAdd(&acc[2], 1ULL);
 }
 
+__global__ __launch_bounds__(kBlock) void k_pair_to_key(const int2 *pairs, int64_t count, uint64_t *keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) keys[i] = ((uint64_t)(uint32_t)pairs[i].x << 32) | (uint64_t)(uint32_t)pairs[i].y;
+}
+
 __global__ __launch_bounds__(kBlock) void k_label_degrees(Geo g, Csr csr, int32_t *deg)
 {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1324,6 +1330,29 @@ hipError_t launch_build_csr(const Geo &g, const int32_t *xy, int64_t n, int K, c
     hipLaunchKernelGGL(k_row_finish, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, xy, g.orig, n, rowptr, col,
                        cost);
     return hipGetLastError();
+}
+
+size_t pair_sort_temp_bytes(int64_t count)
+{
+    size_t a = 0, b = 0;
+    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr, (int)count, 0,
+                                            64);
+    (void)hipcub::DeviceSelect::Unique(nullptr, b, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                       (int64_t *)nullptr, (int)count);
+    return a > b ? a : b;
+}
+
+hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *keys, uint64_t *keys_sorted,
+                                    uint64_t *keys_out, int64_t *count_dev, void *temp, size_t temp_bytes,
+                                    hipStream_t st)
+{
+    if (count <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int64_t), st);
+    hipLaunchKernelGGL(k_pair_to_key, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, pairs, count, keys);
+    size_t tb = temp_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, tb, keys, keys_sorted, (int)count, 0, 64, st);
+    if (e != hipSuccess) return e;
+    tb = temp_bytes;
+    return hipcub::DeviceSelect::Unique(temp, tb, keys_sorted, keys_out, count_dev, (int)count, st);
 }
 
 hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_sorted, unsigned long long *acc,
