@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--scan", choices=("culled", "full"), default="culled",
                     help="culled: skip column tiles that provably hold no relevant pair (default); "
                          "full: test every ordered pair")
+    ap.add_argument("--start", choices=("both", "cold"), default="both",
+                    help="both: time the cold start, then the learned warm start (when trained weights exist)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -113,58 +115,96 @@ def main():
     torch.cuda.synchronize()
     log("workload: n=%d %s [0,1e6)^2 seed=%d graph=%s; warmup %d, steps %d" % (
         n, args.instance, args.seed, args.graph, args.warmup, args.steps))
-    for i in range(args.warmup):
-        r = ctx.solve(xy_dev, scan=args.scan, graph=args.graph)
-        log("warmup %d: %s, %d iterations, %.3f s" % (i, r["status"], r["iterations"], r["seconds"]["total"]))
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    runs = []
-    for i in range(args.steps):
-        r = ctx.solve(xy_dev, time_kernels=True, scan=args.scan, graph=args.graph)
-        runs.append(r)
-        log("step %d: %s stop=%s iterations=%d total=%.3f s (gdp %.3f, finish %.3f, certify %.3f)" % (
-            i, r["status"], r["stop"], r["iterations"], r["seconds"]["total"], r["seconds"]["gdp"],
-            r["seconds"]["finish"], r["seconds"]["certify"]))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    theta = None
+    if args.start == "both":
+        from paper_2011_08170_amd import warm
+        if os.path.exists(warm.DEFAULT_WEIGHTS):
+            theta = warm.load()
+        else:
+            log("no trained warm-start weights at %s: cold start only" % warm.DEFAULT_WEIGHTS)
 
-    pairs = n * (n - 1) / 2
-    iters = sum(r["iterations"] for r in runs)
-    scan_ms = sum(r["scan_ms"] for r in runs)
-    launches = sum(r["scan_launches"] for r in runs)
-    avg_ms = scan_ms / max(launches, 1)
-    if args.graph == "complete":
-        # ordered pairs the scan evaluated per launch (culled tiles excluded)
-        tested = sum(r["scan_pairs"] for r in runs) / max(launches, 1)
-        ops = OPS_PER_PAIR * tested
-        achieved = ops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "k_rowscan<%d,gdp>" % runs[-1]["scan_rows"], "achieved": achieved,
-                "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
-                "pairs_tested_per_launch": tested, "ops_per_launch": ops,
-                "slices": runs[-1]["scan_slices"]}
-        value = iters * pairs / elapsed
-        unit = "pair-evals/s"
-    else:
-        nnz = runs[-1]["graph_nnz"]
-        # per row: rowptr 4, own label 4, Lam in 8, Lam out 8, top-4 Z 32 and labels 16;
-        # per entry: column 4, cost 4, Lam 8, label 4
-        nbytes = n * 72 + nnz * 20
-        achieved = nbytes / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "k_graph_step", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": achieved / 8000.0, "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
-                "bytes_per_launch": nbytes, "nnz": nnz}
-        value = iters * nnz / 2 / elapsed
-        unit = "edge-evals/s"
+    def leg(name, kw):
+        for i in range(args.warmup):
+            r = ctx.solve(xy_dev, scan=args.scan, graph=args.graph, **kw)
+            log("%s warmup %d: %s, %d iterations, %.3f s" % (name, i, r["status"], r["iterations"],
+                                                             r["seconds"]["total"]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = []
+        for i in range(args.steps):
+            r = ctx.solve(xy_dev, time_kernels=True, scan=args.scan, graph=args.graph, **kw)
+            runs.append(r)
+            log("%s step %d: %s stop=%s iterations=%d total=%.3f s (warm %.3f, gdp %.3f, finish %.3f, "
+                "certify %.3f)" % (name, i, r["status"], r["stop"], r["iterations"], r["seconds"]["total"],
+                                   r["seconds"]["warm"], r["seconds"]["gdp"], r["seconds"]["finish"],
+                                   r["seconds"]["certify"]))
+        torch.cuda.synchronize()
+        return runs, time.perf_counter() - t0
+
+    def summary(runs, elapsed):
+        pairs = n * (n - 1) / 2
+        iters = sum(r["iterations"] for r in runs)
+        scan_ms = sum(r["scan_ms"] for r in runs)
+        launches = sum(r["scan_launches"] for r in runs)
+        avg_ms = scan_ms / max(launches, 1)
+        if args.graph == "complete":
+            # ordered pairs the scan evaluated per launch (culled tiles excluded)
+            tested = sum(r["scan_pairs"] for r in runs) / max(launches, 1)
+            ops = OPS_PER_PAIR * tested
+            achieved = ops / (avg_ms * 1e-3) / 1e12
+            roof = {"bound": "alu", "kernel": "k_rowscan<%d,gdp>" % runs[-1]["scan_rows"], "achieved": achieved,
+                    "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                    "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
+                    "pairs_tested_per_launch": tested, "ops_per_launch": ops,
+                    "slices": runs[-1]["scan_slices"]}
+            value = iters * pairs / elapsed
+        else:
+            nnz = runs[-1]["graph_nnz"]
+            # per row: rowptr 4, own label 4, Lam in 8, Lam out 8, top-4 Z 32 and labels 16;
+            # per entry: column 4, cost 4, Lam 8, label 4
+            nbytes = n * 72 + nnz * 20
+            achieved = nbytes / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "kernel": "k_graph_step", "achieved": achieved, "peak": 8000.0,
+                    "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None, "avg_launch_ms": avg_ms,
+                    "launches": launches, "bytes_per_launch": nbytes, "nnz": nnz}
+            value = iters * nnz / 2 / elapsed
+        out = {
+            "value": value,
+            "ms_per_step": 1e3 * elapsed / len(runs),
+            "time_to_certified_s": elapsed / len(runs),
+            "certified": all(r["certified"] for r in runs),
+            "certified_complete": all(r["certified_complete"] for r in runs),
+            "iterations": [r["iterations"] for r in runs],
+            "stop": [r["stop"] for r in runs],
+            "objective2": runs[-1]["primal2"],
+            "phase_s": {k: float(np.mean([r["seconds"][k] for r in runs]))
+                        for k in ("setup", "warm", "gdp", "finish", "certify")},
+            "finish_detail": {"seconds": {k: float(np.mean([r["finish_seconds"][k] for r in runs]))
+                                          for k in ("collect", "build", "flow")},
+                              "paths": runs[-1]["finish_paths"], "phases": runs[-1]["finish_phases"],
+                              "rounds": runs[-1]["finish_rounds"], "candidates": runs[-1]["finish_candidates"]},
+            "roofline": roof,
+        }
+        if args.graph == "complete":
+            out["scan_pair_evals_per_s"] = pairs / (avg_ms * 1e-3)
+        return out
+
+    cold_runs, cold_s = leg("cold", {})
+    cold = summary(cold_runs, cold_s)
+    warm_out = None
+    if theta is not None:
+        warm_out = summary(*leg("warm", {"mlp_theta": theta}))
+        warm_out["same_objective"] = warm_out["objective2"] == cold["objective2"]
+        warm_out["speedup_time_to_certified"] = cold["time_to_certified_s"] / warm_out["time_to_certified_s"]
     out = {
         "metric": METRIC,
-        "value": value,
-        "unit": unit,
+        "value": cold["value"],
+        "unit": "pair-evals/s" if args.graph == "complete" else "edge-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": cold["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -174,25 +214,13 @@ def main():
                        args.graph, n, args.instance, args.seed,
                        "%s scan" % args.scan if args.graph == "complete" else "k=10"),
                    "n": n, "instance": args.instance, "graph": args.graph, "start": "cold", "scan": args.scan},
-        "time_to_certified_s": elapsed / args.steps,
-        "certified": all(r["certified"] for r in runs),
-        "certified_complete": all(r["certified_complete"] for r in runs),
-        "iterations": [r["iterations"] for r in runs],
-        "stop": [r["stop"] for r in runs],
-        "objective2": runs[-1]["primal2"],
-        "phase_s": {k: float(np.mean([r["seconds"][k] for r in runs])) for k in ("setup", "gdp", "finish", "certify")},
-        "finish_detail": {"seconds": {k: float(np.mean([r["finish_seconds"][k] for r in runs]))
-                                      for k in ("collect", "build", "flow")},
-                          "paths": runs[-1]["finish_paths"], "phases": runs[-1]["finish_phases"],
-                          "rounds": runs[-1]["finish_rounds"], "candidates": runs[-1]["finish_candidates"]},
-        "roofline": roof,
     }
-    if args.graph == "complete":
-        out["scan_pair_evals_per_s"] = pairs / (avg_ms * 1e-3)
+    out.update({k: v for k, v in cold.items() if k not in ("value", "ms_per_step")})
+    out["warm"] = warm_out
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(xy, runs[-1]["lambda2_gdp"], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(xy, cold_runs[-1]["lambda2_gdp"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

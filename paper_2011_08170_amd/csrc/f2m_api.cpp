@@ -214,7 +214,7 @@ GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st
     gh.cy = (int32_t)(((int64_t)h[2] + h[3]) >> 1);
     gh.xy = xy_dev;
     GeoBufs b{grow<int32_t>(ctx, ctx->orig, n), grow<int32_t>(ctx, ctx->pos, n), grow<float4>(ctx, ctx->col, n),
-              grow<float4>(ctx, ctx->box, ntiles_of(n)), grow<float>(ctx, ctx->xy2max, 1)};
+              grow<float4>(ctx, ctx->box, ntiles_of(n) * kBoxStride), grow<float>(ctx, ctx->xy2max, 1)};
     enqueue_geo(ctx, xy_dev, n, h[0], h[2], gh.cx, gh.cy, b, st);
     float x2host = 0.0f;
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, b.xy2max, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
@@ -232,7 +232,7 @@ LamView place_lam(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label_dev,
     const int64_t n = gh.g.n;
     float4 *col = grow<float4>(ctx, ctx->c_col, n);
     int64_t *ls = grow<int64_t>(ctx, ctx->c_lam, n);
-    float *th = grow<float>(ctx, ctx->c_tile_hmax, ntiles_of(n));
+    float *th = grow<float>(ctx, ctx->c_tile_hmax, ntiles_of(n) * kBoxStride);
     Ctrl *cc = grow<Ctrl>(ctx, ctx->c_ctrl, 1);
     float *x2m = grow<float>(ctx, ctx->xy2max, 1);
     ck(ctx, launch_prep(gh.xy, gh.g.orig, n, gh.cx, gh.cy, col, const_cast<float4 *>(gh.g.box), x2m, st), "prep");
@@ -485,7 +485,7 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     int64_t *lam[2] = {grow<int64_t>(ctx, ctx->lam[0], n), grow<int64_t>(ctx, ctx->lam[1], n)};
     int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
     int64_t *l0 = grow<int64_t>(ctx, ctx->lam_label, n);
-    float *thm = grow<float>(ctx, ctx->tile_hmax, ntiles_of(n));
+    float *thm = grow<float>(ctx, ctx->tile_hmax, ntiles_of(n) * kBoxStride);
     int64_t *pz = grow<int64_t>(ctx, ctx->pz, sh.slices * kTop * n);
     int32_t *pi = grow<int32_t>(ctx, ctx->pi, sh.slices * kTop * n);
     int32_t *pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
@@ -917,7 +917,7 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
         int64_t *ls = grow<int64_t>(ctx, ctx->lam[0], n);
         int64_t *lo = grow<int64_t>(ctx, ctx->lam[1], n);
         int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
-        float *thm = grow<float>(ctx, ctx->tile_hmax, ntiles_of(n));
+        float *thm = grow<float>(ctx, ctx->tile_hmax, ntiles_of(n) * kBoxStride);
         int64_t *pz = grow<int64_t>(ctx, ctx->pz, sh.slices * kTop * n);
         int32_t *pi = grow<int32_t>(ctx, ctx->pi, sh.slices * kTop * n);
         int32_t *pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
@@ -1240,7 +1240,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             shp[i].slice_len = ((nt + sl - 1) / sl) * kTileCols;
             shp[i].slices = (n + shp[i].slice_len - 1) / shp[i].slice_len;
             P[i + 1] = P[i] + nt * kTileCols;
-            T[i + 1] = T[i] + nt;
+            T[i + 1] = T[i] + nt * kBoxStride;   // box and tile-maximum slots
             PZ[i + 1] = PZ[i] + shp[i].slices * n;
             if (n >= 4) active.push_back(i);
         }

@@ -22,6 +22,12 @@ constexpr int kTraceW = 8;
 constexpr int kTop = 4;
 // Columns per LDS tile; also the alignment of row blocks and slices.
 constexpr int kTileCols = 256;
+// Tiles are cut in sub-tiles of kSubCols positions for finer culling.  The
+// per-tile arrays (boxes, maxima of h) hold kBoxStride entries per tile:
+// entry 0 covers the whole tile, entry 1 + s its sub-tile s.
+constexpr int kSubCols = 32;
+constexpr int kSubs = kTileCols / kSubCols;
+constexpr int kBoxStride = 1 + kSubs;
 
 // Device-resident control block of the GDP loop.  The update kernel's
 // last block reads the accumulators, writes the iteration record, takes
@@ -62,7 +68,7 @@ struct Geo {
     int64_t n;
     const int32_t *orig;        // position -> label
     const int32_t *pos;         // label -> position
-    const float4 *box;          // per tile: xmin, xmax, ymin, ymax (centred)
+    const float4 *box;          // per tile and sub-tile (kBoxStride per tile): xmin, xmax, ymin, ymax
     float xy2max;               // >= max over cities of x^2 + y^2 (centred)
 };
 
@@ -71,7 +77,7 @@ struct Geo {
 struct LamView {
     const float4 *col;
     const int64_t *lam;         // Lam in sorted order
-    const float *tile_hmax;     // per tile: max h
+    const float *tile_hmax;     // per tile and sub-tile (kBoxStride per tile): max h
     const Ctrl *ctrl;           // maxabs_lam (and done for the GDP loop)
 };
 
@@ -115,7 +121,7 @@ struct UpdateArgs {
     int64_t *lam_out;           // Lam_{k+1}, sorted; holds Lam_{k-1} on entry
     int64_t *lam_best;          // sorted copy of the best-dual iterate
     float4 *col;                // h, q rewritten for Lam_{k+1}
-    float *tile_hmax;           // per tile max h of Lam_{k+1}
+    float *tile_hmax;           // per tile and sub-tile max h of Lam_{k+1} (kBoxStride per tile)
     int64_t *z4;                // [4n] by label (4v + j)
     int32_t *i4;                // [4n] by label, entries are labels
     int32_t *seed;              // [j][n] positions of the top-4, for the next scan

@@ -36,6 +36,8 @@ namespace f2m {
 constexpr int kBlock = 256;   // threads per workgroup (4 waves of 64)
 constexpr int kTile = kTileCols;   // columns staged in LDS per tile
 constexpr int kGroup = 8;     // columns per filter test
+static_assert(kBlock == kTile, "one update block covers one column tile");
+static_assert(kSubCols % kGroup == 0, "filter groups do not straddle sub-tiles");
 constexpr int32_t kNoIdx = INT32_MAX;
 
 // ---------------------------------------------------------------------------
@@ -178,6 +180,15 @@ __device__ __forceinline__ T wave_min(T x)
     return x;
 }
 
+// max over each aligned group of kSubCols lanes of a wave
+static_assert(kSubCols <= 64 && 64 % kSubCols == 0, "sub-tiles split a wave evenly");
+__device__ __forceinline__ float sub_max(float x)
+{
+#pragma unroll
+    for (int o = kSubCols / 2; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
 // Sums (or maxes) one value per thread over the block; the result is
 // returned to every thread.  `buf` holds kBlock/64 entries.
 template <typename T, bool kMax>
@@ -218,6 +229,22 @@ __device__ __forceinline__ bool seeded_bound(const ScanArgs &a, int64_t p, float
     }
     *out = mx;
     return cnt == kTop;
+}
+
+// Culling test of a column box against a box of rows.  A pair (v, u) can
+// pass the scan only if 2c <= theta_v + Lam_v + Lam_u, and c >= sqrt(D) - 1/2,
+// so only if sqrt(D) <= hv + hu with hv = (theta_v + Lam_v + 1)/2 and
+// hu = Lam_u/2.  Every pair of the two boxes has D >= d2 (the squared
+// distance between the boxes); false means no pair can pass.  hv and hu are
+// float roundings of exact values, hence the small widening.
+__device__ __forceinline__ bool may_pass(float4 b, float4 rbox, float hv, float hu)
+{
+    const double dx = fmax(0.0, fmax((double)b.x - rbox.y, (double)rbox.x - b.y));
+    const double dy = fmax(0.0, fmax((double)b.z - rbox.w, (double)rbox.z - b.w));
+    const double d2 = dx * dx + dy * dy;
+    double hs = (double)hv + (double)hu;
+    hs += 1e-6 * (fabs((double)hv) + fabs((double)hu)) + 1.0;
+    return hs > 0.0 && d2 <= hs * hs;
 }
 
 // MODE kModeGdp: per row the four smallest (Z, label), #Z<0, #Z==0 and the
@@ -272,17 +299,28 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         }
     }
 
-    // culling data: the largest row half-radius and the row block's box
+    // culling data: the largest row half-radius and the box of the block's
+    // rows, and the same for the rows of this wave
     float4 rbox = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+    float4 wbox = rbox;
+    float hvw = -INFINITY;
+    const int wave = t >> 6;
     if (a.cull) {
+        hvw = wave_max(hvmax);
         hvmax = block_reduce<float, true>(hvmax, redf);
         const int64_t ntiles = (n + kTile - 1) / kTile;
         for (int r = 0; r < R; ++r) {
             const int64_t ti = rblk * R + r;
             if (ti < ntiles) {
-                const float4 b = a.g.box[ti];
+                const float4 b = a.g.box[ti * kBoxStride];
                 rbox.x = fminf(rbox.x, b.x); rbox.y = fmaxf(rbox.y, b.y);
                 rbox.z = fminf(rbox.z, b.z); rbox.w = fmaxf(rbox.w, b.w);
+                // the wave's 64 rows of this row tile are whole sub-tiles
+                for (int s = wave * (64 / kSubCols); s < (wave + 1) * (64 / kSubCols); ++s) {
+                    const float4 sb = a.g.box[ti * kBoxStride + 1 + s];
+                    wbox.x = fminf(wbox.x, sb.x); wbox.y = fmaxf(wbox.y, sb.y);
+                    wbox.z = fminf(wbox.z, sb.z); wbox.w = fmaxf(wbox.w, sb.w);
+                }
             }
         }
     }
@@ -292,66 +330,68 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
     const int64_t rb1 = min(n, rb0 + (int64_t)kBlock * R);
     unsigned long long tested = 0;
     for (int64_t tile = c0; tile < c1; tile += kTile) {
-        if (a.cull) {
-            // every pair of the tile has D >= d2; it can pass only if
-            // D < (hv + hu)^2 for some row and column: uniform over the block
-            const int64_t ti = tile / kTile;
-            const float4 b = a.g.box[ti];
-            const float hu = a.lv.tile_hmax[ti];
-            const double dx = fmax(0.0, fmax((double)b.x - rbox.y, (double)rbox.x - b.y));
-            const double dy = fmax(0.0, fmax((double)b.z - rbox.w, (double)rbox.z - b.w));
-            const double d2 = dx * dx + dy * dy;
-            double hs = (double)hvmax + (double)hu;
-            hs += 1e-6 * (fabs((double)hvmax) + fabs((double)hu)) + 1.0;
-            if (hs <= 0.0 || d2 > hs * hs) continue;
-        }
+        const int64_t ti = tile / kTile;
+        if (a.cull && !may_pass(a.g.box[ti * kBoxStride], rbox, hvmax, a.lv.tile_hmax[ti * kBoxStride])) continue;
         __syncthreads();
         const int64_t cc = tile + t;
         sc[t] = (cc < c1) ? a.lv.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
         __syncthreads();
         const int64_t ntile = min((int64_t)kTile, c1 - tile);
-        // ordered pairs of this tile, the diagonal excluded
-        tested += (unsigned long long)((rb1 - rb0) * ntile -
-                                       max((int64_t)0, min(rb1, tile + ntile) - max(rb0, tile)));
-        for (int g = 0; g < ntile; g += kGroup) {
-            float m[R];
+        for (int s = 0; s * kSubCols < ntile; ++s) {
+            // a sub-tile no row of this wave can reach is skipped by the
+            // whole wave (the test is wave-uniform)
+            if (a.cull && !__builtin_amdgcn_readfirstlane(
+                              (int)may_pass(a.g.box[ti * kBoxStride + 1 + s], wbox, hvw,
+                                            a.lv.tile_hmax[ti * kBoxStride + 1 + s])))
+                continue;
+            const int g0 = s * kSubCols;
+            const int g1 = (int)min((int64_t)(g0 + kSubCols), ntile);
+            // ordered pairs of this sub-tile for this lane's rows, the diagonal excluded
 #pragma unroll
-            for (int r = 0; r < R; ++r) m[r] = INFINITY;
+            for (int r = 0; r < R; ++r)
+                if (rw[r].v < n)
+                    tested += (unsigned long long)(g1 - g0) -
+                              ((rw[r].v >= tile + g0 && rw[r].v < tile + g1) ? 1u : 0u);
+            for (int g = g0; g < g1; g += kGroup) {
+                float m[R];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const float4 cd = sc[g + q];
+                for (int r = 0; r < R; ++r) m[r] = INFINITY;
 #pragma unroll
-                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
-            }
+                for (int q = 0; q < kGroup; ++q) {
+                    const float4 cd = sc[g + q];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (m[r] <= rw[r].thr) {
-                    // exact pass over the group for this row
-                    for (int q = 0; q < kGroup; ++q) {
-                        const int64_t u = tile + g + q;
-                        if (u >= c1 || u == rw[r].v) continue;
-                        const float4 cd = sc[g + q];
-                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
-                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lv.lam[u]);
-                        if (MODE == kModeCert) {
-                            if (z < 0) rn[r] += z;
-                            continue;
-                        }
-                        if (z > rw[r].theta) continue;
-                        if (MODE == kModeCollect) {
-                            const unsigned long long slot = atomicAdd(a.count, 1ULL);
-                            if ((int64_t)slot < a.cap) {
-                                const int32_t lv = a.g.orig[rw[r].v], lu = a.g.orig[u];
-                                a.out[slot] = make_int2(min(lv, lu), max(lv, lu));
+                    for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (m[r] <= rw[r].thr) {
+                        // exact pass over the group for this row
+                        for (int q = 0; q < kGroup; ++q) {
+                            const int64_t u = tile + g + q;
+                            if (u >= c1 || u == rw[r].v) continue;
+                            const float4 cd = sc[g + q];
+                            if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
+                            const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lv.lam[u]);
+                            if (MODE == kModeCert) {
+                                if (z < 0) rn[r] += z;
+                                continue;
                             }
-                            continue;
-                        }
-                        if (z < 0) { ++neg[r]; rn[r] += z; }
-                        else if (z == 0) ++zero[r];
-                        top[r].insert(z, a.g.orig[u]);
-                        if (top[r].id[3] != kNoIdx) {
-                            const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
-                            if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
+                            if (z > rw[r].theta) continue;
+                            if (MODE == kModeCollect) {
+                                const unsigned long long slot = atomicAdd(a.count, 1ULL);
+                                if ((int64_t)slot < a.cap) {
+                                    const int32_t lv = a.g.orig[rw[r].v], lu = a.g.orig[u];
+                                    a.out[slot] = make_int2(min(lv, lu), max(lv, lu));
+                                }
+                                continue;
+                            }
+                            if (z < 0) { ++neg[r]; rn[r] += z; }
+                            else if (z == 0) ++zero[r];
+                            top[r].insert(z, a.g.orig[u]);
+                            if (top[r].id[3] != kNoIdx) {
+                                const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
+                                if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
+                            }
                         }
                     }
                 }
@@ -359,7 +399,10 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         }
     }
 
-    if (a.tested && threadIdx.x == 0 && tested) atomicAdd(a.tested, tested);
+    if (a.tested) {
+        tested = block_reduce<unsigned long long, false>(tested, redu);
+        if (threadIdx.x == 0 && tested) atomicAdd(a.tested, tested);
+    }
     if (MODE == kModeGdp) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -465,8 +508,10 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
     __shared__ int s_last;
     if (tile_hmax) {
         // a block of kBlock positions is one column tile
+        const float hs = sub_max(o.hmax);
+        if ((threadIdx.x & (kSubCols - 1)) == 0) tile_hmax[blk * kBoxStride + 1 + threadIdx.x / kSubCols] = hs;
         const float hm = block_reduce<float, true>(o.hmax, redf);
-        if (threadIdx.x == 0) tile_hmax[blk] = hm;
+        if (threadIdx.x == 0) tile_hmax[blk * kBoxStride] = hm;
     }
     const unsigned long long sumlam = block_reduce<unsigned long long, false>(o.sumlam, red);
     const unsigned long long rowneg = block_reduce<unsigned long long, false>(o.rowneg, red);
@@ -679,9 +724,9 @@ __global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_
     }
     float thrf = valid ? (float)thr * (1.0f + 0x1p-20f) + 1.0f : -INFINITY;
     const double thrmax = block_reduce<double, true>(valid ? (double)thr : -1.0, redd);
-    const float4 rbox = g.box[blockIdx.x];
+    const float4 rbox = g.box[blockIdx.x * kBoxStride];
     for (int64_t tile = 0; tile < n; tile += kTile) {
-        const float4 b = g.box[tile / kTile];
+        const float4 b = g.box[tile / kTile * kBoxStride];
         const double dx = fmax(0.0, fmax((double)b.x - rbox.y, (double)rbox.x - b.y));
         const double dy = fmax(0.0, fmax((double)b.z - rbox.w, (double)rbox.z - b.w));
         if (dx * dx + dy * dy > thrmax) continue;   // uniform over the block
@@ -941,13 +986,18 @@ __global__ __launch_bounds__(kBlock) void k_prep(const int32_t *xy, const int32_
         // round the bound up by a relative 2^-22 so it is >= the exact value
         r2 = fmaf(x, x, y * y) * (1.0f + 0x1p-22f) + 1.0f;
     }
+    // sub-tile boxes (an empty sub-tile gets an empty box: min +inf, max -inf)
+    const float smnx = -sub_max(ok ? -x : -INFINITY), smxx = sub_max(ok ? x : -INFINITY);
+    const float smny = -sub_max(ok ? -y : -INFINITY), smxy = sub_max(ok ? y : -INFINITY);
+    if ((threadIdx.x & (kSubCols - 1)) == 0)
+        box[blockIdx.x * kBoxStride + 1 + threadIdx.x / kSubCols] = make_float4(smnx, smxx, smny, smxy);
     const float mnx = -block_reduce<float, true>(ok ? -x : -INFINITY, redf);
     const float mxx = block_reduce<float, true>(ok ? x : -INFINITY, redf);
     const float mny = -block_reduce<float, true>(ok ? -y : -INFINITY, redf);
     const float mxy = block_reduce<float, true>(ok ? y : -INFINITY, redf);
     r2 = block_reduce<float, true>(r2, redf);
     if (threadIdx.x == 0) {
-        box[blockIdx.x] = make_float4(mnx, mxx, mny, mxy);
+        box[blockIdx.x * kBoxStride] = make_float4(mnx, mxx, mny, mxy);
         atomicMax(xy2max_bits, __float_as_uint(r2));
     }
 }
@@ -970,10 +1020,12 @@ __global__ __launch_bounds__(kBlock) void k_set_lam(const int64_t *lam_label, co
         col[p] = cv;
         ab = (unsigned long long)(l < 0 ? -l : l);
     }
+    const float hs = sub_max(h);
+    if ((threadIdx.x & (kSubCols - 1)) == 0) tile_hmax[blockIdx.x * kBoxStride + 1 + threadIdx.x / kSubCols] = hs;
     h = block_reduce<float, true>(h, redf);
     ab = block_reduce<unsigned long long, true>(ab, redu);
     if (threadIdx.x == 0) {
-        tile_hmax[blockIdx.x] = h;
+        tile_hmax[blockIdx.x * kBoxStride] = h;
         atomicMax((unsigned long long *)&ctrl->maxabs_lam, ab);
     }
 }

@@ -72,6 +72,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libf2m.so is not built: run `python -m paper_2011_08170_amd.build`")
+        # Device memory comes from torch; load torch's HIP runtime first so
+        # that libf2m binds to the same one (both carry the SONAME
+        # libamdhip64.so.7) instead of bringing a second runtime into the
+        # process, which would hide the GPUs from torch.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         p, i64 = C.c_void_p, C.c_int64
         L.f2m_opts_default.restype = None
