@@ -97,13 +97,22 @@ public:
 
     // Min-cost flow on the current candidates; false when some excess
     // cannot reach a deficit (the candidate graph is too small).
+    //
+    // Primal-dual: while many excess nodes remain, one Dijkstra from all of
+    // them sets the distance D of the nearest deficit, the potentials move
+    // by min(dist, D) and every excess node augments along zero-reduced-cost
+    // paths.  Once a phase augments few paths, the remaining excess nodes
+    // are served one at a time (successive shortest paths): a Dijkstra from
+    // the node alone stops at its nearest deficit and the path of the
+    // search tree is augmented.  Both keep every residual reduced cost
+    // nonnegative, so the end result is a minimum-cost flow.
     bool solve(int64_t &paths, int64_t &phases)
     {
-        std::vector<int64_t> &dist = dist_;
-        dist.assign(2 * n_, kInf);
+        dist_.assign(2 * n_, kInf);
+        par_.assign(2 * n_, -1);
         std::vector<int32_t> seen(2 * n_, 0);
         int32_t stamp = 0;
-        std::vector<int64_t> touched;
+        bool single = false;
         for (;;) {
             // the excess nodes (the list only shrinks while solving)
             size_t w = 0;
@@ -113,41 +122,38 @@ public:
             std::sort(src_.begin(), src_.end());
             src_.erase(std::unique(src_.begin(), src_.end()), src_.end());
             if (src_.empty()) return true;
-            // Dijkstra from every excess node on reduced costs
-            using Item = std::pair<int64_t, int64_t>;
-            std::priority_queue<Item, std::vector<Item>, std::greater<Item>> pq;
-            for (int64_t x : touched) dist[x] = kInf;
-            touched.clear();
-            for (int64_t x : src_) { dist[x] = 0; touched.push_back(x); pq.push({0, x}); }
-            int64_t D = -1;
-            while (!pq.empty()) {
-                const auto [d, x] = pq.top();
-                pq.pop();
-                if (d != dist[x]) continue;
-                if (ex_[x] < 0) { D = d; break; }
-                relax_from(x, d, dist, touched, pq);
+            if (single) {
+                for (int64_t s : src_) {
+                    while (ex_[s] > 0) {
+                        int64_t t;
+                        if (!shortest(&s, 1, t)) return false;
+                        ++phases;
+                        for (int64_t x = t; x != s;) {   // flip the tree path back to s
+                            const int64_t k = par_[x];
+                            y_[k] ^= 1;
+                            x = (x < n_) ? n_ + head(k) : tail(k);
+                        }
+                        --ex_[s];
+                        ++ex_[t];
+                        ++paths;
+                    }
+                }
+                continue;
             }
-            if (D < 0) return false;
+            int64_t t;
+            if (!shortest(src_.data(), src_.size(), t)) return false;
             ++phases;
-            // potentials: p(x) -= min(dist(x), D) with p(v') = alpha_v,
-            // p(u'') = -beta_u; only nodes closer than D move relative to
-            // the global offsets
-            for (int64_t x : touched) {
-                const int64_t d = dist[x];
-                if (d >= D) continue;
-                if (x < n_) alpha_[x] += D - d;
-                else beta_[x - n_] -= D - d;
-            }
-            A_ -= D;
-            B_ += D;
             // unit augmentations along zero-reduced-cost paths
             ++stamp;
+            int64_t found = 0;
             for (int64_t s : src_) {
                 while (ex_[s] > 0 && seen[s] != stamp) {
                     if (!augment_from(s, stamp, seen)) break;
                     ++paths;
+                    ++found;
                 }
             }
+            single = found < std::max<int64_t>(8, (int64_t)src_.size() / 16);
         }
     }
 
@@ -192,6 +198,44 @@ private:
         for (int64_t k = 0; k < m; ++k) { larc_[lp[tail(k)]++] = k; rarc_[rp[head(k)]++] = k; }
     }
 
+    // Dijkstra on reduced costs from the given excess nodes up to the first
+    // deficit t (at distance D); then p(x) moves by min(dist(x), D) for
+    // every node (through the global offsets for the nodes not reached).
+    // par_ holds the search tree's arcs.  False when no deficit is reachable.
+    bool shortest(const int64_t *srcs, size_t ns, int64_t &t)
+    {
+        std::vector<int64_t> &dist = dist_;
+        using Item = std::pair<int64_t, int64_t>;
+        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> pq;
+        for (int64_t x : touched_) dist[x] = kInf;
+        touched_.clear();
+        for (size_t i = 0; i < ns; ++i) {
+            const int64_t x = srcs[i];
+            dist[x] = 0;
+            par_[x] = -1;
+            touched_.push_back(x);
+            pq.push({0, x});
+        }
+        int64_t D = -1;
+        while (!pq.empty()) {
+            const auto [d, x] = pq.top();
+            pq.pop();
+            if (d != dist[x]) continue;
+            if (ex_[x] < 0) { D = d; t = x; break; }
+            relax_from(x, d, dist, touched_, pq);
+        }
+        if (D < 0) return false;
+        for (int64_t x : touched_) {
+            const int64_t d = dist[x];
+            if (d >= D) continue;
+            if (x < n_) alpha_[x] += D - d;
+            else beta_[x - n_] -= D - d;
+        }
+        A_ -= D;
+        B_ += D;
+        return true;
+    }
+
     template <typename PQ>
     void relax_from(int64_t x, int64_t d, std::vector<int64_t> &dist, std::vector<int64_t> &touched, PQ &pq)
     {
@@ -201,7 +245,7 @@ private:
                 if (y_[k]) continue;
                 const int64_t to = n_ + head(k);
                 const int64_t nd = d + red(k);
-                if (nd < dist[to]) { if (dist[to] == kInf) touched.push_back(to); dist[to] = nd; pq.push({nd, to}); }
+                if (nd < dist[to]) { if (dist[to] == kInf) touched.push_back(to); dist[to] = nd; par_[to] = k; pq.push({nd, to}); }
             }
         } else {        // right copy: arcs with y = 1, backward
             const int64_t u = x - n_;
@@ -210,7 +254,7 @@ private:
                 if (!y_[k]) continue;
                 const int64_t to = tail(k);
                 const int64_t nd = d - red(k);
-                if (nd < dist[to]) { if (dist[to] == kInf) touched.push_back(to); dist[to] = nd; pq.push({nd, to}); }
+                if (nd < dist[to]) { if (dist[to] == kInf) touched.push_back(to); dist[to] = nd; par_[to] = k; pq.push({nd, to}); }
             }
         }
     }
@@ -271,7 +315,7 @@ private:
     int64_t A_ = 0, B_ = 0;          // global offsets of alpha and beta
     std::vector<int64_t> ex_;
     std::vector<int64_t> src_;       // nodes with excess (may hold stale entries)
-    std::vector<int64_t> dist_;
+    std::vector<int64_t> dist_, par_, touched_;
     std::vector<uint64_t> keys_;     // sorted keys a*n+b of the candidate edges
     std::vector<int32_t> ea_, eb_;
     std::vector<int64_t> ec_;
