@@ -40,6 +40,7 @@ public:
             ex_[n + v] = -2;   // right copies demand 2
             src_.push_back(v);
         }
+        build_adjacency();
     }
 
     int64_t edges() const { return (int64_t)ea_.size(); }
@@ -86,12 +87,11 @@ public:
                 }
             }
         }
-        if (!fresh.empty()) {
-            std::vector<uint64_t> merged;
-            merged.reserve(keys_.size() + fresh.size());
-            std::merge(keys_.begin(), keys_.end(), fresh.begin(), fresh.end(), std::back_inserter(merged));
-            keys_.swap(merged);
-        }
+        if (fresh.empty()) return;
+        std::vector<uint64_t> merged;
+        merged.reserve(keys_.size() + fresh.size());
+        std::merge(keys_.begin(), keys_.end(), fresh.begin(), fresh.end(), std::back_inserter(merged));
+        keys_.swap(merged);
         build_adjacency();
     }
 
