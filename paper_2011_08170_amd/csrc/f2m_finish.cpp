@@ -69,8 +69,12 @@ public:
             }
             fresh.push_back(key);
         }
+        ea_.reserve(ea_.size() + fresh.size());
+        eb_.reserve(eb_.size() + fresh.size());
+        ec_.reserve(ec_.size() + fresh.size());
+        y_.reserve(y_.size() + 2 * fresh.size());
         for (uint64_t key : fresh) {
-            const int32_t a = (int32_t)(key / (uint64_t)n_), b = (int32_t)(key % (uint64_t)n_);
+            const int32_t a = (int32_t)(key / (uint64_t)n_), b = (int32_t)(key - (uint64_t)a * (uint64_t)n_);
             const int64_t dx = (int64_t)xy_[2 * a] - xy_[2 * b], dy = (int64_t)xy_[2 * a + 1] - xy_[2 * b + 1];
             const int64_t c = nint_sqrt_host(dx * dx + dy * dy);
             ea_.push_back(a);
@@ -187,15 +191,23 @@ private:
 
     void build_adjacency()
     {
-        const int64_t m = 2 * (int64_t)ea_.size();
+        // arc 2i leaves a_i' and enters b_i''; arc 2i+1 leaves b_i' and
+        // enters a_i'': both copies of a node see the same arc count
+        const int64_t e = (int64_t)ea_.size();
         lstart_.assign(n_ + 1, 0);
-        rstart_.assign(n_ + 1, 0);
-        for (int64_t k = 0; k < m; ++k) { ++lstart_[tail(k) + 1]; ++rstart_[head(k) + 1]; }
-        for (int64_t v = 0; v < n_; ++v) { lstart_[v + 1] += lstart_[v]; rstart_[v + 1] += rstart_[v]; }
-        larc_.assign(m, 0);
-        rarc_.assign(m, 0);
-        std::vector<int64_t> lp(lstart_.begin(), lstart_.end() - 1), rp(rstart_.begin(), rstart_.end() - 1);
-        for (int64_t k = 0; k < m; ++k) { larc_[lp[tail(k)]++] = k; rarc_[rp[head(k)]++] = k; }
+        for (int64_t i = 0; i < e; ++i) { ++lstart_[ea_[i] + 1]; ++lstart_[eb_[i] + 1]; }
+        for (int64_t v = 0; v < n_; ++v) lstart_[v + 1] += lstart_[v];
+        rstart_ = lstart_;
+        larc_.resize(2 * e);
+        rarc_.resize(2 * e);
+        std::vector<int64_t> lp(lstart_.begin(), lstart_.end() - 1), rp(lp);
+        for (int64_t i = 0; i < e; ++i) {
+            const int64_t a = ea_[i], b = eb_[i];
+            larc_[lp[a]++] = 2 * i;
+            larc_[lp[b]++] = 2 * i + 1;
+            rarc_[rp[b]++] = 2 * i;
+            rarc_[rp[a]++] = 2 * i + 1;
+        }
     }
 
     // Dijkstra on reduced costs from the given excess nodes up to the first
