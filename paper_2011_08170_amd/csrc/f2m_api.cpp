@@ -11,8 +11,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace f2m;
@@ -50,6 +52,8 @@ struct f2m_ctx {
         b_pzero, b_prn, b_z4, b_i4, b_seed, b_ctrl, b_trace, b_sargs, b_uargs, b_sitems, b_uitems, b_nblk, b_active;
     Ctrl *ctrl_host = nullptr;   // pinned
     int64_t *scratch_host = nullptr;   // pinned, 16 entries
+    // contexts (own stream and workspaces) of the batch's finishing threads
+    std::vector<f2m_ctx *> workers;
 
     f2m_ctx()
     {
@@ -108,6 +112,15 @@ double now_s()
 }
 
 int64_t ntiles_of(int64_t n) { return (n + kTileCols - 1) / kTileCols; }
+
+// Host threads for the batch's per-instance finishes: one per two hardware
+// threads, at most 8 (the work per instance is a few host syncs and a small
+// flow; more threads only contend).
+int finish_threads()
+{
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(8u, hw / 2));
+}
 
 // Scan launch shape: rows per lane and column slices (slice length a
 // multiple of the tile width).  Results never depend on it.
@@ -860,6 +873,8 @@ f2m_status f2m_create(f2m_ctx **out, int device)
 void f2m_destroy(f2m_ctx *ctx)
 {
     if (!ctx) return;
+    for (f2m_ctx *w : ctx->workers) f2m_destroy(w);
+    ctx->workers.clear();
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (DevBuf *b : ctx->bufs)
@@ -1385,32 +1400,77 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         ck(ctx, hipMemcpyAsync(ch.data(), ctrl, n_inst * sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
         ck(ctx, hipStreamSynchronize(st), "sync");
 
-        // per-instance finish and certificate
+        // per-instance finish and certificate: independent instances, so
+        // host threads take them largest first, each with its own context
+        // (stream, workspaces); every kernel they launch reads the pools
+        // the loop above has finished writing (st is synchronised)
+        std::vector<int32_t> todo;
         for (int32_t i = 0; i < n_inst; ++i) {
-            const int64_t n = offsets[i + 1] - offsets[i], X = offsets[i];
-            const double ti = now_s();
-            if (n == 3) {
-                (void)solve_n3(ctx, coords + 2 * X, &res[i]);
-                continue;
-            }
-            if (ch[i].overflow) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| reached 2^38");
-            GeoHost gh;
-            gh.g = Geo{n, orig + P[i], pos + X, box + T[i], x2h[i]};
-            gh.xy = xy + 2 * X;
-            gh.cx = cxs[i];
-            gh.cy = cys[i];
-            gh.col = col + P[i];
-            const Ctrl &c = ch[i];
-            const int64_t *last = (c.k_last & 1) ? lam1 + P[i] : lam0 + P[i];
-            const int64_t *lstar = (c.kstar == c.k_last) ? last : best + P[i];
-            InstanceState is{gh, c, lstar, z4 + kTop * X, i4 + kTop * X, seed + kTop * X,
-                             trace ? trace + (int64_t)i * trace_cap * kTraceW : nullptr, nullptr};
-            complete_result(ctx, is, o, coords + 2 * X, st, res[i]);
-            res[i].scan_rows = 1;
-            res[i].scan_slices = shp[i].slices;
-            res[i].seconds[2] = t2 - t1;
-            res[i].seconds[5] = now_s() - ti;
+            const int64_t n = offsets[i + 1] - offsets[i];
+            if (n == 3) (void)solve_n3(ctx, coords + 2 * offsets[i], &res[i]);
+            else if (n >= 4) todo.push_back(i);
         }
+        for (int32_t i : todo)
+            if (ch[i].overflow) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| reached 2^38");
+        std::stable_sort(todo.begin(), todo.end(), [&](int32_t a, int32_t b) {
+            return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+        });
+        const int nw = (int)std::min<size_t>(todo.size(), (size_t)finish_threads());
+        while ((int)ctx->workers.size() < nw) {
+            f2m_ctx *w = nullptr;
+            const f2m_status cs = f2m_create(&w, ctx->device);
+            if (cs != F2M_OK) fail(ctx, cs, "cannot create a finishing context");
+            ctx->workers.push_back(w);
+        }
+        std::vector<f2m_status> ist(n_inst, F2M_OK);
+        std::vector<std::string> imsg(n_inst);
+        std::atomic<size_t> next{0};
+        auto work = [&](f2m_ctx *wc) {
+            (void)hipSetDevice(wc->device);
+            for (size_t j; (j = next.fetch_add(1)) < todo.size();) {
+                const int32_t i = todo[j];
+                const int64_t n = offsets[i + 1] - offsets[i], X = offsets[i];
+                const double ti = now_s();
+                try {
+                    GeoHost gh;
+                    gh.g = Geo{n, orig + P[i], pos + X, box + T[i], x2h[i]};
+                    gh.xy = xy + 2 * X;
+                    gh.cx = cxs[i];
+                    gh.cy = cys[i];
+                    gh.col = col + P[i];
+                    const Ctrl &c = ch[i];
+                    const int64_t *last = (c.k_last & 1) ? lam1 + P[i] : lam0 + P[i];
+                    const int64_t *lstar = (c.kstar == c.k_last) ? last : best + P[i];
+                    InstanceState is{gh, c, lstar, z4 + kTop * X, i4 + kTop * X, seed + kTop * X,
+                                     trace ? trace + (int64_t)i * trace_cap * kTraceW : nullptr, nullptr};
+                    complete_result(wc, is, o, coords + 2 * X, wc->stream, res[i]);
+                } catch (const Fail &f) {
+                    ist[i] = f.st;
+                    imsg[i] = wc->err;
+                } catch (const std::bad_alloc &) {
+                    ist[i] = F2M_ERR_NOMEM;
+                    imsg[i] = "host allocation failed";
+                }
+                res[i].scan_rows = 1;
+                res[i].scan_slices = shp[i].slices;
+                res[i].seconds[2] = t2 - t1;
+                res[i].seconds[5] = now_s() - ti;
+            }
+        };
+        {
+            std::vector<std::thread> pool;
+            for (int w = 1; w < nw; ++w) {
+                try {
+                    pool.emplace_back(work, ctx->workers[w]);
+                } catch (const std::exception &) {
+                    break;   // fewer threads: the shared queue still covers every instance
+                }
+            }
+            if (nw > 0) work(ctx->workers[0]);
+            for (auto &th : pool) th.join();
+        }
+        for (int32_t i = 0; i < n_inst; ++i)
+            if (ist[i] != F2M_OK) fail(ctx, ist[i], "instance " + std::to_string(i) + ": " + imsg[i]);
         for (int32_t i = 0; i < n_inst; ++i) {
             res[i].seconds[0] = t1 - t0;
             outs[i] = res[i];
