@@ -1368,7 +1368,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             const int chunk = o.chunk > 0 ? 2 * ((o.chunk + 1) / 2) : 8;
             ck(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
             for (int j = 0; j < chunk; ++j) {
-                hipError_t e1 = launch_scan_batch(sa_d, si_d, (int64_t)sitems.size(), 1, st);
+                hipError_t e1 = launch_scan_batch(sa_d, si_d, (int64_t)sitems.size(), 1, cull, st);
                 hipError_t e2 = launch_update_batch(ua_d, ui_d, (int64_t)uitems.size(), st);
                 if (e1 != hipSuccess || e2 != hipSuccess) {
                     hipGraph_t g2 = nullptr;

@@ -167,7 +167,7 @@ struct BatchTileItem {
 // Single-instance ScanArgs/UpdateArgs pointers are rebased per instance; the
 // iteration index of a batched update comes from the instance's Ctrl.
 hipError_t launch_scan_batch(const ScanArgs *args_dev, const BatchScanItem *items, int64_t nitems, int rows,
-                             hipStream_t st);
+                             bool cull, hipStream_t st);
 hipError_t launch_update_batch(const UpdateArgs *args_dev, const BatchTileItem *items, int64_t nitems,
                                hipStream_t st);
 // ctrls[i].nblocks = nblocks[i]

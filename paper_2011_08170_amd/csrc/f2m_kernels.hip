@@ -234,28 +234,33 @@ __device__ __forceinline__ bool seeded_bound(const ScanArgs &a, int64_t p, float
 // Culling test of a column box against a box of rows.  A pair (v, u) can
 // pass the scan only if 2c <= theta_v + Lam_v + Lam_u, and c >= sqrt(D) - 1/2,
 // so only if sqrt(D) <= hv + hu with hv = (theta_v + Lam_v + 1)/2 and
-// hu = Lam_u/2.  Every pair of the two boxes has D >= d2 (the squared
-// distance between the boxes); false means no pair can pass.  hv and hu are
-// float roundings of exact values, hence the small widening.
+// hu = Lam_u/2.  Every pair of the two boxes has D >= dx^2 + dy^2 (the
+// squared distance between the boxes); false means no pair can pass.  Box
+// corners are integers below 2^20 in magnitude, so dx and dy are exact;
+// hv and hu are float roundings of exact values, hence the widening of
+// hv + hu, and the 2^-16 relative margin covers the roundings of the two
+// squares.  Empty boxes (min +inf, max -inf) and hv = -inf never pass.
 __device__ __forceinline__ bool may_pass(float4 b, float4 rbox, float hv, float hu)
 {
-    const double dx = fmax(0.0, fmax((double)b.x - rbox.y, (double)rbox.x - b.y));
-    const double dy = fmax(0.0, fmax((double)b.z - rbox.w, (double)rbox.z - b.w));
-    const double d2 = dx * dx + dy * dy;
-    double hs = (double)hv + (double)hu;
-    hs += 1e-6 * (fabs((double)hv) + fabs((double)hu)) + 1.0;
-    return hs > 0.0 && d2 <= hs * hs;
+    const float dx = fmaxf(0.0f, fmaxf(b.x - rbox.y, rbox.x - b.y));
+    const float dy = fmaxf(0.0f, fmaxf(b.z - rbox.w, rbox.z - b.w));
+    float hs = hv + hu;
+    hs += 1e-6f * (fabsf(hv) + fabsf(hu)) + 1.0f;
+    if (!(hs > 0.0f)) return false;
+    return fmaf(dx, dx, dy * dy) <= hs * hs * (1.0f + 0x1p-16f);
 }
 
 // MODE kModeGdp: per row the four smallest (Z, label), #Z<0, #Z==0 and the
 // sum of the negative Z over the slice's columns, written as partials.
 // MODE kModeCert: the sum over the slice of min(0, Z) (theta = 0), added to
 // acc[0].  MODE kModeCollect: every pair with Z <= theta_row.
-template <int R, int MODE>
+template <int R, int MODE, bool CULL>
 __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rblk, const int64_t sl)
 {
     if (a.check_done && a.lv.ctrl->done) return;
     __shared__ float4 sc[kTile];
+    __shared__ long long slam[kTile];   // the tile's Lam (exact)
+    __shared__ int32_t so[kTile];     // the tile's labels
     __shared__ float redf[kBlock / 64];
     __shared__ unsigned long long redu[kBlock / 64];
     const int t = threadIdx.x;
@@ -305,7 +310,7 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
     float4 wbox = rbox;
     float hvw = -INFINITY;
     const int wave = t >> 6;
-    if (a.cull) {
+    if (CULL) {
         hvw = wave_max(hvmax);
         hvmax = block_reduce<float, true>(hvmax, redf);
         const int64_t ntiles = (n + kTile - 1) / kTile;
@@ -325,84 +330,139 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         }
     }
 
-    // rows of this block: positions [rb0, rb1)
-    const int64_t rb0 = rblk * (kBlock * R);
-    const int64_t rb1 = min(n, rb0 + (int64_t)kBlock * R);
+    const int lane = t & 63;
+    // ordered (row, column) pairs of this wave's rows and the columns
+    // [col0, col1), the diagonal excluded; wave-uniform
     unsigned long long tested = 0;
-    for (int64_t tile = c0; tile < c1; tile += kTile) {
-        const int64_t ti = tile / kTile;
-        if (a.cull && !may_pass(a.g.box[ti * kBoxStride], rbox, hvmax, a.lv.tile_hmax[ti * kBoxStride])) continue;
-        __syncthreads();
-        const int64_t cc = tile + t;
-        sc[t] = (cc < c1) ? a.lv.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
-        __syncthreads();
-        const int64_t ntile = min((int64_t)kTile, c1 - tile);
-        for (int s = 0; s * kSubCols < ntile; ++s) {
-            // a sub-tile no row of this wave can reach is skipped by the
-            // whole wave (the test is wave-uniform)
-            if (a.cull && !__builtin_amdgcn_readfirstlane(
-                              (int)may_pass(a.g.box[ti * kBoxStride + 1 + s], wbox, hvw,
-                                            a.lv.tile_hmax[ti * kBoxStride + 1 + s])))
-                continue;
-            const int g0 = s * kSubCols;
-            const int g1 = (int)min((int64_t)(g0 + kSubCols), ntile);
-            // ordered pairs of this sub-tile for this lane's rows, the diagonal excluded
+    auto count_tested = [&](int64_t col0, int64_t col1) {
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (rw[r].v < n)
-                    tested += (unsigned long long)(g1 - g0) -
-                              ((rw[r].v >= tile + g0 && rw[r].v < tile + g1) ? 1u : 0u);
-            for (int g = g0; g < g1; g += kGroup) {
-                float m[R];
+        for (int r = 0; r < R; ++r) {
+            const int64_t w0 = rblk * (kBlock * R) + r * kBlock + wave * 64;
+            const int64_t w1 = min(n, w0 + 64);
+            if (w1 > w0)
+                tested += (unsigned long long)((w1 - w0) * (col1 - col0) -
+                                               max((int64_t)0, min(w1, col1) - max(w0, col0)));
+        }
+    };
+    // every row of this lane against the LDS columns [g0, g1) of the tile
+    // that starts at position `tile`
+    auto scan_cols = [&](int64_t tile, int g0, int g1) {
+        for (int g = g0; g < g1; g += kGroup) {
+            float m[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) m[r] = INFINITY;
+            for (int r = 0; r < R; ++r) m[r] = INFINITY;
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const float4 cd = sc[g + q];
+            for (int q = 0; q < kGroup; ++q) {
+                const float4 cd = sc[g + q];
 #pragma unroll
-                    for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
-                }
+                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
+            }
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if (m[r] <= rw[r].thr) {
-                        // exact pass over the group for this row
-                        for (int q = 0; q < kGroup; ++q) {
-                            const int64_t u = tile + g + q;
-                            if (u >= c1 || u == rw[r].v) continue;
-                            const float4 cd = sc[g + q];
-                            if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;
-                            const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, a.lv.lam[u]);
-                            if (MODE == kModeCert) {
-                                if (z < 0) rn[r] += z;
-                                continue;
+            for (int r = 0; r < R; ++r) {
+                if (m[r] <= rw[r].thr) {
+                    // this row's passing columns of the group as a bit mask;
+                    // each lane then walks its own bits, so lanes passing at
+                    // different columns are evaluated together
+                    unsigned pm = 0;
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q)
+                        pm |= (filter_value(rw[r], sc[g + q]) <= rw[r].thr) ? (1u << q) : 0u;
+                    while (pm) {
+                        const int q = __ffs(pm) - 1;
+                        pm &= pm - 1;
+                        const int64_t u = tile + g + q;
+                        if (u >= c1 || u == rw[r].v) continue;
+                        const float4 cd = sc[g + q];
+                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;   // theta may have dropped
+                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, slam[g + q]);
+                        if (MODE == kModeCert) {
+                            if (z < 0) rn[r] += z;
+                            continue;
+                        }
+                        if (z > rw[r].theta) continue;
+                        if (MODE == kModeCollect) {
+                            const unsigned long long slot = atomicAdd(a.count, 1ULL);
+                            if ((int64_t)slot < a.cap) {
+                                const int32_t lv = a.g.orig[rw[r].v], lu = so[g + q];
+                                a.out[slot] = make_int2(min(lv, lu), max(lv, lu));
                             }
-                            if (z > rw[r].theta) continue;
-                            if (MODE == kModeCollect) {
-                                const unsigned long long slot = atomicAdd(a.count, 1ULL);
-                                if ((int64_t)slot < a.cap) {
-                                    const int32_t lv = a.g.orig[rw[r].v], lu = a.g.orig[u];
-                                    a.out[slot] = make_int2(min(lv, lu), max(lv, lu));
-                                }
-                                continue;
-                            }
-                            if (z < 0) { ++neg[r]; rn[r] += z; }
-                            else if (z == 0) ++zero[r];
-                            top[r].insert(z, a.g.orig[u]);
-                            if (top[r].id[3] != kNoIdx) {
-                                const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
-                                if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
-                            }
+                            continue;
+                        }
+                        if (z < 0) { ++neg[r]; rn[r] += z; }
+                        else if (z == 0) ++zero[r];
+                        top[r].insert(z, so[g + q]);
+                        if (top[r].id[3] != kNoIdx) {
+                            const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
+                            if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
                         }
                     }
                 }
             }
         }
+    };
+    auto load_tile = [&](int64_t tile) {
+        __syncthreads();
+        const int64_t cc = tile + t;
+        sc[t] = (cc < c1) ? a.lv.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        slam[t] = (cc < c1) ? a.lv.lam[cc] : 0;
+        so[t] = (cc < c1) ? a.g.orig[cc] : 0;
+        __syncthreads();
+    };
+
+    if (!CULL) {
+        for (int64_t tile = c0; tile < c1; tile += kTile) {
+            load_tile(tile);
+            const int ntile = (int)min((int64_t)kTile, c1 - tile);
+            count_tested(tile, tile + ntile);
+            scan_cols(tile, 0, ntile);
+        }
+    } else {
+        // The slice's tiles are tested in parallel (one per thread) against
+        // the block's rows; the survivors are compacted, in order, into an
+        // LDS list.  Each wave then tests the eight sub-tiles of a loaded
+        // tile in parallel (one per lane) against its own rows and scans
+        // the survivors.
+        __shared__ int32_t tlist[kBlock];
+        __shared__ int32_t wcnt[kBlock / 64];
+        const int64_t t0 = c0 / kTile, t1 = (c1 + kTile - 1) / kTile;
+        for (int64_t base = t0; base < t1; base += kBlock) {
+            const int64_t ti = base + t;
+            const bool ok = ti < t1 && may_pass(a.g.box[ti * kBoxStride], rbox, hvmax,
+                                                a.lv.tile_hmax[ti * kBoxStride]);
+            const unsigned long long mk = __ballot(ok);
+            __syncthreads();   // the previous chunk's list is no longer read
+            if (lane == 0) wcnt[wave] = __popcll(mk);
+            __syncthreads();
+            int off = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                off += (w < wave) ? wcnt[w] : 0;
+                total += wcnt[w];
+            }
+            if (ok) tlist[off + __popcll(mk & ((1ULL << lane) - 1ULL))] = (int32_t)(ti - t0);
+            __syncthreads();
+            for (int j = 0; j < total; ++j) {
+                const int64_t tj = t0 + tlist[j];
+                const int64_t tile = tj * kTile;
+                load_tile(tile);
+                const int ntile = (int)min((int64_t)kTile, c1 - tile);
+                const bool sp = lane < kSubs && lane * kSubCols < ntile &&
+                                may_pass(a.g.box[tj * kBoxStride + 1 + lane], wbox, hvw,
+                                         a.lv.tile_hmax[tj * kBoxStride + 1 + lane]);
+                unsigned long long sm = __ballot(sp);
+                while (sm) {
+                    const int sb = __ffsll((long long)sm) - 1;
+                    sm &= sm - 1;
+                    const int g0 = sb * kSubCols;
+                    const int g1 = min(g0 + kSubCols, ntile);
+                    count_tested(tile + g0, tile + g1);
+                    scan_cols(tile, g0, g1);
+                }
+            }
+        }
     }
 
-    if (a.tested) {
-        tested = block_reduce<unsigned long long, false>(tested, redu);
-        if (threadIdx.x == 0 && tested) atomicAdd(a.tested, tested);
-    }
+    if (a.tested && lane == 0 && tested) atomicAdd(a.tested, tested);
     if (MODE == kModeGdp) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -427,20 +487,20 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
     }
 }
 
-template <int R, int MODE>
+template <int R, int MODE, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
 {
-    rowscan_body<R, MODE>(a, blockIdx.x, blockIdx.y);
+    rowscan_body<R, MODE, CULL>(a, blockIdx.x, blockIdx.y);
 }
 
 // batched GDP scan: one block per (instance, row block, slice)
-template <int R>
+template <int R, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_rowscan_batch(const ScanArgs *args, const BatchScanItem *items)
 {
     const BatchScanItem w = items[blockIdx.x];
     ScanArgs a = args[w.inst];
     if (a.lv.ctrl->k_next & 1) a.lv.lam = a.lam_odd;
-    rowscan_body<R, kModeGdp>(a, w.row_block, w.slice);
+    rowscan_body<R, kModeGdp, CULL>(a, w.row_block, w.slice);
 }
 
 // ---------------------------------------------------------------------------
@@ -1273,17 +1333,23 @@ hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, in
     return hipGetLastError();
 }
 
-template <int MODE>
+template <int MODE, bool CULL>
 static hipError_t launch_scan_mode(const ScanArgs &a, int64_t nslices, int R, hipStream_t st)
 {
     const unsigned gy = (unsigned)nslices;
     switch (R) {
-    case 1: hipLaunchKernelGGL((k_rowscan<1, MODE>), dim3(blocks_for(a.g.n, kBlock), gy), dim3(kBlock), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_rowscan<2, MODE>), dim3(blocks_for(a.g.n, 2 * kBlock), gy), dim3(kBlock), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_rowscan<4, MODE>), dim3(blocks_for(a.g.n, 4 * kBlock), gy), dim3(kBlock), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_rowscan<1, MODE, CULL>), dim3(blocks_for(a.g.n, kBlock), gy), dim3(kBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_rowscan<2, MODE, CULL>), dim3(blocks_for(a.g.n, 2 * kBlock), gy), dim3(kBlock), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_rowscan<4, MODE, CULL>), dim3(blocks_for(a.g.n, 4 * kBlock), gy), dim3(kBlock), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_scan_mode(const ScanArgs &a, int64_t nslices, int R, hipStream_t st)
+{
+    return a.cull ? launch_scan_mode<MODE, true>(a, nslices, R, st) : launch_scan_mode<MODE, false>(a, nslices, R, st);
 }
 
 hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_per_thread, hipStream_t st)
@@ -1304,13 +1370,22 @@ hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
 }
 
 hipError_t launch_scan_batch(const ScanArgs *args_dev, const BatchScanItem *items, int64_t nitems, int rows,
-                             hipStream_t st)
+                             bool cull, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    switch (rows) {
-    case 1: hipLaunchKernelGGL(k_rowscan_batch<1>, dim3((unsigned)nitems), dim3(kBlock), 0, st, args_dev, items); break;
-    case 2: hipLaunchKernelGGL(k_rowscan_batch<2>, dim3((unsigned)nitems), dim3(kBlock), 0, st, args_dev, items); break;
-    default: return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nitems);
+    if (cull) {
+        switch (rows) {
+        case 1: hipLaunchKernelGGL((k_rowscan_batch<1, true>), grid, dim3(kBlock), 0, st, args_dev, items); break;
+        case 2: hipLaunchKernelGGL((k_rowscan_batch<2, true>), grid, dim3(kBlock), 0, st, args_dev, items); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (rows) {
+        case 1: hipLaunchKernelGGL((k_rowscan_batch<1, false>), grid, dim3(kBlock), 0, st, args_dev, items); break;
+        case 2: hipLaunchKernelGGL((k_rowscan_batch<2, false>), grid, dim3(kBlock), 0, st, args_dev, items); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
