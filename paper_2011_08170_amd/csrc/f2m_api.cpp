@@ -41,7 +41,7 @@ struct f2m_ctx {
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
     // certificate / pair collection state
     DevBuf c_col, c_lam, c_tile_hmax, c_ctrl, c_deg, c_cnt, c_nb, c_acc, c_lam_label, c_eu, c_ev, c_ex;
-    DevBuf p_pairs, p_count, p_keys, p_keys2, p_keys3, p_temp, p_ucount;
+    DevBuf p_pairs, p_count, p_keys, p_keys2, p_keys3, p_temp, p_ucount, p_costs;
     // candidate graph
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
     // warm-start network
@@ -61,7 +61,7 @@ struct f2m_ctx {
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
                          &prowneg, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
-                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &knn_nbr, &csr_keys,
+                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
                          &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
@@ -289,23 +289,30 @@ void certify_dev(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label, int6
 }
 
 // Sorts and de-duplicates `found` collected pairs on the device and copies
-// the distinct ones (increasing) to the host.
-void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, PairList &out, hipStream_t st)
+// the distinct ones (increasing) and their exact costs to the host.
+void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const int32_t *xy_dev, PairList &out,
+                        std::vector<int32_t> &costs, hipStream_t st)
 {
     out.clear();
+    costs.clear();
     if (found <= 0) return;
     uint64_t *k1 = grow<uint64_t>(ctx, ctx->p_keys, found);
     uint64_t *k2 = grow<uint64_t>(ctx, ctx->p_keys2, found);
     uint64_t *k3 = grow<uint64_t>(ctx, ctx->p_keys3, found);
+    int32_t *cd = grow<int32_t>(ctx, ctx->p_costs, found);
     int64_t *uc = grow<int64_t>(ctx, ctx->p_ucount, 1);
     const size_t tb = pair_sort_temp_bytes(found);
     void *temp = grow<char>(ctx, ctx->p_temp, tb);
-    ck(ctx, launch_sort_unique_pairs(pairs, found, k1, k2, k3, uc, temp, tb, st), "sort_unique");
+    ck(ctx, launch_sort_unique_pairs(pairs, found, k1, k2, k3, uc, temp, tb, xy_dev, cd, st), "sort_unique");
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, uc, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     const int64_t u = ctx->scratch_host[0];
     std::vector<uint64_t> h(u);
-    if (u) ck(ctx, hipMemcpyAsync(h.data(), k3, u * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy");
+    costs.resize(u);
+    if (u) {
+        ck(ctx, hipMemcpyAsync(h.data(), k3, u * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(costs.data(), cd, u * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+    }
     ck(ctx, hipStreamSynchronize(st), "sync");
     out.reserve(u);
     for (uint64_t k : h) out.emplace_back((int32_t)(k >> 32), (int32_t)(k & 0xffffffffULL));
@@ -359,7 +366,7 @@ private:
                 ck(ctx, hipStreamSynchronize(st_), "sync");
                 const int64_t found = ctx->scratch_host[0];
                 if (found > cap) { cap = found + found / 4; continue; }
-                fetch_unique_pairs(ctx, pairs, found, out, st_);
+                fetch_unique_pairs(ctx, pairs, found, gh_.xy, out, costs, st_);
                 cap_ = cap;
                 return true;
             }
@@ -461,7 +468,7 @@ private:
             ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st_), "copy");
             ck(ctx, hipStreamSynchronize(st_), "sync");
             const int64_t found = std::min<int64_t>(ctx->scratch_host[0], cap);
-            fetch_unique_pairs(ctx, pairs, found, out, st_);
+            fetch_unique_pairs(ctx, pairs, found, gh_.xy, out, costs, st_);
             return true;
         } catch (const Fail &) {
             err = ctx_->err;

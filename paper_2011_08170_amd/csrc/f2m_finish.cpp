@@ -47,12 +47,16 @@ public:
 
     // Adds new candidate edges (a sorted list of distinct pairs); arcs of
     // negative reduced cost start saturated.
-    void add(const PairList &pl)
+    void add(const PairList &pl, const std::vector<int32_t> &costs)
     {
+        const bool have_c = costs.size() == pl.size();
         std::vector<uint64_t> fresh;
+        std::vector<int32_t> fresh_c;
         fresh.reserve(pl.size());
+        if (have_c) fresh_c.reserve(pl.size());
         size_t j = 0;
-        for (const auto &p : pl) {
+        for (size_t q = 0; q < pl.size(); ++q) {
+            const auto &p = pl[q];
             const int32_t a = std::min(p.first, p.second), b = std::max(p.first, p.second);
             if (a == b || a < 0 || b >= n_) continue;
             const uint64_t key = (uint64_t)a * (uint64_t)n_ + (uint64_t)b;
@@ -64,19 +68,26 @@ public:
                 std::vector<std::pair<int32_t, int32_t>> cp(pl.begin(), pl.end());
                 std::sort(cp.begin(), cp.end());
                 cp.erase(std::unique(cp.begin(), cp.end()), cp.end());
-                add(cp);
+                add(cp, std::vector<int32_t>());
                 return;
             }
             fresh.push_back(key);
+            if (have_c) fresh_c.push_back(costs[q]);
         }
         ea_.reserve(ea_.size() + fresh.size());
         eb_.reserve(eb_.size() + fresh.size());
         ec_.reserve(ec_.size() + fresh.size());
         y_.reserve(y_.size() + 2 * fresh.size());
-        for (uint64_t key : fresh) {
+        for (size_t q = 0; q < fresh.size(); ++q) {
+            const uint64_t key = fresh[q];
             const int32_t a = (int32_t)(key / (uint64_t)n_), b = (int32_t)(key - (uint64_t)a * (uint64_t)n_);
-            const int64_t dx = (int64_t)xy_[2 * a] - xy_[2 * b], dy = (int64_t)xy_[2 * a + 1] - xy_[2 * b + 1];
-            const int64_t c = nint_sqrt_host(dx * dx + dy * dy);
+            int64_t c;
+            if (have_c) {
+                c = fresh_c[q];
+            } else {
+                const int64_t dx = (int64_t)xy_[2 * a] - xy_[2 * b], dy = (int64_t)xy_[2 * a + 1] - xy_[2 * b + 1];
+                c = nint_sqrt_host(dx * dx + dy * dy);
+            }
             ea_.push_back(a);
             eb_.push_back(b);
             ec_.push_back(c);
@@ -116,7 +127,7 @@ public:
         par_.assign(2 * n_, -1);
         std::vector<int32_t> seen(2 * n_, 0);
         int32_t stamp = 0;
-        bool single = false;
+        bool single = false, first = true;
         for (;;) {
             // the excess nodes (the list only shrinks while solving)
             size_t w = 0;
@@ -144,9 +155,15 @@ public:
                 }
                 continue;
             }
-            int64_t t;
-            if (!shortest(src_.data(), src_.size(), t)) return false;
-            ++phases;
+            // the starting potentials are feasible, so the first pass
+            // augments along the zero-reduced-cost paths they already have;
+            // later passes follow a Dijkstra that moves the potentials
+            if (!first) {
+                int64_t t;
+                if (!shortest(src_.data(), src_.size(), t)) return false;
+                ++phases;
+            }
+            first = false;
             // unit augmentations along zero-reduced-cost paths
             ++stamp;
             int64_t found = 0;
@@ -189,25 +206,45 @@ private:
     // alpha, beta are stored relative to the global offsets A_, B_
     int64_t red(int64_t k) const { return ec_[k >> 1] - alpha_[tail(k)] - beta_[head(k)] - A_ - B_; }
 
+    // Incident edges per node, in increasing edge index: both copies of a
+    // node use the same list (edge e leaves a_e' and b_e' and enters b_e''
+    // and a_e'').  Edges [built_, size) are new since the last call: a bulk
+    // counting sort the first time, later a sequential merge that appends
+    // the few new edges to each node's list (new edges have the largest
+    // indexes, so every list stays sorted).
     void build_adjacency()
     {
-        // arc 2i leaves a_i' and enters b_i''; arc 2i+1 leaves b_i' and
-        // enters a_i'': both copies of a node see the same arc count
         const int64_t e = (int64_t)ea_.size();
-        lstart_.assign(n_ + 1, 0);
-        for (int64_t i = 0; i < e; ++i) { ++lstart_[ea_[i] + 1]; ++lstart_[eb_[i] + 1]; }
-        for (int64_t v = 0; v < n_; ++v) lstart_[v + 1] += lstart_[v];
-        rstart_ = lstart_;
-        larc_.resize(2 * e);
-        rarc_.resize(2 * e);
-        std::vector<int64_t> lp(lstart_.begin(), lstart_.end() - 1), rp(lp);
-        for (int64_t i = 0; i < e; ++i) {
-            const int64_t a = ea_[i], b = eb_[i];
-            larc_[lp[a]++] = 2 * i;
-            larc_[lp[b]++] = 2 * i + 1;
-            rarc_[rp[b]++] = 2 * i;
-            rarc_[rp[a]++] = 2 * i + 1;
+        if (built_ == 0 || e - built_ > built_ / 8) {
+            start_.assign(n_ + 1, 0);
+            for (int64_t i = 0; i < e; ++i) { ++start_[ea_[i] + 1]; ++start_[eb_[i] + 1]; }
+            for (int64_t v = 0; v < n_; ++v) start_[v + 1] += start_[v];
+            inc_.resize(2 * e);
+            std::vector<int64_t> pos(start_.begin(), start_.end() - 1);
+            for (int64_t i = 0; i < e; ++i) {
+                inc_[pos[ea_[i]]++] = (int32_t)i;
+                inc_[pos[eb_[i]]++] = (int32_t)i;
+            }
+        } else if (e > built_) {
+            std::vector<int64_t> add(n_ + 1, 0);
+            for (int64_t i = built_; i < e; ++i) { ++add[ea_[i] + 1]; ++add[eb_[i] + 1]; }
+            std::vector<int64_t> ns(n_ + 1, 0);
+            for (int64_t v = 0; v < n_; ++v) ns[v + 1] = ns[v] + (start_[v + 1] - start_[v]) + add[v + 1];
+            std::vector<int32_t> ni(2 * e);
+            std::vector<int64_t> pos(n_);
+            for (int64_t v = 0; v < n_; ++v) {
+                const int64_t len = start_[v + 1] - start_[v];
+                std::copy(inc_.begin() + start_[v], inc_.begin() + start_[v + 1], ni.begin() + ns[v]);
+                pos[v] = ns[v] + len;
+            }
+            for (int64_t i = built_; i < e; ++i) {
+                ni[pos[ea_[i]]++] = (int32_t)i;
+                ni[pos[eb_[i]]++] = (int32_t)i;
+            }
+            start_.swap(ns);
+            inc_.swap(ni);
         }
+        built_ = e;
     }
 
     // Dijkstra on reduced costs from the given excess nodes up to the first
@@ -217,24 +254,39 @@ private:
     bool shortest(const int64_t *srcs, size_t ns, int64_t &t)
     {
         std::vector<int64_t> &dist = dist_;
-        using Item = std::pair<int64_t, int64_t>;
-        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> pq;
         for (int64_t x : touched_) dist[x] = kInf;
         touched_.clear();
+        // nodes at the current distance wait in a plain list (zero-cost
+        // arcs are common here); larger distances go through the heap
+        std::vector<int64_t> &cur = cur_;
+        cur.clear();
+        heap_.clear();
+        int64_t dcur = 0;
         for (size_t i = 0; i < ns; ++i) {
             const int64_t x = srcs[i];
             dist[x] = 0;
             par_[x] = -1;
             touched_.push_back(x);
-            pq.push({0, x});
+            cur.push_back(x);
         }
         int64_t D = -1;
-        while (!pq.empty()) {
-            const auto [d, x] = pq.top();
-            pq.pop();
-            if (d != dist[x]) continue;
-            if (ex_[x] < 0) { D = d; t = x; break; }
-            relax_from(x, d, dist, touched_, pq);
+        for (;;) {
+            int64_t x;
+            if (!cur.empty()) {
+                x = cur.back();
+                cur.pop_back();
+                if (dist[x] != dcur) continue;
+            } else {
+                if (heap_.empty()) break;
+                std::pop_heap(heap_.begin(), heap_.end(), std::greater<Item>());
+                const Item it = heap_.back();
+                heap_.pop_back();
+                if (it.first != dist[it.second]) continue;
+                dcur = it.first;
+                x = it.second;
+            }
+            if (ex_[x] < 0) { D = dcur; t = x; break; }
+            relax_from(x, dcur);
         }
         if (D < 0) return false;
         for (int64_t x : touched_) {
@@ -248,25 +300,39 @@ private:
         return true;
     }
 
-    template <typename PQ>
-    void relax_from(int64_t x, int64_t d, std::vector<int64_t> &dist, std::vector<int64_t> &touched, PQ &pq)
+    void push(int64_t to, int64_t nd, int64_t dcur, int64_t k)
+    {
+        if (nd >= dist_[to]) return;
+        if (dist_[to] == kInf) touched_.push_back(to);
+        dist_[to] = nd;
+        par_[to] = k;
+        if (nd == dcur) {
+            cur_.push_back(to);
+        } else {
+            heap_.push_back({nd, to});
+            std::push_heap(heap_.begin(), heap_.end(), std::greater<Item>());
+        }
+    }
+
+    // the arc of incident edge ie that leaves v' (left) or enters v''
+    int64_t out_arc(int64_t ie, int64_t v) const { return 2 * ie + (ea_[ie] != v); }
+    int64_t in_arc(int64_t ie, int64_t v) const { return 2 * ie + (eb_[ie] != v); }
+    int64_t other(int64_t ie, int64_t v) const { return (int64_t)ea_[ie] + eb_[ie] - v; }
+
+    void relax_from(int64_t x, int64_t d)
     {
         if (x < n_) {   // left copy: arcs with y = 0, forward
-            for (int64_t p = lstart_[x]; p < lstart_[x + 1]; ++p) {
-                const int64_t k = larc_[p];
+            for (int64_t p = start_[x]; p < start_[x + 1]; ++p) {
+                const int64_t ie = inc_[p], k = out_arc(ie, x);
                 if (y_[k]) continue;
-                const int64_t to = n_ + head(k);
-                const int64_t nd = d + red(k);
-                if (nd < dist[to]) { if (dist[to] == kInf) touched.push_back(to); dist[to] = nd; par_[to] = k; pq.push({nd, to}); }
+                push(n_ + other(ie, x), d + red(k), d, k);
             }
         } else {        // right copy: arcs with y = 1, backward
             const int64_t u = x - n_;
-            for (int64_t p = rstart_[u]; p < rstart_[u + 1]; ++p) {
-                const int64_t k = rarc_[p];
+            for (int64_t p = start_[u]; p < start_[u + 1]; ++p) {
+                const int64_t ie = inc_[p], k = in_arc(ie, u);
                 if (!y_[k]) continue;
-                const int64_t to = tail(k);
-                const int64_t nd = d - red(k);
-                if (nd < dist[to]) { if (dist[to] == kInf) touched.push_back(to); dist[to] = nd; par_[to] = k; pq.push({nd, to}); }
+                push(other(ie, u), d - red(k), d, k);
             }
         }
     }
@@ -275,10 +341,10 @@ private:
     // node with a deficit; flips the arcs of the path found.
     bool augment_from(int64_t s, int32_t stamp, std::vector<int32_t> &seen)
     {
-        struct Frame { int64_t x, p, via; };
-        std::vector<Frame> st;
+        std::vector<Frame> &st = frames_;
+        st.clear();
         seen[s] = stamp;
-        st.push_back({s, s < n_ ? lstart_[s] : rstart_[s - n_], -1});
+        st.push_back({s, start_[s < n_ ? s : s - n_], -1});
         while (!st.empty()) {
             Frame &f = st.back();
             const int64_t x = f.x;
@@ -291,27 +357,27 @@ private:
             }
             bool pushed = false;
             if (x < n_) {
-                for (; f.p < lstart_[x + 1]; ++f.p) {
-                    const int64_t k = larc_[f.p];
+                for (; f.p < start_[x + 1]; ++f.p) {
+                    const int64_t ie = inc_[f.p], k = out_arc(ie, x);
                     if (y_[k] || red(k) != 0) continue;
-                    const int64_t to = n_ + head(k);
+                    const int64_t w = other(ie, x), to = n_ + w;
                     if (seen[to] == stamp) continue;
                     seen[to] = stamp;
                     ++f.p;
-                    st.push_back({to, rstart_[head(k)], k});
+                    st.push_back({to, start_[w], k});
                     pushed = true;
                     break;
                 }
             } else {
                 const int64_t u = x - n_;
-                for (; f.p < rstart_[u + 1]; ++f.p) {
-                    const int64_t k = rarc_[f.p];
+                for (; f.p < start_[u + 1]; ++f.p) {
+                    const int64_t ie = inc_[f.p], k = in_arc(ie, u);
                     if (!y_[k] || red(k) != 0) continue;
-                    const int64_t to = tail(k);
+                    const int64_t to = other(ie, u);
                     if (seen[to] == stamp) continue;
                     seen[to] = stamp;
                     ++f.p;
-                    st.push_back({to, lstart_[to], k});
+                    st.push_back({to, start_[to], k});
                     pushed = true;
                     break;
                 }
@@ -327,12 +393,18 @@ private:
     int64_t A_ = 0, B_ = 0;          // global offsets of alpha and beta
     std::vector<int64_t> ex_;
     std::vector<int64_t> src_;       // nodes with excess (may hold stale entries)
-    std::vector<int64_t> dist_, par_, touched_;
+    using Item = std::pair<int64_t, int64_t>;
+    std::vector<int64_t> dist_, par_, touched_, cur_;
+    std::vector<Item> heap_;
     std::vector<uint64_t> keys_;     // sorted keys a*n+b of the candidate edges
     std::vector<int32_t> ea_, eb_;
     std::vector<int64_t> ec_;
     std::vector<uint8_t> y_;
-    std::vector<int64_t> lstart_, rstart_, larc_, rarc_;
+    std::vector<int64_t> start_;     // incident-edge lists (see build_adjacency)
+    std::vector<int32_t> inc_;
+    int64_t built_ = 0;              // edges covered by start_/inc_
+    struct Frame { int64_t x, p, via; };
+    std::vector<Frame> frames_;
 };
 
 }  // namespace
@@ -354,7 +426,7 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
     if (!src.near(lam0, slack, pl, err)) { r.msg = err; return; }
     r.t_collect += secs() - t;
     t = secs();
-    g.add(pl);
+    g.add(pl, src.costs);
     r.t_build += secs() - t;
     std::vector<int64_t> lam;
     for (int round = 0; round < 64; ++round) {
@@ -371,7 +443,7 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
             if (!src.near(lam.data(), slack, pl, err)) { r.msg = err; return; }
             r.t_collect += secs() - t;
             t = secs();
-            g.add(pl);
+            g.add(pl, src.costs);
             r.t_build += secs() - t;
             continue;
         }
@@ -382,7 +454,7 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
         r.t_collect += secs() - t;
         const int64_t before = g.edges();
         t = secs();
-        g.add(pl);
+        g.add(pl, src.costs);
         r.t_build += secs() - t;
         if (g.edges() == before) {
             r.ok = true;

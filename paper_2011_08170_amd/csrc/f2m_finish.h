@@ -33,6 +33,10 @@ using PairList = std::vector<std::pair<int32_t, int32_t>>;   // (u, v), u < v
 // uses GPU scans).
 struct PairSource {
     virtual ~PairSource() = default;
+    // exact costs c of the pairs the last call returned, in the same order,
+    // when the source computes them (else left empty: the finish computes
+    // them itself)
+    std::vector<int32_t> costs;
     // pairs {u, v} with Z_uv(lam) <= max(0, 4th smallest Z at u or v) + slack
     virtual bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) = 0;
     // pairs {u, v} with Z_uv(lam) < 0

@@ -192,11 +192,12 @@ hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_so
 hipError_t launch_graph_collect(const Geo &g, const Csr &csr, const int64_t *lam_sorted, int64_t slack,
                                 unsigned long long *count, int2 *out, int64_t cap, hipStream_t st);
 // (lo, hi) label pairs -> sorted distinct keys lo * 2^32 + hi in keys_out;
-// the distinct count lands in *count_dev
+// the distinct count lands in *count_dev; with costs non-null, costs[i] is
+// the exact cost of keys_out[i] from the label-order coordinates xy
 size_t pair_sort_temp_bytes(int64_t count);
 hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *keys, uint64_t *keys_sorted,
                                     uint64_t *keys_out, int64_t *count_dev, void *temp, size_t temp_bytes,
-                                    hipStream_t st);
+                                    const int32_t *xy, int32_t *costs, hipStream_t st);
 // labels: edges of x must be edges of the graph; acc[2] += violations
 hipError_t launch_graph_membership(const Geo &g, const Csr &csr, int64_t m, const int32_t *eu, const int32_t *ev,
                                    unsigned long long *acc, hipStream_t st);

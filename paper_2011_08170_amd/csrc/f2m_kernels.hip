@@ -952,6 +952,17 @@ __global__ __launch_bounds__(kBlock) void k_pair_to_key(const int2 *pairs, int64
     if (i < count) keys[i] = ((uint64_t)(uint32_t)pairs[i].x << 32) | (uint64_t)(uint32_t)pairs[i].y;
 }
 
+// exact cost of each distinct pair key (labels a << 32 | b); count on the device
+__global__ __launch_bounds__(kBlock) void k_key_costs(const uint64_t *keys, const int64_t *count, const int32_t *xy,
+                                                      int32_t *cost)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= *count) return;
+    const int64_t a = (int64_t)(keys[i] >> 32), b = (int64_t)(keys[i] & 0xffffffffULL);
+    const int64_t dx = (int64_t)xy[2 * a] - xy[2 * b], dy = (int64_t)xy[2 * a + 1] - xy[2 * b + 1];
+    cost[i] = (int32_t)nint_sqrt(dx * dx + dy * dy);
+}
+
 __global__ __launch_bounds__(kBlock) void k_label_degrees(Geo g, Csr csr, int32_t *deg)
 {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1471,7 +1482,7 @@ size_t pair_sort_temp_bytes(int64_t count)
 
 hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *keys, uint64_t *keys_sorted,
                                     uint64_t *keys_out, int64_t *count_dev, void *temp, size_t temp_bytes,
-                                    hipStream_t st)
+                                    const int32_t *xy, int32_t *costs, hipStream_t st)
 {
     if (count <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int64_t), st);
     hipLaunchKernelGGL(k_pair_to_key, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, pairs, count, keys);
@@ -1479,7 +1490,14 @@ hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *
     hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, tb, keys, keys_sorted, (int)count, 0, 64, st);
     if (e != hipSuccess) return e;
     tb = temp_bytes;
-    return hipcub::DeviceSelect::Unique(temp, tb, keys_sorted, keys_out, count_dev, (int)count, st);
+    e = hipcub::DeviceSelect::Unique(temp, tb, keys_sorted, keys_out, count_dev, (int)count, st);
+    if (e != hipSuccess) return e;
+    if (costs) {
+        hipLaunchKernelGGL(k_key_costs, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, keys_out, count_dev, xy,
+                           costs);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_sorted, unsigned long long *acc,
