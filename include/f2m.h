@@ -73,8 +73,15 @@ typedef enum f2m_status {
 enum { F2M_GRAPH_COMPLETE = 0, F2M_GRAPH_KNN = 1 };
 /* F2M_WARM_MLP: Lam_0 from the warm-start network (see f2m_mlp_forward),
  * parameters in opts.mlp_theta; the GDP, the finish and the certificate
- * are unchanged, so the certified optimum equals the cold start's. */
-enum { F2M_WARM_COLD = 0, F2M_WARM_USER = 1, F2M_WARM_MLP = 2 };
+ * are unchanged, so the certified optimum equals the cold start's.
+ * F2M_WARM_GRAPH (complete graph only): Lam_0 is the Lam* of a cold GDP
+ * run, with the same stop rules, on the candidate graph of Sec. 5.3
+ * (knn_k nearest neighbours), and the complete-graph GDP starts from it
+ * with the candidate graph's final four smallest per node as its first
+ * thresholds; result.warm_iterations counts the candidate-graph iterations
+ * (0 when n <= knn_k: then the start is cold).  Again only iterations and
+ * time change, never the certified optimum. */
+enum { F2M_WARM_COLD = 0, F2M_WARM_USER = 1, F2M_WARM_MLP = 2, F2M_WARM_GRAPH = 3 };
 enum { F2M_FINISH_NONE = 0, F2M_FINISH_EXACT = 1 };
 /* Scan over the complete graph: F2M_SCAN_CULLED skips column tiles whose
  * bounding box is provably too far for any pair to matter (exact: same
@@ -95,7 +102,7 @@ typedef struct f2m_opts {
     uint32_t rule_version;        /* must be 1 */
     int32_t graph;                /* F2M_GRAPH_COMPLETE or F2M_GRAPH_KNN */
     int32_t knn_k;                /* neighbours per node for F2M_GRAPH_KNN: 10 or 16 */
-    int32_t warm;                 /* F2M_WARM_COLD (Lam0 = 0) or F2M_WARM_USER */
+    int32_t warm;                 /* F2M_WARM_COLD (Lam0 = 0), _USER, _MLP or _GRAPH */
     const int64_t *lambda2_init;  /* host, n entries, read when warm == USER */
     const float *mlp_theta;       /* device, F2M_MLP_PARAMS floats, read when warm == MLP */
     int64_t max_iters;            /* iteration cap (>= 0) */
@@ -145,7 +152,8 @@ typedef struct f2m_result {
     int64_t dual2_complete;     /* 2 L(lambda2) on the complete graph */
     int32_t certified_complete; /* x is also optimal for the complete graph */
     int32_t pad1;
-    int64_t graph_nnz;          /* directed entries of the candidate graph (F2M_GRAPH_KNN) */
+    int64_t graph_nnz;          /* directed entries of the candidate graph (F2M_GRAPH_KNN, F2M_WARM_GRAPH) */
+    int64_t warm_iterations;    /* GDP iterations of the F2M_WARM_GRAPH start (0 otherwise) */
 } f2m_result;
 
 /* Fills opts with the defaults: rule 1, complete graph, cold start,

@@ -494,7 +494,8 @@ struct LoopOut {
 // (null: zero).
 LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev, int64_t max_iters,
                  int64_t handoff_div, int32_t chunk_opt, bool want_trace, bool time_kernels, bool cull,
-                 const Csr *csr, int rows_override, int64_t slices_override, hipStream_t st)
+                 const Csr *csr, int rows_override, int64_t slices_override, hipStream_t st,
+                 bool keep_seeds = false)
 {
     LoopOut o;
     const int64_t n = gh.g.n;
@@ -524,7 +525,7 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
         ck(ctx, hipMemsetAsync(l0, 0, n * sizeof(int64_t), st), "memset");
     ck(ctx, launch_ctrl_init(cd, max_iters, trace_cap, handoff_div, st), "ctrl_init");
     ck(ctx, launch_set_lam(l0, gh.g.orig, n, lam[0], col, thm, cd, st), "set_lam");
-    ck(ctx, launch_seed_neighbours(n, seed, st), "seed");
+    if (!keep_seeds) ck(ctx, launch_seed_neighbours(n, seed, st), "seed");
     ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2_init| must be below 2^38");
@@ -1108,8 +1109,10 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             fail(ctx, F2M_ERR_ARG, "scan_rows must be 0, 1, 2 or 4");
         if (o.scan_slices < 0) fail(ctx, F2M_ERR_ARG, "scan_slices < 0");
         if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
-        if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER && o.warm != F2M_WARM_MLP)
+        if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER && o.warm != F2M_WARM_MLP &&
+            o.warm != F2M_WARM_GRAPH)
             fail(ctx, F2M_ERR_ARG, "unknown warm mode");
+        if (o.warm == F2M_WARM_GRAPH && on_graph) fail(ctx, F2M_ERR_ARG, "the graph warm start is for the complete graph");
         if (o.warm == F2M_WARM_MLP && !o.mlp_theta) fail(ctx, F2M_ERR_ARG, "warm start without mlp_theta");
         if (n < 3) fail(ctx, F2M_ERR_INFEASIBLE, "F2M needs n >= 3");
         if (n >= (int64_t)1 << 30) fail(ctx, F2M_ERR_ARG, "n must be below 2^30");
@@ -1158,15 +1161,30 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             res.graph_nnz = csr.nnz;
         }
         const double tw = now_s();
+        bool keep_seeds = false;
         if (o.warm == F2M_WARM_MLP) {
             lam0_dev = mlp_lam0_dev(ctx, gh, o.mlp_theta, st);
             ck(ctx, hipStreamSynchronize(st), "sync");
+        } else if (o.warm == F2M_WARM_GRAPH && n > o.knn_k) {
+            // cold GDP on the candidate graph; its Lam* and final four
+            // smallest start the complete-graph GDP
+            const Csr wcsr = build_graph(ctx, gh, o.knn_k, st);
+            res.graph_nnz = wcsr.nnz;
+            const LoopOut wl = gdp_loop(ctx, gh, nullptr, o.max_iters, o.handoff_div, o.chunk, false, false, true,
+                                        &wcsr, 0, 0, st);
+            int64_t *l = grow<int64_t>(ctx, ctx->m_lam0, n);
+            ck(ctx, launch_unpermute(wl.lam_star, gh.g.orig, n, l, st), "unpermute");
+            ck(ctx, launch_seed_from_top(static_cast<const int32_t *>(ctx->i4.p), gh.g.orig, gh.g.pos, n,
+                                         static_cast<int32_t *>(ctx->seed.p), st), "seed");
+            res.warm_iterations = wl.c.k_last + 1;
+            lam0_dev = l;
+            keep_seeds = true;
         }
         const double t1 = now_s();
         res.seconds[1] = t1 - tw;
         LoopOut lo = gdp_loop(ctx, gh, lam0_dev, o.max_iters, o.handoff_div, o.chunk, o.record_trace != 0,
                               o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, on_graph ? &csr : nullptr,
-                              o.scan_rows, o.scan_slices, st);
+                              o.scan_rows, o.scan_slices, st, keep_seeds);
         const double t2 = now_s();
         InstanceState is{gh, lo.c, lo.lam_star, static_cast<const int64_t *>(ctx->z4.p),
                          static_cast<const int32_t *>(ctx->i4.p), static_cast<const int32_t *>(ctx->seed.p),

@@ -746,66 +746,49 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
 // candidate graph: k nearest neighbours and the CSR
 // ---------------------------------------------------------------------------
 
-// K smallest (D, label) per row over every column, by tiles, culled by the
-// block's largest current threshold.  Thresholds start at the largest D of
-// K + 1 neighbouring positions (any K distinct columns bound the K-th
-// smallest D); the float test keeps every pair with D <= thr exactly.
+// K smallest (D, label) per row over every column.  A workgroup owns one
+// tile of 256 Morton-consecutive rows: it first scans its own tile, which
+// gives every row a K-th smallest D to beat; tiles whose box lies farther
+// from the rows' box than the largest such bound are skipped (tested in
+// parallel and compacted), and each wave skips the 32-column sub-tiles
+// beyond its own rows' bound.  The float distance test keeps every pair with
+// D <= the current K-th smallest exactly (see thrf); insertion is exact in
+// int64 with ties broken by label.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_t *nbr, int64_t *nbr_d)
 {
     __shared__ float2 sc[kTile];
-    __shared__ double redd[kBlock / 64];
-    const int t = threadIdx.x;
+    __shared__ int32_t sl[kTile];
+    __shared__ int32_t tlist[kBlock];
+    __shared__ int32_t wcnt[kBlock / 64];
+    __shared__ float redf[kBlock / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t n = g.n;
-    const int64_t p = (int64_t)blockIdx.x * kBlock + t;
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t own = blockIdx.x;
+    const int64_t p = own * kTile + t;
     const bool valid = p < n;
     float xv = 0.0f, yv = 0.0f;
     int64_t bd[K];
     int32_t bl[K], bp[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) { bd[j] = INT64_MAX; bl[j] = kNoIdx; bp[j] = -1; }
-    int64_t thr = INT64_MAX;
-    int32_t lv = 0;
-    if (valid) {
-        const float4 cv = col[p];
-        xv = cv.x; yv = cv.y;
-        lv = g.orig[p];
-        int64_t lo = p - K / 2;
-        lo = lo < 0 ? 0 : (lo > n - K - 1 ? n - K - 1 : lo);
-        int64_t mx = 0;
-        for (int64_t q = lo; q < lo + K + 1; ++q) {
-            if (q == p) continue;
-            const float4 cu = col[q];
-            const int32_t dx = (int32_t)(xv - cu.x), dy = (int32_t)(yv - cu.y);
-            const int64_t D = (int64_t)dx * dx + (int64_t)dy * dy;
-            mx = D > mx ? D : mx;
-        }
-        thr = mx;
-    }
-    float thrf = valid ? (float)thr * (1.0f + 0x1p-20f) + 1.0f : -INFINITY;
-    const double thrmax = block_reduce<double, true>(valid ? (double)thr : -1.0, redd);
-    const float4 rbox = g.box[blockIdx.x * kBoxStride];
-    for (int64_t tile = 0; tile < n; tile += kTile) {
-        const float4 b = g.box[tile / kTile * kBoxStride];
-        const double dx = fmax(0.0, fmax((double)b.x - rbox.y, (double)rbox.x - b.y));
-        const double dy = fmax(0.0, fmax((double)b.z - rbox.w, (double)rbox.z - b.w));
-        if (dx * dx + dy * dy > thrmax) continue;   // uniform over the block
-        __syncthreads();
-        const int64_t cc = tile + t;
-        if (cc < n) { const float4 c4 = col[cc]; sc[t] = make_float2(c4.x, c4.y); }
-        else sc[t] = make_float2(INFINITY, INFINITY);
-        __syncthreads();
-        const int64_t ntile = min((int64_t)kTile, n - tile);
-        for (int j = 0; j < ntile; ++j) {
+    if (valid) { const float4 cv = col[p]; xv = cv.x; yv = cv.y; }
+    // float bound of the current K-th smallest D (exact integers below 2^42;
+    // the widening covers the rounding of the float distance)
+    float thrf = INFINITY;
+
+    // all columns [tile, tile + ntile) of the LDS tile against this row
+    auto scan = [&](int64_t tile, int j0, int j1) {
+        for (int j = j0; j < j1; ++j) {
             const float2 cu = sc[j];
             const float ddx = xv - cu.x, ddy = yv - cu.y;
-            const float df = fmaf(ddx, ddx, ddy * ddy);
-            if (!(df <= thrf)) continue;
+            if (!(fmaf(ddx, ddx, ddy * ddy) <= thrf)) continue;
             const int64_t u = tile + j;
-            if (u == p) continue;
+            if (u == p || u >= n) continue;
             const int32_t ix = (int32_t)ddx, iy = (int32_t)ddy;
             const int64_t D = (int64_t)ix * ix + (int64_t)iy * iy;
-            const int32_t lu = g.orig[u];
+            const int32_t lu = sl[j];
             if (!(D < bd[K - 1] || (D == bd[K - 1] && lu < bl[K - 1]))) continue;
             bd[K - 1] = D; bl[K - 1] = lu; bp[K - 1] = (int32_t)u;
 #pragma unroll
@@ -816,13 +799,72 @@ __global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_
                     const int32_t tp = bp[q]; bp[q] = bp[q - 1]; bp[q - 1] = tp;
                 }
             }
-            if (bp[K - 1] >= 0 && bd[K - 1] < thr) {
-                thr = bd[K - 1];
-                thrf = (float)thr * (1.0f + 0x1p-20f) + 1.0f;
+            if (bp[K - 1] >= 0) thrf = (float)bd[K - 1] * (1.0f + 0x1p-20f) + 1.0f;
+        }
+    };
+    auto load = [&](int64_t tile) {
+        __syncthreads();
+        const int64_t cc = tile + t;
+        if (cc < n) { const float4 c4 = col[cc]; sc[t] = make_float2(c4.x, c4.y); sl[t] = g.orig[cc]; }
+        else { sc[t] = make_float2(INFINITY, INFINITY); sl[t] = kNoIdx; }
+        __syncthreads();
+    };
+
+    // 1. the block's own tile (its rows' spatial neighbourhood in Morton
+    //    order) gives every row a first K-th distance
+    load(own * kTile);
+    scan(own * kTile, 0, (int)min((int64_t)kTile, n - own * kTile));
+
+    // 2. bounds of the block and of each wave: the largest K-th distance of
+    //    their rows (a squared radius), and their boxes
+    const float thr_w = wave_max(valid ? thrf : -INFINITY);
+    const float thr_b = block_reduce<float, true>(valid ? thrf : -INFINITY, redf);
+    const float4 rbox = g.box[own * kBoxStride];
+    float4 wbox = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+    for (int s = wave * (64 / kSubCols); s < (wave + 1) * (64 / kSubCols); ++s) {
+        const float4 sb = g.box[own * kBoxStride + 1 + s];
+        wbox.x = fminf(wbox.x, sb.x); wbox.y = fmaxf(wbox.y, sb.y);
+        wbox.z = fminf(wbox.z, sb.z); wbox.w = fmaxf(wbox.w, sb.w);
+    }
+    // squared distance between boxes (exact integer corners) against a
+    // squared radius, with a relative margin for the float rounding
+    auto near_box = [](float4 b, float4 r, float thr2) {
+        const float dx = fmaxf(0.0f, fmaxf(b.x - r.y, r.x - b.y));
+        const float dy = fmaxf(0.0f, fmaxf(b.z - r.w, r.z - b.w));
+        return fmaf(dx, dx, dy * dy) <= thr2 * (1.0f + 0x1p-16f);
+    };
+
+    // 3. the other tiles: tested in parallel against the block, compacted
+    //    in order; each wave then tests the sub-tiles against its own rows
+    for (int64_t base = 0; base < ntiles; base += kBlock) {
+        const int64_t ti = base + t;
+        const bool ok = ti < ntiles && ti != own && near_box(g.box[ti * kBoxStride], rbox, thr_b);
+        const unsigned long long mk = __ballot(ok);
+        __syncthreads();
+        if (lane == 0) wcnt[wave] = __popcll(mk);
+        __syncthreads();
+        int off = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            off += (w < wave) ? wcnt[w] : 0;
+            total += wcnt[w];
+        }
+        if (ok) tlist[off + __popcll(mk & ((1ULL << lane) - 1ULL))] = (int32_t)ti;
+        __syncthreads();
+        for (int j = 0; j < total; ++j) {
+            const int64_t tj = tlist[j];
+            load(tj * kTile);
+            const int ntile = (int)min((int64_t)kTile, n - tj * kTile);
+            const bool sp = lane < kSubs && lane * kSubCols < ntile &&
+                            near_box(g.box[tj * kBoxStride + 1 + lane], wbox, thr_w);
+            unsigned long long sm = __ballot(sp);
+            while (sm) {
+                const int sb = __ffsll((long long)sm) - 1;
+                sm &= sm - 1;
+                scan(tj * kTile, sb * kSubCols, min(sb * kSubCols + kSubCols, ntile));
             }
         }
     }
-    (void)lv;
     if (valid) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -1108,6 +1150,21 @@ __global__ __launch_bounds__(kBlock) void k_unpermute(const int64_t *lam_sorted,
     if (p < n) lam_label[orig[p]] = lam_sorted[p];
 }
 
+// the first thresholds' seeds from a previous run's four smallest per node
+// (labels, by label) as positions
+__global__ __launch_bounds__(kBlock) void k_seed_from_top(const int32_t *i4, const int32_t *orig, const int32_t *pos,
+                                                          int64_t n, int32_t *seed)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const int64_t v = orig[p];
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) {
+        const int32_t u = i4[kTop * v + j];
+        seed[j * n + p] = (u >= 0 && u < n) ? pos[u] : -1;
+    }
+}
+
 // four positions next to p in the sorted order (spatial neighbours): the
 // first iteration's threshold seeds
 __global__ __launch_bounds__(kBlock) void k_seed_neighbours(int64_t n, int32_t *seed)
@@ -1329,6 +1386,13 @@ hipError_t launch_unpermute(const int64_t *lam_sorted, const int32_t *orig, int6
                             hipStream_t st)
 {
     hipLaunchKernelGGL(k_unpermute, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam_sorted, orig, n, lam_label);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_from_top(const int32_t *i4, const int32_t *orig, const int32_t *pos, int64_t n, int32_t *seed,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_seed_from_top, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, i4, orig, pos, n, seed);
     return hipGetLastError();
 }
 

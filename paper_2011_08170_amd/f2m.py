@@ -28,7 +28,7 @@ SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gd
            "f2m_knn_graph", "f2m_solve_batch", "f2m_features", "f2m_mlp_forward", "f2m_mlp_grad", "f2m_mlp_adamw",
            "f2m_result_free", "f2m_status_str", "f2m_last_error")
 MLP_PARAMS = 18817
-WARM = {"cold": 0, "user": 1, "mlp": 2}
+WARM = {"cold": 0, "user": 1, "mlp": 2, "graph": 3}
 GRAPH = {"complete": 0, "knn": 1}
 
 
@@ -60,7 +60,7 @@ class Result(C.Structure):
                 ("pad0", C.c_int32), ("scan_slices", C.c_int64), ("scan_pairs", C.c_int64),
                 ("finish_phases", C.c_int64), ("finish_candidates", C.c_int64), ("finish_seconds", C.c_double * 3),
                 ("dual2_complete", C.c_int64), ("certified_complete", C.c_int32), ("pad1", C.c_int32),
-                ("graph_nnz", C.c_int64)]
+                ("graph_nnz", C.c_int64), ("warm_iterations", C.c_int64)]
 
 
 _lib = None
@@ -148,7 +148,7 @@ def _result_dict(res, n, st):
         finish_phases=res.finish_phases, finish_candidates=res.finish_candidates,
         finish_seconds=dict(zip(("collect", "build", "flow"), list(res.finish_seconds))),
         dual2_complete=res.dual2_complete, certified_complete=bool(res.certified_complete),
-        graph_nnz=res.graph_nnz,
+        graph_nnz=res.graph_nnz, warm_iterations=res.warm_iterations,
     )
     if res.trace_len:
         out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(
@@ -189,7 +189,7 @@ class Context:
 
     def solve(self, coords, *, max_iters=100000, handoff_div=300, finish="exact", lambda2_init=None,
               trace=False, chunk=0, stream=None, time_kernels=False, scan="culled", graph="complete", knn_k=10,
-              shape=None, mlp_theta=None):
+              shape=None, mlp_theta=None, warm=None):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
         array on the host or a contiguous int32 device tensor."""
         o = Opts()
@@ -216,6 +216,8 @@ class Context:
         if mlp_theta is not None:
             o.warm = WARM["mlp"]
             o.mlp_theta = _dptr(mlp_theta)
+        if warm is not None:
+            o.warm = WARM[warm]
         if hasattr(coords, "is_cuda") and coords.is_cuda:
             o.coords_on_device = 1
             n = coords.shape[0]

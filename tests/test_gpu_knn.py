@@ -94,3 +94,30 @@ def test_c3_shape_sampled_rows(ctx):
             assert all(v in theirs[i] for i in range(extra.size))
     r = ctx.solve(xy, graph="knn", knn_k=10)
     assert r["certified"] and r["graph_nnz"] == len(col)
+
+
+@pytest.mark.parametrize("name,make", [("uniform_2500", lambda: I.uniform(2500, 1000000, 11)),
+                                       ("clustered_3000", lambda: I.clustered(3000, 1000000, 12)),
+                                       ("lattice_ties", lambda: I.lattice_jitter(35, 36, 30, 2, 13))])
+def test_graph_warm_start_equals_oracle(ctx, name, make):
+    # the oracle's two stages: a cold GDP on the k = 10 candidate graph, then
+    # the complete-graph GDP from its Lam*; the GPU's seeds from the first
+    # stage change no bit of the second stage's trajectory
+    xy = make()
+    g = core.knn_graph(xy, 10)
+    og = core.gdp_solve(xy, graph=g, handoff_div=300)
+    oc = core.gdp_solve(xy, lam0=og["lam"], handoff_div=300)
+    r = ctx.solve(dev(xy), warm="graph", trace=True, handoff_div=300)
+    assert r["warm_iterations"] == og["iters"]
+    assert r["iterations"] == oc["iters"] and r["stop"] == oc["stop"] and r["kstar"] == oc["kstar"]
+    assert np.array_equal(r["trace"], oc["trace"])
+    assert np.array_equal(r["lambda2_gdp"], oc["lam"])
+    cold = ctx.solve(dev(xy))
+    assert r["certified"] and cold["certified"] and r["primal2"] == cold["primal2"]
+
+
+def test_graph_warm_start_small_n_is_cold(ctx):
+    xy = I.uniform(9, 1000, 3)   # n <= knn_k: no candidate graph, a cold start
+    r = ctx.solve(dev(xy), warm="graph")
+    c = ctx.solve(dev(xy))
+    assert r["warm_iterations"] == 0 and r["iterations"] == c["iterations"] and r["primal2"] == c["primal2"]
