@@ -36,6 +36,7 @@ namespace f2m {
 constexpr int kBlock = 256;   // threads per workgroup (4 waves of 64)
 constexpr int kTile = kTileCols;   // columns staged in LDS per tile
 constexpr int kGroup = 8;     // columns per filter test
+constexpr int kCollectBuf = 128;   // pairs a wave stages in LDS while collecting
 static_assert(kBlock == kTile, "one update block covers one column tile");
 static_assert(kSubCols % kGroup == 0, "filter groups do not straddle sub-tiles");
 constexpr int32_t kNoIdx = INT32_MAX;
@@ -331,6 +332,11 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
     }
 
     const int lane = t & 63;
+    // collection: per-wave staging of the pairs found (see scan_cols)
+    __shared__ int2 cbuf[kBlock / 64][kCollectBuf];
+    __shared__ int cfill_s[kBlock / 64];
+    volatile int *cfill = cfill_s;
+    if (MODE == kModeCollect && lane == 0) cfill[wave] = 0;
     // ordered (row, column) pairs of this wave's rows and the columns
     // [col0, col1), the diagonal excluded; wave-uniform
     unsigned long long tested = 0;
@@ -379,15 +385,32 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
                             if (z < 0) rn[r] += z;
                             continue;
                         }
-                        if (z > rw[r].theta) continue;
                         if (MODE == kModeCollect) {
-                            const unsigned long long slot = atomicAdd(a.count, 1ULL);
-                            if ((int64_t)slot < a.cap) {
-                                const int32_t lv = a.g.orig[rw[r].v], lu = so[g + q];
-                                a.out[slot] = make_int2(min(lv, lu), max(lv, lu));
+                            // the wave's pairs gather in its LDS buffer (the
+                            // lanes with a pair take consecutive places after
+                            // the wave's fill count); the buffer goes out at
+                            // the end with one atomic, a full buffer's excess
+                            // goes out at once
+                            const bool emit = z <= rw[r].theta;
+                            const unsigned long long em = __ballot(emit);
+                            if (em) {
+                                const int base = cfill[wave];
+                                if (emit) {
+                                    const int32_t lv = a.g.orig[rw[r].v], lu = so[g + q];
+                                    const int2 pr = make_int2(min(lv, lu), max(lv, lu));
+                                    const int slot = base + __popcll(em & ((1ULL << lane) - 1ULL));
+                                    if (slot < kCollectBuf) {
+                                        cbuf[wave][slot] = pr;
+                                    } else {
+                                        const unsigned long long gs = atomicAdd(a.count, 1ULL);
+                                        if ((int64_t)gs < a.cap) a.out[gs] = pr;
+                                    }
+                                }
+                                if (lane == __ffsll((long long)em) - 1) cfill[wave] = base + __popcll(em);
                             }
                             continue;
                         }
+                        if (z > rw[r].theta) continue;
                         if (z < 0) { ++neg[r]; rn[r] += z; }
                         else if (z == 0) ++zero[r];
                         top[r].insert(z, so[g + q]);
@@ -463,6 +486,15 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
     }
 
     if (a.tested && lane == 0 && tested) atomicAdd(a.tested, tested);
+    if (MODE == kModeCollect) {
+        __syncthreads();   // every lane's buffer writes are done
+        const int fill = min(cfill[wave], kCollectBuf);
+        unsigned long long base = 0;
+        if (lane == 0 && fill > 0) base = atomicAdd(a.count, (unsigned long long)fill);
+        base = __shfl(base, 0, 64);
+        for (int i = lane; i < fill; i += 64)
+            if ((int64_t)(base + i) < a.cap) a.out[base + i] = cbuf[wave][i];
+    }
     if (MODE == kModeGdp) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
