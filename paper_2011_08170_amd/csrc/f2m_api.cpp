@@ -36,12 +36,12 @@ struct f2m_ctx {
     // geometry of the current instance (sorted order)
     DevBuf xy, minmax, keys, keys_alt, ids, orig, pos, box, xy2max, sort_temp;
     // GDP loop state
-    DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, z4, i4, seed, ctrl, trace;
+    DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, pflag, z4, i4, seed, ctrl, trace;
     // trivial x
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
     // certificate / pair collection state
     DevBuf c_col, c_lam, c_tile_hmax, c_ctrl, c_deg, c_cnt, c_nb, c_acc, c_lam_label, c_eu, c_ev, c_ex;
-    DevBuf p_pairs, p_count, p_keys, p_keys2, p_keys3, p_temp, p_ucount, p_costs;
+    DevBuf p_pairs, p_count, p_keys, p_keys2, p_keys3, p_temp, p_ucount, p_costs, p_neg, p_deg, p_start, p_inc;
     // candidate graph
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
     // warm-start network
@@ -59,9 +59,9 @@ struct f2m_ctx {
     {
         DevBuf *all[] = {&xy, &minmax, &keys, &keys_alt, &ids, &orig, &pos, &box, &xy2max, &sort_temp,
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
-                         &prowneg, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
+                         &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
-                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &knn_nbr, &csr_keys,
+                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
                          &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
@@ -289,29 +289,55 @@ void certify_dev(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label, int6
 }
 
 // Sorts and de-duplicates `found` collected pairs on the device and copies
-// the distinct ones (increasing) and their exact costs to the host.
-void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const int32_t *xy_dev, PairList &out,
-                        std::vector<int32_t> &costs, hipStream_t st)
+// the distinct ones (increasing) and their exact costs to the host; with
+// lam_bulk (device, labels) also the finish's bulk data (see PairSource).
+void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const int32_t *xy_dev, int64_t n,
+                        const int64_t *lam_bulk, PairSource &src, PairList &out, hipStream_t st)
 {
     out.clear();
-    costs.clear();
+    src.costs.clear();
+    src.neg.clear();
+    src.inc_start.clear();
+    src.inc.clear();
     if (found <= 0) return;
-    uint64_t *k1 = grow<uint64_t>(ctx, ctx->p_keys, found);
-    uint64_t *k2 = grow<uint64_t>(ctx, ctx->p_keys2, found);
+    uint64_t *k1 = grow<uint64_t>(ctx, ctx->p_keys, 2 * found);
+    uint64_t *k2 = grow<uint64_t>(ctx, ctx->p_keys2, 2 * found);
     uint64_t *k3 = grow<uint64_t>(ctx, ctx->p_keys3, found);
     int32_t *cd = grow<int32_t>(ctx, ctx->p_costs, found);
     int64_t *uc = grow<int64_t>(ctx, ctx->p_ucount, 1);
-    const size_t tb = pair_sort_temp_bytes(found);
+    size_t tb = pair_sort_temp_bytes(found);
+    if (lam_bulk) tb = std::max(tb, pair_bulk_temp_bytes(found, n));
     void *temp = grow<char>(ctx, ctx->p_temp, tb);
-    ck(ctx, launch_sort_unique_pairs(pairs, found, k1, k2, k3, uc, temp, tb, xy_dev, cd, st), "sort_unique");
+    ck(ctx, launch_sort_unique_pairs(pairs, found, k1, k2, k3, uc, temp, tb, xy_dev, lam_bulk ? nullptr : cd, st),
+       "sort_unique");
+    uint8_t *ng = nullptr;
+    int32_t *deg = nullptr, *stt = nullptr, *inc = nullptr;
+    if (lam_bulk) {
+        // k1, k2 are free again: the incidences sort through them
+        ng = grow<uint8_t>(ctx, ctx->p_neg, found);
+        deg = grow<int32_t>(ctx, ctx->p_deg, n + 1);
+        stt = grow<int32_t>(ctx, ctx->p_start, n + 1);
+        inc = grow<int32_t>(ctx, ctx->p_inc, 2 * found);
+        ck(ctx, launch_pair_bulk(k3, uc, found, xy_dev, lam_bulk, n, cd, ng, k1, k2, deg, stt, inc, temp, tb, st),
+           "pair_bulk");
+    }
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, uc, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     const int64_t u = ctx->scratch_host[0];
     std::vector<uint64_t> h(u);
-    costs.resize(u);
+    src.costs.resize(u);
     if (u) {
         ck(ctx, hipMemcpyAsync(h.data(), k3, u * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipMemcpyAsync(costs.data(), cd, u * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(src.costs.data(), cd, u * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        if (lam_bulk) {
+            src.neg.resize(u);
+            src.inc_start.resize(n + 1);
+            src.inc.resize(2 * u);
+            ck(ctx, hipMemcpyAsync(src.neg.data(), ng, u, hipMemcpyDeviceToHost, st), "copy");
+            ck(ctx, hipMemcpyAsync(src.inc_start.data(), stt, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+               "copy");
+            ck(ctx, hipMemcpyAsync(src.inc.data(), inc, 2 * u * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        }
     }
     ck(ctx, hipStreamSynchronize(st), "sync");
     out.reserve(u);
@@ -366,7 +392,7 @@ private:
                 ck(ctx, hipStreamSynchronize(st_), "sync");
                 const int64_t found = ctx->scratch_host[0];
                 if (found > cap) { cap = found + found / 4; continue; }
-                fetch_unique_pairs(ctx, pairs, found, gh_.xy, out, costs, st_);
+                fetch_unique_pairs(ctx, pairs, found, gh_.xy, n, (want_bulk && seed) ? lam : nullptr, *this, out, st_);
                 cap_ = cap;
                 return true;
             }
@@ -468,7 +494,7 @@ private:
             ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st_), "copy");
             ck(ctx, hipStreamSynchronize(st_), "sync");
             const int64_t found = std::min<int64_t>(ctx->scratch_host[0], cap);
-            fetch_unique_pairs(ctx, pairs, found, gh_.xy, out, costs, st_);
+            fetch_unique_pairs(ctx, pairs, found, gh_.xy, n, want_bulk ? lam : nullptr, *this, out, st_);
             return true;
         } catch (const Fail &) {
             err = ctx_->err;
@@ -512,6 +538,8 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     int32_t *pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
     int32_t *pzero = grow<int32_t>(ctx, ctx->pzero, sh.slices * n);
     int64_t *prn = grow<int64_t>(ctx, ctx->prowneg, sh.slices * n);
+    const int64_t nrb = (n + (int64_t)kTileCols * sh.rows - 1) / ((int64_t)kTileCols * sh.rows);
+    int32_t *pflag = grow<int32_t>(ctx, ctx->pflag, sh.slices * nrb);
     int64_t *z4 = grow<int64_t>(ctx, ctx->z4, kTop * n);
     int32_t *i4 = grow<int32_t>(ctx, ctx->i4, kTop * n);
     int32_t *seed = grow<int32_t>(ctx, ctx->seed, kTop * n);
@@ -561,11 +589,13 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             sa.tested = &cd->pairs_tested;
             sa.seed = seed;
             sa.pz = pz; sa.pi = pi; sa.pneg = pneg; sa.pzero = pzero; sa.prowneg = prn;
+            sa.pflag = pflag;
+            sa.nrb = nrb;
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
             ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
             UpdateArgs ua{gh.g, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
-                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace};
+                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pflag, nrb, sh.rows};
             ck(ctx, launch_update(ua, st), "update");
         }
         ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");

@@ -45,6 +45,50 @@ public:
 
     int64_t edges() const { return (int64_t)ea_.size(); }
 
+    // The first candidates in bulk: the pair source's costs, the initial
+    // flow (negative-reduced-cost bits under the starting potentials) and
+    // the incidence lists.  False (nothing changed) when the cover already
+    // has edges or the data does not fit; then add() does the work.
+    bool add_bulk(const PairList &pl, const PairSource &src)
+    {
+        const size_t m = pl.size();
+        if (!ea_.empty() || m == 0 || src.costs.size() != m || src.neg.size() != m ||
+            src.inc_start.size() != (size_t)n_ + 1 || src.inc.size() != 2 * m || src.inc_start[n_] != (int64_t)(2 * m))
+            return false;
+        for (size_t i = 0; i < m; ++i) {
+            const int64_t a = pl[i].first, b = pl[i].second;
+            if (a < 0 || a >= b || b >= n_) return false;
+            if (i > 0 && (pl[i - 1].first > a || (pl[i - 1].first == a && pl[i - 1].second >= b))) return false;
+        }
+        keys_.resize(m);
+        ea_.resize(m);
+        eb_.resize(m);
+        ec_.resize(m);
+        y_.resize(2 * m);
+        for (size_t i = 0; i < m; ++i) {
+            const int32_t a = pl[i].first, b = pl[i].second;
+            keys_[i] = (uint64_t)a * (uint64_t)n_ + (uint64_t)b;
+            ea_[i] = a;
+            eb_[i] = b;
+            ec_[i] = src.costs[i];
+            const uint8_t f = src.neg[i];
+            y_[2 * i] = f & 1;
+            y_[2 * i + 1] = (f >> 1) & 1;
+            if (f & 1) {
+                --ex_[a];
+                if (++ex_[n_ + b] == 1) src_.push_back(n_ + b);
+            }
+            if (f & 2) {
+                --ex_[b];
+                if (++ex_[n_ + a] == 1) src_.push_back(n_ + a);
+            }
+        }
+        start_.assign(src.inc_start.begin(), src.inc_start.end());
+        inc_ = src.inc;
+        built_ = (int64_t)m;
+        return true;
+    }
+
     // Adds new candidate edges (a sorted list of distinct pairs); arcs of
     // negative reduced cost start saturated.
     void add(const PairList &pl, const std::vector<int32_t> &costs)
@@ -423,10 +467,13 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
     std::string err;
     PairList pl;
     int64_t slack = 16;
-    if (!src.near(lam0, slack, pl, err)) { r.msg = err; return; }
+    src.want_bulk = true;
+    const bool got = src.near(lam0, slack, pl, err);
+    src.want_bulk = false;
+    if (!got) { r.msg = err; return; }
     r.t_collect += secs() - t;
     t = secs();
-    g.add(pl, src.costs);
+    if (!g.add_bulk(pl, src)) g.add(pl, src.costs);
     r.t_build += secs() - t;
     std::vector<int64_t> lam;
     for (int round = 0; round < 64; ++round) {

@@ -37,6 +37,15 @@ struct PairSource {
     // when the source computes them (else left empty: the finish computes
     // them itself)
     std::vector<int32_t> costs;
+    // Bulk data the finish asks for (want_bulk) on its first call, for the
+    // pairs returned in the same order: neg bit 0 / bit 1 = the arc u'->v''
+    // / v'->u'' has negative reduced cost c - alpha_tail - beta_head under
+    // alpha = floor(lam/2), beta = lam - alpha of the lam passed, and every
+    // node's incident pair indices in increasing order (inc_start[n + 1],
+    // inc[2 * pairs]).  Left empty by sources that do not compute them.
+    bool want_bulk = false;
+    std::vector<uint8_t> neg;
+    std::vector<int32_t> inc_start, inc;
     // pairs {u, v} with Z_uv(lam) <= max(0, 4th smallest Z at u or v) + slack
     virtual bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) = 0;
     // pairs {u, v} with Z_uv(lam) < 0

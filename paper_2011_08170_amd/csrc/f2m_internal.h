@@ -106,6 +106,10 @@ struct ScanArgs {
     unsigned long long *count;
     int2 *out;
     int64_t cap;
+    // GDP mode, optional: pflag[slice * nrb + row block] = 1 when the block
+    // had a column tile to scan; a block without one writes no partials
+    int32_t *pflag;
+    int64_t nrb;                // row blocks of the launch
 };
 
 struct UpdateArgs {
@@ -130,6 +134,10 @@ struct UpdateArgs {
     int64_t *step;              // [n] by label, or null
     Ctrl *ctrl;
     int64_t *trace;             // [trace_cap][8] or null
+    // optional: the scan's flags (see ScanArgs); slices without one are skipped
+    const int32_t *pflag;
+    int64_t nrb;
+    int64_t scan_rows;          // rows per lane of the scan (tiles per scan row block)
 };
 
 // Candidate graph (k nearest neighbours, union-symmetrised) in CSR over
@@ -195,6 +203,16 @@ hipError_t launch_graph_collect(const Geo &g, const Csr &csr, const int64_t *lam
 // the distinct count lands in *count_dev; with costs non-null, costs[i] is
 // the exact cost of keys_out[i] from the label-order coordinates xy
 size_t pair_sort_temp_bytes(int64_t count);
+// Bulk candidate data for the exact finish from the distinct keys (count on
+// the device, at most cap): exact costs, the negative-reduced-cost bits of
+// the two arcs under alpha = floor(Lam/2), beta = Lam - alpha (lam by label),
+// and every node's incident pair ids in increasing order, as start[n + 1]
+// (int32) and inc[2 * count]
+size_t pair_bulk_temp_bytes(int64_t count, int64_t n);
+hipError_t launch_pair_bulk(const uint64_t *keys, const int64_t *count_dev, int64_t cap, const int32_t *xy,
+                            const int64_t *lam, int64_t n, int32_t *costs, uint8_t *neg, uint64_t *inc_keys,
+                            uint64_t *inc_sorted, int32_t *deg, int32_t *start, int32_t *inc, void *temp,
+                            size_t temp_bytes, hipStream_t st);
 hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *keys, uint64_t *keys_sorted,
                                     uint64_t *keys_out, int64_t *count_dev, void *temp, size_t temp_bytes,
                                     const int32_t *xy, int32_t *costs, hipStream_t st);

@@ -432,6 +432,7 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         __syncthreads();
     };
 
+    bool any = !CULL;   // block-uniform: some column tile was scanned
     if (!CULL) {
         for (int64_t tile = c0; tile < c1; tile += kTile) {
             load_tile(tile);
@@ -464,6 +465,7 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
             }
             if (ok) tlist[off + __popcll(mk & ((1ULL << lane) - 1ULL))] = (int32_t)(ti - t0);
             __syncthreads();
+            any = any || total > 0;
             for (int j = 0; j < total; ++j) {
                 const int64_t tj = t0 + tlist[j];
                 const int64_t tile = tj * kTile;
@@ -495,7 +497,8 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         for (int i = lane; i < fill; i += 64)
             if ((int64_t)(base + i) < a.cap) a.out[base + i] = cbuf[wave][i];
     }
-    if (MODE == kModeGdp) {
+    if (MODE == kModeGdp && a.pflag && t == 0) a.pflag[sl * a.nrb + rblk] = any ? 1 : 0;
+    if (MODE == kModeGdp && (any || !a.pflag)) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t p = rw[r].v;
@@ -692,13 +695,32 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
         Top4 top;
         top.clear();
         int64_t cn = 0, cz = 0, rn = 0;
-        for (int64_t sl = 0; sl < a.nslices; ++sl) {
+        // slices in groups of four: the group's loads are issued together,
+        // then merged (the merge order does not matter: (Z, u) is a total
+        // order and the counts are sums)
+        constexpr int kG = 4;
+        for (int64_t s0 = 0; s0 < a.nslices; s0 += kG) {
+            int64_t gz[kG][kTop];
+            int32_t gi[kG][kTop];
 #pragma unroll
-            for (int j = 0; j < kTop; ++j)
-                top.insert(a.pz[(sl * kTop + j) * n + p], a.pi[(sl * kTop + j) * n + p]);
-            cn += a.pneg[sl * n + p];
-            cz += a.pzero[sl * n + p];
-            rn += a.prowneg[sl * n + p];
+            for (int q = 0; q < kG; ++q) {
+                const int64_t sl = s0 + q;
+                const bool ok = sl < a.nslices && (!a.pflag || a.pflag[sl * a.nrb + blk / a.scan_rows] != 0);
+#pragma unroll
+                for (int j = 0; j < kTop; ++j) {
+                    gz[q][j] = ok ? a.pz[(sl * kTop + j) * n + p] : INT64_MAX;
+                    gi[q][j] = ok ? a.pi[(sl * kTop + j) * n + p] : kNoIdx;
+                }
+                if (ok) {
+                    cn += a.pneg[sl * n + p];
+                    cz += a.pzero[sl * n + p];
+                    rn += a.prowneg[sl * n + p];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kG; ++q)
+#pragma unroll
+                for (int j = 0; j < kTop; ++j) top.insert(gz[q][j], gi[q][j]);
         }
         step_row(a.g, p, top, cn, cz, rn, a.lam_in[p], copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
                  a.neg, a.zero, a.step, a.col, o);
@@ -1026,15 +1048,54 @@ __global__ __launch_bounds__(kBlock) void k_pair_to_key(const int2 *pairs, int64
     if (i < count) keys[i] = ((uint64_t)(uint32_t)pairs[i].x << 32) | (uint64_t)(uint32_t)pairs[i].y;
 }
 
-// exact cost of each distinct pair key (labels a << 32 | b); count on the device
-__global__ __launch_bounds__(kBlock) void k_key_costs(const uint64_t *keys, const int64_t *count, const int32_t *xy,
-                                                      int32_t *cost)
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t count, int32_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= *count) return;
+    if (i < count) p[i] = v;
+}
+
+__device__ __forceinline__ int64_t floor_half_d(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
+
+// Per distinct pair key i (labels a << 32 | b, count on the device): the
+// exact cost, and with lam (labels) the bits "arc a'->b'' (bit 0) / b'->a''
+// (bit 1) has negative reduced cost c - alpha_tail - beta_head" for
+// alpha = floor(Lam/2), beta = Lam - alpha; inc_keys gets (a << 32 | i) and
+// (b << 32 | i), the incidences to sort; slots past the count get ~0.
+__global__ __launch_bounds__(kBlock) void k_key_info(const uint64_t *keys, const int64_t *count, int64_t cap,
+                                                     const int32_t *xy, const int64_t *lam, int32_t *cost,
+                                                     uint8_t *neg, uint64_t *inc_keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= cap) return;
+    const int64_t u = *count;
+    if (i >= u) {
+        if (inc_keys) { inc_keys[2 * i] = ~0ULL; inc_keys[2 * i + 1] = ~0ULL; }
+        return;
+    }
     const int64_t a = (int64_t)(keys[i] >> 32), b = (int64_t)(keys[i] & 0xffffffffULL);
     const int64_t dx = (int64_t)xy[2 * a] - xy[2 * b], dy = (int64_t)xy[2 * a + 1] - xy[2 * b + 1];
-    cost[i] = (int32_t)nint_sqrt(dx * dx + dy * dy);
+    const int64_t c = nint_sqrt(dx * dx + dy * dy);
+    cost[i] = (int32_t)c;
+    if (lam) {
+        const int64_t aa = floor_half_d(lam[a]), ab = floor_half_d(lam[b]);
+        const int64_t ba = lam[a] - aa, bb = lam[b] - ab;
+        neg[i] = (uint8_t)((c - aa - bb < 0 ? 1 : 0) | (c - ab - ba < 0 ? 2 : 0));
+    }
+    if (inc_keys) {
+        inc_keys[2 * i] = ((uint64_t)a << 32) | (uint64_t)i;
+        inc_keys[2 * i + 1] = ((uint64_t)b << 32) | (uint64_t)i;
+    }
+}
+
+// sorted incidences -> per-node counts (deg zeroed, n + 1 entries) and the edge ids
+__global__ __launch_bounds__(kBlock) void k_inc_split(const uint64_t *sorted, const int64_t *count, int32_t *deg,
+                                                      int32_t *inc)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= 2 * *count) return;
+    const uint64_t k = sorted[j];
+    inc[j] = (int32_t)(k & 0xffffffffULL);
+    atomicAdd(&deg[(k >> 32) + 1], 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_label_degrees(Geo g, Csr csr, int32_t *deg)
@@ -1589,11 +1650,38 @@ hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *
     e = hipcub::DeviceSelect::Unique(temp, tb, keys_sorted, keys_out, count_dev, (int)count, st);
     if (e != hipSuccess) return e;
     if (costs) {
-        hipLaunchKernelGGL(k_key_costs, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, keys_out, count_dev, xy,
-                           costs);
+        hipLaunchKernelGGL(k_key_info, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, keys_out, count_dev,
+                           count, xy, (const int64_t *)nullptr, costs, (uint8_t *)nullptr, (uint64_t *)nullptr);
         e = hipGetLastError();
     }
     return e;
+}
+
+size_t pair_bulk_temp_bytes(int64_t count, int64_t n)
+{
+    size_t a = 0, b = 0;
+    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                            (int)(2 * count), 0, 64);
+    (void)hipcub::DeviceScan::InclusiveSum(nullptr, b, (const int32_t *)nullptr, (int32_t *)nullptr, (int)(n + 1));
+    return a > b ? a : b;
+}
+
+hipError_t launch_pair_bulk(const uint64_t *keys, const int64_t *count_dev, int64_t cap, const int32_t *xy,
+                            const int64_t *lam, int64_t n, int32_t *costs, uint8_t *neg, uint64_t *inc_keys,
+                            uint64_t *inc_sorted, int32_t *deg, int32_t *start, int32_t *inc, void *temp,
+                            size_t temp_bytes, hipStream_t st)
+{
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_key_info, dim3(blocks_for(cap, kBlock)), dim3(kBlock), 0, st, keys, count_dev, cap, xy, lam,
+                       costs, neg, inc_keys);
+    size_t tb = temp_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, tb, inc_keys, inc_sorted, (int)(2 * cap), 0, 64, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n + 1, kBlock)), dim3(kBlock), 0, st, deg, n + 1, 0);
+    hipLaunchKernelGGL(k_inc_split, dim3(blocks_for(2 * cap, kBlock)), dim3(kBlock), 0, st, inc_sorted, count_dev, deg,
+                       inc);
+    tb = temp_bytes;
+    return hipcub::DeviceScan::InclusiveSum(temp, tb, deg, start, (int)(n + 1), st);
 }
 
 hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_sorted, unsigned long long *acc,
