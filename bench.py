@@ -35,6 +35,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(key):
+    """HBM bytes per launch from the committed rocprofv3 counters
+    (profiles/traffic.json), or None when the kernel source has changed
+    since they were taken or the workload differs."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(here, "profiles", "traffic.json")) as f:
+            t = json.load(f)
+        with open(os.path.join(here, t["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if sha != t.get("sha256"):
+        return None
+    return t.get("bytes_per_launch", {}).get(key)
+
+
 def cpu_baseline(xy, lam, budget_s):
     """The oracle's plain per-row GDP pass on a sample of rows of the same
     instance, scaled to unordered pair evaluations per second."""
@@ -156,7 +174,8 @@ def main():
             achieved = ops / (avg_ms * 1e-3) / 1e12
             roof = {"bound": "alu", "kernel": "k_rowscan<%d,gdp>" % runs[-1]["scan_rows"], "achieved": achieved,
                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                    "traffic": None, "avg_launch_ms": avg_ms, "launches": launches,
+                    "traffic": measured_traffic("complete|%s|%s|%d" % (args.scan, args.instance, n)),
+                    "avg_launch_ms": avg_ms, "launches": launches,
                     "pairs_tested_per_launch": tested, "ops_per_launch": ops,
                     "slices": runs[-1]["scan_slices"]}
             value = iters * pairs / elapsed
@@ -167,7 +186,8 @@ def main():
             nbytes = n * 72 + nnz * 20
             achieved = nbytes / (avg_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "kernel": "k_graph_step", "achieved": achieved, "peak": 8000.0,
-                    "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None, "avg_launch_ms": avg_ms,
+                    "unit": "GB/s", "frac": achieved / 8000.0,
+                    "traffic": measured_traffic("knn|%s|%d" % (args.instance, n)), "avg_launch_ms": avg_ms,
                     "launches": launches, "bytes_per_launch": nbytes, "nnz": nnz}
             value = iters * nnz / 2 / elapsed
         out = {
