@@ -352,77 +352,116 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
     };
     // every row of this lane against the LDS columns [g0, g1) of the tile
     // that starts at position `tile`
+    // the exact evaluation of column c of the LDS tile (position tile + c)
+    // for row r, after the float filter passed it
+    auto eval_col = [&](int r, int64_t tile, int c) {
+        const int64_t u = tile + c;
+        if (u >= c1 || u == rw[r].v) return;
+        const float4 cd = sc[c];
+        if (!(filter_value(rw[r], cd) <= rw[r].thr)) return;   // theta may have dropped
+        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, slam[c]);
+        if (MODE == kModeCert) {
+            if (z < 0) rn[r] += z;
+            return;
+        }
+        if (MODE == kModeCollect) {
+            // the wave's pairs gather in its LDS buffer (the lanes with a
+            // pair take consecutive places after the wave's fill count); the
+            // buffer goes out at the end with one atomic, a full buffer's
+            // excess goes out at once
+            const bool emit = z <= rw[r].theta;
+            const unsigned long long em = __ballot(emit);
+            if (em) {
+                const int base = cfill[wave];
+                if (emit) {
+                    const int32_t lv = a.g.orig[rw[r].v], lu = so[c];
+                    const int2 pr = make_int2(min(lv, lu), max(lv, lu));
+                    const int slot = base + __popcll(em & ((1ULL << lane) - 1ULL));
+                    if (slot < kCollectBuf) {
+                        cbuf[wave][slot] = pr;
+                    } else {
+                        const unsigned long long gs = atomicAdd(a.count, 1ULL);
+                        if ((int64_t)gs < a.cap) a.out[gs] = pr;
+                    }
+                }
+                if (lane == __ffsll((long long)em) - 1) cfill[wave] = base + __popcll(em);
+            }
+            return;
+        }
+        if (z > rw[r].theta) return;
+        if (z < 0) { ++neg[r]; rn[r] += z; }
+        else if (z == 0) ++zero[r];
+        top[r].insert(z, so[c]);
+        if (top[r].id[3] != kNoIdx) {
+            const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
+            if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
+        }
+    };
+    // the float filter over the group of kGroup columns at g: per row a bit
+    // mask of the columns that pass (0 when none can)
+    auto filter_group = [&](int g, unsigned (&pm)[R]) {
+        float m[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) m[r] = INFINITY;
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            const float4 cd = sc[g + q];
+#pragma unroll
+            for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            pm[r] = 0;
+            if (m[r] <= rw[r].thr) {
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q)
+                    pm[r] |= (filter_value(rw[r], sc[g + q]) <= rw[r].thr) ? (1u << q) : 0u;
+            }
+        }
+    };
+    // every row of this lane against the LDS columns [g0, g1), evaluated
+    // group by group: each lane walks its own passing columns, so lanes
+    // passing at different columns are evaluated together
     auto scan_cols = [&](int64_t tile, int g0, int g1) {
         for (int g = g0; g < g1; g += kGroup) {
-            float m[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) m[r] = INFINITY;
-#pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
-                const float4 cd = sc[g + q];
-#pragma unroll
-                for (int r = 0; r < R; ++r) m[r] = fminf(m[r], filter_value(rw[r], cd));
-            }
+            unsigned pm[R];
+            filter_group(g, pm);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (m[r] <= rw[r].thr) {
-                    // this row's passing columns of the group as a bit mask;
-                    // each lane then walks its own bits, so lanes passing at
-                    // different columns are evaluated together
-                    unsigned pm = 0;
-#pragma unroll
-                    for (int q = 0; q < kGroup; ++q)
-                        pm |= (filter_value(rw[r], sc[g + q]) <= rw[r].thr) ? (1u << q) : 0u;
-                    while (pm) {
-                        const int q = __ffs(pm) - 1;
-                        pm &= pm - 1;
-                        const int64_t u = tile + g + q;
-                        if (u >= c1 || u == rw[r].v) continue;
-                        const float4 cd = sc[g + q];
-                        if (!(filter_value(rw[r], cd) <= rw[r].thr)) continue;   // theta may have dropped
-                        const int64_t z = exact_z(rw[r].xv, rw[r].yv, rw[r].lamv, cd.x, cd.y, slam[g + q]);
-                        if (MODE == kModeCert) {
-                            if (z < 0) rn[r] += z;
-                            continue;
-                        }
-                        if (MODE == kModeCollect) {
-                            // the wave's pairs gather in its LDS buffer (the
-                            // lanes with a pair take consecutive places after
-                            // the wave's fill count); the buffer goes out at
-                            // the end with one atomic, a full buffer's excess
-                            // goes out at once
-                            const bool emit = z <= rw[r].theta;
-                            const unsigned long long em = __ballot(emit);
-                            if (em) {
-                                const int base = cfill[wave];
-                                if (emit) {
-                                    const int32_t lv = a.g.orig[rw[r].v], lu = so[g + q];
-                                    const int2 pr = make_int2(min(lv, lu), max(lv, lu));
-                                    const int slot = base + __popcll(em & ((1ULL << lane) - 1ULL));
-                                    if (slot < kCollectBuf) {
-                                        cbuf[wave][slot] = pr;
-                                    } else {
-                                        const unsigned long long gs = atomicAdd(a.count, 1ULL);
-                                        if ((int64_t)gs < a.cap) a.out[gs] = pr;
-                                    }
-                                }
-                                if (lane == __ffsll((long long)em) - 1) cfill[wave] = base + __popcll(em);
-                            }
-                            continue;
-                        }
-                        if (z > rw[r].theta) continue;
-                        if (z < 0) { ++neg[r]; rn[r] += z; }
-                        else if (z == 0) ++zero[r];
-                        top[r].insert(z, so[g + q]);
-                        if (top[r].id[3] != kNoIdx) {
-                            const int64_t nt = top[r].z[3] > 0 ? top[r].z[3] : 0;
-                            if (nt < rw[r].theta) { rw[r].theta = nt; set_filter(rw[r], colmax); }
-                        }
-                    }
+                while (pm[r]) {
+                    const int q = __ffs(pm[r]) - 1;
+                    pm[r] &= pm[r] - 1;
+                    eval_col(r, tile, g + q);
                 }
             }
         }
     };
+    // culled scan with one row per lane: the passing columns of a whole
+    // tile are gathered first (one bit per column, in LDS) and evaluated
+    // after the tile's last sub-tile, so a lane's evaluations wait for no
+    // other lane's
+    __shared__ uint32_t cmask[CULL && R == 1 ? kSubs : 1][kBlock];
+    auto mark_cols = [&](int g0, int g1) {
+        for (int g = g0; g < g1; g += kGroup) {
+            unsigned pm[R];
+            filter_group(g, pm);
+            if (pm[0]) cmask[g >> 5][t] |= pm[0] << (g & 31);
+        }
+    };
+    auto eval_marked = [&](int64_t tile, unsigned long long subs) {
+        while (subs) {
+            const int w = __ffsll((long long)subs) - 1;
+            subs &= subs - 1;
+            uint32_t b = cmask[w][t];
+            cmask[w][t] = 0;
+            while (b) {
+                const int q = __ffs(b) - 1;
+                b &= b - 1;
+                eval_col(0, tile, w * 32 + q);
+            }
+        }
+    };
+    static_assert(kSubCols == 32, "one mask word per sub-tile");
     auto load_tile = [&](int64_t tile) {
         __syncthreads();
         const int64_t cc = tile + t;
@@ -432,6 +471,10 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         __syncthreads();
     };
 
+    if (CULL && R == 1) {
+#pragma unroll
+        for (int w = 0; w < kSubs; ++w) cmask[w][t] = 0;
+    }
     bool any = !CULL;   // block-uniform: some column tile was scanned
     if (!CULL) {
         for (int64_t tile = c0; tile < c1; tile += kTile) {
@@ -474,15 +517,17 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
                 const bool sp = lane < kSubs && lane * kSubCols < ntile &&
                                 may_pass(a.g.box[tj * kBoxStride + 1 + lane], wbox, hvw,
                                          a.lv.tile_hmax[tj * kBoxStride + 1 + lane]);
-                unsigned long long sm = __ballot(sp);
-                while (sm) {
+                const unsigned long long sm0 = __ballot(sp);
+                for (unsigned long long sm = sm0; sm;) {
                     const int sb = __ffsll((long long)sm) - 1;
                     sm &= sm - 1;
                     const int g0 = sb * kSubCols;
                     const int g1 = min(g0 + kSubCols, ntile);
                     count_tested(tile + g0, tile + g1);
-                    scan_cols(tile, g0, g1);
+                    if (R == 1) mark_cols(g0, g1);
+                    else scan_cols(tile, g0, g1);
                 }
+                if (R == 1) eval_marked(tile, sm0);
             }
         }
     }
