@@ -553,7 +553,7 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
         ck(ctx, hipMemsetAsync(l0, 0, n * sizeof(int64_t), st), "memset");
     ck(ctx, launch_ctrl_init(cd, max_iters, trace_cap, handoff_div, st), "ctrl_init");
     ck(ctx, launch_set_lam(l0, gh.g.orig, n, lam[0], col, thm, cd, st), "set_lam");
-    if (!keep_seeds) ck(ctx, launch_seed_neighbours(n, seed, st), "seed");
+    if (!keep_seeds) ck(ctx, launch_seed_neighbours(n, col, seed, st), "seed");
     ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2_init| must be below 2^38");
@@ -983,7 +983,7 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
         int64_t *trace = grow<int64_t>(ctx, ctx->trace, kTraceW);
         ck(ctx, launch_ctrl_init(cd, INT64_MAX, 1, 0, st), "ctrl_init");
         ck(ctx, launch_set_lam(lam_in, gh.g.orig, n, ls, col, thm, cd, st), "set_lam");
-        ck(ctx, launch_seed_neighbours(n, seed, st), "seed");
+        ck(ctx, launch_seed_neighbours(n, col, seed, st), "seed");
         ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
         ck(ctx, hipStreamSynchronize(st), "sync");
         if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| must be below 2^38");
@@ -1354,7 +1354,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             ck(ctx, launch_ctrl_init(ctrl + i, o.max_iters, trace_cap, o.handoff_div, st), "ctrl_init");
             ck(ctx, launch_set_lam(lamlabel + X, orig + P[i], n, lam0 + P[i], col + P[i], thm + T[i], ctrl + i, st),
                "set_lam");
-            ck(ctx, launch_seed_neighbours(n, seed + kTop * X, st), "seed");
+            ck(ctx, launch_seed_neighbours(n, col + P[i], seed + kTop * X, st), "seed");
             nb_host[i] = ntiles_of(n);
         }
         ck(ctx, hipMemcpyAsync(nblk, nb_host.data(), n_inst * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");

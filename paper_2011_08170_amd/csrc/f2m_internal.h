@@ -239,7 +239,7 @@ hipError_t launch_unpermute(const int64_t *lam_sorted, const int32_t *orig, int6
 // seeds (positions, [4][n]) from the four smallest of a previous run (labels, [n][4] by label)
 hipError_t launch_seed_from_top(const int32_t *i4, const int32_t *orig, const int32_t *pos, int64_t n, int32_t *seed,
                                 hipStream_t st);
-hipError_t launch_seed_neighbours(int64_t n, int32_t *seed, hipStream_t st);
+hipError_t launch_seed_neighbours(int64_t n, const float4 *col, int32_t *seed, hipStream_t st);
 hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div,
                             hipStream_t st);
 hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_per_thread, hipStream_t st);

@@ -1303,9 +1303,12 @@ __global__ __launch_bounds__(kBlock) void k_seed_from_top(const int32_t *i4, con
     }
 }
 
-// four positions next to p in the sorted order (spatial neighbours): the
-// first iteration's threshold seeds
-__global__ __launch_bounds__(kBlock) void k_seed_neighbours(int64_t n, int32_t *seed)
+// The first scan's threshold seeds: the four nearest (by exact D, then
+// position) among the positions within kSeedWin of p in the sorted order
+// (Morton order keeps most nearest neighbours close); any four columns
+// bound the 4th smallest Z, close ones tightly.
+constexpr int kSeedWin = 16;
+__global__ __launch_bounds__(kBlock) void k_seed_neighbours(int64_t n, const float4 *col, int32_t *seed)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
@@ -1313,11 +1316,30 @@ __global__ __launch_bounds__(kBlock) void k_seed_neighbours(int64_t n, int32_t *
         for (int j = 0; j < kTop; ++j) seed[j * n + p] = -1;
         return;
     }
-    int64_t lo = p - 2;
-    lo = lo < 0 ? 0 : (lo > n - 5 ? n - 5 : lo);
-    int j = 0;
-    for (int64_t q = lo; q < lo + 5; ++q)
-        if (q != p) seed[(j++) * n + p] = (int32_t)q;
+    const float4 cv = col[p];
+    int64_t bd[kTop];
+    int32_t bq[kTop];
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) { bd[j] = INT64_MAX; bq[j] = -1; }
+    const int64_t lo = p - kSeedWin < 0 ? 0 : p - kSeedWin;
+    const int64_t hi = p + kSeedWin >= n ? n - 1 : p + kSeedWin;
+    for (int64_t q = lo; q <= hi; ++q) {
+        if (q == p) continue;
+        const float4 cu = col[q];
+        const int32_t dx = (int32_t)(cv.x - cu.x), dy = (int32_t)(cv.y - cu.y);
+        int64_t d = (int64_t)dx * dx + (int64_t)dy * dy;
+        int32_t qq = (int32_t)q;
+        if (d >= bd[kTop - 1]) continue;
+#pragma unroll
+        for (int j = 0; j < kTop; ++j) {
+            if (d < bd[j]) {
+                const int64_t td = bd[j]; bd[j] = d; d = td;
+                const int32_t tq = bq[j]; bq[j] = qq; qq = tq;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) seed[j * n + p] = bq[j];
 }
 
 __global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div)
@@ -1534,9 +1556,9 @@ hipError_t launch_seed_from_top(const int32_t *i4, const int32_t *orig, const in
     return hipGetLastError();
 }
 
-hipError_t launch_seed_neighbours(int64_t n, int32_t *seed, hipStream_t st)
+hipError_t launch_seed_neighbours(int64_t n, const float4 *col, int32_t *seed, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_seed_neighbours, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, n, seed);
+    hipLaunchKernelGGL(k_seed_neighbours, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, n, col, seed);
     return hipGetLastError();
 }
 
