@@ -37,6 +37,7 @@ constexpr int kBlock = 256;   // threads per workgroup (4 waves of 64)
 constexpr int kTile = kTileCols;   // columns staged in LDS per tile
 constexpr int kGroup = 8;     // columns per filter test
 constexpr int kCollectBuf = 128;   // pairs a wave stages in LDS while collecting
+constexpr int kSeedWin = 16;       // positions each side of a node whose distances seed its bounds
 static_assert(kBlock == kTile, "one update block covers one column tile");
 static_assert(kSubCols % kGroup == 0, "filter groups do not straddle sub-tiles");
 constexpr int32_t kNoIdx = INT32_MAX;
@@ -1307,7 +1308,6 @@ __global__ __launch_bounds__(kBlock) void k_seed_from_top(const int32_t *i4, con
 // position) among the positions within kSeedWin of p in the sorted order
 // (Morton order keeps most nearest neighbours close); any four columns
 // bound the 4th smallest Z, close ones tightly.
-constexpr int kSeedWin = 16;
 __global__ __launch_bounds__(kBlock) void k_seed_neighbours(int64_t n, const float4 *col, int32_t *seed)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
