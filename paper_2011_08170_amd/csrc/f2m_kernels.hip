@@ -638,15 +638,18 @@ __device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &to
     o.hsh = mix64((uint64_t)lamv ^ (0x9E3779B97F4A7C15ULL * (uint64_t)(v + 1)));
 }
 
+static_assert(offsetof(Ctrl, acc_maxabs_next) == offsetof(Ctrl, acc_sumlam) + 7 * sizeof(unsigned long long),
+              "the eight accumulators are consecutive 64-bit fields");
 // Block reductions of the rows' records, then the last block of the grid
 // writes the iteration record, takes the stop decision and clears the
 // accumulators.  Called by every thread of the block.
 __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t k, Ctrl *ctrl, int64_t *trace,
                                                    float *tile_hmax, int64_t blk, int64_t nblk)
 {
-    __shared__ unsigned long long red[kBlock / 64];
+    __shared__ unsigned long long red8[kBlock / 64][8];
     __shared__ float redf[kBlock / 64];
     __shared__ int s_last;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (tile_hmax) {
         // a block of kBlock positions is one column tile
         const float hs = sub_max(o.hmax);
@@ -654,77 +657,84 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
         const float hm = block_reduce<float, true>(o.hmax, redf);
         if (threadIdx.x == 0) tile_hmax[blk * kBoxStride] = hm;
     }
-    const unsigned long long sumlam = block_reduce<unsigned long long, false>(o.sumlam, red);
-    const unsigned long long rowneg = block_reduce<unsigned long long, false>(o.rowneg, red);
-    const unsigned long long unsat = block_reduce<unsigned long long, false>(o.unsat, red);
-    const unsigned long long bad = block_reduce<unsigned long long, false>(o.bad, red);
-    const unsigned long long nonzero = block_reduce<unsigned long long, false>(o.nonzero, red);
-    const unsigned long long hsh = block_reduce<unsigned long long, false>(o.hsh, red);
-    const unsigned long long maxstep = block_reduce<unsigned long long, true>((unsigned long long)o.maxstep, red);
-    const unsigned long long maxabs = block_reduce<unsigned long long, true>((unsigned long long)o.maxabs, red);
-    if (threadIdx.x == 0) {
-        atomicAdd(&ctrl->acc_sumlam, sumlam);
-        atomicAdd(&ctrl->acc_rowneg, rowneg);
-        atomicAdd(&ctrl->acc_unsat, unsat);
-        atomicAdd(&ctrl->acc_bad, bad);
-        atomicAdd(&ctrl->acc_nonzero, nonzero);
-        atomicAdd(&ctrl->acc_hash, hsh);
-        atomicMax((unsigned long long *)&ctrl->acc_maxstep, maxstep);
-        atomicMax((unsigned long long *)&ctrl->acc_maxabs_next, maxabs);
-        __threadfence();
-        const unsigned prev = atomicAdd(&ctrl->blocks_done, 1u);
-        s_last = (prev == (unsigned)(nblk - 1));
+    // the record's eight accumulators in the order of the Ctrl fields
+    // acc_sumlam .. acc_maxabs_next; entries 4 and 7 are maxima, the rest sums
+    unsigned long long v[8] = {o.sumlam, o.rowneg, o.unsat, o.bad, (unsigned long long)o.maxstep, o.nonzero,
+                               o.hsh, (unsigned long long)o.maxabs};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (i == 4 || i == 7) ? wave_max(v[i]) : wave_sum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) red8[w][i] = v[i];
     }
     __syncthreads();
-    if (!s_last || threadIdx.x != 0) return;
+    unsigned long long *acc = &ctrl->acc_sumlam;
+    if (w == 0) {
+        // lanes 0..7 each carry one accumulator to the control block
+        unsigned long long mine = 0;
+        if (lane < 8) {
+            mine = red8[0][lane];
+            for (int q = 1; q < kBlock / 64; ++q) {
+                const unsigned long long x = red8[q][lane];
+                mine = (lane == 4 || lane == 7) ? (x > mine ? x : mine) : mine + x;
+            }
+            if (lane == 4 || lane == 7) atomicMax(&acc[lane], mine);
+            else atomicAdd(&acc[lane], mine);
+        }
+        __threadfence();
+        if (lane == 0) {
+            const unsigned prev = atomicAdd(&ctrl->blocks_done, 1u);
+            s_last = (prev == (unsigned)(nblk - 1));
+        }
+    }
+    __syncthreads();
+    if (!s_last || w != 0) return;
 
-    // last block: every other block's atomics are visible
+    // last block: every other block's atomics are visible; lanes 0..7 read
+    // the accumulators together
     __threadfence();
-    const long long sl = (long long)atomicAdd(&ctrl->acc_sumlam, 0ULL);
-    const long long rnsum = (long long)atomicAdd(&ctrl->acc_rowneg, 0ULL);
-    const long long un = (long long)atomicAdd(&ctrl->acc_unsat, 0ULL);
-    const long long bd = (long long)atomicAdd(&ctrl->acc_bad, 0ULL);
-    const long long nz = (long long)atomicAdd(&ctrl->acc_nonzero, 0ULL);
-    const unsigned long long hh = atomicAdd(&ctrl->acc_hash, 0ULL);
-    const long long ms = (long long)atomicAdd((unsigned long long *)&ctrl->acc_maxstep, 0ULL);
-    const long long mx = (long long)atomicAdd((unsigned long long *)&ctrl->acc_maxabs_next, 0ULL);
-    // each unordered pair sits in two rows
-    const long long dual2 = 2 * sl + rnsum / 2;
-    if (trace && k < ctrl->trace_cap) {
-        long long *rec = (long long *)trace + kTraceW * k;
-        rec[0] = k; rec[1] = dual2; rec[2] = un; rec[3] = bd;
-        rec[4] = ms; rec[5] = nz; rec[6] = (long long)hh; rec[7] = sl;
+    unsigned long long got = 0;
+    if (lane < 8) got = atomicAdd(&acc[lane], 0ULL);
+    const long long sl = (long long)__shfl(got, 0, 64);
+    const long long rnsum = (long long)__shfl(got, 1, 64);
+    const long long un = (long long)__shfl(got, 2, 64);
+    const long long bd = (long long)__shfl(got, 3, 64);
+    const long long ms = (long long)__shfl(got, 4, 64);
+    const long long nz = (long long)__shfl(got, 5, 64);
+    const unsigned long long hh = __shfl(got, 6, 64);
+    const long long mx = (long long)__shfl(got, 7, 64);
+    if (lane < 8) atomicExch(&acc[lane], 0ULL);
+    if (lane == 0) {
+        // each unordered pair sits in two rows
+        const long long dual2 = 2 * sl + rnsum / 2;
+        if (trace && k < ctrl->trace_cap) {
+            long long *rec = (long long *)trace + kTraceW * k;
+            rec[0] = k; rec[1] = dual2; rec[2] = un; rec[3] = bd;
+            rec[4] = ms; rec[5] = nz; rec[6] = (long long)hh; rec[7] = sl;
+        }
+        if (ctrl->best_k < 0 || dual2 > ctrl->best_dual2) { ctrl->best_dual2 = dual2; ctrl->best_k = k; }
+        long long stop = 0;
+        if (bd == 0) stop = 1;                                                      // trivial
+        else if (ctrl->handoff_div > 0 && un * ctrl->handoff_div <= n) stop = 5;    // handoff
+        else if (nz == 0) stop = 2;                                                 // fixed
+        else if (k >= 2 && hh == ctrl->h2) stop = 3;                                // cycle
+        else if (k >= ctrl->max_iters) stop = 4;                                    // cap
+        else if (mx >= kLamLimit) { stop = 4; ctrl->overflow = 1; }
+        ctrl->k_last = k;
+        ctrl->dual2_last = dual2;
+        if (stop) {
+            ctrl->stop = stop;
+            ctrl->kstar = (stop == 3 || stop == 4) ? ctrl->best_k : k;
+            ctrl->done = 1;
+        } else {
+            ctrl->h2 = ctrl->h1;
+            ctrl->h1 = hh;
+            ctrl->k_next = k + 1;
+        }
+        ctrl->maxabs_lam = mx;
     }
-    if (ctrl->best_k < 0 || dual2 > ctrl->best_dual2) { ctrl->best_dual2 = dual2; ctrl->best_k = k; }
-    long long stop = 0;
-    if (bd == 0) stop = 1;                                                      // trivial
-    else if (ctrl->handoff_div > 0 && un * ctrl->handoff_div <= n) stop = 5;    // handoff
-    else if (nz == 0) stop = 2;                                                 // fixed
-    else if (k >= 2 && hh == ctrl->h2) stop = 3;                                // cycle
-    else if (k >= ctrl->max_iters) stop = 4;                                    // cap
-    else if (mx >= kLamLimit) { stop = 4; ctrl->overflow = 1; }
-    ctrl->k_last = k;
-    ctrl->dual2_last = dual2;
-    if (stop) {
-        ctrl->stop = stop;
-        ctrl->kstar = (stop == 3 || stop == 4) ? ctrl->best_k : k;
-        ctrl->done = 1;
-    } else {
-        ctrl->h2 = ctrl->h1;
-        ctrl->h1 = hh;
-        ctrl->k_next = k + 1;
-    }
-    ctrl->maxabs_lam = mx;
-    atomicExch(&ctrl->acc_sumlam, 0ULL);
-    atomicExch(&ctrl->acc_rowneg, 0ULL);
-    atomicExch(&ctrl->acc_unsat, 0ULL);
-    atomicExch(&ctrl->acc_bad, 0ULL);
-    atomicExch(&ctrl->acc_nonzero, 0ULL);
-    atomicExch(&ctrl->acc_hash, 0ULL);
-    atomicExch((unsigned long long *)&ctrl->acc_maxstep, 0ULL);
-    atomicExch((unsigned long long *)&ctrl->acc_maxabs_next, 0ULL);
     __threadfence();
-    atomicExch(&ctrl->blocks_done, 0u);
+    if (lane == 0) atomicExch(&ctrl->blocks_done, 0u);
 }
 
 // complete graph: merge the slices' partials, step, reduce, stop test
