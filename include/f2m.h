@@ -157,7 +157,7 @@ typedef struct f2m_result {
 } f2m_result;
 
 /* Fills opts with the defaults: rule 1, complete graph, cold start,
- * knn_k 10, max_iters 100000, handoff_div 300, exact finish, host coords,
+ * knn_k 10, max_iters 100000, handoff_div 50, exact finish, host coords,
  * no trace, auto chunk, culled scan. */
 void f2m_opts_default(f2m_opts *opts);
 

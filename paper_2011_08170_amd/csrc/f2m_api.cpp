@@ -881,7 +881,7 @@ void f2m_opts_default(f2m_opts *o)
     o->graph = F2M_GRAPH_COMPLETE;
     o->warm = F2M_WARM_COLD;
     o->max_iters = 100000;
-    o->handoff_div = 300;
+    o->handoff_div = 50;
     o->knn_k = 10;
     o->finish = F2M_FINISH_EXACT;
 }

@@ -30,6 +30,7 @@ SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gd
 MLP_PARAMS = 18817
 WARM = {"cold": 0, "user": 1, "mlp": 2, "graph": 3}
 GRAPH = {"complete": 0, "knn": 1}
+HANDOFF_DIV = 50   # the library default: hand off once #unsatisfied * 50 <= n
 
 
 class F2MError(RuntimeError):
@@ -187,7 +188,7 @@ class Context:
             raise F2MError(st, lib().f2m_last_error(self._h).decode())
         return st
 
-    def solve(self, coords, *, max_iters=100000, handoff_div=300, finish="exact", lambda2_init=None,
+    def solve(self, coords, *, max_iters=100000, handoff_div=HANDOFF_DIV, finish="exact", lambda2_init=None,
               trace=False, chunk=0, stream=None, time_kernels=False, scan="culled", graph="complete", knn_k=10,
               shape=None, mlp_theta=None, warm=None):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
@@ -234,7 +235,7 @@ class Context:
         finally:
             lib().f2m_result_free(C.byref(res))
 
-    def solve_batch(self, coords, offsets, *, max_iters=100000, handoff_div=300, finish="exact", trace=False,
+    def solve_batch(self, coords, offsets, *, max_iters=100000, handoff_div=HANDOFF_DIV, finish="exact", trace=False,
                     chunk=0, scan="culled", lambda2_init=None, slices=0):
         """Solves many instances in one batched loop.  coords: int32 (sum n, 2)
         on the host; offsets: int64 (n_inst + 1).  Returns (status, [dict])."""

@@ -33,6 +33,7 @@ def small_batch():
 
 
 def test_batch_matches_oracle(ctx):
+    from paper_2011_08170_amd import f2m
     xy, off, parts = small_batch()
     st, res = ctx.solve_batch(xy, off, trace=True)
     assert st == "ok"
@@ -41,7 +42,7 @@ def test_batch_matches_oracle(ctx):
         if len(part) == 3:
             assert r["primal2"] == core.exact_opt2(part)
             continue
-        o = core.gdp_solve(part, handoff_div=300)
+        o = core.gdp_solve(part, handoff_div=f2m.HANDOFF_DIV)
         assert r["iterations"] == o["iters"] and r["stop"] == o["stop"] and r["kstar"] == o["kstar"]
         assert np.array_equal(r["trace"], o["trace"])
         assert np.array_equal(r["lambda2_gdp"], o["lam"])

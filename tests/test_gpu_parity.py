@@ -97,7 +97,8 @@ def test_solve_certified_optimum(ctx, name, make):
     assert g["primal2"] == g["dual2"] == core.exact_opt2(xy)
     c = core.certify(xy, g["lambda2"], g["edge_u"], g["edge_v"], g["edge_x2"])
     assert c["certified"] and c["primal2"] == g["primal2"]
-    o = core.gdp_solve(xy, handoff_div=300)
+    from paper_2011_08170_amd import f2m
+    o = core.gdp_solve(xy, handoff_div=f2m.HANDOFF_DIV)
     assert np.array_equal(g["trace"], o["trace"])
 
 
