@@ -471,6 +471,25 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         so[t] = (cc < c1) ? a.g.orig[cc] : 0;
         __syncthreads();
     };
+    // the next tile's column of this thread, fetched while the current tile
+    // is scanned
+    float4 nx_c = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+    long long nx_l = 0;
+    int32_t nx_o = 0;
+    auto fetch_tile = [&](int64_t tile) {
+        const int64_t cc = tile + t;
+        const bool in = cc < c1;
+        nx_c = in ? a.lv.col[cc] : make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        nx_l = in ? a.lv.lam[cc] : 0;
+        nx_o = in ? a.g.orig[cc] : 0;
+    };
+    auto store_tile = [&]() {
+        __syncthreads();
+        sc[t] = nx_c;
+        slam[t] = nx_l;
+        so[t] = nx_o;
+        __syncthreads();
+    };
 
     if (CULL && R == 1) {
 #pragma unroll
@@ -510,10 +529,12 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
             if (ok) tlist[off + __popcll(mk & ((1ULL << lane) - 1ULL))] = (int32_t)(ti - t0);
             __syncthreads();
             any = any || total > 0;
+            if (total > 0) fetch_tile((t0 + tlist[0]) * kTile);
             for (int j = 0; j < total; ++j) {
                 const int64_t tj = t0 + tlist[j];
                 const int64_t tile = tj * kTile;
-                load_tile(tile);
+                store_tile();
+                if (j + 1 < total) fetch_tile((t0 + tlist[j + 1]) * kTile);
                 const int ntile = (int)min((int64_t)kTile, c1 - tile);
                 const bool sp = lane < kSubs && lane * kSubCols < ntile &&
                                 may_pass(a.g.box[tj * kBoxStride + 1 + lane], wbox, hvw,
