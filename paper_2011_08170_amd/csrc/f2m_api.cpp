@@ -41,7 +41,8 @@ struct f2m_ctx {
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
     // certificate / pair collection state
     DevBuf c_col, c_lam, c_tile_hmax, c_ctrl, c_deg, c_cnt, c_nb, c_acc, c_lam_label, c_eu, c_ev, c_ex;
-    DevBuf p_pairs, p_count, p_keys, p_keys2, p_keys3, p_temp, p_ucount, p_costs, p_neg, p_deg, p_start, p_inc;
+    DevBuf p_pairs, p_count, p_keys, p_keys2, p_keys3, p_temp, p_ucount, p_costs, p_neg, p_deg, p_start, p_inc, p_ucount2,
+        p_cand;
     // candidate graph
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
     // warm-start network
@@ -61,7 +62,7 @@ struct f2m_ctx {
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
                          &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
-                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &knn_nbr, &csr_keys,
+                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
                          &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
@@ -291,8 +292,12 @@ void certify_dev(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label, int6
 // Sorts and de-duplicates `found` collected pairs on the device and copies
 // the distinct ones (increasing) and their exact costs to the host; with
 // lam_bulk (device, labels) also the finish's bulk data (see PairSource).
+// With exclude (a sorted device key set) only the keys outside it are
+// returned; with keep the returned keys are also kept on the device
+// (ctx->p_cand) and *kept is their number.
 void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const int32_t *xy_dev, int64_t n,
-                        const int64_t *lam_bulk, PairSource &src, PairList &out, hipStream_t st)
+                        const int64_t *lam_bulk, PairSource &src, PairList &out, hipStream_t st,
+                        const uint64_t *exclude = nullptr, int64_t nexclude = 0, int64_t *kept = nullptr)
 {
     out.clear();
     src.costs.clear();
@@ -307,9 +312,21 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
     int64_t *uc = grow<int64_t>(ctx, ctx->p_ucount, 1);
     size_t tb = pair_sort_temp_bytes(found);
     if (lam_bulk) tb = std::max(tb, pair_bulk_temp_bytes(found, n));
+    if (exclude) tb = std::max(tb, exclude_temp_bytes(found));
     void *temp = grow<char>(ctx, ctx->p_temp, tb);
-    ck(ctx, launch_sort_unique_pairs(pairs, found, k1, k2, k3, uc, temp, tb, xy_dev, lam_bulk ? nullptr : cd, st),
+    const bool excl = exclude && nexclude > 0;
+    ck(ctx, launch_sort_unique_pairs(pairs, found, k1, k2, k3, uc, temp, tb, xy_dev,
+                                     (lam_bulk || excl) ? nullptr : cd, st),
        "sort_unique");
+    if (excl) {
+        // only the pairs outside the kept set, compacted into k1
+        int64_t *uc2 = grow<int64_t>(ctx, ctx->p_ucount2, 1);
+        uint8_t *fl = grow<uint8_t>(ctx, ctx->p_neg, found);
+        ck(ctx, launch_exclude_keys(k3, uc, found, exclude, nexclude, xy_dev, fl, k1, uc2, cd, temp, tb, st),
+           "exclude");
+        k3 = k1;
+        uc = uc2;
+    }
     uint8_t *ng = nullptr;
     int32_t *deg = nullptr, *stt = nullptr, *inc = nullptr;
     if (lam_bulk) {
@@ -317,13 +334,18 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
         ng = grow<uint8_t>(ctx, ctx->p_neg, found);
         deg = grow<int32_t>(ctx, ctx->p_deg, n + 1);
         stt = grow<int32_t>(ctx, ctx->p_start, n + 1);
-        inc = grow<int32_t>(ctx, ctx->p_inc, 2 * found);
+        inc = grow<int32_t>(ctx, ctx->p_inc, 2 * found + 2 * n);
         ck(ctx, launch_pair_bulk(k3, uc, found, xy_dev, lam_bulk, n, cd, ng, k1, k2, deg, stt, inc, temp, tb, st),
            "pair_bulk");
     }
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, uc, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     const int64_t u = ctx->scratch_host[0];
+    if (kept) {
+        uint64_t *keep = grow<uint64_t>(ctx, ctx->p_cand, std::max<int64_t>(u, 1));
+        if (u) ck(ctx, hipMemcpyAsync(keep, k3, u * sizeof(uint64_t), hipMemcpyDeviceToDevice, st), "copy");
+        *kept = u;
+    }
     std::vector<uint64_t> h(u);
     src.costs.resize(u);
     if (u) {
@@ -332,11 +354,12 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
         if (lam_bulk) {
             src.neg.resize(u);
             src.inc_start.resize(n + 1);
-            src.inc.resize(2 * u);
+            src.inc.resize(2 * u + 2 * n);
             ck(ctx, hipMemcpyAsync(src.neg.data(), ng, u, hipMemcpyDeviceToHost, st), "copy");
             ck(ctx, hipMemcpyAsync(src.inc_start.data(), stt, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st),
                "copy");
-            ck(ctx, hipMemcpyAsync(src.inc.data(), inc, 2 * u * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+            ck(ctx, hipMemcpyAsync(src.inc.data(), inc, (2 * u + 2 * n) * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+               "copy");
         }
     }
     ck(ctx, hipStreamSynchronize(st), "sync");
@@ -392,7 +415,14 @@ private:
                 ck(ctx, hipStreamSynchronize(st_), "sync");
                 const int64_t found = ctx->scratch_host[0];
                 if (found > cap) { cap = found + found / 4; continue; }
-                fetch_unique_pairs(ctx, pairs, found, gh_.xy, n, (want_bulk && seed) ? lam : nullptr, *this, out, st_);
+                if (want_bulk && seed) {
+                    fetch_unique_pairs(ctx, pairs, found, gh_.xy, n, lam, *this, out, st_, nullptr, 0, &ncand_);
+                } else {
+                    // known candidates stay on the device; only new pairs come back
+                    fetch_unique_pairs(ctx, pairs, found, gh_.xy, n, nullptr, *this, out, st_,
+                                       (!seed && ncand_ > 0) ? static_cast<const uint64_t *>(ctx->p_cand.p) : nullptr,
+                                       ncand_);
+                }
                 cap_ = cap;
                 return true;
             }
@@ -407,6 +437,7 @@ private:
     const int32_t *seed_;
     hipStream_t st_;
     int64_t cap_ = 0;
+    int64_t ncand_ = 0;   // candidate keys kept on the device (ctx->p_cand)
 };
 
 // The candidate graph (k nearest neighbours, union-symmetrised) as CSR

@@ -53,7 +53,8 @@ public:
     {
         const size_t m = pl.size();
         if (!ea_.empty() || m == 0 || src.costs.size() != m || src.neg.size() != m ||
-            src.inc_start.size() != (size_t)n_ + 1 || src.inc.size() != 2 * m || src.inc_start[n_] != (int64_t)(2 * m))
+            src.inc_start.size() != (size_t)n_ + 1 || src.inc.size() != 2 * m + kSpare * (size_t)n_ ||
+            src.inc_start[n_] != (int64_t)(2 * m + kSpare * n_))
             return false;
         for (size_t i = 0; i < m; ++i) {
             const int64_t a = pl[i].first, b = pl[i].second;
@@ -84,6 +85,8 @@ public:
             }
         }
         start_.assign(src.inc_start.begin(), src.inc_start.end());
+        end_.resize(n_);
+        for (int64_t v = 0; v < n_; ++v) end_[v] = start_[v + 1] - kSpare;
         inc_ = src.inc;
         built_ = (int64_t)m;
         return true;
@@ -104,7 +107,7 @@ public:
             const int32_t a = std::min(p.first, p.second), b = std::max(p.first, p.second);
             if (a == b || a < 0 || b >= n_) continue;
             const uint64_t key = (uint64_t)a * (uint64_t)n_ + (uint64_t)b;
-            while (j < keys_.size() && keys_[j] < key) ++j;
+            j = (size_t)(std::lower_bound(keys_.begin() + j, keys_.end(), key) - keys_.begin());
             if (j < keys_.size() && keys_[j] == key) continue;
             if (!fresh.empty() && fresh.back() >= key) {
                 if (fresh.back() == key) continue;
@@ -118,10 +121,6 @@ public:
             fresh.push_back(key);
             if (have_c) fresh_c.push_back(costs[q]);
         }
-        ea_.reserve(ea_.size() + fresh.size());
-        eb_.reserve(eb_.size() + fresh.size());
-        ec_.reserve(ec_.size() + fresh.size());
-        y_.reserve(y_.size() + 2 * fresh.size());
         for (size_t q = 0; q < fresh.size(); ++q) {
             const uint64_t key = fresh[q];
             const int32_t a = (int32_t)(key / (uint64_t)n_), b = (int32_t)(key - (uint64_t)a * (uint64_t)n_);
@@ -252,41 +251,37 @@ private:
 
     // Incident edges per node, in increasing edge index: both copies of a
     // node use the same list (edge e leaves a_e' and b_e' and enters b_e''
-    // and a_e'').  Edges [built_, size) are new since the last call: a bulk
-    // counting sort the first time, later a sequential merge that appends
-    // the few new edges to each node's list (new edges have the largest
-    // indexes, so every list stays sorted).
+    // and a_e'').  Node v's list is inc_[start_[v], end_[v]) with kSpare
+    // free slots behind it (start_[v + 1] - end_[v] >= 0).  Edges [built_,
+    // size) are new since the last call: they go into the free slots (new
+    // edges have the largest indexes, so every list stays sorted); when a
+    // slot runs out the lists are rebuilt by a counting sort.
+    static constexpr int64_t kSpare = 2;
     void build_adjacency()
     {
         const int64_t e = (int64_t)ea_.size();
-        if (built_ == 0 || e - built_ > built_ / 8) {
-            start_.assign(n_ + 1, 0);
-            for (int64_t i = 0; i < e; ++i) { ++start_[ea_[i] + 1]; ++start_[eb_[i] + 1]; }
-            for (int64_t v = 0; v < n_; ++v) start_[v + 1] += start_[v];
-            inc_.resize(2 * e);
-            std::vector<int64_t> pos(start_.begin(), start_.end() - 1);
-            for (int64_t i = 0; i < e; ++i) {
-                inc_[pos[ea_[i]]++] = (int32_t)i;
-                inc_[pos[eb_[i]]++] = (int32_t)i;
+        if (built_ > 0) {
+            bool fits = true;
+            for (int64_t i = built_; i < e && fits; ++i) {
+                const int64_t a = ea_[i], b = eb_[i];
+                if (end_[a] < start_[a + 1] && end_[b] < start_[b + 1]) {
+                    inc_[end_[a]++] = (int32_t)i;
+                    inc_[end_[b]++] = (int32_t)i;
+                    built_ = i + 1;
+                } else {
+                    fits = false;
+                }
             }
-        } else if (e > built_) {
-            std::vector<int64_t> add(n_ + 1, 0);
-            for (int64_t i = built_; i < e; ++i) { ++add[ea_[i] + 1]; ++add[eb_[i] + 1]; }
-            std::vector<int64_t> ns(n_ + 1, 0);
-            for (int64_t v = 0; v < n_; ++v) ns[v + 1] = ns[v] + (start_[v + 1] - start_[v]) + add[v + 1];
-            std::vector<int32_t> ni(2 * e);
-            std::vector<int64_t> pos(n_);
-            for (int64_t v = 0; v < n_; ++v) {
-                const int64_t len = start_[v + 1] - start_[v];
-                std::copy(inc_.begin() + start_[v], inc_.begin() + start_[v + 1], ni.begin() + ns[v]);
-                pos[v] = ns[v] + len;
-            }
-            for (int64_t i = built_; i < e; ++i) {
-                ni[pos[ea_[i]]++] = (int32_t)i;
-                ni[pos[eb_[i]]++] = (int32_t)i;
-            }
-            start_.swap(ns);
-            inc_.swap(ni);
+            if (fits) return;
+        }
+        start_.assign(n_ + 1, 0);
+        for (int64_t i = 0; i < e; ++i) { ++start_[ea_[i] + 1]; ++start_[eb_[i] + 1]; }
+        for (int64_t v = 0; v < n_; ++v) start_[v + 1] += start_[v] + kSpare;
+        inc_.assign(2 * e + kSpare * n_, 0);
+        end_.assign(start_.begin(), start_.end() - 1);
+        for (int64_t i = 0; i < e; ++i) {
+            inc_[end_[ea_[i]]++] = (int32_t)i;
+            inc_[end_[eb_[i]]++] = (int32_t)i;
         }
         built_ = e;
     }
@@ -366,14 +361,14 @@ private:
     void relax_from(int64_t x, int64_t d)
     {
         if (x < n_) {   // left copy: arcs with y = 0, forward
-            for (int64_t p = start_[x]; p < start_[x + 1]; ++p) {
+            for (int64_t p = start_[x]; p < end_[x]; ++p) {
                 const int64_t ie = inc_[p], k = out_arc(ie, x);
                 if (y_[k]) continue;
                 push(n_ + other(ie, x), d + red(k), d, k);
             }
         } else {        // right copy: arcs with y = 1, backward
             const int64_t u = x - n_;
-            for (int64_t p = start_[u]; p < start_[u + 1]; ++p) {
+            for (int64_t p = start_[u]; p < end_[u]; ++p) {
                 const int64_t ie = inc_[p], k = in_arc(ie, u);
                 if (!y_[k]) continue;
                 push(other(ie, u), d - red(k), d, k);
@@ -401,7 +396,7 @@ private:
             }
             bool pushed = false;
             if (x < n_) {
-                for (; f.p < start_[x + 1]; ++f.p) {
+                for (; f.p < end_[x]; ++f.p) {
                     const int64_t ie = inc_[f.p], k = out_arc(ie, x);
                     if (y_[k] || red(k) != 0) continue;
                     const int64_t w = other(ie, x), to = n_ + w;
@@ -414,7 +409,7 @@ private:
                 }
             } else {
                 const int64_t u = x - n_;
-                for (; f.p < start_[u + 1]; ++f.p) {
+                for (; f.p < end_[u]; ++f.p) {
                     const int64_t ie = inc_[f.p], k = in_arc(ie, u);
                     if (!y_[k] || red(k) != 0) continue;
                     const int64_t to = other(ie, u);
@@ -444,7 +439,7 @@ private:
     std::vector<int32_t> ea_, eb_;
     std::vector<int64_t> ec_;
     std::vector<uint8_t> y_;
-    std::vector<int64_t> start_;     // incident-edge lists (see build_adjacency)
+    std::vector<int64_t> start_, end_;   // incident-edge lists (see build_adjacency)
     std::vector<int32_t> inc_;
     int64_t built_ = 0;              // edges covered by start_/inc_
     struct Frame { int64_t x, p, via; };

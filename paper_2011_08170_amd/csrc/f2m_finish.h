@@ -41,8 +41,10 @@ struct PairSource {
     // pairs returned in the same order: neg bit 0 / bit 1 = the arc u'->v''
     // / v'->u'' has negative reduced cost c - alpha_tail - beta_head under
     // alpha = floor(lam/2), beta = lam - alpha of the lam passed, and every
-    // node's incident pair indices in increasing order (inc_start[n + 1],
-    // inc[2 * pairs]).  Left empty by sources that do not compute them.
+    // node's incident pair indices in increasing order, each node's list
+    // followed by two free slots (node v: inc[inc_start[v] ..
+    // inc_start[v + 1] - 2), inc of 2 * pairs + 2 * n entries).  Left empty
+    // by sources that do not compute them.
     bool want_bulk = false;
     std::vector<uint8_t> neg;
     std::vector<int32_t> inc_start, inc;

@@ -1164,15 +1164,19 @@ __global__ __launch_bounds__(kBlock) void k_key_info(const uint64_t *keys, const
     }
 }
 
-// sorted incidences -> per-node counts (deg zeroed, n + 1 entries) and the edge ids
+// sorted incidences -> per-node counts added to deg[v + 1] and the edge ids
+// placed with kIncSpare free slots after every node's list: the j-th
+// incidence overall, of node v, lands at j + kIncSpare * v
+constexpr int kIncSpare = 2;
 __global__ __launch_bounds__(kBlock) void k_inc_split(const uint64_t *sorted, const int64_t *count, int32_t *deg,
                                                       int32_t *inc)
 {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= 2 * *count) return;
     const uint64_t k = sorted[j];
-    inc[j] = (int32_t)(k & 0xffffffffULL);
-    atomicAdd(&deg[(k >> 32) + 1], 1);
+    const int64_t v = (int64_t)(k >> 32);
+    inc[j + kIncSpare * v] = (int32_t)(k & 0xffffffffULL);
+    atomicAdd(&deg[v + 1], 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_label_degrees(Geo g, Csr csr, int32_t *deg)
@@ -1755,6 +1759,49 @@ hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *
     return e;
 }
 
+// flags[i] = 1 for the distinct keys (i < count) not in the sorted set ex
+__global__ __launch_bounds__(kBlock) void k_flag_new(const uint64_t *keys, const int64_t *count, int64_t cap,
+                                                     const uint64_t *ex, int64_t nex, uint8_t *flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= cap) return;
+    uint8_t f = 0;
+    if (i < *count) {
+        const uint64_t k = keys[i];
+        int64_t lo = 0, hi = nex;   // first ex[j] >= k
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ex[mid] < k) lo = mid + 1;
+            else hi = mid;
+        }
+        f = (lo < nex && ex[lo] == k) ? 0 : 1;
+    }
+    flags[i] = f;
+}
+
+size_t exclude_temp_bytes(int64_t count)
+{
+    size_t b = 0;
+    (void)hipcub::DeviceSelect::Flagged(nullptr, b, (const uint64_t *)nullptr, (const uint8_t *)nullptr,
+                                        (uint64_t *)nullptr, (int64_t *)nullptr, (int)count);
+    return b;
+}
+
+hipError_t launch_exclude_keys(const uint64_t *keys, const int64_t *count_dev, int64_t cap, const uint64_t *ex,
+                               int64_t nex, const int32_t *xy, uint8_t *flags, uint64_t *out, int64_t *out_count,
+                               int32_t *costs, void *temp, size_t temp_bytes, hipStream_t st)
+{
+    if (cap <= 0) return hipMemsetAsync(out_count, 0, sizeof(int64_t), st);
+    hipLaunchKernelGGL(k_flag_new, dim3(blocks_for(cap, kBlock)), dim3(kBlock), 0, st, keys, count_dev, cap, ex, nex,
+                       flags);
+    size_t tb = temp_bytes;
+    hipError_t e = hipcub::DeviceSelect::Flagged(temp, tb, keys, flags, out, out_count, (int)cap, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_key_info, dim3(blocks_for(cap, kBlock)), dim3(kBlock), 0, st, out, out_count, cap, xy,
+                       (const int64_t *)nullptr, costs, (uint8_t *)nullptr, (uint64_t *)nullptr);
+    return hipGetLastError();
+}
+
 size_t pair_bulk_temp_bytes(int64_t count, int64_t n)
 {
     size_t a = 0, b = 0;
@@ -1775,7 +1822,10 @@ hipError_t launch_pair_bulk(const uint64_t *keys, const int64_t *count_dev, int6
     size_t tb = temp_bytes;
     hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, tb, inc_keys, inc_sorted, (int)(2 * cap), 0, 64, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n + 1, kBlock)), dim3(kBlock), 0, st, deg, n + 1, 0);
+    // deg[0] = 0, deg[v + 1] = kIncSpare + incidences of v: its inclusive sum
+    // is every list's start including the free slots
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, deg, (int64_t)1, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, deg + 1, n, kIncSpare);
     hipLaunchKernelGGL(k_inc_split, dim3(blocks_for(2 * cap, kBlock)), dim3(kBlock), 0, st, inc_sorted, count_dev, deg,
                        inc);
     tb = temp_bytes;
