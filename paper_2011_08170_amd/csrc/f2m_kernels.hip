@@ -906,8 +906,30 @@ __global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_
     for (int j = 0; j < K; ++j) { bd[j] = INT64_MAX; bl[j] = kNoIdx; bp[j] = -1; }
     if (valid) { const float4 cv = col[p]; xv = cv.x; yv = cv.y; }
     // float bound of the current K-th smallest D (exact integers below 2^42;
-    // the widening covers the rounding of the float distance)
+    // the widening covers the rounding of the float distance).  It starts
+    // at the K-th smallest D among the positions within kSeedWin of p in
+    // Morton order (those cross tile boundaries, so a row in a stray
+    // fragment of its tile still gets a near bound); the list itself is
+    // filled by the tile scans only.
     float thrf = INFINITY;
+    if (valid) {
+        int64_t wd[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) wd[j] = INT64_MAX;
+        const int64_t lo = p - kSeedWin < 0 ? 0 : p - kSeedWin;
+        const int64_t hi = p + kSeedWin >= n ? n - 1 : p + kSeedWin;
+        for (int64_t u = lo; u <= hi; ++u) {
+            if (u == p) continue;
+            const float4 cu = col[u];
+            const int32_t ix = (int32_t)(xv - cu.x), iy = (int32_t)(yv - cu.y);
+            int64_t d = (int64_t)ix * ix + (int64_t)iy * iy;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (d < wd[j]) { const int64_t td = wd[j]; wd[j] = d; d = td; }
+            }
+        }
+        if (wd[K - 1] != INT64_MAX) thrf = (float)wd[K - 1] * (1.0f + 0x1p-20f) + 1.0f;
+    }
 
     // all columns [tile, tile + ntile) of the LDS tile against this row
     auto scan = [&](int64_t tile, int j0, int j1) {
@@ -930,7 +952,7 @@ __global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_
                     const int32_t tp = bp[q]; bp[q] = bp[q - 1]; bp[q - 1] = tp;
                 }
             }
-            if (bp[K - 1] >= 0) thrf = (float)bd[K - 1] * (1.0f + 0x1p-20f) + 1.0f;
+            if (bp[K - 1] >= 0) thrf = fminf(thrf, (float)bd[K - 1] * (1.0f + 0x1p-20f) + 1.0f);
         }
     };
     auto load = [&](int64_t tile) {
