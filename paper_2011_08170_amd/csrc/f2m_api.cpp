@@ -43,6 +43,8 @@ struct f2m_ctx {
     DevBuf c_col, c_lam, c_tile_hmax, c_ctrl, c_deg, c_cnt, c_nb, c_acc, c_lam_label, c_eu, c_ev, c_ex;
     DevBuf p_pairs, p_count, p_keys, p_keys2, p_keys3, p_temp, p_ucount, p_costs, p_neg, p_deg, p_start, p_inc, p_ucount2,
         p_cand;
+    // the exact finish's node order (Morton positions): coordinates, Lam
+    DevBuf f_xyp, f_lam;
     // candidate graph
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
     // warm-start network
@@ -62,7 +64,7 @@ struct f2m_ctx {
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
                          &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
-                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &knn_nbr, &csr_keys,
+                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
                          &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
@@ -241,7 +243,8 @@ GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st
 
 // A Lam placed on the certificate / collection state: sorted Lam, column
 // records and tile maxima; lam_label_dev is in label order.
-LamView place_lam(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label_dev, hipStream_t st)
+LamView place_lam(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label_dev, hipStream_t st,
+                  bool by_position = false)
 {
     const int64_t n = gh.g.n;
     float4 *col = grow<float4>(ctx, ctx->c_col, n);
@@ -251,7 +254,7 @@ LamView place_lam(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label_dev,
     float *x2m = grow<float>(ctx, ctx->xy2max, 1);
     ck(ctx, launch_prep(gh.xy, gh.g.orig, n, gh.cx, gh.cy, col, const_cast<float4 *>(gh.g.box), x2m, st), "prep");
     ck(ctx, launch_ctrl_init(cc, 0, 0, 0, st), "ctrl");
-    ck(ctx, launch_set_lam(lam_label_dev, gh.g.orig, n, ls, col, th, cc, st), "set_lam");
+    ck(ctx, launch_set_lam(lam_label_dev, by_position ? nullptr : gh.g.orig, n, ls, col, th, cc, st), "set_lam");
     return LamView{col, ls, th, cc};
 }
 
@@ -367,11 +370,14 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
     for (uint64_t k : h) out.emplace_back((int32_t)(k >> 32), (int32_t)(k & 0xffffffffULL));
 }
 
-// Candidate pairs for the exact finish from GPU scans of the complete graph.
+// Candidate pairs for the exact finish from GPU scans of the complete
+// graph.  The finish runs on Morton positions (nodes near in the plane are
+// near in memory): Lam comes in and pairs go out in that order, and xyp
+// holds the coordinates by position.
 class GpuPairs : public PairSource {
 public:
-    GpuPairs(f2m_ctx *ctx, const GeoHost &gh, const int32_t *seed_dev, hipStream_t st)
-        : ctx_(ctx), gh_(gh), seed_(seed_dev), st_(st)
+    GpuPairs(f2m_ctx *ctx, const GeoHost &gh, const int32_t *xyp, const int32_t *seed_dev, hipStream_t st)
+        : ctx_(ctx), gh_(gh), xyp_(xyp), seed_(seed_dev), st_(st)
     {
     }
     bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) override
@@ -390,10 +396,10 @@ private:
         try {
             f2m_ctx *ctx = ctx_;
             const int64_t n = gh_.g.n;
-            int64_t *lam = grow<int64_t>(ctx, ctx->c_lam_label, n);
+            int64_t *lam = grow<int64_t>(ctx, ctx->f_lam, n);
             unsigned long long *cnt = grow<unsigned long long>(ctx, ctx->p_count, 1);
             ck(ctx, hipMemcpyAsync(lam, lam_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st_), "copy");
-            LamView lv = place_lam(ctx, gh_, lam, st_);
+            LamView lv = place_lam(ctx, gh_, lam, st_, true);
             const ScanShape sh = scan_shape(n, true);
             int64_t cap = std::max<int64_t>(cap_, 8 * n);
             for (;;) {
@@ -416,10 +422,10 @@ private:
                 const int64_t found = ctx->scratch_host[0];
                 if (found > cap) { cap = found + found / 4; continue; }
                 if (want_bulk && seed) {
-                    fetch_unique_pairs(ctx, pairs, found, gh_.xy, n, lam, *this, out, st_, nullptr, 0, &ncand_);
+                    fetch_unique_pairs(ctx, pairs, found, xyp_, n, lam, *this, out, st_, nullptr, 0, &ncand_);
                 } else {
                     // known candidates stay on the device; only new pairs come back
-                    fetch_unique_pairs(ctx, pairs, found, gh_.xy, n, nullptr, *this, out, st_,
+                    fetch_unique_pairs(ctx, pairs, found, xyp_, n, nullptr, *this, out, st_,
                                        (!seed && ncand_ > 0) ? static_cast<const uint64_t *>(ctx->p_cand.p) : nullptr,
                                        ncand_);
                 }
@@ -434,6 +440,7 @@ private:
 
     f2m_ctx *ctx_;
     GeoHost gh_;
+    const int32_t *xyp_;
     const int32_t *seed_;
     hipStream_t st_;
     int64_t cap_ = 0;
@@ -498,8 +505,8 @@ void certify_graph_dev(f2m_ctx *ctx, const GeoHost &gh, const Csr &csr, const in
 // Candidate pairs for the exact finish on the candidate graph.
 class GpuGraphPairs : public PairSource {
 public:
-    GpuGraphPairs(f2m_ctx *ctx, const GeoHost &gh, const Csr &csr, hipStream_t st)
-        : ctx_(ctx), gh_(gh), csr_(csr), st_(st)
+    GpuGraphPairs(f2m_ctx *ctx, const GeoHost &gh, const int32_t *xyp, const Csr &csr, hipStream_t st)
+        : ctx_(ctx), gh_(gh), xyp_(xyp), csr_(csr), st_(st)
     {
     }
     bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) override
@@ -514,10 +521,10 @@ private:
         try {
             f2m_ctx *ctx = ctx_;
             const int64_t n = gh_.g.n;
-            int64_t *lam = grow<int64_t>(ctx, ctx->c_lam_label, n);
+            int64_t *lam = grow<int64_t>(ctx, ctx->f_lam, n);
             unsigned long long *cnt = grow<unsigned long long>(ctx, ctx->p_count, 1);
             ck(ctx, hipMemcpyAsync(lam, lam_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st_), "copy");
-            LamView lv = place_lam(ctx, gh_, lam, st_);
+            LamView lv = place_lam(ctx, gh_, lam, st_, true);
             const int64_t cap = csr_.nnz + 1;
             int2 *pairs = grow<int2>(ctx, ctx->p_pairs, cap);
             ck(ctx, hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st_), "memset");
@@ -525,7 +532,7 @@ private:
             ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st_), "copy");
             ck(ctx, hipStreamSynchronize(st_), "sync");
             const int64_t found = std::min<int64_t>(ctx->scratch_host[0], cap);
-            fetch_unique_pairs(ctx, pairs, found, gh_.xy, n, want_bulk ? lam : nullptr, *this, out, st_);
+            fetch_unique_pairs(ctx, pairs, found, xyp_, n, want_bulk ? lam : nullptr, *this, out, st_);
             return true;
         } catch (const Fail &) {
             err = ctx_->err;
@@ -535,6 +542,7 @@ private:
 
     f2m_ctx *ctx_;
     GeoHost gh_;
+    const int32_t *xyp_;
     Csr csr_;
     hipStream_t st_;
 };
@@ -781,7 +789,7 @@ struct InstanceState {
     const Csr *csr;            // candidate graph or null
 };
 
-void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, const int32_t *xy_host, hipStream_t st,
+void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, hipStream_t st,
                      f2m_result &res)
 {
     const int64_t n = is.gh.g.n;
@@ -827,13 +835,23 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, c
         m = ctx->scratch_host[0];
         have_x = true;
     } else if (o.finish == F2M_FINISH_EXACT) {
+        // the finish runs on Morton positions: coordinates and Lam* in that
+        // order go in, its Lam and edges come back to labels on the device
+        int32_t *xyp = grow<int32_t>(ctx, ctx->f_xyp, 2 * n);
+        ck(ctx, launch_gather_xy(gh.xy, gh.g.orig, n, xyp, st), "gather_xy");
+        std::vector<int32_t> xyp_host(2 * n);
+        std::vector<int64_t> lamp_host(n);
+        ck(ctx, hipMemcpyAsync(xyp_host.data(), xyp, 2 * n * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(lamp_host.data(), is.lam_star, n * sizeof(int64_t), hipMemcpyDeviceToHost, st),
+           "copy");
+        ck(ctx, hipStreamSynchronize(st), "sync");
         FinishResult fr;
         if (is.csr) {
-            GpuGraphPairs src(ctx, gh, *is.csr, st);
-            finish_exact(xy_host, n, res.lambda2_gdp, src, &fr);
+            GpuGraphPairs src(ctx, gh, xyp, *is.csr, st);
+            finish_exact(xyp_host.data(), n, lamp_host.data(), src, &fr);
         } else {
-            GpuPairs src(ctx, gh, is.seed, st);
-            finish_exact(xy_host, n, res.lambda2_gdp, src, &fr);
+            GpuPairs src(ctx, gh, xyp, is.seed, st);
+            finish_exact(xyp_host.data(), n, lamp_host.data(), src, &fr);
         }
         res.finish_paths = fr.paths;
         res.finish_rounds = fr.rounds;
@@ -851,12 +869,15 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, c
         // the GDP multipliers stay available in lstar; the certificate's
         // duals go to their own buffer
         int64_t *lf = grow<int64_t>(ctx, ctx->lam_best, n);
-        ck(ctx, hipMemcpyAsync(lf, fr.lam.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+        int64_t *lp = grow<int64_t>(ctx, ctx->f_lam, n);
+        ck(ctx, hipMemcpyAsync(lp, fr.lam.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+        ck(ctx, launch_unpermute(lp, gh.g.orig, n, lf, st), "unpermute");
         (void)ld;
         if (m) {
             ck(ctx, hipMemcpyAsync(eu, fr.eu.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
             ck(ctx, hipMemcpyAsync(ev, fr.ev.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
             ck(ctx, hipMemcpyAsync(ex, fr.ex2.data(), m * sizeof(uint8_t), hipMemcpyHostToDevice, st), "copy");
+            ck(ctx, launch_edges_to_labels(gh.g.orig, m, eu, ev, st), "edges_to_labels");
         }
         lam_final_dev = lf;
         have_x = true;
@@ -1251,7 +1272,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
                          static_cast<const int32_t *>(ctx->i4.p), static_cast<const int32_t *>(ctx->seed.p),
                          o.record_trace ? static_cast<const int64_t *>(ctx->trace.p) : nullptr,
                          on_graph ? &csr : nullptr};
-        complete_result(ctx, is, o, xy_host.data(), st, res);
+        complete_result(ctx, is, o, st, res);
         res.scan_ms = lo.scan_ms;
         res.scan_launches = lo.scan_launches;
         res.scan_rows = lo.shape.rows;
@@ -1529,7 +1550,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
                     const int64_t *lstar = (c.kstar == c.k_last) ? last : best + P[i];
                     InstanceState is{gh, c, lstar, z4 + kTop * X, i4 + kTop * X, seed + kTop * X,
                                      trace ? trace + (int64_t)i * trace_cap * kTraceW : nullptr, nullptr};
-                    complete_result(wc, is, o, coords + 2 * X, wc->stream, res[i]);
+                    complete_result(wc, is, o, wc->stream, res[i]);
                 } catch (const Fail &f) {
                     ist[i] = f.st;
                     imsg[i] = wc->err;

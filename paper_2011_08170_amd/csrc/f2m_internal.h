@@ -100,7 +100,7 @@ struct ScanArgs {
     int64_t *prowneg;           // [slice][n]
     // certificate mode
     unsigned long long *acc;    // [0] += sum of min(0, Z) over ordered pairs
-    // collect mode: pairs (label, label), lo < hi, with Z <= theta_row
+    // collect mode: pairs (Morton positions), lo < hi, with Z <= theta_row
     int64_t theta;              // threshold when no seed bound exists
     int64_t slack;              // added to the seeded bound
     unsigned long long *count;
@@ -195,17 +195,18 @@ hipError_t launch_graph_step(const GraphStepArgs &a, hipStream_t st);
 // graph certificate dual side: acc[0] += sum over CSR entries of min(0, Z)
 hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_sorted, unsigned long long *acc,
                              hipStream_t st);
-// pairs (labels, lo < hi) of CSR edges with Z <= theta_row (theta_row =
+// pairs (Morton positions, lo < hi) of CSR edges with Z <= theta_row (theta_row =
 // max(0, 4th smallest Z of the row) + slack when slack >= 0, else -1)
 hipError_t launch_graph_collect(const Geo &g, const Csr &csr, const int64_t *lam_sorted, int64_t slack,
                                 unsigned long long *count, int2 *out, int64_t cap, hipStream_t st);
-// (lo, hi) label pairs -> sorted distinct keys lo * 2^32 + hi in keys_out;
+// (lo, hi) node pairs -> sorted distinct keys lo * 2^32 + hi in keys_out;
 // the distinct count lands in *count_dev; with costs non-null, costs[i] is
-// the exact cost of keys_out[i] from the label-order coordinates xy
+// the exact cost of keys_out[i] from the coordinates xy (same node order)
 size_t pair_sort_temp_bytes(int64_t count);
 // Bulk candidate data for the exact finish from the distinct keys (count on
 // the device, at most cap): exact costs, the negative-reduced-cost bits of
-// the two arcs under alpha = floor(Lam/2), beta = Lam - alpha (lam by label),
+// the two arcs under alpha = floor(Lam/2), beta = Lam - alpha (xy and lam
+// in the node order of the keys),
 // and every node's incident pair ids in increasing order, each node's list
 // followed by two free slots, as start[n + 1] (int32) and inc[2 * count + 2 * n]
 // The distinct keys (count on the device, at most cap) that are not in the
@@ -238,11 +239,16 @@ hipError_t launch_sort(const int32_t *xy, int64_t n, int32_t minx, int32_t miny,
 // centred float coordinates in sorted order, tile boxes, xy2max
 hipError_t launch_prep(const int32_t *xy, const int32_t *orig, int64_t n, int32_t cx, int32_t cy, float4 *col,
                        float4 *box, float *xy2max_dev, hipStream_t st);
-// Lam (labels) -> sorted Lam, h and q, tile maxima of h, max |Lam|
+// Lam (labels; orig null: already in Morton order) -> sorted Lam, h and q,
+// tile maxima of h, max |Lam|
 hipError_t launch_set_lam(const int64_t *lam_label, const int32_t *orig, int64_t n, int64_t *lam_sorted,
                           float4 *col, float *tile_hmax, Ctrl *ctrl, hipStream_t st);
 hipError_t launch_unpermute(const int64_t *lam_sorted, const int32_t *orig, int64_t n, int64_t *lam_label,
                             hipStream_t st);
+// coordinates by label -> by Morton position (xy_pos[2n])
+hipError_t launch_gather_xy(const int32_t *xy, const int32_t *orig, int64_t n, int32_t *xy_pos, hipStream_t st);
+// edges as Morton positions -> labels (lo < hi), in place
+hipError_t launch_edges_to_labels(const int32_t *orig, int64_t m, int32_t *eu, int32_t *ev, hipStream_t st);
 // seeds (positions, [4][n]) from the four smallest of a previous run (labels, [n][4] by label)
 hipError_t launch_seed_from_top(const int32_t *i4, const int32_t *orig, const int32_t *pos, int64_t n, int32_t *seed,
                                 hipStream_t st);

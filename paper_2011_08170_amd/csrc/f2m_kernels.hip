@@ -255,7 +255,8 @@ __device__ __forceinline__ bool may_pass(float4 b, float4 rbox, float hv, float 
 // MODE kModeGdp: per row the four smallest (Z, label), #Z<0, #Z==0 and the
 // sum of the negative Z over the slice's columns, written as partials.
 // MODE kModeCert: the sum over the slice of min(0, Z) (theta = 0), added to
-// acc[0].  MODE kModeCollect: every pair with Z <= theta_row.
+// acc[0].  MODE kModeCollect: every pair with Z <= theta_row, as Morton
+// positions (lo, hi).
 template <int R, int MODE, bool CULL>
 __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rblk, const int64_t sl)
 {
@@ -375,8 +376,8 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
             if (em) {
                 const int base = cfill[wave];
                 if (emit) {
-                    const int32_t lv = a.g.orig[rw[r].v], lu = so[c];
-                    const int2 pr = make_int2(min(lv, lu), max(lv, lu));
+                    const int32_t pv = (int32_t)rw[r].v, pu = (int32_t)u;
+                    const int2 pr = make_int2(min(pv, pu), max(pv, pu));
                     const int slot = base + __popcll(em & ((1ULL << lane) - 1ULL));
                     if (slot < kCollectBuf) {
                         cbuf[wave][slot] = pr;
@@ -1112,16 +1113,13 @@ __global__ __launch_bounds__(kBlock) void k_graph_collect(Geo g, Csr csr, const 
         }
         th = b[3] == INT64_MAX ? INT64_MAX / 4 : (b[3] > 0 ? b[3] : 0) + slack;
     }
-    const int32_t lp = g.orig[p];
+    const int32_t pp = (int32_t)p;
     for (int32_t e = e0; e < e1; ++e) {
         const int32_t u = csr.col[e];
         const int64_t z = 2 * (int64_t)csr.cost[e] - lv - lam[u];
         if (z > th) continue;
         const unsigned long long slot = atomicAdd(count, 1ULL);
-        if ((int64_t)slot < cap) {
-            const int32_t lu = g.orig[u];
-            out[slot] = make_int2(min(lp, lu), max(lp, lu));
-        }
+        if ((int64_t)slot < cap) out[slot] = make_int2(min(pp, u), max(pp, u));
     }
 }
 
@@ -1320,7 +1318,7 @@ __global__ __launch_bounds__(kBlock) void k_set_lam(const int64_t *lam_label, co
     unsigned long long ab = 0;
     float h = -INFINITY;
     if (p < n) {
-        const int64_t l = lam_label[orig[p]];
+        const int64_t l = orig ? lam_label[orig[p]] : lam_label[p];
         lam_sorted[p] = l;
         float4 cv = col[p];
         h = (float)(0.5 * (double)l);
@@ -1344,6 +1342,29 @@ __global__ __launch_bounds__(kBlock) void k_unpermute(const int64_t *lam_sorted,
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p < n) lam_label[orig[p]] = lam_sorted[p];
+}
+
+// coordinates in Morton order
+__global__ __launch_bounds__(kBlock) void k_gather_xy(const int32_t *xy, const int32_t *orig, int64_t n,
+                                                      int32_t *xy_pos)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) {
+        const int64_t l = orig[p];
+        xy_pos[2 * p] = xy[2 * l];
+        xy_pos[2 * p + 1] = xy[2 * l + 1];
+    }
+}
+
+// edges given by positions -> labels, lo < hi, in place
+__global__ __launch_bounds__(kBlock) void k_edges_to_labels(const int32_t *orig, int64_t m, int32_t *eu, int32_t *ev)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < m) {
+        const int32_t a = orig[eu[e]], b = orig[ev[e]];
+        eu[e] = min(a, b);
+        ev[e] = max(a, b);
+    }
 }
 
 // the first thresholds' seeds from a previous run's four smallest per node
@@ -1603,6 +1624,20 @@ hipError_t launch_unpermute(const int64_t *lam_sorted, const int32_t *orig, int6
                             hipStream_t st)
 {
     hipLaunchKernelGGL(k_unpermute, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam_sorted, orig, n, lam_label);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_xy(const int32_t *xy, const int32_t *orig, int64_t n, int32_t *xy_pos, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_xy, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, xy, orig, n, xy_pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_edges_to_labels(const int32_t *orig, int64_t m, int32_t *eu, int32_t *ev, hipStream_t st)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edges_to_labels, dim3(blocks_for(m, kBlock)), dim3(kBlock), 0, st, orig, m, eu, ev);
     return hipGetLastError();
 }
 
