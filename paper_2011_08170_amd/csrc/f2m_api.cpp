@@ -26,6 +26,11 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+struct HostBuf {   // pinned host memory
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
 }  // namespace
 
 struct f2m_ctx {
@@ -55,6 +60,11 @@ struct f2m_ctx {
         b_pzero, b_prn, b_z4, b_i4, b_seed, b_ctrl, b_trace, b_sargs, b_uargs, b_sitems, b_uitems, b_nblk, b_active;
     Ctrl *ctrl_host = nullptr;   // pinned
     int64_t *scratch_host = nullptr;   // pinned, 16 entries
+    // the finish's host side: pinned staging of the GPU's pair data, and its
+    // workspace and result, kept from one solve to the next
+    HostBuf h_keys, h_costs, h_neg, h_start, h_inc, h_xyp, h_lamp;
+    f2m::FinishWork *fwork = nullptr;
+    f2m::FinishResult fres;
     // contexts (own stream and workspaces) of the batch's finishing threads
     std::vector<f2m_ctx *> workers;
 
@@ -93,6 +103,20 @@ void ck(f2m_ctx *ctx, hipError_t e, const char *what)
         fail(ctx, e == hipErrorOutOfMemory ? F2M_ERR_NOMEM : F2M_ERR_DEVICE,
              std::string(what) + ": " + hipGetErrorString(e));
     }
+}
+
+template <typename T>
+T *grow_host(f2m_ctx *ctx, HostBuf &b, size_t count)
+{
+    const size_t need = std::max<size_t>(count * sizeof(T), 256);
+    if (b.bytes < need) {
+        if (b.p) (void)hipHostFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        ck(ctx, hipHostMalloc(&b.p, need, hipHostMallocDefault), "hipHostMalloc");
+        b.bytes = need;
+    }
+    return static_cast<T *>(b.p);
 }
 
 template <typename T>
@@ -303,10 +327,10 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
                         const uint64_t *exclude = nullptr, int64_t nexclude = 0, int64_t *kept = nullptr)
 {
     out.clear();
-    src.costs.clear();
-    src.neg.clear();
-    src.inc_start.clear();
-    src.inc.clear();
+    src.costs = nullptr;
+    src.neg = nullptr;
+    src.inc_start = nullptr;
+    src.inc = nullptr;
     if (found <= 0) return;
     uint64_t *k1 = grow<uint64_t>(ctx, ctx->p_keys, 2 * found);
     uint64_t *k2 = grow<uint64_t>(ctx, ctx->p_keys2, 2 * found);
@@ -349,25 +373,29 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
         if (u) ck(ctx, hipMemcpyAsync(keep, k3, u * sizeof(uint64_t), hipMemcpyDeviceToDevice, st), "copy");
         *kept = u;
     }
-    std::vector<uint64_t> h(u);
-    src.costs.resize(u);
-    if (u) {
-        ck(ctx, hipMemcpyAsync(h.data(), k3, u * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipMemcpyAsync(src.costs.data(), cd, u * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-        if (lam_bulk) {
-            src.neg.resize(u);
-            src.inc_start.resize(n + 1);
-            src.inc.resize(2 * u + 2 * n);
-            ck(ctx, hipMemcpyAsync(src.neg.data(), ng, u, hipMemcpyDeviceToHost, st), "copy");
-            ck(ctx, hipMemcpyAsync(src.inc_start.data(), stt, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st),
-               "copy");
-            ck(ctx, hipMemcpyAsync(src.inc.data(), inc, (2 * u + 2 * n) * sizeof(int32_t), hipMemcpyDeviceToHost, st),
-               "copy");
-        }
+    if (u == 0) return;
+    // through pinned staging: the pair source's views point there
+    uint64_t *hk = grow_host<uint64_t>(ctx, ctx->h_keys, u);
+    int32_t *hc = grow_host<int32_t>(ctx, ctx->h_costs, u);
+    ck(ctx, hipMemcpyAsync(hk, k3, u * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipMemcpyAsync(hc, cd, u * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+    uint8_t *hn = nullptr;
+    int32_t *hs = nullptr, *hi = nullptr;
+    if (lam_bulk) {
+        hn = grow_host<uint8_t>(ctx, ctx->h_neg, u);
+        hs = grow_host<int32_t>(ctx, ctx->h_start, n + 1);
+        hi = grow_host<int32_t>(ctx, ctx->h_inc, 2 * u + 2 * n);
+        ck(ctx, hipMemcpyAsync(hn, ng, u, hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(hs, stt, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(hi, inc, (2 * u + 2 * n) * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
     }
     ck(ctx, hipStreamSynchronize(st), "sync");
-    out.reserve(u);
-    for (uint64_t k : h) out.emplace_back((int32_t)(k >> 32), (int32_t)(k & 0xffffffffULL));
+    out.resize(u);
+    for (int64_t i = 0; i < u; ++i) out[i] = {(int32_t)(hk[i] >> 32), (int32_t)(hk[i] & 0xffffffffULL)};
+    src.costs = hc;
+    src.neg = hn;
+    src.inc_start = hs;
+    src.inc = hi;
 }
 
 // Candidate pairs for the exact finish from GPU scans of the complete
@@ -532,7 +560,15 @@ private:
             ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st_), "copy");
             ck(ctx, hipStreamSynchronize(st_), "sync");
             const int64_t found = std::min<int64_t>(ctx->scratch_host[0], cap);
-            fetch_unique_pairs(ctx, pairs, found, xyp_, n, want_bulk ? lam : nullptr, *this, out, st_);
+            if (want_bulk) {
+                fetch_unique_pairs(ctx, pairs, found, xyp_, n, lam, *this, out, st_, nullptr, 0, &ncand_);
+            } else {
+                // pricing: known candidates stay on the device, only new pairs come back
+                const bool excl = slack < 0 && ncand_ > 0;
+                fetch_unique_pairs(ctx, pairs, found, xyp_, n, nullptr, *this, out, st_,
+                                   excl ? static_cast<const uint64_t *>(ctx->p_cand.p) : nullptr,
+                                   excl ? ncand_ : 0);
+            }
             return true;
         } catch (const Fail &) {
             err = ctx_->err;
@@ -545,6 +581,7 @@ private:
     const int32_t *xyp_;
     Csr csr_;
     hipStream_t st_;
+    int64_t ncand_ = 0;   // candidate keys kept on the device (ctx->p_cand)
 };
 
 struct LoopOut {
@@ -839,19 +876,19 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
         // order go in, its Lam and edges come back to labels on the device
         int32_t *xyp = grow<int32_t>(ctx, ctx->f_xyp, 2 * n);
         ck(ctx, launch_gather_xy(gh.xy, gh.g.orig, n, xyp, st), "gather_xy");
-        std::vector<int32_t> xyp_host(2 * n);
-        std::vector<int64_t> lamp_host(n);
-        ck(ctx, hipMemcpyAsync(xyp_host.data(), xyp, 2 * n * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipMemcpyAsync(lamp_host.data(), is.lam_star, n * sizeof(int64_t), hipMemcpyDeviceToHost, st),
-           "copy");
+        int32_t *xyp_host = grow_host<int32_t>(ctx, ctx->h_xyp, 2 * n);
+        int64_t *lamp_host = grow_host<int64_t>(ctx, ctx->h_lamp, n);
+        ck(ctx, hipMemcpyAsync(xyp_host, xyp, 2 * n * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, hipMemcpyAsync(lamp_host, is.lam_star, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
         ck(ctx, hipStreamSynchronize(st), "sync");
-        FinishResult fr;
+        if (!ctx->fwork) ctx->fwork = finish_work_create();
+        FinishResult &fr = ctx->fres;
         if (is.csr) {
             GpuGraphPairs src(ctx, gh, xyp, *is.csr, st);
-            finish_exact(xyp_host.data(), n, lamp_host.data(), src, &fr);
+            finish_exact(xyp_host, n, lamp_host, src, &fr, ctx->fwork);
         } else {
             GpuPairs src(ctx, gh, xyp, is.seed, st);
-            finish_exact(xyp_host.data(), n, lamp_host.data(), src, &fr);
+            finish_exact(xyp_host, n, lamp_host, src, &fr, ctx->fwork);
         }
         res.finish_paths = fr.paths;
         res.finish_rounds = fr.rounds;
@@ -971,6 +1008,9 @@ void f2m_destroy(f2m_ctx *ctx)
         if (b->p) (void)hipFree(b->p);
     if (ctx->ctrl_host) (void)hipHostFree(ctx->ctrl_host);
     if (ctx->scratch_host) (void)hipHostFree(ctx->scratch_host);
+    for (HostBuf *h : {&ctx->h_keys, &ctx->h_costs, &ctx->h_neg, &ctx->h_start, &ctx->h_inc, &ctx->h_xyp, &ctx->h_lamp})
+        if (h->p) (void)hipHostFree(h->p);
+    if (ctx->fwork) finish_work_destroy(ctx->fwork);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

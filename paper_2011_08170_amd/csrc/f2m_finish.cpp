@@ -9,6 +9,7 @@
 #include <queue>
 #include <chrono>
 #include <iterator>
+#include <memory>
 
 namespace f2m {
 
@@ -27,12 +28,23 @@ constexpr int64_t kInf = std::numeric_limits<int64_t>::max() / 4;
 
 int64_t floor_half(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
 
+// candidate edge key: (a, b), a < b, in lexicographic order
+uint64_t pair_key(int64_t a, int64_t b) { return ((uint64_t)a << 32) | (uint64_t)b; }
+
 // Node ids: left copy v' -> v, right copy u'' -> n + u.
 // Arc 2i is a_i' -> b_i'', arc 2i+1 is b_i' -> a_i'' for candidate edge i.
+// One object serves one instance after another (reset): its buffers keep
+// their capacity.
 class DoubleCover {
 public:
-    DoubleCover(const int32_t *xy, int64_t n, const int64_t *lam) : xy_(xy), n_(n), alpha_(n), beta_(n), ex_(2 * n, 0)
+    void reset(const int32_t *xy, int64_t n, const int64_t *lam)
     {
+        xy_ = xy;
+        n_ = n;
+        alpha_.resize(n);
+        beta_.resize(n);
+        ex_.resize(2 * n);
+        src_.clear();
         for (int64_t v = 0; v < n; ++v) {
             alpha_[v] = floor_half(lam[v]);
             beta_[v] = lam[v] - alpha_[v];
@@ -40,7 +52,29 @@ public:
             ex_[n + v] = -2;   // right copies demand 2
             src_.push_back(v);
         }
-        build_adjacency();
+        A_ = B_ = 0;
+        keys_.clear();
+        ea_.clear();
+        eb_.clear();
+        ec_.clear();
+        y_.clear();
+        start_.assign(n, 0);
+        end_.assign(n, 0);
+        cap_.assign(n, 0);
+        inc_.clear();
+        built_ = 0;
+        // search state: dist is infinite outside the last search's touched set
+        if ((int64_t)dist_.size() != 2 * n) {
+            dist_.assign(2 * n, kInf);
+        } else {
+            for (int64_t x : touched_) dist_[x] = kInf;
+        }
+        touched_.clear();
+        par_.resize(2 * n);
+        if ((int64_t)seen_.size() != 2 * n) {
+            seen_.assign(2 * n, 0);
+            stamp_ = 0;
+        }
     }
 
     int64_t edges() const { return (int64_t)ea_.size(); }
@@ -48,27 +82,29 @@ public:
     // The first candidates in bulk: the pair source's costs, the initial
     // flow (negative-reduced-cost bits under the starting potentials) and
     // the incidence lists.  False (nothing changed) when the cover already
-    // has edges or the data does not fit; then add() does the work.
+    // has edges or the data is missing or does not fit; then add() does the
+    // work.
     bool add_bulk(const PairList &pl, const PairSource &src)
     {
-        const size_t m = pl.size();
-        if (!ea_.empty() || m == 0 || src.costs.size() != m || src.neg.size() != m ||
-            src.inc_start.size() != (size_t)n_ + 1 || src.inc.size() != 2 * m + kSpare * (size_t)n_ ||
-            src.inc_start[n_] != (int64_t)(2 * m + kSpare * n_))
-            return false;
-        for (size_t i = 0; i < m; ++i) {
+        const int64_t m = (int64_t)pl.size();
+        if (!ea_.empty() || m == 0 || !src.costs || !src.neg || !src.inc_start || !src.inc) return false;
+        const int32_t *is = src.inc_start;
+        if (is[0] != 0 || (int64_t)is[n_] != 2 * m + kSpare * n_) return false;
+        for (int64_t v = 0; v < n_; ++v)
+            if (is[v + 1] - is[v] < kSpare) return false;
+        keys_.resize(m);
+        for (int64_t i = 0; i < m; ++i) {
             const int64_t a = pl[i].first, b = pl[i].second;
             if (a < 0 || a >= b || b >= n_) return false;
-            if (i > 0 && (pl[i - 1].first > a || (pl[i - 1].first == a && pl[i - 1].second >= b))) return false;
+            keys_[i] = pair_key(a, b);
+            if (i > 0 && keys_[i - 1] >= keys_[i]) return false;
         }
-        keys_.resize(m);
         ea_.resize(m);
         eb_.resize(m);
         ec_.resize(m);
         y_.resize(2 * m);
-        for (size_t i = 0; i < m; ++i) {
+        for (int64_t i = 0; i < m; ++i) {
             const int32_t a = pl[i].first, b = pl[i].second;
-            keys_[i] = (uint64_t)a * (uint64_t)n_ + (uint64_t)b;
             ea_[i] = a;
             eb_[i] = b;
             ec_[i] = src.costs[i];
@@ -84,50 +120,55 @@ public:
                 if (++ex_[n_ + a] == 1) src_.push_back(n_ + a);
             }
         }
-        start_.assign(src.inc_start.begin(), src.inc_start.end());
-        end_.resize(n_);
-        for (int64_t v = 0; v < n_; ++v) end_[v] = start_[v + 1] - kSpare;
-        inc_ = src.inc;
-        built_ = (int64_t)m;
+        for (int64_t v = 0; v < n_; ++v) {
+            start_[v] = is[v];
+            end_[v] = is[v + 1] - kSpare;
+            cap_[v] = is[v + 1];
+        }
+        inc_.assign(src.inc, src.inc + is[n_]);
+        built_ = m;
         return true;
     }
 
-    // Adds new candidate edges (a sorted list of distinct pairs); arcs of
-    // negative reduced cost start saturated.
-    void add(const PairList &pl, const std::vector<int32_t> &costs)
+    // Adds new candidate edges (pairs with costs, or null: computed here);
+    // pairs already present are skipped.  Arcs of negative reduced cost
+    // start saturated.
+    void add(const PairList &pl, const int32_t *costs)
     {
-        const bool have_c = costs.size() == pl.size();
-        std::vector<uint64_t> fresh;
-        std::vector<int32_t> fresh_c;
-        fresh.reserve(pl.size());
-        if (have_c) fresh_c.reserve(pl.size());
+        fresh_.clear();
+        fresh_c_.clear();
         size_t j = 0;
+        uint64_t prev = 0;
+        bool have_prev = false;
         for (size_t q = 0; q < pl.size(); ++q) {
-            const auto &p = pl[q];
-            const int32_t a = std::min(p.first, p.second), b = std::max(p.first, p.second);
+            const int32_t a = std::min(pl[q].first, pl[q].second), b = std::max(pl[q].first, pl[q].second);
             if (a == b || a < 0 || b >= n_) continue;
-            const uint64_t key = (uint64_t)a * (uint64_t)n_ + (uint64_t)b;
-            j = (size_t)(std::lower_bound(keys_.begin() + j, keys_.end(), key) - keys_.begin());
-            if (j < keys_.size() && keys_[j] == key) continue;
-            if (!fresh.empty() && fresh.back() >= key) {
-                if (fresh.back() == key) continue;
-                // unsorted input: fall back to a sorted copy
-                std::vector<std::pair<int32_t, int32_t>> cp(pl.begin(), pl.end());
+            const uint64_t key = pair_key(a, b);
+            if (have_prev && key <= prev) {
+                if (key == prev) continue;
+                // unsorted input: go again over a sorted copy (costs recomputed)
+                PairList cp;
+                cp.reserve(pl.size());
+                for (const auto &p : pl) cp.emplace_back(std::min(p.first, p.second), std::max(p.first, p.second));
                 std::sort(cp.begin(), cp.end());
                 cp.erase(std::unique(cp.begin(), cp.end()), cp.end());
-                add(cp, std::vector<int32_t>());
+                fresh_.clear();
+                fresh_c_.clear();
+                add(cp, nullptr);
                 return;
             }
-            fresh.push_back(key);
-            if (have_c) fresh_c.push_back(costs[q]);
+            prev = key;
+            have_prev = true;
+            j = (size_t)(std::lower_bound(keys_.begin() + j, keys_.end(), key) - keys_.begin());
+            if (j < keys_.size() && keys_[j] == key) continue;
+            fresh_.push_back(key);
+            fresh_c_.push_back(costs ? costs[q] : -1);
         }
-        for (size_t q = 0; q < fresh.size(); ++q) {
-            const uint64_t key = fresh[q];
-            const int32_t a = (int32_t)(key / (uint64_t)n_), b = (int32_t)(key - (uint64_t)a * (uint64_t)n_);
-            int64_t c;
-            if (have_c) {
-                c = fresh_c[q];
-            } else {
+        if (fresh_.empty()) return;
+        for (size_t q = 0; q < fresh_.size(); ++q) {
+            const int32_t a = (int32_t)(fresh_[q] >> 32), b = (int32_t)(fresh_[q] & 0xffffffffULL);
+            int64_t c = fresh_c_[q];
+            if (!costs) {
                 const int64_t dx = (int64_t)xy_[2 * a] - xy_[2 * b], dy = (int64_t)xy_[2 * a + 1] - xy_[2 * b + 1];
                 c = nint_sqrt_host(dx * dx + dy * dy);
             }
@@ -145,11 +186,9 @@ public:
                 }
             }
         }
-        if (fresh.empty()) return;
-        std::vector<uint64_t> merged;
-        merged.reserve(keys_.size() + fresh.size());
-        std::merge(keys_.begin(), keys_.end(), fresh.begin(), fresh.end(), std::back_inserter(merged));
-        keys_.swap(merged);
+        merged_.resize(keys_.size() + fresh_.size());
+        std::merge(keys_.begin(), keys_.end(), fresh_.begin(), fresh_.end(), merged_.begin());
+        keys_.swap(merged_);
         build_adjacency();
     }
 
@@ -166,10 +205,6 @@ public:
     // nonnegative, so the end result is a minimum-cost flow.
     bool solve(int64_t &paths, int64_t &phases)
     {
-        dist_.assign(2 * n_, kInf);
-        par_.assign(2 * n_, -1);
-        std::vector<int32_t> seen(2 * n_, 0);
-        int32_t stamp = 0;
         bool single = false, first = true;
         for (;;) {
             // the excess nodes (the list only shrinks while solving)
@@ -208,11 +243,11 @@ public:
             }
             first = false;
             // unit augmentations along zero-reduced-cost paths
-            ++stamp;
+            const int32_t stamp = ++stamp_;
             int64_t found = 0;
             for (int64_t s : src_) {
-                while (ex_[s] > 0 && seen[s] != stamp) {
-                    if (!augment_from(s, stamp, seen)) break;
+                while (ex_[s] > 0 && seen_[s] != stamp) {
+                    if (!augment_from(s, stamp)) break;
                     ++paths;
                     ++found;
                 }
@@ -227,19 +262,18 @@ public:
         for (int64_t v = 0; v < n_; ++v) out[v] = alpha_[v] + A_ + beta_[v] + B_;
     }
 
+    // the edges with flow, in candidate order
     void x(std::vector<int32_t> &eu, std::vector<int32_t> &ev, std::vector<uint8_t> &ex2) const
     {
-        std::vector<int64_t> order;
-        for (int64_t i = 0; i < (int64_t)ea_.size(); ++i)
-            if (y_[2 * i] + y_[2 * i + 1] > 0) order.push_back(i);
-        std::sort(order.begin(), order.end(), [&](int64_t p, int64_t q) {
-            return ea_[p] != ea_[q] ? ea_[p] < ea_[q] : eb_[p] < eb_[q];
-        });
-        eu.clear(); ev.clear(); ex2.clear();
-        for (int64_t i : order) {
+        eu.clear();
+        ev.clear();
+        ex2.clear();
+        for (int64_t i = 0; i < (int64_t)ea_.size(); ++i) {
+            const int f = y_[2 * i] + y_[2 * i + 1];
+            if (f == 0) continue;
             eu.push_back(ea_[i]);
             ev.push_back(eb_[i]);
-            ex2.push_back((uint8_t)(y_[2 * i] + y_[2 * i + 1]));
+            ex2.push_back((uint8_t)f);
         }
     }
 
@@ -251,39 +285,52 @@ private:
 
     // Incident edges per node, in increasing edge index: both copies of a
     // node use the same list (edge e leaves a_e' and b_e' and enters b_e''
-    // and a_e'').  Node v's list is inc_[start_[v], end_[v]) with kSpare
-    // free slots behind it (start_[v + 1] - end_[v] >= 0).  Edges [built_,
-    // size) are new since the last call: they go into the free slots (new
-    // edges have the largest indexes, so every list stays sorted); when a
-    // slot runs out the lists are rebuilt by a counting sort.
+    // and a_e'').  Node v's list is inc_[start_[v], end_[v]) with free slots
+    // up to cap_[v].  Edges [built_, size) are new since the last call: they
+    // go into the free slots (new edges have the largest indexes, so every
+    // list stays sorted); a full list first moves to the end of inc_ with
+    // room to grow.  Without bulk lists the first call builds them all by a
+    // counting sort, kSpare free slots each.
     static constexpr int64_t kSpare = 2;
     void build_adjacency()
     {
         const int64_t e = (int64_t)ea_.size();
-        if (built_ > 0) {
-            bool fits = true;
-            for (int64_t i = built_; i < e && fits; ++i) {
-                const int64_t a = ea_[i], b = eb_[i];
-                if (end_[a] < start_[a + 1] && end_[b] < start_[b + 1]) {
-                    inc_[end_[a]++] = (int32_t)i;
-                    inc_[end_[b]++] = (int32_t)i;
-                    built_ = i + 1;
-                } else {
-                    fits = false;
-                }
+        if (built_ == 0 && inc_.empty()) {
+            int64_t at = 0;
+            for (int64_t v = 0; v < n_; ++v) end_[v] = 0;
+            for (int64_t i = 0; i < e; ++i) { ++end_[ea_[i]]; ++end_[eb_[i]]; }
+            for (int64_t v = 0; v < n_; ++v) {
+                start_[v] = at;
+                at += end_[v] + kSpare;
+                cap_[v] = at;
+                end_[v] = start_[v];
             }
-            if (fits) return;
-        }
-        start_.assign(n_ + 1, 0);
-        for (int64_t i = 0; i < e; ++i) { ++start_[ea_[i] + 1]; ++start_[eb_[i] + 1]; }
-        for (int64_t v = 0; v < n_; ++v) start_[v + 1] += start_[v] + kSpare;
-        inc_.assign(2 * e + kSpare * n_, 0);
-        end_.assign(start_.begin(), start_.end() - 1);
-        for (int64_t i = 0; i < e; ++i) {
-            inc_[end_[ea_[i]]++] = (int32_t)i;
-            inc_[end_[eb_[i]]++] = (int32_t)i;
+            inc_.resize(at);
+            for (int64_t i = 0; i < e; ++i) {
+                inc_[end_[ea_[i]]++] = (int32_t)i;
+                inc_[end_[eb_[i]]++] = (int32_t)i;
+            }
+        } else {
+            for (int64_t i = built_; i < e; ++i) {
+                place(ea_[i], (int32_t)i);
+                place(eb_[i], (int32_t)i);
+            }
         }
         built_ = e;
+    }
+
+    void place(int64_t v, int32_t i)
+    {
+        if (end_[v] == cap_[v]) {
+            const int64_t len = end_[v] - start_[v], ncap = 2 * len + kSpare + 2;
+            const int64_t at = (int64_t)inc_.size();
+            inc_.resize(at + ncap);
+            std::copy(inc_.begin() + start_[v], inc_.begin() + end_[v], inc_.begin() + at);
+            start_[v] = at;
+            end_[v] = at + len;
+            cap_[v] = at + ncap;
+        }
+        inc_[end_[v]++] = i;
     }
 
     // Dijkstra on reduced costs from the given excess nodes up to the first
@@ -378,8 +425,9 @@ private:
 
     // Depth-first search from s over zero-reduced-cost residual arcs to a
     // node with a deficit; flips the arcs of the path found.
-    bool augment_from(int64_t s, int32_t stamp, std::vector<int32_t> &seen)
+    bool augment_from(int64_t s, int32_t stamp)
     {
+        std::vector<int32_t> &seen = seen_;
         std::vector<Frame> &st = frames_;
         st.clear();
         seen[s] = stamp;
@@ -426,8 +474,8 @@ private:
         return false;
     }
 
-    const int32_t *xy_;
-    int64_t n_;
+    const int32_t *xy_ = nullptr;
+    int64_t n_ = 0;
     std::vector<int64_t> alpha_, beta_;
     int64_t A_ = 0, B_ = 0;          // global offsets of alpha and beta
     std::vector<int64_t> ex_;
@@ -435,13 +483,17 @@ private:
     using Item = std::pair<int64_t, int64_t>;
     std::vector<int64_t> dist_, par_, touched_, cur_;
     std::vector<Item> heap_;
-    std::vector<uint64_t> keys_;     // sorted keys a*n+b of the candidate edges
+    std::vector<uint64_t> keys_;     // sorted keys (pair_key) of the candidate edges
+    std::vector<uint64_t> fresh_, merged_;
+    std::vector<int32_t> fresh_c_;
     std::vector<int32_t> ea_, eb_;
     std::vector<int64_t> ec_;
     std::vector<uint8_t> y_;
-    std::vector<int64_t> start_, end_;   // incident-edge lists (see build_adjacency)
+    std::vector<int64_t> start_, end_, cap_;   // incident-edge lists (see build_adjacency)
     std::vector<int32_t> inc_;
-    int64_t built_ = 0;              // edges covered by start_/inc_
+    int64_t built_ = 0;              // edges covered by the lists
+    std::vector<int32_t> seen_;      // augmentation pass stamps
+    int32_t stamp_ = 0;
     struct Frame { int64_t x, p, via; };
     std::vector<Frame> frames_;
 };
@@ -453,14 +505,40 @@ static double secs()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out)
-{
-    FinishResult &r = *out;
-    r = FinishResult();
-    double t = secs();
-    DoubleCover g(xy, n, lam0);
-    std::string err;
+struct FinishWork {
+    DoubleCover g;
     PairList pl;
+    std::vector<int64_t> lam;
+};
+
+FinishWork *finish_work_create() { return new FinishWork(); }
+
+void finish_work_destroy(FinishWork *work) { delete work; }
+
+void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out,
+                  FinishWork *work)
+{
+    std::unique_ptr<FinishWork> own;
+    if (!work) {
+        own.reset(new FinishWork());
+        work = own.get();
+    }
+    FinishResult &r = *out;
+    r.ok = false;
+    r.msg.clear();
+    r.lam.clear();
+    r.eu.clear();
+    r.ev.clear();
+    r.ex2.clear();
+    r.paths = r.rounds = r.phases = r.candidates = 0;
+    r.t_collect = r.t_build = r.t_flow = 0.0;
+    double t = secs();
+    DoubleCover &g = work->g;
+    g.reset(xy, n, lam0);
+    PairList &pl = work->pl;
+    std::vector<int64_t> &lam = work->lam;
+    std::string err;
+    pl.clear();
     int64_t slack = 16;
     src.want_bulk = true;
     const bool got = src.near(lam0, slack, pl, err);
@@ -470,7 +548,6 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
     t = secs();
     if (!g.add_bulk(pl, src)) g.add(pl, src.costs);
     r.t_build += secs() - t;
-    std::vector<int64_t> lam;
     for (int round = 0; round < 64; ++round) {
         ++r.rounds;
         t = secs();
@@ -500,7 +577,7 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
         r.t_build += secs() - t;
         if (g.edges() == before) {
             r.ok = true;
-            r.lam = lam;
+            r.lam.assign(lam.begin(), lam.end());
             g.x(r.eu, r.ev, r.ex2);
             r.candidates = g.edges();
             return;

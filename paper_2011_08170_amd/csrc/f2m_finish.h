@@ -33,21 +33,23 @@ using PairList = std::vector<std::pair<int32_t, int32_t>>;   // (u, v), u < v
 // uses GPU scans).
 struct PairSource {
     virtual ~PairSource() = default;
-    // exact costs c of the pairs the last call returned, in the same order,
-    // when the source computes them (else left empty: the finish computes
-    // them itself)
-    std::vector<int32_t> costs;
+    // Data returned beside the pairs of the last call, as views into the
+    // source's own memory, valid until its next call; null when the source
+    // does not compute them.  costs: the exact costs c of the pairs, in the
+    // same order (else the finish computes them itself).
+    const int32_t *costs = nullptr;
     // Bulk data the finish asks for (want_bulk) on its first call, for the
     // pairs returned in the same order: neg bit 0 / bit 1 = the arc u'->v''
     // / v'->u'' has negative reduced cost c - alpha_tail - beta_head under
     // alpha = floor(lam/2), beta = lam - alpha of the lam passed, and every
     // node's incident pair indices in increasing order, each node's list
     // followed by two free slots (node v: inc[inc_start[v] ..
-    // inc_start[v + 1] - 2), inc of 2 * pairs + 2 * n entries).  Left empty
-    // by sources that do not compute them.
+    // inc_start[v + 1] - 2), inc_start of n + 1 entries, inc of 2 * pairs +
+    // 2 * n entries).
     bool want_bulk = false;
-    std::vector<uint8_t> neg;
-    std::vector<int32_t> inc_start, inc;
+    const uint8_t *neg = nullptr;
+    const int32_t *inc_start = nullptr;
+    const int32_t *inc = nullptr;
     // pairs {u, v} with Z_uv(lam) <= max(0, 4th smallest Z at u or v) + slack
     virtual bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) = 0;
     // pairs {u, v} with Z_uv(lam) < 0
@@ -58,7 +60,7 @@ struct FinishResult {
     bool ok = false;
     std::string msg;
     std::vector<int64_t> lam;       // Lam = alpha + beta
-    std::vector<int32_t> eu, ev;    // edges of x, eu < ev
+    std::vector<int32_t> eu, ev;    // edges of x, eu < ev (no particular order)
     std::vector<uint8_t> ex2;       // 2x in {1, 2}
     int64_t paths = 0;              // unit augmentations
     int64_t rounds = 0;             // pricing rounds
@@ -69,6 +71,15 @@ struct FinishResult {
     double t_flow = 0.0;            // seconds in the flow phases
 };
 
-void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out);
+// Host memory of the finish, kept from one call to the next so that its
+// buffers are reused (no fresh pages per solve); one per finishing thread.
+struct FinishWork;
+FinishWork *finish_work_create();
+void finish_work_destroy(FinishWork *work);
+
+// work may be null (a temporary one is used).  out's vectors keep their
+// capacity when it is reused.
+void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out,
+                  FinishWork *work = nullptr);
 
 }  // namespace f2m

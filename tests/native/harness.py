@@ -17,11 +17,12 @@ def build(outdir):
     subprocess.run(cmd, check=True)
     L = C.CDLL(so)
     L.finish_cpu.restype = C.c_int64
-    L.finish_cpu.argtypes = [C.c_int64] + [C.c_void_p] * 2 + [C.c_void_p, C.c_int64] + [C.c_void_p] * 4
+    L.finish_cpu.argtypes = [C.c_int64] + [C.c_void_p] * 2 + [C.c_void_p, C.c_int64] + [C.c_void_p] * 4 + \
+        [C.c_int32, C.c_int32]
     return L
 
 
-def finish(L, xy, lam0):
+def finish(L, xy, lam0, bulk=False, reuse=False):
     xy = np.ascontiguousarray(xy, np.int32)
     n = xy.shape[0]
     lam0 = np.ascontiguousarray(lam0, np.int64)
@@ -30,6 +31,6 @@ def finish(L, xy, lam0):
     eu = np.zeros(cap, np.int32); ev = np.zeros(cap, np.int32); ex = np.zeros(cap, np.uint8)
     st = np.zeros(4, np.int64)
     m = L.finish_cpu(n, xy.ctypes.data, lam0.ctypes.data, lam.ctypes.data, cap, eu.ctypes.data,
-                     ev.ctypes.data, ex.ctypes.data, st.ctypes.data)
+                     ev.ctypes.data, ex.ctypes.data, st.ctypes.data, int(bulk), int(reuse))
     assert m >= 0, "finish failed"
     return lam, eu[:m], ev[:m], ex[:m], dict(zip(("paths", "rounds", "phases", "candidates"), st.tolist()))

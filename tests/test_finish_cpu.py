@@ -21,6 +21,14 @@ def check(L, xy, lam0):
     assert c["certified"], (c, st)
     assert c["primal2"] == core.exact_opt2(xy)
     assert np.all(eu < ev)
+    # the bulk path (costs, initial flow bits and incidence lists from the
+    # source) starts from the same state, so it must end in the same bits;
+    # so must a workspace that served other instances before
+    for bulk, reuse in ((True, False), (True, True), (False, True)):
+        got = harness.finish(L, xy, lam0, bulk=bulk, reuse=reuse)
+        for a, b in zip((lam, eu, ev, ex), got[:4]):
+            assert np.array_equal(a, b), (bulk, reuse)
+        assert got[4] == st
     return st
 
 
