@@ -177,8 +177,11 @@ ScanShape scan_shape_auto(int64_t n, bool cull)
     ScanShape s;
     const int64_t nt = ntiles_of(n);
     if (cull) {
+        // one row per lane; each wave's surviving sub-tiles are dealt to 4
+        // slices (measured at n = 20k, 100k and 200k: 2 slices leave the
+        // SIMDs too few waves, 8 repeat the per-wave tile walk too often)
         s.rows = 1;
-        const int64_t sl = std::max<int64_t>(1, std::min<int64_t>(nt, 8));
+        const int64_t sl = std::max<int64_t>(1, std::min<int64_t>(nt, 4));
         s.slice_len = ((nt + sl - 1) / sl) * kTileCols;
     } else {
         s.rows = n >= 65536 ? 4 : (n >= 8192 ? 2 : 1);
@@ -1479,6 +1482,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             a.lam_odd = lam1 + P[i];
             a.slice_len = shp[i].slice_len;
             a.cull = cull ? 1 : 0;
+            a.interleave = cull ? shp[i].slices : 0;
             a.check_done = 1;
             a.tested = &ctrl[i].pairs_tested;
             a.seed = seed + kTop * X;

@@ -110,6 +110,11 @@ struct ScanArgs {
     // had a column tile to scan; a block without one writes no partials
     int32_t *pflag;
     int64_t nrb;                // row blocks of the launch
+    // culled scan: > 0 = the number of slices, each of which scans every
+    // interleave-th of the row block's surviving column tiles (over all
+    // columns; slice_len is then not used); 0 = slice s scans columns
+    // [s * slice_len, (s + 1) * slice_len)
+    int64_t interleave;
 };
 
 struct UpdateArgs {

@@ -268,8 +268,12 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
     __shared__ unsigned long long redu[kBlock / 64];
     const int t = threadIdx.x;
     const int64_t n = a.g.n;
-    const int64_t c0 = sl * a.slice_len;
-    const int64_t c1 = min(n, c0 + a.slice_len);
+    // the slice's columns: a contiguous range, or (interleaved culled scan)
+    // every S-th surviving tile of all columns, starting with the sid-th
+    const bool il = CULL && a.interleave > 0;
+    const int64_t S = il ? a.interleave : 1, sid = il ? sl : 0;
+    const int64_t c0 = il ? 0 : sl * a.slice_len;
+    const int64_t c1 = il ? n : min(n, c0 + a.slice_len);
     const float colmax = col_bound(a.g.xy2max, a.lv.ctrl->maxabs_lam);
 
     Row rw[R];
@@ -438,32 +442,6 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
             }
         }
     };
-    // culled scan with one row per lane: the passing columns of a whole
-    // tile are gathered first (one bit per column, in LDS) and evaluated
-    // after the tile's last sub-tile, so a lane's evaluations wait for no
-    // other lane's
-    __shared__ uint32_t cmask[CULL && R == 1 ? kSubs : 1][kBlock];
-    auto mark_cols = [&](int g0, int g1) {
-        for (int g = g0; g < g1; g += kGroup) {
-            unsigned pm[R];
-            filter_group(g, pm);
-            if (pm[0]) cmask[g >> 5][t] |= pm[0] << (g & 31);
-        }
-    };
-    auto eval_marked = [&](int64_t tile, unsigned long long subs) {
-        while (subs) {
-            const int w = __ffsll((long long)subs) - 1;
-            subs &= subs - 1;
-            uint32_t b = cmask[w][t];
-            cmask[w][t] = 0;
-            while (b) {
-                const int q = __ffs(b) - 1;
-                b &= b - 1;
-                eval_col(0, tile, w * 32 + q);
-            }
-        }
-    };
-    static_assert(kSubCols == 32, "one mask word per sub-tile");
     auto load_tile = [&](int64_t tile) {
         __syncthreads();
         const int64_t cc = tile + t;
@@ -492,10 +470,6 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         __syncthreads();
     };
 
-    if (CULL && R == 1) {
-#pragma unroll
-        for (int w = 0; w < kSubs; ++w) cmask[w][t] = 0;
-    }
     bool any = !CULL;   // block-uniform: some column tile was scanned
     if (!CULL) {
         for (int64_t tile = c0; tile < c1; tile += kTile) {
@@ -513,6 +487,7 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         __shared__ int32_t tlist[kBlock];
         __shared__ int32_t wcnt[kBlock / 64];
         const int64_t t0 = c0 / kTile, t1 = (c1 + kTile - 1) / kTile;
+        int64_t jbase = 0;   // survivors in the chunks before
         for (int64_t base = t0; base < t1; base += kBlock) {
             const int64_t ti = base + t;
             const bool ok = ti < t1 && may_pass(a.g.box[ti * kBoxStride], rbox, hvmax,
@@ -529,13 +504,16 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
             }
             if (ok) tlist[off + __popcll(mk & ((1ULL << lane) - 1ULL))] = (int32_t)(ti - t0);
             __syncthreads();
-            any = any || total > 0;
-            if (total > 0) fetch_tile((t0 + tlist[0]) * kTile);
-            for (int j = 0; j < total; ++j) {
+            // this slice's survivors: global index = sid (mod S)
+            const int j0 = (int)((((sid - jbase) % S) + S) % S);
+            jbase += total;
+            any = any || j0 < total;
+            if (j0 < total) fetch_tile((t0 + tlist[j0]) * kTile);
+            for (int j = j0; j < total; j += (int)S) {
                 const int64_t tj = t0 + tlist[j];
                 const int64_t tile = tj * kTile;
                 store_tile();
-                if (j + 1 < total) fetch_tile((t0 + tlist[j + 1]) * kTile);
+                if (j + S < total) fetch_tile((t0 + tlist[j + S]) * kTile);
                 const int ntile = (int)min((int64_t)kTile, c1 - tile);
                 const bool sp = lane < kSubs && lane * kSubCols < ntile &&
                                 may_pass(a.g.box[tj * kBoxStride + 1 + lane], wbox, hvw,
@@ -547,10 +525,8 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
                     const int g0 = sb * kSubCols;
                     const int g1 = min(g0 + kSubCols, ntile);
                     count_tested(tile + g0, tile + g1);
-                    if (R == 1) mark_cols(g0, g1);
-                    else scan_cols(tile, g0, g1);
+                    scan_cols(tile, g0, g1);
                 }
-                if (R == 1) eval_marked(tile, sm0);
             }
         }
     }
@@ -590,10 +566,291 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
     }
 }
 
+// Orders the LDS accesses of one wave (no other wave takes part).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Culled scan, one row per lane, every wave on its own.  A wave holds 64
+// Morton-consecutive rows (a small box); it tests the column tiles against
+// that box (64 tiles at a time, one per lane), then the 32-column sub-tiles
+// of eight surviving tiles at a time (one per lane), and keeps the
+// survivors dealt to this slice (every S-th, round-robin) in a short list.  The list's
+// sub-tiles are staged two at a time in the wave's own LDS (the next pair is
+// fetched into registers meanwhile) and scanned by every lane against its
+// row: the float filter marks columns in a 64-bit mask, the marked ones get
+// the exact evaluation.  No wave waits for another until the end, where the
+// block agrees on whether any of its waves scanned a column (pflag).
+template <int MODE>
+__device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64_t rblk, const int64_t sl)
+{
+    static_assert(kSubCols == 32 && kSubs == 8, "two sub-tiles per wave-wide stage, eight per tile test");
+    if (a.check_done && a.lv.ctrl->done) return;
+    constexpr int kList = 128;
+    __shared__ int32_t wl[kBlock / 64][kList];       // the wave's sub-tile list
+    __shared__ int32_t tl[kBlock / 64][64];          // the wave's pending surviving tiles
+    __shared__ float4 wc[kBlock / 64][64];           // staged columns
+    __shared__ long long wlam[kBlock / 64][64];
+    __shared__ int32_t wlab[kBlock / 64][64];
+    __shared__ int32_t wpos[kBlock / 64][64];        // position, -1: none
+    __shared__ unsigned long long redu[kBlock / 64];
+    __shared__ int bany;
+    __shared__ int2 cbuf[kBlock / 64][MODE == kModeCollect ? kCollectBuf : 1];
+    __shared__ int cfill_s[kBlock / 64];
+    volatile int *cfill = cfill_s;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t n = a.g.n;
+    const int64_t S = a.interleave > 0 ? a.interleave : 1, sid = a.interleave > 0 ? sl : 0;
+    const float colmax = col_bound(a.g.xy2max, a.lv.ctrl->maxabs_lam);
+    if (t == 0) bany = 0;
+    if (lane == 0) cfill[wave] = 0;
+
+    Row rw;
+    Top4 top;
+    int32_t neg = 0, zero = 0;
+    int64_t rn = 0;
+    top.clear();
+    const int64_t p = rblk * kBlock + t;
+    rw.v = p;
+    if (p < n) {
+        const float4 cv = a.lv.col[p];
+        rw.xv = cv.x; rw.yv = cv.y;
+        rw.lamv = a.lv.lam[p];
+        int64_t th;
+        if (MODE == kModeCert) {
+            th = 0;
+        } else {
+            int64_t mx;
+            const bool ok = a.seed && seeded_bound(a, p, cv.x, cv.y, rw.lamv, &mx);
+            if (MODE == kModeGdp) th = ok ? (mx > 0 ? mx : 0) : kThetaNone;
+            else th = ok ? (mx > 0 ? mx : 0) + a.slack : a.theta;
+        }
+        rw.theta = th;
+        set_filter(rw, colmax);
+    } else {
+        rw.xv = rw.yv = 0.0f;
+        rw.lamv = 0; rw.theta = 0;
+        rw.a = rw.b = rw.c = 0.0f;
+        rw.thr = -INFINITY;   // never passes
+    }
+    __syncthreads();   // bany and cfill are set
+
+    // the wave's rows: positions [w0, w1), their box (two sub-tile boxes)
+    const int64_t w0 = rblk * kBlock + wave * 64, w1 = min(n, w0 + 64);
+    float4 wbox = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+    if (w1 > w0) {
+        for (int s = wave * (64 / kSubCols); s < (wave + 1) * (64 / kSubCols); ++s) {
+            const float4 sb = a.g.box[rblk * kBoxStride + 1 + s];
+            wbox.x = fminf(wbox.x, sb.x); wbox.y = fmaxf(wbox.y, sb.y);
+            wbox.z = fminf(wbox.z, sb.z); wbox.w = fmaxf(wbox.w, sb.w);
+        }
+    }
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    unsigned long long tested = 0;
+    bool scanned = false;
+
+    // exact evaluation of staged column c against this lane's row
+    auto eval = [&](int c) {
+        const int64_t u = wpos[wave][c];
+        if (u < 0 || u == rw.v) return;
+        const float4 cd = wc[wave][c];
+        if (!(filter_value(rw, cd) <= rw.thr)) return;   // theta may have dropped
+        const int64_t z = exact_z(rw.xv, rw.yv, rw.lamv, cd.x, cd.y, wlam[wave][c]);
+        if (MODE == kModeCert) {
+            if (z < 0) rn += z;
+            return;
+        }
+        if (MODE == kModeCollect) {
+            // the wave's pairs gather in its LDS buffer; a full buffer's
+            // excess goes out at once
+            const bool emit = z <= rw.theta;
+            const unsigned long long em = __ballot(emit);
+            if (em) {
+                const int base = cfill[wave];
+                if (emit) {
+                    const int32_t pv = (int32_t)rw.v, pu = (int32_t)u;
+                    const int2 pr = make_int2(min(pv, pu), max(pv, pu));
+                    const int slot = base + __popcll(em & ((1ULL << lane) - 1ULL));
+                    if (slot < kCollectBuf) {
+                        cbuf[wave][slot] = pr;
+                    } else {
+                        const unsigned long long gs = atomicAdd(a.count, 1ULL);
+                        if ((int64_t)gs < a.cap) a.out[gs] = pr;
+                    }
+                }
+                if (lane == __ffsll((long long)em) - 1) cfill[wave] = base + __popcll(em);
+            }
+            return;
+        }
+        if (z > rw.theta) return;
+        if (z < 0) { ++neg; rn += z; }
+        else if (z == 0) ++zero;
+        top.insert(z, wlab[wave][c]);
+        if (top.id[3] != kNoIdx) {
+            const int64_t nt = top.z[3] > 0 ? top.z[3] : 0;
+            if (nt < rw.theta) { rw.theta = nt; set_filter(rw, colmax); }
+        }
+    };
+
+    // the next pair of list entries' columns, one per lane (lanes 0-31
+    // entry e, lanes 32-63 entry e + 1)
+    float4 nx_c = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+    long long nx_l = 0;
+    int32_t nx_o = 0, nx_u = -1;
+    auto fetch = [&](int e, int cnt) {
+        const int ee = e + (lane >> 5);
+        nx_c = make_float4(0.0f, 0.0f, 0.0f, INFINITY);
+        nx_l = 0;
+        nx_o = 0;
+        nx_u = -1;
+        if (ee < cnt) {
+            const int32_t st = wl[wave][ee];
+            const int64_t cc = (int64_t)(st / kSubs) * kTile + (int64_t)(st % kSubs) * kSubCols + (lane & 31);
+            if (cc < n) {
+                nx_c = a.lv.col[cc];
+                nx_l = a.lv.lam[cc];
+                nx_o = a.g.orig[cc];
+                nx_u = (int32_t)cc;
+            }
+        }
+    };
+
+    if (w1 > w0) {
+        // The culling radius comes from the rows' starting thresholds: every
+        // slice must see the same survivors in the same order, or the
+        // round-robin deal would lose or repeat sub-tiles.
+        const float hvw = wave_max(p < n ? -0.5f * rw.c : -INFINITY);
+        const unsigned long long below = (1ULL << lane) - 1ULL;
+        int64_t tb = 0;               // next chunk of 64 tiles
+        int tcnt = 0, tpos = 0;       // surviving tiles pending in tl: [tpos, tcnt)
+        int64_t kk = 0;               // surviving sub-tiles so far (round-robin)
+        for (;;) {
+            int cnt = 0;
+            while (cnt <= kList - 64) {
+                if (tpos == tcnt) {
+                    // the next surviving tiles, one chunk of 64 at a time
+                    wave_sync();   // tl is no longer read
+                    tpos = tcnt = 0;
+                    while (tcnt == 0 && tb < ntiles) {
+                        const int64_t ti = tb + lane;
+                        const bool ok = ti < ntiles &&
+                                        may_pass(a.g.box[ti * kBoxStride], wbox, hvw, a.lv.tile_hmax[ti * kBoxStride]);
+                        const unsigned long long mk = __ballot(ok);
+                        if (ok) tl[wave][__popcll(mk & below)] = (int32_t)ti;
+                        tcnt = __popcll(mk);
+                        tb += 64;
+                    }
+                    wave_sync();
+                    if (tcnt == 0) break;
+                }
+                // up to eight pending tiles at once: lane 8i + s tests
+                // sub-tile s of the i-th
+                const int ti8 = lane >> 3, s8 = lane & 7;
+                const int nt8 = min(8, tcnt - tpos);
+                bool sp = false;
+                int64_t tj = 0;
+                if (ti8 < nt8) {
+                    tj = tl[wave][tpos + ti8];
+                    sp = (int64_t)s8 * kSubCols < n - tj * kTile &&
+                         may_pass(a.g.box[tj * kBoxStride + 1 + s8], wbox, hvw,
+                                  a.lv.tile_hmax[tj * kBoxStride + 1 + s8]);
+                }
+                const unsigned long long sm = __ballot(sp);
+                const int64_t my = kk + __popcll(sm & below);
+                const bool take = sp && (my % S) == sid;
+                const unsigned long long tk = __ballot(take);
+                if (take) wl[wave][cnt + __popcll(tk & below)] = (int32_t)(tj * kSubs + s8);
+                cnt += __popcll(tk);
+                kk += __popcll(sm);
+                tpos += nt8;
+            }
+            if (cnt == 0) break;
+            scanned = true;
+            wave_sync();   // the list is written
+            fetch(0, cnt);
+            for (int e = 0; e < cnt; e += 2) {
+                wave_sync();   // the previous pair's reads are done
+                wc[wave][lane] = nx_c;
+                wlam[wave][lane] = nx_l;
+                wlab[wave][lane] = nx_o;
+                wpos[wave][lane] = nx_u;
+                wave_sync();
+                const int ncol = (e + 1 < cnt) ? 64 : 32;
+                // ordered pairs of the wave's rows against the staged columns
+                for (int h = 0; h < ncol / 32; ++h) {
+                    const int32_t st = wl[wave][e + h];
+                    const int64_t cs = (int64_t)(st / kSubs) * kTile + (int64_t)(st % kSubs) * kSubCols;
+                    const int64_t ce = min(n, cs + kSubCols);
+                    tested += (unsigned long long)((w1 - w0) * (ce - cs) - max((int64_t)0, min(w1, ce) - max(w0, cs)));
+                }
+                if (e + 2 < cnt) fetch(e + 2, cnt);
+                // float filter, kGroup columns at a time, into a pass mask
+                unsigned long long pm = 0;
+                for (int g = 0; g < ncol; g += kGroup) {
+                    float m = INFINITY;
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) m = fminf(m, filter_value(rw, wc[wave][g + q]));
+                    if (m <= rw.thr) {
+#pragma unroll
+                        for (int q = 0; q < kGroup; ++q)
+                            pm |= (filter_value(rw, wc[wave][g + q]) <= rw.thr) ? (1ULL << (g + q)) : 0ULL;
+                    }
+                }
+                while (pm) {
+                    const int c = __ffsll((long long)pm) - 1;
+                    pm &= pm - 1;
+                    eval(c);
+                }
+            }
+        }
+    }
+
+    if (a.tested && lane == 0 && tested) atomicAdd(a.tested, tested);
+    if (MODE == kModeCollect) {
+        wave_sync();   // every lane's buffer writes are done
+        const int fill = min(cfill[wave], kCollectBuf);
+        unsigned long long base = 0;
+        if (lane == 0 && fill > 0) base = atomicAdd(a.count, (unsigned long long)fill);
+        base = __shfl(base, 0, 64);
+        for (int i = lane; i < fill; i += 64)
+            if ((int64_t)(base + i) < a.cap) a.out[base + i] = cbuf[wave][i];
+    }
+    if (MODE == kModeGdp) {
+        if (scanned && lane == 0) bany = 1;
+        __syncthreads();
+        const bool any = bany != 0;
+        if (a.pflag && t == 0) a.pflag[sl * a.nrb + rblk] = any ? 1 : 0;
+        if ((any || !a.pflag) && p < n) {
+#pragma unroll
+            for (int j = 0; j < kTop; ++j) {
+                a.pz[(sl * kTop + j) * n + p] = top.z[j];
+                a.pi[(sl * kTop + j) * n + p] = top.id[j];
+            }
+            a.pneg[sl * n + p] = neg;
+            a.pzero[sl * n + p] = zero;
+            a.prowneg[sl * n + p] = rn;
+        }
+    }
+    if (MODE == kModeCert) {
+        const unsigned long long tot = block_reduce<unsigned long long, false>((unsigned long long)rn, redu);
+        if (threadIdx.x == 0 && tot != 0) atomicAdd(&a.acc[0], tot);
+    }
+}
+
 template <int R, int MODE, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
 {
     rowscan_body<R, MODE, CULL>(a, blockIdx.x, blockIdx.y);
+}
+
+// the culled scan with one row per lane (see rowscan_wave_body)
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_rowscan_w(ScanArgs a)
+{
+    rowscan_wave_body<MODE>(a, blockIdx.x, blockIdx.y);
 }
 
 // batched GDP scan: one block per (instance, row block, slice)
@@ -603,7 +860,8 @@ __global__ __launch_bounds__(kBlock) void k_rowscan_batch(const ScanArgs *args, 
     const BatchScanItem w = items[blockIdx.x];
     ScanArgs a = args[w.inst];
     if (a.lv.ctrl->k_next & 1) a.lv.lam = a.lam_odd;
-    rowscan_body<R, kModeGdp, CULL>(a, w.row_block, w.slice);
+    if constexpr (CULL && R == 1) rowscan_wave_body<kModeGdp>(a, w.row_block, w.slice);
+    else rowscan_body<R, kModeGdp, CULL>(a, w.row_block, w.slice);
 }
 
 // ---------------------------------------------------------------------------
@@ -1665,7 +1923,10 @@ static hipError_t launch_scan_mode(const ScanArgs &a, int64_t nslices, int R, hi
 {
     const unsigned gy = (unsigned)nslices;
     switch (R) {
-    case 1: hipLaunchKernelGGL((k_rowscan<1, MODE, CULL>), dim3(blocks_for(a.g.n, kBlock), gy), dim3(kBlock), 0, st, a); break;
+    case 1:
+        if constexpr (CULL) hipLaunchKernelGGL((k_rowscan_w<MODE>), dim3(blocks_for(a.g.n, kBlock), gy), dim3(kBlock), 0, st, a);
+        else hipLaunchKernelGGL((k_rowscan<1, MODE, CULL>), dim3(blocks_for(a.g.n, kBlock), gy), dim3(kBlock), 0, st, a);
+        break;
     case 2: hipLaunchKernelGGL((k_rowscan<2, MODE, CULL>), dim3(blocks_for(a.g.n, 2 * kBlock), gy), dim3(kBlock), 0, st, a); break;
     case 4: hipLaunchKernelGGL((k_rowscan<4, MODE, CULL>), dim3(blocks_for(a.g.n, 4 * kBlock), gy), dim3(kBlock), 0, st, a); break;
     default: return hipErrorInvalidValue;
@@ -1679,13 +1940,24 @@ static hipError_t launch_scan_mode(const ScanArgs &a, int64_t nslices, int R, hi
     return a.cull ? launch_scan_mode<MODE, true>(a, nslices, R, st) : launch_scan_mode<MODE, false>(a, nslices, R, st);
 }
 
+// the culled scan deals each row block's surviving tiles round-robin to the
+// slices (the survivors gather near the block's own Morton position, so
+// contiguous slices would leave most slice blocks idle)
+static ScanArgs with_interleave(const ScanArgs &a, int64_t nslices)
+{
+    ScanArgs b = a;
+    b.interleave = a.cull ? nslices : 0;
+    return b;
+}
+
 hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_per_thread, hipStream_t st)
 {
     if (a.slice_len % kTile != 0) return hipErrorInvalidValue;
     switch (mode) {
-    case kModeGdp: return launch_scan_mode<kModeGdp>(a, nslices, rows_per_thread, st);
-    case kModeCert: return launch_scan_mode<kModeCert>(a, nslices, rows_per_thread, st);
-    case kModeCollect: return launch_scan_mode<kModeCollect>(a, nslices, rows_per_thread, st);
+    case kModeGdp: return launch_scan_mode<kModeGdp>(with_interleave(a, nslices), nslices, rows_per_thread, st);
+    case kModeCert: return launch_scan_mode<kModeCert>(with_interleave(a, nslices), nslices, rows_per_thread, st);
+    case kModeCollect:
+        return launch_scan_mode<kModeCollect>(with_interleave(a, nslices), nslices, rows_per_thread, st);
     }
     return hipErrorInvalidValue;
 }
