@@ -67,6 +67,7 @@ struct f2m_ctx {
     f2m::FinishResult fres;
     // contexts (own stream and workspaces) of the batch's finishing threads
     std::vector<f2m_ctx *> workers;
+    bool is_worker = false;   // one of those: its finish runs on one thread
 
     f2m_ctx()
     {
@@ -884,7 +885,7 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
         ck(ctx, hipMemcpyAsync(xyp_host, xyp, 2 * n * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
         ck(ctx, hipMemcpyAsync(lamp_host, is.lam_star, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
         ck(ctx, hipStreamSynchronize(st), "sync");
-        if (!ctx->fwork) ctx->fwork = finish_work_create();
+        if (!ctx->fwork) ctx->fwork = finish_work_create(ctx->is_worker ? 1 : finish_threads());
         FinishResult &fr = ctx->fres;
         if (is.csr) {
             GpuGraphPairs src(ctx, gh, xyp, *is.csr, st);
@@ -1571,6 +1572,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             f2m_ctx *w = nullptr;
             const f2m_status cs = f2m_create(&w, ctx->device);
             if (cs != F2M_OK) fail(ctx, cs, "cannot create a finishing context");
+            w->is_worker = true;
             ctx->workers.push_back(w);
         }
         std::vector<f2m_status> ist(n_inst, F2M_OK);

@@ -9,7 +9,9 @@
 #include <queue>
 #include <chrono>
 #include <iterator>
+#include <atomic>
 #include <memory>
+#include <thread>
 
 namespace f2m {
 
@@ -33,61 +35,54 @@ uint64_t pair_key(int64_t a, int64_t b) { return ((uint64_t)a << 32) | (uint64_t
 
 // Node ids: left copy v' -> v, right copy u'' -> n + u.
 // Arc 2i is a_i' -> b_i'', arc 2i+1 is b_i' -> a_i'' for candidate edge i.
-// One object serves one instance after another (reset): its buffers keep
-// their capacity.
+// The data a search touches per arc sit together: one record per edge
+// (ends, cost, the flow of its two arcs) and one per node copy (potential,
+// excess, search state).  One object serves one instance after another
+// (reset): its buffers keep their capacity.
 class DoubleCover {
 public:
     void reset(const int32_t *xy, int64_t n, const int64_t *lam)
     {
         xy_ = xy;
         n_ = n;
-        alpha_.resize(n);
-        beta_.resize(n);
-        ex_.resize(2 * n);
+        // search state: dist is infinite outside the last search's touched set
+        const bool same = (int64_t)cp_.size() == 2 * n;
+        if (same) {
+            for (int64_t x : touched_) cp_[x].dist = kInf;
+        } else {
+            cp_.assign(2 * n, Copy{});
+        }
+        touched_.clear();
         src_.clear();
         for (int64_t v = 0; v < n; ++v) {
-            alpha_[v] = floor_half(lam[v]);
-            beta_[v] = lam[v] - alpha_[v];
-            ex_[v] = 2;        // left copies supply 2
-            ex_[n + v] = -2;   // right copies demand 2
+            const int64_t al = floor_half(lam[v]);
+            cp_[v].pot = al;          // alpha_v
+            cp_[v].ex = 2;            // left copies supply 2
+            cp_[n + v].pot = lam[v] - al;   // beta_v
+            cp_[n + v].ex = -2;       // right copies demand 2
             src_.push_back(v);
         }
         A_ = B_ = 0;
         keys_.clear();
-        ea_.clear();
-        eb_.clear();
-        ec_.clear();
-        y_.clear();
+        e_.clear();
         start_.assign(n, 0);
         end_.assign(n, 0);
         cap_.assign(n, 0);
         inc_.clear();
         built_ = 0;
-        // search state: dist is infinite outside the last search's touched set
-        if ((int64_t)dist_.size() != 2 * n) {
-            dist_.assign(2 * n, kInf);
-        } else {
-            for (int64_t x : touched_) dist_[x] = kInf;
-        }
-        touched_.clear();
-        par_.resize(2 * n);
-        if ((int64_t)seen_.size() != 2 * n) {
-            seen_.assign(2 * n, 0);
-            stamp_ = 0;
-        }
     }
 
-    int64_t edges() const { return (int64_t)ea_.size(); }
+    int64_t edges() const { return (int64_t)e_.size(); }
 
-    // The first candidates in bulk: the pair source's costs, the initial
-    // flow (negative-reduced-cost bits under the starting potentials) and
-    // the incidence lists.  False (nothing changed) when the cover already
-    // has edges or the data is missing or does not fit; then add() does the
-    // work.
+    // The first candidates in bulk: the pair source's keys and costs, the
+    // initial flow (negative-reduced-cost bits under the starting
+    // potentials) and the incidence lists.  False (nothing changed) when
+    // the cover already has edges or the data is missing or does not fit;
+    // then add() does the work.
     bool add_bulk(const PairList &pl, const PairSource &src)
     {
         const int64_t m = (int64_t)pl.size();
-        if (!ea_.empty() || m == 0 || !src.costs || !src.neg || !src.inc_start || !src.inc) return false;
+        if (!e_.empty() || m == 0 || !src.costs || !src.neg || !src.inc_start || !src.inc) return false;
         const int32_t *is = src.inc_start;
         if (is[0] != 0 || (int64_t)is[n_] != 2 * m + kSpare * n_) return false;
         for (int64_t v = 0; v < n_; ++v)
@@ -99,25 +94,23 @@ public:
             keys_[i] = pair_key(a, b);
             if (i > 0 && keys_[i - 1] >= keys_[i]) return false;
         }
-        ea_.resize(m);
-        eb_.resize(m);
-        ec_.resize(m);
-        y_.resize(2 * m);
+        e_.resize(m);
         for (int64_t i = 0; i < m; ++i) {
             const int32_t a = pl[i].first, b = pl[i].second;
-            ea_[i] = a;
-            eb_[i] = b;
-            ec_[i] = src.costs[i];
             const uint8_t f = src.neg[i];
-            y_[2 * i] = f & 1;
-            y_[2 * i + 1] = (f >> 1) & 1;
+            Edge &ed = e_[i];
+            ed.a = a;
+            ed.b = b;
+            ed.c = src.costs[i];
+            ed.y[0] = f & 1;
+            ed.y[1] = (f >> 1) & 1;
             if (f & 1) {
-                --ex_[a];
-                if (++ex_[n_ + b] == 1) src_.push_back(n_ + b);
+                --cp_[a].ex;
+                if (++cp_[n_ + b].ex == 1) src_.push_back(n_ + b);
             }
             if (f & 2) {
-                --ex_[b];
-                if (++ex_[n_ + a] == 1) src_.push_back(n_ + a);
+                --cp_[b].ex;
+                if (++cp_[n_ + a].ex == 1) src_.push_back(n_ + a);
             }
         }
         for (int64_t v = 0; v < n_; ++v) {
@@ -166,25 +159,26 @@ public:
         }
         if (fresh_.empty()) return;
         for (size_t q = 0; q < fresh_.size(); ++q) {
-            const int32_t a = (int32_t)(fresh_[q] >> 32), b = (int32_t)(fresh_[q] & 0xffffffffULL);
-            int64_t c = fresh_c_[q];
-            if (!costs) {
-                const int64_t dx = (int64_t)xy_[2 * a] - xy_[2 * b], dy = (int64_t)xy_[2 * a + 1] - xy_[2 * b + 1];
-                c = nint_sqrt_host(dx * dx + dy * dy);
+            Edge ed;
+            ed.a = (int32_t)(fresh_[q] >> 32);
+            ed.b = (int32_t)(fresh_[q] & 0xffffffffULL);
+            if (costs) {
+                ed.c = fresh_c_[q];
+            } else {
+                const int64_t dx = (int64_t)xy_[2 * ed.a] - xy_[2 * ed.b];
+                const int64_t dy = (int64_t)xy_[2 * ed.a + 1] - xy_[2 * ed.b + 1];
+                ed.c = (int32_t)nint_sqrt_host(dx * dx + dy * dy);
             }
-            ea_.push_back(a);
-            eb_.push_back(b);
-            ec_.push_back(c);
             for (int d = 0; d < 2; ++d) {
-                const int64_t k = 2 * ((int64_t)ea_.size() - 1) + d;
-                const bool neg = red(k) < 0;
-                y_.push_back(neg ? 1 : 0);
+                const int64_t t = d ? ed.b : ed.a, h = d ? ed.a : ed.b;
+                const bool neg = ed.c - cp_[t].pot - cp_[n_ + h].pot - A_ - B_ < 0;
+                ed.y[d] = neg ? 1 : 0;
                 if (neg) {
-                    --ex_[tail(k)];
-                    const int64_t h = n_ + head(k);
-                    if (++ex_[h] == 1) src_.push_back(h);
+                    --cp_[t].ex;
+                    if (++cp_[n_ + h].ex == 1) src_.push_back(n_ + h);
                 }
             }
+            e_.push_back(ed);
         }
         merged_.resize(keys_.size() + fresh_.size());
         std::merge(keys_.begin(), keys_.end(), fresh_.begin(), fresh_.end(), merged_.begin());
@@ -210,24 +204,29 @@ public:
             // the excess nodes (the list only shrinks while solving)
             size_t w = 0;
             for (size_t i = 0; i < src_.size(); ++i)
-                if (ex_[src_[i]] > 0) src_[w++] = src_[i];
+                if (cp_[src_[i]].ex > 0) src_[w++] = src_[i];
             src_.resize(w);
             std::sort(src_.begin(), src_.end());
             src_.erase(std::unique(src_.begin(), src_.end()), src_.end());
             if (src_.empty()) return true;
             if (single) {
+                if ((int64_t)src_.size() >= parallel_min_) {
+                    single_chunks(paths, phases);
+                    if (src_.empty()) return true;
+                }
                 for (int64_t s : src_) {
-                    while (ex_[s] > 0) {
+                    while (cp_[s].ex > 0) {
                         int64_t t;
                         if (!shortest(&s, 1, t)) return false;
                         ++phases;
                         for (int64_t x = t; x != s;) {   // flip the tree path back to s
-                            const int64_t k = par_[x];
-                            y_[k] ^= 1;
-                            x = (x < n_) ? n_ + head(k) : tail(k);
+                            const int64_t k = cp_[x].par;
+                            Edge &ed = e_[k >> 1];
+                            ed.y[k & 1] ^= 1;
+                            x = (x < n_) ? n_ + head(ed, k & 1) : tail(ed, k & 1);
                         }
-                        --ex_[s];
-                        ++ex_[t];
+                        --cp_[s].ex;
+                        ++cp_[t].ex;
                         ++paths;
                     }
                 }
@@ -246,7 +245,7 @@ public:
             const int32_t stamp = ++stamp_;
             int64_t found = 0;
             for (int64_t s : src_) {
-                while (ex_[s] > 0 && seen_[s] != stamp) {
+                while (cp_[s].ex > 0 && cp_[s].seen != stamp) {
                     if (!augment_from(s, stamp)) break;
                     ++paths;
                     ++found;
@@ -256,10 +255,16 @@ public:
         }
     }
 
+    void set_threads(int t, int64_t parallel_min)
+    {
+        threads_ = std::max(1, t);
+        parallel_min_ = std::max<int64_t>(1, parallel_min);
+    }
+
     void lam(std::vector<int64_t> &out) const
     {
         out.resize(n_);
-        for (int64_t v = 0; v < n_; ++v) out[v] = alpha_[v] + A_ + beta_[v] + B_;
+        for (int64_t v = 0; v < n_; ++v) out[v] = cp_[v].pot + A_ + cp_[n_ + v].pot + B_;
     }
 
     // the edges with flow, in candidate order
@@ -268,20 +273,40 @@ public:
         eu.clear();
         ev.clear();
         ex2.clear();
-        for (int64_t i = 0; i < (int64_t)ea_.size(); ++i) {
-            const int f = y_[2 * i] + y_[2 * i + 1];
+        for (const Edge &ed : e_) {
+            const int f = ed.y[0] + ed.y[1];
             if (f == 0) continue;
-            eu.push_back(ea_[i]);
-            ev.push_back(eb_[i]);
+            eu.push_back(ed.a);
+            ev.push_back(ed.b);
             ex2.push_back((uint8_t)f);
         }
     }
 
 private:
-    int64_t tail(int64_t k) const { return (k & 1) ? eb_[k >> 1] : ea_[k >> 1]; }
-    int64_t head(int64_t k) const { return (k & 1) ? ea_[k >> 1] : eb_[k >> 1]; }
-    // alpha, beta are stored relative to the global offsets A_, B_
-    int64_t red(int64_t k) const { return ec_[k >> 1] - alpha_[tail(k)] - beta_[head(k)] - A_ - B_; }
+    using Item = std::pair<int64_t, int64_t>;   // (distance, node copy)
+    struct Edge {
+        int32_t a, b;      // a < b
+        int32_t c;         // cost
+        uint8_t y[2];      // flow of arc a'->b'' (0) and b'->a'' (1)
+        uint8_t pad[2];
+    };
+    struct Copy {
+        int64_t pot;       // alpha (left copy) or beta (right copy), before the global offsets
+        int64_t dist = kInf;
+        int64_t par = -1;  // arc of the search tree into this copy
+        int32_t ex = 0;    // excess
+        int32_t seen = 0;  // augmentation pass stamp
+    };
+    static_assert(sizeof(Edge) == 16 && sizeof(Copy) == 32, "records share cache lines evenly");
+
+    static int64_t tail(const Edge &ed, int d) { return d ? ed.b : ed.a; }
+    static int64_t head(const Edge &ed, int d) { return d ? ed.a : ed.b; }
+    // reduced cost of arc d of edge ed: c - alpha_tail - beta_head (with
+    // the global offsets A_ of alpha and B_ of beta)
+    int64_t red(const Edge &ed, int d) const
+    {
+        return ed.c - cp_[tail(ed, d)].pot - cp_[n_ + head(ed, d)].pot - A_ - B_;
+    }
 
     // Incident edges per node, in increasing edge index: both copies of a
     // node use the same list (edge e leaves a_e' and b_e' and enters b_e''
@@ -294,11 +319,11 @@ private:
     static constexpr int64_t kSpare = 2;
     void build_adjacency()
     {
-        const int64_t e = (int64_t)ea_.size();
+        const int64_t e = (int64_t)e_.size();
         if (built_ == 0 && inc_.empty()) {
             int64_t at = 0;
             for (int64_t v = 0; v < n_; ++v) end_[v] = 0;
-            for (int64_t i = 0; i < e; ++i) { ++end_[ea_[i]]; ++end_[eb_[i]]; }
+            for (int64_t i = 0; i < e; ++i) { ++end_[e_[i].a]; ++end_[e_[i].b]; }
             for (int64_t v = 0; v < n_; ++v) {
                 start_[v] = at;
                 at += end_[v] + kSpare;
@@ -307,13 +332,13 @@ private:
             }
             inc_.resize(at);
             for (int64_t i = 0; i < e; ++i) {
-                inc_[end_[ea_[i]]++] = (int32_t)i;
-                inc_[end_[eb_[i]]++] = (int32_t)i;
+                inc_[end_[e_[i].a]++] = (int32_t)i;
+                inc_[end_[e_[i].b]++] = (int32_t)i;
             }
         } else {
             for (int64_t i = built_; i < e; ++i) {
-                place(ea_[i], (int32_t)i);
-                place(eb_[i], (int32_t)i);
+                place(e_[i].a, (int32_t)i);
+                place(e_[i].b, (int32_t)i);
             }
         }
         built_ = e;
@@ -336,62 +361,232 @@ private:
     // Dijkstra on reduced costs from the given excess nodes up to the first
     // deficit t (at distance D); then p(x) moves by min(dist(x), D) for
     // every node (through the global offsets for the nodes not reached).
-    // par_ holds the search tree's arcs.  False when no deficit is reachable.
+    // The tree arcs are in Copy::par.  False when no deficit is reachable.
     bool shortest(const int64_t *srcs, size_t ns, int64_t &t)
     {
-        std::vector<int64_t> &dist = dist_;
-        for (int64_t x : touched_) dist[x] = kInf;
+        for (int64_t x : touched_) cp_[x].dist = kInf;
         touched_.clear();
         // nodes at the current distance wait in a plain list (zero-cost
         // arcs are common here); larger distances go through the heap
-        std::vector<int64_t> &cur = cur_;
-        cur.clear();
+        cur_.clear();
         heap_.clear();
         int64_t dcur = 0;
         for (size_t i = 0; i < ns; ++i) {
             const int64_t x = srcs[i];
-            dist[x] = 0;
-            par_[x] = -1;
+            cp_[x].dist = 0;
+            cp_[x].par = -1;
             touched_.push_back(x);
-            cur.push_back(x);
+            cur_.push_back(x);
         }
         int64_t D = -1;
         for (;;) {
             int64_t x;
-            if (!cur.empty()) {
-                x = cur.back();
-                cur.pop_back();
-                if (dist[x] != dcur) continue;
+            if (!cur_.empty()) {
+                x = cur_.back();
+                cur_.pop_back();
+                if (cp_[x].dist != dcur) continue;
             } else {
                 if (heap_.empty()) break;
                 std::pop_heap(heap_.begin(), heap_.end(), std::greater<Item>());
                 const Item it = heap_.back();
                 heap_.pop_back();
-                if (it.first != dist[it.second]) continue;
+                if (it.first != cp_[it.second].dist) continue;
                 dcur = it.first;
                 x = it.second;
             }
-            if (ex_[x] < 0) { D = dcur; t = x; break; }
+            if (cp_[x].ex < 0) { D = dcur; t = x; break; }
             relax_from(x, dcur);
         }
         if (D < 0) return false;
         for (int64_t x : touched_) {
-            const int64_t d = dist[x];
-            if (d >= D) continue;
-            if (x < n_) alpha_[x] += D - d;
-            else beta_[x - n_] -= D - d;
+            Copy &c = cp_[x];
+            if (c.dist >= D) continue;
+            if (x < n_) c.pot += D - c.dist;
+            else c.pot -= D - c.dist;
         }
         A_ -= D;
         B_ += D;
         return true;
     }
 
+    // The single-source tail by chunks, in parallel.  Nodes are split into
+    // contiguous chunks (the callers number them in a spatial order, so a
+    // chunk is a region); a thread serves the excess nodes of its chunks,
+    // and a search
+    // that would reach a node outside its chunk is undone and left to the
+    // sequential tail.  A chunk's searches read and write only its own
+    // nodes and the edges inside it, and skip the global offsets (which
+    // change no reduced cost and no Lam), so chunks never share state and
+    // every chunk's result is the same whatever the threads' timing.  Leaves
+    // the deferred excess nodes in src_ (sorted).
+    struct Worker {
+        std::vector<int64_t> touched, cur, deferred;
+        std::vector<Item> heap;
+        int64_t paths = 0, phases = 0;
+    };
+    void single_chunks(int64_t &paths, int64_t &phases)
+    {
+        // the last sequential search's distances are still set
+        for (int64_t x : touched_) cp_[x].dist = kInf;
+        touched_.clear();
+        // at most 64 chunks of W nodes, at least 256 each (never a function
+        // of the thread count, so every count gives the same result); a
+        // second round with the boundaries moved by W / 2 serves most of the
+        // searches that crossed one
+        const int64_t K = std::max<int64_t>(1, std::min<int64_t>(64, n_ / 256));
+        const int64_t W = (n_ + K - 1) / K;
+        chunk_round(W, 0, paths, phases);
+        if (src_.size() > 1 && W > 1) chunk_round(W, W / 2, paths, phases);
+    }
+
+    // One parallel round over the chunks c = [max(0, (c - 1) W + o),
+    // min(n, c W + o)); the deferred excess nodes are left in src_ (sorted).
+    void chunk_round(int64_t W, int64_t o, int64_t &paths, int64_t &phases)
+    {
+        auto chunk_of = [&](int64_t x) { return ((x < n_ ? x : x - n_) + W - o) / W; };
+        const int64_t K = chunk_of(n_ - 1) + 1;
+        std::vector<int64_t> first(K + 1, 0);
+        for (int64_t x : src_) ++first[chunk_of(x) + 1];
+        for (int64_t c = 0; c < K; ++c) first[c + 1] += first[c];
+        std::vector<int64_t> bysrc(src_.size());
+        {
+            std::vector<int64_t> at(first.begin(), first.end() - 1);
+            for (int64_t x : src_) bysrc[at[chunk_of(x)]++] = x;
+        }
+        const int T = (int)std::min<int64_t>(threads_, K);
+        workers_.resize(T);
+        std::atomic<int64_t> next{0};
+        auto run = [&](int w) {
+            Worker &wk = workers_[w];
+            wk.paths = wk.phases = 0;
+            wk.deferred.clear();
+            for (int64_t c; (c = next.fetch_add(1)) < K;) {
+                const int64_t lo = std::max<int64_t>(0, (c - 1) * W + o), hi = std::min<int64_t>(n_, c * W + o);
+                for (int64_t i = first[c]; i < first[c + 1]; ++i) {
+                    const int64_t s = bysrc[i];
+                    while (cp_[s].ex > 0) {
+                        int64_t t;
+                        if (!shortest_in(wk, s, lo, hi, t)) {
+                            wk.deferred.push_back(s);
+                            break;
+                        }
+                        ++wk.phases;
+                        for (int64_t x = t; x != s;) {
+                            const int64_t k = cp_[x].par;
+                            Edge &ed = e_[k >> 1];
+                            ed.y[k & 1] ^= 1;
+                            x = (x < n_) ? n_ + head(ed, k & 1) : tail(ed, k & 1);
+                        }
+                        --cp_[s].ex;
+                        ++cp_[t].ex;
+                        ++wk.paths;
+                    }
+                }
+            }
+            for (int64_t x : wk.touched) cp_[x].dist = kInf;
+            wk.touched.clear();
+        };
+        std::vector<std::thread> th;
+        for (int w = 1; w < T; ++w) th.emplace_back(run, w);
+        run(0);
+        for (auto &x : th) x.join();
+        src_.clear();
+        for (int w = 0; w < T; ++w) {
+            Worker &wk = workers_[w];
+            paths += wk.paths;
+            phases += wk.phases;
+            src_.insert(src_.end(), wk.deferred.begin(), wk.deferred.end());
+        }
+        std::sort(src_.begin(), src_.end());
+    }
+
+    // shortest() from one node, restricted to the nodes [lo, hi) (both
+    // copies): false (nothing changed) when the search would leave them or
+    // finds no deficit inside.  No global offsets (see single_chunks).
+    bool shortest_in(Worker &wk, int64_t s, int64_t lo, int64_t hi, int64_t &t)
+    {
+        for (int64_t x : wk.touched) cp_[x].dist = kInf;
+        wk.touched.clear();
+        wk.cur.clear();
+        wk.heap.clear();
+        int64_t dcur = 0;
+        cp_[s].dist = 0;
+        cp_[s].par = -1;
+        wk.touched.push_back(s);
+        wk.cur.push_back(s);
+        auto inside = [&](int64_t x) { const int64_t v = x < n_ ? x : x - n_; return v >= lo && v < hi; };
+        auto push = [&](int64_t to, int64_t nd, int64_t k) {
+            Copy &c = cp_[to];
+            if (nd >= c.dist) return;
+            if (c.dist == kInf) wk.touched.push_back(to);
+            c.dist = nd;
+            c.par = k;
+            if (nd == dcur) {
+                wk.cur.push_back(to);
+            } else {
+                wk.heap.push_back({nd, to});
+                std::push_heap(wk.heap.begin(), wk.heap.end(), std::greater<Item>());
+            }
+        };
+        int64_t D = -1;
+        for (;;) {
+            int64_t x;
+            if (!wk.cur.empty()) {
+                x = wk.cur.back();
+                wk.cur.pop_back();
+                if (cp_[x].dist != dcur) continue;
+            } else {
+                if (wk.heap.empty()) break;
+                std::pop_heap(wk.heap.begin(), wk.heap.end(), std::greater<Item>());
+                const Item it = wk.heap.back();
+                wk.heap.pop_back();
+                if (it.first != cp_[it.second].dist) continue;
+                dcur = it.first;
+                x = it.second;
+            }
+            if (cp_[x].ex < 0) { D = dcur; t = x; break; }
+            // relax x's residual arcs; any head outside the chunk ends the search
+            const int64_t base = cp_[x].pot + A_ + B_;
+            if (x < n_) {
+                for (int64_t p = start_[x]; p < end_[x]; ++p) {
+                    const int64_t ie = inc_[p];
+                    const Edge &ed = e_[ie];
+                    const int dd = ed.a != x;
+                    if (ed.y[dd]) continue;
+                    const int64_t w = dd ? ed.a : ed.b;
+                    if (!inside(w)) return false;
+                    push(n_ + w, dcur + ed.c - base - cp_[n_ + w].pot, 2 * ie + dd);
+                }
+            } else {
+                const int64_t u = x - n_;
+                for (int64_t p = start_[u]; p < end_[u]; ++p) {
+                    const int64_t ie = inc_[p];
+                    const Edge &ed = e_[ie];
+                    const int dd = ed.b != u;
+                    if (!ed.y[dd]) continue;
+                    const int64_t w = dd ? ed.b : ed.a;
+                    if (!inside(w)) return false;
+                    push(w, dcur - (ed.c - cp_[w].pot - base), 2 * ie + dd);
+                }
+            }
+        }
+        if (D < 0) return false;
+        for (int64_t x : wk.touched) {
+            Copy &c = cp_[x];
+            if (c.dist >= D) continue;
+            if (x < n_) c.pot += D - c.dist;
+            else c.pot -= D - c.dist;
+        }
+        return true;
+    }
+
     void push(int64_t to, int64_t nd, int64_t dcur, int64_t k)
     {
-        if (nd >= dist_[to]) return;
-        if (dist_[to] == kInf) touched_.push_back(to);
-        dist_[to] = nd;
-        par_[to] = k;
+        Copy &c = cp_[to];
+        if (nd >= c.dist) return;
+        if (c.dist == kInf) touched_.push_back(to);
+        c.dist = nd;
+        c.par = k;
         if (nd == dcur) {
             cur_.push_back(to);
         } else {
@@ -400,25 +595,28 @@ private:
         }
     }
 
-    // the arc of incident edge ie that leaves v' (left) or enters v''
-    int64_t out_arc(int64_t ie, int64_t v) const { return 2 * ie + (ea_[ie] != v); }
-    int64_t in_arc(int64_t ie, int64_t v) const { return 2 * ie + (eb_[ie] != v); }
-    int64_t other(int64_t ie, int64_t v) const { return (int64_t)ea_[ie] + eb_[ie] - v; }
-
     void relax_from(int64_t x, int64_t d)
     {
         if (x < n_) {   // left copy: arcs with y = 0, forward
+            const int64_t base = cp_[x].pot + A_ + B_;
             for (int64_t p = start_[x]; p < end_[x]; ++p) {
-                const int64_t ie = inc_[p], k = out_arc(ie, x);
-                if (y_[k]) continue;
-                push(n_ + other(ie, x), d + red(k), d, k);
+                const int64_t ie = inc_[p];
+                const Edge &ed = e_[ie];
+                const int dd = ed.a != x;            // the arc that leaves x'
+                if (ed.y[dd]) continue;
+                const int64_t w = dd ? ed.a : ed.b;  // its head w''
+                push(n_ + w, d + ed.c - base - cp_[n_ + w].pot, d, 2 * ie + dd);
             }
         } else {        // right copy: arcs with y = 1, backward
             const int64_t u = x - n_;
+            const int64_t base = cp_[x].pot + A_ + B_;
             for (int64_t p = start_[u]; p < end_[u]; ++p) {
-                const int64_t ie = inc_[p], k = in_arc(ie, u);
-                if (!y_[k]) continue;
-                push(other(ie, u), d - red(k), d, k);
+                const int64_t ie = inc_[p];
+                const Edge &ed = e_[ie];
+                const int dd = ed.b != u;            // the arc that enters u''
+                if (!ed.y[dd]) continue;
+                const int64_t w = dd ? ed.b : ed.a;  // its tail w'
+                push(w, d - (ed.c - cp_[w].pot - base), d, 2 * ie + dd);
             }
         }
     }
@@ -427,44 +625,54 @@ private:
     // node with a deficit; flips the arcs of the path found.
     bool augment_from(int64_t s, int32_t stamp)
     {
-        std::vector<int32_t> &seen = seen_;
         std::vector<Frame> &st = frames_;
         st.clear();
-        seen[s] = stamp;
+        cp_[s].seen = stamp;
         st.push_back({s, start_[s < n_ ? s : s - n_], -1});
         while (!st.empty()) {
             Frame &f = st.back();
             const int64_t x = f.x;
-            if (x != s && ex_[x] < 0) {
+            if (x != s && cp_[x].ex < 0) {
                 // flip the path
-                for (size_t i = 1; i < st.size(); ++i) y_[st[i].via] ^= 1;
-                --ex_[s];
-                ++ex_[x];
+                for (size_t i = 1; i < st.size(); ++i) {
+                    const int64_t k = st[i].via;
+                    e_[k >> 1].y[k & 1] ^= 1;
+                }
+                --cp_[s].ex;
+                ++cp_[x].ex;
                 return true;
             }
             bool pushed = false;
             if (x < n_) {
+                const int64_t base = cp_[x].pot + A_ + B_;
                 for (; f.p < end_[x]; ++f.p) {
-                    const int64_t ie = inc_[f.p], k = out_arc(ie, x);
-                    if (y_[k] || red(k) != 0) continue;
-                    const int64_t w = other(ie, x), to = n_ + w;
-                    if (seen[to] == stamp) continue;
-                    seen[to] = stamp;
+                    const int64_t ie = inc_[f.p];
+                    const Edge &ed = e_[ie];
+                    const int dd = ed.a != x;
+                    if (ed.y[dd]) continue;
+                    const int64_t w = dd ? ed.a : ed.b, to = n_ + w;
+                    if (ed.c - base - cp_[to].pot != 0) continue;
+                    if (cp_[to].seen == stamp) continue;
+                    cp_[to].seen = stamp;
                     ++f.p;
-                    st.push_back({to, start_[w], k});
+                    st.push_back({to, start_[w], 2 * ie + dd});
                     pushed = true;
                     break;
                 }
             } else {
                 const int64_t u = x - n_;
+                const int64_t base = cp_[x].pot + A_ + B_;
                 for (; f.p < end_[u]; ++f.p) {
-                    const int64_t ie = inc_[f.p], k = in_arc(ie, u);
-                    if (!y_[k] || red(k) != 0) continue;
-                    const int64_t to = other(ie, u);
-                    if (seen[to] == stamp) continue;
-                    seen[to] = stamp;
+                    const int64_t ie = inc_[f.p];
+                    const Edge &ed = e_[ie];
+                    const int dd = ed.b != u;
+                    if (!ed.y[dd]) continue;
+                    const int64_t to = dd ? ed.b : ed.a;
+                    if (ed.c - cp_[to].pot - base != 0) continue;
+                    if (cp_[to].seen == stamp) continue;
+                    cp_[to].seen = stamp;
                     ++f.p;
-                    st.push_back({to, start_[to], k});
+                    st.push_back({to, start_[to], 2 * ie + dd});
                     pushed = true;
                     break;
                 }
@@ -476,26 +684,24 @@ private:
 
     const int32_t *xy_ = nullptr;
     int64_t n_ = 0;
-    std::vector<int64_t> alpha_, beta_;
     int64_t A_ = 0, B_ = 0;          // global offsets of alpha and beta
-    std::vector<int64_t> ex_;
+    std::vector<Copy> cp_;           // node copies: left v, right n + v
     std::vector<int64_t> src_;       // nodes with excess (may hold stale entries)
-    using Item = std::pair<int64_t, int64_t>;
-    std::vector<int64_t> dist_, par_, touched_, cur_;
+    std::vector<int64_t> touched_, cur_;
     std::vector<Item> heap_;
     std::vector<uint64_t> keys_;     // sorted keys (pair_key) of the candidate edges
     std::vector<uint64_t> fresh_, merged_;
     std::vector<int32_t> fresh_c_;
-    std::vector<int32_t> ea_, eb_;
-    std::vector<int64_t> ec_;
-    std::vector<uint8_t> y_;
+    std::vector<Edge> e_;
     std::vector<int64_t> start_, end_, cap_;   // incident-edge lists (see build_adjacency)
     std::vector<int32_t> inc_;
     int64_t built_ = 0;              // edges covered by the lists
-    std::vector<int32_t> seen_;      // augmentation pass stamps
-    int32_t stamp_ = 0;
+    int32_t stamp_ = 0;              // augmentation pass stamps (Copy::seen)
     struct Frame { int64_t x, p, via; };
     std::vector<Frame> frames_;
+    int threads_ = 1;
+    int64_t parallel_min_ = 256;     // excess nodes for the chunked tail
+    std::vector<Worker> workers_;
 };
 
 }  // namespace
@@ -511,7 +717,12 @@ struct FinishWork {
     std::vector<int64_t> lam;
 };
 
-FinishWork *finish_work_create() { return new FinishWork(); }
+FinishWork *finish_work_create(int threads, int64_t parallel_min)
+{
+    FinishWork *w = new FinishWork();
+    w->g.set_threads(threads, parallel_min);
+    return w;
+}
 
 void finish_work_destroy(FinishWork *work) { delete work; }
 

@@ -73,8 +73,11 @@ struct FinishResult {
 
 // Host memory of the finish, kept from one call to the next so that its
 // buffers are reused (no fresh pages per solve); one per finishing thread.
+// Once parallel_min excess nodes are left for the flow's single-source
+// tail, it runs over ranges of nodes, on `threads` threads; the result
+// depends neither on the thread count nor on the threads' timing.
 struct FinishWork;
-FinishWork *finish_work_create();
+FinishWork *finish_work_create(int threads = 1, int64_t parallel_min = 256);
 void finish_work_destroy(FinishWork *work);
 
 // work may be null (a temporary one is used).  out's vectors keep their

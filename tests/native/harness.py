@@ -22,7 +22,7 @@ def build(outdir):
     return L
 
 
-def finish(L, xy, lam0, bulk=False, reuse=False):
+def finish(L, xy, lam0, bulk=False, reuse=0):
     xy = np.ascontiguousarray(xy, np.int32)
     n = xy.shape[0]
     lam0 = np.ascontiguousarray(lam0, np.int64)

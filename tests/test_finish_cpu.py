@@ -29,6 +29,15 @@ def check(L, xy, lam0):
         for a, b in zip((lam, eu, ev, ex), got[:4]):
             assert np.array_equal(a, b), (bulk, reuse)
         assert got[4] == st
+    # the chunked single-source tail serves the excess nodes in another
+    # order: another optimum may come out, always certified, and the same
+    # one on every run and for any thread count
+    par = [harness.finish(L, xy, lam0, bulk=True, reuse=r) for r in (2, 2, 3)]
+    c = core.certify(xy, *par[0][:4])
+    assert c["certified"] and c["primal2"] == core.exact_opt2(xy), c
+    for other in par[1:]:
+        for a, b in zip(par[0][:4], other[:4]):
+            assert np.array_equal(a, b)
     return st
 
 
@@ -69,3 +78,34 @@ def test_odd_lattice_half_values(L):
     # every node; the optimum has half values or longer edges
     xy = I.lattice(3, 3, 10)
     check(L, xy, np.zeros(9, np.int64))
+
+
+def z_order(xy):
+    """The instance with its nodes renumbered along a Z-order curve (the
+    library hands the finish nodes in such a spatial order)."""
+    x = xy[:, 0].astype(np.int64)
+    y = xy[:, 1].astype(np.int64)
+    key = np.zeros(len(xy), np.int64)
+    for b in range(20):
+        key |= ((x >> b) & 1) << (2 * b) | ((y >> b) & 1) << (2 * b + 1)
+    return xy[np.argsort(key, kind="stable")]
+
+
+def test_parallel_tail_many_chunks(L):
+    # n = 2000 in a spatial order: the parallel tail has several chunks,
+    # most searches commit inside their chunk, the rest go to the
+    # sequential tail
+    rnd = np.random.default_rng(11)
+    for xy in (z_order(I.uniform(2000, 100000, 7)), z_order(I.clustered(2000, 100000, 8, centres=6))):
+        n = len(xy)
+        lam = harness.finish(L, xy, np.zeros(n, np.int64), bulk=True)[0]
+        for lam0 in (lam + rnd.integers(-3, 4, n), rnd.integers(0, 3000, n).astype(np.int64)):
+            ref = harness.finish(L, xy, lam0, bulk=True)
+            cr = core.certify(xy, *ref[:4])
+            assert cr["certified"], cr
+            par = [harness.finish(L, xy, lam0, bulk=True, reuse=r) for r in (2, 2, 3)]
+            c = core.certify(xy, *par[0][:4])
+            assert c["certified"] and c["primal2"] == cr["primal2"], c
+            for other in par[1:]:
+                for a, b in zip(par[0][:4], other[:4]):
+                    assert np.array_equal(a, b)

@@ -62,3 +62,19 @@ def test_batch_equals_independent_solves(ctx):
             for k in ("trace", "lambda2_gdp", "lambda2", "edge_u", "edge_v", "edge_x2"):
                 assert np.array_equal(r[k], s[k]), (scan, i, k)
             assert r["primal2"] == s["primal2"] and r["certified"]
+
+
+def test_batch_equals_independent_solves_large(ctx):
+    # instances big enough that the finish's single-source tail runs by
+    # chunks: the batch's finishing threads use one thread each, a single
+    # solve several, and the bits must not differ
+    parts = [I.uniform(40000, 1000000, 21), I.clustered(50000, 1000000, 22), I.uniform(30000, 1000000, 23)]
+    off = np.zeros(len(parts) + 1, np.int64)
+    off[1:] = np.cumsum([len(p) for p in parts])
+    st, res = ctx.solve_batch(np.concatenate(parts), off)
+    assert st == "ok"
+    for part, r in zip(parts, res):
+        s = ctx.solve(part)
+        for k in ("lambda2_gdp", "lambda2", "edge_u", "edge_v", "edge_x2"):
+            assert np.array_equal(r[k], s[k]), k
+        assert r["primal2"] == s["primal2"] and r["certified"] and s["certified"]
