@@ -82,8 +82,8 @@ def cpu_baseline(xy, lam, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -172,7 +172,9 @@ def main():
             tested = sum(r["scan_pairs"] for r in runs) / max(launches, 1)
             ops = OPS_PER_PAIR * tested
             achieved = ops / (avg_ms * 1e-3) / 1e12
-            roof = {"bound": "alu", "kernel": "k_rowscan<%d,gdp>" % runs[-1]["scan_rows"], "achieved": achieved,
+            kern = ("k_rowscan_w<gdp>" if args.scan == "culled" and runs[-1]["scan_rows"] == 1
+                    else "k_rowscan<%d,gdp>" % runs[-1]["scan_rows"])
+            roof = {"bound": "alu", "kernel": kern, "achieved": achieved,
                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                     "traffic": measured_traffic("complete|%s|%s|%d" % (args.scan, args.instance, n)),
                     "avg_launch_ms": avg_ms, "launches": launches,
