@@ -28,6 +28,7 @@ struct DevBuf {
 
 struct HostBuf {   // pinned host memory
     void *p = nullptr;
+    void *dp = nullptr;   // the same memory as the device addresses it
     size_t bytes = 0;
 };
 
@@ -112,10 +113,11 @@ T *grow_host(f2m_ctx *ctx, HostBuf &b, size_t count)
     const size_t need = std::max<size_t>(count * sizeof(T), 256);
     if (b.bytes < need) {
         if (b.p) (void)hipHostFree(b.p);
-        b.p = nullptr;
+        b.p = b.dp = nullptr;
         b.bytes = 0;
-        ck(ctx, hipHostMalloc(&b.p, need, hipHostMallocDefault), "hipHostMalloc");
+        ck(ctx, hipHostMalloc(&b.p, need, hipHostMallocDefault | hipHostMallocMapped), "hipHostMalloc");
         b.bytes = need;
+        ck(ctx, hipHostGetDevicePointer(&b.dp, b.p, 0), "hipHostGetDevicePointer");
     }
     return static_cast<T *>(b.p);
 }
@@ -378,20 +380,21 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
         *kept = u;
     }
     if (u == 0) return;
-    // through pinned staging: the pair source's views point there
+    // into pinned staging, written by kernels through its device mapping;
+    // the pair source's views point there
     uint64_t *hk = grow_host<uint64_t>(ctx, ctx->h_keys, u);
     int32_t *hc = grow_host<int32_t>(ctx, ctx->h_costs, u);
-    ck(ctx, hipMemcpyAsync(hk, k3, u * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy");
-    ck(ctx, hipMemcpyAsync(hc, cd, u * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, launch_copy_bytes(k3, ctx->h_keys.dp, u * sizeof(uint64_t), st), "copy");
+    ck(ctx, launch_copy_bytes(cd, ctx->h_costs.dp, u * sizeof(int32_t), st), "copy");
     uint8_t *hn = nullptr;
     int32_t *hs = nullptr, *hi = nullptr;
     if (lam_bulk) {
         hn = grow_host<uint8_t>(ctx, ctx->h_neg, u);
         hs = grow_host<int32_t>(ctx, ctx->h_start, n + 1);
         hi = grow_host<int32_t>(ctx, ctx->h_inc, 2 * u + 2 * n);
-        ck(ctx, hipMemcpyAsync(hn, ng, u, hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipMemcpyAsync(hs, stt, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipMemcpyAsync(hi, inc, (2 * u + 2 * n) * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, launch_copy_bytes(ng, ctx->h_neg.dp, u, st), "copy");
+        ck(ctx, launch_copy_bytes(stt, ctx->h_start.dp, (n + 1) * sizeof(int32_t), st), "copy");
+        ck(ctx, launch_copy_bytes(inc, ctx->h_inc.dp, (2 * u + 2 * n) * sizeof(int32_t), st), "copy");
     }
     ck(ctx, hipStreamSynchronize(st), "sync");
     out.resize(u);

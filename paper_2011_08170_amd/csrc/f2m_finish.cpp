@@ -85,42 +85,81 @@ public:
         if (!e_.empty() || m == 0 || !src.costs || !src.neg || !src.inc_start || !src.inc) return false;
         const int32_t *is = src.inc_start;
         if (is[0] != 0 || (int64_t)is[n_] != 2 * m + kSpare * n_) return false;
-        for (int64_t v = 0; v < n_; ++v)
-            if (is[v + 1] - is[v] < kSpare) return false;
+        std::atomic<bool> ok{true};
+        // the pairs: in range, strictly increasing; edge records
         keys_.resize(m);
-        for (int64_t i = 0; i < m; ++i) {
-            const int64_t a = pl[i].first, b = pl[i].second;
-            if (a < 0 || a >= b || b >= n_) return false;
-            keys_[i] = pair_key(a, b);
-            if (i > 0 && keys_[i - 1] >= keys_[i]) return false;
-        }
         e_.resize(m);
-        for (int64_t i = 0; i < m; ++i) {
-            const int32_t a = pl[i].first, b = pl[i].second;
-            const uint8_t f = src.neg[i];
-            Edge &ed = e_[i];
-            ed.a = a;
-            ed.b = b;
-            ed.c = src.costs[i];
-            ed.y[0] = f & 1;
-            ed.y[1] = (f >> 1) & 1;
-            if (f & 1) {
-                --cp_[a].ex;
-                if (++cp_[n_ + b].ex == 1) src_.push_back(n_ + b);
+        parallel_for(m, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) {
+                const int32_t a = pl[i].first, b = pl[i].second;
+                if (a < 0 || a >= b || b >= n_ ||
+                    (i > 0 && pair_key(pl[i - 1].first, pl[i - 1].second) >= pair_key(a, b))) {
+                    ok = false;
+                    return;
+                }
+                keys_[i] = pair_key(a, b);
+                const uint8_t f = src.neg[i];
+                Edge &ed = e_[i];
+                ed.a = a;
+                ed.b = b;
+                ed.c = src.costs[i];
+                ed.y[0] = f & 1;
+                ed.y[1] = (f >> 1) & 1;
             }
-            if (f & 2) {
-                --cp_[b].ex;
-                if (++cp_[n_ + a].ex == 1) src_.push_back(n_ + a);
-            }
+        });
+        // per node: its list (copied, with its free slots), and the excess
+        // of both copies from the arcs its list's edges saturate
+        if (ok) {
+            parallel_for(n_, [&](int64_t lo, int64_t hi) {
+                for (int64_t v = lo; v < hi; ++v) {
+                    const int64_t s0 = is[v], s1 = is[v + 1] - kSpare;
+                    if (s1 < s0) { ok = false; return; }
+                    int32_t out = 0, in = 0;
+                    for (int64_t p = s0; p < s1; ++p) {
+                        const int32_t ie = src.inc[p];
+                        if (ie < 0 || ie >= m || (e_[ie].a != v && e_[ie].b != v)) { ok = false; return; }
+                        const Edge &ed = e_[ie];
+                        out += ed.y[ed.a != v];   // the arc that leaves v'
+                        in += ed.y[ed.b != v];    // the arc that enters v''
+                    }
+                    cp_[v].ex = 2 - out;
+                    cp_[n_ + v].ex = -2 + in;
+                    start_[v] = s0;
+                    end_[v] = s1;
+                    cap_[v] = is[v + 1];
+                }
+            });
         }
-        for (int64_t v = 0; v < n_; ++v) {
-            start_[v] = is[v];
-            end_[v] = is[v + 1] - kSpare;
-            cap_[v] = is[v + 1];
+        if (!ok) {
+            keys_.clear();
+            e_.clear();
+            for (int64_t v = 0; v < n_; ++v) {
+                cp_[v].ex = 2;
+                cp_[n_ + v].ex = -2;
+                start_[v] = end_[v] = cap_[v] = 0;
+            }
+            return false;
         }
         inc_.assign(src.inc, src.inc + is[n_]);
+        for (int64_t v = 0; v < n_; ++v)
+            if (cp_[n_ + v].ex > 0) src_.push_back(n_ + v);
         built_ = m;
         return true;
+    }
+
+    // f(lo, hi) over [0, count) split in contiguous ranges, one per thread
+    template <class F>
+    void parallel_for(int64_t count, F f)
+    {
+        const int T = (int)std::max<int64_t>(1, std::min<int64_t>(threads_, count / 4096));
+        if (T == 1) {
+            f(0, count);
+            return;
+        }
+        std::vector<std::thread> th;
+        for (int w = 1; w < T; ++w) th.emplace_back([&, w] { f(count * w / T, count * (w + 1) / T); });
+        f(0, count / T);
+        for (auto &x : th) x.join();
     }
 
     // Adds new candidate edges (pairs with costs, or null: computed here);
@@ -189,17 +228,21 @@ public:
     // Min-cost flow on the current candidates; false when some excess
     // cannot reach a deficit (the candidate graph is too small).
     //
-    // Primal-dual: while many excess nodes remain, one Dijkstra from all of
-    // them sets the distance D of the nearest deficit, the potentials move
-    // by min(dist, D) and every excess node augments along zero-reduced-cost
-    // paths.  Once a phase augments few paths, the remaining excess nodes
-    // are served one at a time (successive shortest paths): a Dijkstra from
-    // the node alone stops at its nearest deficit and the path of the
-    // search tree is augmented.  Both keep every residual reduced cost
-    // nonnegative, so the end result is a minimum-cost flow.
+    // Primal-dual from feasible potentials (every residual reduced cost
+    // nonnegative).  The first pass augments unit paths along the
+    // zero-reduced-cost arcs the starting potentials already have.  The
+    // excess nodes left then lie at many different distances from their
+    // deficits (one Dijkstra from all of them would serve only the nearest
+    // few: measured at n = 100k, such a phase found 11 paths for 3000
+    // excess nodes), so they are served one at a time (successive shortest
+    // paths): a Dijkstra from the node alone stops at its nearest deficit,
+    // the potentials move by min(dist, D) and the path of the search tree
+    // is augmented.  Both keep every residual reduced cost nonnegative, so
+    // the end result is a minimum-cost flow.  Both run by chunks first (in
+    // parallel), then over the whole graph.
     bool solve(int64_t &paths, int64_t &phases)
     {
-        bool single = false, first = true;
+        bool first = true;
         for (;;) {
             // the excess nodes (the list only shrinks while solving)
             size_t w = 0;
@@ -209,49 +252,38 @@ public:
             std::sort(src_.begin(), src_.end());
             src_.erase(std::unique(src_.begin(), src_.end()), src_.end());
             if (src_.empty()) return true;
-            if (single) {
-                if ((int64_t)src_.size() >= parallel_min_) {
-                    single_chunks(paths, phases);
-                    if (src_.empty()) return true;
-                }
+            if (first) {
+                first = false;
+                if ((int64_t)src_.size() >= parallel_min_) zero_chunks(paths);
+                const int32_t stamp = ++stamp_;
                 for (int64_t s : src_) {
-                    while (cp_[s].ex > 0) {
-                        int64_t t;
-                        if (!shortest(&s, 1, t)) return false;
-                        ++phases;
-                        for (int64_t x = t; x != s;) {   // flip the tree path back to s
-                            const int64_t k = cp_[x].par;
-                            Edge &ed = e_[k >> 1];
-                            ed.y[k & 1] ^= 1;
-                            x = (x < n_) ? n_ + head(ed, k & 1) : tail(ed, k & 1);
-                        }
-                        --cp_[s].ex;
-                        ++cp_[t].ex;
+                    while (cp_[s].ex > 0 && cp_[s].seen != stamp) {
+                        if (!augment_from(s, stamp)) break;
                         ++paths;
                     }
                 }
                 continue;
             }
-            // the starting potentials are feasible, so the first pass
-            // augments along the zero-reduced-cost paths they already have;
-            // later passes follow a Dijkstra that moves the potentials
-            if (!first) {
-                int64_t t;
-                if (!shortest(src_.data(), src_.size(), t)) return false;
-                ++phases;
+            if ((int64_t)src_.size() >= parallel_min_) {
+                single_chunks(paths, phases);
+                if (src_.empty()) return true;
             }
-            first = false;
-            // unit augmentations along zero-reduced-cost paths
-            const int32_t stamp = ++stamp_;
-            int64_t found = 0;
             for (int64_t s : src_) {
-                while (cp_[s].ex > 0 && cp_[s].seen != stamp) {
-                    if (!augment_from(s, stamp)) break;
+                while (cp_[s].ex > 0) {
+                    int64_t t;
+                    if (!shortest(&s, 1, t)) return false;
+                    ++phases;
+                    for (int64_t x = t; x != s;) {   // flip the tree path back to s
+                        const int64_t k = cp_[x].par;
+                        Edge &ed = e_[k >> 1];
+                        ed.y[k & 1] ^= 1;
+                        x = (x < n_) ? n_ + head(ed, k & 1) : tail(ed, k & 1);
+                    }
+                    --cp_[s].ex;
+                    ++cp_[t].ex;
                     ++paths;
-                    ++found;
                 }
             }
-            single = found < std::max<int64_t>(8, (int64_t)src_.size() / 16);
         }
     }
 
@@ -284,6 +316,7 @@ public:
 
 private:
     using Item = std::pair<int64_t, int64_t>;   // (distance, node copy)
+    struct Frame { int64_t x, p, via; };        // depth-first search stack entry
     struct Edge {
         int32_t a, b;      // a < b
         int32_t c;         // cost
@@ -422,26 +455,89 @@ private:
     struct Worker {
         std::vector<int64_t> touched, cur, deferred;
         std::vector<Item> heap;
+        std::vector<Frame> frames;
         int64_t paths = 0, phases = 0;
     };
+    // at most 64 chunks of W nodes, at least 256 each (never a function of
+    // the thread count, so every count gives the same result)
+    int64_t chunk_width() const
+    {
+        const int64_t K = std::max<int64_t>(1, std::min<int64_t>(64, n_ / 256));
+        return (n_ + K - 1) / K;
+    }
+
     void single_chunks(int64_t &paths, int64_t &phases)
     {
         // the last sequential search's distances are still set
         for (int64_t x : touched_) cp_[x].dist = kInf;
         touched_.clear();
-        // at most 64 chunks of W nodes, at least 256 each (never a function
-        // of the thread count, so every count gives the same result); a
-        // second round with the boundaries moved by W / 2 serves most of the
-        // searches that crossed one
-        const int64_t K = std::max<int64_t>(1, std::min<int64_t>(64, n_ / 256));
-        const int64_t W = (n_ + K - 1) / K;
-        chunk_round(W, 0, paths, phases);
-        if (src_.size() > 1 && W > 1) chunk_round(W, W / 2, paths, phases);
+        // a second round with the boundaries moved by W / 2 serves most of
+        // the searches that crossed one;
+        const int64_t W = chunk_width();
+        auto serve = [&](Worker &wk, int64_t lo, int64_t hi, int64_t s) {
+            while (cp_[s].ex > 0) {
+                int64_t t;
+                if (!shortest_in(wk, s, lo, hi, t)) {
+                    wk.deferred.push_back(s);
+                    return;
+                }
+                ++wk.phases;
+                for (int64_t x = t; x != s;) {
+                    const int64_t k = cp_[x].par;
+                    Edge &ed = e_[k >> 1];
+                    ed.y[k & 1] ^= 1;
+                    x = (x < n_) ? n_ + head(ed, k & 1) : tail(ed, k & 1);
+                }
+                --cp_[s].ex;
+                ++cp_[t].ex;
+                ++wk.paths;
+            }
+        };
+        // a third round with 4 W wide chunks takes most of the long searches
+        for (int round = 0; round < 3; ++round) {
+            if (src_.empty() || (round == 1 && W < 2) || (round == 2 && 4 * W >= n_)) break;
+            if (round < 2) chunk_round(W, round == 0 ? 0 : W / 2, serve);
+            else chunk_round(4 * W, 0, serve);
+            src_.clear();
+            for (Worker &wk : workers_) {
+                paths += wk.paths;
+                phases += wk.phases;
+                src_.insert(src_.end(), wk.deferred.begin(), wk.deferred.end());
+            }
+            std::sort(src_.begin(), src_.end());
+        }
+    }
+
+    // The first augmentations of the zero-reduced-cost pass, chunk by chunk
+    // (a search never leaves its chunk; a second round with the boundaries
+    // moved by half a chunk); returns the paths found.  src_ is kept:
+    // solve() goes on with a pass over the whole graph.
+    int64_t zero_chunks(int64_t &paths)
+    {
+        const int64_t W = chunk_width();
+        int64_t found = 0;
+        for (int round = 0; round < 2; ++round) {
+            if (round == 1 && W < 2) break;
+            const int32_t stamp = ++stamp_;
+            auto serve = [&](Worker &wk, int64_t lo, int64_t hi, int64_t s) {
+                while (cp_[s].ex > 0 && cp_[s].seen != stamp) {
+                    if (!augment_in(wk, s, stamp, lo, hi)) return;
+                    ++wk.paths;
+                }
+            };
+            chunk_round(W, round == 0 ? 0 : W / 2, serve);
+            for (Worker &wk : workers_) found += wk.paths;
+        }
+        paths += found;
+        return found;
     }
 
     // One parallel round over the chunks c = [max(0, (c - 1) W + o),
-    // min(n, c W + o)); the deferred excess nodes are left in src_ (sorted).
-    void chunk_round(int64_t W, int64_t o, int64_t &paths, int64_t &phases)
+    // min(n, c W + o)): serve(worker, lo, hi, s) for every excess node of
+    // src_ in chunk c, in increasing order; the workers' counters and
+    // deferred lists start empty.
+    template <class Serve>
+    void chunk_round(int64_t W, int64_t o, Serve &serve)
     {
         auto chunk_of = [&](int64_t x) { return ((x < n_ ? x : x - n_) + W - o) / W; };
         const int64_t K = chunk_of(n_ - 1) + 1;
@@ -453,7 +549,7 @@ private:
             std::vector<int64_t> at(first.begin(), first.end() - 1);
             for (int64_t x : src_) bysrc[at[chunk_of(x)]++] = x;
         }
-        const int T = (int)std::min<int64_t>(threads_, K);
+        const int T = (int)std::max<int64_t>(1, std::min<int64_t>(threads_, K));
         workers_.resize(T);
         std::atomic<int64_t> next{0};
         auto run = [&](int w) {
@@ -462,26 +558,7 @@ private:
             wk.deferred.clear();
             for (int64_t c; (c = next.fetch_add(1)) < K;) {
                 const int64_t lo = std::max<int64_t>(0, (c - 1) * W + o), hi = std::min<int64_t>(n_, c * W + o);
-                for (int64_t i = first[c]; i < first[c + 1]; ++i) {
-                    const int64_t s = bysrc[i];
-                    while (cp_[s].ex > 0) {
-                        int64_t t;
-                        if (!shortest_in(wk, s, lo, hi, t)) {
-                            wk.deferred.push_back(s);
-                            break;
-                        }
-                        ++wk.phases;
-                        for (int64_t x = t; x != s;) {
-                            const int64_t k = cp_[x].par;
-                            Edge &ed = e_[k >> 1];
-                            ed.y[k & 1] ^= 1;
-                            x = (x < n_) ? n_ + head(ed, k & 1) : tail(ed, k & 1);
-                        }
-                        --cp_[s].ex;
-                        ++cp_[t].ex;
-                        ++wk.paths;
-                    }
-                }
+                for (int64_t i = first[c]; i < first[c + 1]; ++i) serve(wk, lo, hi, bysrc[i]);
             }
             for (int64_t x : wk.touched) cp_[x].dist = kInf;
             wk.touched.clear();
@@ -490,14 +567,6 @@ private:
         for (int w = 1; w < T; ++w) th.emplace_back(run, w);
         run(0);
         for (auto &x : th) x.join();
-        src_.clear();
-        for (int w = 0; w < T; ++w) {
-            Worker &wk = workers_[w];
-            paths += wk.paths;
-            phases += wk.phases;
-            src_.insert(src_.end(), wk.deferred.begin(), wk.deferred.end());
-        }
-        std::sort(src_.begin(), src_.end());
     }
 
     // shortest() from one node, restricted to the nodes [lo, hi) (both
@@ -623,9 +692,17 @@ private:
 
     // Depth-first search from s over zero-reduced-cost residual arcs to a
     // node with a deficit; flips the arcs of the path found.
-    bool augment_from(int64_t s, int32_t stamp)
+    bool augment_from(int64_t s, int32_t stamp) { return augment(frames_, s, stamp, 0, n_); }
+
+    // The same inside the nodes [lo, hi) (both copies), with the worker's
+    // own stack.
+    bool augment_in(Worker &wk, int64_t s, int32_t stamp, int64_t lo, int64_t hi)
     {
-        std::vector<Frame> &st = frames_;
+        return augment(wk.frames, s, stamp, lo, hi);
+    }
+
+    bool augment(std::vector<Frame> &st, int64_t s, int32_t stamp, int64_t lo, int64_t hi)
+    {
         st.clear();
         cp_[s].seen = stamp;
         st.push_back({s, start_[s < n_ ? s : s - n_], -1});
@@ -651,6 +728,7 @@ private:
                     const int dd = ed.a != x;
                     if (ed.y[dd]) continue;
                     const int64_t w = dd ? ed.a : ed.b, to = n_ + w;
+                    if (w < lo || w >= hi) continue;
                     if (ed.c - base - cp_[to].pot != 0) continue;
                     if (cp_[to].seen == stamp) continue;
                     cp_[to].seen = stamp;
@@ -668,6 +746,7 @@ private:
                     const int dd = ed.b != u;
                     if (!ed.y[dd]) continue;
                     const int64_t to = dd ? ed.b : ed.a;
+                    if (to < lo || to >= hi) continue;
                     if (ed.c - cp_[to].pot - base != 0) continue;
                     if (cp_[to].seen == stamp) continue;
                     cp_[to].seen = stamp;
@@ -697,7 +776,6 @@ private:
     std::vector<int32_t> inc_;
     int64_t built_ = 0;              // edges covered by the lists
     int32_t stamp_ = 0;              // augmentation pass stamps (Copy::seen)
-    struct Frame { int64_t x, p, via; };
     std::vector<Frame> frames_;
     int threads_ = 1;
     int64_t parallel_min_ = 256;     // excess nodes for the chunked tail

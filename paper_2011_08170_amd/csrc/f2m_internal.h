@@ -250,6 +250,9 @@ hipError_t launch_set_lam(const int64_t *lam_label, const int32_t *orig, int64_t
                           float4 *col, float *tile_hmax, Ctrl *ctrl, hipStream_t st);
 hipError_t launch_unpermute(const int64_t *lam_sorted, const int32_t *orig, int64_t n, int64_t *lam_label,
                             hipStream_t st);
+// copy of `bytes` bytes by a kernel (both 16-byte aligned; dst may be
+// pinned host memory mapped into the device's address space)
+hipError_t launch_copy_bytes(const void *src, void *dst, int64_t bytes, hipStream_t st);
 // coordinates by label -> by Morton position (xy_pos[2n])
 hipError_t launch_gather_xy(const int32_t *xy, const int32_t *orig, int64_t n, int32_t *xy_pos, hipStream_t st);
 // edges as Morton positions -> labels (lo < hi), in place

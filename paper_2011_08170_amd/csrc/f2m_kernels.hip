@@ -1403,6 +1403,18 @@ __global__ __launch_bounds__(kBlock) void k_pair_to_key(const int2 *pairs, int64
     if (i < count) keys[i] = ((uint64_t)(uint32_t)pairs[i].x << 32) | (uint64_t)(uint32_t)pairs[i].y;
 }
 
+// bytes [0, n16 * 16) as 16-byte words, then the tail byte by byte (both
+// pointers 16-byte aligned); the destination may be mapped host memory
+__global__ __launch_bounds__(kBlock) void k_copy_bytes(const uint8_t *src, uint8_t *dst, int64_t bytes)
+{
+    const int64_t n16 = bytes / 16;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride) d4[i] = s4[i];
+    if (blockIdx.x == 0 && threadIdx.x < bytes - 16 * n16) dst[16 * n16 + threadIdx.x] = src[16 * n16 + threadIdx.x];
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t count, int32_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1882,6 +1894,18 @@ hipError_t launch_unpermute(const int64_t *lam_sorted, const int32_t *orig, int6
                             hipStream_t st)
 {
     hipLaunchKernelGGL(k_unpermute, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam_sorted, orig, n, lam_label);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_bytes(const void *src, void *dst, int64_t bytes, hipStream_t st)
+{
+    if (bytes <= 0) return hipSuccess;
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0) return hipErrorInvalidValue;
+    const int64_t n16 = bytes / 16;
+    const int64_t want = (n16 + kBlock - 1) / kBlock;
+    const unsigned blocks = (unsigned)(want < 1 ? 1 : (want > 1024 ? 1024 : want));
+    hipLaunchKernelGGL(k_copy_bytes, dim3(blocks), dim3(kBlock), 0, st, static_cast<const uint8_t *>(src),
+                       static_cast<uint8_t *>(dst), bytes);
     return hipGetLastError();
 }
 
