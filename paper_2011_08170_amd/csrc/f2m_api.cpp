@@ -180,11 +180,12 @@ ScanShape scan_shape_auto(int64_t n, bool cull)
     ScanShape s;
     const int64_t nt = ntiles_of(n);
     if (cull) {
-        // one row per lane; each wave's surviving sub-tiles are dealt to 4
-        // slices (measured at n = 20k, 100k and 200k: 2 slices leave the
-        // SIMDs too few waves, 8 repeat the per-wave tile walk too often)
+        // one row per lane; the four waves of a block share 64 rows and the
+        // surviving sub-tiles are dealt among them (4 parts: measured best at
+        // n = 20k, 100k and 200k; 2 leave the SIMDs too few waves, 8 repeat
+        // the tile walk too often), so one slice
         s.rows = 1;
-        const int64_t sl = std::max<int64_t>(1, std::min<int64_t>(nt, 4));
+        const int64_t sl = 1;
         s.slice_len = ((nt + sl - 1) / sl) * kTileCols;
     } else {
         s.rows = n >= 65536 ? 4 : (n >= 8192 ? 2 : 1);
@@ -672,13 +673,16 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             sa.tested = &cd->pairs_tested;
             sa.seed = seed;
             sa.pz = pz; sa.pi = pi; sa.pneg = pneg; sa.pzero = pzero; sa.prowneg = prn;
-            sa.pflag = pflag;
+            // the culled one-row-per-lane scan writes every row's partial
+            // (its blocks hold 64 rows, not the flags' row blocks)
+            int32_t *pf = (cull && sh.rows == 1) ? nullptr : pflag;
+            sa.pflag = pf;
             sa.nrb = nrb;
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
             ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
             UpdateArgs ua{gh.g, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
-                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pflag, nrb, sh.rows};
+                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows};
             ck(ctx, launch_update(ua, st), "update");
         }
         ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");

@@ -584,7 +584,13 @@ __device__ __forceinline__ void wave_sync()
 // row: the float filter marks columns in a 64-bit mask, the marked ones get
 // the exact evaluation.  No wave waits for another until the end, where the
 // block agrees on whether any of its waves scanned a column (pflag).
-template <int MODE>
+//
+// QUAD: the four waves of a block hold the same 64 rows (block rblk of 64
+// rows) and are four of the parts the survivors are dealt to (part
+// 4 sl + wave of 4 S); at the end they merge their top-4 lists and counts in
+// LDS and the block writes one partial per row for its slice.  Without
+// QUAD each wave holds its own 64 of the block's 256 rows (part sl of S).
+template <int MODE, bool QUAD>
 __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64_t rblk, const int64_t sl)
 {
     static_assert(kSubCols == 32 && kSubs == 8, "two sub-tiles per wave-wide stage, eight per tile test");
@@ -603,7 +609,8 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
     volatile int *cfill = cfill_s;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t n = a.g.n;
-    const int64_t S = a.interleave > 0 ? a.interleave : 1, sid = a.interleave > 0 ? sl : 0;
+    const int64_t S0 = a.interleave > 0 ? a.interleave : 1, sl0 = a.interleave > 0 ? sl : 0;
+    const int64_t S = QUAD ? 4 * S0 : S0, sid = QUAD ? 4 * sl0 + wave : sl0;
     const float colmax = col_bound(a.g.xy2max, a.lv.ctrl->maxabs_lam);
     if (t == 0) bany = 0;
     if (lane == 0) cfill[wave] = 0;
@@ -613,7 +620,7 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
     int32_t neg = 0, zero = 0;
     int64_t rn = 0;
     top.clear();
-    const int64_t p = rblk * kBlock + t;
+    const int64_t p = QUAD ? rblk * 64 + lane : rblk * kBlock + t;
     rw.v = p;
     if (p < n) {
         const float4 cv = a.lv.col[p];
@@ -638,12 +645,15 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
     }
     __syncthreads();   // bany and cfill are set
 
-    // the wave's rows: positions [w0, w1), their box (two sub-tile boxes)
-    const int64_t w0 = rblk * kBlock + wave * 64, w1 = min(n, w0 + 64);
+    // the wave's rows: positions [w0, w1), their box (two sub-tile boxes
+    // of the row tile rt)
+    const int64_t w0 = QUAD ? rblk * 64 : rblk * kBlock + wave * 64, w1 = min(n, w0 + 64);
+    const int64_t rt = w0 / kTile;
+    const int s0 = (int)((w0 % kTile) / kSubCols);
     float4 wbox = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
     if (w1 > w0) {
-        for (int s = wave * (64 / kSubCols); s < (wave + 1) * (64 / kSubCols); ++s) {
-            const float4 sb = a.g.box[rblk * kBoxStride + 1 + s];
+        for (int s = s0; s < s0 + 64 / kSubCols; ++s) {
+            const float4 sb = a.g.box[rt * kBoxStride + 1 + s];
             wbox.x = fminf(wbox.x, sb.x); wbox.y = fmaxf(wbox.y, sb.y);
             wbox.z = fminf(wbox.z, sb.z); wbox.w = fmaxf(wbox.w, sb.w);
         }
@@ -818,7 +828,42 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         for (int i = lane; i < fill; i += 64)
             if ((int64_t)(base + i) < a.cap) a.out[base + i] = cbuf[wave][i];
     }
-    if (MODE == kModeGdp) {
+    if (MODE == kModeGdp && QUAD) {
+        // waves 1-3 hand their rows' lists and counts to wave 0
+        __shared__ long long mz[QUAD && MODE == kModeGdp ? 3 : 1][kTop][64];
+        __shared__ int32_t mi[QUAD && MODE == kModeGdp ? 3 : 1][kTop][64];
+        __shared__ int32_t mneg[QUAD && MODE == kModeGdp ? 3 : 1][64], mzero[QUAD && MODE == kModeGdp ? 3 : 1][64];
+        __shared__ long long mrn[QUAD && MODE == kModeGdp ? 3 : 1][64];
+        if (wave > 0) {
+#pragma unroll
+            for (int j = 0; j < kTop; ++j) {
+                mz[wave - 1][j][lane] = top.z[j];
+                mi[wave - 1][j][lane] = top.id[j];
+            }
+            mneg[wave - 1][lane] = neg;
+            mzero[wave - 1][lane] = zero;
+            mrn[wave - 1][lane] = rn;
+        }
+        __syncthreads();
+        if (wave == 0 && p < n) {
+            for (int w = 0; w < 3; ++w) {
+#pragma unroll
+                for (int j = 0; j < kTop; ++j) top.insert(mz[w][j][lane], mi[w][j][lane]);
+                neg += mneg[w][lane];
+                zero += mzero[w][lane];
+                rn += mrn[w][lane];
+            }
+#pragma unroll
+            for (int j = 0; j < kTop; ++j) {
+                a.pz[(sl * kTop + j) * n + p] = top.z[j];
+                a.pi[(sl * kTop + j) * n + p] = top.id[j];
+            }
+            a.pneg[sl * n + p] = neg;
+            a.pzero[sl * n + p] = zero;
+            a.prowneg[sl * n + p] = rn;
+        }
+    }
+    if (MODE == kModeGdp && !QUAD) {
         if (scanned && lane == 0) bany = 1;
         __syncthreads();
         const bool any = bany != 0;
@@ -846,11 +891,12 @@ __global__ __launch_bounds__(kBlock) void k_rowscan(ScanArgs a)
     rowscan_body<R, MODE, CULL>(a, blockIdx.x, blockIdx.y);
 }
 
-// the culled scan with one row per lane (see rowscan_wave_body)
+// the culled scan with one row per lane, four waves per 64 rows (see
+// rowscan_wave_body)
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_rowscan_w(ScanArgs a)
 {
-    rowscan_wave_body<MODE>(a, blockIdx.x, blockIdx.y);
+    rowscan_wave_body<MODE, true>(a, blockIdx.x, blockIdx.y);
 }
 
 // batched GDP scan: one block per (instance, row block, slice)
@@ -860,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_rowscan_batch(const ScanArgs *args, 
     const BatchScanItem w = items[blockIdx.x];
     ScanArgs a = args[w.inst];
     if (a.lv.ctrl->k_next & 1) a.lv.lam = a.lam_odd;
-    if constexpr (CULL && R == 1) rowscan_wave_body<kModeGdp>(a, w.row_block, w.slice);
+    if constexpr (CULL && R == 1) rowscan_wave_body<kModeGdp, false>(a, w.row_block, w.slice);
     else rowscan_body<R, kModeGdp, CULL>(a, w.row_block, w.slice);
 }
 
@@ -1948,7 +1994,7 @@ static hipError_t launch_scan_mode(const ScanArgs &a, int64_t nslices, int R, hi
     const unsigned gy = (unsigned)nslices;
     switch (R) {
     case 1:
-        if constexpr (CULL) hipLaunchKernelGGL((k_rowscan_w<MODE>), dim3(blocks_for(a.g.n, kBlock), gy), dim3(kBlock), 0, st, a);
+        if constexpr (CULL) hipLaunchKernelGGL((k_rowscan_w<MODE>), dim3(blocks_for(a.g.n, 64), gy), dim3(kBlock), 0, st, a);
         else hipLaunchKernelGGL((k_rowscan<1, MODE, CULL>), dim3(blocks_for(a.g.n, kBlock), gy), dim3(kBlock), 0, st, a);
         break;
     case 2: hipLaunchKernelGGL((k_rowscan<2, MODE, CULL>), dim3(blocks_for(a.g.n, 2 * kBlock), gy), dim3(kBlock), 0, st, a); break;
