@@ -15,6 +15,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <initializer_list>
 #include <vector>
 
 using namespace f2m;
@@ -63,7 +64,7 @@ struct f2m_ctx {
     int64_t *scratch_host = nullptr;   // pinned, 16 entries
     // the finish's host side: pinned staging of the GPU's pair data, and its
     // workspace and result, kept from one solve to the next
-    HostBuf h_keys, h_costs, h_neg, h_start, h_inc, h_xyp, h_lamp;
+    HostBuf h_keys, h_costs, h_neg, h_start, h_inc, h_xyp, h_lamp, h_up;
     f2m::FinishWork *fwork = nullptr;
     f2m::FinishResult fres;
     // contexts (own stream and workspaces) of the batch's finishing threads
@@ -135,6 +136,17 @@ T *grow(f2m_ctx *ctx, DevBuf &b, size_t count)
     }
     return static_cast<T *>(b.p);
 }
+
+// Host arrays to the device through the pinned staging h_up: copied there,
+// then read by a kernel through its device mapping (parts[i] = {host
+// source, device destination, bytes}).  The staging is reused by the next
+// call, which comes after the stream has been synchronised.
+struct UpPart {
+    const void *src;
+    void *dst;
+    size_t bytes;
+};
+void upload(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st);
 
 double now_s()
 {
@@ -323,6 +335,22 @@ void certify_dev(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label, int6
     out[3] = (viol == 0 && out[0] == out[1]) ? 1 : 0;
 }
 
+void upload(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st)
+{
+    size_t total = 0;
+    for (const UpPart &q : parts) total += (q.bytes + 255) / 256 * 256;
+    char *h = grow_host<char>(ctx, ctx->h_up, total);
+    char *hd = static_cast<char *>(ctx->h_up.dp);
+    size_t at = 0;
+    for (const UpPart &q : parts) {
+        if (q.bytes) {
+            std::memcpy(h + at, q.src, q.bytes);
+            ck(ctx, launch_copy_bytes(hd + at, q.dst, (int64_t)q.bytes, st), "upload");
+        }
+        at += (q.bytes + 255) / 256 * 256;
+    }
+}
+
 // Sorts and de-duplicates `found` collected pairs on the device and copies
 // the distinct ones (increasing) and their exact costs to the host; with
 // lam_bulk (device, labels) also the finish's bulk data (see PairSource).
@@ -434,7 +462,7 @@ private:
             const int64_t n = gh_.g.n;
             int64_t *lam = grow<int64_t>(ctx, ctx->f_lam, n);
             unsigned long long *cnt = grow<unsigned long long>(ctx, ctx->p_count, 1);
-            ck(ctx, hipMemcpyAsync(lam, lam_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st_), "copy");
+            upload(ctx, {{lam_host, lam, n * sizeof(int64_t)}}, st_);
             LamView lv = place_lam(ctx, gh_, lam, st_, true);
             const ScanShape sh = scan_shape(n, true);
             int64_t cap = std::max<int64_t>(cap_, 8 * n);
@@ -559,7 +587,7 @@ private:
             const int64_t n = gh_.g.n;
             int64_t *lam = grow<int64_t>(ctx, ctx->f_lam, n);
             unsigned long long *cnt = grow<unsigned long long>(ctx, ctx->p_count, 1);
-            ck(ctx, hipMemcpyAsync(lam, lam_host, n * sizeof(int64_t), hipMemcpyHostToDevice, st_), "copy");
+            upload(ctx, {{lam_host, lam, n * sizeof(int64_t)}}, st_);
             LamView lv = place_lam(ctx, gh_, lam, st_, true);
             const int64_t cap = csr_.nnz + 1;
             int2 *pairs = grow<int2>(ctx, ctx->p_pairs, cap);
@@ -918,15 +946,11 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
         // duals go to their own buffer
         int64_t *lf = grow<int64_t>(ctx, ctx->lam_best, n);
         int64_t *lp = grow<int64_t>(ctx, ctx->f_lam, n);
-        ck(ctx, hipMemcpyAsync(lp, fr.lam.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, st), "copy");
+        upload(ctx, {{fr.lam.data(), lp, n * sizeof(int64_t)}, {fr.eu.data(), eu, m * sizeof(int32_t)},
+                     {fr.ev.data(), ev, m * sizeof(int32_t)}, {fr.ex2.data(), ex, m * sizeof(uint8_t)}}, st);
         ck(ctx, launch_unpermute(lp, gh.g.orig, n, lf, st), "unpermute");
         (void)ld;
-        if (m) {
-            ck(ctx, hipMemcpyAsync(eu, fr.eu.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
-            ck(ctx, hipMemcpyAsync(ev, fr.ev.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
-            ck(ctx, hipMemcpyAsync(ex, fr.ex2.data(), m * sizeof(uint8_t), hipMemcpyHostToDevice, st), "copy");
-            ck(ctx, launch_edges_to_labels(gh.g.orig, m, eu, ev, st), "edges_to_labels");
-        }
+        if (m) ck(ctx, launch_edges_to_labels(gh.g.orig, m, eu, ev, st), "edges_to_labels");
         lam_final_dev = lf;
         have_x = true;
     }
@@ -1019,7 +1043,8 @@ void f2m_destroy(f2m_ctx *ctx)
         if (b->p) (void)hipFree(b->p);
     if (ctx->ctrl_host) (void)hipHostFree(ctx->ctrl_host);
     if (ctx->scratch_host) (void)hipHostFree(ctx->scratch_host);
-    for (HostBuf *h : {&ctx->h_keys, &ctx->h_costs, &ctx->h_neg, &ctx->h_start, &ctx->h_inc, &ctx->h_xyp, &ctx->h_lamp})
+    for (HostBuf *h : {&ctx->h_keys, &ctx->h_costs, &ctx->h_neg, &ctx->h_start, &ctx->h_inc, &ctx->h_xyp, &ctx->h_lamp,
+                       &ctx->h_up})
         if (h->p) (void)hipHostFree(h->p);
     if (ctx->fwork) finish_work_destroy(ctx->fwork);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
