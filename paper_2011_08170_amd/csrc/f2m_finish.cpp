@@ -238,8 +238,9 @@ public:
     // paths): a Dijkstra from the node alone stops at its nearest deficit,
     // the potentials move by min(dist, D) and the path of the search tree
     // is augmented.  Both keep every residual reduced cost nonnegative, so
-    // the end result is a minimum-cost flow.  Both run by chunks first (in
-    // parallel), then over the whole graph.
+    // the end result is a minimum-cost flow.  With many excess nodes both
+    // run by chunks first (in parallel); the first pass then leaves the rest
+    // to the tail, the tail to its sequential part.
     bool solve(int64_t &paths, int64_t &phases)
     {
         bool first = true;
@@ -254,7 +255,13 @@ public:
             if (src_.empty()) return true;
             if (first) {
                 first = false;
-                if ((int64_t)src_.size() >= parallel_min_) zero_chunks(paths);
+                // by chunks when there are many excess nodes: the ones left
+                // then go straight to the tail (which finds their
+                // zero-distance paths too, and runs by chunks as well)
+                if ((int64_t)src_.size() >= parallel_min_) {
+                    zero_chunks(paths);
+                    continue;
+                }
                 const int32_t stamp = ++stamp_;
                 for (int64_t s : src_) {
                     while (cp_[s].ex > 0 && cp_[s].seen != stamp) {
