@@ -43,7 +43,8 @@ struct f2m_ctx {
     // geometry of the current instance (sorted order)
     DevBuf xy, minmax, keys, keys_alt, ids, orig, pos, box, xy2max, sort_temp;
     // GDP loop state
-    DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, pflag, z4, i4, seed, ctrl, trace;
+    DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, pflag, z4, i4, seed, ctrl, trace,
+        lst, lcnt;
     // trivial x
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
     // certificate / pair collection state
@@ -75,7 +76,7 @@ struct f2m_ctx {
     {
         DevBuf *all[] = {&xy, &minmax, &keys, &keys_alt, &ids, &orig, &pos, &box, &xy2max, &sort_temp,
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
-                         &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
+                         &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &lst, &lcnt, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
                          &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
@@ -658,6 +659,11 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     Ctrl *cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
     const int64_t trace_cap = want_trace ? max_iters + 1 : 0;
     int64_t *trace = want_trace ? grow<int64_t>(ctx, ctx->trace, kTraceW * trace_cap) : nullptr;
+    // the culled one-row-per-lane scan keeps candidate lists (kLW per row
+    // and wave) and evaluates only them while they stay exact
+    const bool lists = !csr && cull && sh.rows == 1;
+    int32_t *lst = lists ? grow<int32_t>(ctx, ctx->lst, 4 * kLW * n) : nullptr;
+    int32_t *lcnt = lists ? grow<int32_t>(ctx, ctx->lcnt, 4 * n) : nullptr;
 
     if (lam0_label_dev)
         ck(ctx, hipMemcpyAsync(l0, lam0_label_dev, n * sizeof(int64_t), hipMemcpyDeviceToDevice, st), "copy");
@@ -706,11 +712,13 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             int32_t *pf = (cull && sh.rows == 1) ? nullptr : pflag;
             sa.pflag = pf;
             sa.nrb = nrb;
+            sa.lst = lst;
+            sa.lcnt = lcnt;
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
             ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
             UpdateArgs ua{gh.g, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
-                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows};
+                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows, lists ? 1 : 0};
             ck(ctx, launch_update(ua, st), "update");
         }
         ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");

@@ -61,6 +61,13 @@ struct Ctrl {
     unsigned long long pairs_tested;   // ordered pairs the GDP scans evaluated (all iterations)
     long long k_next;      // iteration the next update evaluates (batched, graph-replayed loops)
     long long nblocks;     // blocks of this instance's update launch (batched loops)
+    // candidate lists of the culled one-row-per-lane scan (see ScanArgs::lst)
+    long long list_ok;     // 1: the next scan evaluates the lists only
+    long long list_d;      // sum of the max steps since the lists were built
+    long long list_D;      // the next build keeps Z <= theta + 2 list_D (0: no build)
+    long long list_over;   // a list overflowed in the building scan
+    long long list_ms0;    // max step of iteration 0
+    long long list_Dmax;   // margins above this overflowed (half the last one that did; 0: none yet)
 };
 
 // Static geometry of an instance in sorted order.
@@ -115,6 +122,14 @@ struct ScanArgs {
     // columns; slice_len is then not used); 0 = slice s scans columns
     // [s * slice_len, (s + 1) * slice_len)
     int64_t interleave;
+    // GDP mode, culled, one row per lane, optional: candidate lists, kLW
+    // positions per (row, wave of the block) in lst[(4 p + wave) kLW + i] and
+    // their count in lcnt[4 p + wave] (-1: overflowed).  A full scan with
+    // ctrl->list_D > 0 stores every column it finds with Z <= theta + 2 D;
+    // while ctrl->list_ok the scan evaluates only the lists (exact as long
+    // as the steps since the build sum to at most D / 2)
+    int32_t *lst;
+    int32_t *lcnt;
 };
 
 struct UpdateArgs {
@@ -143,7 +158,15 @@ struct UpdateArgs {
     const int32_t *pflag;
     int64_t nrb;
     int64_t scan_rows;          // rows per lane of the scan (tiles per scan row block)
+    int lists;                  // the scan keeps candidate lists: track their drift
 };
+
+// candidate list entries per row and wave (see ScanArgs::lst); the margin
+// of a build is kListMult times the last max step, allowed once that step
+// is at most 1/16 of iteration 0's and the margin at most half of the last
+// one whose lists overflowed
+constexpr int kLW = 16;
+constexpr int64_t kListMult = 6;
 
 // Candidate graph (k nearest neighbours, union-symmetrised) in CSR over
 // positions: rowptr[n+1], col (positions, increasing within a row), cost.

@@ -122,12 +122,13 @@ struct Row {
     float xv, yv;
     int64_t lamv, theta;
     int64_t v;
+    int64_t slk = 0;      // the filter passes Z <= theta + slk
 };
 
 // Recomputes the filter of a row from theta (see the header comment).
 __device__ __forceinline__ void set_filter(Row &r, float colmax)
 {
-    const float hv = (float)(0.5 * (double)(r.theta + r.lamv + 1));
+    const float hv = (float)(0.5 * (double)(r.theta + r.slk + r.lamv + 1));
     r.a = -2.0f * r.xv;
     r.b = -2.0f * r.yv;
     r.c = -2.0f * hv;
@@ -611,6 +612,12 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
     const int64_t n = a.g.n;
     const int64_t S0 = a.interleave > 0 ? a.interleave : 1, sl0 = a.interleave > 0 ? sl : 0;
     const int64_t S = QUAD ? 4 * S0 : S0, sid = QUAD ? 4 * sl0 + wave : sl0;
+    // candidate lists: evaluate them (use) or store them during the walk
+    // (build, margin 2 LD); see ScanArgs::lst
+    const bool lists = QUAD && MODE == kModeGdp && a.lst != nullptr;
+    const bool use = lists && a.lv.ctrl->list_ok != 0;
+    const int64_t LD = (lists && !use) ? a.lv.ctrl->list_D : 0;
+    const bool build = LD > 0;
     const float colmax = col_bound(a.g.xy2max, a.lv.ctrl->maxabs_lam);
     if (t == 0) bany = 0;
     if (lane == 0) cfill[wave] = 0;
@@ -636,6 +643,7 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
             else th = ok ? (mx > 0 ? mx : 0) + a.slack : a.theta;
         }
         rw.theta = th;
+        rw.slk = build ? 2 * LD : 0;
         set_filter(rw, colmax);
     } else {
         rw.xv = rw.yv = 0.0f;
@@ -643,6 +651,8 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         rw.a = rw.b = rw.c = 0.0f;
         rw.thr = -INFINITY;   // never passes
     }
+    int lc = 0;   // list entries found (build)
+    const int64_t lbase = (4 * p + wave) * kLW;
     __syncthreads();   // bany and cfill are set
 
     // the wave's rows: positions [w0, w1), their box (two sub-tile boxes
@@ -695,6 +705,10 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
             }
             return;
         }
+        if (build && z <= rw.theta + rw.slk) {
+            if (lc < kLW) a.lst[lbase + lc] = (int32_t)u;
+            ++lc;
+        }
         if (z > rw.theta) return;
         if (z < 0) { ++neg; rn += z; }
         else if (z == 0) ++zero;
@@ -728,7 +742,30 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         }
     };
 
-    if (w1 > w0) {
+    if (use) {
+        // the row's list from the last building scan holds every column
+        // that can matter now: evaluate those only
+        int cnt = 0;
+        if (p < n) {
+            cnt = a.lcnt[4 * p + wave];
+            for (int i = 0; i < cnt; ++i) {
+                const int64_t u = a.lst[lbase + i];
+                const float4 cu = a.lv.col[u];
+                const int64_t z = exact_z(rw.xv, rw.yv, rw.lamv, cu.x, cu.y, a.lv.lam[u]);
+                if (z > rw.theta) continue;
+                if (z < 0) { ++neg; rn += z; }
+                else if (z == 0) ++zero;
+                top.insert(z, a.g.orig[u]);
+                if (top.id[3] != kNoIdx) {
+                    const int64_t nt = top.z[3] > 0 ? top.z[3] : 0;
+                    if (nt < rw.theta) rw.theta = nt;
+                }
+            }
+        }
+        tested += (unsigned long long)wave_sum((long long)cnt);
+        scanned = true;
+    }
+    if (w1 > w0 && !use) {
         // The culling radius comes from the rows' starting thresholds: every
         // slice must see the same survivors in the same order, or the
         // round-robin deal would lose or repeat sub-tiles.
@@ -827,6 +864,10 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         base = __shfl(base, 0, 64);
         for (int i = lane; i < fill; i += 64)
             if ((int64_t)(base + i) < a.cap) a.out[base + i] = cbuf[wave][i];
+    }
+    if (build && p < n) {
+        a.lcnt[4 * p + wave] = lc <= kLW ? lc : -1;
+        if (lc > kLW) const_cast<Ctrl *>(a.lv.ctrl)->list_over = 1;   // the next update rebuilds
     }
     if (MODE == kModeGdp && QUAD) {
         // waves 1-3 hand their rows' lists and counts to wave 0
@@ -970,7 +1011,7 @@ static_assert(offsetof(Ctrl, acc_maxabs_next) == offsetof(Ctrl, acc_sumlam) + 7 
 // writes the iteration record, takes the stop decision and clears the
 // accumulators.  Called by every thread of the block.
 __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t k, Ctrl *ctrl, int64_t *trace,
-                                                   float *tile_hmax, int64_t blk, int64_t nblk)
+                                                   float *tile_hmax, int64_t blk, int64_t nblk, bool lists = false)
 {
     __shared__ unsigned long long red8[kBlock / 64][8];
     __shared__ float redf[kBlock / 64];
@@ -1046,6 +1087,26 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
         else if (k >= 2 && hh == ctrl->h2) stop = 3;                                // cycle
         else if (k >= ctrl->max_iters) stop = 4;                                    // cap
         else if (mx >= kLamLimit) { stop = 4; ctrl->overflow = 1; }
+        if (lists) {
+            // Z moves by at most twice the max step per iteration: lists
+            // built with margin 2D stay exact while the steps since the
+            // build sum to at most D / 2
+            if (k == 0) ctrl->list_ms0 = ms;
+            const bool used = ctrl->list_ok != 0;
+            const bool built = !used && ctrl->list_D > 0;
+            const long long d = used ? ctrl->list_d + ms : ms;
+            const bool ok = (used || (built && !ctrl->list_over)) && 2 * d <= ctrl->list_D;
+            ctrl->list_ok = ok ? 1 : 0;
+            ctrl->list_d = ok ? d : 0;
+            if (!ok) {
+                // a build whose lists overflowed caps the later margins
+                if (built && ctrl->list_over) ctrl->list_Dmax = ctrl->list_D / 2;
+                const long long D = kListMult * ms;
+                const bool go = ms * 16 <= ctrl->list_ms0 && (ctrl->list_Dmax == 0 || D <= ctrl->list_Dmax);
+                ctrl->list_D = go ? D : 0;
+                ctrl->list_over = 0;
+            }
+        }
         ctrl->k_last = k;
         ctrl->dual2_last = dual2;
         if (stop) {
@@ -1107,7 +1168,7 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
         step_row(a.g, p, top, cn, cz, rn, a.lam_in[p], copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
                  a.neg, a.zero, a.step, a.col, o);
     }
-    reduce_and_control(o, n, k, ctrl, a.trace, a.tile_hmax, blk, nblk);
+    reduce_and_control(o, n, k, ctrl, a.trace, a.tile_hmax, blk, nblk, a.lists != 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
