@@ -636,6 +636,8 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         int64_t th;
         if (MODE == kModeCert) {
             th = 0;
+        } else if (use) {
+            th = kThetaNone;   // the lists are exact: no bound needed
         } else {
             int64_t mx;
             const bool ok = a.seed && seeded_bound(a, p, cv.x, cv.y, rw.lamv, &mx);
@@ -748,17 +750,27 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         int cnt = 0;
         if (p < n) {
             cnt = a.lcnt[4 * p + wave];
-            for (int i = 0; i < cnt; ++i) {
-                const int64_t u = a.lst[lbase + i];
-                const float4 cu = a.lv.col[u];
-                const int64_t z = exact_z(rw.xv, rw.yv, rw.lamv, cu.x, cu.y, a.lv.lam[u]);
-                if (z > rw.theta) continue;
-                if (z < 0) { ++neg; rn += z; }
-                else if (z == 0) ++zero;
-                top.insert(z, a.g.orig[u]);
-                if (top.id[3] != kNoIdx) {
-                    const int64_t nt = top.z[3] > 0 ? top.z[3] : 0;
-                    if (nt < rw.theta) rw.theta = nt;
+            // four entries' gathers in flight at a time
+            for (int i0 = 0; i0 < cnt; i0 += 4) {
+                float4 cu[4];
+                long long lu[4];
+                int32_t ou[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (i0 + q < cnt) {
+                        const int64_t u = a.lst[lbase + i0 + q];
+                        cu[q] = a.lv.col[u];
+                        lu[q] = a.lv.lam[u];
+                        ou[q] = a.g.orig[u];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (i0 + q >= cnt) break;
+                    const int64_t z = exact_z(rw.xv, rw.yv, rw.lamv, cu[q].x, cu[q].y, lu[q]);
+                    if (z < 0) { ++neg; rn += z; }
+                    else if (z == 0) ++zero;
+                    top.insert(z, ou[q]);
                 }
             }
         }
