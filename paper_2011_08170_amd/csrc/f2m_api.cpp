@@ -44,7 +44,7 @@ struct f2m_ctx {
     DevBuf xy, minmax, keys, keys_alt, ids, orig, pos, box, xy2max, sort_temp;
     // GDP loop state
     DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, pflag, z4, i4, seed, ctrl, trace,
-        lst, lcnt;
+        lst, lcnt, tpart;
     // trivial x
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
     // certificate / pair collection state
@@ -76,7 +76,7 @@ struct f2m_ctx {
     {
         DevBuf *all[] = {&xy, &minmax, &keys, &keys_alt, &ids, &orig, &pos, &box, &xy2max, &sort_temp,
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
-                         &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &lst, &lcnt, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
+                         &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &lst, &lcnt, &tpart, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
                          &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
@@ -664,6 +664,9 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     const bool lists = !csr && cull && sh.rows == 1;
     int32_t *lst = lists ? grow<int32_t>(ctx, ctx->lst, 4 * kLW * n) : nullptr;
     int32_t *lcnt = lists ? grow<int32_t>(ctx, ctx->lcnt, 4 * n) : nullptr;
+    // its workgroups store their pairs tested for k_update to sum (one
+    // atomic per update block instead of one per scan wave)
+    unsigned long long *tpart = lists ? grow<unsigned long long>(ctx, ctx->tpart, sh.slices * ((n + 63) / 64)) : nullptr;
 
     if (lam0_label_dev)
         ck(ctx, hipMemcpyAsync(l0, lam0_label_dev, n * sizeof(int64_t), hipMemcpyDeviceToDevice, st), "copy");
@@ -714,11 +717,13 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             sa.nrb = nrb;
             sa.lst = lst;
             sa.lcnt = lcnt;
+            sa.tpart = tpart;
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
             ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
             if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
             UpdateArgs ua{gh.g, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
-                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows, lists ? 1 : 0};
+                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows, lists ? 1 : 0,
+                          tpart};
             ck(ctx, launch_update(ua, st), "update");
         }
         ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");

@@ -130,6 +130,10 @@ struct ScanArgs {
     // as the steps since the build sum to at most D / 2)
     int32_t *lst;
     int32_t *lcnt;
+    // GDP mode, culled, one row per lane, optional: each workgroup stores
+    // its ordered pairs tested in tpart[slice * groups + group] (groups of
+    // 64 rows) instead of adding them to *tested; k_update sums them
+    unsigned long long *tpart;
 };
 
 struct UpdateArgs {
@@ -159,6 +163,9 @@ struct UpdateArgs {
     int64_t nrb;
     int64_t scan_rows;          // rows per lane of the scan (tiles per scan row block)
     int lists;                  // the scan keeps candidate lists: track their drift
+    // optional: the scan's pairs tested per (slice, group of 64 rows), added
+    // to ctrl->pairs_tested (one atomic per update block)
+    const unsigned long long *tpart;
 };
 
 // candidate list entries per row and wave (see ScanArgs::lst); the margin

@@ -867,7 +867,10 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         }
     }
 
-    if (a.tested && lane == 0 && tested) atomicAdd(a.tested, tested);
+    // the count of pairs tested: one store per workgroup when k_update sums
+    // them, else one atomic per wave
+    const bool tstore = QUAD && MODE == kModeGdp && a.tpart != nullptr;
+    if (!tstore && a.tested && lane == 0 && tested) atomicAdd(a.tested, tested);
     if (MODE == kModeCollect) {
         wave_sync();   // every lane's buffer writes are done
         const int fill = min(cfill[wave], kCollectBuf);
@@ -897,7 +900,13 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
             mzero[wave - 1][lane] = zero;
             mrn[wave - 1][lane] = rn;
         }
+        if (lane == 0) redu[wave] = tested;
         __syncthreads();
+        if (tstore && t == 0) {
+            unsigned long long tt = 0;
+            for (int w = 0; w < kBlock / 64; ++w) tt += redu[w];
+            a.tpart[sl * (int64_t)gridDim.x + rblk] = tt;
+        }
         if (wave == 0 && p < n) {
             for (int w = 0; w < 3; ++w) {
 #pragma unroll
@@ -1141,6 +1150,15 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
                                             const int64_t nblk)
 {
     Ctrl *ctrl = a.ctrl;
+    if (a.tpart && threadIdx.x == 0) {
+        // the scan's pairs tested in this block's rows (groups of 64)
+        const int64_t groups = (a.g.n + 63) / 64;
+        unsigned long long tt = 0;
+        for (int64_t s = 0; s < a.nslices; ++s)
+            for (int64_t g = blk * (kBlock / 64); g < min(groups, (blk + 1) * (kBlock / 64)); ++g)
+                tt += a.tpart[s * groups + g];
+        if (tt) atomicAdd(&ctrl->pairs_tested, tt);
+    }
     const int64_t n = a.g.n;
     const int64_t p = blk * kBlock + threadIdx.x;
     // Lam_{k-1} sits in lam_out until it is overwritten
