@@ -872,11 +872,18 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
     const bool tstore = QUAD && MODE == kModeGdp && a.tpart != nullptr;
     if (!tstore && a.tested && lane == 0 && tested) atomicAdd(a.tested, tested);
     if (MODE == kModeCollect) {
-        wave_sync();   // every lane's buffer writes are done
+        // the workgroup's buffers go out behind one atomic
+        __shared__ unsigned long long cbase;
+        __syncthreads();   // every wave's buffer is complete
+        if (t == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < kBlock / 64; ++w) tot += (unsigned long long)min(cfill[w], kCollectBuf);
+            cbase = tot ? atomicAdd(a.count, tot) : 0ULL;
+        }
+        __syncthreads();
+        unsigned long long base = cbase;
+        for (int w = 0; w < wave; ++w) base += (unsigned long long)min(cfill[w], kCollectBuf);
         const int fill = min(cfill[wave], kCollectBuf);
-        unsigned long long base = 0;
-        if (lane == 0 && fill > 0) base = atomicAdd(a.count, (unsigned long long)fill);
-        base = __shfl(base, 0, 64);
         for (int i = lane; i < fill; i += 64)
             if ((int64_t)(base + i) < a.cap) a.out[base + i] = cbuf[wave][i];
     }
@@ -1495,26 +1502,44 @@ __global__ __launch_bounds__(kBlock) void k_graph_collect(Geo g, Csr csr, const 
                                                           unsigned long long *count, int2 *out, int64_t cap)
 {
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= g.n) return;
-    const int64_t lv = lam[p];
-    const int32_t e0 = csr.rowptr[p], e1 = csr.rowptr[p + 1];
-    int64_t th = -1;
-    if (slack >= 0) {
-        int64_t b[kTop] = {INT64_MAX, INT64_MAX, INT64_MAX, INT64_MAX};
-        for (int32_t e = e0; e < e1; ++e) {
-            int64_t z = 2 * (int64_t)csr.cost[e] - lv - lam[csr.col[e]];
+    const int lane = threadIdx.x & 63;
+    const bool valid = p < g.n;
+    int64_t lv = 0, th = -1;
+    int32_t e0 = 0, e1 = 0;
+    if (valid) {
+        lv = lam[p];
+        e0 = csr.rowptr[p];
+        e1 = csr.rowptr[p + 1];
+        if (slack >= 0) {
+            int64_t b[kTop] = {INT64_MAX, INT64_MAX, INT64_MAX, INT64_MAX};
+            for (int32_t e = e0; e < e1; ++e) {
+                int64_t z = 2 * (int64_t)csr.cost[e] - lv - lam[csr.col[e]];
 #pragma unroll
-            for (int j = 0; j < kTop; ++j) if (z < b[j]) { const int64_t tt = b[j]; b[j] = z; z = tt; }
+                for (int j = 0; j < kTop; ++j) if (z < b[j]) { const int64_t tt = b[j]; b[j] = z; z = tt; }
+            }
+            th = b[3] == INT64_MAX ? INT64_MAX / 4 : (b[3] > 0 ? b[3] : 0) + slack;
         }
-        th = b[3] == INT64_MAX ? INT64_MAX / 4 : (b[3] > 0 ? b[3] : 0) + slack;
     }
+    // the row's pairs counted, then written behind one atomic per wave
+    int cnt = 0;
+    for (int32_t e = e0; e < e1; ++e)
+        if (2 * (int64_t)csr.cost[e] - lv - lam[csr.col[e]] <= th) ++cnt;
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    const int total = __shfl(incl, 63, 64);
+    unsigned long long base = 0;
+    if (lane == 0 && total > 0) base = atomicAdd(count, (unsigned long long)total);
+    base = __shfl(base, 0, 64) + (unsigned long long)(incl - cnt);
     const int32_t pp = (int32_t)p;
     for (int32_t e = e0; e < e1; ++e) {
         const int32_t u = csr.col[e];
-        const int64_t z = 2 * (int64_t)csr.cost[e] - lv - lam[u];
-        if (z > th) continue;
-        const unsigned long long slot = atomicAdd(count, 1ULL);
-        if ((int64_t)slot < cap) out[slot] = make_int2(min(pp, u), max(pp, u));
+        if (2 * (int64_t)csr.cost[e] - lv - lam[u] > th) continue;
+        if ((int64_t)base < cap) out[base] = make_int2(min(pp, u), max(pp, u));
+        ++base;
     }
 }
 
