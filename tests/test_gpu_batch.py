@@ -78,3 +78,20 @@ def test_batch_equals_independent_solves_large(ctx):
         for k in ("lambda2_gdp", "lambda2", "edge_u", "edge_v", "edge_x2"):
             assert np.array_equal(r[k], s[k]), k
         assert r["primal2"] == s["primal2"] and r["certified"] and s["certified"]
+
+
+def test_benchmark_size_single_equals_batched(ctx):
+    # n = 100000 uniform in [0, 10^6)^2, seed 1, as bench.py times it: the
+    # single solve (four waves per 64 rows, candidate lists) and a batch of
+    # that one instance (one wave per 64 rows, no lists) run different scan
+    # code; the trajectories, Lam and the objective must agree bit for bit
+    xy = I.uniform(100000, 1000000, 1)
+    off = np.array([0, len(xy)], np.int64)
+    st, res = ctx.solve_batch(xy, off, trace=True)
+    assert st == "ok"
+    s = ctx.solve(xy, trace=True)
+    r = res[0]
+    for k in ("trace", "lambda2_gdp"):
+        assert np.array_equal(r[k], s[k]), k
+    assert r["iterations"] == s["iterations"] and r["stop"] == s["stop"]
+    assert r["primal2"] == s["primal2"] and r["certified"] and s["certified"]
