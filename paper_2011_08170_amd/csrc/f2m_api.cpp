@@ -65,7 +65,7 @@ struct f2m_ctx {
     int64_t *scratch_host = nullptr;   // pinned, 16 entries
     // the finish's host side: pinned staging of the GPU's pair data, and its
     // workspace and result, kept from one solve to the next
-    HostBuf h_keys, h_costs, h_neg, h_start, h_inc, h_xyp, h_lamp, h_up;
+    HostBuf h_keys, h_costs, h_neg, h_start, h_inc, h_xyp, h_lamp, h_up, h_down;
     f2m::FinishWork *fwork = nullptr;
     f2m::FinishResult fres;
     // contexts (own stream and workspaces) of the batch's finishing threads
@@ -148,6 +148,11 @@ struct UpPart {
     size_t bytes;
 };
 void upload(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st);
+// Device arrays to host memory the same way back (parts[i] = {device source,
+// host destination, bytes}): kernels write them into the pinned staging
+// h_down through its device mapping; after a stream synchronisation they
+// are copied out.
+void download(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st);
 
 double now_s()
 {
@@ -348,6 +353,25 @@ void upload(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st)
             std::memcpy(h + at, q.src, q.bytes);
             ck(ctx, launch_copy_bytes(hd + at, q.dst, (int64_t)q.bytes, st), "upload");
         }
+        at += (q.bytes + 255) / 256 * 256;
+    }
+}
+
+void download(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st)
+{
+    size_t total = 0;
+    for (const UpPart &q : parts) total += (q.bytes + 255) / 256 * 256;
+    char *h = grow_host<char>(ctx, ctx->h_down, total);
+    char *hd = static_cast<char *>(ctx->h_down.dp);
+    size_t at = 0;
+    for (const UpPart &q : parts) {
+        if (q.bytes) ck(ctx, launch_copy_bytes(q.src, hd + at, (int64_t)q.bytes, st), "download");
+        at += (q.bytes + 255) / 256 * 256;
+    }
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    at = 0;
+    for (const UpPart &q : parts) {
+        if (q.bytes) std::memcpy(q.dst, h + at, q.bytes);
         at += (q.bytes + 255) / 256 * 256;
     }
 }
@@ -891,14 +915,12 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
     int64_t *lstar = grow<int64_t>(ctx, ctx->lam_label, n);
     ck(ctx, launch_unpermute(is.lam_star, gh.g.orig, n, lstar, st), "unpermute");
     res.lambda2_gdp = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
-    ck(ctx, hipMemcpyAsync(res.lambda2_gdp, lstar, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
     if (is.trace) {
         res.trace_len = std::min<int64_t>(res.iterations, c.trace_cap);
         res.trace = reinterpret_cast<int64_t *>(host_alloc(ctx, res.trace_len * kTraceW * sizeof(int64_t)));
-        ck(ctx, hipMemcpyAsync(res.trace, is.trace, res.trace_len * kTraceW * sizeof(int64_t),
-                               hipMemcpyDeviceToHost, st), "copy");
     }
-    ck(ctx, hipStreamSynchronize(st), "sync");
+    download(ctx, {{lstar, res.lambda2_gdp, n * sizeof(int64_t)},
+                   {is.trace, res.trace, is.trace ? res.trace_len * kTraceW * sizeof(int64_t) : 0}}, st);
     res.dual2_gdp = (c.kstar == c.k_last) ? c.dual2_last : c.best_dual2;
 
     int32_t *eu = nullptr, *ev = nullptr;
@@ -930,8 +952,8 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
         ck(ctx, launch_gather_xy(gh.xy, gh.g.orig, n, xyp, st), "gather_xy");
         int32_t *xyp_host = grow_host<int32_t>(ctx, ctx->h_xyp, 2 * n);
         int64_t *lamp_host = grow_host<int64_t>(ctx, ctx->h_lamp, n);
-        ck(ctx, hipMemcpyAsync(xyp_host, xyp, 2 * n * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipMemcpyAsync(lamp_host, is.lam_star, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+        ck(ctx, launch_copy_bytes(xyp, ctx->h_xyp.dp, 2 * n * sizeof(int32_t), st), "copy");
+        ck(ctx, launch_copy_bytes(is.lam_star, ctx->h_lamp.dp, n * sizeof(int64_t), st), "copy");
         ck(ctx, hipStreamSynchronize(st), "sync");
         if (!ctx->fwork) ctx->fwork = finish_work_create(ctx->is_worker ? 1 : finish_threads());
         FinishResult &fr = ctx->fres;
@@ -984,13 +1006,8 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
     res.edge_v = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(m, 1) * sizeof(int32_t)));
     res.edge_x2 = reinterpret_cast<uint8_t *>(host_alloc(ctx, std::max<int64_t>(m, 1)));
     res.lambda2 = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
-    if (m) {
-        ck(ctx, hipMemcpyAsync(res.edge_u, eu, m * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipMemcpyAsync(res.edge_v, ev, m * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipMemcpyAsync(res.edge_x2, ex, m * sizeof(uint8_t), hipMemcpyDeviceToHost, st), "copy");
-    }
-    ck(ctx, hipMemcpyAsync(res.lambda2, lam_final_dev, n * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
-    ck(ctx, hipStreamSynchronize(st), "sync");
+    download(ctx, {{eu, res.edge_u, m * sizeof(int32_t)}, {ev, res.edge_v, m * sizeof(int32_t)},
+                   {ex, res.edge_x2, m * sizeof(uint8_t)}, {lam_final_dev, res.lambda2, n * sizeof(int64_t)}}, st);
     res.primal2 = cert[0];
     res.dual2 = have_x ? cert[1] : res.dual2_gdp;
     res.certified = (int32_t)cert[3];
@@ -1057,7 +1074,7 @@ void f2m_destroy(f2m_ctx *ctx)
     if (ctx->ctrl_host) (void)hipHostFree(ctx->ctrl_host);
     if (ctx->scratch_host) (void)hipHostFree(ctx->scratch_host);
     for (HostBuf *h : {&ctx->h_keys, &ctx->h_costs, &ctx->h_neg, &ctx->h_start, &ctx->h_inc, &ctx->h_xyp, &ctx->h_lamp,
-                       &ctx->h_up})
+                       &ctx->h_up, &ctx->h_down})
         if (h->p) (void)hipHostFree(h->p);
     if (ctx->fwork) finish_work_destroy(ctx->fwork);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
