@@ -475,7 +475,7 @@ public:
     }
     bool negative(const int64_t *lam, PairList &out, std::string &err) override
     {
-        return run(lam, nullptr, -1, 0, out, err);
+        return run(lam, nullptr, price_slack - 1, 0, out, err);   // Z <= theta
     }
 
 private:
@@ -602,6 +602,7 @@ public:
     {
         return run(lam, slack < 0 ? 0 : slack, out, err);
     }
+    // Z < 0 only (price_slack is not used on the candidate graph)
     bool negative(const int64_t *lam, PairList &out, std::string &err) override { return run(lam, -1, out, err); }
 
 private:

@@ -225,6 +225,26 @@ public:
         build_adjacency();
     }
 
+    // Whether some pair of pl that is not a candidate yet has Z < 0 under
+    // lam (costs: the pairs' costs, or null: computed here)
+    bool fresh_negative(const PairList &pl, const int32_t *costs, const std::vector<int64_t> &lam) const
+    {
+        for (size_t q = 0; q < pl.size(); ++q) {
+            const int32_t a = std::min(pl[q].first, pl[q].second), b = std::max(pl[q].first, pl[q].second);
+            if (a == b || a < 0 || b >= n_) continue;
+            if (std::binary_search(keys_.begin(), keys_.end(), pair_key(a, b))) continue;
+            int64_t c;
+            if (costs) {
+                c = costs[q];
+            } else {
+                const int64_t dx = (int64_t)xy_[2 * a] - xy_[2 * b], dy = (int64_t)xy_[2 * a + 1] - xy_[2 * b + 1];
+                c = nint_sqrt_host(dx * dx + dy * dy);
+            }
+            if (2 * c - lam[a] - lam[b] < 0) return true;
+        }
+        return false;
+    }
+
     // Min-cost flow on the current candidates; false when some excess
     // cannot reach a deficit (the candidate graph is too small).
     //
@@ -796,6 +816,9 @@ static double secs()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// pricing also returns the pairs with 0 <= Z < kPriceSlack
+constexpr int64_t kPriceSlack = 16;
+
 struct FinishWork {
     DoubleCover g;
     PairList pl;
@@ -865,19 +888,24 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
         g.lam(lam);
         pl.clear();
         t = secs();
-        if (!src.negative(lam.data(), pl, err)) { r.msg = err; return; }
+        // pricing: the pairs with Z < kPriceSlack; optimal when none of
+        // them with Z < 0 is new, else all the new ones join (the near-tight
+        // ones often save the next round)
+        src.price_slack = kPriceSlack;
+        const bool priced = src.negative(lam.data(), pl, err);
+        src.price_slack = 0;
+        if (!priced) { r.msg = err; return; }
         r.t_collect += secs() - t;
-        const int64_t before = g.edges();
-        t = secs();
-        g.add(pl, src.costs);
-        r.t_build += secs() - t;
-        if (g.edges() == before) {
+        if (!g.fresh_negative(pl, src.costs, lam)) {
             r.ok = true;
             r.lam.assign(lam.begin(), lam.end());
             g.x(r.eu, r.ev, r.ex2);
             r.candidates = g.edges();
             return;
         }
+        t = secs();
+        g.add(pl, src.costs);
+        r.t_build += secs() - t;
     }
     r.msg = "pricing did not converge in 64 rounds";
 }

@@ -52,7 +52,9 @@ struct PairSource {
     const int32_t *inc = nullptr;
     // pairs {u, v} with Z_uv(lam) <= max(0, 4th smallest Z at u or v) + slack
     virtual bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &err) = 0;
-    // pairs {u, v} with Z_uv(lam) < 0
+    // pairs {u, v} with Z_uv(lam) < price_slack (the finish sets it: a few
+    // near-tight pairs priced together with the negative ones)
+    int64_t price_slack = 0;
     virtual bool negative(const int64_t *lam, PairList &out, std::string &err) = 0;
 };
 

@@ -81,7 +81,7 @@ struct BrutePairs : PairSource {
         out.clear();
         for (int64_t u = 0; u < n; ++u)
             for (int64_t v = u + 1; v < n; ++v)
-                if (z(lam, u, v) < 0) out.emplace_back((int32_t)u, (int32_t)v);
+                if (z(lam, u, v) < price_slack) out.emplace_back((int32_t)u, (int32_t)v);
         extras(lam, out);
         return true;
     }
