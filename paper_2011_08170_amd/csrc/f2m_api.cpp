@@ -974,7 +974,6 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
         res.finish_seconds[2] = fr.t_flow;
         if (!fr.ok) fail(ctx, F2M_ERR_DEVICE, "exact finish failed: " + fr.msg);
         m = (int64_t)fr.eu.size();
-        int64_t *ld = grow<int64_t>(ctx, ctx->c_lam_label, n);
         eu = grow<int32_t>(ctx, ctx->c_eu, std::max<int64_t>(m, 1));
         ev = grow<int32_t>(ctx, ctx->c_ev, std::max<int64_t>(m, 1));
         ex = grow<uint8_t>(ctx, ctx->c_ex, std::max<int64_t>(m, 1));
@@ -985,7 +984,6 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
         upload(ctx, {{fr.lam.data(), lp, n * sizeof(int64_t)}, {fr.eu.data(), eu, m * sizeof(int32_t)},
                      {fr.ev.data(), ev, m * sizeof(int32_t)}, {fr.ex2.data(), ex, m * sizeof(uint8_t)}}, st);
         ck(ctx, launch_unpermute(lp, gh.g.orig, n, lf, st), "unpermute");
-        (void)ld;
         if (m) ck(ctx, launch_edges_to_labels(gh.g.orig, m, eu, ev, st), "edges_to_labels");
         lam_final_dev = lf;
         have_x = true;
