@@ -520,11 +520,12 @@ private:
                 ++wk.paths;
             }
         };
-        // a third round with 4 W wide chunks takes most of the long searches
-        for (int round = 0; round < 3; ++round) {
-            if (src_.empty() || (round == 1 && W < 2) || (round == 2 && 4 * W >= n_)) break;
+        // rounds with 4 W and 16 W wide chunks take most of the long searches
+        for (int round = 0; round < 4; ++round) {
+            if (src_.empty() || (round == 1 && W < 2) || (round == 2 && 4 * W >= n_) || (round == 3 && 16 * W >= n_))
+                break;
             if (round < 2) chunk_round(W, round == 0 ? 0 : W / 2, serve);
-            else chunk_round(4 * W, 0, serve);
+            else chunk_round(round == 2 ? 4 * W : 16 * W, 0, serve);
             src_.clear();
             for (Worker &wk : workers_) {
                 paths += wk.paths;
