@@ -10,6 +10,9 @@
 #include <chrono>
 #include <iterator>
 #include <atomic>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <memory>
 #include <thread>
 
@@ -32,6 +35,72 @@ int64_t floor_half(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
 
 // candidate edge key: (a, b), a < b, in lexicographic order
 uint64_t pair_key(int64_t a, int64_t b) { return ((uint64_t)a << 32) | (uint64_t)b; }
+
+// A fixed set of threads that run one function at a time, fn(worker) for
+// workers 1 .. T-1 while the caller runs fn(0); they stay for the owner's
+// lifetime, so a solve starts no thread.
+class Pool {
+public:
+    ~Pool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            quit_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+
+    void run(int T, const std::function<void(int)> &fn)
+    {
+        if (T <= 1) {
+            fn(0);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            // a new thread starts from the generation before this run's
+            while ((int)th_.size() < T - 1) {
+                const int id = (int)th_.size() + 1;
+                th_.emplace_back([this, id, g = gen_] { loop(id, g); });
+            }
+            fn_ = &fn;
+            want_ = T - 1;
+            done_ = 0;
+            ++gen_;
+        }
+        cv_.notify_all();
+        fn(0);
+        std::unique_lock<std::mutex> lk(m_);
+        cv_done_.wait(lk, [&] { return done_ == want_; });
+        fn_ = nullptr;
+    }
+
+private:
+    void loop(int id, uint64_t seen)
+    {
+        std::unique_lock<std::mutex> lk(m_);
+        for (;;) {
+            cv_.wait(lk, [&] { return quit_ || gen_ != seen; });
+            if (quit_) return;
+            seen = gen_;
+            if (id > want_) continue;   // not needed this time
+            const std::function<void(int)> *f = fn_;
+            lk.unlock();
+            (*f)(id);
+            lk.lock();
+            if (++done_ == want_) cv_done_.notify_one();
+        }
+    }
+
+    std::mutex m_;
+    std::condition_variable cv_, cv_done_;
+    std::vector<std::thread> th_;
+    const std::function<void(int)> *fn_ = nullptr;
+    int want_ = 0, done_ = 0;
+    uint64_t gen_ = 0;
+    bool quit_ = false;
+};
 
 // Node ids: left copy v' -> v, right copy u'' -> n + u.
 // Arc 2i is a_i' -> b_i'', arc 2i+1 is b_i' -> a_i'' for candidate edge i.
@@ -156,10 +225,7 @@ public:
             f(0, count);
             return;
         }
-        std::vector<std::thread> th;
-        for (int w = 1; w < T; ++w) th.emplace_back([&, w] { f(count * w / T, count * (w + 1) / T); });
-        f(0, count / T);
-        for (auto &x : th) x.join();
+        pool_.run(T, [&](int w) { f(count * w / T, count * (w + 1) / T); });
     }
 
     // Adds new candidate edges (pairs with costs, or null: computed here);
@@ -591,10 +657,7 @@ private:
             for (int64_t x : wk.touched) cp_[x].dist = kInf;
             wk.touched.clear();
         };
-        std::vector<std::thread> th;
-        for (int w = 1; w < T; ++w) th.emplace_back(run, w);
-        run(0);
-        for (auto &x : th) x.join();
+        pool_.run(T, run);
     }
 
     // shortest() from one node, restricted to the nodes [lo, hi) (both
@@ -807,6 +870,7 @@ private:
     std::vector<Frame> frames_;
     int threads_ = 1;
     int64_t parallel_min_ = 256;     // excess nodes for the chunked tail
+    Pool pool_;
     std::vector<Worker> workers_;
 };
 
