@@ -44,6 +44,7 @@
  * here by plain successive shortest paths with node potentials on the dense
  * complete graph.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -69,17 +70,18 @@
 /* integer square root and the exact EUC_2D length                     */
 /* ------------------------------------------------------------------ */
 
-/* floor(sqrt(x)) for 0 <= x < 2^62, by bisection on r*r <= x. */
+/* floor(sqrt(x)) for 0 <= x < 2^62: the library square root gives an
+ * estimate r; the two loops then move r until r*r <= x < (r+1)*(r+1),
+ * which defines floor(sqrt(x)) whatever the estimate's rounding was
+ * (r stays below 2^31, so (r+1)^2 <= 2^62 cannot overflow). */
 int64_t or_isqrt(int64_t x)
 {
     if (x <= 0) return 0;
-    int64_t lo = 0, hi = 1;
-    while (hi * hi <= x) hi *= 2;          /* hi*hi > x, hi <= 2^31 */
-    while (hi - lo > 1) {                  /* invariant lo*lo <= x < hi*hi */
-        int64_t mid = lo + (hi - lo) / 2;
-        if (mid * mid <= x) lo = mid; else hi = mid;
-    }
-    return lo;
+    int64_t r = (int64_t)sqrt((double)x);
+    if (r > 2147483647) r = 2147483647;
+    while (r > 0 && r * r > x) r--;
+    while ((r + 1) * (r + 1) <= x) r++;
+    return r;
 }
 
 /* nint(sqrt(D)): the integer k with k - 1/2 <= sqrt(D) < k + 1/2, i.e.
