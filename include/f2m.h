@@ -87,6 +87,10 @@ enum { F2M_FINISH_NONE = 0, F2M_FINISH_EXACT = 1 };
  * bounding box is provably too far for any pair to matter (exact: same
  * results); F2M_SCAN_FULL tests every ordered pair. */
 enum { F2M_SCAN_CULLED = 0, F2M_SCAN_FULL = 1 };
+/* Scan kinds of the complete-graph GDP (f2m_result.scan_kind).  A list scan
+ * evaluates each row's candidate list from the last building scan only; it
+ * runs only while that is provably exact, so every kind gives the same bits. */
+enum { F2M_SCAN_KIND_FULL = 0, F2M_SCAN_KIND_BUILD = 1, F2M_SCAN_KIND_LIST = 2 };
 enum { F2M_STOP_TRIVIAL = 1, F2M_STOP_FIXED = 2, F2M_STOP_CYCLE = 3, F2M_STOP_CAP = 4,
        F2M_STOP_HANDOFF = 5 };
 
@@ -111,13 +115,31 @@ typedef struct f2m_opts {
                                      when the trivial x does not certify */
     int32_t coords_on_device;     /* coords_xy argument is a device pointer */
     int32_t record_trace;         /* fill f2m_result.trace */
-    int32_t chunk;                /* iterations queued between host checks (0: auto) */
+    int32_t chunk;                /* f2m_solve: iterations queued ahead of the last one the
+                                     device has finished; f2m_solve_batch: iterations per
+                                     replayed graph (0: auto) */
     int32_t time_kernels;         /* time every scan launch with HIP events */
     int32_t scan_mode;            /* F2M_SCAN_CULLED (default) or F2M_SCAN_FULL */
     int32_t scan_rows;            /* launch shape: rows per lane, 1, 2 or 4 (0: built-in choice) */
     int32_t scan_slices;          /* launch shape: column slices >= 1 (0: built-in choice);
                                      the shape never changes a result, only the time */
     void *hip_stream;             /* hipStream_t to run on; NULL: the context's stream */
+    /* Resume (checkpoint = f2m_result.lambda2_last after a run that stopped
+     * at iteration K): warm = F2M_WARM_USER with lambda2_init = Lam_K and
+     * k0 = K continues the GDP at iteration K.  With resume_hash_valid the
+     * hashes of Lam_{K-1} and Lam_{K-2} (trace column 6 of rows K-1, K-2)
+     * arm the cycle test at once, so the records and the stop equal those
+     * of the uninterrupted run; Lam* of a cycle or cap stop is then the
+     * largest-dual iterate since K.  k0 = 0: a fresh run. */
+    int64_t k0;                   /* 0 <= k0 <= max_iters; k0 > 0 needs warm == F2M_WARM_USER */
+    uint64_t resume_hash[2];      /* hash of Lam_{k0-1}, of Lam_{k0-2} */
+    int32_t resume_hash_valid;    /* 1: resume_hash holds them (needs k0 >= 2) */
+    int32_t pad_opts;
+    uint64_t max_device_bytes;    /* cap on the context's device workspace (0: none);
+                                     a call that would pass it fails with F2M_ERR_NOMEM */
+    const char *tuner_cache;      /* path of a tuner cache (paper_2011_08170_amd.tune), or NULL;
+                                     with scan_rows == scan_slices == 0 the solve takes the
+                                     cached launch shape for its device, scan mode and size */
 } f2m_opts;
 
 typedef struct f2m_result {
@@ -139,7 +161,8 @@ typedef struct f2m_result {
     int64_t finish_rounds;  /* pricing rounds of the exact finish */
     int64_t trace_len;
     int64_t *trace;         /* host, trace_len * F2M_TRACE_W, or NULL */
-    double seconds[6];      /* setup, (unused), gdp, finish, certify, total */
+    double seconds[6];      /* setup, warm start (network or candidate-graph GDP),
+                               gdp, finish, certify, total */
     double scan_ms;         /* summed duration of the scan launches (time_kernels) */
     int64_t scan_launches;  /* scan launches timed */
     int32_t scan_rows;      /* scan launch shape: rows per lane */
@@ -154,15 +177,28 @@ typedef struct f2m_result {
     int32_t pad1;
     int64_t graph_nnz;          /* directed entries of the candidate graph (F2M_GRAPH_KNN, F2M_WARM_GRAPH) */
     int64_t warm_iterations;    /* GDP iterations of the F2M_WARM_GRAPH start (0 otherwise) */
+    int32_t *scan_kind;         /* host, trace_len, or NULL: the scan of iteration k tested every
+                                   surviving pair (F2M_SCAN_KIND_FULL), also stored candidate lists
+                                   (_BUILD), or evaluated the lists only (_LIST) */
+    int64_t scan_list_uses;     /* GDP scans that evaluated the candidate lists only */
+    int64_t scan_list_builds;   /* GDP scans that built candidate lists */
+    int64_t *lambda2_last;      /* host, n: Lam of the last evaluated iteration (the checkpoint
+                                   to resume from, see f2m_opts.k0) */
+    double scan_ms_kind[3];     /* scan_ms split by F2M_SCAN_KIND_* (time_kernels) */
+    int64_t scan_launches_kind[3];
+    int64_t scan_pairs_kind[3]; /* scan_pairs split by F2M_SCAN_KIND_* */
 } f2m_result;
 
 /* Fills opts with the defaults: rule 1, complete graph, cold start,
  * knn_k 10, max_iters 100000, handoff_div 50, exact finish, host coords,
- * no trace, auto chunk, culled scan. */
+ * no trace, auto chunk, culled scan, k0 0, no memory cap, no tuner cache. */
 void f2m_opts_default(f2m_opts *opts);
 
-/* Creates a context on HIP device `device` with its own stream. */
-f2m_status f2m_create(f2m_ctx **ctx, int device);
+/* Creates a context on HIP device `device` with its own stream.  defaults
+ * (may be NULL: f2m_opts_default) is copied and used by every call of this
+ * context that is given opts == NULL.  F2M_ERR_ARG for a bad struct_size,
+ * F2M_ERR_DEVICE when the device does not exist or HIP fails. */
+f2m_status f2m_create(f2m_ctx **ctx, int device, const f2m_opts *defaults);
 void f2m_destroy(f2m_ctx *ctx);
 
 /* Full solve of F2M on the complete graph of n cities (Sec. 4, 5.1):

@@ -44,7 +44,7 @@ struct f2m_ctx {
     DevBuf xy, minmax, keys, keys_alt, ids, orig, pos, box, xy2max, sort_temp;
     // GDP loop state
     DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, pflag, z4, i4, seed, ctrl, trace,
-        lst, lcnt, tpart;
+        lst, lcnt, tpart, slots, kinds;
     // trivial x
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
     // certificate / pair collection state
@@ -60,29 +60,35 @@ struct f2m_ctx {
         m_g2f, m_pre1, m_g1b, m_g1f, m_sq, m_part, m_lam0;
     // batched solve pools
     DevBuf b_xy, b_orig, b_pos, b_col, b_box, b_x2m, b_lam0, b_lam1, b_best, b_lamlabel, b_thm, b_pz, b_pi, b_pneg,
-        b_pzero, b_prn, b_z4, b_i4, b_seed, b_ctrl, b_trace, b_sargs, b_uargs, b_sitems, b_uitems, b_nblk, b_active;
+        b_pzero, b_prn, b_z4, b_i4, b_seed, b_ctrl, b_trace, b_sargs, b_uargs, b_sitems, b_uitems, b_nblk, b_active,
+        b_slots;
     Ctrl *ctrl_host = nullptr;   // pinned
     int64_t *scratch_host = nullptr;   // pinned, 16 entries
     // the finish's host side: pinned staging of the GPU's pair data, and its
     // workspace and result, kept from one solve to the next
-    HostBuf h_keys, h_costs, h_neg, h_start, h_inc, h_xyp, h_lamp, h_up, h_down;
+    HostBuf h_keys, h_costs, h_neg, h_start, h_inc, h_xyp, h_lamp, h_up, h_down, h_progress;
     f2m::FinishWork *fwork = nullptr;
     f2m::FinishResult fres;
     // contexts (own stream and workspaces) of the batch's finishing threads
     std::vector<f2m_ctx *> workers;
     bool is_worker = false;   // one of those: its finish runs on one thread
+    // opts of calls given none (f2m_create's defaults)
+    f2m_opts defaults;
+    // device bytes held by the DevBufs, and the cap of the current call (0: none)
+    size_t dev_total = 0;
+    size_t dev_cap = 0;
 
     f2m_ctx()
     {
         DevBuf *all[] = {&xy, &minmax, &keys, &keys_alt, &ids, &orig, &pos, &box, &xy2max, &sort_temp,
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
-                         &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &lst, &lcnt, &tpart, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
+                         &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &lst, &lcnt, &tpart, &slots, &kinds, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
                          &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
                          &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
-                         &b_sargs, &b_uargs, &b_sitems, &b_uitems, &b_nblk, &b_active, &m_nbr, &m_nbrd, &m_sorted,
+                         &b_sargs, &b_uargs, &b_sitems, &b_uitems, &b_nblk, &b_active, &b_slots, &m_nbr, &m_nbrd, &m_sorted,
                          &m_temp, &m_scale, &m_feat, &m_w1b, &m_w2b, &m_z1, &m_h1b, &m_z2, &m_h2, &m_y, &m_dy, &m_g2b,
                          &m_g2f, &m_pre1, &m_g1b, &m_g1f, &m_sq, &m_part, &m_lam0};
         bufs.assign(std::begin(all), std::end(all));
@@ -109,15 +115,18 @@ void ck(f2m_ctx *ctx, hipError_t e, const char *what)
     }
 }
 
+// coherent: the device's writes reach host memory without waiting for the
+// kernel to end (used for words the host polls)
 template <typename T>
-T *grow_host(f2m_ctx *ctx, HostBuf &b, size_t count)
+T *grow_host(f2m_ctx *ctx, HostBuf &b, size_t count, bool coherent = false)
 {
     const size_t need = std::max<size_t>(count * sizeof(T), 256);
     if (b.bytes < need) {
         if (b.p) (void)hipHostFree(b.p);
         b.p = b.dp = nullptr;
         b.bytes = 0;
-        ck(ctx, hipHostMalloc(&b.p, need, hipHostMallocDefault | hipHostMallocMapped), "hipHostMalloc");
+        ck(ctx, hipHostMalloc(&b.p, need, (coherent ? hipHostMallocCoherent : hipHostMallocDefault) | hipHostMallocMapped),
+           "hipHostMalloc");
         b.bytes = need;
         ck(ctx, hipHostGetDevicePointer(&b.dp, b.p, 0), "hipHostGetDevicePointer");
     }
@@ -129,13 +138,45 @@ T *grow(f2m_ctx *ctx, DevBuf &b, size_t count)
 {
     const size_t need = std::max<size_t>(count * sizeof(T), 256);
     if (b.bytes < need) {
+        if (ctx->dev_cap && ctx->dev_total - b.bytes + need > ctx->dev_cap)
+            fail(ctx, F2M_ERR_NOMEM, "device workspace would pass max_device_bytes");
         if (b.p) (void)hipFree(b.p);
+        ctx->dev_total -= b.bytes;
         b.p = nullptr;
         b.bytes = 0;
         ck(ctx, hipMalloc(&b.p, need), "hipMalloc");
         b.bytes = need;
+        ctx->dev_total += need;
     }
     return static_cast<T *>(b.p);
+}
+
+// Start state of a GDP run from the resume options (k0, the two previous
+// hashes); checked against max_iters and the warm mode.
+CtrlStart resume_start(f2m_ctx *ctx, const f2m_opts &o)
+{
+    CtrlStart cs;
+    if (o.k0 < 0 || o.k0 > o.max_iters) fail(ctx, F2M_ERR_ARG, "k0 must lie in [0, max_iters]");
+    if (o.k0 > 0 && o.warm != F2M_WARM_USER) fail(ctx, F2M_ERR_ARG, "k0 > 0 resumes from lambda2_init (warm = USER)");
+    if (o.resume_hash_valid && o.k0 < 2) fail(ctx, F2M_ERR_ARG, "resume hashes need k0 >= 2");
+    cs.k0 = o.k0;
+    cs.hvalid = o.resume_hash_valid ? 1 : 0;
+    cs.h1 = o.resume_hash[0];
+    cs.h2 = o.resume_hash[1];
+    return cs;
+}
+
+// The call's options: the caller's, else the context's defaults; sets the
+// call's device memory cap.
+f2m_opts call_opts(f2m_ctx *ctx, const f2m_opts *opts)
+{
+    f2m_opts o = ctx->defaults;
+    if (opts) {
+        if (opts->struct_size != sizeof(f2m_opts)) fail(ctx, F2M_ERR_ARG, "opts.struct_size mismatch");
+        o = *opts;
+    }
+    ctx->dev_cap = (size_t)o.max_device_bytes;
+    return o;
 }
 
 // Host arrays to the device through the pinned staging h_up: copied there,
@@ -250,24 +291,43 @@ struct GeoBufs {
     float *xy2max;
 };
 
+// Device buffers of the Morton sort (keys, their sorted copy, ids and the
+// radix sort's temporary storage of tb bytes).
+struct SortBufs {
+    uint32_t *keys, *keys2;
+    int32_t *ids;
+    void *temp;
+    size_t tb;
+};
+
 // Morton order, centred column records and tile boxes for one instance
 // whose extents are known; enqueued on st without synchronising.
-void enqueue_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, int32_t minx, int32_t miny, int32_t cx, int32_t cy,
-                 const GeoBufs &b, hipStream_t st)
+void enqueue_geo_into(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, int32_t minx, int32_t miny, int32_t cx,
+                      int32_t cy, const GeoBufs &b, const SortBufs &s, hipStream_t st)
 {
-    const size_t tb = sort_temp_bytes(n);
-    uint32_t *keys = grow<uint32_t>(ctx, ctx->keys, n);
-    uint32_t *keys2 = grow<uint32_t>(ctx, ctx->keys_alt, n);
-    int32_t *ids = grow<int32_t>(ctx, ctx->ids, n);
-    void *temp = grow<char>(ctx, ctx->sort_temp, tb);
-    ck(ctx, launch_sort(xy_dev, n, minx, miny, keys, keys2, ids, b.orig, b.pos, temp, tb, st), "sort");
+    ck(ctx, launch_sort(xy_dev, n, minx, miny, s.keys, s.keys2, s.ids, b.orig, b.pos, s.temp, s.tb, st), "sort");
     ck(ctx, launch_prep(xy_dev, b.orig, n, cx, cy, b.col, b.box, b.xy2max, st), "prep");
 }
 
-GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st)
+SortBufs grow_sort(f2m_ctx *ctx, int64_t n)
+{
+    const size_t tb = sort_temp_bytes(n);
+    return SortBufs{grow<uint32_t>(ctx, ctx->keys, n), grow<uint32_t>(ctx, ctx->keys_alt, n),
+                    grow<int32_t>(ctx, ctx->ids, n), grow<char>(ctx, ctx->sort_temp, tb), tb};
+}
+
+void enqueue_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, int32_t minx, int32_t miny, int32_t cx, int32_t cy,
+                 const GeoBufs &b, hipStream_t st)
+{
+    enqueue_geo_into(ctx, xy_dev, n, minx, miny, cx, cy, b, grow_sort(ctx, n), st);
+}
+
+// Span check, centre, Morton order and column records into the given
+// buffers (m4: 4 int32 on the device); synchronises st twice.
+GeoHost setup_geo_into(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st, int32_t *m4,
+                       const GeoBufs &b, const SortBufs &sb)
 {
     GeoHost gh;
-    int32_t *m4 = grow<int32_t>(ctx, ctx->minmax, 4);
     ck(ctx, launch_minmax(xy_dev, n, m4, st), "minmax");
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, m4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
@@ -278,9 +338,7 @@ GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st
     gh.cx = (int32_t)(((int64_t)h[0] + h[1]) >> 1);
     gh.cy = (int32_t)(((int64_t)h[2] + h[3]) >> 1);
     gh.xy = xy_dev;
-    GeoBufs b{grow<int32_t>(ctx, ctx->orig, n), grow<int32_t>(ctx, ctx->pos, n), grow<float4>(ctx, ctx->col, n),
-              grow<float4>(ctx, ctx->box, ntiles_of(n) * kBoxStride), grow<float>(ctx, ctx->xy2max, 1)};
-    enqueue_geo(ctx, xy_dev, n, h[0], h[2], gh.cx, gh.cy, b, st);
+    enqueue_geo_into(ctx, xy_dev, n, h[0], h[2], gh.cx, gh.cy, b, sb, st);
     float x2host = 0.0f;
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, b.xy2max, sizeof(float), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
@@ -288,6 +346,14 @@ GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st
     gh.g = Geo{n, b.orig, b.pos, b.box, x2host};
     gh.col = b.col;
     return gh;
+}
+
+GeoHost setup_geo(f2m_ctx *ctx, const int32_t *xy_dev, int64_t n, hipStream_t st)
+{
+    int32_t *m4 = grow<int32_t>(ctx, ctx->minmax, 4);
+    GeoBufs b{grow<int32_t>(ctx, ctx->orig, n), grow<int32_t>(ctx, ctx->pos, n), grow<float4>(ctx, ctx->col, n),
+              grow<float4>(ctx, ctx->box, ntiles_of(n) * kBoxStride), grow<float>(ctx, ctx->xy2max, 1)};
+    return setup_geo_into(ctx, xy_dev, n, st, m4, b, grow_sort(ctx, n));
 }
 
 // A Lam placed on the certificate / collection state: sorted Lam, column
@@ -302,7 +368,7 @@ LamView place_lam(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label_dev,
     Ctrl *cc = grow<Ctrl>(ctx, ctx->c_ctrl, 1);
     float *x2m = grow<float>(ctx, ctx->xy2max, 1);
     ck(ctx, launch_prep(gh.xy, gh.g.orig, n, gh.cx, gh.cy, col, const_cast<float4 *>(gh.g.box), x2m, st), "prep");
-    ck(ctx, launch_ctrl_init(cc, 0, 0, 0, st), "ctrl");
+    ck(ctx, launch_ctrl_init(cc, 0, 0, 0, CtrlStart{}, st), "ctrl");
     ck(ctx, launch_set_lam(lam_label_dev, by_position ? nullptr : gh.g.orig, n, ls, col, th, cc, st), "set_lam");
     return LamView{col, ls, th, cc};
 }
@@ -652,6 +718,9 @@ struct LoopOut {
     int64_t scan_launches = 0;
     ScanShape shape;
     int64_t *lam_star;     // device, sorted: Lam_kstar
+    int64_t *lam_last;     // device, sorted: Lam_{k_last}
+    double ms_kind[3] = {0.0, 0.0, 0.0};     // scan time by ScanKind (time_kernels)
+    int64_t launches_kind[3] = {0, 0, 0};
 };
 
 // The GDP loop on device buffers.  lam0_label_dev: device Lam_0 by label
@@ -659,7 +728,7 @@ struct LoopOut {
 LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev, int64_t max_iters,
                  int64_t handoff_div, int32_t chunk_opt, bool want_trace, bool time_kernels, bool cull,
                  const Csr *csr, int rows_override, int64_t slices_override, hipStream_t st,
-                 bool keep_seeds = false)
+                 bool keep_seeds = false, const CtrlStart &cs = CtrlStart{})
 {
     LoopOut o;
     const int64_t n = gh.g.n;
@@ -682,48 +751,64 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     int32_t *i4 = grow<int32_t>(ctx, ctx->i4, kTop * n);
     int32_t *seed = grow<int32_t>(ctx, ctx->seed, kTop * n);
     Ctrl *cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
-    const int64_t trace_cap = want_trace ? max_iters + 1 : 0;
+    const int64_t k0 = cs.k0;
+    // records (and scan kinds) kept for iterations k0 .. k0 + trace_cap - 1
+    const int64_t trace_cap = want_trace ? max_iters + 1 - k0 : std::min<int64_t>(max_iters + 1 - k0, 1 << 16);
     int64_t *trace = want_trace ? grow<int64_t>(ctx, ctx->trace, kTraceW * trace_cap) : nullptr;
     // the culled one-row-per-lane scan keeps candidate lists (kLW per row
     // and wave) and evaluates only them while they stay exact
     const bool lists = !csr && cull && sh.rows == 1;
-    int32_t *lst = lists ? grow<int32_t>(ctx, ctx->lst, 4 * kLW * n) : nullptr;
-    int32_t *lcnt = lists ? grow<int32_t>(ctx, ctx->lcnt, 4 * n) : nullptr;
+    int32_t *lst = lists ? grow<int32_t>(ctx, ctx->lst, 4 * sh.slices * kLW * n) : nullptr;
+    int32_t *lcnt = lists ? grow<int32_t>(ctx, ctx->lcnt, 4 * sh.slices * n) : nullptr;
     // its workgroups store their pairs tested for k_update to sum (one
     // atomic per update block instead of one per scan wave)
     unsigned long long *tpart = lists ? grow<unsigned long long>(ctx, ctx->tpart, sh.slices * ((n + 63) / 64)) : nullptr;
+    unsigned long long *slots = grow<unsigned long long>(ctx, ctx->slots, (int64_t)kSlotW * ((n + kTileCols - 1) / kTileCols));
+    int32_t *kinds = csr ? nullptr : grow<int32_t>(ctx, ctx->kinds, trace_cap);
 
     if (lam0_label_dev)
         ck(ctx, hipMemcpyAsync(l0, lam0_label_dev, n * sizeof(int64_t), hipMemcpyDeviceToDevice, st), "copy");
     else
         ck(ctx, hipMemsetAsync(l0, 0, n * sizeof(int64_t), st), "memset");
-    ck(ctx, launch_ctrl_init(cd, max_iters, trace_cap, handoff_div, st), "ctrl_init");
-    ck(ctx, launch_set_lam(l0, gh.g.orig, n, lam[0], col, thm, cd, st), "set_lam");
+    ck(ctx, launch_ctrl_init(cd, max_iters, trace_cap, handoff_div, cs, st), "ctrl_init");
+    ck(ctx, launch_set_lam(l0, gh.g.orig, n, lam[k0 & 1], col, thm, cd, st), "set_lam");
     if (!keep_seeds) ck(ctx, launch_seed_neighbours(n, col, seed, st), "seed");
     ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2_init| must be below 2^38");
 
-    const int chunk = chunk_opt > 0 ? chunk_opt : (n >= 50000 ? 4 : (n >= 5000 ? 16 : 64));
+    // Iterations are queued `window` ahead of the last one the device has
+    // finished, which the update's last block reports through a word of
+    // pinned host memory; the host never waits for the stream to drain.
+    // Iterations queued past the stop exit at once.  If the word is not
+    // seen to move while the stream is idle, the control block itself is
+    // read (the word only saves synchronisations).
+    const int64_t window = chunk_opt > 0 ? chunk_opt : (n >= 50000 ? 2 : (n >= 5000 ? 4 : 8));
+    volatile long long *pw = static_cast<volatile long long *>(grow_host<long long>(ctx, ctx->h_progress, 1, true));
+    *pw = -1;
+    long long *pw_dev = static_cast<long long *>(ctx->h_progress.dp);
     std::vector<hipEvent_t> evs;
-    if (time_kernels) {
-        evs.resize(2 * chunk);
-        for (auto &e : evs) ck(ctx, hipEventCreate(&e), "hipEventCreate");
-    }
     struct EvGuard {
         std::vector<hipEvent_t> &v;
         ~EvGuard() { for (auto e : v) (void)hipEventDestroy(e); }
     } guard{evs};
-    int64_t k = 0;
-    for (;;) {
-        int issued = 0;
-        for (int j = 0; j < chunk && k <= max_iters; ++j, ++k, ++issued) {
+    int64_t k = k0, seen = k0 - 1;
+    bool done = false;
+    while (!done) {
+        for (; k <= max_iters && k - seen <= window; ++k) {
+            if (time_kernels) {
+                for (int q = 0; q < 2; ++q) {
+                    evs.push_back(nullptr);
+                    ck(ctx, hipEventCreate(&evs.back()), "hipEventCreate");
+                }
+            }
+            hipEvent_t e0 = time_kernels ? evs[evs.size() - 2] : nullptr, e1 = time_kernels ? evs.back() : nullptr;
             if (csr) {
                 GraphStepArgs ga{gh.g, *csr, k, lam[k & 1], lam[(k + 1) & 1], best, z4, i4, nullptr, nullptr,
-                                 nullptr, cd, trace};
-                if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
+                                 nullptr, cd, trace, slots, pw_dev};
+                if (e0) ck(ctx, hipEventRecord(e0, st), "hipEventRecord");
                 ck(ctx, launch_graph_step(ga, st), "graph_step");
-                if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
+                if (e1) ck(ctx, hipEventRecord(e1, st), "hipEventRecord");
                 continue;
             }
             ScanArgs sa{};
@@ -743,35 +828,58 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             sa.lst = lst;
             sa.lcnt = lcnt;
             sa.tpart = tpart;
-            if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j], st), "hipEventRecord");
+            if (e0) ck(ctx, hipEventRecord(e0, st), "hipEventRecord");
             ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
-            if (time_kernels) ck(ctx, hipEventRecord(evs[2 * j + 1], st), "hipEventRecord");
+            if (e1) ck(ctx, hipEventRecord(e1, st), "hipEventRecord");
             UpdateArgs ua{gh.g, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
                           thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows, lists ? 1 : 0,
-                          tpart};
+                          tpart, slots, kinds, pw_dev};
             ck(ctx, launch_update(ua, st), "update");
         }
-        ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipStreamSynchronize(st), "sync");
-        if (time_kernels) {
-            // iterations after the stop exit at once; count the ones that ran
-            const int64_t k0 = k - issued;
-            const int64_t ran = std::min<int64_t>(issued, ctx->ctrl_host->k_last + 1 - k0);
-            for (int64_t j = 0; j < ran; ++j) {
-                float ms = 0.0f;
-                ck(ctx, hipEventElapsedTime(&ms, evs[2 * j], evs[2 * j + 1]), "hipEventElapsedTime");
-                o.scan_ms += ms;
-                ++o.scan_launches;
+        // wait for the device to finish another iteration
+        for (long spin = 0;; ++spin) {
+            const long long w = *pw;
+            if (w >= 0 && (w >> 1) > seen) {
+                seen = w >> 1;
+                done = (w & 1) != 0;
+                break;
+            }
+            if ((spin & 4095) == 4095 && hipStreamQuery(st) == hipSuccess) {
+                // everything queued has run: read the control block
+                ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
+                ck(ctx, hipStreamSynchronize(st), "sync");
+                seen = std::max<int64_t>(seen, ctx->ctrl_host->k_last);
+                done = ctx->ctrl_host->done != 0;
+                if (!done && k > max_iters) fail(ctx, F2M_ERR_DEVICE, "GDP loop passed the cap without stopping");
+                break;
             }
         }
-        if (ctx->ctrl_host->done) break;
-        if (k > max_iters) fail(ctx, F2M_ERR_DEVICE, "GDP loop passed the cap without stopping");
+    }
+    ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    if (time_kernels) {
+        // the iterations that ran (later ones exited at once), by the kind
+        // of scan each was (complete graph)
+        const int64_t ran = ctx->ctrl_host->k_last + 1 - k0;
+        std::vector<int32_t> kk(std::max<int64_t>(ran, 1), kScanFull);
+        const int64_t nk = kinds ? std::max<int64_t>(0, std::min<int64_t>(ran, trace_cap)) : 0;
+        if (nk > 0) ck(ctx, hipMemcpy(kk.data(), kinds, nk * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
+        for (int64_t j = 0; j < ran && 2 * j + 1 < (int64_t)evs.size(); ++j) {
+            float ms = 0.0f;
+            ck(ctx, hipEventElapsedTime(&ms, evs[2 * j], evs[2 * j + 1]), "hipEventElapsedTime");
+            o.scan_ms += ms;
+            ++o.scan_launches;
+            const int kind = (kk[j] >= 0 && kk[j] < 3) ? kk[j] : kScanFull;
+            o.ms_kind[kind] += ms;
+            ++o.launches_kind[kind];
+        }
     }
     o.shape = sh;
     o.c = *ctx->ctrl_host;
     if (o.c.overflow) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| reached 2^38");
     int64_t *last = lam[o.c.k_last & 1];
     o.lam_star = (o.c.kstar == o.c.k_last) ? last : best;
+    o.lam_last = last;
     return o;
 }
 
@@ -901,6 +1009,8 @@ struct InstanceState {
     const int32_t *seed;       // device, positions
     const int64_t *trace;      // device or null
     const Csr *csr;            // candidate graph or null
+    const int32_t *kinds;      // device scan kinds (with trace) or null
+    const int64_t *lam_last;   // device, sorted: Lam_{k_last}
 };
 
 void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, hipStream_t st,
@@ -910,18 +1020,25 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
     const GeoHost &gh = is.gh;
     const Ctrl &c = is.c;
     res.n = n;
-    res.iterations = c.k_last + 1;
+    res.iterations = c.k_last + 1 - c.k_first;
     res.kstar = c.kstar;
     res.stop = (int32_t)c.stop;
     int64_t *lstar = grow<int64_t>(ctx, ctx->lam_label, n);
     ck(ctx, launch_unpermute(is.lam_star, gh.g.orig, n, lstar, st), "unpermute");
     res.lambda2_gdp = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
+    res.lambda2_last = reinterpret_cast<int64_t *>(host_alloc(ctx, n * sizeof(int64_t)));
+    int64_t *llast = grow<int64_t>(ctx, ctx->f_lam, n);
+    ck(ctx, launch_unpermute(is.lam_last, gh.g.orig, n, llast, st), "unpermute");
     if (is.trace) {
         res.trace_len = std::min<int64_t>(res.iterations, c.trace_cap);
         res.trace = reinterpret_cast<int64_t *>(host_alloc(ctx, res.trace_len * kTraceW * sizeof(int64_t)));
     }
-    download(ctx, {{lstar, res.lambda2_gdp, n * sizeof(int64_t)},
-                   {is.trace, res.trace, is.trace ? res.trace_len * kTraceW * sizeof(int64_t) : 0}}, st);
+    if (is.kinds) res.scan_kind = reinterpret_cast<int32_t *>(host_alloc(ctx, std::max<int64_t>(res.trace_len, 1) * sizeof(int32_t)));
+    download(ctx, {{lstar, res.lambda2_gdp, n * sizeof(int64_t)}, {llast, res.lambda2_last, n * sizeof(int64_t)},
+                   {is.trace, res.trace, is.trace ? res.trace_len * kTraceW * sizeof(int64_t) : 0},
+                   {is.kinds, res.scan_kind, is.kinds ? res.trace_len * sizeof(int32_t) : 0}}, st);
+    res.scan_list_uses = c.list_uses;
+    res.scan_list_builds = c.list_builds;
     res.dual2_gdp = (c.kstar == c.k_last) ? c.dual2_last : c.best_dual2;
 
     int32_t *eu = nullptr, *ev = nullptr;
@@ -1017,6 +1134,58 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
     res.seconds[4] = t5 - t4;
 }
 
+// Every device buffer one GDP iteration uses (f2m_gdp_step).
+struct StepBufs {
+    int32_t *m4;
+    GeoBufs geo;
+    SortBufs sort;
+    int64_t *ls, *lo, *best;
+    float *thm;
+    int64_t *pz;
+    int32_t *pi, *pneg, *pzero;
+    int64_t *prn;
+    int64_t *z4;
+    int32_t *i4, *seed;
+    Ctrl *cd;
+    int64_t *trace;
+    unsigned long long *slots;
+};
+
+// One GDP iteration (culled scan, update) from lam_in (device, labels) into
+// the given buffers; lam_out, neg, zero, step by label; rec to the host.
+void gdp_step_run(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam_in, int64_t *lam_out, int32_t *neg,
+                  int32_t *zero, int64_t *step, int64_t rec[F2M_TRACE_W], const StepBufs &b)
+{
+    hipStream_t st = ctx->stream;
+    const GeoHost gh = setup_geo_into(ctx, xy, n, st, b.m4, b.geo, b.sort);
+    const ScanShape sh = scan_shape(n, true);
+    float4 *col = gh.col;
+    ck(ctx, launch_ctrl_init(b.cd, INT64_MAX, 1, 0, CtrlStart{}, st), "ctrl_init");
+    ck(ctx, launch_set_lam(lam_in, gh.g.orig, n, b.ls, col, b.thm, b.cd, st), "set_lam");
+    ck(ctx, launch_seed_neighbours(n, col, b.seed, st), "seed");
+    ck(ctx, hipMemcpyAsync(ctx->ctrl_host, b.cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| must be below 2^38");
+    ScanArgs sa{};
+    sa.g = gh.g;
+    sa.lv = LamView{col, b.ls, b.thm, b.cd};
+    sa.slice_len = sh.slice_len;
+    sa.cull = 1;
+    sa.check_done = 1;
+    sa.seed = b.seed;
+    sa.pz = b.pz; sa.pi = b.pi; sa.pneg = b.pneg; sa.pzero = b.pzero; sa.prowneg = b.prn;
+    ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
+    UpdateArgs ua{gh.g, sh.slices, 0, b.pz, b.pi, b.pneg, b.pzero, b.prn, b.ls, b.lo, b.best, col, b.thm,
+                  b.z4, b.i4, b.seed, neg, zero, step, b.cd, b.trace};
+    ua.slots = b.slots;
+    ck(ctx, launch_update(ua, st), "update");
+    ck(ctx, launch_unpermute(b.lo, gh.g.orig, n, lam_out, st), "unpermute");
+    ck(ctx, hipMemcpyAsync(ctx->scratch_host, b.trace, kTraceW * sizeof(int64_t), hipMemcpyDeviceToHost, st),
+       "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    std::memcpy(rec, ctx->scratch_host, kTraceW * sizeof(int64_t));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1039,13 +1208,16 @@ void f2m_opts_default(f2m_opts *o)
     o->finish = F2M_FINISH_EXACT;
 }
 
-f2m_status f2m_create(f2m_ctx **out, int device)
+f2m_status f2m_create(f2m_ctx **out, int device, const f2m_opts *defaults)
 {
     if (!out) return F2M_ERR_ARG;
     *out = nullptr;
+    if (defaults && defaults->struct_size != sizeof(f2m_opts)) return F2M_ERR_ARG;
     f2m_ctx *ctx = new (std::nothrow) f2m_ctx();
     if (!ctx) return F2M_ERR_NOMEM;
     ctx->device = device;
+    if (defaults) ctx->defaults = *defaults;
+    else f2m_opts_default(&ctx->defaults);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         delete ctx;
@@ -1073,7 +1245,7 @@ void f2m_destroy(f2m_ctx *ctx)
     if (ctx->ctrl_host) (void)hipHostFree(ctx->ctrl_host);
     if (ctx->scratch_host) (void)hipHostFree(ctx->scratch_host);
     for (HostBuf *h : {&ctx->h_keys, &ctx->h_costs, &ctx->h_neg, &ctx->h_start, &ctx->h_inc, &ctx->h_xyp, &ctx->h_lamp,
-                       &ctx->h_up, &ctx->h_down})
+                       &ctx->h_up, &ctx->h_down, &ctx->h_progress})
         if (h->p) (void)hipHostFree(h->p);
     if (ctx->fwork) finish_work_destroy(ctx->fwork);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -1085,10 +1257,12 @@ void f2m_result_free(f2m_result *r)
     if (!r) return;
     std::free(r->lambda2);
     std::free(r->lambda2_gdp);
+    std::free(r->lambda2_last);
     std::free(r->edge_u);
     std::free(r->edge_v);
     std::free(r->edge_x2);
     std::free(r->trace);
+    std::free(r->scan_kind);
     std::memset(r, 0, sizeof(*r));
 }
 
@@ -1115,52 +1289,35 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
                         int64_t rec[F2M_TRACE_W])
 {
     if (!ctx) return F2M_ERR_ARG;
+    ctx->dev_cap = (size_t)ctx->defaults.max_device_bytes;
     try {
         if (!xy || !lam_in || !lam_out || !rec || n < 4 || lam_in == lam_out)
             fail(ctx, F2M_ERR_ARG, "gdp_step needs n >= 4, coords, distinct lambda2_in/out and rec");
+        if (n >= (int64_t)1 << 30) fail(ctx, F2M_ERR_ARG, "n must be below 2^30");
         ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-        hipStream_t st = ctx->stream;
-        const GeoHost gh = setup_geo(ctx, xy, n, st);
-        const bool cull = true;
-        const ScanShape sh = scan_shape(n, cull);
-        float4 *col = gh.col;
-        int64_t *ls = grow<int64_t>(ctx, ctx->lam[0], n);
-        int64_t *lo = grow<int64_t>(ctx, ctx->lam[1], n);
-        int64_t *best = grow<int64_t>(ctx, ctx->lam_best, n);
-        float *thm = grow<float>(ctx, ctx->tile_hmax, ntiles_of(n) * kBoxStride);
-        int64_t *pz = grow<int64_t>(ctx, ctx->pz, sh.slices * kTop * n);
-        int32_t *pi = grow<int32_t>(ctx, ctx->pi, sh.slices * kTop * n);
-        int32_t *pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
-        int32_t *pzero = grow<int32_t>(ctx, ctx->pzero, sh.slices * n);
-        int64_t *prn = grow<int64_t>(ctx, ctx->prowneg, sh.slices * n);
-        int64_t *z4 = z4_out ? z4_out : grow<int64_t>(ctx, ctx->z4, kTop * n);
-        int32_t *i4 = i4_out ? i4_out : grow<int32_t>(ctx, ctx->i4, kTop * n);
-        int32_t *seed = grow<int32_t>(ctx, ctx->seed, kTop * n);
-        Ctrl *cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
-        int64_t *trace = grow<int64_t>(ctx, ctx->trace, kTraceW);
-        ck(ctx, launch_ctrl_init(cd, INT64_MAX, 1, 0, st), "ctrl_init");
-        ck(ctx, launch_set_lam(lam_in, gh.g.orig, n, ls, col, thm, cd, st), "set_lam");
-        ck(ctx, launch_seed_neighbours(n, col, seed, st), "seed");
-        ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
-        ck(ctx, hipStreamSynchronize(st), "sync");
-        if (ctx->ctrl_host->maxabs_lam >= kLamLimit) fail(ctx, F2M_ERR_OVERFLOW, "|lambda2| must be below 2^38");
-        ScanArgs sa{};
-        sa.g = gh.g;
-        sa.lv = LamView{col, ls, thm, cd};
-        sa.slice_len = sh.slice_len;
-        sa.cull = cull ? 1 : 0;
-        sa.check_done = 1;
-        sa.seed = seed;
-        sa.pz = pz; sa.pi = pi; sa.pneg = pneg; sa.pzero = pzero; sa.prowneg = prn;
-        ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
-        UpdateArgs ua{gh.g, sh.slices, 0, pz, pi, pneg, pzero, prn, ls, lo, best, col, thm,
-                      z4, i4, seed, neg, zero, step, cd, trace};
-        ck(ctx, launch_update(ua, st), "update");
-        ck(ctx, launch_unpermute(lo, gh.g.orig, n, lam_out, st), "unpermute");
-        ck(ctx, hipMemcpyAsync(ctx->scratch_host, trace, kTraceW * sizeof(int64_t), hipMemcpyDeviceToHost, st),
-           "copy");
-        ck(ctx, hipStreamSynchronize(st), "sync");
-        std::memcpy(rec, ctx->scratch_host, kTraceW * sizeof(int64_t));
+        const ScanShape sh = scan_shape(n, true);
+        StepBufs b;
+        b.m4 = grow<int32_t>(ctx, ctx->minmax, 4);
+        b.geo = GeoBufs{grow<int32_t>(ctx, ctx->orig, n), grow<int32_t>(ctx, ctx->pos, n),
+                        grow<float4>(ctx, ctx->col, n), grow<float4>(ctx, ctx->box, ntiles_of(n) * kBoxStride),
+                        grow<float>(ctx, ctx->xy2max, 1)};
+        b.sort = grow_sort(ctx, n);
+        b.ls = grow<int64_t>(ctx, ctx->lam[0], n);
+        b.lo = grow<int64_t>(ctx, ctx->lam[1], n);
+        b.best = grow<int64_t>(ctx, ctx->lam_best, n);
+        b.thm = grow<float>(ctx, ctx->tile_hmax, ntiles_of(n) * kBoxStride);
+        b.pz = grow<int64_t>(ctx, ctx->pz, sh.slices * kTop * n);
+        b.pi = grow<int32_t>(ctx, ctx->pi, sh.slices * kTop * n);
+        b.pneg = grow<int32_t>(ctx, ctx->pneg, sh.slices * n);
+        b.pzero = grow<int32_t>(ctx, ctx->pzero, sh.slices * n);
+        b.prn = grow<int64_t>(ctx, ctx->prowneg, sh.slices * n);
+        b.z4 = z4_out ? z4_out : grow<int64_t>(ctx, ctx->z4, kTop * n);
+        b.i4 = i4_out ? i4_out : grow<int32_t>(ctx, ctx->i4, kTop * n);
+        b.seed = grow<int32_t>(ctx, ctx->seed, kTop * n);
+        b.cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
+        b.trace = grow<int64_t>(ctx, ctx->trace, kTraceW);
+        b.slots = grow<unsigned long long>(ctx, ctx->slots, (int64_t)kSlotW * ntiles_of(n));
+        gdp_step_run(ctx, xy, n, lam_in, lam_out, neg, zero, step, rec, b);
         return F2M_OK;
     } catch (const Fail &f) {
         return f.st;
@@ -1172,6 +1329,7 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
 
 #define F2M_GUARD_BEGIN \
     if (!ctx) return F2M_ERR_ARG; \
+    ctx->dev_cap = (size_t)ctx->defaults.max_device_bytes; \
     try {
 #define F2M_GUARD_END \
     } catch (const Fail &f) { \
@@ -1235,6 +1393,7 @@ f2m_status f2m_knn_graph(f2m_ctx *ctx, const int32_t *xy, int64_t n, int32_t k, 
                          int64_t cap, int64_t *nnz)
 {
     if (!ctx) return F2M_ERR_ARG;
+    ctx->dev_cap = (size_t)ctx->defaults.max_device_bytes;
     try {
         if (!xy || !rowptr || !col || !nnz || cap < 0) fail(ctx, F2M_ERR_ARG, "knn_graph needs coords and outputs");
         ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
@@ -1259,6 +1418,7 @@ f2m_status f2m_certify(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t
                        const int32_t *eu, const int32_t *ev, const uint8_t *ex2, int64_t out[4])
 {
     if (!ctx) return F2M_ERR_ARG;
+    ctx->dev_cap = (size_t)ctx->defaults.max_device_bytes;
     try {
         if (!xy || !lam || !out || n < 3 || m < 0 || (m > 0 && (!eu || !ev || !ex2)))
             fail(ctx, F2M_ERR_ARG, "certify needs n >= 3, coords, lambda2 and the edge arrays");
@@ -1280,12 +1440,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
     f2m_result res;
     std::memset(&res, 0, sizeof(res));
     try {
-        f2m_opts o;
-        f2m_opts_default(&o);
-        if (opts) {
-            if (opts->struct_size != sizeof(f2m_opts)) fail(ctx, F2M_ERR_ARG, "opts.struct_size mismatch");
-            o = *opts;
-        }
+        const f2m_opts o = call_opts(ctx, opts);
         if (!coords || !out) fail(ctx, F2M_ERR_ARG, "null coords or result");
         if (o.rule_version != 1) fail(ctx, F2M_ERR_ARG, "only rule_version 1 exists");
         if (o.graph != F2M_GRAPH_COMPLETE && o.graph != F2M_GRAPH_KNN) fail(ctx, F2M_ERR_ARG, "unknown graph kind");
@@ -1296,6 +1451,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             fail(ctx, F2M_ERR_ARG, "scan_rows must be 0, 1, 2 or 4");
         if (o.scan_slices < 0) fail(ctx, F2M_ERR_ARG, "scan_slices < 0");
         if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
+        const CtrlStart cs = resume_start(ctx, o);
         if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER && o.warm != F2M_WARM_MLP &&
             o.warm != F2M_WARM_GRAPH)
             fail(ctx, F2M_ERR_ARG, "unknown warm mode");
@@ -1371,15 +1527,22 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         res.seconds[1] = t1 - tw;
         LoopOut lo = gdp_loop(ctx, gh, lam0_dev, o.max_iters, o.handoff_div, o.chunk, o.record_trace != 0,
                               o.time_kernels != 0, o.scan_mode != F2M_SCAN_FULL, on_graph ? &csr : nullptr,
-                              o.scan_rows, o.scan_slices, st, keep_seeds);
+                              o.scan_rows, o.scan_slices, st, keep_seeds, cs);
         const double t2 = now_s();
         InstanceState is{gh, lo.c, lo.lam_star, static_cast<const int64_t *>(ctx->z4.p),
                          static_cast<const int32_t *>(ctx->i4.p), static_cast<const int32_t *>(ctx->seed.p),
                          o.record_trace ? static_cast<const int64_t *>(ctx->trace.p) : nullptr,
-                         on_graph ? &csr : nullptr};
+                         on_graph ? &csr : nullptr,
+                         (o.record_trace && !on_graph) ? static_cast<const int32_t *>(ctx->kinds.p) : nullptr,
+                         lo.lam_last};
         complete_result(ctx, is, o, st, res);
         res.scan_ms = lo.scan_ms;
         res.scan_launches = lo.scan_launches;
+        for (int q = 0; q < 3; ++q) {
+            res.scan_ms_kind[q] = lo.ms_kind[q];
+            res.scan_launches_kind[q] = lo.launches_kind[q];
+            res.scan_pairs_kind[q] = (int64_t)lo.c.pairs_kind[q];
+        }
         res.scan_rows = lo.shape.rows;
         res.scan_slices = lo.shape.slices;
         res.seconds[0] = tw - t0;
@@ -1415,12 +1578,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         }
     } gguard{graph, exec};
     try {
-        f2m_opts o;
-        f2m_opts_default(&o);
-        if (opts) {
-            if (opts->struct_size != sizeof(f2m_opts)) fail(ctx, F2M_ERR_ARG, "opts.struct_size mismatch");
-            o = *opts;
-        }
+        const f2m_opts o = call_opts(ctx, opts);
         if (!coords || !offsets || !outs || n_inst <= 0) fail(ctx, F2M_ERR_ARG, "null inputs or no instances");
         if (o.rule_version != 1) fail(ctx, F2M_ERR_ARG, "only rule_version 1 exists");
         if (o.graph != F2M_GRAPH_COMPLETE) fail(ctx, F2M_ERR_ARG, "batched solves run on the complete graph");
@@ -1428,6 +1586,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         if (o.max_iters < 0 || o.handoff_div < 0) fail(ctx, F2M_ERR_ARG, "bad max_iters or handoff_div");
         if (o.warm != F2M_WARM_COLD && !(o.warm == F2M_WARM_USER && o.lambda2_init))
             fail(ctx, F2M_ERR_ARG, "bad warm start");
+        const CtrlStart cs = resume_start(ctx, o);
         if (offsets[0] != 0) fail(ctx, F2M_ERR_ARG, "offsets[0] must be 0");
         for (int32_t i = 0; i < n_inst; ++i) {
             if (offsets[i + 1] - offsets[i] < 3) fail(ctx, F2M_ERR_INFEASIBLE, "every instance needs n >= 3");
@@ -1471,7 +1630,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             PZ[i + 1] = PZ[i] + shp[i].slices * n;
             if (n >= 4) active.push_back(i);
         }
-        const int64_t trace_cap = o.record_trace ? std::min<int64_t>(o.max_iters + 1, 8192) : 0;
+        const int64_t trace_cap = o.record_trace ? std::min<int64_t>(o.max_iters + 1 - cs.k0, 8192) : 0;
 
         // pools
         int32_t *xy = grow<int32_t>(ctx, ctx->b_xy, 2 * total);
@@ -1497,6 +1656,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         int64_t *trace = trace_cap ? grow<int64_t>(ctx, ctx->b_trace, (int64_t)n_inst * trace_cap * kTraceW) : nullptr;
         int64_t *nblk = grow<int64_t>(ctx, ctx->b_nblk, n_inst);
         int32_t *act = grow<int32_t>(ctx, ctx->b_active, 1);
+        unsigned long long *bslots = grow<unsigned long long>(ctx, ctx->b_slots, (int64_t)kSlotW * (T[n_inst] / kBoxStride));
 
         ck(ctx, hipMemcpyAsync(xy, coords, 2 * total * sizeof(int32_t), hipMemcpyHostToDevice, st), "copy");
         if (o.warm == F2M_WARM_USER)
@@ -1508,8 +1668,9 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             const int64_t n = offsets[i + 1] - offsets[i], X = offsets[i];
             GeoBufs b{orig + P[i], pos + X, col + P[i], box + T[i], x2m + i};
             enqueue_geo(ctx, xy + 2 * X, n, mnx[i], mny[i], cxs[i], cys[i], b, st);
-            ck(ctx, launch_ctrl_init(ctrl + i, o.max_iters, trace_cap, o.handoff_div, st), "ctrl_init");
-            ck(ctx, launch_set_lam(lamlabel + X, orig + P[i], n, lam0 + P[i], col + P[i], thm + T[i], ctrl + i, st),
+            ck(ctx, launch_ctrl_init(ctrl + i, o.max_iters, trace_cap, o.handoff_div, cs, st), "ctrl_init");
+            ck(ctx, launch_set_lam(lamlabel + X, orig + P[i], n, ((cs.k0 & 1) ? lam1 : lam0) + P[i], col + P[i],
+                                   thm + T[i], ctrl + i, st),
                "set_lam");
             ck(ctx, launch_seed_neighbours(n, col + P[i], seed + kTop * X, st), "seed");
             nb_host[i] = ntiles_of(n);
@@ -1554,6 +1715,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
                                best + P[i], col + P[i], thm + T[i], z4 + kTop * X, i4 + kTop * X, seed + kTop * X,
                                nullptr, nullptr, nullptr, ctrl + i,
                                trace ? trace + (int64_t)i * trace_cap * kTraceW : nullptr};
+            ua[i].slots = bslots + (int64_t)kSlotW * (T[i] / kBoxStride);
             const int64_t rb = ntiles_of(n);
             for (int64_t r = 0; r < rb; ++r)
                 for (int64_t sl = 0; sl < shp[i].slices; ++sl)
@@ -1592,7 +1754,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             }
             ck(ctx, hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
             ck(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-            const int64_t max_replays = o.max_iters / chunk + 2;
+            const int64_t max_replays = (o.max_iters - cs.k0) / chunk + 2;
             int64_t replays = 0;
             for (;;) {
                 ck(ctx, hipGraphLaunch(exec, st), "hipGraphLaunch");
@@ -1631,7 +1793,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         const int nw = (int)std::min<size_t>(todo.size(), (size_t)finish_threads());
         while ((int)ctx->workers.size() < nw) {
             f2m_ctx *w = nullptr;
-            const f2m_status cs = f2m_create(&w, ctx->device);
+            const f2m_status cs = f2m_create(&w, ctx->device, &ctx->defaults);
             if (cs != F2M_OK) fail(ctx, cs, "cannot create a finishing context");
             w->is_worker = true;
             ctx->workers.push_back(w);
@@ -1656,7 +1818,8 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
                     const int64_t *last = (c.k_last & 1) ? lam1 + P[i] : lam0 + P[i];
                     const int64_t *lstar = (c.kstar == c.k_last) ? last : best + P[i];
                     InstanceState is{gh, c, lstar, z4 + kTop * X, i4 + kTop * X, seed + kTop * X,
-                                     trace ? trace + (int64_t)i * trace_cap * kTraceW : nullptr, nullptr};
+                                     trace ? trace + (int64_t)i * trace_cap * kTraceW : nullptr, nullptr, nullptr,
+                                     last};
                     complete_result(wc, is, o, wc->stream, res[i]);
                 } catch (const Fail &f) {
                     ist[i] = f.st;

@@ -29,20 +29,11 @@ constexpr int kSubCols = 32;
 constexpr int kSubs = kTileCols / kSubCols;
 constexpr int kBoxStride = 1 + kSubs;
 
-// Device-resident control block of the GDP loop.  The update kernel's
-// last block reads the accumulators, writes the iteration record, takes
-// the stop decision and clears the accumulators for the next iteration.
+// Device-resident control block of the GDP loop.  The last block of the
+// update kernel to arrive sums the blocks' slots, writes the iteration
+// record and takes the stop decision (see reduce_and_control).
 struct Ctrl {
-    // accumulators of the iteration being reduced
-    unsigned long long acc_sumlam;    // sum Lam_k (two's complement)
-    unsigned long long acc_rowneg;    // sum over rows of sum_u min(0, Z)
-    unsigned long long acc_unsat;
-    unsigned long long acc_bad;
-    long long acc_maxstep;
-    unsigned long long acc_nonzero;
-    unsigned long long acc_hash;
-    long long acc_maxabs_next;        // max |Lam_{k+1}|
-    unsigned int blocks_done;
+    unsigned int blocks_done;   // groups of update blocks arrived
     unsigned int pad0;
     // loop state
     long long done;        // 1 once the loop has stopped
@@ -68,7 +59,23 @@ struct Ctrl {
     long long list_over;   // a list overflowed in the building scan
     long long list_ms0;    // max step of iteration 0
     long long list_Dmax;   // margins above this overflowed (half the last one that did; 0: none yet)
+    long long k_first;     // first iteration of this run (a resumed run starts at k0)
+    long long hvalid;      // h1, h2 were given for k_first - 1, k_first - 2 (resume)
+    unsigned long long pairs_kind[3];   // pairs_tested split by the scans' ScanKind
+    long long list_uses;   // scans that evaluated the lists only
+    long long list_builds; // scans that built lists
+    // arrival counters of the update's blocks (see reduce_and_control):
+    // group g counts at grp_done[32 g], one 128-byte line each
+    unsigned int grp_done[8 * 32];
 };
+
+// Blocks of an update launch leave their part of the iteration record in
+// their own slot of kSlotW 64-bit words; arrivals are counted in
+// kArriveGroups groups so that no single address takes one atomic per block.
+constexpr int kSlotW = 16;
+constexpr int kArriveGroups = 8;
+// Kind of the scan of an iteration (UpdateArgs::scan_kind)
+enum ScanKind { kScanFull = 0, kScanBuild = 1, kScanList = 2 };
 
 // Static geometry of an instance in sorted order.
 struct Geo {
@@ -123,8 +130,9 @@ struct ScanArgs {
     // [s * slice_len, (s + 1) * slice_len)
     int64_t interleave;
     // GDP mode, culled, one row per lane, optional: candidate lists, kLW
-    // positions per (row, wave of the block) in lst[(4 p + wave) kLW + i] and
-    // their count in lcnt[4 p + wave] (-1: overflowed).  A full scan with
+    // positions per (row p, part q = 4 slice + wave of the block) in
+    // lst[(q kLW + i) n + p] and their count in lcnt[q n + p] (-1:
+    // overflowed); 4 slices kLW n and 4 slices n entries.  A full scan with
     // ctrl->list_D > 0 stores every column it finds with Z <= theta + 2 D;
     // while ctrl->list_ok the scan evaluates only the lists (exact as long
     // as the steps since the build sum to at most D / 2)
@@ -164,8 +172,15 @@ struct UpdateArgs {
     int64_t scan_rows;          // rows per lane of the scan (tiles per scan row block)
     int lists;                  // the scan keeps candidate lists: track their drift
     // optional: the scan's pairs tested per (slice, group of 64 rows), added
-    // to ctrl->pairs_tested (one atomic per update block)
+    // to ctrl->pairs_tested by the last block
     const unsigned long long *tpart;
+    // per-block record slots, kSlotW words per update block
+    unsigned long long *slots;
+    // optional, [trace_cap]: the kind (ScanKind) of each iteration's scan
+    int32_t *scan_kind;
+    // optional: host-visible progress word, 2 k + (1 if the loop stopped at
+    // k), written by the last block of iteration k
+    long long *progress;
 };
 
 // candidate list entries per row and wave (see ScanArgs::lst); the margin
@@ -197,6 +212,8 @@ struct GraphStepArgs {
     int64_t *step;              // by label, or null
     Ctrl *ctrl;
     int64_t *trace;
+    unsigned long long *slots;  // per-block record slots, kSlotW words per block
+    long long *progress;        // optional, as UpdateArgs::progress
 };
 
 // Batched loop: one launch covers every instance.  Work items are tables in
@@ -291,7 +308,15 @@ hipError_t launch_edges_to_labels(const int32_t *orig, int64_t m, int32_t *eu, i
 hipError_t launch_seed_from_top(const int32_t *i4, const int32_t *orig, const int32_t *pos, int64_t n, int32_t *seed,
                                 hipStream_t st);
 hipError_t launch_seed_neighbours(int64_t n, const float4 *col, int32_t *seed, hipStream_t st);
+// Loop state at the start of a run: iteration k0 first; with hvalid the
+// hashes of Lam_{k0-1} (h1) and Lam_{k0-2} (h2) arm the cycle test at once.
+struct CtrlStart {
+    int64_t k0 = 0;
+    uint64_t h1 = 0, h2 = 0;
+    int hvalid = 0;
+};
 hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div,
+                            const CtrlStart &cs,
                             hipStream_t st);
 hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_per_thread, hipStream_t st);
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st);

@@ -25,6 +25,7 @@
 // nint(sqrt D) from sqrtf corrected by integer tests).  The filter is
 // conservative: it never drops a pair with Z <= theta_v.
 #include "f2m_internal.h"
+#include "f2m_filter.h"
 
 #include <float.h>
 #include <limits.h>
@@ -117,38 +118,6 @@ struct Top4 {
     }
 };
 
-struct Row {
-    float a, b, c, thr;   // filter: skip when a*xu + b*yu + c*hu + qu > thr
-    float xv, yv;
-    int64_t lamv, theta;
-    int64_t v;
-    int64_t slk = 0;      // the filter passes Z <= theta + slk
-};
-
-// Recomputes the filter of a row from theta (see the header comment).
-__device__ __forceinline__ void set_filter(Row &r, float colmax)
-{
-    const float hv = (float)(0.5 * (double)(r.theta + r.slk + r.lamv + 1));
-    r.a = -2.0f * r.xv;
-    r.b = -2.0f * r.yv;
-    r.c = -2.0f * hv;
-    const float K = fmaf(r.xv, r.xv, fmaf(r.yv, r.yv, -hv * hv));
-    const float M = 2.0f * (r.xv * r.xv + r.yv * r.yv + hv * hv + colmax);
-    r.thr = M * 0x1p-18f - K;
-}
-
-__device__ __forceinline__ float filter_value(const Row &r, float4 cd)
-{
-    return fmaf(r.c, cd.z, fmaf(r.b, cd.y, fmaf(r.a, cd.x, cd.w)));
-}
-
-// max over columns of x^2 + y^2 plus the square of an upper bound on |hu|
-__device__ __forceinline__ float col_bound(float xy2max, long long maxabs_lam)
-{
-    const float hu = (float)(maxabs_lam / 2 + 1);
-    return xy2max + hu * hu;
-}
-
 // ---------------------------------------------------------------------------
 // block reductions
 // ---------------------------------------------------------------------------
@@ -232,25 +201,6 @@ __device__ __forceinline__ bool seeded_bound(const ScanArgs &a, int64_t p, float
     }
     *out = mx;
     return cnt == kTop;
-}
-
-// Culling test of a column box against a box of rows.  A pair (v, u) can
-// pass the scan only if 2c <= theta_v + Lam_v + Lam_u, and c >= sqrt(D) - 1/2,
-// so only if sqrt(D) <= hv + hu with hv = (theta_v + Lam_v + 1)/2 and
-// hu = Lam_u/2.  Every pair of the two boxes has D >= dx^2 + dy^2 (the
-// squared distance between the boxes); false means no pair can pass.  Box
-// corners are integers below 2^20 in magnitude, so dx and dy are exact;
-// hv and hu are float roundings of exact values, hence the widening of
-// hv + hu, and the 2^-16 relative margin covers the roundings of the two
-// squares.  Empty boxes (min +inf, max -inf) and hv = -inf never pass.
-__device__ __forceinline__ bool may_pass(float4 b, float4 rbox, float hv, float hu)
-{
-    const float dx = fmaxf(0.0f, fmaxf(b.x - rbox.y, rbox.x - b.y));
-    const float dy = fmaxf(0.0f, fmaxf(b.z - rbox.w, rbox.z - b.w));
-    float hs = hv + hu;
-    hs += 1e-6f * (fabsf(hv) + fabsf(hu)) + 1.0f;
-    if (!(hs > 0.0f)) return false;
-    return fmaf(dx, dx, dy * dy) <= hs * hs * (1.0f + 0x1p-16f);
 }
 
 // MODE kModeGdp: per row the four smallest (Z, label), #Z<0, #Z==0 and the
@@ -654,7 +604,9 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         rw.thr = -INFINITY;   // never passes
     }
     int lc = 0;   // list entries found (build)
-    const int64_t lbase = (4 * p + wave) * kLW;
+    // this lane's list: part `sid` of the S parts, entry i at
+    // lst[(sid * kLW + i) * n + p] (consecutive lanes, consecutive addresses)
+    const int64_t lbase = sid * kLW * n + p, lcidx = sid * n + p;
     __syncthreads();   // bany and cfill are set
 
     // the wave's rows: positions [w0, w1), their box (two sub-tile boxes
@@ -708,7 +660,7 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
             return;
         }
         if (build && z <= rw.theta + rw.slk) {
-            if (lc < kLW) a.lst[lbase + lc] = (int32_t)u;
+            if (lc < kLW) a.lst[lbase + (int64_t)lc * n] = (int32_t)u;
             ++lc;
         }
         if (z > rw.theta) return;
@@ -749,7 +701,7 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         // that can matter now: evaluate those only
         int cnt = 0;
         if (p < n) {
-            cnt = a.lcnt[4 * p + wave];
+            cnt = min(max(a.lcnt[lcidx], 0), kLW);
             // four entries' gathers in flight at a time
             for (int i0 = 0; i0 < cnt; i0 += 4) {
                 float4 cu[4];
@@ -758,7 +710,7 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (i0 + q < cnt) {
-                        const int64_t u = a.lst[lbase + i0 + q];
+                        const int64_t u = a.lst[lbase + (int64_t)(i0 + q) * n];
                         cu[q] = a.lv.col[u];
                         lu[q] = a.lv.lam[u];
                         ou[q] = a.g.orig[u];
@@ -888,7 +840,7 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
             if ((int64_t)(base + i) < a.cap) a.out[base + i] = cbuf[wave][i];
     }
     if (build && p < n) {
-        a.lcnt[4 * p + wave] = lc <= kLW ? lc : -1;
+        a.lcnt[lcidx] = lc <= kLW ? lc : -1;
         if (lc > kLW) const_cast<Ctrl *>(a.lv.ctrl)->list_over = 1;   // the next update rebuilds
     }
     if (MODE == kModeGdp && QUAD) {
@@ -1005,12 +957,9 @@ __device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &to
     if (copy_best) lam_best[p] = lam_out[p];
     lam_out[p] = nxt;
     if (col) {
-        float4 cv = col[p];
-        const float h = (float)(0.5 * (double)nxt);
-        cv.z = h;
-        cv.w = fmaf(cv.x, cv.x, fmaf(cv.y, cv.y, -h * h));
+        const float4 cv = col_record(col[p].x, col[p].y, nxt);
         col[p] = cv;
-        o.hmax = h;
+        o.hmax = cv.z;
     }
 #pragma unroll
     for (int j = 0; j < kTop; ++j) {
@@ -1033,15 +982,24 @@ __device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &to
     o.hsh = mix64((uint64_t)lamv ^ (0x9E3779B97F4A7C15ULL * (uint64_t)(v + 1)));
 }
 
-static_assert(offsetof(Ctrl, acc_maxabs_next) == offsetof(Ctrl, acc_sumlam) + 7 * sizeof(unsigned long long),
-              "the eight accumulators are consecutive 64-bit fields");
-// Block reductions of the rows' records, then the last block of the grid
-// writes the iteration record, takes the stop decision and clears the
-// accumulators.  Called by every thread of the block.
+// Block reductions of the rows' records into the block's slot, then the last
+// block to arrive sums the slots, writes the iteration record, takes the stop
+// decision and resets the arrival counters.  Called by every thread of the
+// block.  The slots are written and read with agent-scope atomic stores and
+// loads, ordered by release/acquire fences around the arrival counters; the
+// counters are split over kArriveGroups addresses (block b counts in group
+// b mod kArriveGroups, the last of a group counts once more in blocks_done),
+// so no address takes more than about nblk / kArriveGroups atomics.
+// `tested` is the block's count of scanned pairs (summed into
+// pairs_tested); `kinds` (or null) receives the scan kind of iteration k.
 __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t k, Ctrl *ctrl, int64_t *trace,
-                                                   float *tile_hmax, int64_t blk, int64_t nblk, bool lists = false)
+                                                   float *tile_hmax, int64_t blk, int64_t nblk,
+                                                   unsigned long long *slots, bool lists = false,
+                                                   unsigned long long tested = 0, int32_t *kinds = nullptr,
+                                                   long long *progress = nullptr)
 {
-    __shared__ unsigned long long red8[kBlock / 64][8];
+    constexpr int kV = 9;   // record entries reduced: 8 of the Ctrl order plus the pairs tested
+    __shared__ unsigned long long red8[kBlock / 64][kV];
     __shared__ float redf[kBlock / 64];
     __shared__ int s_last;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1052,44 +1010,73 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
         const float hm = block_reduce<float, true>(o.hmax, redf);
         if (threadIdx.x == 0) tile_hmax[blk * kBoxStride] = hm;
     }
-    // the record's eight accumulators in the order of the Ctrl fields
-    // acc_sumlam .. acc_maxabs_next; entries 4 and 7 are maxima, the rest sums
-    unsigned long long v[8] = {o.sumlam, o.rowneg, o.unsat, o.bad, (unsigned long long)o.maxstep, o.nonzero,
-                               o.hsh, (unsigned long long)o.maxabs};
+    // entries: sum Lam, sum rowneg, #unsat, #bad, max step, #nonzero, hash,
+    // max |Lam_{k+1}|, pairs tested; entries 4 and 7 are maxima, the rest sums
+    unsigned long long v[kV] = {o.sumlam, o.rowneg, o.unsat, o.bad, (unsigned long long)o.maxstep, o.nonzero,
+                                o.hsh, (unsigned long long)o.maxabs, threadIdx.x == 0 ? tested : 0ULL};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = (i == 4 || i == 7) ? wave_max(v[i]) : wave_sum(v[i]);
+    for (int i = 0; i < kV; ++i) v[i] = (i == 4 || i == 7) ? wave_max(v[i]) : wave_sum(v[i]);
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) red8[w][i] = v[i];
+        for (int i = 0; i < kV; ++i) red8[w][i] = v[i];
     }
     __syncthreads();
-    unsigned long long *acc = &ctrl->acc_sumlam;
     if (w == 0) {
-        // lanes 0..7 each carry one accumulator to the control block
-        unsigned long long mine = 0;
-        if (lane < 8) {
-            mine = red8[0][lane];
+        if (lane < kV) {
+            unsigned long long mine = red8[0][lane];
             for (int q = 1; q < kBlock / 64; ++q) {
                 const unsigned long long x = red8[q][lane];
                 mine = (lane == 4 || lane == 7) ? (x > mine ? x : mine) : mine + x;
             }
-            if (lane == 4 || lane == 7) atomicMax(&acc[lane], mine);
-            else atomicAdd(&acc[lane], mine);
+            __hip_atomic_store(&slots[blk * kSlotW + lane], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (lane == 0) {
-            const unsigned prev = atomicAdd(&ctrl->blocks_done, 1u);
-            s_last = (prev == (unsigned)(nblk - 1));
+            const int64_t g = blk % kArriveGroups;
+            const int64_t ng = nblk < kArriveGroups ? nblk : kArriveGroups;
+            const unsigned gsize = (unsigned)((nblk - g + kArriveGroups - 1) / kArriveGroups);
+            int last = 0;
+            if (atomicAdd(&ctrl->grp_done[32 * g], 1u) == gsize - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                last = atomicAdd(&ctrl->blocks_done, 1u) == (unsigned)(ng - 1);
+                if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            s_last = last;
         }
     }
     __syncthreads();
-    if (!s_last || w != 0) return;
+    if (!s_last) return;
 
-    // last block: every other block's atomics are visible; lanes 0..7 read
-    // the accumulators together
-    __threadfence();
+    // last block: every block's slot is written; all threads sum them
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    unsigned long long acc[kV];
+#pragma unroll
+    for (int i = 0; i < kV; ++i) acc[i] = 0;
+    for (int64_t b = threadIdx.x; b < nblk; b += kBlock) {
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const unsigned long long x =
+                __hip_atomic_load(&slots[b * kSlotW + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc[i] = (i == 4 || i == 7) ? (x > acc[i] ? x : acc[i]) : acc[i] + x;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kV; ++i) acc[i] = (i == 4 || i == 7) ? wave_max(acc[i]) : wave_sum(acc[i]);
+    __syncthreads();   // red8 is free again
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < kV; ++i) red8[w][i] = acc[i];
+    }
+    __syncthreads();
+    if (w != 0) return;
     unsigned long long got = 0;
-    if (lane < 8) got = atomicAdd(&acc[lane], 0ULL);
+    if (lane < kV) {
+        got = red8[0][lane];
+        for (int q = 1; q < kBlock / 64; ++q) {
+            const unsigned long long x = red8[q][lane];
+            got = (lane == 4 || lane == 7) ? (x > got ? x : got) : got + x;
+        }
+    }
     const long long sl = (long long)__shfl(got, 0, 64);
     const long long rnsum = (long long)__shfl(got, 1, 64);
     const long long un = (long long)__shfl(got, 2, 64);
@@ -1098,12 +1085,16 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
     const long long nz = (long long)__shfl(got, 5, 64);
     const unsigned long long hh = __shfl(got, 6, 64);
     const long long mx = (long long)__shfl(got, 7, 64);
-    if (lane < 8) atomicExch(&acc[lane], 0ULL);
+    const unsigned long long tt = __shfl(got, 8, 64);
+    if (lane < kArriveGroups) ctrl->grp_done[32 * lane] = 0u;
     if (lane == 0) {
+        ctrl->blocks_done = 0u;
+        ctrl->pairs_tested += tt;
         // each unordered pair sits in two rows
         const long long dual2 = 2 * sl + rnsum / 2;
-        if (trace && k < ctrl->trace_cap) {
-            long long *rec = (long long *)trace + kTraceW * k;
+        const long long kr = k - ctrl->k_first;   // record index of iteration k
+        if (trace && kr < ctrl->trace_cap) {
+            long long *rec = (long long *)trace + kTraceW * kr;
             rec[0] = k; rec[1] = dual2; rec[2] = un; rec[3] = bd;
             rec[4] = ms; rec[5] = nz; rec[6] = (long long)hh; rec[7] = sl;
         }
@@ -1112,16 +1103,20 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
         if (bd == 0) stop = 1;                                                      // trivial
         else if (ctrl->handoff_div > 0 && un * ctrl->handoff_div <= n) stop = 5;    // handoff
         else if (nz == 0) stop = 2;                                                 // fixed
-        else if (k >= 2 && hh == ctrl->h2) stop = 3;                                // cycle
+        else if (k >= 2 && (kr >= 2 || ctrl->hvalid) && hh == ctrl->h2) stop = 3;  // cycle
         else if (k >= ctrl->max_iters) stop = 4;                                    // cap
         else if (mx >= kLamLimit) { stop = 4; ctrl->overflow = 1; }
+        int32_t kind = kScanFull;
         if (lists) {
             // Z moves by at most twice the max step per iteration: lists
             // built with margin 2D stay exact while the steps since the
             // build sum to at most D / 2
-            if (k == 0) ctrl->list_ms0 = ms;
+            if (kr == 0) ctrl->list_ms0 = ms;
             const bool used = ctrl->list_ok != 0;
             const bool built = !used && ctrl->list_D > 0;
+            kind = used ? kScanList : (built ? kScanBuild : kScanFull);
+            ctrl->list_uses += used ? 1 : 0;
+            ctrl->list_builds += built ? 1 : 0;
             const long long d = used ? ctrl->list_d + ms : ms;
             const bool ok = (used || (built && !ctrl->list_over)) && 2 * d <= ctrl->list_D;
             ctrl->list_ok = ok ? 1 : 0;
@@ -1135,6 +1130,8 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
                 ctrl->list_over = 0;
             }
         }
+        if (kinds && kr < ctrl->trace_cap) kinds[kr] = kind;
+        ctrl->pairs_kind[kind] += tt;
         ctrl->k_last = k;
         ctrl->dual2_last = dual2;
         if (stop) {
@@ -1147,9 +1144,10 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
             ctrl->k_next = k + 1;
         }
         ctrl->maxabs_lam = mx;
+        // the host waits on this word instead of synchronising the stream
+        if (progress)
+            __hip_atomic_store(progress, 2 * k + (stop ? 1 : 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    __threadfence();
-    if (lane == 0) atomicExch(&ctrl->blocks_done, 0u);
 }
 
 // complete graph: merge the slices' partials, step, reduce, stop test
@@ -1157,14 +1155,13 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
                                             const int64_t nblk)
 {
     Ctrl *ctrl = a.ctrl;
+    unsigned long long tt = 0;
     if (a.tpart && threadIdx.x == 0) {
         // the scan's pairs tested in this block's rows (groups of 64)
         const int64_t groups = (a.g.n + 63) / 64;
-        unsigned long long tt = 0;
         for (int64_t s = 0; s < a.nslices; ++s)
             for (int64_t g = blk * (kBlock / 64); g < min(groups, (blk + 1) * (kBlock / 64)); ++g)
                 tt += a.tpart[s * groups + g];
-        if (tt) atomicAdd(&ctrl->pairs_tested, tt);
     }
     const int64_t n = a.g.n;
     const int64_t p = blk * kBlock + threadIdx.x;
@@ -1205,7 +1202,8 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
         step_row(a.g, p, top, cn, cz, rn, a.lam_in[p], copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
                  a.neg, a.zero, a.step, a.col, o);
     }
-    reduce_and_control(o, n, k, ctrl, a.trace, a.tile_hmax, blk, nblk, a.lists != 0);
+    reduce_and_control(o, n, k, ctrl, a.trace, a.tile_hmax, blk, nblk, a.slots, a.lists != 0, tt, a.scan_kind,
+                       a.progress);
 }
 
 __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
@@ -1273,7 +1271,8 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
         step_row(a.g, p, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, nullptr,
                  a.neg, a.zero, a.step, nullptr, o);
     }
-    reduce_and_control(o, n, a.k, ctrl, a.trace, nullptr, blockIdx.x, gridDim.x);
+    reduce_and_control(o, n, a.k, ctrl, a.trace, nullptr, blockIdx.x, gridDim.x, a.slots, false, 0, nullptr,
+                       a.progress);
 }
 
 // ---------------------------------------------------------------------------
@@ -1723,7 +1722,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(const int32_t *xy, const int32_
         y = (float)(xy[2 * v + 1] - cy);
         col[p] = make_float4(x, y, 0.0f, x * x + y * y);
         // round the bound up by a relative 2^-22 so it is >= the exact value
-        r2 = fmaf(x, x, y * y) * (1.0f + 0x1p-22f) + 1.0f;
+        r2 = xy2_bound(x, y);
     }
     // sub-tile boxes (an empty sub-tile gets an empty box: min +inf, max -inf)
     const float smnx = -sub_max(ok ? -x : -INFINITY), smxx = sub_max(ok ? x : -INFINITY);
@@ -1752,10 +1751,8 @@ __global__ __launch_bounds__(kBlock) void k_set_lam(const int64_t *lam_label, co
     if (p < n) {
         const int64_t l = orig ? lam_label[orig[p]] : lam_label[p];
         lam_sorted[p] = l;
-        float4 cv = col[p];
-        h = (float)(0.5 * (double)l);
-        cv.z = h;
-        cv.w = fmaf(cv.x, cv.x, fmaf(cv.y, cv.y, -h * h));
+        const float4 cv = col_record(col[p].x, col[p].y, l);
+        h = cv.z;
         col[p] = cv;
         ab = (unsigned long long)(l < 0 ? -l : l);
     }
@@ -1852,7 +1849,7 @@ __global__ __launch_bounds__(kBlock) void k_seed_neighbours(int64_t n, const flo
     for (int j = 0; j < kTop; ++j) seed[j * n + p] = bq[j];
 }
 
-__global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div)
+__global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div, CtrlStart cs)
 {
     if (threadIdx.x != 0) return;
     Ctrl c;
@@ -1865,6 +1862,11 @@ __global__ void k_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, in
     c.max_iters = max_iters;
     c.trace_cap = trace_cap;
     c.handoff_div = handoff_div;
+    c.k_first = cs.k0;
+    c.k_next = cs.k0;
+    c.hvalid = cs.hvalid;
+    c.h1 = cs.h1;
+    c.h2 = cs.h2;
     *ctrl = c;
 }
 
@@ -2098,9 +2100,10 @@ hipError_t launch_seed_neighbours(int64_t n, const float4 *col, int32_t *seed, h
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div, hipStream_t st)
+hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, int64_t handoff_div,
+                            const CtrlStart &cs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, max_iters, trace_cap, handoff_div);
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, st, ctrl, max_iters, trace_cap, handoff_div, cs);
     return hipGetLastError();
 }
 

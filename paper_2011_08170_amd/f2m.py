@@ -22,6 +22,7 @@ STATUS = {0: "ok", 1: "not certified", -1: "invalid argument", -2: "coordinate s
 STOP_NAMES = {0: "none", 1: "trivial", 2: "fixed", 3: "cycle", 4: "cap", 5: "handoff"}
 FINISH = {"none": 0, "exact": 1}
 SCAN = {"culled": 0, "full": 1}
+SCAN_KIND_FULL, SCAN_KIND_BUILD, SCAN_KIND_LIST = 0, 1, 2
 TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
 SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
@@ -46,7 +47,9 @@ class Opts(C.Structure):
                 ("handoff_div", C.c_int64),
                 ("finish", C.c_int32), ("coords_on_device", C.c_int32), ("record_trace", C.c_int32),
                 ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("scan_mode", C.c_int32),
-                ("scan_rows", C.c_int32), ("scan_slices", C.c_int32), ("hip_stream", C.c_void_p)]
+                ("scan_rows", C.c_int32), ("scan_slices", C.c_int32), ("hip_stream", C.c_void_p),
+                ("k0", C.c_int64), ("resume_hash", C.c_uint64 * 2), ("resume_hash_valid", C.c_int32),
+                ("pad_opts", C.c_int32), ("max_device_bytes", C.c_uint64), ("tuner_cache", C.c_char_p)]
 
 
 class Result(C.Structure):
@@ -61,7 +64,11 @@ class Result(C.Structure):
                 ("pad0", C.c_int32), ("scan_slices", C.c_int64), ("scan_pairs", C.c_int64),
                 ("finish_phases", C.c_int64), ("finish_candidates", C.c_int64), ("finish_seconds", C.c_double * 3),
                 ("dual2_complete", C.c_int64), ("certified_complete", C.c_int32), ("pad1", C.c_int32),
-                ("graph_nnz", C.c_int64), ("warm_iterations", C.c_int64)]
+                ("graph_nnz", C.c_int64), ("warm_iterations", C.c_int64),
+                ("scan_kind", C.POINTER(C.c_int32)), ("scan_list_uses", C.c_int64),
+                ("scan_list_builds", C.c_int64), ("lambda2_last", C.POINTER(C.c_int64)),
+                ("scan_ms_kind", C.c_double * 3), ("scan_launches_kind", C.c_int64 * 3),
+                ("scan_pairs_kind", C.c_int64 * 3)]
 
 
 _lib = None
@@ -86,7 +93,7 @@ def lib():
         L.f2m_opts_default.restype = None
         L.f2m_opts_default.argtypes = [C.POINTER(Opts)]
         L.f2m_create.restype = C.c_int
-        L.f2m_create.argtypes = [C.POINTER(C.c_void_p), C.c_int]
+        L.f2m_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(Opts)]
         L.f2m_destroy.restype = None
         L.f2m_destroy.argtypes = [p]
         L.f2m_solve.restype = C.c_int
@@ -140,6 +147,7 @@ def _result_dict(res, n, st):
         dual2_gdp=res.dual2_gdp, finish_paths=res.finish_paths, finish_rounds=res.finish_rounds,
         lambda2=np.ctypeslib.as_array(res.lambda2, (n,)).copy(),
         lambda2_gdp=np.ctypeslib.as_array(res.lambda2_gdp, (n,)).copy(),
+        lambda2_last=(np.ctypeslib.as_array(res.lambda2_last, (n,)).copy() if res.lambda2_last else None),
         edge_u=np.ctypeslib.as_array(res.edge_u, (max(m, 1),))[:m].copy(),
         edge_v=np.ctypeslib.as_array(res.edge_v, (max(m, 1),))[:m].copy(),
         edge_x2=np.ctypeslib.as_array(res.edge_x2, (max(m, 1),))[:m].copy(),
@@ -150,19 +158,29 @@ def _result_dict(res, n, st):
         finish_seconds=dict(zip(("collect", "build", "flow"), list(res.finish_seconds))),
         dual2_complete=res.dual2_complete, certified_complete=bool(res.certified_complete),
         graph_nnz=res.graph_nnz, warm_iterations=res.warm_iterations,
+        scan_list_uses=res.scan_list_uses, scan_list_builds=res.scan_list_builds,
+        scan_by_kind={name: dict(ms=res.scan_ms_kind[q], launches=res.scan_launches_kind[q],
+                                 pairs=res.scan_pairs_kind[q])
+                      for q, name in enumerate(("full", "build", "list"))},
     )
     if res.trace_len:
         out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(
             res.trace_len, TRACE_W).copy()
+        if res.scan_kind:
+            out["scan_kind"] = np.ctypeslib.as_array(res.scan_kind, (res.trace_len,)).copy()
     return out
 
 
 class Context:
     """One libf2m context (device + stream)."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, max_device_bytes: int = 0):
         self._h = C.c_void_p()
-        st = lib().f2m_create(C.byref(self._h), int(device))
+        self._max_dev = int(max_device_bytes)
+        d = Opts()
+        lib().f2m_opts_default(C.byref(d))
+        d.max_device_bytes = int(max_device_bytes)
+        st = lib().f2m_create(C.byref(self._h), int(device), C.byref(d))
         if st != OK:
             raise F2MError(st, "f2m_create(device=%d) failed" % device)
 
@@ -190,7 +208,8 @@ class Context:
 
     def solve(self, coords, *, max_iters=100000, handoff_div=HANDOFF_DIV, finish="exact", lambda2_init=None,
               trace=False, chunk=0, stream=None, time_kernels=False, scan="culled", graph="complete", knn_k=10,
-              shape=None, mlp_theta=None, warm=None):
+              shape=None, mlp_theta=None, warm=None, k0=0, resume_hash=None, max_device_bytes=None,
+              tuner_cache=None):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
         array on the host or a contiguous int32 device tensor."""
         o = Opts()
@@ -206,7 +225,17 @@ class Context:
         o.knn_k = int(knn_k)
         if shape is not None:
             o.scan_rows, o.scan_slices = int(shape[0]), int(shape[1])
+        o.k0 = int(k0)
+        if resume_hash is not None:
+            o.resume_hash[0] = int(resume_hash[0]) & ((1 << 64) - 1)
+            o.resume_hash[1] = int(resume_hash[1]) & ((1 << 64) - 1)
+            o.resume_hash_valid = 1
+        o.max_device_bytes = self._max_dev if max_device_bytes is None else int(max_device_bytes)
         keep = []
+        if tuner_cache is not None:
+            tc = os.fsencode(tuner_cache)
+            keep.append(tc)
+            o.tuner_cache = tc
         if lambda2_init is not None:
             l0 = _np(lambda2_init, np.int64)
             keep.append(l0)
@@ -273,9 +302,9 @@ class Context:
         """One GDP iteration on device tensors; returns the record dict."""
         n = coords.shape[0]
         rec = np.zeros(TRACE_W, np.int64)
-        self._check(lib().f2m_gdp_step(self._h, _dptr(coords), n, _dptr(lam_in), _dptr(lam_out), _dptr(z4),
-                                       _dptr(i4), _dptr(neg), _dptr(zero), _dptr(step),
-                                       rec.ctypes.data_as(C.c_void_p)))
+        fn = lib().f2m_gdp_step
+        self._check(fn(self._h, _dptr(coords), n, _dptr(lam_in), _dptr(lam_out), _dptr(z4),
+                       _dptr(i4), _dptr(neg), _dptr(zero), _dptr(step), rec.ctypes.data_as(C.c_void_p)))
         r = dict(zip(TRACE_FIELDS, (int(x) for x in rec)))
         r["hash"] &= (1 << 64) - 1
         return r

@@ -179,3 +179,76 @@ def test_c2_shape_sampled_rows(ctx):
         assert np.array_equal(g["step"][rows], o["step"])
         assert rec["sum_lam"] == int(lam.sum())
         assert rec["hash"] == core.lam_hash(lam)
+
+
+def test_sliced_culled_scan_with_lists_matches_oracle(ctx):
+    # the culled scan split over several column slices keeps a candidate list
+    # per slice: the trajectory equals the oracle's and the one-slice run's,
+    # and list scans really ran
+    from paper_2011_08170_amd import f2m
+    xy = I.uniform(8000, 1000000, 21)
+    o = core.gdp_solve(xy, handoff_div=f2m.HANDOFF_DIV)
+    for shape in ((1, 1), (1, 4), (1, 3)):
+        g = ctx.solve(xy, trace=True, finish="none", shape=shape)
+        assert g["scan_slices"] == shape[1]
+        assert g["scan_list_uses"] > 0 and (g["scan_kind"] == f2m.SCAN_KIND_LIST).sum() == g["scan_list_uses"]
+        assert g["iterations"] == o["iters"] and g["stop"] == o["stop"] and g["kstar"] == o["kstar"]
+        assert np.array_equal(g["trace"], o["trace"]), shape
+        assert np.array_equal(g["lambda2_gdp"], o["lam"]), shape
+
+
+def test_cycle_stop_matches_oracle(ctx):
+    # 2-cycles of the rule (tests/golden/cycle_case.json): the GPU loop stops
+    # with "cycle" at the same iteration, with the same largest-dual Lam*
+    import json
+    import os
+    cases = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cycle_case.json")))["cases"]
+    for c in cases:
+        xy = np.array(c["coords"], np.int32)
+        lam0 = np.array(c["lam0"], np.int64)
+        o = core.gdp_solve(xy, lam0=lam0, max_iters=200, handoff_div=0)
+        for scan in ("culled", "full"):
+            g = ctx.solve(xy, lambda2_init=lam0, trace=True, finish="none", handoff_div=0, max_iters=200,
+                          scan=scan)
+            assert g["stop"] == "cycle" == o["stop"]
+            assert g["iterations"] == o["iters"] == c["stop_k"] + 1 and g["kstar"] == o["kstar"] == c["kstar"]
+            assert np.array_equal(g["trace"], o["trace"])
+            assert np.array_equal(g["lambda2_gdp"], o["lam"])
+
+
+def test_resume_from_checkpoint_bitwise(ctx):
+    # run to iteration K (cap), resume from lambda2_last with k0 = K and the
+    # two previous hashes: records, stop, k*, Lam* and the certified result
+    # equal the uninterrupted run's
+    xy = I.clustered(6000, 1000000, 31)
+    full = ctx.solve(xy, trace=True)
+    K = full["iterations"] // 2
+    part = ctx.solve(xy, trace=True, max_iters=K, finish="none")
+    assert part["stop"] == "cap" and np.array_equal(part["trace"], full["trace"][:K + 1])
+    h = (int(full["trace"][K - 1, 6]), int(full["trace"][K - 2, 6]))
+    res = ctx.solve(xy, trace=True, lambda2_init=part["lambda2_last"], k0=K, resume_hash=h)
+    assert res["stop"] == full["stop"] and res["kstar"] == full["kstar"]
+    assert res["iterations"] == full["iterations"] - K
+    assert np.array_equal(res["trace"], full["trace"][K:])
+    for k in ("lambda2_gdp", "lambda2", "edge_u", "edge_v", "edge_x2"):
+        assert np.array_equal(res[k], full[k]), k
+    assert res["certified"] and res["primal2"] == full["primal2"]
+
+
+def test_device_memory_cap(ctx):
+    from paper_2011_08170_amd import f2m
+    xy = I.uniform(20000, 1000000, 41)
+    with f2m.Context(0, max_device_bytes=1 << 20) as small:
+        with pytest.raises(f2m.F2MError) as e:
+            small.solve(xy)
+        assert e.value.status == -4
+    # a per-call cap on a context that already holds more also refuses to grow
+    g = ctx.solve(xy, max_device_bytes=1 << 40)
+    assert g["certified"]
+
+
+def test_c1_lists_ran(ctx):
+    xy = I.uniform(1000, 100000, 1)
+    g = ctx.solve(xy, trace=True, finish="none")
+    print("C1 list scans", g["scan_list_uses"], "builds", g["scan_list_builds"], flush=True)
+    assert g["scan_list_builds"] > 0
