@@ -39,13 +39,13 @@ def lib():
         L.or_hash.restype = C.c_uint64; L.or_hash.argtypes = [i64, p]
         L.or_check_coords.restype = C.c_int; L.or_check_coords.argtypes = [p, i64]
         L.or_gdp_rows.restype = None
-        L.or_gdp_rows.argtypes = [i64, p, p, p, p, i64, p, p, p, p, p, p, p]
+        L.or_gdp_rows.argtypes = [i64, p, p, p, p, p, i64, p, p, p, p, p, p, p]
         L.or_gdp_iter.restype = C.c_int
-        L.or_gdp_iter.argtypes = [i64, p, p, p, p, p, p, p, p, p, p]
+        L.or_gdp_iter.argtypes = [i64, p, p, p, p, p, p, p, p, p, p, p]
         L.or_gdp_solve.restype = C.c_int
-        L.or_gdp_solve.argtypes = [i64, p, p, p, p, i64, i64, p, p, p, p, p, p, p, p]
+        L.or_gdp_solve.argtypes = [i64, p, p, p, p, p, i64, i64, p, p, p, p, p, p, p, p]
         L.or_certify.restype = C.c_int
-        L.or_certify.argtypes = [i64, p, p, p, p, i64, p, p, p, p]
+        L.or_certify.argtypes = [i64, p, p, p, p, p, i64, p, p, p, p]
         L.or_knn.restype = C.c_int
         L.or_knn.argtypes = [i64, p, i64, p]
         L.or_knn_rows.restype = C.c_int
@@ -53,7 +53,7 @@ def lib():
         L.or_trivial_x.restype = i64
         L.or_trivial_x.argtypes = [i64, p, p, i64, p, p, p]
         L.or_exact_opt2.restype = C.c_int
-        L.or_exact_opt2.argtypes = [i64, p, p, p, p, p, p]
+        L.or_exact_opt2.argtypes = [i64, p, p, p, p, p, p, p]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -108,9 +108,19 @@ def check_coords(xy) -> int:
     return int(lib().or_check_coords(_ptr(xy), xy.shape[0]))
 
 
-def gdp_rows(xy, lam, rows, graph=None):
+def _degrees(b, n):
+    """Per-node right-hand sides b_v as int32 (None: F2M, every b_v = 2)."""
+    if b is None:
+        return None
+    b = np.ascontiguousarray(b, dtype=np.int32)
+    assert b.shape == (n,)
+    return b
+
+
+def gdp_rows(xy, lam, rows, graph=None, b=None):
     """Per-row GDP quantities at Lam for the listed rows (on `graph`, a
-    (rowptr, col) CSR candidate graph, or the complete graph).
+    (rowptr, col) CSR candidate graph, or the complete graph; b: per-node
+    degrees, None for F2M).
     Returns dict: z4 (r,4) int64, i4 (r,4) int32, neg, zero (int32),
     rowneg, step (int64)."""
     xy = _coords(xy)
@@ -122,12 +132,14 @@ def gdp_rows(xy, lam, rows, graph=None):
                neg=np.empty(r, np.int32), zero=np.empty(r, np.int32),
                rowneg=np.empty(r, np.int64), step=np.empty(r, np.int64))
     rp, cl = _graph(graph)
-    lib().or_gdp_rows(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), r, _ptr(rows), _ptr(out["z4"]), _ptr(out["i4"]),
+    bb = _degrees(b, n)
+    lib().or_gdp_rows(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), _ptr(bb), r, _ptr(rows), _ptr(out["z4"]),
+                      _ptr(out["i4"]),
                       _ptr(out["neg"]), _ptr(out["zero"]), _ptr(out["rowneg"]), _ptr(out["step"]))
     return out
 
 
-def gdp_iter(xy, lam, graph=None):
+def gdp_iter(xy, lam, graph=None, b=None):
     """One full GDP evaluation at Lam: per-node arrays plus the record
     (dict keyed by TRACE_FIELDS; 'k' is 0)."""
     xy = _coords(xy)
@@ -137,8 +149,9 @@ def gdp_iter(xy, lam, graph=None):
     neg = np.empty(n, np.int32); zero = np.empty(n, np.int32); st = np.empty(n, np.int64)
     rec = np.zeros(TRACE_W, np.int64)
     rp, cl = _graph(graph)
-    rc = lib().or_gdp_iter(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), _ptr(z4), _ptr(i4), _ptr(neg), _ptr(zero),
-                           _ptr(st), _ptr(rec))
+    bb = _degrees(b, n)
+    rc = lib().or_gdp_iter(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), _ptr(bb), _ptr(z4), _ptr(i4), _ptr(neg),
+                           _ptr(zero), _ptr(st), _ptr(rec))
     if rc:
         raise RuntimeError("or_gdp_iter failed: %d" % rc)
     r = dict(zip(TRACE_FIELDS, (int(x) for x in rec)))
@@ -146,7 +159,7 @@ def gdp_iter(xy, lam, graph=None):
     return dict(z4=z4, i4=i4, neg=neg, zero=zero, step=st, rec=r)
 
 
-def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0, graph=None):
+def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0, graph=None, b=None):
     """GDP rule loop (handoff_div > 0: stop once #unsatisfied*div <= n).
     Returns dict: lam (Lam*), stop (name), iters,
     kstar, trace (iters x TRACE_W int64), z4/i4/neg/zero at the last
@@ -159,7 +172,8 @@ def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0, graph=None):
     z4 = np.empty((n, 4), np.int64); i4 = np.empty((n, 4), np.int32)
     neg = np.empty(n, np.int32); zero = np.empty(n, np.int32)
     rp, cl = _graph(graph)
-    rc = lib().or_gdp_solve(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), int(max_iters), int(handoff_div),
+    bb = _degrees(b, n)
+    rc = lib().or_gdp_solve(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(bb), _ptr(lam), int(max_iters), int(handoff_div),
                             _ptr(trace), C.byref(iters),
                             C.byref(stop), C.byref(kstar), _ptr(z4), _ptr(i4), _ptr(neg), _ptr(zero))
     if rc:
@@ -169,7 +183,7 @@ def gdp_solve(xy, lam0=None, max_iters=100000, handoff_div=0, graph=None):
                 trace=trace[:k].copy(), z4=z4, i4=i4, neg=neg, zero=zero)
 
 
-def certify(xy, lam, eu, ev, ex2, graph=None):
+def certify(xy, lam, eu, ev, ex2, graph=None, b=None):
     """Returns dict(primal2, dual2, feasible, certified) on `graph` (the
     complete graph by default)."""
     xy = _coords(xy)
@@ -180,8 +194,9 @@ def certify(xy, lam, eu, ev, ex2, graph=None):
     ex2 = np.ascontiguousarray(ex2, dtype=np.uint8)
     out = np.zeros(4, np.int64)
     rp, cl = _graph(graph)
-    rc = lib().or_certify(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(lam), eu.size, _ptr(eu), _ptr(ev), _ptr(ex2),
-                          _ptr(out))
+    bb = _degrees(b, n)
+    rc = lib().or_certify(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(bb), _ptr(lam), eu.size, _ptr(eu), _ptr(ev),
+                          _ptr(ex2), _ptr(out))
     if rc:
         raise RuntimeError("or_certify failed: %d" % rc)
     return dict(primal2=int(out[0]), dual2=int(out[1]), feasible=bool(out[2]), certified=bool(out[3]))
@@ -200,7 +215,7 @@ def trivial_x(xy, lam, cap=None):
     return eu[:m].copy(), ev[:m].copy(), ex2[:m].copy()
 
 
-def exact_opt2(xy, want_x=False, graph=None):
+def exact_opt2(xy, want_x=False, graph=None, b=None):
     """2 * F2M optimum by min-cost flow on the double cover.  With want_x,
     returns (opt2, x2, lam): the optimal x as a dense (n, n) uint8 matrix of
     x2 = 2x and an optimal Lam = 2*lambda from the flow's potentials."""
@@ -210,7 +225,10 @@ def exact_opt2(xy, want_x=False, graph=None):
     x2 = np.zeros((n, n), np.uint8) if want_x else None
     lam = np.zeros(n, np.int64) if want_x else None
     rp, cl = _graph(graph)
-    rc = lib().or_exact_opt2(n, _ptr(xy), _ptr(rp), _ptr(cl), C.byref(out), _ptr(x2), _ptr(lam))
+    bb = _degrees(b, n)
+    rc = lib().or_exact_opt2(n, _ptr(xy), _ptr(rp), _ptr(cl), _ptr(bb), C.byref(out), _ptr(x2), _ptr(lam))
+    if rc == -3:
+        return (None, None, None) if want_x else None
     if rc:
         raise RuntimeError("or_exact_opt2 failed: %d" % rc)
     return (out.value, x2, lam) if want_x else out.value

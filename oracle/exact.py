@@ -1,4 +1,6 @@
-"""Pure-Python exact checkers for the F2M optimum (Sec. 4).
+"""Pure-Python exact checkers for the F2M optimum (Sec. 4) and for its
+generalisation to per-node degrees b_v (fractional b-matching: rows with
+binary coefficients and integral right-hand sides, Sec. 3, condition 8).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -41,9 +43,16 @@ def graph_edges(graph, n):
     return [(u, int(v)) for u in range(n) for v in col[rowptr[u]:rowptr[u + 1]] if u < v]
 
 
-def brute_force_opt2(xy, graph=None):
-    """2 * min c.x over x in {0,1/2,1}^E with every degree 2; None if none."""
+def _rhs(b, n):
+    return [2] * n if b is None else [int(x) for x in b]
+
+
+def brute_force_opt2(xy, graph=None, b=None):
+    """2 * min c.x over x in {0,1/2,1}^E with every degree b_v (2 when b is
+    None); None if none.  Some optimal vertex is half-integral (the double
+    cover argument holds for any b), so the enumeration is exact."""
     n = len(xy)
+    need = [2 * x for x in _rhs(b, n)]   # doubled degrees
     E = graph_edges(graph, n)
     c = [euc2d(xy, u, v) for (u, v) in E]
     deg = [0] * n              # doubled degrees so far
@@ -58,16 +67,16 @@ def brute_force_opt2(xy, graph=None):
         if best[0] is not None and acc >= best[0]:
             return
         if i == len(E):
-            if all(d == 4 for d in deg):
+            if all(d == t for d, t in zip(deg, need)):
                 best[0] = acc
             return
         u, v = E[i]
         left[u] -= 1; left[v] -= 1
         for x2 in (0, 1, 2):
             du, dv = deg[u] + x2, deg[v] + x2
-            if du > 4 or dv > 4:
+            if du > need[u] or dv > need[v]:
                 continue
-            if du + 2 * left[u] < 4 or dv + 2 * left[v] < 4:
+            if du + 2 * left[u] < need[u] or dv + 2 * left[v] < need[v]:
                 continue
             deg[u], deg[v] = du, dv
             rec(i + 1, acc + x2 * c[i])
@@ -78,10 +87,11 @@ def brute_force_opt2(xy, graph=None):
     return best[0]
 
 
-def simplex_opt2(xy, max_pivots=200000):
+def simplex_opt2(xy, max_pivots=200000, b=None):
     """Exact optimum * 2 by a bounded-variable simplex over Fractions.
 
-    Standard form: rows A x = b (one per node, b = 2), 0 <= x <= 1.  Phase 1
+    Standard form: rows A x = b (one per node, b_v = 2 unless given),
+    0 <= x <= 1.  Phase 1
     adds one artificial per row (x_a >= 0, no upper bound) and minimises
     their sum; phase 2 minimises c.x.  Nonbasic variables sit at 0 or at
     their upper bound; entering/leaving by Bland's rule (smallest index)."""
@@ -101,7 +111,7 @@ def simplex_opt2(xy, max_pivots=200000):
         A[i][m + i] = Fraction(1)
     basis = [m + i for i in range(n)]
     at_upper = [False] * nv
-    xB = [Fraction(2)] * n           # values of basic variables
+    xB = [Fraction(r) for r in _rhs(b, n)]   # values of basic variables
 
     def run(obj, allowed):
         pivots = 0
@@ -186,7 +196,7 @@ def simplex_opt2(xy, max_pivots=200000):
     return int(2 * val)
 
 
-def highs_opt2(xy, graph=None):
+def highs_opt2(xy, graph=None, b=None):
     """2 * optimum from scipy's HiGHS LP solver (a library cross-check;
     the optimum is a half-integer, recovered by rounding 2*fun)."""
     from scipy.optimize import linprog
@@ -198,6 +208,8 @@ def highs_opt2(xy, graph=None):
     rows = np.array([u for u, v in E] + [v for u, v in E])
     cols = np.concatenate([np.arange(m), np.arange(m)])
     A = coo_matrix((np.ones(2 * m), (rows, cols)), shape=(n, m)).tocsr()
-    r = linprog(c, A_eq=A, b_eq=2 * np.ones(n), bounds=(0, 1), method="highs")
+    r = linprog(c, A_eq=A, b_eq=np.array(_rhs(b, n), dtype=float), bounds=(0, 1), method="highs")
+    if r.status == 2:
+        return None
     assert r.status == 0
     return int(round(2 * r.fun))

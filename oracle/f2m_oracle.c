@@ -30,6 +30,17 @@
  * units  dual2 = 2*L = 2*sum Lam + sum_{u<v} min(0, Z_uv).  For any feasible
  * x, c.x >= L (weak duality); equality certifies optimality.
  *
+ * Rows with other right-hand sides (Sec. 3: the method applies to LP3 rows
+ * with binary coefficients and an integral b_i, condition 8): every routine
+ * takes an optional per-node degree b_v (NULL: 2, the F2M of Sec. 4), so the
+ * problem is the fractional b-matching  sum_{e in delta(v)} x_e = b_v,
+ * 0 <= x <= 1.  The row's gradient then compares positions b_v and b_v + 1
+ * of its sorted adjusted lengths (Sec. 3), the step is
+ * sign(s) floor((|s| + 2)/4) with s = Z_(b) + Z_(b+1), the trivial doubled
+ * degree must equal 2 b_v, and the dual bound is sum_v b_v lambda_v +
+ * sum_e min(0, v^e), i.e. dual2 = sum_v b_v Lam_v + sum_{u<v} min(0, Z).
+ * The top four are kept per row, so b_v is 1, 2 or 3.
+ *
  * Candidate graphs (Sec. 5.3: "the top N closest neighbors for each node"):
  * every routine takes an optional CSR graph (rowptr[n+1], col[]), symmetric,
  * no self loops; NULL means the complete graph.  On a graph, a row's
@@ -38,8 +49,8 @@
  *
  * The exact optimum (used to pin the GDP and the finisher) comes from the
  * bipartite double cover: left copy v', right copy v'', arc v'->u'' of cost
- * c_uv and capacity 1 for every ordered pair; every copy has degree 2.
- * Its min-cost flow equals 2 * F2M optimum and x_e = (y_u'v'' + y_v'u'')/2
+ * c_uv and capacity 1 for every ordered pair; every copy has degree b_v (2
+ * for F2M).  Its min-cost flow equals 2 * the optimum and x_e = (y_u'v'' + y_v'u'')/2
  * is an optimal F2M solution (Edmonds' half-integrality, Sec. 4).  Solved
  * here by plain successive shortest paths with node potentials on the dense
  * complete graph.
@@ -143,7 +154,7 @@ int64_t or_step(int64_t s)
  * the step.  Outputs are indexed by position in `rows`.  z4/i4 hold four
  * entries per row (unused slots: Z = INT64_MAX, u = -1).  Requires n >= 2. */
 void or_gdp_rows(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
-                 const int64_t *lam, int64_t nrows, const int64_t *rows,
+                 const int64_t *lam, const int32_t *b, int64_t nrows, const int64_t *rows,
                  int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
                  int64_t *rowneg, int64_t *step)
 {
@@ -173,9 +184,12 @@ void or_gdp_rows(int64_t n, const int32_t *xy, const int64_t *rowptr, const int3
         neg[r] = (int32_t)cn;
         zero[r] = (int32_t)cz;
         rowneg[r] = rn;
-        /* eq. 10: second and third shortest adjusted edges (positions 1, 2 of
-         * the sorted list, counting from 0).  A row needs a third edge. */
-        step[r] = (bu[2] >= 0) ? or_step(bz[1] + bz[2]) : 0;
+        /* eq. 10 (Sec. 3 for a row with right-hand side b): the b-th and
+         * (b+1)-th shortest adjusted edges, positions b-1 and b of the sorted
+         * list counting from 0 (F2M: the 2nd and 3rd).  The row needs b+1
+         * edges. */
+        const int bv = b ? b[v] : 2;
+        step[r] = (bu[bv] >= 0) ? or_step(bz[bv - 1] + bz[bv]) : 0;
     }
 }
 
@@ -203,27 +217,39 @@ uint64_t or_hash(int64_t n, const int64_t *lam)
 
 /* Full GDP iteration at Lam: all rows, then the global statistics.
  * Outputs per node: z4, i4, neg, zero, step (n rows); rec[OR_TRACE_W]. */
+/* every b_v in {1, 2, 3} (or b NULL) */
+static int check_b(int64_t n, const int32_t *b)
+{
+    if (!b) return OR_OK;
+    for (int64_t v = 0; v < n; v++)
+        if (b[v] < 1 || b[v] > 3) return OR_ERR_ARG;
+    return OR_OK;
+}
+
 int or_gdp_iter(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
-                const int64_t *lam, int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
+                const int64_t *lam, const int32_t *b, int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
                 int64_t *step, int64_t *rec)
 {
+    if (check_b(n, b)) return OR_ERR_ARG;
     int64_t *rows = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int64_t *rowneg = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     if (!rows || !rowneg) { free(rows); free(rowneg); return OR_ERR_NOMEM; }
     for (int64_t v = 0; v < n; v++) rows[v] = v;
-    or_gdp_rows(n, xy, rowptr, col, lam, n, rows, z4, i4, neg, zero, rowneg, step);
-    int64_t sl = 0, sneg = 0, unsat = 0, bad = 0, mx = 0, nz = 0;
+    or_gdp_rows(n, xy, rowptr, col, lam, b, n, rows, z4, i4, neg, zero, rowneg, step);
+    int64_t sl = 0, sbl = 0, sneg = 0, unsat = 0, bad = 0, mx = 0, nz = 0;
     for (int64_t v = 0; v < n; v++) {
+        const int64_t bv = b ? b[v] : 2;
         sl += lam[v];
+        sbl += bv * lam[v];
         sneg += rowneg[v];
-        if (z4[4 * v + 1] > 0 || z4[4 * v + 2] < 0) unsat++;
-        if (2 * neg[v] + zero[v] != 4) bad++;
+        if (z4[4 * v + bv - 1] > 0 || z4[4 * v + bv] < 0) unsat++;
+        if (2 * neg[v] + zero[v] != 2 * bv) bad++;
         int64_t a = step[v] < 0 ? -step[v] : step[v];
         if (a > mx) mx = a;
         if (step[v] != 0) nz++;
     }
     /* every unordered pair appears in two rows */
-    rec[1] = 2 * sl + sneg / 2;
+    rec[1] = sbl + sneg / 2;
     rec[2] = unsat; rec[3] = bad; rec[4] = mx; rec[5] = nz;
     rec[6] = (int64_t)or_hash(n, lam);
     rec[7] = sl;
@@ -240,11 +266,11 @@ int or_gdp_iter(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32
  *   iterations evaluated (records written); *stop = reason; *kstar = index
  *   of Lam*.  z4/i4/neg/zero describe Lam_k of the last evaluated k. */
 int or_gdp_solve(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
-                 int64_t *lam, int64_t max_iters, int64_t handoff_div,
+                 const int32_t *b, int64_t *lam, int64_t max_iters, int64_t handoff_div,
                  int64_t *trace, int64_t *iters, int32_t *stop, int64_t *kstar,
                  int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero)
 {
-    if (n < 4 || max_iters < 0 || handoff_div < 0 || !lam) return OR_ERR_ARG;
+    if (n < 4 || max_iters < 0 || handoff_div < 0 || !lam || check_b(n, b)) return OR_ERR_ARG;
     int rc = or_check_coords(xy, n);
     if (rc) return rc;
     int64_t *step = malloc(sizeof(int64_t) * (size_t)n);
@@ -256,7 +282,7 @@ int or_gdp_solve(int64_t n, const int32_t *xy, const int64_t *rowptr, const int3
     int64_t k = 0;
     int32_t why = 0;
     for (;; k++) {
-        rc = or_gdp_iter(n, xy, rowptr, col, lam, z4, i4, neg, zero, step, rec);
+        rc = or_gdp_iter(n, xy, rowptr, col, lam, b, z4, i4, neg, zero, step, rec);
         if (rc) break;
         rec[0] = k;
         if (trace) memcpy(trace + OR_TRACE_W * k, rec, sizeof(rec));
@@ -301,14 +327,14 @@ static int cmp_pair(const void *a, const void *b)
  *   out[0] primal2 = sum_e c_e * x2_e  (= 2 c.x)
  *   out[1] dual2   = 2*sum Lam + sum_{u<v} min(0, Z_uv)  (= 2 L)
  *   out[2] feasible: endpoints valid, u != v, x2 in {1,2}, no repeated
- *          pair, every node's sum of x2 equal to 4 (degree 2)
+ *          pair, every node's sum of x2 equal to 2 b_v (degree b_v; 4 for F2M)
  *   out[3] certified = feasible && primal2 == dual2 */
 int or_certify(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
-               const int64_t *lam, int64_t m,
+               const int32_t *b, const int64_t *lam, int64_t m,
                const int32_t *eu, const int32_t *ev, const uint8_t *ex2,
                int64_t *out)
 {
-    if (n < 3 || !xy || !lam || m < 0) return OR_ERR_ARG;
+    if (n < 3 || !xy || !lam || m < 0 || check_b(n, b)) return OR_ERR_ARG;
     int rc = or_check_coords(xy, n);
     if (rc) return rc;
     int feas = 1;
@@ -333,9 +359,9 @@ int or_certify(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_
     }
     qsort(keys, (size_t)m, sizeof(int64_t), cmp_pair);
     for (int64_t e = 1; e < m; e++) if (keys[e] == keys[e - 1]) feas = 0;
-    for (int64_t v = 0; v < n; v++) if (deg[v] != 4) feas = 0;
-    int64_t sl = 0, sneg = 0;
-    for (int64_t v = 0; v < n; v++) sl += lam[v];
+    for (int64_t v = 0; v < n; v++) if (deg[v] != 2 * (b ? b[v] : 2)) feas = 0;
+    int64_t sbl = 0, sneg = 0;
+    for (int64_t v = 0; v < n; v++) sbl += (b ? b[v] : 2) * lam[v];
 #pragma omp parallel for reduction(+ : sneg) schedule(dynamic, 16)
     for (int64_t v = 0; v < n; v++) {
         const int64_t deg = rowptr ? rowptr[v + 1] - rowptr[v] : n;
@@ -347,7 +373,7 @@ int or_certify(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_
         }
     }
     out[0] = primal;
-    out[1] = 2 * sl + sneg;
+    out[1] = sbl + sneg;
     out[2] = feas;
     out[3] = feas && primal == out[1];
     free(deg); free(keys);
@@ -385,9 +411,9 @@ int64_t or_trivial_x(int64_t n, const int32_t *xy, const int64_t *lam, int64_t c
  * lambda = (alpha + beta)/2 is optimal for F2M by the symmetry of the cover,
  * so Lam_v = pot(v'') - pot(v').  x2 and lam may be NULL. */
 int or_exact_opt2(int64_t n, const int32_t *xy, const int64_t *rowptr, const int32_t *col,
-                  int64_t *opt2, uint8_t *x2, int64_t *lam)
+                  const int32_t *b, int64_t *opt2, uint8_t *x2, int64_t *lam)
 {
-    if (n < 3 || !xy || !opt2) return OR_ERR_ARG;
+    if (n < 2 || !xy || !opt2 || check_b(n, b)) return OR_ERR_ARG;
     int rc = or_check_coords(xy, n);
     if (rc) return rc;
     int64_t N = 2 * n;
@@ -415,9 +441,10 @@ int or_exact_opt2(int64_t n, const int32_t *xy, const int64_t *rowptr, const int
         for (int64_t v = 0; v < n; v++) if (c[v * n + u] < mn) mn = c[v * n + u];
         pot[n + u] = mn < INF ? mn : 0;
     }
-    for (int64_t v = 0; v < n; v++) { exl[v] = 2; dfr[v] = 2; }
+    int64_t units = 0;   /* every copy has degree b_v: sum_v b_v augmentations */
+    for (int64_t v = 0; v < n; v++) { exl[v] = b ? b[v] : 2; dfr[v] = exl[v]; units += exl[v]; }
     int64_t total = 0;
-    for (int64_t it = 0; it < 2 * n; it++) {
+    for (int64_t it = 0; it < units; it++) {
         /* multi-source Dijkstra from every left copy with supply left */
         for (int64_t i = 0; i < N; i++) { dist[i] = INF; prev[i] = -1; done[i] = 0; }
         for (int64_t v = 0; v < n; v++) if (exl[v] > 0) dist[v] = 0;
@@ -463,7 +490,7 @@ int or_exact_opt2(int64_t n, const int32_t *xy, const int64_t *rowptr, const int
     for (int64_t v = 0; v < n; v++)
         for (int64_t u = 0; u < n; u++) if (y[v * n + u]) total += c[v * n + u];
     (void)0;
-    *opt2 = total;   /* = 2 * F2M optimum (sum over both copies) */
+    *opt2 = total;   /* = 2 * optimum (sum over both copies) */
     if (lam)
         for (int64_t v = 0; v < n; v++) lam[v] = pot[n + v] - pot[v];
     if (x2)
