@@ -67,6 +67,10 @@ struct f2m_ctx {
     // the finish's host side: pinned staging of the GPU's pair data, and its
     // workspace and result, kept from one solve to the next
     HostBuf h_keys, h_costs, h_neg, h_start, h_inc, h_xyp, h_lamp, h_up, h_down, h_progress;
+    // recorded after the copy kernels that read h_up; the next upload waits
+    // on it before it rewrites (or reallocates) the staging
+    hipEvent_t up_done = nullptr;
+    bool up_pending = false;
     f2m::FinishWork *fwork = nullptr;
     f2m::FinishResult fres;
     // contexts (own stream and workspaces) of the batch's finishing threads
@@ -181,8 +185,8 @@ f2m_opts call_opts(f2m_ctx *ctx, const f2m_opts *opts)
 
 // Host arrays to the device through the pinned staging h_up: copied there,
 // then read by a kernel through its device mapping (parts[i] = {host
-// source, device destination, bytes}).  The staging is reused by the next
-// call, which comes after the stream has been synchronised.
+// source, device destination, bytes}).  The next call waits until those
+// copy kernels have finished before it touches the staging.
 struct UpPart {
     const void *src;
     void *dst;
@@ -411,6 +415,11 @@ void upload(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st)
 {
     size_t total = 0;
     for (const UpPart &q : parts) total += (q.bytes + 255) / 256 * 256;
+    if (ctx->up_pending) {
+        // the previous upload's kernels may still read the staging
+        ck(ctx, hipEventSynchronize(ctx->up_done), "upload wait");
+        ctx->up_pending = false;
+    }
     char *h = grow_host<char>(ctx, ctx->h_up, total);
     char *hd = static_cast<char *>(ctx->h_up.dp);
     size_t at = 0;
@@ -421,6 +430,8 @@ void upload(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st)
         }
         at += (q.bytes + 255) / 256 * 256;
     }
+    ck(ctx, hipEventRecord(ctx->up_done, st), "upload record");
+    ctx->up_pending = true;
 }
 
 void download(f2m_ctx *ctx, std::initializer_list<UpPart> parts, hipStream_t st)
@@ -1225,7 +1236,8 @@ f2m_status f2m_create(f2m_ctx **out, int device, const f2m_opts *defaults)
     }
     if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void **)&ctx->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->scratch_host, 16 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&ctx->scratch_host, 16 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->up_done, hipEventDisableTiming) != hipSuccess) {
         f2m_destroy(ctx);
         return F2M_ERR_DEVICE;
     }
@@ -1248,6 +1260,7 @@ void f2m_destroy(f2m_ctx *ctx)
                        &ctx->h_up, &ctx->h_down, &ctx->h_progress})
         if (h->p) (void)hipHostFree(h->p);
     if (ctx->fwork) finish_work_destroy(ctx->fwork);
+    if (ctx->up_done) (void)hipEventDestroy(ctx->up_done);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

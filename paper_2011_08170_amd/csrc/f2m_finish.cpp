@@ -11,6 +11,7 @@
 #include <iterator>
 #include <atomic>
 #include <condition_variable>
+#include <exception>
 #include <functional>
 #include <mutex>
 #include <memory>
@@ -67,13 +68,25 @@ public:
             fn_ = &fn;
             want_ = T - 1;
             done_ = 0;
+            err_ = nullptr;
             ++gen_;
         }
         cv_.notify_all();
-        fn(0);
+        // the workers use fn (and what it refers to) until they report done:
+        // wait for them whatever fn(0) does, then rethrow the first error
+        std::exception_ptr mine;
+        try {
+            fn(0);
+        } catch (...) {
+            mine = std::current_exception();
+        }
         std::unique_lock<std::mutex> lk(m_);
         cv_done_.wait(lk, [&] { return done_ == want_; });
         fn_ = nullptr;
+        if (!mine) mine = err_;
+        err_ = nullptr;
+        lk.unlock();
+        if (mine) std::rethrow_exception(mine);
     }
 
 private:
@@ -87,8 +100,14 @@ private:
             if (id > want_) continue;   // not needed this time
             const std::function<void(int)> *f = fn_;
             lk.unlock();
-            (*f)(id);
+            std::exception_ptr e;
+            try {
+                (*f)(id);
+            } catch (...) {
+                e = std::current_exception();
+            }
             lk.lock();
+            if (e && !err_) err_ = e;
             if (++done_ == want_) cv_done_.notify_one();
         }
     }
@@ -98,6 +117,7 @@ private:
     std::vector<std::thread> th_;
     const std::function<void(int)> *fn_ = nullptr;
     int want_ = 0, done_ = 0;
+    std::exception_ptr err_;   // first error a worker threw in this run
     uint64_t gen_ = 0;
     bool quit_ = false;
 };
