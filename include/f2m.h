@@ -137,9 +137,17 @@ typedef struct f2m_opts {
     int32_t pad_opts;
     uint64_t max_device_bytes;    /* cap on the context's device workspace (0: none);
                                      a call that would pass it fails with F2M_ERR_NOMEM */
-    const char *tuner_cache;      /* path of a tuner cache (paper_2011_08170_amd.tune), or NULL;
-                                     with scan_rows == scan_slices == 0 the solve takes the
-                                     cached launch shape for its device, scan mode and size */
+    const char *tuner_cache;      /* path of a tuner cache, or NULL.  Text, one entry per line,
+                                     tab-separated: device name (f2m_device_name), mode
+                                     ("culled", "full", "batch-culled", "batch-full"), size
+                                     bucket (the integer nearest 2 log2 n, exactly
+                                     floor(bitlength(n^4) / 2); the batch uses the total node
+                                     count), rows, slices, chunk; 0 keeps the built-in value;
+                                     '#' lines are comments.  f2m_solve takes the entry for
+                                     its device, scan mode and n when scan_rows == scan_slices
+                                     == 0 (complete graph); f2m_solve_batch when scan_slices
+                                     == 0; chunk applies when opts.chunk == 0.  A missing
+                                     file or entry leaves the built-in shape. */
 } f2m_opts;
 
 typedef struct f2m_result {
@@ -290,6 +298,9 @@ f2m_status f2m_mlp_adamw(f2m_ctx *ctx, float *theta, const float *grad, float *m
 void f2m_result_free(f2m_result *res);
 const char *f2m_status_str(f2m_status s);
 const char *f2m_last_error(const f2m_ctx *ctx);
+/* Name of the context's device (hipDeviceProp_t::name; "" if unknown): the
+ * device field of tuner-cache entries.  The string lives as long as ctx. */
+const char *f2m_device_name(const f2m_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -37,6 +37,7 @@ struct HostBuf {   // pinned host memory
 
 struct f2m_ctx {
     int device = 0;
+    std::string device_name;   // hipDeviceProp_t::name, the tuner cache's device key
     hipStream_t stream = nullptr;
     std::string err;
     std::vector<DevBuf *> bufs;
@@ -260,6 +261,70 @@ ScanShape scan_shape_auto(int64_t n, bool cull)
     }
     s.slices = (n + s.slice_len - 1) / s.slice_len;
     return s;
+}
+
+// Tuner cache (written by paper_2011_08170_amd/tune.py): a text file, one
+// entry per line, tab-separated fields
+//   device name, mode, size bucket, rows per lane, slices, chunk
+// mode "culled" or "full" (f2m_solve's scan), "batch-culled" or
+// "batch-full" (f2m_solve_batch: slices per instance, iterations per
+// replayed graph); 0 in a field keeps the built-in choice.  Lines that start
+// with '#' and lines that do not parse are skipped; a missing file is no
+// error (the built-in shape is used).  The size bucket of n is the integer
+// nearest to 2 log2 n, computed exactly as floor(bitlength(n^4) / 2).
+int size_bucket(int64_t n)
+{
+    const unsigned __int128 x = (unsigned __int128)n * (unsigned __int128)n * (unsigned __int128)n * (unsigned __int128)n;
+    int bits = 0;
+    for (unsigned __int128 y = x; y; y >>= 1) ++bits;
+    return bits / 2;
+}
+
+struct Tuned {
+    bool found = false;
+    int rows = 0;
+    int64_t slices = 0;
+    int32_t chunk = 0;
+};
+
+Tuned tuner_lookup(const f2m_ctx *ctx, const char *path, const char *mode, int64_t n)
+{
+    Tuned t;
+    if (!path || !*path) return t;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return t;
+    const int b = size_bucket(n);
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#') continue;
+        std::vector<std::string> fld;
+        std::string cur;
+        for (const char *c = line; *c && *c != '\n' && *c != '\r'; ++c) {
+            if (*c == '\t') {
+                fld.push_back(cur);
+                cur.clear();
+            } else {
+                cur.push_back(*c);
+            }
+        }
+        fld.push_back(cur);
+        if (fld.size() < 6 || fld[0] != ctx->device_name || fld[1] != mode) continue;
+        char *end = nullptr;
+        const long bb = std::strtol(fld[2].c_str(), &end, 10);
+        if (*end || bb != b) continue;
+        const long r = std::strtol(fld[3].c_str(), &end, 10);
+        if (*end || (r != 0 && r != 1 && r != 2 && r != 4)) continue;
+        const long long sl = std::strtoll(fld[4].c_str(), &end, 10);
+        if (*end || sl < 0) continue;
+        const long ch = std::strtol(fld[5].c_str(), &end, 10);
+        if (*end || ch < 0 || ch > 4096) continue;
+        t.found = true;   // the last matching line wins
+        t.rows = (int)r;
+        t.slices = sl;
+        t.chunk = (int32_t)ch;
+    }
+    std::fclose(f);
+    return t;
 }
 
 hipStream_t pick_stream(f2m_ctx *ctx, const f2m_opts *o)
@@ -1234,6 +1299,8 @@ f2m_status f2m_create(f2m_ctx **out, int device, const f2m_opts *defaults)
         delete ctx;
         return F2M_ERR_DEVICE;
     }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->device_name = prop.name;
     if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void **)&ctx->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&ctx->scratch_host, 16 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
@@ -1296,6 +1363,8 @@ const char *f2m_status_str(f2m_status s)
 }
 
 const char *f2m_last_error(const f2m_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+const char *f2m_device_name(const f2m_ctx *ctx) { return ctx ? ctx->device_name.c_str() : ""; }
 
 f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam_in, int64_t *lam_out,
                         int64_t *z4_out, int32_t *i4_out, int32_t *neg, int32_t *zero, int64_t *step,
@@ -1453,7 +1522,7 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
     f2m_result res;
     std::memset(&res, 0, sizeof(res));
     try {
-        const f2m_opts o = call_opts(ctx, opts);
+        f2m_opts o = call_opts(ctx, opts);
         if (!coords || !out) fail(ctx, F2M_ERR_ARG, "null coords or result");
         if (o.rule_version != 1) fail(ctx, F2M_ERR_ARG, "only rule_version 1 exists");
         if (o.graph != F2M_GRAPH_COMPLETE && o.graph != F2M_GRAPH_KNN) fail(ctx, F2M_ERR_ARG, "unknown graph kind");
@@ -1464,6 +1533,14 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             fail(ctx, F2M_ERR_ARG, "scan_rows must be 0, 1, 2 or 4");
         if (o.scan_slices < 0) fail(ctx, F2M_ERR_ARG, "scan_slices < 0");
         if (o.warm == F2M_WARM_USER && !o.lambda2_init) fail(ctx, F2M_ERR_ARG, "warm start without lambda2_init");
+        if (o.tuner_cache && o.scan_rows == 0 && o.scan_slices == 0 && !on_graph) {
+            const Tuned tu = tuner_lookup(ctx, o.tuner_cache, o.scan_mode == F2M_SCAN_FULL ? "full" : "culled", n);
+            if (tu.found) {
+                o.scan_rows = tu.rows;
+                o.scan_slices = tu.slices;
+                if (o.chunk == 0) o.chunk = tu.chunk;
+            }
+        }
         const CtrlStart cs = resume_start(ctx, o);
         if (o.warm != F2M_WARM_COLD && o.warm != F2M_WARM_USER && o.warm != F2M_WARM_MLP &&
             o.warm != F2M_WARM_GRAPH)
@@ -1591,7 +1668,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         }
     } gguard{graph, exec};
     try {
-        const f2m_opts o = call_opts(ctx, opts);
+        f2m_opts o = call_opts(ctx, opts);
         if (!coords || !offsets || !outs || n_inst <= 0) fail(ctx, F2M_ERR_ARG, "null inputs or no instances");
         if (o.rule_version != 1) fail(ctx, F2M_ERR_ARG, "only rule_version 1 exists");
         if (o.graph != F2M_GRAPH_COMPLETE) fail(ctx, F2M_ERR_ARG, "batched solves run on the complete graph");
@@ -1611,6 +1688,14 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         res.assign(n_inst, f2m_result{});
         const int64_t total = offsets[n_inst];
         const bool cull = o.scan_mode != F2M_SCAN_FULL;
+        if (o.tuner_cache && o.scan_slices == 0) {
+            // batch entries are keyed by the batch's total node count
+            const Tuned tu = tuner_lookup(ctx, o.tuner_cache, cull ? "batch-culled" : "batch-full", total);
+            if (tu.found) {
+                o.scan_slices = tu.slices;
+                if (o.chunk == 0) o.chunk = tu.chunk;
+            }
+        }
 
         // layout: positions and tiles 256-aligned per instance
         std::vector<int64_t> P(n_inst + 1, 0), T(n_inst + 1, 0), PZ(n_inst + 1, 0), PS(n_inst + 1, 0);

@@ -27,7 +27,7 @@ TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
 SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
            "f2m_knn_graph", "f2m_solve_batch", "f2m_features", "f2m_mlp_forward", "f2m_mlp_grad", "f2m_mlp_adamw",
-           "f2m_result_free", "f2m_status_str", "f2m_last_error")
+           "f2m_result_free", "f2m_status_str", "f2m_last_error", "f2m_device_name")
 MLP_PARAMS = 18817
 WARM = {"cold": 0, "user": 1, "mlp": 2, "graph": 3}
 GRAPH = {"complete": 0, "knn": 1}
@@ -120,6 +120,8 @@ def lib():
         L.f2m_status_str.argtypes = [C.c_int]
         L.f2m_last_error.restype = C.c_char_p
         L.f2m_last_error.argtypes = [p]
+        L.f2m_device_name.restype = C.c_char_p
+        L.f2m_device_name.argtypes = [p]
         _lib = L
     return _lib
 
@@ -183,6 +185,10 @@ class Context:
         st = lib().f2m_create(C.byref(self._h), int(device), C.byref(d))
         if st != OK:
             raise F2MError(st, "f2m_create(device=%d) failed" % device)
+
+    def device_name(self) -> str:
+        """The device's name as the tuner cache keys it."""
+        return lib().f2m_device_name(self._h).decode()
 
     def close(self):
         if self._h:
@@ -265,7 +271,7 @@ class Context:
             lib().f2m_result_free(C.byref(res))
 
     def solve_batch(self, coords, offsets, *, max_iters=100000, handoff_div=HANDOFF_DIV, finish="exact", trace=False,
-                    chunk=0, scan="culled", lambda2_init=None, slices=0):
+                    chunk=0, scan="culled", lambda2_init=None, slices=0, tuner_cache=None):
         """Solves many instances in one batched loop.  coords: int32 (sum n, 2)
         on the host; offsets: int64 (n_inst + 1).  Returns (status, [dict])."""
         o = Opts()
@@ -280,6 +286,10 @@ class Context:
         xy = _np(coords, np.int32)
         off = _np(offsets, np.int64)
         keep = [xy, off]
+        if tuner_cache is not None:
+            tc = os.fsencode(tuner_cache)
+            keep.append(tc)
+            o.tuner_cache = tc
         if lambda2_init is not None:
             l0 = _np(lambda2_init, np.int64)
             keep.append(l0)
