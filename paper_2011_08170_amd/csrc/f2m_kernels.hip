@@ -1674,7 +1674,18 @@ __global__ __launch_bounds__(kBlock) void k_minmax(const int32_t *xy, int64_t n,
         mnx = min(mnx, __shfl_xor(mnx, o, 64)); mxx = max(mxx, __shfl_xor(mxx, o, 64));
         mny = min(mny, __shfl_xor(mny, o, 64)); mxy = max(mxy, __shfl_xor(mxy, o, 64));
     }
+    // one set of four atomics per block (atomics on one cache line serialise)
+    __shared__ int32_t red[kBlock / 64][4];
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
+        red[w][0] = mnx; red[w][1] = mxx; red[w][2] = mny; red[w][3] = mxy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlock / 64; ++q) {
+            mnx = min(mnx, red[q][0]); mxx = max(mxx, red[q][1]);
+            mny = min(mny, red[q][2]); mxy = max(mxy, red[q][3]);
+        }
         atomicMin(&out4[0], mnx); atomicMax(&out4[1], mxx);
         atomicMin(&out4[2], mny); atomicMax(&out4[3], mxy);
     }
@@ -2011,8 +2022,9 @@ static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + p
 hipError_t launch_minmax(const int32_t *xy, int64_t n, int32_t *out4, hipStream_t st)
 {
     hipLaunchKernelGGL(k_minmax_init, dim3(1), dim3(64), 0, st, out4);
-    unsigned nb = blocks_for(n, kBlock);
-    if (nb > 1024) nb = 1024;
+    // a few blocks that loop: few atomics, and the pass is bandwidth-trivial
+    unsigned nb = blocks_for(n, kBlock * 8);
+    if (nb > 256) nb = 256;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL(k_minmax, dim3(nb), dim3(kBlock), 0, st, xy, n, out4);
     return hipGetLastError();
