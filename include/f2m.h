@@ -252,6 +252,24 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
                         int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
                         int64_t *step, int64_t rec[F2M_TRACE_W]);
 
+/* f2m_gdp_step for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it):
+ * the same iteration, arguments and results as f2m_gdp_step, with every
+ * workspace buffer taken from one fixed device array of 32 MiB that the
+ * library holds on each device it runs on until the process ends.  It
+ * calls no hipMalloc, hipFree or other allocating routine.
+ *   n           4 <= n <= F2M_NOALLOC_MAX_N; larger n returns
+ *               F2M_ERR_CAPACITY before any work is queued
+ * Every call on one device, from any context, uses the same array and
+ * finds the previous call's contents there (each call initialises what it
+ * reads): calls that overlap on one device race and must be serialised by
+ * the caller.  Runs on the context's stream and waits for it. */
+#define F2M_NOALLOC_MAX_N 131072
+f2m_status f2m_gdp_step_noalloc(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n,
+                                const int64_t *lambda2_in, int64_t *lambda2_out,
+                                int64_t *z4, int32_t *i4, int32_t *neg, int32_t *zero,
+                                int64_t *step, int64_t rec[F2M_TRACE_W]);
+
 /* Certificate on the complete graph (weak/strong duality of Sec. 2):
  *   coords_xy device int32[2n]; lambda2 device int64[n];
  *   eu, ev, ex2 device arrays of m edges.

@@ -72,6 +72,10 @@ struct f2m_ctx {
     // on it before it rewrites (or reallocates) the staging
     hipEvent_t up_done = nullptr;
     bool up_pending = false;
+    // this device's copy of the no-alloc workspace (f2m_gdp_step_noalloc),
+    // or null with noalloc_err set when the lookup failed
+    void *noalloc = nullptr;
+    hipError_t noalloc_err = hipSuccess;
     f2m::FinishWork *fwork = nullptr;
     f2m::FinishResult fres;
     // contexts (own stream and workspaces) of the batch's finishing threads
@@ -1262,6 +1266,51 @@ void gdp_step_run(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam
     std::memcpy(rec, ctx->scratch_host, kTraceW * sizeof(int64_t));
 }
 
+// Buffers of one GDP iteration carved out of a fixed workspace at base
+// (256-byte aligned pieces); returns the bytes used.  With base == null only
+// the size is computed.  z4 and i4 get workspace only when the caller gives
+// none.
+size_t carve_step(char *base, int64_t n, bool own_z4, bool own_i4, StepBufs *b)
+{
+    const ScanShape sh = scan_shape(n, true);
+    const int64_t nt = ntiles_of(n);
+    size_t at = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? static_cast<void *>(base + at) : nullptr;
+        at += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        return p;
+    };
+    StepBufs t{};
+    t.m4 = static_cast<int32_t *>(take(4 * sizeof(int32_t)));
+    t.geo.orig = static_cast<int32_t *>(take(n * sizeof(int32_t)));
+    t.geo.pos = static_cast<int32_t *>(take(n * sizeof(int32_t)));
+    t.geo.col = static_cast<float4 *>(take(n * sizeof(float4)));
+    t.geo.box = static_cast<float4 *>(take(nt * kBoxStride * sizeof(float4)));
+    t.geo.xy2max = static_cast<float *>(take(sizeof(float)));
+    t.sort.tb = sort_temp_bytes(n);
+    t.sort.keys = static_cast<uint32_t *>(take(n * sizeof(uint32_t)));
+    t.sort.keys2 = static_cast<uint32_t *>(take(n * sizeof(uint32_t)));
+    t.sort.ids = static_cast<int32_t *>(take(n * sizeof(int32_t)));
+    t.sort.temp = take(t.sort.tb);
+    t.ls = static_cast<int64_t *>(take(n * sizeof(int64_t)));
+    t.lo = static_cast<int64_t *>(take(n * sizeof(int64_t)));
+    t.best = static_cast<int64_t *>(take(n * sizeof(int64_t)));
+    t.thm = static_cast<float *>(take(nt * kBoxStride * sizeof(float)));
+    t.pz = static_cast<int64_t *>(take(sh.slices * kTop * n * sizeof(int64_t)));
+    t.pi = static_cast<int32_t *>(take(sh.slices * kTop * n * sizeof(int32_t)));
+    t.pneg = static_cast<int32_t *>(take(sh.slices * n * sizeof(int32_t)));
+    t.pzero = static_cast<int32_t *>(take(sh.slices * n * sizeof(int32_t)));
+    t.prn = static_cast<int64_t *>(take(sh.slices * n * sizeof(int64_t)));
+    t.z4 = own_z4 ? static_cast<int64_t *>(take(kTop * n * sizeof(int64_t))) : nullptr;
+    t.i4 = own_i4 ? static_cast<int32_t *>(take(kTop * n * sizeof(int32_t))) : nullptr;
+    t.seed = static_cast<int32_t *>(take(kTop * n * sizeof(int32_t)));
+    t.cd = static_cast<Ctrl *>(take(sizeof(Ctrl)));
+    t.trace = static_cast<int64_t *>(take(kTraceW * sizeof(int64_t)));
+    t.slots = static_cast<unsigned long long *>(take((size_t)kSlotW * nt * sizeof(unsigned long long)));
+    if (b) *b = t;
+    return at;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1308,6 +1357,9 @@ f2m_status f2m_create(f2m_ctx **out, int device, const f2m_opts *defaults)
         f2m_destroy(ctx);
         return F2M_ERR_DEVICE;
     }
+    // the no-alloc workspace's device address, looked up once per device
+    // with the device current (a failure only disables f2m_gdp_step_noalloc)
+    ctx->noalloc_err = noalloc_scratch(device, &ctx->noalloc);
     *out = ctx;
     return F2M_OK;
 }
@@ -1399,6 +1451,40 @@ f2m_status f2m_gdp_step(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_
         b.cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
         b.trace = grow<int64_t>(ctx, ctx->trace, kTraceW);
         b.slots = grow<unsigned long long>(ctx, ctx->slots, (int64_t)kSlotW * ntiles_of(n));
+        gdp_step_run(ctx, xy, n, lam_in, lam_out, neg, zero, step, rec, b);
+        return F2M_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+f2m_status f2m_gdp_step_noalloc(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam_in,
+                                int64_t *lam_out, int64_t *z4_out, int32_t *i4_out, int32_t *neg, int32_t *zero,
+                                int64_t *step, int64_t rec[F2M_TRACE_W])
+{
+    if (!ctx) return F2M_ERR_ARG;
+    try {
+        if (!xy || !lam_in || !lam_out || !rec || n < 4 || lam_in == lam_out)
+            fail(ctx, F2M_ERR_ARG, "gdp_step_noalloc needs n >= 4, coords, distinct lambda2_in/out and rec");
+        if (n > F2M_NOALLOC_MAX_N)
+            fail(ctx, F2M_ERR_CAPACITY, "gdp_step_noalloc: n = " + std::to_string(n) + " is above its maximum " +
+                                            std::to_string((long long)F2M_NOALLOC_MAX_N));
+        if (!ctx->noalloc)
+            fail(ctx, F2M_ERR_DEVICE, std::string("gdp_step_noalloc: no device workspace: ") +
+                                          hipGetErrorString(ctx->noalloc_err));
+        const size_t need = carve_step(nullptr, n, !z4_out, !i4_out, nullptr);
+        if (need > kNoAllocBytes)
+            fail(ctx, F2M_ERR_CAPACITY, "gdp_step_noalloc: n = " + std::to_string(n) + " needs " +
+                                            std::to_string(need) + " bytes of workspace, " +
+                                            std::to_string(kNoAllocBytes) + " exist");
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        StepBufs b;
+        carve_step(static_cast<char *>(ctx->noalloc), n, !z4_out, !i4_out, &b);
+        if (z4_out) b.z4 = z4_out;
+        if (i4_out) b.i4 = i4_out;
         gdp_step_run(ctx, xy, n, lam_in, lam_out, neg, zero, step, rec, b);
         return F2M_OK;
     } catch (const Fail &f) {

@@ -283,6 +283,11 @@ hipError_t launch_graph_membership(const Geo &g, const Csr &csr, int64_t m, cons
 hipError_t launch_csr_to_labels(const Geo &g, const Csr &csr, int32_t *rowptr_l, int32_t *col_l, int32_t *deg_tmp,
                                 hipStream_t st);
 hipError_t launch_minmax(const int32_t *xy, int64_t n, int32_t *out4, hipStream_t st);
+
+// Size of the fixed device workspace of f2m_gdp_step_noalloc, and its device
+// address on the current device (f2m_noalloc.hip).
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+hipError_t noalloc_scratch(int device, void **ptr);
 // Morton order: fills orig (position -> label) and pos (label -> position).
 size_t sort_temp_bytes(int64_t n);
 hipError_t launch_sort(const int32_t *xy, int64_t n, int32_t minx, int32_t miny, uint32_t *keys,

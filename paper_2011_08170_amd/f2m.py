@@ -27,8 +27,10 @@ TRACE_W = 8
 TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "sum_lam")
 SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
            "f2m_knn_graph", "f2m_solve_batch", "f2m_features", "f2m_mlp_forward", "f2m_mlp_grad", "f2m_mlp_adamw",
-           "f2m_result_free", "f2m_status_str", "f2m_last_error", "f2m_device_name")
+           "f2m_result_free", "f2m_status_str", "f2m_last_error", "f2m_device_name",
+           "f2m_gdp_step_noalloc")
 MLP_PARAMS = 18817
+NOALLOC_MAX_N = 131072   # F2M_NOALLOC_MAX_N
 WARM = {"cold": 0, "user": 1, "mlp": 2, "graph": 3}
 GRAPH = {"complete": 0, "knn": 1}
 HANDOFF_DIV = 50   # the library default: hand off once #unsatisfied * 50 <= n
@@ -100,6 +102,8 @@ def lib():
         L.f2m_solve.argtypes = [p, p, i64, C.POINTER(Opts), C.POINTER(Result)]
         L.f2m_gdp_step.restype = C.c_int
         L.f2m_gdp_step.argtypes = [p, p, i64, p, p, p, p, p, p, p, p]
+        L.f2m_gdp_step_noalloc.restype = C.c_int
+        L.f2m_gdp_step_noalloc.argtypes = [p, p, i64, p, p, p, p, p, p, p, p]
         L.f2m_certify.restype = C.c_int
         L.f2m_certify.argtypes = [p, p, i64, p, i64, p, p, p, p]
         L.f2m_features.restype = C.c_int
@@ -310,9 +314,16 @@ class Context:
 
     def gdp_step(self, coords, lam_in, lam_out, z4=None, i4=None, neg=None, zero=None, step=None):
         """One GDP iteration on device tensors; returns the record dict."""
+        return self._step(lib().f2m_gdp_step, coords, lam_in, lam_out, z4, i4, neg, zero, step)
+
+    def gdp_step_noalloc(self, coords, lam_in, lam_out, z4=None, i4=None, neg=None, zero=None, step=None):
+        """gdp_step on the library's fixed device workspace (no allocation;
+        n <= NOALLOC_MAX_N; calls on one device must not overlap)."""
+        return self._step(lib().f2m_gdp_step_noalloc, coords, lam_in, lam_out, z4, i4, neg, zero, step)
+
+    def _step(self, fn, coords, lam_in, lam_out, z4, i4, neg, zero, step):
         n = coords.shape[0]
         rec = np.zeros(TRACE_W, np.int64)
-        fn = lib().f2m_gdp_step
         self._check(fn(self._h, _dptr(coords), n, _dptr(lam_in), _dptr(lam_out), _dptr(z4),
                        _dptr(i4), _dptr(neg), _dptr(zero), _dptr(step), rec.ctypes.data_as(C.c_void_p)))
         r = dict(zip(TRACE_FIELDS, (int(x) for x in rec)))
