@@ -186,9 +186,11 @@ def main():
         avg_ms = scan_ms / max(launches, 1)
         rates = None
         if args.graph == "complete":
-            # ordered pairs the scan evaluated per launch (culled tiles excluded)
+            # ordered pairs the scan kernel evaluated per launch (culled tiles
+            # excluded; a list iteration's entries are evaluated by the update,
+            # its scan launch exits at once and counts as a launch with none)
             tested_all = sum(r["scan_pairs"] for r in runs)
-            tested = tested_all / max(launches, 1)
+            tested = sum(r["scan_by_kind"][k]["pairs"] for r in runs for k in ("full", "build")) / max(launches, 1)
             ops = OPS_PER_PAIR * tested
             achieved = ops / (avg_ms * 1e-3) / 1e12
             kern = ("k_rowscan_w<gdp>" if args.scan == "culled" and runs[-1]["scan_rows"] == 1
@@ -196,12 +198,17 @@ def main():
             by_kind = {}
             for kind in ("full", "build", "list"):
                 ms = sum(r["scan_by_kind"][kind]["ms"] for r in runs)
+                mu = sum(r["scan_by_kind"][kind]["update_ms"] for r in runs)
                 nl = sum(r["scan_by_kind"][kind]["launches"] for r in runs)
                 pk = sum(r["scan_by_kind"][kind]["pairs"] for r in runs)
                 if nl:
-                    a = OPS_PER_PAIR * pk / nl / (ms / nl * 1e-3) / 1e12
-                    by_kind[kind] = {"launches": nl, "avg_launch_ms": ms / nl, "pairs_tested_per_launch": pk / nl,
-                                     "achieved": a, "frac": a / VALU_PEAK_TOPS}
+                    # a list iteration's pairs are evaluated by the update
+                    # (its scan launch exits at once): rate over the update
+                    t = mu if kind == "list" else ms
+                    a = OPS_PER_PAIR * pk / nl / (t / nl * 1e-3) / 1e12
+                    by_kind[kind] = {"launches": nl, "avg_launch_ms": ms / nl, "avg_update_ms": mu / nl,
+                                     "pairs_tested_per_launch": pk / nl, "achieved": a, "frac": a / VALU_PEAK_TOPS,
+                                     "rate_over": "update" if kind == "list" else "scan"}
             roof = {"bound": "alu", "kernel": kern, "achieved": achieved,
                     "peak": VALU_PEAK_TOPS, "unit": "T lane-op/s", "frac": achieved / VALU_PEAK_TOPS,
                     "ops_per_pair": OPS_PER_PAIR,
@@ -209,11 +216,14 @@ def main():
                     "avg_launch_ms": avg_ms, "launches": launches,
                     "pairs_tested_per_launch": tested, "ops_per_launch": ops,
                     "slices": runs[-1]["scan_slices"], "by_kind": by_kind,
+                    "update_avg_ms": sum(r["update_ms"] for r in runs) / max(launches, 1),
                     "valu_counter": measured_traffic("valu|complete|%s|%s|%d" % (args.scan, args.instance, n))}
-            rates = {"tested_pairs_per_s": tested_all / (scan_ms * 1e-3) if scan_ms else None,
-                     "decided_pairs_per_s": iters * pairs / (scan_ms * 1e-3) if scan_ms else None,
-                     "note": "tested: ordered pairs the culled scan evaluated (filter or lists); decided: "
-                             "the n(n-1)/2 unordered pairs each iteration settles, over the scan time"}
+            gdp_ms = scan_ms + sum(r["update_ms"] for r in runs)
+            rates = {"tested_pairs_per_s": tested_all / (gdp_ms * 1e-3) if gdp_ms else None,
+                     "decided_pairs_per_s": iters * pairs / (gdp_ms * 1e-3) if gdp_ms else None,
+                     "note": "tested: ordered pairs the GDP kernels evaluated (the scan's filter, or the "
+                             "candidate lists in the update); decided: the n(n-1)/2 unordered pairs each "
+                             "iteration settles; both over the scan and update kernels' time"}
         else:
             nnz = runs[-1]["graph_nnz"]
             # per row: rowptr 4, own label 4, Lam in 8, Lam out 8, top-4 Z 32 and labels 16;

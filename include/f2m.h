@@ -89,7 +89,9 @@ enum { F2M_FINISH_NONE = 0, F2M_FINISH_EXACT = 1 };
 enum { F2M_SCAN_CULLED = 0, F2M_SCAN_FULL = 1 };
 /* Scan kinds of the complete-graph GDP (f2m_result.scan_kind).  A list scan
  * evaluates each row's candidate list from the last building scan only; it
- * runs only while that is provably exact, so every kind gives the same bits. */
+ * runs only while that is provably exact, so every kind gives the same bits.
+ * On a list iteration the update kernel evaluates the lists and the scan
+ * launch exits at once. */
 enum { F2M_SCAN_KIND_FULL = 0, F2M_SCAN_KIND_BUILD = 1, F2M_SCAN_KIND_LIST = 2 };
 enum { F2M_STOP_TRIVIAL = 1, F2M_STOP_FIXED = 2, F2M_STOP_CYCLE = 3, F2M_STOP_CAP = 4,
        F2M_STOP_HANDOFF = 5 };
@@ -148,6 +150,16 @@ typedef struct f2m_opts {
                                      == 0 (complete graph); f2m_solve_batch when scan_slices
                                      == 0; chunk applies when opts.chunk == 0.  A missing
                                      file or entry leaves the built-in shape. */
+    /* Rows with other right-hand sides (Sec. 3: binary rows, integral b; here
+     * the fractional b-matching): host, n entries by label, each 1, 2 or 3,
+     * or NULL for 2 everywhere (F2M).  Node v then needs degree b_v: the
+     * GDP steps on the b_v-th and (b_v+1)-th smallest Z, a node is
+     * unsatisfied when Z_(b) > 0 or Z_(b+1) < 0, its trivial doubled degree
+     * must be 2 b_v, dual2 = sum_v b_v Lam_v + sum_e min(0, Z_e), and the
+     * finish and the certificate use degree b_v.  The x is always made by the
+     * exact finish (finish == EXACT; else NOT_CERTIFIED).  f2m_solve only,
+     * n >= 4, cold or user warm start. */
+    const int32_t *degree_b;
 } f2m_opts;
 
 typedef struct f2m_result {
@@ -195,6 +207,10 @@ typedef struct f2m_result {
     double scan_ms_kind[3];     /* scan_ms split by F2M_SCAN_KIND_* (time_kernels) */
     int64_t scan_launches_kind[3];
     int64_t scan_pairs_kind[3]; /* scan_pairs split by F2M_SCAN_KIND_* */
+    double update_ms;           /* summed duration of the update launches (time_kernels); on a
+                                   F2M_SCAN_KIND_LIST iteration the update evaluates the lists
+                                   and the scan launch exits at once */
+    double update_ms_kind[3];   /* update_ms split by the iteration's F2M_SCAN_KIND_* */
 } f2m_result;
 
 /* Fills opts with the defaults: rule 1, complete graph, cold start,

@@ -44,8 +44,8 @@ struct f2m_ctx {
     // geometry of the current instance (sorted order)
     DevBuf xy, minmax, keys, keys_alt, ids, orig, pos, box, xy2max, sort_temp;
     // GDP loop state
-    DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, pflag, z4, i4, seed, ctrl, trace,
-        lst, lcnt, tpart, slots, kinds;
+    DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, pflag, z4, i4, z4p, i4p, seed,
+        ctrl, trace, lst, lcnt, tpart, slots, kinds;
     // trivial x
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
     // certificate / pair collection state
@@ -54,6 +54,8 @@ struct f2m_ctx {
         p_cand;
     // the exact finish's node order (Morton positions): coordinates, Lam
     DevBuf f_xyp, f_lam;
+    // node degrees b (b-matching rows) by label and by position
+    DevBuf deg_label, deg_pos;
     // candidate graph
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
     // warm-start network
@@ -91,9 +93,9 @@ struct f2m_ctx {
     {
         DevBuf *all[] = {&xy, &minmax, &keys, &keys_alt, &ids, &orig, &pos, &box, &xy2max, &sort_temp,
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
-                         &prowneg, &pflag, &z4, &i4, &seed, &ctrl, &trace, &lst, &lcnt, &tpart, &slots, &kinds, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
+                         &prowneg, &pflag, &z4, &i4, &z4p, &i4p, &seed, &ctrl, &trace, &lst, &lcnt, &tpart, &slots, &kinds, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
-                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &knn_nbr, &csr_keys,
+                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &deg_label, &deg_pos, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
                          &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
@@ -210,6 +212,9 @@ double now_s()
 }
 
 int64_t ntiles_of(int64_t n) { return (n + kTileCols - 1) / kTileCols; }
+// threads per block of the update and candidate-graph step launches (one row
+// per thread, one column tile per block)
+constexpr int64_t kBlockThreads = kTileCols;
 
 // Host threads for the batch's per-instance finishes: one per two hardware
 // threads, at most 8 (the work per instance is a few host syncs and a small
@@ -448,13 +453,13 @@ LamView place_lam(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label_dev,
 
 // Certificate of (lam, edges); lam and the edges are device arrays by label.
 void certify_dev(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label, int64_t m, const int32_t *eu,
-                 const int32_t *ev, const uint8_t *ex, hipStream_t st, int64_t out[4])
+                 const int32_t *ev, const uint8_t *ex, hipStream_t st, int64_t out[4], const int8_t *b_label = nullptr)
 {
     const int64_t n = gh.g.n;
     LamView lv = place_lam(ctx, gh, lam_label, st);
     int32_t *deg = grow<int32_t>(ctx, ctx->c_deg, n);
     int32_t *cnt = grow<int32_t>(ctx, ctx->c_cnt, n);
-    int32_t *nb = grow<int32_t>(ctx, ctx->c_nb, kTop * n);
+    int32_t *nb = grow<int32_t>(ctx, ctx->c_nb, kCertNb * n);
     unsigned long long *acc = grow<unsigned long long>(ctx, ctx->c_acc, 4);
     ck(ctx, hipMemsetAsync(deg, 0, n * sizeof(int32_t), st), "memset");
     ck(ctx, hipMemsetAsync(cnt, 0, n * sizeof(int32_t), st), "memset");
@@ -468,14 +473,14 @@ void certify_dev(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam_label, int6
     sa.acc = acc;
     ck(ctx, launch_scan(sa, kModeCert, sh.slices, sh.rows, st), "cert_scan");
     ck(ctx, launch_cert_edges(gh.xy, n, m, eu, ev, ex, deg, cnt, nb, acc, st), "cert_edges");
-    ck(ctx, launch_cert_nodes(lam_label, n, deg, cnt, nb, acc, st), "cert_nodes");
+    ck(ctx, launch_cert_nodes(lam_label, n, deg, cnt, nb, acc, b_label, st), "cert_nodes");
     unsigned long long h[4];
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, acc, sizeof(h), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     std::memcpy(h, ctx->scratch_host, sizeof(h));
     const int64_t rowneg = (int64_t)h[0], primal2 = (int64_t)h[1], viol = (int64_t)h[2], sl = (int64_t)h[3];
     out[0] = primal2;
-    out[1] = 2 * sl + rowneg / 2;
+    out[1] = sl + rowneg / 2;   // sl = sum_v b_v Lam_v
     out[2] = viol == 0 ? 1 : 0;
     out[3] = (viol == 0 && out[0] == out[1]) ? 1 : 0;
 }
@@ -711,13 +716,14 @@ Csr build_graph(f2m_ctx *ctx, const GeoHost &gh, int K, hipStream_t st)
 
 // Certificate of (lam, edges) restricted to the candidate graph.
 void certify_graph_dev(f2m_ctx *ctx, const GeoHost &gh, const Csr &csr, const int64_t *lam_label, int64_t m,
-                       const int32_t *eu, const int32_t *ev, const uint8_t *ex, hipStream_t st, int64_t out[4])
+                       const int32_t *eu, const int32_t *ev, const uint8_t *ex, hipStream_t st, int64_t out[4],
+                       const int8_t *b_label = nullptr)
 {
     const int64_t n = gh.g.n;
     LamView lv = place_lam(ctx, gh, lam_label, st);
     int32_t *deg = grow<int32_t>(ctx, ctx->c_deg, n);
     int32_t *cnt = grow<int32_t>(ctx, ctx->c_cnt, n);
-    int32_t *nb = grow<int32_t>(ctx, ctx->c_nb, kTop * n);
+    int32_t *nb = grow<int32_t>(ctx, ctx->c_nb, kCertNb * n);
     unsigned long long *acc = grow<unsigned long long>(ctx, ctx->c_acc, 4);
     ck(ctx, hipMemsetAsync(deg, 0, n * sizeof(int32_t), st), "memset");
     ck(ctx, hipMemsetAsync(cnt, 0, n * sizeof(int32_t), st), "memset");
@@ -725,14 +731,14 @@ void certify_graph_dev(f2m_ctx *ctx, const GeoHost &gh, const Csr &csr, const in
     ck(ctx, launch_graph_dual(gh.g, csr, lv.lam, acc, st), "graph_dual");
     ck(ctx, launch_cert_edges(gh.xy, n, m, eu, ev, ex, deg, cnt, nb, acc, st), "cert_edges");
     ck(ctx, launch_graph_membership(gh.g, csr, m, eu, ev, acc, st), "membership");
-    ck(ctx, launch_cert_nodes(lam_label, n, deg, cnt, nb, acc, st), "cert_nodes");
+    ck(ctx, launch_cert_nodes(lam_label, n, deg, cnt, nb, acc, b_label, st), "cert_nodes");
     unsigned long long h[4];
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, acc, sizeof(h), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     std::memcpy(h, ctx->scratch_host, sizeof(h));
     const int64_t rowneg = (int64_t)h[0], primal2 = (int64_t)h[1], viol = (int64_t)h[2], sl = (int64_t)h[3];
     out[0] = primal2;
-    out[1] = 2 * sl + rowneg / 2;
+    out[1] = sl + rowneg / 2;   // sl = sum_v b_v Lam_v
     out[2] = viol == 0 ? 1 : 0;
     out[3] = (viol == 0 && out[0] == out[1]) ? 1 : 0;
 }
@@ -801,6 +807,8 @@ struct LoopOut {
     int64_t *lam_last;     // device, sorted: Lam_{k_last}
     double ms_kind[3] = {0.0, 0.0, 0.0};     // scan time by ScanKind (time_kernels)
     int64_t launches_kind[3] = {0, 0, 0};
+    double update_ms = 0.0;                   // update launches (time_kernels)
+    double update_ms_kind[3] = {0.0, 0.0, 0.0};
 };
 
 // The GDP loop on device buffers.  lam0_label_dev: device Lam_0 by label
@@ -829,6 +837,10 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     int32_t *pflag = grow<int32_t>(ctx, ctx->pflag, sh.slices * nrb);
     int64_t *z4 = grow<int64_t>(ctx, ctx->z4, kTop * n);
     int32_t *i4 = grow<int32_t>(ctx, ctx->i4, kTop * n);
+    // the loop keeps the four smallest by position (coalesced stores); they
+    // go to label order once, after the loop
+    int64_t *z4p = grow<int64_t>(ctx, ctx->z4p, kTop * n);
+    int32_t *i4p = grow<int32_t>(ctx, ctx->i4p, kTop * n);
     int32_t *seed = grow<int32_t>(ctx, ctx->seed, kTop * n);
     Ctrl *cd = grow<Ctrl>(ctx, ctx->ctrl, 1);
     const int64_t k0 = cs.k0;
@@ -876,19 +888,25 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     bool done = false;
     while (!done) {
         for (; k <= max_iters && k - seen <= window; ++k) {
+            // three events per iteration: before the scan, between scan and
+            // update, after the update (the candidate graph: around its step)
             if (time_kernels) {
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < 3; ++q) {
                     evs.push_back(nullptr);
                     ck(ctx, hipEventCreate(&evs.back()), "hipEventCreate");
                 }
             }
-            hipEvent_t e0 = time_kernels ? evs[evs.size() - 2] : nullptr, e1 = time_kernels ? evs.back() : nullptr;
+            hipEvent_t e0 = time_kernels ? evs[evs.size() - 3] : nullptr;
+            hipEvent_t e1 = time_kernels ? evs[evs.size() - 2] : nullptr, e2 = time_kernels ? evs.back() : nullptr;
             if (csr) {
-                GraphStepArgs ga{gh.g, *csr, k, lam[k & 1], lam[(k + 1) & 1], best, z4, i4, nullptr, nullptr,
-                                 nullptr, cd, trace, slots, pw_dev};
+                GraphStepArgs ga{gh.g, *csr, k, lam[k & 1], lam[(k + 1) & 1], best, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, cd, trace, slots, pw_dev, z4p, i4p};
                 if (e0) ck(ctx, hipEventRecord(e0, st), "hipEventRecord");
                 ck(ctx, launch_graph_step(ga, st), "graph_step");
                 if (e1) ck(ctx, hipEventRecord(e1, st), "hipEventRecord");
+                const ControlArgs ca{cd, n, k, (n + kBlockThreads - 1) / kBlockThreads, slots, trace, nullptr, pw_dev, 0};
+                ck(ctx, launch_control(ca, st), "control");
+                if (e2) ck(ctx, hipEventRecord(e2, st), "hipEventRecord");
                 continue;
             }
             ScanArgs sa{};
@@ -912,9 +930,13 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
             if (e1) ck(ctx, hipEventRecord(e1, st), "hipEventRecord");
             UpdateArgs ua{gh.g, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
-                          thm, z4, i4, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows, lists ? 1 : 0,
-                          tpart, slots, kinds, pw_dev};
+                          thm, nullptr, nullptr, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows,
+                          lists ? 1 : 0, tpart, slots, kinds, pw_dev, z4p, i4p, lst, lcnt, 4 * sh.slices};
             ck(ctx, launch_update(ua, st), "update");
+            const ControlArgs ca{cd, n, k, (n + kBlockThreads - 1) / kBlockThreads, slots, trace, kinds, pw_dev,
+                                 lists ? 1 : 0};
+            ck(ctx, launch_control(ca, st), "control");
+            if (e2) ck(ctx, hipEventRecord(e2, st), "hipEventRecord");
         }
         // wait for the device to finish another iteration
         for (long spin = 0;; ++spin) {
@@ -935,6 +957,7 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             }
         }
     }
+    ck(ctx, launch_top_to_labels(z4p, i4p, gh.g.orig, n, z4, i4, st), "top_to_labels");
     ck(ctx, hipMemcpyAsync(ctx->ctrl_host, cd, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "copy");
     ck(ctx, hipStreamSynchronize(st), "sync");
     if (time_kernels) {
@@ -944,14 +967,17 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
         std::vector<int32_t> kk(std::max<int64_t>(ran, 1), kScanFull);
         const int64_t nk = kinds ? std::max<int64_t>(0, std::min<int64_t>(ran, trace_cap)) : 0;
         if (nk > 0) ck(ctx, hipMemcpy(kk.data(), kinds, nk * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
-        for (int64_t j = 0; j < ran && 2 * j + 1 < (int64_t)evs.size(); ++j) {
-            float ms = 0.0f;
-            ck(ctx, hipEventElapsedTime(&ms, evs[2 * j], evs[2 * j + 1]), "hipEventElapsedTime");
+        for (int64_t j = 0; j < ran && 3 * j + 2 < (int64_t)evs.size(); ++j) {
+            float ms = 0.0f, mu = 0.0f;
+            ck(ctx, hipEventElapsedTime(&ms, evs[3 * j], evs[3 * j + 1]), "hipEventElapsedTime");
+            ck(ctx, hipEventElapsedTime(&mu, evs[3 * j + 1], evs[3 * j + 2]), "hipEventElapsedTime");
             o.scan_ms += ms;
             ++o.scan_launches;
             const int kind = (kk[j] >= 0 && kk[j] < 3) ? kk[j] : kScanFull;
             o.ms_kind[kind] += ms;
             ++o.launches_kind[kind];
+            o.update_ms += mu;
+            o.update_ms_kind[kind] += mu;
         }
     }
     o.shape = sh;
@@ -1091,6 +1117,7 @@ struct InstanceState {
     const Csr *csr;            // candidate graph or null
     const int32_t *kinds;      // device scan kinds (with trace) or null
     const int64_t *lam_last;   // device, sorted: Lam_{k_last}
+    const int8_t *b_label = nullptr;   // device node degrees by label, or null (F2M)
 };
 
 void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, hipStream_t st,
@@ -1127,7 +1154,9 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
     const int64_t *lam_final_dev = lstar;
     const double t3 = now_s();
     bool have_x = false;
-    if (c.stop == F2M_STOP_TRIVIAL) {
+    // with degrees b a node may have up to 2 b = 6 edges of Z <= 0, more
+    // than its four smallest hold: the finish then produces x
+    if (c.stop == F2M_STOP_TRIVIAL && !gh.g.b) {
         const int64_t ns = kTop * n;
         int32_t *su = grow<int32_t>(ctx, ctx->slot_u, ns);
         int32_t *sv = grow<int32_t>(ctx, ctx->slot_v, ns);
@@ -1155,12 +1184,19 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
         ck(ctx, hipStreamSynchronize(st), "sync");
         if (!ctx->fwork) ctx->fwork = finish_work_create(ctx->is_worker ? 1 : finish_threads());
         FinishResult &fr = ctx->fres;
+        std::vector<int32_t> bpos;   // node degrees by position (b-matching), else empty
+        if (gh.g.b) {
+            std::vector<int8_t> b8(n);
+            download(ctx, {{gh.g.b, b8.data(), (size_t)n}}, st);
+            bpos.assign(b8.begin(), b8.end());
+        }
+        const int32_t *bp = bpos.empty() ? nullptr : bpos.data();
         if (is.csr) {
             GpuGraphPairs src(ctx, gh, xyp, *is.csr, st);
-            finish_exact(xyp_host, n, lamp_host, src, &fr, ctx->fwork);
+            finish_exact(xyp_host, n, lamp_host, src, &fr, ctx->fwork, bp);
         } else {
             GpuPairs src(ctx, gh, xyp, is.seed, st);
-            finish_exact(xyp_host, n, lamp_host, src, &fr, ctx->fwork);
+            finish_exact(xyp_host, n, lamp_host, src, &fr, ctx->fwork, bp);
         }
         res.finish_paths = fr.paths;
         res.finish_rounds = fr.rounds;
@@ -1189,10 +1225,10 @@ void complete_result(f2m_ctx *ctx, const InstanceState &is, const f2m_opts &o, h
     int64_t cert[4] = {0, 0, 0, 0}, cert_full[4] = {0, 0, 0, 0};
     if (have_x) {
         if (is.csr) {
-            certify_graph_dev(ctx, gh, *is.csr, lam_final_dev, m, eu, ev, ex, st, cert);
-            certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert_full);
+            certify_graph_dev(ctx, gh, *is.csr, lam_final_dev, m, eu, ev, ex, st, cert, is.b_label);
+            certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert_full, is.b_label);
         } else {
-            certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert);
+            certify_dev(ctx, gh, lam_final_dev, m, eu, ev, ex, st, cert, is.b_label);
             std::memcpy(cert_full, cert, sizeof(cert));
         }
     }
@@ -1259,6 +1295,8 @@ void gdp_step_run(f2m_ctx *ctx, const int32_t *xy, int64_t n, const int64_t *lam
                   b.z4, b.i4, b.seed, neg, zero, step, b.cd, b.trace};
     ua.slots = b.slots;
     ck(ctx, launch_update(ua, st), "update");
+    const ControlArgs ca{b.cd, n, 0, (n + kBlockThreads - 1) / kBlockThreads, b.slots, b.trace, nullptr, nullptr, 0};
+    ck(ctx, launch_control(ca, st), "control");
     ck(ctx, launch_unpermute(b.lo, gh.g.orig, n, lam_out, st), "unpermute");
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, b.trace, kTraceW * sizeof(int64_t), hipMemcpyDeviceToHost, st),
        "copy");
@@ -1635,6 +1673,13 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
         if (o.warm == F2M_WARM_MLP && !o.mlp_theta) fail(ctx, F2M_ERR_ARG, "warm start without mlp_theta");
         if (n < 3) fail(ctx, F2M_ERR_INFEASIBLE, "F2M needs n >= 3");
         if (n >= (int64_t)1 << 30) fail(ctx, F2M_ERR_ARG, "n must be below 2^30");
+        if (o.degree_b) {
+            if (n < 4) fail(ctx, F2M_ERR_ARG, "degree_b needs n >= 4");
+            if (o.warm == F2M_WARM_MLP || o.warm == F2M_WARM_GRAPH)
+                fail(ctx, F2M_ERR_ARG, "degree_b takes a cold or a user warm start");
+            for (int64_t v = 0; v < n; ++v)
+                if (o.degree_b[v] < 1 || o.degree_b[v] > 3) fail(ctx, F2M_ERR_ARG, "degree_b entries must be 1, 2 or 3");
+        }
         ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
         hipStream_t st = pick_stream(ctx, &o);
         const double t0 = now_s();
@@ -1667,7 +1712,18 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
             *out = res;
             return s;
         }
-        const GeoHost gh = setup_geo(ctx, xy_dev, n, st);
+        GeoHost gh = setup_geo(ctx, xy_dev, n, st);
+        const int8_t *b_label_dev = nullptr;
+        if (o.degree_b) {
+            // the rows' right-hand sides b_v (Sec. 3) by label, then by position
+            std::vector<int8_t> b8(o.degree_b, o.degree_b + n);
+            int8_t *bl = grow<int8_t>(ctx, ctx->deg_label, n);
+            int8_t *bp = grow<int8_t>(ctx, ctx->deg_pos, n);
+            upload(ctx, {{b8.data(), bl, (size_t)n}}, st);
+            ck(ctx, launch_b_to_positions(bl, gh.g.orig, n, bp, st), "b_to_positions");
+            gh.g.b = bp;
+            b_label_dev = bl;
+        }
         const int64_t *lam0_dev = nullptr;
         if (o.warm == F2M_WARM_USER) {
             int64_t *d = grow<int64_t>(ctx, ctx->c_lam_label, n);
@@ -1710,13 +1766,15 @@ f2m_status f2m_solve(f2m_ctx *ctx, const int32_t *coords, int64_t n, const f2m_o
                          o.record_trace ? static_cast<const int64_t *>(ctx->trace.p) : nullptr,
                          on_graph ? &csr : nullptr,
                          (o.record_trace && !on_graph) ? static_cast<const int32_t *>(ctx->kinds.p) : nullptr,
-                         lo.lam_last};
+                         lo.lam_last, b_label_dev};
         complete_result(ctx, is, o, st, res);
         res.scan_ms = lo.scan_ms;
+        res.update_ms = lo.update_ms;
         res.scan_launches = lo.scan_launches;
         for (int q = 0; q < 3; ++q) {
             res.scan_ms_kind[q] = lo.ms_kind[q];
             res.scan_launches_kind[q] = lo.launches_kind[q];
+            res.update_ms_kind[q] = lo.update_ms_kind[q];
             res.scan_pairs_kind[q] = (int64_t)lo.c.pairs_kind[q];
         }
         res.scan_rows = lo.shape.rows;
@@ -1764,6 +1822,7 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             fail(ctx, F2M_ERR_ARG, "bad warm start");
         const CtrlStart cs = resume_start(ctx, o);
         if (offsets[0] != 0) fail(ctx, F2M_ERR_ARG, "offsets[0] must be 0");
+        if (o.degree_b) fail(ctx, F2M_ERR_ARG, "the batched solve takes no degree_b");
         for (int32_t i = 0; i < n_inst; ++i) {
             if (offsets[i + 1] - offsets[i] < 3) fail(ctx, F2M_ERR_INFEASIBLE, "every instance needs n >= 3");
             if (offsets[i + 1] - offsets[i] >= (int64_t)1 << 30) fail(ctx, F2M_ERR_ARG, "instance too large");
@@ -1929,11 +1988,12 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
             for (int j = 0; j < chunk; ++j) {
                 hipError_t e1 = launch_scan_batch(sa_d, si_d, (int64_t)sitems.size(), 1, cull, st);
                 hipError_t e2 = launch_update_batch(ua_d, ui_d, (int64_t)uitems.size(), st);
-                if (e1 != hipSuccess || e2 != hipSuccess) {
+                hipError_t e3 = e2 == hipSuccess ? launch_control_batch(ua_d, n_inst, st) : e2;
+                if (e1 != hipSuccess || e3 != hipSuccess) {
                     hipGraph_t g2 = nullptr;
                     (void)hipStreamEndCapture(st, &g2);
                     if (g2) (void)hipGraphDestroy(g2);
-                    ck(ctx, e1 != hipSuccess ? e1 : e2, "batched launch");
+                    ck(ctx, e1 != hipSuccess ? e1 : e3, "batched launch");
                 }
             }
             ck(ctx, hipStreamEndCapture(st, &graph), "hipStreamEndCapture");

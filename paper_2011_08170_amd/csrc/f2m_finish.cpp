@@ -130,10 +130,12 @@ private:
 // (reset): its buffers keep their capacity.
 class DoubleCover {
 public:
-    void reset(const int32_t *xy, int64_t n, const int64_t *lam)
+    // b: every node's degree (right-hand side of its row), or null for 2
+    void reset(const int32_t *xy, int64_t n, const int64_t *lam, const int32_t *b)
     {
         xy_ = xy;
         n_ = n;
+        b_ = b;
         // search state: dist is infinite outside the last search's touched set
         const bool same = (int64_t)cp_.size() == 2 * n;
         if (same) {
@@ -146,9 +148,9 @@ public:
         for (int64_t v = 0; v < n; ++v) {
             const int64_t al = floor_half(lam[v]);
             cp_[v].pot = al;          // alpha_v
-            cp_[v].ex = 2;            // left copies supply 2
+            cp_[v].ex = deg(v);       // left copies supply b_v
             cp_[n + v].pot = lam[v] - al;   // beta_v
-            cp_[n + v].ex = -2;       // right copies demand 2
+            cp_[n + v].ex = -deg(v);  // right copies demand b_v
             src_.push_back(v);
         }
         A_ = B_ = 0;
@@ -162,6 +164,7 @@ public:
     }
 
     int64_t edges() const { return (int64_t)e_.size(); }
+    int32_t deg(int64_t v) const { return b_ ? b_[v] : 2; }
 
     // The first candidates in bulk: the pair source's keys and costs, the
     // initial flow (negative-reduced-cost bits under the starting
@@ -211,8 +214,8 @@ public:
                         out += ed.y[ed.a != v];   // the arc that leaves v'
                         in += ed.y[ed.b != v];    // the arc that enters v''
                     }
-                    cp_[v].ex = 2 - out;
-                    cp_[n_ + v].ex = -2 + in;
+                    cp_[v].ex = deg(v) - out;
+                    cp_[n_ + v].ex = -deg(v) + in;
                     start_[v] = s0;
                     end_[v] = s1;
                     cap_[v] = is[v + 1];
@@ -223,8 +226,8 @@ public:
             keys_.clear();
             e_.clear();
             for (int64_t v = 0; v < n_; ++v) {
-                cp_[v].ex = 2;
-                cp_[n_ + v].ex = -2;
+                cp_[v].ex = deg(v);
+                cp_[n_ + v].ex = -deg(v);
                 start_[v] = end_[v] = cap_[v] = 0;
             }
             return false;
@@ -873,6 +876,7 @@ private:
     }
 
     const int32_t *xy_ = nullptr;
+    const int32_t *b_ = nullptr;     // degrees, or null for 2
     int64_t n_ = 0;
     int64_t A_ = 0, B_ = 0;          // global offsets of alpha and beta
     std::vector<Copy> cp_;           // node copies: left v, right n + v
@@ -920,7 +924,7 @@ FinishWork *finish_work_create(int threads, int64_t parallel_min)
 void finish_work_destroy(FinishWork *work) { delete work; }
 
 void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out,
-                  FinishWork *work)
+                  FinishWork *work, const int32_t *b)
 {
     std::unique_ptr<FinishWork> own;
     if (!work) {
@@ -938,7 +942,7 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
     r.t_collect = r.t_build = r.t_flow = 0.0;
     double t = secs();
     DoubleCover &g = work->g;
-    g.reset(xy, n, lam0);
+    g.reset(xy, n, lam0, b);
     PairList &pl = work->pl;
     std::vector<int64_t> &lam = work->lam;
     std::string err;

@@ -5,7 +5,8 @@
 // need not be optimal (degenerate cases, Sec. 3 of arXiv 2011.08170).  The
 // finish solves F2M exactly as a min-cost flow on the bipartite double
 // cover (left copy v', right copy v'', arc v'->u'' of cost c_uv and
-// capacity 1, every copy of degree 2; its optimum is twice the F2M optimum
+// capacity 1, every copy of degree 2 -- or b_v, see finish_exact; its
+// optimum is twice the F2M optimum
 // and x_e = (y_u'v'' + y_v'u'')/2), by a primal-dual method: Dijkstra on
 // reduced costs from every node with excess, a potential update, then unit
 // augmentations along zero-reduced-cost paths.  It starts from the GDP's
@@ -83,8 +84,10 @@ FinishWork *finish_work_create(int threads = 1, int64_t parallel_min = 256);
 void finish_work_destroy(FinishWork *work);
 
 // work may be null (a temporary one is used).  out's vectors keep their
-// capacity when it is reused.
+// capacity when it is reused.  b: the degree of every node (the right-hand
+// side b_v of its row, 1 to 3: the b-matching of Sec. 3), or null for 2
+// (F2M); both copies of node v then carry b_v units.
 void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource &src, FinishResult *out,
-                  FinishWork *work = nullptr);
+                  FinishWork *work = nullptr, const int32_t *b = nullptr);
 
 }  // namespace f2m

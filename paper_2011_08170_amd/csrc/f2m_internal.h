@@ -29,12 +29,12 @@ constexpr int kSubCols = 32;
 constexpr int kSubs = kTileCols / kSubCols;
 constexpr int kBoxStride = 1 + kSubs;
 
-// Device-resident control block of the GDP loop.  The last block of the
-// update kernel to arrive sums the blocks' slots, writes the iteration
-// record and takes the stop decision (see reduce_and_control).
+// Device-resident control block of the GDP loop.  A one-block control
+// kernel after each update launch sums the update blocks' slots, writes the
+// iteration record and takes the stop decision (see control_body).  Every
+// field is 64 bits wide: the control kernel reads and writes the block as
+// an array of words.
 struct Ctrl {
-    unsigned int blocks_done;   // groups of update blocks arrived
-    unsigned int pad0;
     // loop state
     long long done;        // 1 once the loop has stopped
     long long stop;        // F2M_STOP_* or 0
@@ -64,16 +64,11 @@ struct Ctrl {
     unsigned long long pairs_kind[3];   // pairs_tested split by the scans' ScanKind
     long long list_uses;   // scans that evaluated the lists only
     long long list_builds; // scans that built lists
-    // arrival counters of the update's blocks (see reduce_and_control):
-    // group g counts at grp_done[32 g], one 128-byte line each
-    unsigned int grp_done[8 * 32];
 };
 
 // Blocks of an update launch leave their part of the iteration record in
-// their own slot of kSlotW 64-bit words; arrivals are counted in
-// kArriveGroups groups so that no single address takes one atomic per block.
+// their own slot of kSlotW 64-bit words, which the control kernel sums.
 constexpr int kSlotW = 16;
-constexpr int kArriveGroups = 8;
 // Kind of the scan of an iteration (UpdateArgs::scan_kind)
 enum ScanKind { kScanFull = 0, kScanBuild = 1, kScanList = 2 };
 
@@ -84,6 +79,9 @@ struct Geo {
     const int32_t *pos;         // label -> position
     const float4 *box;          // per tile and sub-tile (kBoxStride per tile): xmin, xmax, ymin, ymax
     float xy2max;               // >= max over cities of x^2 + y^2 (centred)
+    // by position: the right-hand side b_v of each node's degree row (1, 2
+    // or 3: the b-matching of Sec. 3), or null for 2 everywhere (F2M)
+    const int8_t *b = nullptr;
 };
 
 // Column records, one per position: centred coordinates, h = Lam/2 and
@@ -181,6 +179,16 @@ struct UpdateArgs {
     // optional: host-visible progress word, 2 k + (1 if the loop stopped at
     // k), written by the last block of iteration k
     long long *progress;
+    // optional: the four smallest by position, z4p[j n + p] and their labels
+    // i4p[j n + p] (coalesced; z4 / i4 by label may then be null)
+    int64_t *z4p;
+    int32_t *i4p;
+    // the scan's candidate lists (ScanArgs::lst, lcnt) over nparts parts:
+    // with lists set, an iteration whose ctrl->list_ok holds is evaluated
+    // here from the lists (the scan exits at once)
+    const int32_t *lst;
+    const int32_t *lcnt;
+    int64_t nparts;
 };
 
 // candidate list entries per row and wave (see ScanArgs::lst); the margin
@@ -214,6 +222,8 @@ struct GraphStepArgs {
     int64_t *trace;
     unsigned long long *slots;  // per-block record slots, kSlotW words per block
     long long *progress;        // optional, as UpdateArgs::progress
+    int64_t *z4p;               // optional, as UpdateArgs::z4p / i4p
+    int32_t *i4p;
 };
 
 // Batched loop: one launch covers every instance.  Work items are tables in
@@ -325,6 +335,23 @@ hipError_t launch_ctrl_init(Ctrl *ctrl, int64_t max_iters, int64_t trace_cap, in
                             hipStream_t st);
 hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_per_thread, hipStream_t st);
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st);
+// The control of iteration k after an update (or candidate-graph step)
+// launch of nblk blocks whose slots hold their parts of the record.
+struct ControlArgs {
+    Ctrl *ctrl;
+    int64_t n, k, nblk;
+    const unsigned long long *slots;
+    int64_t *trace;             // or null
+    int32_t *kinds;             // or null
+    long long *progress;        // or null
+    int lists;                  // the loop's scans keep candidate lists
+};
+hipError_t launch_control(const ControlArgs &a, hipStream_t st);
+// batched: one block per instance (args: the instances' update arguments)
+hipError_t launch_control_batch(const UpdateArgs *args_dev, int64_t ninst, hipStream_t st);
+// z4[4v + j], i4[4v + j] by label from z4p[j n + p], i4p[j n + p] by position
+hipError_t launch_top_to_labels(const int64_t *z4p, const int32_t *i4p, const int32_t *orig, int64_t n, int64_t *z4,
+                                int32_t *i4, hipStream_t st);
 hipError_t launch_extract_trivial(const int64_t *z4, const int32_t *i4, int64_t n,
                                   int32_t *slot_u, int32_t *slot_v, uint8_t *slot_x2,
                                   hipStream_t st);
@@ -335,8 +362,14 @@ int64_t compact_block_tmp_len(int64_t nslots);
 hipError_t launch_cert_edges(const int32_t *xy, int64_t n, int64_t m, const int32_t *eu,
                              const int32_t *ev, const uint8_t *ex2, int32_t *deg, int32_t *cnt,
                              int32_t *nb, unsigned long long *acc, hipStream_t st);
+// b by label, or null (F2M): every doubled degree must be 2 b_v; acc[3] +=
+// sum_v b_v Lam_v.  nb holds kCertNb neighbour slots per node.
 hipError_t launch_cert_nodes(const int64_t *lam, int64_t n, const int32_t *deg,
                              const int32_t *cnt, const int32_t *nb, unsigned long long *acc,
-                             hipStream_t st);
+                             const int8_t *b, hipStream_t st);
+constexpr int kCertNb = 6;
+// b_pos[p] = b_label[orig[p]]
+hipError_t launch_b_to_positions(const int8_t *b_label, const int32_t *orig, int64_t n, int8_t *b_pos,
+                                 hipStream_t st);
 
 }  // namespace f2m

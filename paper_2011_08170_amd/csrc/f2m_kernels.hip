@@ -562,11 +562,12 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
     const int64_t n = a.g.n;
     const int64_t S0 = a.interleave > 0 ? a.interleave : 1, sl0 = a.interleave > 0 ? sl : 0;
     const int64_t S = QUAD ? 4 * S0 : S0, sid = QUAD ? 4 * sl0 + wave : sl0;
-    // candidate lists: evaluate them (use) or store them during the walk
-    // (build, margin 2 LD); see ScanArgs::lst
+    // candidate lists (see ScanArgs::lst): an iteration that may use them
+    // is left to the update, which evaluates them per row; a full scan may
+    // store them during the walk (build, margin 2 LD)
     const bool lists = QUAD && MODE == kModeGdp && a.lst != nullptr;
-    const bool use = lists && a.lv.ctrl->list_ok != 0;
-    const int64_t LD = (lists && !use) ? a.lv.ctrl->list_D : 0;
+    if (lists && a.lv.ctrl->list_ok != 0) return;
+    const int64_t LD = lists ? a.lv.ctrl->list_D : 0;
     const bool build = LD > 0;
     const float colmax = col_bound(a.g.xy2max, a.lv.ctrl->maxabs_lam);
     if (t == 0) bany = 0;
@@ -586,8 +587,6 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         int64_t th;
         if (MODE == kModeCert) {
             th = 0;
-        } else if (use) {
-            th = kThetaNone;   // the lists are exact: no bound needed
         } else {
             int64_t mx;
             const bool ok = a.seed && seeded_bound(a, p, cv.x, cv.y, rw.lamv, &mx);
@@ -696,40 +695,7 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         }
     };
 
-    if (use) {
-        // the row's list from the last building scan holds every column
-        // that can matter now: evaluate those only
-        int cnt = 0;
-        if (p < n) {
-            cnt = min(max(a.lcnt[lcidx], 0), kLW);
-            // four entries' gathers in flight at a time
-            for (int i0 = 0; i0 < cnt; i0 += 4) {
-                float4 cu[4];
-                long long lu[4];
-                int32_t ou[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (i0 + q < cnt) {
-                        const int64_t u = a.lst[lbase + (int64_t)(i0 + q) * n];
-                        cu[q] = a.lv.col[u];
-                        lu[q] = a.lv.lam[u];
-                        ou[q] = a.g.orig[u];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (i0 + q >= cnt) break;
-                    const int64_t z = exact_z(rw.xv, rw.yv, rw.lamv, cu[q].x, cu[q].y, lu[q]);
-                    if (z < 0) { ++neg; rn += z; }
-                    else if (z == 0) ++zero;
-                    top.insert(z, ou[q]);
-                }
-            }
-        }
-        tested += (unsigned long long)wave_sum((long long)cnt);
-        scanned = true;
-    }
-    if (w1 > w0 && !use) {
+    if (w1 > w0) {
         // The culling radius comes from the rows' starting thresholds: every
         // slice must see the same survivors in the same order, or the
         // round-robin deal would lose or repeat sub-tiles.
@@ -937,35 +903,58 @@ __global__ __launch_bounds__(kBlock) void k_rowscan_batch(const ScanArgs *args, 
 // ---------------------------------------------------------------------------
 
 struct RowOut {
-    unsigned long long sumlam = 0, rowneg = 0, unsat = 0, bad = 0, nonzero = 0, hsh = 0;
+    unsigned long long sumlam = 0, rowneg = 0, unsat = 0, bad = 0, nonzero = 0, hsh = 0, sumblam = 0;
     long long maxstep = 0, maxabs = 0;
     float hmax = -INFINITY;
 };
 
 // Step of the row at position p from its merged statistics: eq. 10 on the
 // 2nd and 3rd smallest Z; writes Lam_{k+1} and the per-node outputs.
+// The four smallest go to z4p / i4p by position ([j][n], coalesced) when
+// those are given, and to z4 / i4 by label (4v + j) when those are.
 __device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &top, int64_t cn, int64_t cz,
                                          int64_t rn, int64_t lamv, bool copy_best, int64_t *lam_out,
                                          int64_t *lam_best, int64_t *z4, int32_t *i4, int32_t *seed,
-                                         int32_t *neg, int32_t *zero, int64_t *step, float4 *col, RowOut &o)
+                                         int32_t *neg, int32_t *zero, int64_t *step, float4 *col, RowOut &o,
+                                         int64_t *z4p = nullptr, int32_t *i4p = nullptr)
 {
     const int64_t n = g.n;
     const int64_t v = g.orig[p];
-    // a row needs a third edge (n >= 4 on the complete graph)
-    const int64_t st = top.id[2] != kNoIdx ? gdp_step(top.z[1] + top.z[2]) : 0;
+    // eq. 10 for a row with right-hand side b (Sec. 3): the b-th and
+    // (b+1)-th smallest Z (F2M: b = 2, the 2nd and 3rd); the row needs b + 1
+    // edges (n >= 4 on the complete graph)
+    const int bv = g.b ? (int)g.b[p] : 2;
+    // the three candidates are formed from values and then selected (a
+    // selected index into the list would put it in scratch memory)
+    const int64_t z0 = top.z[0], z1 = top.z[1], z2 = top.z[2], z3 = top.z[3];
+    const bool h1 = top.id[1] != kNoIdx, h2 = top.id[2] != kNoIdx, h3 = top.id[3] != kNoIdx;
+    const bool has = bv == 1 ? h1 : (bv == 2 ? h2 : h3);
+    const int64_t st1 = h1 ? gdp_step(z0 + z1) : 0, st2 = h2 ? gdp_step(z1 + z2) : 0, st3 = h3 ? gdp_step(z2 + z3) : 0;
+    const int64_t st = has ? (bv == 1 ? st1 : (bv == 2 ? st2 : st3)) : 0;
+    const bool un1 = z0 > 0 || z1 < 0, un2 = z1 > 0 || z2 < 0, un3 = z2 > 0 || z3 < 0;
+    const bool unsat = bv == 1 ? un1 : (bv == 2 ? un2 : un3);
     const int64_t nxt = lamv + st;
     if (copy_best) lam_best[p] = lam_out[p];
     lam_out[p] = nxt;
     if (col) {
-        const float4 cv = col_record(col[p].x, col[p].y, nxt);
-        col[p] = cv;
+        // only the (h, q) half changes: the (x, y) half of every record stays
+        // untouched, so threads of the same launch may read it (list step)
+        const float2 xy = reinterpret_cast<const float2 *>(col)[2 * p];
+        const float4 cv = col_record(xy.x, xy.y, nxt);
+        reinterpret_cast<float2 *>(col)[2 * p + 1] = make_float2(cv.z, cv.w);
         o.hmax = cv.z;
     }
 #pragma unroll
     for (int j = 0; j < kTop; ++j) {
         const bool ok = top.id[j] != kNoIdx;
-        z4[kTop * v + j] = top.z[j];
-        i4[kTop * v + j] = ok ? top.id[j] : -1;
+        if (z4p) {
+            z4p[j * n + p] = top.z[j];
+            i4p[j * n + p] = ok ? top.id[j] : -1;
+        }
+        if (z4) {
+            z4[kTop * v + j] = top.z[j];
+            i4[kTop * v + j] = ok ? top.id[j] : -1;
+        }
         if (seed) seed[j * n + p] = ok ? g.pos[top.id[j]] : -1;
     }
     const int64_t deg2 = 2 * cn + cz;
@@ -973,35 +962,28 @@ __device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &to
     if (zero) zero[v] = (int32_t)cz;
     if (step) step[v] = st;
     o.sumlam = (unsigned long long)lamv;
+    o.sumblam = (unsigned long long)(bv * lamv);
     o.rowneg = (unsigned long long)rn;
-    o.unsat = (top.z[1] > 0 || top.z[2] < 0) ? 1 : 0;
-    o.bad = deg2 != 4 ? 1 : 0;
+    o.unsat = unsat ? 1 : 0;
+    o.bad = deg2 != 2 * bv ? 1 : 0;
     o.nonzero = st != 0 ? 1 : 0;
     o.maxstep = st < 0 ? -st : st;
     o.maxabs = nxt < 0 ? -nxt : nxt;
     o.hsh = mix64((uint64_t)lamv ^ (0x9E3779B97F4A7C15ULL * (uint64_t)(v + 1)));
 }
 
-// Block reductions of the rows' records into the block's slot, then the last
-// block to arrive sums the slots, writes the iteration record, takes the stop
-// decision and resets the arrival counters.  Called by every thread of the
-// block.  The slots are written and read with agent-scope atomic stores and
-// loads, ordered by release/acquire fences around the arrival counters; the
-// counters are split over kArriveGroups addresses (block b counts in group
-// b mod kArriveGroups, the last of a group counts once more in blocks_done),
-// so no address takes more than about nblk / kArriveGroups atomics.
-// `tested` is the block's count of scanned pairs (summed into
-// pairs_tested); `kinds` (or null) receives the scan kind of iteration k.
-__device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t k, Ctrl *ctrl, int64_t *trace,
-                                                   float *tile_hmax, int64_t blk, int64_t nblk,
-                                                   unsigned long long *slots, bool lists = false,
-                                                   unsigned long long tested = 0, int32_t *kinds = nullptr,
-                                                   long long *progress = nullptr)
+// Block reductions of the rows' records into the block's slot (plain stores:
+// the control kernel that sums the slots runs after this launch).  Called by
+// every thread of the block.  `tested` (summed over the block's threads) is
+// the count of scanned pairs added to pairs_tested.
+constexpr int kRecV = 10;   // record entries: 8 of the Ctrl order, the pairs tested, sum b Lam
+
+__device__ __forceinline__ void block_record(RowOut o, float *tile_hmax, int64_t blk, unsigned long long *slots,
+                                             unsigned long long tested)
 {
-    constexpr int kV = 9;   // record entries reduced: 8 of the Ctrl order plus the pairs tested
+    constexpr int kV = kRecV;
     __shared__ unsigned long long red8[kBlock / 64][kV];
     __shared__ float redf[kBlock / 64];
-    __shared__ int s_last;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (tile_hmax) {
         // a block of kBlock positions is one column tile
@@ -1011,9 +993,10 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
         if (threadIdx.x == 0) tile_hmax[blk * kBoxStride] = hm;
     }
     // entries: sum Lam, sum rowneg, #unsat, #bad, max step, #nonzero, hash,
-    // max |Lam_{k+1}|, pairs tested; entries 4 and 7 are maxima, the rest sums
+    // max |Lam_{k+1}|, pairs tested, sum b Lam; entries 4 and 7 are maxima,
+    // the rest sums
     unsigned long long v[kV] = {o.sumlam, o.rowneg, o.unsat, o.bad, (unsigned long long)o.maxstep, o.nonzero,
-                                o.hsh, (unsigned long long)o.maxabs, threadIdx.x == 0 ? tested : 0ULL};
+                                o.hsh, (unsigned long long)o.maxabs, tested, o.sumblam};
 #pragma unroll
     for (int i = 0; i < kV; ++i) v[i] = (i == 4 || i == 7) ? wave_max(v[i]) : wave_sum(v[i]);
     if (lane == 0) {
@@ -1021,48 +1004,40 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
         for (int i = 0; i < kV; ++i) red8[w][i] = v[i];
     }
     __syncthreads();
-    if (w == 0) {
-        if (lane < kV) {
-            unsigned long long mine = red8[0][lane];
-            for (int q = 1; q < kBlock / 64; ++q) {
-                const unsigned long long x = red8[q][lane];
-                mine = (lane == 4 || lane == 7) ? (x > mine ? x : mine) : mine + x;
-            }
-            __hip_atomic_store(&slots[blk * kSlotW + lane], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (w == 0 && lane < kV) {
+        unsigned long long mine = red8[0][lane];
+        for (int q = 1; q < kBlock / 64; ++q) {
+            const unsigned long long x = red8[q][lane];
+            mine = (lane == 4 || lane == 7) ? (x > mine ? x : mine) : mine + x;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) {
-            const int64_t g = blk % kArriveGroups;
-            const int64_t ng = nblk < kArriveGroups ? nblk : kArriveGroups;
-            const unsigned gsize = (unsigned)((nblk - g + kArriveGroups - 1) / kArriveGroups);
-            int last = 0;
-            if (atomicAdd(&ctrl->grp_done[32 * g], 1u) == gsize - 1) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-                last = atomicAdd(&ctrl->blocks_done, 1u) == (unsigned)(ng - 1);
-                if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-            s_last = last;
-        }
+        slots[blk * kSlotW + lane] = mine;
     }
-    __syncthreads();
-    if (!s_last) return;
+}
 
-    // last block: every block's slot is written; all threads sum them
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// The iteration's control, by one block after the launch that filled the
+// nblk slots: sums them, writes the iteration record, takes the stop
+// decision and the candidate lists' decision (see ScanArgs::lst).  `kinds`
+// (or null) receives the scan kind of iteration k; `progress` (or null) the
+// host's progress word.
+__device__ __forceinline__ void control_body(int64_t n, int64_t k, Ctrl *ctrl, int64_t *trace, int64_t nblk,
+                                             const unsigned long long *slots, bool lists, int32_t *kinds,
+                                             long long *progress)
+{
+    constexpr int kV = kRecV;
+    __shared__ unsigned long long red8[kBlock / 64][kV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     unsigned long long acc[kV];
 #pragma unroll
     for (int i = 0; i < kV; ++i) acc[i] = 0;
     for (int64_t b = threadIdx.x; b < nblk; b += kBlock) {
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
-            const unsigned long long x =
-                __hip_atomic_load(&slots[b * kSlotW + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long x = slots[b * kSlotW + i];
             acc[i] = (i == 4 || i == 7) ? (x > acc[i] ? x : acc[i]) : acc[i] + x;
         }
     }
 #pragma unroll
     for (int i = 0; i < kV; ++i) acc[i] = (i == 4 || i == 7) ? wave_max(acc[i]) : wave_sum(acc[i]);
-    __syncthreads();   // red8 is free again
     if (lane == 0) {
 #pragma unroll
         for (int i = 0; i < kV; ++i) red8[w][i] = acc[i];
@@ -1086,67 +1061,82 @@ __device__ __forceinline__ void reduce_and_control(RowOut o, int64_t n, int64_t 
     const unsigned long long hh = __shfl(got, 6, 64);
     const long long mx = (long long)__shfl(got, 7, 64);
     const unsigned long long tt = __shfl(got, 8, 64);
-    if (lane < kArriveGroups) ctrl->grp_done[32 * lane] = 0u;
+    const long long sbl = (long long)__shfl(got, 9, 64);
+    // the control block is read into LDS with one load per lane, decided on
+    // there by lane 0 and written back with one store per lane (a chain of
+    // dependent global accesses costs more than the decision itself)
+    constexpr int kCW = (int)(sizeof(Ctrl) / sizeof(long long));
+    static_assert(sizeof(Ctrl) % sizeof(long long) == 0 && kCW <= 64, "Ctrl fits one wave's words");
+    __shared__ long long cw[kCW];
+    long long *const gw = reinterpret_cast<long long *>(ctrl);
+    if (lane < kCW) cw[lane] = gw[lane];
+    wave_sync();
     if (lane == 0) {
-        ctrl->blocks_done = 0u;
-        ctrl->pairs_tested += tt;
-        // each unordered pair sits in two rows
-        const long long dual2 = 2 * sl + rnsum / 2;
-        const long long kr = k - ctrl->k_first;   // record index of iteration k
-        if (trace && kr < ctrl->trace_cap) {
+        Ctrl *const c = reinterpret_cast<Ctrl *>(cw);
+        c->pairs_tested += tt;
+        // 2 L = sum_v b_v Lam_v + sum_e min(0, Z_e); each unordered pair sits
+        // in two rows
+        const long long dual2 = sbl + rnsum / 2;
+        const long long kr = k - c->k_first;   // record index of iteration k
+        if (trace && kr < c->trace_cap) {
             long long *rec = (long long *)trace + kTraceW * kr;
             rec[0] = k; rec[1] = dual2; rec[2] = un; rec[3] = bd;
             rec[4] = ms; rec[5] = nz; rec[6] = (long long)hh; rec[7] = sl;
         }
-        if (ctrl->best_k < 0 || dual2 > ctrl->best_dual2) { ctrl->best_dual2 = dual2; ctrl->best_k = k; }
+        if (c->best_k < 0 || dual2 > c->best_dual2) { c->best_dual2 = dual2; c->best_k = k; }
         long long stop = 0;
         if (bd == 0) stop = 1;                                                      // trivial
-        else if (ctrl->handoff_div > 0 && un * ctrl->handoff_div <= n) stop = 5;    // handoff
+        else if (c->handoff_div > 0 && un * c->handoff_div <= n) stop = 5;    // handoff
         else if (nz == 0) stop = 2;                                                 // fixed
-        else if (k >= 2 && (kr >= 2 || ctrl->hvalid) && hh == ctrl->h2) stop = 3;  // cycle
-        else if (k >= ctrl->max_iters) stop = 4;                                    // cap
-        else if (mx >= kLamLimit) { stop = 4; ctrl->overflow = 1; }
+        else if (k >= 2 && (kr >= 2 || c->hvalid) && hh == c->h2) stop = 3;  // cycle
+        else if (k >= c->max_iters) stop = 4;                                    // cap
+        else if (mx >= kLamLimit) { stop = 4; c->overflow = 1; }
         int32_t kind = kScanFull;
         if (lists) {
             // Z moves by at most twice the max step per iteration: lists
             // built with margin 2D stay exact while the steps since the
             // build sum to at most D / 2
-            if (kr == 0) ctrl->list_ms0 = ms;
-            const bool used = ctrl->list_ok != 0;
-            const bool built = !used && ctrl->list_D > 0;
+            if (kr == 0) c->list_ms0 = ms;
+            const bool used = c->list_ok != 0;
+            const bool built = !used && c->list_D > 0;
             kind = used ? kScanList : (built ? kScanBuild : kScanFull);
-            ctrl->list_uses += used ? 1 : 0;
-            ctrl->list_builds += built ? 1 : 0;
-            const long long d = used ? ctrl->list_d + ms : ms;
-            const bool ok = (used || (built && !ctrl->list_over)) && 2 * d <= ctrl->list_D;
-            ctrl->list_ok = ok ? 1 : 0;
-            ctrl->list_d = ok ? d : 0;
+            c->list_uses += used ? 1 : 0;
+            c->list_builds += built ? 1 : 0;
+            const long long d = used ? c->list_d + ms : ms;
+            const bool ok = (used || (built && !c->list_over)) && 2 * d <= c->list_D;
+            c->list_ok = ok ? 1 : 0;
+            c->list_d = ok ? d : 0;
             if (!ok) {
                 // a build whose lists overflowed caps the later margins
-                if (built && ctrl->list_over) ctrl->list_Dmax = ctrl->list_D / 2;
+                if (built && c->list_over) c->list_Dmax = c->list_D / 2;
                 const long long D = kListMult * ms;
-                const bool go = ms * 16 <= ctrl->list_ms0 && (ctrl->list_Dmax == 0 || D <= ctrl->list_Dmax);
-                ctrl->list_D = go ? D : 0;
-                ctrl->list_over = 0;
+                const bool go = ms * 16 <= c->list_ms0 && (c->list_Dmax == 0 || D <= c->list_Dmax);
+                c->list_D = go ? D : 0;
+                c->list_over = 0;
             }
         }
-        if (kinds && kr < ctrl->trace_cap) kinds[kr] = kind;
-        ctrl->pairs_kind[kind] += tt;
-        ctrl->k_last = k;
-        ctrl->dual2_last = dual2;
+        if (kinds && kr < c->trace_cap) kinds[kr] = kind;
+        c->pairs_kind[kind] += tt;
+        c->k_last = k;
+        c->dual2_last = dual2;
         if (stop) {
-            ctrl->stop = stop;
-            ctrl->kstar = (stop == 3 || stop == 4) ? ctrl->best_k : k;
-            ctrl->done = 1;
+            c->stop = stop;
+            c->kstar = (stop == 3 || stop == 4) ? c->best_k : k;
+            c->done = 1;
         } else {
-            ctrl->h2 = ctrl->h1;
-            ctrl->h1 = hh;
-            ctrl->k_next = k + 1;
+            c->h2 = c->h1;
+            c->h1 = hh;
+            c->k_next = k + 1;
         }
-        ctrl->maxabs_lam = mx;
-        // the host waits on this word instead of synchronising the stream
-        if (progress)
-            __hip_atomic_store(progress, 2 * k + (stop ? 1 : 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        c->maxabs_lam = mx;
+    }
+    wave_sync();
+    if (lane < kCW) gw[lane] = cw[lane];
+    // the host waits on this word instead of synchronising the stream; it
+    // reads nothing else before it synchronises, so no ordering is needed
+    if (progress && lane == 0) {
+        const Ctrl *const c = reinterpret_cast<const Ctrl *>(cw);
+        __hip_atomic_store(progress, 2 * k + (c->done ? 1 : 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1155,8 +1145,11 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
                                             const int64_t nblk)
 {
     Ctrl *ctrl = a.ctrl;
+    // a list iteration: the scan has left this iteration's rows to the
+    // update, which evaluates each row's candidate lists itself
+    const bool use = a.lists && a.lst && ctrl->list_ok != 0;
     unsigned long long tt = 0;
-    if (a.tpart && threadIdx.x == 0) {
+    if (!use && a.tpart && threadIdx.x == 0) {
         // the scan's pairs tested in this block's rows (groups of 64)
         const int64_t groups = (a.g.n + 63) / 64;
         for (int64_t s = 0; s < a.nslices; ++s)
@@ -1172,11 +1165,59 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
         Top4 top;
         top.clear();
         int64_t cn = 0, cz = 0, rn = 0;
+        const int64_t lamv = a.lam_in[p];
+        if (use) {
+            // every column that can matter is in one of the row's lists
+            // (see ScanArgs::lst).  Four parts at a time: their counts, then
+            // two entries of each per round (eight list loads, then their
+            // gathers, in flight together)
+            constexpr int kR = 2;
+            const float2 xyv = reinterpret_cast<const float2 *>(a.col)[2 * p];
+            for (int64_t q0 = 0; q0 < a.nparts; q0 += 4) {
+                int cq[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    cq[r] = q0 + r < a.nparts ? min(max(a.lcnt[(q0 + r) * n + p], 0), kLW) : 0;
+                const int cmax = max(max(cq[0], cq[1]), max(cq[2], cq[3]));
+                tt += (unsigned long long)(cq[0] + cq[1] + cq[2] + cq[3]);
+                for (int i0 = 0; i0 < cmax; i0 += kR) {
+                    int32_t uu[4][kR];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int t = 0; t < kR; ++t)
+                            uu[r][t] = i0 + t < cq[r] ? a.lst[((q0 + r) * kLW + i0 + t) * n + p] : -1;
+                    float2 cu[4][kR];
+                    long long lu[4][kR];
+                    int32_t ou[4][kR];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int t = 0; t < kR; ++t) {
+                            if (uu[r][t] >= 0) {
+                                cu[r][t] = reinterpret_cast<const float2 *>(a.col)[2 * (int64_t)uu[r][t]];
+                                lu[r][t] = a.lam_in[uu[r][t]];
+                                ou[r][t] = a.g.orig[uu[r][t]];
+                            }
+                        }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int t = 0; t < kR; ++t) {
+                            if (uu[r][t] < 0) continue;
+                            const int64_t z = exact_z(xyv.x, xyv.y, lamv, cu[r][t].x, cu[r][t].y, lu[r][t]);
+                            if (z < 0) { ++cn; rn += z; }
+                            else if (z == 0) ++cz;
+                            top.insert(z, ou[r][t]);
+                        }
+                }
+            }
+        }
         // slices in groups of four: the group's loads are issued together,
         // then merged (the merge order does not matter: (Z, u) is a total
         // order and the counts are sums)
         constexpr int kG = 4;
-        for (int64_t s0 = 0; s0 < a.nslices; s0 += kG) {
+        for (int64_t s0 = 0; !use && s0 < a.nslices; s0 += kG) {
             int64_t gz[kG][kTop];
             int32_t gi[kG][kTop];
 #pragma unroll
@@ -1199,11 +1240,10 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
 #pragma unroll
                 for (int j = 0; j < kTop; ++j) top.insert(gz[q][j], gi[q][j]);
         }
-        step_row(a.g, p, top, cn, cz, rn, a.lam_in[p], copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
-                 a.neg, a.zero, a.step, a.col, o);
+        step_row(a.g, p, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
+                 a.neg, a.zero, a.step, a.col, o, a.z4p, a.i4p);
     }
-    reduce_and_control(o, n, k, ctrl, a.trace, a.tile_hmax, blk, nblk, a.slots, a.lists != 0, tt, a.scan_kind,
-                       a.progress);
+    block_record(o, a.tile_hmax, blk, a.slots, tt);
 }
 
 __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs a)
@@ -1228,6 +1268,22 @@ __global__ __launch_bounds__(kBlock) void k_update_batch(const UpdateArgs *args,
     update_body(a, k, w.block, a.ctrl->nblocks);
 }
 
+// one block: the control of iteration k after the update (or candidate-graph
+// step) launch of nblk blocks
+__global__ __launch_bounds__(kBlock) void k_control(ControlArgs a)
+{
+    if (a.ctrl->done) return;
+    control_body(a.n, a.k, a.ctrl, a.trace, a.nblk, a.slots, a.lists != 0, a.kinds, a.progress);
+}
+
+// batched: one block per instance, after k_update_batch
+__global__ __launch_bounds__(kBlock) void k_control_batch(const UpdateArgs *args)
+{
+    const UpdateArgs &a = args[blockIdx.x];
+    if (!a.ctrl || a.ctrl->done) return;
+    control_body(a.g.n, a.ctrl->k_next, a.ctrl, a.trace, a.ctrl->nblocks, a.slots, false, nullptr, nullptr);
+}
+
 __global__ void k_ctrl_nblocks(Ctrl *ctrls, const int64_t *nb, int64_t ninst)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1246,33 +1302,66 @@ __global__ void k_count_active(const Ctrl *ctrls, int64_t ninst, int32_t *out)
     if (threadIdx.x == 0) out[0] = cnt;
 }
 
-// candidate graph: one fused pass per iteration over the CSR rows
+// candidate graph: one fused pass per iteration over the CSR rows.  A wave
+// owns 64 consecutive rows, whose entries are contiguous in the CSR.  It
+// reads them in chunks of kGChunk entries, every lane loading entries
+// lane, lane + 64, ... (coalesced column and cost loads, and all the
+// neighbours' Lam and label gathers of the chunk in flight at once) into the
+// wave's LDS; then each lane walks its own row's entries of the chunk there.
+constexpr int kGChunk = 512;
+
 __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
 {
     Ctrl *ctrl = a.ctrl;
     if (ctrl->done) return;
+    __shared__ int32_t gcost[kBlock / 64][kGChunk];
+    __shared__ int32_t glab[kBlock / 64][kGChunk];
+    __shared__ long long glam[kBlock / 64][kGChunk];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n = a.g.n;
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t w0 = (int64_t)blockIdx.x * kBlock + wave * 64;
     const bool copy_best = a.k > 0 && ctrl->best_k == a.k - 1;
     RowOut o;
+    Top4 top;
+    top.clear();
+    int64_t cn = 0, cz = 0, rn = 0;
+    int64_t lamv = 0;
+    int32_t rb = 0, re = 0;
     if (p < n) {
-        Top4 top;
-        top.clear();
-        int64_t cn = 0, cz = 0, rn = 0;
-        const int64_t lamv = a.lam_in[p];
-        const int32_t e1 = a.csr.rowptr[p + 1];
-        for (int32_t e = a.csr.rowptr[p]; e < e1; ++e) {
-            const int32_t u = a.csr.col[e];
-            const int64_t z = 2 * (int64_t)a.csr.cost[e] - lamv - a.lam_in[u];   // eq. 9, doubled
-            if (z < 0) { ++cn; rn += z; }
-            else if (z == 0) ++cz;
-            top.insert(z, a.g.orig[u]);
-        }
-        step_row(a.g, p, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, nullptr,
-                 a.neg, a.zero, a.step, nullptr, o);
+        lamv = a.lam_in[p];
+        rb = a.csr.rowptr[p];
+        re = a.csr.rowptr[p + 1];
     }
-    reduce_and_control(o, n, a.k, ctrl, a.trace, nullptr, blockIdx.x, gridDim.x, a.slots, false, 0, nullptr,
-                       a.progress);
+    if (w0 < n) {
+        const int32_t e0 = a.csr.rowptr[w0], e1 = a.csr.rowptr[min(n, w0 + 64)];
+        for (int32_t c0 = e0; c0 < e1; c0 += kGChunk) {
+            const int32_t cnt = min(kGChunk, e1 - c0);
+            wave_sync();   // the previous chunk's reads are done
+#pragma unroll 4
+            for (int i = lane; i < kGChunk; i += 64) {
+                if (i < cnt) {
+                    const int32_t u = a.csr.col[c0 + i];
+                    gcost[wave][i] = a.csr.cost[c0 + i];
+                    glam[wave][i] = a.lam_in[u];
+                    glab[wave][i] = a.g.orig[u];
+                }
+            }
+            wave_sync();
+            const int32_t lo = max(rb, c0), hi = min(re, c0 + cnt);
+            for (int32_t e = lo; e < hi; ++e) {
+                const int i = e - c0;
+                const int64_t z = 2 * (int64_t)gcost[wave][i] - lamv - glam[wave][i];   // eq. 9, doubled
+                if (z < 0) { ++cn; rn += z; }
+                else if (z == 0) ++cz;
+                top.insert(z, glab[wave][i]);
+            }
+        }
+    }
+    if (p < n)
+        step_row(a.g, p, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, nullptr,
+                 a.neg, a.zero, a.step, nullptr, o, a.z4p, a.i4p);
+    block_record(o, nullptr, blockIdx.x, a.slots, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1968,41 +2057,53 @@ __global__ __launch_bounds__(kBlock) void k_cert_edges(const int32_t *xy, int64_
                                                        const int32_t *ev, const uint8_t *ex2, int32_t *deg,
                                                        int32_t *cnt, int32_t *nb, unsigned long long *acc)
 {
+    __shared__ unsigned long long red[kBlock / 64];
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= m) return;
-    const int64_t u = eu[e], v = ev[e];
-    const int x2 = ex2[e];
-    if (u < 0 || v < 0 || u >= n || v >= n || u == v || (x2 != 1 && x2 != 2)) {
-        atomicAdd(&acc[2], 1ULL);
-        return;
+    unsigned long long cost2 = 0, viol = 0;
+    if (e < m) {
+        const int64_t u = eu[e], v = ev[e];
+        const int x2 = ex2[e];
+        if (u < 0 || v < 0 || u >= n || v >= n || u == v || (x2 != 1 && x2 != 2)) {
+            viol = 1;
+        } else {
+            const int64_t dx = (int64_t)xy[2 * u] - xy[2 * v];
+            const int64_t dy = (int64_t)xy[2 * u + 1] - xy[2 * v + 1];
+            cost2 = (unsigned long long)(nint_sqrt(dx * dx + dy * dy) * x2);
+            atomicAdd(&deg[u], x2);
+            atomicAdd(&deg[v], x2);
+            const int su = atomicAdd(&cnt[u], 1);
+            if (su < kCertNb) nb[kCertNb * u + su] = (int32_t)v;
+            const int sv = atomicAdd(&cnt[v], 1);
+            if (sv < kCertNb) nb[kCertNb * v + sv] = (int32_t)u;
+        }
     }
-    const int64_t dx = (int64_t)xy[2 * u] - xy[2 * v];
-    const int64_t dy = (int64_t)xy[2 * u + 1] - xy[2 * v + 1];
-    const int64_t c = nint_sqrt(dx * dx + dy * dy);
-    atomicAdd(&acc[1], (unsigned long long)(c * x2));
-    atomicAdd(&deg[u], x2);
-    atomicAdd(&deg[v], x2);
-    const int su = atomicAdd(&cnt[u], 1);
-    if (su < kTop) nb[kTop * u + su] = (int32_t)v;
-    const int sv = atomicAdd(&cnt[v], 1);
-    if (sv < kTop) nb[kTop * v + sv] = (int32_t)u;
+    // one atomic per block for the cost (atomics on one address serialise)
+    cost2 = block_reduce<unsigned long long, false>(cost2, red);
+    viol = block_reduce<unsigned long long, false>(viol, red);
+    if (threadIdx.x == 0) {
+        if (cost2) atomicAdd(&acc[1], cost2);
+        if (viol) atomicAdd(&acc[2], viol);
+    }
 }
 
+// b (by label) or null: every doubled degree must be 2 b_v (4 for F2M);
+// acc[3] += sum_v b_v Lam_v
 __global__ __launch_bounds__(kBlock) void k_cert_nodes(const int64_t *lam, int64_t n, const int32_t *deg,
                                                        const int32_t *cnt, const int32_t *nb,
-                                                       unsigned long long *acc)
+                                                       unsigned long long *acc, const int8_t *b)
 {
     __shared__ unsigned long long red[kBlock / 64];
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     unsigned long long bad = 0, sl = 0;
     if (v < n) {
-        sl = (unsigned long long)lam[v];
+        const int bv = b ? (int)b[v] : 2;
+        sl = (unsigned long long)(bv * lam[v]);
         const int c = cnt[v];
-        if (deg[v] != 4 || c > kTop) bad = 1;
+        if (deg[v] != 2 * bv || c > kCertNb) bad = 1;
         else {
             for (int i = 0; i < c; ++i)
                 for (int j = i + 1; j < c; ++j)
-                    if (nb[kTop * v + i] == nb[kTop * v + j]) bad = 1;
+                    if (nb[kCertNb * v + i] == nb[kCertNb * v + j]) bad = 1;
         }
     }
     bad = block_reduce<unsigned long long, false>(bad, red);
@@ -2161,6 +2262,52 @@ hipError_t launch_scan(const ScanArgs &a, int mode, int64_t nslices, int rows_pe
         return launch_scan_mode<kModeCollect>(with_interleave(a, nslices), nslices, rows_per_thread, st);
     }
     return hipErrorInvalidValue;
+}
+
+__global__ __launch_bounds__(kBlock) void k_top_to_labels(const int64_t *z4p, const int32_t *i4p,
+                                                          const int32_t *orig, int64_t n, int64_t *z4, int32_t *i4)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    const int64_t v = orig[p];
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) {
+        z4[kTop * v + j] = z4p[j * n + p];
+        i4[kTop * v + j] = i4p[j * n + p];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_to_positions(const int8_t *b_label, const int32_t *orig, int64_t n,
+                                                           int8_t *b_pos)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) b_pos[p] = b_label[orig[p]];
+}
+
+hipError_t launch_b_to_positions(const int8_t *b_label, const int32_t *orig, int64_t n, int8_t *b_pos, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_b_to_positions, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, b_label, orig, n, b_pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_top_to_labels(const int64_t *z4p, const int32_t *i4p, const int32_t *orig, int64_t n, int64_t *z4,
+                                int32_t *i4, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_top_to_labels, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, z4p, i4p, orig, n, z4, i4);
+    return hipGetLastError();
+}
+
+hipError_t launch_control(const ControlArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_control_batch(const UpdateArgs *args_dev, int64_t ninst, hipStream_t st)
+{
+    if (ninst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_control_batch, dim3((unsigned)ninst), dim3(kBlock), 0, st, args_dev);
+    return hipGetLastError();
 }
 
 hipError_t launch_update(const UpdateArgs &a, hipStream_t st)
@@ -2435,9 +2582,9 @@ hipError_t launch_cert_edges(const int32_t *xy, int64_t n, int64_t m, const int3
 }
 
 hipError_t launch_cert_nodes(const int64_t *lam, int64_t n, const int32_t *deg, const int32_t *cnt,
-                             const int32_t *nb, unsigned long long *acc, hipStream_t st)
+                             const int32_t *nb, unsigned long long *acc, const int8_t *b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cert_nodes, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam, n, deg, cnt, nb, acc);
+    hipLaunchKernelGGL(k_cert_nodes, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, lam, n, deg, cnt, nb, acc, b);
     return hipGetLastError();
 }
 

@@ -51,7 +51,8 @@ class Opts(C.Structure):
                 ("chunk", C.c_int32), ("time_kernels", C.c_int32), ("scan_mode", C.c_int32),
                 ("scan_rows", C.c_int32), ("scan_slices", C.c_int32), ("hip_stream", C.c_void_p),
                 ("k0", C.c_int64), ("resume_hash", C.c_uint64 * 2), ("resume_hash_valid", C.c_int32),
-                ("pad_opts", C.c_int32), ("max_device_bytes", C.c_uint64), ("tuner_cache", C.c_char_p)]
+                ("pad_opts", C.c_int32), ("max_device_bytes", C.c_uint64), ("tuner_cache", C.c_char_p),
+                ("degree_b", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -70,7 +71,7 @@ class Result(C.Structure):
                 ("scan_kind", C.POINTER(C.c_int32)), ("scan_list_uses", C.c_int64),
                 ("scan_list_builds", C.c_int64), ("lambda2_last", C.POINTER(C.c_int64)),
                 ("scan_ms_kind", C.c_double * 3), ("scan_launches_kind", C.c_int64 * 3),
-                ("scan_pairs_kind", C.c_int64 * 3)]
+                ("scan_pairs_kind", C.c_int64 * 3), ("update_ms", C.c_double), ("update_ms_kind", C.c_double * 3)]
 
 
 _lib = None
@@ -166,8 +167,9 @@ def _result_dict(res, n, st):
         graph_nnz=res.graph_nnz, warm_iterations=res.warm_iterations,
         scan_list_uses=res.scan_list_uses, scan_list_builds=res.scan_list_builds,
         scan_by_kind={name: dict(ms=res.scan_ms_kind[q], launches=res.scan_launches_kind[q],
-                                 pairs=res.scan_pairs_kind[q])
+                                 pairs=res.scan_pairs_kind[q], update_ms=res.update_ms_kind[q])
                       for q, name in enumerate(("full", "build", "list"))},
+        update_ms=res.update_ms,
     )
     if res.trace_len:
         out["trace"] = np.ctypeslib.as_array(res.trace, (res.trace_len * TRACE_W,)).reshape(
@@ -219,7 +221,7 @@ class Context:
     def solve(self, coords, *, max_iters=100000, handoff_div=HANDOFF_DIV, finish="exact", lambda2_init=None,
               trace=False, chunk=0, stream=None, time_kernels=False, scan="culled", graph="complete", knn_k=10,
               shape=None, mlp_theta=None, warm=None, k0=0, resume_hash=None, max_device_bytes=None,
-              tuner_cache=None):
+              tuner_cache=None, degree_b=None):
         """Solves F2M on the complete graph.  `coords` is an int32 (n, 2)
         array on the host or a contiguous int32 device tensor."""
         o = Opts()
@@ -246,6 +248,10 @@ class Context:
             tc = os.fsencode(tuner_cache)
             keep.append(tc)
             o.tuner_cache = tc
+        if degree_b is not None:
+            bd = _np(degree_b, np.int32)
+            keep.append(bd)
+            o.degree_b = bd.ctypes.data
         if lambda2_init is not None:
             l0 = _np(lambda2_init, np.int64)
             keep.append(l0)

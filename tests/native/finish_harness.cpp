@@ -94,12 +94,14 @@ FinishWork *g_one = nullptr;    // the same on one thread (reuse = 3)
 }  // namespace
 
 // Returns the edge count (or -1 on failure); stats: paths, rounds, phases, candidates.
+// b: node degrees (b-matching), or null for 2.
 // bulk: the source also supplies costs and the bulk data; reuse 1: one
 // workspace serves every call; reuse 2: the same with the flow's chunked
 // single-source tail from the first excess node, on four threads; reuse 3:
 // that on one thread.
 extern "C" int64_t finish_cpu(int64_t n, const int32_t *xy, const int64_t *lam0, int64_t *lam_out, int64_t cap,
-                              int32_t *eu, int32_t *ev, uint8_t *ex2, int64_t *stats, int32_t bulk, int32_t reuse)
+                              int32_t *eu, int32_t *ev, uint8_t *ex2, int64_t *stats, int32_t bulk, int32_t reuse,
+                              const int32_t *b)
 {
     BrutePairs src;
     src.xy = xy;
@@ -110,7 +112,7 @@ extern "C" int64_t finish_cpu(int64_t n, const int32_t *xy, const int64_t *lam0,
     if (reuse == 2 && !g_par) g_par = finish_work_create(4, 1);
     if (reuse == 3 && !g_one) g_one = finish_work_create(1, 1);
     FinishWork *w = reuse == 1 ? g_work : (reuse == 2 ? g_par : (reuse == 3 ? g_one : nullptr));
-    finish_exact(xy, n, lam0, src, &r, w);
+    finish_exact(xy, n, lam0, src, &r, w, b);
     if (!r.ok || (int64_t)r.eu.size() > cap) return -1;
     std::memcpy(lam_out, r.lam.data(), n * sizeof(int64_t));
     for (size_t i = 0; i < r.eu.size(); ++i) { eu[i] = r.eu[i]; ev[i] = r.ev[i]; ex2[i] = r.ex2[i]; }

@@ -47,11 +47,12 @@ def test_struct_layout_matches_binding():
 #include "f2m.h"
 #include <stdio.h>
 #include <stddef.h>
-int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(f2m_opts), sizeof(f2m_result),
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(f2m_opts), sizeof(f2m_result),
  offsetof(f2m_opts, hip_stream), offsetof(f2m_result, seconds), offsetof(f2m_result, graph_nnz),
  offsetof(f2m_result, warm_iterations), offsetof(f2m_result, scan_kind),
  offsetof(f2m_result, scan_list_builds), offsetof(f2m_opts, tuner_cache),
- offsetof(f2m_result, lambda2_last), offsetof(f2m_result, scan_pairs_kind));return 0;}
+ offsetof(f2m_result, lambda2_last), offsetof(f2m_result, scan_pairs_kind),
+ offsetof(f2m_result, update_ms_kind), offsetof(f2m_opts, degree_b));return 0;}
 '''
     import tempfile
     d = tempfile.mkdtemp()
@@ -63,7 +64,8 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(f2
     assert vals == [ctypes.sizeof(f2m.Opts), ctypes.sizeof(f2m.Result), f2m.Opts.hip_stream.offset,
                     f2m.Result.seconds.offset, f2m.Result.graph_nnz.offset, f2m.Result.warm_iterations.offset,
                     f2m.Result.scan_kind.offset, f2m.Result.scan_list_builds.offset, f2m.Opts.tuner_cache.offset,
-                    f2m.Result.lambda2_last.offset, f2m.Result.scan_pairs_kind.offset]
+                    f2m.Result.lambda2_last.offset, f2m.Result.scan_pairs_kind.offset,
+                    f2m.Result.update_ms_kind.offset, f2m.Opts.degree_b.offset]
 
 
 def test_no_gpu_fails_loudly():

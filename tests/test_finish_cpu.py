@@ -109,3 +109,28 @@ def test_parallel_tail_many_chunks(L):
             for other in par[1:]:
                 for a, b in zip(par[0][:4], other[:4]):
                     assert np.array_equal(a, b)
+
+
+def test_b_matching_degrees(L):
+    # rows with right-hand sides b_v in {1, 2, 3} (the b-matching of Sec. 3):
+    # both copies of v carry b_v units; certified against the oracle's
+    # certificate and exact optimum with the same b, from Lam = 0 and from
+    # the oracle's GDP stop
+    rnd = np.random.default_rng(21)
+    for n, seed in ((5, 1), (9, 2), (40, 3), (200, 4)):
+        xy = I.uniform(n, 100000, seed)
+        b = rnd.integers(1, 4, n).astype(np.int32)
+        opt = core.exact_opt2(xy, b=b)
+        for lam0 in (np.zeros(n, np.int64), core.gdp_solve(xy, b=b, handoff_div=50)["lam"]):
+            ref = harness.finish(L, xy, lam0, b=b)
+            c = core.certify(xy, *ref[:4], b=b)
+            assert c["certified"] and c["primal2"] == opt, (n, c)
+            got = harness.finish(L, xy, lam0, bulk=True, b=b)
+            for x, y in zip(ref[:4], got[:4]):
+                assert np.array_equal(x, y)
+    # b = 2 everywhere is F2M
+    xy = I.uniform(60, 100000, 9)
+    a = harness.finish(L, xy, np.zeros(60, np.int64))
+    c = harness.finish(L, xy, np.zeros(60, np.int64), b=np.full(60, 2, np.int32))
+    for x, y in zip(a[:4], c[:4]):
+        assert np.array_equal(x, y)
