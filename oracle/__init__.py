@@ -8,6 +8,8 @@ HIP library.
 `core` wraps the plain C oracle (GDP rule, certificate, exact optimum by
 min-cost flow on the double cover); `exact` holds pure-Python checkers
 (brute force over {0, 1/2, 1} edge vectors, exact-rational simplex) used to
-pin the C oracle.
+pin the C oracle; `sec` is the GDP with subtour-elimination rows (F2M plus
+rows x(delta(S)) >= 2 with multipliers >= 0, the extension of Sec. 5) in
+plain numpy, pinned by `exact`'s rational LP with those rows.
 """
-from . import core, exact  # noqa: F401
+from . import core, exact, sec  # noqa: F401

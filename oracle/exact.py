@@ -213,3 +213,148 @@ def highs_opt2(xy, graph=None, b=None):
         return None
     assert r.status == 0
     return int(round(2 * r.fun))
+
+
+def lp_min_exact(cost, rows, rhs, ub, max_pivots=500000):
+    """min cost.x  s.t.  rows[i] . x = rhs[i] (rhs >= 0),  0 <= x_j <= ub[j]
+    (ub[j] None: no upper bound), by the same exact-rational bounded-variable
+    simplex as simplex_opt2 (phase 1 on one artificial per row, Bland's
+    rule).  rows[i] is a dict {j: coefficient}.  Returns the optimum as a
+    Fraction, or None when infeasible."""
+    nr = len(rows)
+    m = len(cost)
+    nv = m + nr
+    ubs = [None if u is None else Fraction(u) for u in ub] + [None] * nr
+    A = [[Fraction(0)] * nv for _ in range(nr)]
+    for i, row in enumerate(rows):
+        for j, a in row.items():
+            A[i][j] = Fraction(a)
+        A[i][m + i] = Fraction(1)
+    basis = [m + i for i in range(nr)]
+    at_upper = [False] * nv
+    xB = [Fraction(r) for r in rhs]
+
+    def run(obj, allowed):
+        pivots = 0
+        while True:
+            cb = [obj[b] for b in basis]
+            entering, direction = None, 0
+            inbasis = set(basis)
+            for j in range(allowed):
+                if j in inbasis:
+                    continue
+                d = obj[j] - sum(cb[i] * A[i][j] for i in range(nr) if A[i][j] != 0)
+                if not at_upper[j] and d < 0:
+                    entering, direction = j, +1
+                    break
+                if at_upper[j] and d > 0:
+                    entering, direction = j, -1
+                    break
+            if entering is None:
+                return
+            j = entering
+            tmax = ubs[j]
+            leave = None
+            for i in range(nr):
+                a = A[i][j] * direction
+                if a > 0:
+                    cand = (xB[i] / a, basis[i], i, False)
+                elif a < 0 and ubs[basis[i]] is not None:
+                    cand = ((ubs[basis[i]] - xB[i]) / (-a), basis[i], i, True)
+                else:
+                    continue
+                if tmax is None or cand[0] < tmax or (cand[0] == tmax and leave is not None and cand[1] < leave[1]):
+                    tmax = cand[0]
+                    leave = cand
+            if tmax is None:
+                raise RuntimeError("unbounded")
+            t = tmax
+            for i in range(nr):
+                xB[i] -= t * direction * A[i][j]
+            if leave is None:
+                at_upper[j] = not at_upper[j]
+            else:
+                _, _, r, to_upper = leave
+                old = basis[r]
+                newval = t if direction > 0 else ubs[j] - t
+                piv = A[r][j]
+                A[r] = [a / piv for a in A[r]]
+                for i in range(nr):
+                    if i != r and A[i][j] != 0:
+                        f = A[i][j]
+                        A[i] = [a - f * b for a, b in zip(A[i], A[r])]
+                basis[r] = j
+                xB[r] = newval
+                at_upper[j] = False
+                at_upper[old] = to_upper
+            pivots += 1
+            if pivots > max_pivots:
+                raise RuntimeError("pivot limit")
+
+    run([Fraction(0)] * m + [Fraction(1)] * nr, nv)
+    art = sum(xB[i] for i in range(nr) if basis[i] >= m)
+    if art != 0:
+        return None
+    for i in range(nr):
+        ubs[m + i] = Fraction(0)
+    run([Fraction(c) for c in cost] + [Fraction(0)] * nr, m)
+    x = [Fraction(0)] * m
+    for j in range(m):
+        if at_upper[j]:
+            x[j] = ubs[j]
+    for i, b in enumerate(basis):
+        if b < m:
+            x[b] = xB[i]
+    return sum(Fraction(c) * xi for c, xi in zip(cost, x))
+
+
+def subtour_rows(n, cuts):
+    """The edges (u < v) of delta(S) for every cut S."""
+    out = []
+    for S in cuts:
+        ins = set(int(v) for v in S)
+        out.append([j for j, (u, v) in enumerate(edges_of(n)) if (u in ins) != (v in ins)])
+    return out
+
+
+def simplex_sec_opt2(xy, cuts):
+    """2 * the optimum of F2M with the subtour rows x(delta(S)) >= 2 of
+    `cuts`, exactly (a Fraction: with subtour rows the optimum need not be
+    a multiple of 1/2).  Each inequality row gets a surplus variable:
+    x(delta(S)) - s = 2, s >= 0."""
+    n = len(xy)
+    E = edges_of(n)
+    m = len(E)
+    cost = [euc2d(xy, u, v) for (u, v) in E]
+    rows, rhs = [], []
+    for v in range(n):
+        rows.append({j: 1 for j, (a, b) in enumerate(E) if a == v or b == v})
+        rhs.append(2)
+    for q, cross in enumerate(subtour_rows(n, cuts)):
+        row = {j: 1 for j in cross}
+        row[m + q] = -1
+        rows.append(row)
+        rhs.append(2)
+    val = lp_min_exact(cost + [0] * len(cuts), rows, rhs, [1] * m + [None] * len(cuts))
+    return None if val is None else 2 * val
+
+
+def highs_sec_opt2(xy, cuts):
+    """The same optimum (times 2, float) from scipy's HiGHS."""
+    from scipy.optimize import linprog
+    n = len(xy)
+    E = edges_of(n)
+    m = len(E)
+    c = np.array([euc2d(xy, u, v) for (u, v) in E], dtype=float)
+    Aeq = np.zeros((n, m))
+    for j, (u, v) in enumerate(E):
+        Aeq[u, j] = Aeq[v, j] = 1.0
+    Aub = np.zeros((len(cuts), m))
+    for q, cross in enumerate(subtour_rows(n, cuts)):
+        Aub[q, cross] = -1.0
+    r = linprog(c, A_eq=Aeq, b_eq=np.full(n, 2.0), A_ub=Aub if len(cuts) else None,
+                b_ub=np.full(len(cuts), -2.0) if len(cuts) else None, bounds=(0, 1), method="highs")
+    if r.status == 2:
+        return None
+    assert r.status == 0
+    return 2 * r.fun
