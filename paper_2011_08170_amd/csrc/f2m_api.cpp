@@ -45,7 +45,7 @@ struct f2m_ctx {
     DevBuf xy, minmax, keys, keys_alt, ids, orig, pos, box, xy2max, sort_temp;
     // GDP loop state
     DevBuf col, lam[2], lam_best, lam_label, tile_hmax, pz, pi, pneg, pzero, prowneg, pflag, z4, i4, z4p, i4p, seed,
-        ctrl, trace, lst, lcnt, tpart, slots, kinds;
+        ctrl, trace, lst, lcnt, loff, tpart, slots, kinds;
     // trivial x
     DevBuf slot_u, slot_v, slot_x, eu, ev, ex, btmp, count;
     // certificate / pair collection state
@@ -93,7 +93,7 @@ struct f2m_ctx {
     {
         DevBuf *all[] = {&xy, &minmax, &keys, &keys_alt, &ids, &orig, &pos, &box, &xy2max, &sort_temp,
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
-                         &prowneg, &pflag, &z4, &i4, &z4p, &i4p, &seed, &ctrl, &trace, &lst, &lcnt, &tpart, &slots, &kinds, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
+                         &prowneg, &pflag, &z4, &i4, &z4p, &i4p, &seed, &ctrl, &trace, &lst, &lcnt, &loff, &tpart, &slots, &kinds, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
                          &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &deg_label, &deg_pos, &knn_nbr, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
@@ -850,8 +850,10 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
     // the culled one-row-per-lane scan keeps candidate lists (kLW per row
     // and wave) and evaluates only them while they stay exact
     const bool lists = !csr && cull && sh.rows == 1;
-    int32_t *lst = lists ? grow<int32_t>(ctx, ctx->lst, 4 * sh.slices * kLW * n) : nullptr;
-    int32_t *lcnt = lists ? grow<int32_t>(ctx, ctx->lcnt, 4 * sh.slices * n) : nullptr;
+    const int64_t groups = (n + 63) / 64;
+    int32_t *lst = lists ? grow<int32_t>(ctx, ctx->lst, sh.slices * groups * kListCap) : nullptr;
+    int32_t *lcnt = lists ? grow<int32_t>(ctx, ctx->lcnt, sh.slices * n) : nullptr;
+    int32_t *loff = lists ? grow<int32_t>(ctx, ctx->loff, sh.slices * n) : nullptr;
     // its workgroups store their pairs tested for k_update to sum (one
     // atomic per update block instead of one per scan wave)
     unsigned long long *tpart = lists ? grow<unsigned long long>(ctx, ctx->tpart, sh.slices * ((n + 63) / 64)) : nullptr;
@@ -925,13 +927,14 @@ LoopOut gdp_loop(f2m_ctx *ctx, const GeoHost &gh, const int64_t *lam0_label_dev,
             sa.nrb = nrb;
             sa.lst = lst;
             sa.lcnt = lcnt;
+            sa.loff = loff;
             sa.tpart = tpart;
             if (e0) ck(ctx, hipEventRecord(e0, st), "hipEventRecord");
             ck(ctx, launch_scan(sa, kModeGdp, sh.slices, sh.rows, st), "scan");
             if (e1) ck(ctx, hipEventRecord(e1, st), "hipEventRecord");
             UpdateArgs ua{gh.g, sh.slices, k, pz, pi, pneg, pzero, prn, lam[k & 1], lam[(k + 1) & 1], best, col,
                           thm, nullptr, nullptr, seed, nullptr, nullptr, nullptr, cd, trace, pf, nrb, sh.rows,
-                          lists ? 1 : 0, tpart, slots, kinds, pw_dev, z4p, i4p, lst, lcnt, 4 * sh.slices};
+                          lists ? 1 : 0, tpart, slots, kinds, pw_dev, z4p, i4p, lst, lcnt, loff};
             ck(ctx, launch_update(ua, st), "update");
             const ControlArgs ca{cd, n, k, (n + kBlockThreads - 1) / kBlockThreads, slots, trace, kinds, pw_dev,
                                  lists ? 1 : 0};

@@ -127,15 +127,18 @@ struct ScanArgs {
     // columns; slice_len is then not used); 0 = slice s scans columns
     // [s * slice_len, (s + 1) * slice_len)
     int64_t interleave;
-    // GDP mode, culled, one row per lane, optional: candidate lists, kLW
-    // positions per (row p, part q = 4 slice + wave of the block) in
-    // lst[(q kLW + i) n + p] and their count in lcnt[q n + p] (-1:
-    // overflowed); 4 slices kLW n and 4 slices n entries.  A full scan with
-    // ctrl->list_D > 0 stores every column it finds with Z <= theta + 2 D;
-    // while ctrl->list_ok the scan evaluates only the lists (exact as long
-    // as the steps since the build sum to at most D / 2)
+    // GDP mode, culled, one row per lane, optional: candidate lists.  A
+    // full scan with ctrl->list_D > 0 keeps, per row, every column it finds
+    // with Z <= theta + 2 D (at most kLW per part, the four waves of the
+    // row's block being the parts); the block writes them compacted: row p
+    // of 64-row group g (slice s) has lcnt[s n + p] entries (-1: a part
+    // overflowed) at lst[(s G + g) kListCap + loff[s n + p] ...], G the
+    // number of groups, the group's rows one after another.  While
+    // ctrl->list_ok the update evaluates only the lists (exact as long as
+    // the steps since the build sum to at most D / 2) and the scan exits
     int32_t *lst;
     int32_t *lcnt;
+    int32_t *loff;
     // GDP mode, culled, one row per lane, optional: each workgroup stores
     // its ordered pairs tested in tpart[slice * groups + group] (groups of
     // 64 rows) instead of adding them to *tested; k_update sums them
@@ -183,12 +186,12 @@ struct UpdateArgs {
     // i4p[j n + p] (coalesced; z4 / i4 by label may then be null)
     int64_t *z4p;
     int32_t *i4p;
-    // the scan's candidate lists (ScanArgs::lst, lcnt) over nparts parts:
-    // with lists set, an iteration whose ctrl->list_ok holds is evaluated
-    // here from the lists (the scan exits at once)
+    // the scan's candidate lists (ScanArgs::lst, lcnt, loff; nslices
+    // segments per 64-row group): with lists set, an iteration whose
+    // ctrl->list_ok holds is evaluated here from the lists (the scan exits)
     const int32_t *lst;
     const int32_t *lcnt;
-    int64_t nparts;
+    const int32_t *loff;
 };
 
 // candidate list entries per row and wave (see ScanArgs::lst); the margin
@@ -196,6 +199,8 @@ struct UpdateArgs {
 // is at most 1/16 of iteration 0's and the margin at most half of the last
 // one whose lists overflowed
 constexpr int kLW = 16;
+// entries of one 64-row group's list segment: 64 rows x 4 parts x kLW
+constexpr int64_t kListCap = 64 * 4 * kLW;
 constexpr int64_t kListMult = 6;
 
 // Candidate graph (k nearest neighbours, union-symmetrised) in CSR over

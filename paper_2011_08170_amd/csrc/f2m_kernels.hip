@@ -605,7 +605,9 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
     int lc = 0;   // list entries found (build)
     // this lane's list: part `sid` of the S parts, entry i at
     // lst[(sid * kLW + i) * n + p] (consecutive lanes, consecutive addresses)
-    const int64_t lbase = sid * kLW * n + p, lcidx = sid * n + p;
+    // this wave's part of its rows' lists gathers in LDS during the walk;
+    // the block writes them out compacted per row at the end
+    __shared__ int32_t lbuf[QUAD && MODE == kModeGdp ? kBlock / 64 : 1][kLW][64];
     __syncthreads();   // bany and cfill are set
 
     // the wave's rows: positions [w0, w1), their box (two sub-tile boxes
@@ -659,7 +661,7 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
             return;
         }
         if (build && z <= rw.theta + rw.slk) {
-            if (lc < kLW) a.lst[lbase + (int64_t)lc * n] = (int32_t)u;
+            if (lc < kLW) lbuf[QUAD && MODE == kModeGdp ? wave : 0][lc][lane] = (int32_t)u;
             ++lc;
         }
         if (z > rw.theta) return;
@@ -805,9 +807,45 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         for (int i = lane; i < fill; i += 64)
             if ((int64_t)(base + i) < a.cap) a.out[base + i] = cbuf[wave][i];
     }
-    if (build && p < n) {
-        a.lcnt[lcidx] = lc <= kLW ? lc : -1;
-        if (lc > kLW) const_cast<Ctrl *>(a.lv.ctrl)->list_over = 1;   // the next update rebuilds
+    if (build) {
+        // The block's 64 rows: every row's entries from the four parts go out
+        // as one contiguous run, the rows one after another in the group's
+        // segment of kListCap entries (see ScanArgs::lst).
+        __shared__ int32_t lc_s[QUAD && MODE == kModeGdp ? kBlock / 64 : 1][64];
+        __shared__ int32_t off_s[64];
+        const int wv = QUAD && MODE == kModeGdp ? wave : 0;
+        lc_s[wv][lane] = lc;
+        __syncthreads();
+        if (wave == 0) {
+            int tot = 0;
+            bool ovf = false;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                const int c = lc_s[w][lane];
+                ovf = ovf || c > kLW;
+                tot += min(c, kLW);
+            }
+            const int mine = (ovf || p >= n) ? 0 : tot;
+            int incl = mine;   // inclusive scan over the wave's lanes
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            off_s[lane] = ovf ? -1 : incl - mine;
+            if (p < n) {
+                a.lcnt[sl * n + p] = ovf ? -1 : tot;
+                a.loff[sl * n + p] = incl - mine;
+            }
+            if (ovf && p < n) const_cast<Ctrl *>(a.lv.ctrl)->list_over = 1;   // the next update rebuilds
+        }
+        __syncthreads();
+        if (off_s[lane] >= 0 && p < n) {
+            int start = off_s[lane];
+            for (int w = 0; w < wave; ++w) start += min(lc_s[w][lane], kLW);
+            int32_t *seg = a.lst + (sl * (int64_t)gridDim.x + rblk) * kListCap;
+            const int c = min(lc, kLW);
+            for (int i = 0; i < c; ++i) seg[start + i] = lbuf[wv][i][lane];
+        }
     }
     if (MODE == kModeGdp && QUAD) {
         // waves 1-3 hand their rows' lists and counts to wave 0
@@ -1161,58 +1199,55 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
     // Lam_{k-1} sits in lam_out until it is overwritten
     const bool copy_best = k > 0 && ctrl->best_k == k - 1;
     RowOut o;
-    if (p < n) {
-        Top4 top;
-        top.clear();
-        int64_t cn = 0, cz = 0, rn = 0;
-        const int64_t lamv = a.lam_in[p];
-        if (use) {
-            // every column that can matter is in one of the row's lists
-            // (see ScanArgs::lst).  Four parts at a time: their counts, then
-            // two entries of each per round (eight list loads, then their
-            // gathers, in flight together)
-            constexpr int kR = 2;
-            const float2 xyv = reinterpret_cast<const float2 *>(a.col)[2 * p];
-            for (int64_t q0 = 0; q0 < a.nparts; q0 += 4) {
-                int cq[4];
+    Top4 top;
+    top.clear();
+    int64_t cn = 0, cz = 0, rn = 0;
+    const int64_t lamv = p < n ? a.lam_in[p] : 0;
+    if (use) {
+        // Every column that can matter is in the row's list (see
+        // ScanArgs::lst).  A wave's 64 rows (one scan group) have their lists
+        // in one segment per slice, row after row: the wave reads each
+        // segment in chunks, every lane taking entries lane, lane + 64, ...
+        // (their gathers all in flight together) into LDS, then each lane
+        // walks its own row's run there.
+        constexpr int kLChunk = 256;
+        __shared__ float2 sxy[kBlock / 64][kLChunk];
+        __shared__ long long slam[kBlock / 64][kLChunk];
+        __shared__ int32_t slab[kBlock / 64][kLChunk];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int64_t grp = blk * (kBlock / 64) + wave, groups = (n + 63) / 64;
+        const float2 xyv = p < n ? reinterpret_cast<const float2 *>(a.col)[2 * p] : make_float2(0.0f, 0.0f);
+        for (int64_t sl = 0; sl < a.nslices && grp < groups; ++sl) {
+            const int cnt = p < n ? min(max(a.lcnt[sl * n + p], 0), kLW * (kBlock / 64)) : 0;
+            const int off = p < n ? a.loff[sl * n + p] : 0;
+            tt += (unsigned long long)cnt;
+            const int total = (int)wave_max((long long)(off + cnt));
+            const int32_t *seg = a.lst + (sl * groups + grp) * kListCap;
+            for (int c0 = 0; c0 < total; c0 += kLChunk) {
+                wave_sync();   // the previous chunk's reads are done
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    cq[r] = q0 + r < a.nparts ? min(max(a.lcnt[(q0 + r) * n + p], 0), kLW) : 0;
-                const int cmax = max(max(cq[0], cq[1]), max(cq[2], cq[3]));
-                tt += (unsigned long long)(cq[0] + cq[1] + cq[2] + cq[3]);
-                for (int i0 = 0; i0 < cmax; i0 += kR) {
-                    int32_t uu[4][kR];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int t = 0; t < kR; ++t)
-                            uu[r][t] = i0 + t < cq[r] ? a.lst[((q0 + r) * kLW + i0 + t) * n + p] : -1;
-                    float2 cu[4][kR];
-                    long long lu[4][kR];
-                    int32_t ou[4][kR];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int t = 0; t < kR; ++t) {
-                            if (uu[r][t] >= 0) {
-                                cu[r][t] = reinterpret_cast<const float2 *>(a.col)[2 * (int64_t)uu[r][t]];
-                                lu[r][t] = a.lam_in[uu[r][t]];
-                                ou[r][t] = a.g.orig[uu[r][t]];
-                            }
-                        }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int t = 0; t < kR; ++t) {
-                            if (uu[r][t] < 0) continue;
-                            const int64_t z = exact_z(xyv.x, xyv.y, lamv, cu[r][t].x, cu[r][t].y, lu[r][t]);
-                            if (z < 0) { ++cn; rn += z; }
-                            else if (z == 0) ++cz;
-                            top.insert(z, ou[r][t]);
-                        }
+                for (int j = 0; j < kLChunk / 64; ++j) {
+                    const int e = c0 + j * 64 + lane;
+                    if (e < total) {
+                        const int64_t u = seg[e];
+                        sxy[wave][e - c0] = reinterpret_cast<const float2 *>(a.col)[2 * u];
+                        slam[wave][e - c0] = a.lam_in[u];
+                        slab[wave][e - c0] = a.g.orig[u];
+                    }
+                }
+                wave_sync();
+                const int lo = max(off, c0), hi = min(off + cnt, c0 + kLChunk);
+                for (int e = lo; e < hi; ++e) {
+                    const int i = e - c0;
+                    const int64_t z = exact_z(xyv.x, xyv.y, lamv, sxy[wave][i].x, sxy[wave][i].y, slam[wave][i]);
+                    if (z < 0) { ++cn; rn += z; }
+                    else if (z == 0) ++cz;
+                    top.insert(z, slab[wave][i]);
                 }
             }
         }
+    }
+    if (p < n) {
         // slices in groups of four: the group's loads are issued together,
         // then merged (the merge order does not matter: (Z, u) is a total
         // order and the counts are sums)
