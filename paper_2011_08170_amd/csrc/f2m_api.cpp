@@ -614,6 +614,9 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
 // graph.  The finish runs on Morton positions (nodes near in the plane are
 // near in memory): Lam comes in and pairs go out in that order, and xyp
 // holds the coordinates by position.
+// pricing results up to this many pairs are sorted on the host
+constexpr int64_t kHostSortMax = 1 << 16;
+
 class GpuPairs : public PairSource {
 public:
     GpuPairs(f2m_ctx *ctx, const GeoHost &gh, const int32_t *xyp, const int32_t *seed_dev, hipStream_t st)
@@ -656,18 +659,44 @@ private:
                 sa.count = cnt;
                 sa.out = pairs;
                 sa.cap = cap;
+                // pricing: the scan itself drops the candidates already
+                // known, so only new pairs (and their duplicates) come out
+                const bool excl = !seed && ncand_ > 0;
+                if (excl) {
+                    sa.excl = static_cast<const uint64_t *>(ctx->p_cand.p);
+                    sa.nexcl = ncand_;
+                }
                 ck(ctx, launch_scan(sa, kModeCollect, sh.slices, sh.rows, st_), "collect");
                 ck(ctx, hipMemcpyAsync(ctx->scratch_host, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st_), "copy");
                 ck(ctx, hipStreamSynchronize(st_), "sync");
                 const int64_t found = ctx->scratch_host[0];
                 if (found > cap) { cap = found + found / 4; continue; }
+                if (excl && found <= kHostSortMax) {
+                    // few pairs: sorted and de-duplicated on the host (the
+                    // finish computes their costs)
+                    out.clear();
+                    costs = nullptr;
+                    neg = nullptr;
+                    inc_start = nullptr;
+                    inc = nullptr;
+                    if (found > 0) {
+                        const int2 *hp = static_cast<const int2 *>(static_cast<void *>(
+                            grow_host<uint64_t>(ctx, ctx->h_keys, found)));
+                        ck(ctx, launch_copy_bytes(pairs, ctx->h_keys.dp, found * sizeof(int2), st_), "copy");
+                        ck(ctx, hipStreamSynchronize(st_), "sync");
+                        out.resize(found);
+                        for (int64_t i = 0; i < found; ++i) out[i] = {hp[i].x, hp[i].y};
+                        std::sort(out.begin(), out.end());
+                        out.erase(std::unique(out.begin(), out.end()), out.end());
+                    }
+                    cap_ = cap;
+                    return true;
+                }
                 if (want_bulk && seed) {
                     fetch_unique_pairs(ctx, pairs, found, xyp_, n, lam, *this, out, st_, nullptr, 0, &ncand_);
                 } else {
-                    // known candidates stay on the device; only new pairs come back
-                    fetch_unique_pairs(ctx, pairs, found, xyp_, n, nullptr, *this, out, st_,
-                                       (!seed && ncand_ > 0) ? static_cast<const uint64_t *>(ctx->p_cand.p) : nullptr,
-                                       ncand_);
+                    // (with excl the scan has already dropped the known pairs)
+                    fetch_unique_pairs(ctx, pairs, found, xyp_, n, nullptr, *this, out, st_);
                 }
                 cap_ = cap;
                 return true;

@@ -136,29 +136,32 @@ public:
         xy_ = xy;
         n_ = n;
         b_ = b;
-        // search state: dist is infinite outside the last search's touched set
-        const bool same = (int64_t)cp_.size() == 2 * n;
-        if (same) {
-            for (int64_t x : touched_) cp_[x].dist = kInf;
-        } else {
-            cp_.assign(2 * n, Copy{});
-        }
+        // search state: dist is infinite outside the last search's touched
+        // set, so every copy's dist is reset (one pass over the records that
+        // are written anyway, on the pool's threads)
+        if ((int64_t)cp_.size() != 2 * n) cp_.assign(2 * n, Copy{});
         touched_.clear();
-        src_.clear();
-        for (int64_t v = 0; v < n; ++v) {
-            const int64_t al = floor_half(lam[v]);
-            cp_[v].pot = al;          // alpha_v
-            cp_[v].ex = deg(v);       // left copies supply b_v
-            cp_[n + v].pot = lam[v] - al;   // beta_v
-            cp_[n + v].ex = -deg(v);  // right copies demand b_v
-            src_.push_back(v);
-        }
+        src_.resize(n);
+        start_.resize(n);
+        end_.resize(n);
+        cap_.resize(n);
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            for (int64_t v = lo; v < hi; ++v) {
+                const int64_t al = floor_half(lam[v]);
+                Copy &l = cp_[v], &r = cp_[n + v];
+                l.pot = al;            // alpha_v
+                l.ex = deg(v);         // left copies supply b_v
+                l.dist = kInf;
+                r.pot = lam[v] - al;   // beta_v
+                r.ex = -deg(v);        // right copies demand b_v
+                r.dist = kInf;
+                src_[v] = v;
+                start_[v] = end_[v] = cap_[v] = 0;
+            }
+        });
         A_ = B_ = 0;
         keys_.clear();
         e_.clear();
-        start_.assign(n, 0);
-        end_.assign(n, 0);
-        cap_.assign(n, 0);
         inc_.clear();
         built_ = 0;
     }
@@ -418,16 +421,22 @@ public:
     // the edges with flow, in candidate order
     void x(std::vector<int32_t> &eu, std::vector<int32_t> &ev, std::vector<uint8_t> &ex2) const
     {
-        eu.clear();
-        ev.clear();
-        ex2.clear();
+        // every edge is written, the index moves past those with flow
+        const size_t m = e_.size();
+        eu.resize(m);
+        ev.resize(m);
+        ex2.resize(m);
+        size_t k = 0;
         for (const Edge &ed : e_) {
             const int f = ed.y[0] + ed.y[1];
-            if (f == 0) continue;
-            eu.push_back(ed.a);
-            ev.push_back(ed.b);
-            ex2.push_back((uint8_t)f);
+            eu[k] = ed.a;
+            ev[k] = ed.b;
+            ex2[k] = (uint8_t)f;
+            k += f != 0 ? 1 : 0;
         }
+        eu.resize(k);
+        ev.resize(k);
+        ex2.resize(k);
     }
 
 private:

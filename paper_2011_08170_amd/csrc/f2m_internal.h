@@ -118,6 +118,10 @@ struct ScanArgs {
     unsigned long long *count;
     int2 *out;
     int64_t cap;
+    // collect mode, optional: sorted keys (lo << 32 | hi, positions) of pairs
+    // not to emit (the finish's candidates already known)
+    const uint64_t *excl;
+    int64_t nexcl;
     // GDP mode, optional: pflag[slice * nrb + row block] = 1 when the block
     // had a column tile to scan; a block without one writes no partials
     int32_t *pflag;

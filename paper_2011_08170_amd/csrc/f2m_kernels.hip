@@ -641,7 +641,18 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
         if (MODE == kModeCollect) {
             // the wave's pairs gather in its LDS buffer; a full buffer's
             // excess goes out at once
-            const bool emit = z <= rw.theta;
+            bool emit = z <= rw.theta;
+            if (emit && a.excl) {
+                // skip the pairs already known: binary search of the key
+                const uint64_t key = ((uint64_t)(uint32_t)min(rw.v, u) << 32) | (uint64_t)(uint32_t)max(rw.v, u);
+                int64_t lo = 0, hi = a.nexcl;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (a.excl[mid] < key) lo = mid + 1;
+                    else hi = mid;
+                }
+                emit = !(lo < a.nexcl && a.excl[lo] == key);
+            }
             const unsigned long long em = __ballot(emit);
             if (em) {
                 const int base = cfill[wave];
