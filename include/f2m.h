@@ -329,6 +329,122 @@ f2m_status f2m_mlp_grad(f2m_ctx *ctx, const float *theta, const uint16_t *feat, 
 f2m_status f2m_mlp_adamw(f2m_ctx *ctx, float *theta, const float *grad, float *m, float *v, int64_t step, float lr,
                          float wd);
 
+/* ---- Subtour-elimination rows (F2M + SEC) ------------------------------
+ * The extension of Sec. 5: F2M plus rows x(delta(S_q)) >= 2 for node sets
+ * S_q (2 <= |S_q| <= n - 2), delta(S) the edges with one end in S.  Such a
+ * row enters the Lagrangian with a multiplier lambda_q >= 0 (Sec. 2,
+ * eq. 4-5) and moves by the gradient of Sec. 3 with b = 2 over its edges,
+ * then is projected back onto lambda_q >= 0.  Fixed point: M_q = 2 lambda_q
+ * (int64, >= 0) and, for an edge e = {u, v},
+ *   Z_e = 2c_e - Lam_u - Lam_v - sum_{q: e in delta(S_q)} M_q      (eq. 9)
+ *   dual2 = 2 sum Lam + 2 sum M + sum_{u<v} min(0, Z).
+ * Step of a row q: s = Z_(2) + Z_(3) over delta(S_q), M_q <- max(0, M_q +
+ * sign(s) floor((|s| + 4) / 8)): the midpoint move s/2 divided by the four
+ * rows that move a crossing edge at once (its two degree rows and the
+ * layer's rows of its two ends), where a degree row's s/4 divides by two;
+ * nodes step as in F2M, all rows from the same iterate.  Record fields as F2M_TRACE_W plus [8] sum of M_k; a row
+ * is unsatisfied when Z_(2) > 0, or M_q > 0 and Z_(3) < 0; it is bad when
+ * its trivial doubled crossing degree 2#(Z<0) + #(Z=0) is below 4, or
+ * M_q > 0 and that degree is not 4.  The state hash indexes node v by v
+ * and row q by n + q.  Stops as F2M without the hand-off: trivial, fixed,
+ * cycle, cap; at cycle and cap the result is the largest-dual iterate.
+ *
+ * Rows are given in layers: within a layer the row sets are disjoint, so
+ * an edge crosses at most two rows of a layer (the rows of its two ends).
+ * row_of: device int32[nlayers * n] by label; row_of[l n + v] in [0, nrows)
+ * is the row of layer l whose set holds v, -1 none.  Every row id occurs in
+ * exactly one layer, on 2 .. n - 2 nodes.  delta(S) = delta(V - S), so a
+ * row may be given by either side. */
+#define F2M_SEC_MAX_LAYERS 8
+#define F2M_SEC_TRACE_W 9
+
+typedef struct f2m_sec_rows {
+    int32_t nlayers;              /* 0 .. F2M_SEC_MAX_LAYERS */
+    int32_t reserved;             /* 0 */
+    int64_t nrows;                /* rows numbered 0 .. nrows - 1 */
+    const int32_t *row_of;        /* device, see above (may be null when nlayers == 0) */
+} f2m_sec_rows;
+
+typedef struct f2m_sec_result {
+    int64_t iterations;           /* iterations evaluated */
+    int64_t kstar;                /* iteration of (Lam*, M*) */
+    int32_t stop;                 /* F2M_STOP_TRIVIAL, _FIXED, _CYCLE or _CAP */
+    int32_t overflow;             /* 1: stopped because |Lam| + sum M could pass 2^38 */
+    int64_t dual2;                /* dual2 at (Lam*, M*) */
+    int64_t primal2_last;         /* 2 c.x of the trivial x at the last iterate */
+    int64_t bad_last;             /* bad rows (nodes and subtour rows) at the last iterate */
+    double seconds;
+} f2m_sec_result;
+
+/* GDP with subtour rows from (Lam_0, M_0).
+ *   coords_xy device int32[2n], n >= 4; rows as above (nrows <= 2^31 - 1).
+ *   lambda2 device int64[n] by label: in Lam_0, out Lam*.
+ *   mu device int64[nrows]: in M_0 (every entry >= 0, else F2M_ERR_ARG),
+ *   out M*.  max_iters >= 0.
+ *   trace host int64[trace_cap][F2M_SEC_TRACE_W] or null: records of
+ *   iterations 0 .. min(iterations, trace_cap) - 1.
+ * Status F2M_OK (also when stopped by cycle or cap: the bound is valid for
+ * any iterate), F2M_ERR_OVERFLOW when the multipliers grow past the range
+ * (out->overflow set; Lam* and M* are still returned).  A device
+ * workspace of about 8 + 72 L words per node (L = nlayers rounded up to 1,
+ * 2, 4 or 8) is kept in the context. */
+f2m_status f2m_sec_gdp(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n, const f2m_sec_rows *rows,
+                       int64_t *lambda2, int64_t *mu, int64_t max_iters, int64_t *trace, int64_t trace_cap,
+                       f2m_sec_result *out);
+
+/* Certificate of the trivial x of (Lam, M) (eq. 7 with the Z above):
+ * out host int64[5] = primal2, dual2, feasible (every doubled degree 4 and
+ * every row's doubled crossing degree >= 4), tight (every row with
+ * M_q > 0 has crossing degree exactly 4), certified (feasible, tight and
+ * primal2 == dual2: then x is optimal for F2M with these rows). */
+f2m_status f2m_sec_certify(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n, const f2m_sec_rows *rows,
+                           const int64_t *lambda2, const int64_t *mu, int64_t out[5]);
+
+/* Separation: the connected components of the support of the trivial x of
+ * (Lam, M) (the edges with Z <= 0).  When there are two or more, each
+ * component S is a violated row x(delta(S)) = 0 < 2; it becomes a new row
+ * when 2 <= |S| <= n - 2 and its cut is not already a row (given, or an
+ * earlier component: with two components both give one cut).  New rows
+ * are numbered rows->nrows, rows->nrows + 1, ... in order of their
+ * components' smallest labels and written as one new layer:
+ *   new_row_of device int32[n] by label (-1 for nodes in no new row);
+ *   *new_rows (host) their count, *components (host) the component count. */
+f2m_status f2m_sec_separate(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n, const f2m_sec_rows *rows,
+                            const int64_t *lambda2, const int64_t *mu, int32_t *new_row_of,
+                            int64_t *new_rows, int64_t *components);
+
+/* Rounds of separation and GDP from a given Lam (e.g. an F2M solution's):
+ * round r separates at the current (Lam, M), adds the new rows as layer
+ * nlayers0 + r with M = 0, and runs f2m_sec_gdp from there; it ends when
+ * no new row is found, after max_rounds rounds, when the layers or mu_cap
+ * are full, or when the GDP overflows.
+ *   lambda2 device int64[n]: in the start, out the last round's Lam*.
+ *   row_of device int32[F2M_SEC_MAX_LAYERS * n]: layers 0 .. nlayers0 - 1
+ *   hold given rows (nrows0 of them), the rounds append theirs.
+ *   mu device int64[mu_cap]: entries 0 .. nrows0 - 1 hold their M.
+ *   res host: per round r < rounds the rows added, the GDP's iterations,
+ *   stop and dual2 (at its Lam*); nlayers and nrows at the end; the best
+ *   dual2 over the start and every round (a lower bound on twice the
+ *   shortest tour); certified: the last round's trivial x is certified. */
+typedef struct f2m_sec_solve_result {
+    int32_t rounds;
+    int32_t nlayers;
+    int64_t nrows;
+    int64_t rows_added[F2M_SEC_MAX_LAYERS];
+    int64_t iterations[F2M_SEC_MAX_LAYERS];
+    int32_t stop[F2M_SEC_MAX_LAYERS];
+    int64_t dual2[F2M_SEC_MAX_LAYERS];
+    int64_t dual2_start;          /* dual2 at the start (its given rows and M) */
+    int64_t best_dual2;
+    int32_t certified;
+    int32_t components;           /* components at the last separation */
+    double seconds;
+} f2m_sec_solve_result;
+
+f2m_status f2m_sec_solve(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n, int64_t *lambda2, int32_t *row_of,
+                         int32_t nlayers0, int64_t nrows0, int64_t *mu, int64_t mu_cap, int32_t max_rounds,
+                         int64_t max_iters, f2m_sec_solve_result *res);
+
 void f2m_result_free(f2m_result *res);
 const char *f2m_status_str(f2m_status s);
 const char *f2m_last_error(const f2m_ctx *ctx);

@@ -20,9 +20,16 @@ M_q = 2 lambda_q >= 0, and for an edge e = {u, v}
 
     Z_e = 2 c_e - Lam_u - Lam_v - sum_{q : e in delta(S_q)} M_q      (eq. 9)
 
-A row's step is sign(s) floor((|s| + 2) / 4) with s the sum of its 2nd and
-3rd smallest Z (the rule of the F2M oracle); a subtour row's new value is
-max(0, M_q + step).  All rows step from the same iterate (Jacobi).  The
+With s the sum of a row's 2nd and 3rd smallest Z, moving that row's
+multiplier alone by s/2 would put zero midway between them (Sec. 3).  All
+rows step from the same iterate (Jacobi), so each move is divided by the
+number of rows that share an edge: a degree row's edge lies in two degree
+rows, so it moves by sign(s) floor((|s| + 2) / 4) (the rule of the F2M
+oracle); an edge crossing a subtour row lies in the two degree rows and,
+within its layer, in the subtour rows of both of its ends, so a subtour row
+moves by sign(s) floor((|s| + 4) / 8), and its new value is
+max(0, M_q + step).  (Moved like a degree row, by s/4, the subtour rows
+make the iterates diverge on families from two separation rounds.)  The
 Lagrangian (doubled):
 
     2 L = 2 sum_v Lam_v + 2 sum_q M_q + sum_e min(0, Z_e)
@@ -88,8 +95,14 @@ def z_matrix(c, lam, mu, X):
 
 
 def step(s: int) -> int:
-    """sign(s) floor((|s| + 2) / 4): the damped midpoint move."""
+    """sign(s) floor((|s| + 2) / 4): a degree row's damped midpoint move."""
     a = (abs(int(s)) + 2) // 4
+    return a if s > 0 else (-a if s < 0 else 0)
+
+
+def row_step(s: int) -> int:
+    """sign(s) floor((|s| + 4) / 8): a subtour row's damped midpoint move."""
+    a = (abs(int(s)) + 4) // 8
     return a if s > 0 else (-a if s < 0 else 0)
 
 
@@ -145,7 +158,7 @@ def gdp_iter(xy, lam, cuts, mu, c=None, X=None):
         z2, z3, neg, zero, _ = _row_stats(vals)
         d2 = 2 * neg + zero                      # doubled crossing degree of the trivial x
         cut_deg2.append(d2)
-        new_mu[q] = max(0, int(mu[q]) + step(z2 + z3))
+        new_mu[q] = max(0, int(mu[q]) + row_step(z2 + z3))
         # an inequality row: violated if fewer than two crossing edges can
         # be taken (Z_(2) > 0), or, while its multiplier is positive, if more
         # than two must be (Z_(3) < 0)

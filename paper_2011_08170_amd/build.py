@@ -19,7 +19,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-I", os.
           "-I", CSRC]
 # device code: gfx950 only; no packed fp32 instructions
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("f2m_kernels.hip", True), ("f2m_mlp.hip", True), ("f2m_noalloc.hip", True), ("f2m_api.cpp", False),
+SOURCES = [("f2m_kernels.hip", True), ("f2m_mlp.hip", True), ("f2m_noalloc.hip", True), ("f2m_sec.hip", True), ("f2m_api.cpp", False),
            ("f2m_finish.cpp", False)]
 
 

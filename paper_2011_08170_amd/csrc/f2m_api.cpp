@@ -5,6 +5,7 @@
 #include "f2m_finish.h"
 #include "f2m_internal.h"
 #include "f2m_mlp.h"
+#include "f2m_sec.h"
 
 #include <algorithm>
 #include <chrono>
@@ -59,6 +60,9 @@ struct f2m_ctx {
     DevBuf deg_label, deg_pos;
     // candidate graph
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
+    // GDP with subtour rows
+    DevBuf s_ctrl, s_rowp, s_cnt, s_rptr, s_cur, s_rmem, s_lam0, s_lam1, s_lamb, s_lamp, s_mu0, s_mu1, s_mub, s_pz,
+        s_pc, s_prn, s_ppr, s_pxz, s_pxc, s_xz, s_xc, s_slots, s_trace, s_parent;
     // warm-start network
     DevBuf m_nbr, m_nbrd, m_sorted, m_temp, m_scale, m_feat, m_w1b, m_w2b, m_z1, m_h1b, m_z2, m_h2, m_y, m_dy, m_g2b,
         m_g2f, m_pre1, m_g1b, m_g1f, m_sq, m_part, m_lam0;
@@ -102,7 +106,9 @@ struct f2m_ctx {
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
                          &b_sargs, &b_uargs, &b_sitems, &b_uitems, &b_nblk, &b_active, &b_slots, &m_nbr, &m_nbrd, &m_sorted,
                          &m_temp, &m_scale, &m_feat, &m_w1b, &m_w2b, &m_z1, &m_h1b, &m_z2, &m_h2, &m_y, &m_dy, &m_g2b,
-                         &m_g2f, &m_pre1, &m_g1b, &m_g1f, &m_sq, &m_part, &m_lam0};
+                         &m_g2f, &m_pre1, &m_g1b, &m_g1f, &m_sq, &m_part, &m_lam0, &s_ctrl, &s_rowp, &s_cnt,
+                         &s_rptr, &s_cur, &s_rmem, &s_lam0, &s_lam1, &s_lamb, &s_lamp, &s_mu0, &s_mu1, &s_mub, &s_pz,
+                         &s_pc, &s_prn, &s_ppr, &s_pxz, &s_pxc, &s_xz, &s_xc, &s_slots, &s_trace, &s_parent};
         bufs.assign(std::begin(all), std::end(all));
     }
 };
@@ -1395,6 +1401,300 @@ size_t carve_step(char *base, int64_t n, bool own_z4, bool own_i4, StepBufs *b)
     return at;
 }
 
+
+// ---------------------------------------------------------------------------
+// GDP with subtour rows
+// ---------------------------------------------------------------------------
+
+void sec_check_rows(f2m_ctx *ctx, int64_t n, const f2m_sec_rows *rows)
+{
+    if (!rows) fail(ctx, F2M_ERR_ARG, "rows is null");
+    if (rows->nlayers < 0 || rows->nlayers > F2M_SEC_MAX_LAYERS)
+        fail(ctx, F2M_ERR_ARG, "rows.nlayers must lie in [0, F2M_SEC_MAX_LAYERS]");
+    if (rows->nrows < 0 || rows->nrows > INT32_MAX) fail(ctx, F2M_ERR_ARG, "rows.nrows out of range");
+    if (rows->nlayers == 0 && rows->nrows != 0) fail(ctx, F2M_ERR_ARG, "rows without layers");
+    if (rows->nlayers > 0 && !rows->row_of) fail(ctx, F2M_ERR_ARG, "rows.row_of is null");
+    if ((int64_t)kSecMaxLayers * n >= INT32_MAX) fail(ctx, F2M_ERR_ARG, "n too large for subtour rows");
+}
+
+// The device state of one call: geometry, rows as positions and member
+// lists, Lam (by position), M, Lam' and the control block.
+struct SecSetup {
+    GeoHost gh;
+    int nlayers = 0, L = 1;
+    int64_t nrows = 0;
+    int32_t *rowp = nullptr, *rptr = nullptr, *rmem = nullptr, *rlayer = nullptr;
+    SecCtrl *ctrl = nullptr;
+    int64_t *lam[2] = {nullptr, nullptr}, *mu[2] = {nullptr, nullptr}, *lamp = nullptr;
+};
+
+SecSetup sec_setup(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec_rows *rows, const int64_t *lam_label,
+                   const int64_t *mu, int64_t max_iters, int64_t trace_cap, hipStream_t st)
+{
+    SecSetup s;
+    s.gh = setup_geo(ctx, xy, n, st);
+    s.nlayers = rows->nlayers;
+    s.L = sec_layers_inst(s.nlayers);
+    s.nrows = rows->nrows;
+    const int64_t Q = s.nrows, L = s.L;
+    s.ctrl = grow<SecCtrl>(ctx, ctx->s_ctrl, 1);
+    s.rowp = grow<int32_t>(ctx, ctx->s_rowp, L * n);
+    int32_t *cnt = grow<int32_t>(ctx, ctx->s_cnt, 3 * (Q + 1));
+    int32_t *lo = cnt + (Q + 1), *hi = cnt + 2 * (Q + 1);
+    s.rlayer = lo;
+    s.lam[0] = grow<int64_t>(ctx, ctx->s_lam0, n);
+    s.lam[1] = grow<int64_t>(ctx, ctx->s_lam1, n);
+    s.lamp = grow<int64_t>(ctx, ctx->s_lamp, n);
+    s.mu[0] = grow<int64_t>(ctx, ctx->s_mu0, Q + 1);
+    s.mu[1] = grow<int64_t>(ctx, ctx->s_mu1, Q + 1);
+    ck(ctx, launch_sec_ctrl_init(s.ctrl, max_iters, trace_cap, s.nlayers, st), "sec ctrl");
+    ck(ctx, hipMemsetAsync(cnt, 0, (Q + 1) * sizeof(int32_t), st), "memset");
+    ck(ctx, hipMemsetAsync(lo, 0x7f, (Q + 1) * sizeof(int32_t), st), "memset");
+    ck(ctx, hipMemsetAsync(hi, 0xff, (Q + 1) * sizeof(int32_t), st), "memset");
+    ck(ctx, launch_sec_rows_in(rows->row_of, s.gh.g.orig, n, s.nlayers, s.L, Q, s.rowp, cnt, lo, hi, s.ctrl, st),
+       "sec rows");
+    if (Q > 0) ck(ctx, hipMemcpyAsync(s.mu[0], mu, Q * sizeof(int64_t), hipMemcpyDeviceToDevice, st), "copy");
+    ck(ctx, launch_sec_start(lam_label, s.gh.g.orig, n, s.mu[0], Q, s.lam[0], s.lamp, s.ctrl, st), "sec start");
+    std::vector<int32_t> hc(3 * (Q + 1));
+    SecCtrl hctrl;
+    download(ctx, {{cnt, hc.data(), hc.size() * sizeof(int32_t)}, {s.ctrl, &hctrl, sizeof(SecCtrl)}}, st);
+    if (hctrl.bad_input & 1) fail(ctx, F2M_ERR_ARG, "row_of holds a row id outside [-1, nrows)");
+    if (hctrl.bad_input & 2) fail(ctx, F2M_ERR_ARG, "mu holds a negative multiplier");
+    std::vector<int32_t> ptr(Q + 1);
+    int64_t total = 0;
+    for (int64_t q = 0; q < Q; ++q) {
+        const int32_t c = hc[q];
+        if (c < 2 || c > n - 2) fail(ctx, F2M_ERR_ARG, "every row needs 2 .. n - 2 nodes");
+        if (hc[(Q + 1) + q] != hc[2 * (Q + 1) + q]) fail(ctx, F2M_ERR_ARG, "a row id occurs in two layers");
+        ptr[q] = (int32_t)total;
+        total += c;
+    }
+    ptr[Q] = (int32_t)total;
+    s.rptr = grow<int32_t>(ctx, ctx->s_rptr, Q + 1);
+    s.rmem = grow<int32_t>(ctx, ctx->s_rmem, total + 1);
+    int32_t *cur = grow<int32_t>(ctx, ctx->s_cur, Q + 1);
+    upload(ctx, {{ptr.data(), s.rptr, (Q + 1) * sizeof(int32_t)}}, st);
+    ck(ctx, hipMemsetAsync(cur, 0, (Q + 1) * sizeof(int32_t), st), "memset");
+    ck(ctx, launch_sec_rows_fill(s.rowp, n, s.L, s.rptr, cur, s.rmem, st), "sec fill");
+    ck(ctx, launch_sec_add_mu(s.rptr, s.rmem, s.mu[0], Q, s.lamp, s.ctrl, st), "sec add");
+    return s;
+}
+
+// Column slices of the scan: enough blocks to fill the chip at small n
+struct SecShape {
+    int64_t slices, slice_len;
+};
+
+SecShape sec_shape(int64_t n)
+{
+    const int64_t tiles = (n + 255) / 256;
+    int64_t S = std::min(std::max<int64_t>(1, (1024 + tiles - 1) / tiles), tiles);
+    const int64_t len = ((n + S - 1) / S + 255) / 256 * 256;
+    return SecShape{(n + len - 1) / len, len};
+}
+
+// Runs iterations 0 .. until the stop (at most max_iters + 1); returns the
+// final control block.  trace_dev: [trace_cap][kSecTraceW] or null.
+SecCtrl sec_loop(f2m_ctx *ctx, SecSetup &s, int64_t max_iters, int64_t *trace_dev, hipStream_t st)
+{
+    const int64_t n = s.gh.g.n, Q = s.nrows, L = s.L;
+    const SecShape sh = sec_shape(n);
+    const int64_t S = sh.slices;
+    const int64_t nbn = (n + 255) / 256, nbr = (Q + 3) / 4;
+    SecScanArgs sa{};
+    sa.g = s.gh.g;
+    sa.col = s.gh.col;
+    sa.lamp = s.lamp;
+    sa.rowp = s.rowp;
+    sa.ctrl = s.ctrl;
+    sa.slice_len = sh.slice_len;
+    sa.pz = grow<int64_t>(ctx, ctx->s_pz, S * 3 * n);
+    sa.pc = grow<int32_t>(ctx, ctx->s_pc, S * 2 * n);
+    sa.prn = grow<int64_t>(ctx, ctx->s_prn, S * n);
+    sa.ppr = grow<int64_t>(ctx, ctx->s_ppr, S * n);
+    sa.pxz = grow<int64_t>(ctx, ctx->s_pxz, S * L * 3 * n);
+    sa.pxc = grow<int32_t>(ctx, ctx->s_pxc, S * L * 2 * n);
+    unsigned long long *slots = grow<unsigned long long>(ctx, ctx->s_slots, (nbn + nbr) * kSecSlotW);
+    SecNodeArgs na{};
+    na.g = s.gh.g;
+    na.nslices = S;
+    na.pz = sa.pz; na.pc = sa.pc; na.prn = sa.prn; na.ppr = sa.ppr; na.pxz = sa.pxz; na.pxc = sa.pxc;
+    na.rowp = s.rowp;
+    na.lam_best = grow<int64_t>(ctx, ctx->s_lamb, n);
+    na.lamp = s.lamp;
+    na.xz = grow<int64_t>(ctx, ctx->s_xz, L * 3 * n);
+    na.xc = grow<int32_t>(ctx, ctx->s_xc, L * 2 * n);
+    na.ctrl = s.ctrl;
+    na.slots = slots;
+    SecRowArgs ra{};
+    ra.n = n;
+    ra.nrows = Q;
+    ra.rptr = s.rptr;
+    ra.rmem = s.rmem;
+    ra.rlayer = s.rlayer;
+    ra.xz = na.xz;
+    ra.xc = na.xc;
+    ra.mu_best = grow<int64_t>(ctx, ctx->s_mub, Q + 1);
+    ra.lamp = s.lamp;
+    ra.ctrl = s.ctrl;
+    ra.slots = slots + nbn * kSecSlotW;
+    SecControlArgs ca{s.ctrl, n, 0, nbn + nbr, slots, trace_dev};
+    SecCtrl hc;
+    constexpr int64_t kChunk = 16;
+    for (int64_t k = 0; k <= max_iters;) {
+        for (int64_t j = 0; j < kChunk && k <= max_iters; ++j, ++k) {
+            sa.mu = s.mu[k & 1];
+            na.k = ra.k = ca.k = k;
+            na.lam_in = s.lam[k & 1];
+            na.lam_out = s.lam[(k + 1) & 1];
+            ra.mu_in = s.mu[k & 1];
+            ra.mu_out = s.mu[(k + 1) & 1];
+            ck(ctx, launch_sec_scan(sa, (int)L, S, st), "sec scan");
+            ck(ctx, launch_sec_node(na, (int)L, st), "sec node");
+            ck(ctx, launch_sec_rows(ra, st), "sec rows");
+            ck(ctx, launch_sec_control(ca, st), "sec control");
+        }
+        download(ctx, {{s.ctrl, &hc, sizeof(SecCtrl)}}, st);
+        if (hc.done) return hc;
+    }
+    download(ctx, {{s.ctrl, &hc, sizeof(SecCtrl)}}, st);
+    if (!hc.done) fail(ctx, F2M_ERR_DEVICE, "subtour GDP loop ended without a stop");
+    return hc;
+}
+
+// (Lam*, M*) of a finished loop to the caller's arrays (Lam by label)
+void sec_outputs(f2m_ctx *ctx, const SecSetup &s, const SecCtrl &c, int64_t *lam_label, int64_t *mu, hipStream_t st)
+{
+    const int64_t n = s.gh.g.n, Q = s.nrows;
+    const bool last = c.kstar == c.k_last;
+    const int64_t *lam = last ? s.lam[c.k_last & 1] : (const int64_t *)ctx->s_lamb.p;
+    const int64_t *mm = last ? s.mu[c.k_last & 1] : (const int64_t *)ctx->s_mub.p;
+    ck(ctx, launch_unpermute(lam, s.gh.g.orig, n, lam_label, st), "unpermute");
+    if (Q > 0) ck(ctx, hipMemcpyAsync(mu, mm, Q * sizeof(int64_t), hipMemcpyDeviceToDevice, st), "copy");
+}
+
+// One GDP call; trace to host (optional).  Returns the control block.
+SecCtrl sec_gdp(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec_rows *rows, int64_t *lam, int64_t *mu,
+                int64_t max_iters, int64_t *trace, int64_t trace_cap, bool write_back)
+{
+    hipStream_t st = ctx->stream;
+    if (!trace) trace_cap = 0;
+    SecSetup s = sec_setup(ctx, xy, n, rows, lam, mu, max_iters, trace_cap, st);
+    int64_t *tdev = trace_cap > 0 ? grow<int64_t>(ctx, ctx->s_trace, trace_cap * kSecTraceW) : nullptr;
+    const SecCtrl c = sec_loop(ctx, s, max_iters, tdev, st);
+    if (write_back) sec_outputs(ctx, s, c, lam, mu, st);
+    const int64_t nrec = std::min<int64_t>(c.k_last + 1, trace_cap);
+    if (nrec > 0)
+        ck(ctx, hipMemcpyAsync(trace, tdev, nrec * kSecTraceW * sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
+    ck(ctx, hipStreamSynchronize(st), "sync");
+    return c;
+}
+
+// Separation at (Lam, M): components of the support of the trivial x, new
+// rows for the violated cuts that are not rows yet (see f2m_sec_separate).
+// new_row_host[v]: the new row of v or -1.
+void sec_separate(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec_rows *rows, const int64_t *lam,
+                  const int64_t *mu, std::vector<int32_t> &new_row_host, int64_t *new_rows, int64_t *components)
+{
+    hipStream_t st = ctx->stream;
+    SecSetup s = sec_setup(ctx, xy, n, rows, lam, mu, 0, 0, st);
+    int32_t *parent = grow<int32_t>(ctx, ctx->s_parent, n);
+    ck(ctx, launch_sec_uf_init(parent, n, st), "uf init");
+    SecScanArgs sa{};
+    sa.g = s.gh.g;
+    sa.col = s.gh.col;
+    sa.lamp = s.lamp;
+    sa.rowp = s.rowp;
+    sa.mu = s.mu[0];
+    sa.ctrl = s.ctrl;
+    sa.slice_len = sec_shape(n).slice_len;
+    sa.support = 1;
+    sa.parent = parent;
+    ck(ctx, launch_sec_scan(sa, s.L, sec_shape(n).slices, st), "sec support");
+    ck(ctx, launch_sec_uf_final(parent, n, st), "uf final");
+    // components by their smallest label; the given rows' sets
+    std::vector<int32_t> comp(n), rof;
+    if (s.nlayers > 0) rof.resize((size_t)s.nlayers * n);
+    download(ctx, {{parent, comp.data(), n * sizeof(int32_t)}}, st);
+    if (s.nlayers > 0)
+        ck(ctx, hipMemcpy(rof.data(), rows->row_of, rof.size() * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
+    // a cut is a set and its complement: key it by the side without label 0
+    // (size, and the sum of a hash of its labels); equal keys are compared
+    // member by member
+    auto lab_hash = [](int64_t v) {
+        uint64_t z = (uint64_t)(v + 1) * 0x9E3779B97F4A7C15ULL;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        return z ^ (z >> 31);
+    };
+    uint64_t hall = 0;
+    for (int64_t v = 0; v < n; ++v) hall += lab_hash(v);
+    struct Cut {
+        int64_t size = 0;
+        uint64_t h = 0;
+        bool has0 = false;
+        std::vector<int32_t> mem;   // the given side, sorted
+    };
+    auto canon = [&](Cut &c) {
+        if (c.has0) { c.size = n - c.size; c.h = hall - c.h; }
+    };
+    auto same_cut = [&](const Cut &a, const Cut &b) {
+        if (a.size != b.size || a.h != b.h) return false;
+        if (a.has0 == b.has0) return a.mem == b.mem;
+        // complements: no common member and the sizes add up to n
+        if ((int64_t)(a.mem.size() + b.mem.size()) != n) return false;
+        size_t i = 0, j = 0;
+        while (i < a.mem.size() && j < b.mem.size()) {
+            if (a.mem[i] == b.mem[j]) return false;
+            if (a.mem[i] < b.mem[j]) ++i; else ++j;
+        }
+        return true;
+    };
+    std::vector<Cut> have(s.nrows);
+    for (int64_t l = 0; l < s.nlayers; ++l)
+        for (int64_t v = 0; v < n; ++v) {
+            const int32_t r = rof[l * n + v];
+            if (r >= 0) {
+                have[r].mem.push_back((int32_t)v);
+                have[r].h += lab_hash(v);
+                have[r].has0 = have[r].has0 || v == 0;
+            }
+        }
+    for (Cut &c : have) { c.size = (int64_t)c.mem.size(); canon(c); }
+    std::vector<int64_t> csize(n, 0);
+    for (int64_t v = 0; v < n; ++v) ++csize[comp[v]];
+    int64_t ncomp = 0;
+    for (int64_t v = 0; v < n; ++v) ncomp += comp[v] == v ? 1 : 0;
+    *components = ncomp;
+    new_row_host.assign(n, -1);
+    *new_rows = 0;
+    if (ncomp <= 1) return;
+    std::vector<Cut> fresh;
+    std::vector<int32_t> root_row(n, -1);
+    std::vector<std::vector<int32_t>> members(n);
+    for (int64_t v = 0; v < n; ++v) members[comp[v]].push_back((int32_t)v);
+    for (int64_t r = 0; r < n; ++r) {
+        if (comp[r] != r) continue;
+        const int64_t sz = csize[r];
+        if (sz < 2 || sz > n - 2) continue;
+        Cut c;
+        c.mem = members[r];
+        c.size = sz;
+        c.h = 0;
+        for (int32_t v : c.mem) c.h += lab_hash(v);
+        c.has0 = r == 0;   // the root is the smallest label
+        canon(c);
+        bool dup = false;
+        for (const Cut &h : have) dup = dup || same_cut(h, c);
+        for (const Cut &h : fresh) dup = dup || same_cut(h, c);
+        if (dup) continue;
+        root_row[r] = (int32_t)(s.nrows + (int64_t)fresh.size());
+        fresh.push_back(std::move(c));
+    }
+    for (int64_t v = 0; v < n; ++v) new_row_host[v] = root_row[comp[v]];
+    *new_rows = (int64_t)fresh.size();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2150,6 +2450,161 @@ f2m_status f2m_solve_batch(f2m_ctx *ctx, const int32_t *coords, const int64_t *o
         return f.st;
     } catch (const std::bad_alloc &) {
         for (auto &r : res) f2m_result_free(&r);
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+
+f2m_status f2m_sec_gdp(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec_rows *rows, int64_t *lam,
+                       int64_t *mu, int64_t max_iters, int64_t *trace, int64_t trace_cap, f2m_sec_result *out)
+{
+    if (!ctx) return F2M_ERR_ARG;
+    ctx->dev_cap = (size_t)ctx->defaults.max_device_bytes;
+    try {
+        if (!xy || !lam || !out || n < 4) fail(ctx, F2M_ERR_ARG, "sec_gdp needs n >= 4, coords, lambda2 and out");
+        if (max_iters < 0 || trace_cap < 0) fail(ctx, F2M_ERR_ARG, "max_iters and trace_cap must be >= 0");
+        sec_check_rows(ctx, n, rows);
+        if (rows->nrows > 0 && !mu) fail(ctx, F2M_ERR_ARG, "mu is null");
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        const double t0 = now_s();
+        const SecCtrl c = sec_gdp(ctx, xy, n, rows, lam, mu, max_iters, trace, trace_cap, true);
+        f2m_sec_result r;
+        std::memset(&r, 0, sizeof(r));
+        r.iterations = c.k_last + 1;
+        r.kstar = c.kstar;
+        r.stop = (int32_t)c.stop;
+        r.overflow = (int32_t)c.overflow;
+        r.dual2 = (c.kstar == c.k_last) ? c.dual2_last : c.best_dual2;
+        r.primal2_last = c.primal2_last;
+        r.bad_last = c.node_bad_last + c.row_infeas_last + c.row_loose_last;
+        r.seconds = now_s() - t0;
+        *out = r;
+        return c.overflow ? F2M_ERR_OVERFLOW : F2M_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+f2m_status f2m_sec_certify(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec_rows *rows,
+                           const int64_t *lam, const int64_t *mu, int64_t out[5])
+{
+    if (!ctx) return F2M_ERR_ARG;
+    ctx->dev_cap = (size_t)ctx->defaults.max_device_bytes;
+    try {
+        if (!xy || !lam || !out || n < 4) fail(ctx, F2M_ERR_ARG, "sec_certify needs n >= 4, coords, lambda2 and out");
+        sec_check_rows(ctx, n, rows);
+        if (rows->nrows > 0 && !mu) fail(ctx, F2M_ERR_ARG, "mu is null");
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        // iteration 0 of a loop capped at 0: the statistics of (Lam, M)
+        const SecCtrl c = sec_gdp(ctx, xy, n, rows, const_cast<int64_t *>(lam), const_cast<int64_t *>(mu), 0,
+                                  nullptr, 0, false);
+        const bool feasible = c.node_bad_last == 0 && c.row_infeas_last == 0;
+        const bool tight = c.row_loose_last == 0;
+        out[0] = c.primal2_last;
+        out[1] = c.dual2_last;
+        out[2] = feasible ? 1 : 0;
+        out[3] = tight ? 1 : 0;
+        out[4] = (feasible && tight && c.primal2_last == c.dual2_last) ? 1 : 0;
+        return F2M_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+f2m_status f2m_sec_separate(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec_rows *rows,
+                            const int64_t *lam, const int64_t *mu, int32_t *new_row_of, int64_t *new_rows,
+                            int64_t *components)
+{
+    if (!ctx) return F2M_ERR_ARG;
+    ctx->dev_cap = (size_t)ctx->defaults.max_device_bytes;
+    try {
+        if (!xy || !lam || !new_row_of || !new_rows || !components || n < 4)
+            fail(ctx, F2M_ERR_ARG, "sec_separate needs n >= 4 and every output");
+        sec_check_rows(ctx, n, rows);
+        if (rows->nrows > 0 && !mu) fail(ctx, F2M_ERR_ARG, "mu is null");
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        std::vector<int32_t> nr;
+        int64_t nnew = 0, ncomp = 0;
+        sec_separate(ctx, xy, n, rows, lam, mu, nr, &nnew, &ncomp);
+        // new_row_of need not be 16-byte aligned: a plain copy
+        ck(ctx, hipMemcpyAsync(new_row_of, nr.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream),
+           "copy");
+        ck(ctx, hipStreamSynchronize(ctx->stream), "sync");
+        *new_rows = nnew;
+        *components = ncomp;
+        return F2M_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return F2M_ERR_NOMEM;
+    }
+}
+
+f2m_status f2m_sec_solve(f2m_ctx *ctx, const int32_t *xy, int64_t n, int64_t *lam, int32_t *row_of,
+                         int32_t nlayers0, int64_t nrows0, int64_t *mu, int64_t mu_cap, int32_t max_rounds,
+                         int64_t max_iters, f2m_sec_solve_result *res)
+{
+    if (!ctx) return F2M_ERR_ARG;
+    ctx->dev_cap = (size_t)ctx->defaults.max_device_bytes;
+    try {
+        if (!xy || !lam || !row_of || !res || n < 4) fail(ctx, F2M_ERR_ARG, "sec_solve needs n >= 4 and its arrays");
+        if (max_rounds < 0 || max_iters < 0 || mu_cap < nrows0 || (mu_cap > 0 && !mu))
+            fail(ctx, F2M_ERR_ARG, "bad max_rounds, max_iters or mu capacity");
+        f2m_sec_rows rows{nlayers0, 0, nrows0, row_of};
+        sec_check_rows(ctx, n, &rows);
+        ck(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        const double t0 = now_s();
+        f2m_sec_solve_result r;
+        std::memset(&r, 0, sizeof(r));
+        // the start's bound (its rows and M)
+        {
+            const SecCtrl c = sec_gdp(ctx, xy, n, &rows, lam, mu, 0, nullptr, 0, false);
+            r.dual2_start = c.dual2_last;
+            r.best_dual2 = c.dual2_last;
+        }
+        f2m_status st = F2M_OK;
+        for (int32_t round = 0; round < max_rounds && rows.nlayers < F2M_SEC_MAX_LAYERS; ++round) {
+            std::vector<int32_t> nr;
+            int64_t nnew = 0, ncomp = 0;
+            sec_separate(ctx, xy, n, &rows, lam, mu, nr, &nnew, &ncomp);
+            r.components = (int32_t)std::min<int64_t>(ncomp, INT32_MAX);
+            if (nnew == 0 || rows.nrows + nnew > mu_cap) break;
+            ck(ctx, hipMemcpyAsync(row_of + (int64_t)rows.nlayers * n, nr.data(), n * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, ctx->stream), "copy");
+            ck(ctx, hipStreamSynchronize(ctx->stream), "sync");
+            ck(ctx, hipMemsetAsync(mu + rows.nrows, 0, nnew * sizeof(int64_t), ctx->stream), "memset");
+            rows.nlayers += 1;
+            rows.nrows += nnew;
+            const SecCtrl c = sec_gdp(ctx, xy, n, &rows, lam, mu, max_iters, nullptr, 0, true);
+            r.rows_added[round] = nnew;
+            r.iterations[round] = c.k_last + 1;
+            r.stop[round] = (int32_t)c.stop;
+            r.dual2[round] = (c.kstar == c.k_last) ? c.dual2_last : c.best_dual2;
+            r.best_dual2 = std::max(r.best_dual2, r.dual2[round]);
+            r.rounds = round + 1;
+            if (c.overflow) { st = F2M_ERR_OVERFLOW; break; }
+        }
+        r.nlayers = rows.nlayers;
+        r.nrows = rows.nrows;
+        {
+            const SecCtrl c = sec_gdp(ctx, xy, n, &rows, lam, mu, 0, nullptr, 0, false);
+            const bool ok = c.node_bad_last == 0 && c.row_infeas_last == 0 && c.row_loose_last == 0;
+            r.certified = (ok && c.primal2_last == c.dual2_last) ? 1 : 0;
+        }
+        r.seconds = now_s() - t0;
+        *res = r;
+        return st;
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
         ctx->err = "host allocation failed";
         return F2M_ERR_NOMEM;
     }

@@ -26,6 +26,7 @@
 // conservative: it never drops a pair with Z <= theta_v.
 #include "f2m_internal.h"
 #include "f2m_filter.h"
+#include "f2m_device.h"
 
 #include <float.h>
 #include <limits.h>
@@ -47,18 +48,6 @@ constexpr int32_t kNoIdx = INT32_MAX;
 // exact arithmetic helpers
 // ---------------------------------------------------------------------------
 
-// nint(sqrt(D)) exactly: the k with (2k-1)^2 <= 4D < (2k+1)^2 (TSPLIB
-// EUC_2D rounding).  sqrtf gives k within one; the loops make it exact.
-__device__ __forceinline__ int64_t nint_sqrt(int64_t D)
-{
-    const float f = sqrtf((float)D);
-    int64_t k = (int64_t)(f + 0.5f);
-    const int64_t d4 = 4 * D;
-    while ((2 * k + 1) * (2 * k + 1) <= d4) ++k;
-    while (k > 0 && (2 * k - 1) * (2 * k - 1) > d4) --k;
-    return k;
-}
-
 // Z_vu from centred float coordinates (exact integers, |.| <= 2^19).
 __device__ __forceinline__ int64_t exact_z(float xv, float yv, int64_t lamv, float xu, float yu,
                                            int64_t lamu)
@@ -72,22 +61,6 @@ __device__ __forceinline__ int64_t exact_z(float xv, float yv, int64_t lamv, flo
 __device__ __forceinline__ bool key_less(int64_t za, int32_t ua, int64_t zb, int32_t ub)
 {
     return za < zb || (za == zb && ua < ub);
-}
-
-// dLam = sign(s) * floor((|s| + 2) / 4)
-__device__ __forceinline__ int64_t gdp_step(int64_t s)
-{
-    if (s > 0) return (s + 2) >> 2;
-    if (s < 0) return -((-s + 2) >> 2);
-    return 0;
-}
-
-// SplitMix64 output finaliser (Steele, Lea, Flood 2014)
-__device__ __forceinline__ uint64_t mix64(uint64_t z)
-{
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
-    return z ^ (z >> 31);
 }
 
 // ---------------------------------------------------------------------------
@@ -121,36 +94,6 @@ struct Top4 {
 // ---------------------------------------------------------------------------
 // block reductions
 // ---------------------------------------------------------------------------
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_max(T x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const T y = __shfl_xor(x, o, 64);
-        x = y > x ? y : x;
-    }
-    return x;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_min(T x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const T y = __shfl_xor(x, o, 64);
-        x = y < x ? y : x;
-    }
-    return x;
-}
 
 // max over each aligned group of kSubCols lanes of a wave
 static_assert(kSubCols <= 64 && 64 % kSubCols == 0, "sub-tiles split a wave evenly");
@@ -515,14 +458,6 @@ __device__ __forceinline__ void rowscan_body(const ScanArgs &a, const int64_t rb
         const unsigned long long tot = block_reduce<unsigned long long, false>((unsigned long long)s, redu);
         if (threadIdx.x == 0 && tot != 0) atomicAdd(&a.acc[0], tot);
     }
-}
-
-// Orders the LDS accesses of one wave (no other wave takes part).
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Culled scan, one row per lane, every wave on its own.  A wave holds 64

@@ -28,7 +28,10 @@ TRACE_FIELDS = ("k", "dual2", "unsat", "bad", "max_step", "nonzero", "hash", "su
 SYMBOLS = ("f2m_opts_default", "f2m_create", "f2m_destroy", "f2m_solve", "f2m_gdp_step", "f2m_certify",
            "f2m_knn_graph", "f2m_solve_batch", "f2m_features", "f2m_mlp_forward", "f2m_mlp_grad", "f2m_mlp_adamw",
            "f2m_result_free", "f2m_status_str", "f2m_last_error", "f2m_device_name",
-           "f2m_gdp_step_noalloc")
+           "f2m_gdp_step_noalloc", "f2m_sec_gdp", "f2m_sec_certify", "f2m_sec_separate", "f2m_sec_solve")
+SEC_MAX_LAYERS = 8   # F2M_SEC_MAX_LAYERS
+SEC_TRACE_W = 9
+SEC_TRACE_FIELDS = TRACE_FIELDS + ("sum_mu",)
 MLP_PARAMS = 18817
 NOALLOC_MAX_N = 131072   # F2M_NOALLOC_MAX_N
 WARM = {"cold": 0, "user": 1, "mlp": 2, "graph": 3}
@@ -77,6 +80,24 @@ class Result(C.Structure):
 _lib = None
 
 
+class SecRows(C.Structure):
+    _fields_ = [("nlayers", C.c_int32), ("reserved", C.c_int32), ("nrows", C.c_int64), ("row_of", C.c_void_p)]
+
+
+class SecResult(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("kstar", C.c_int64), ("stop", C.c_int32), ("overflow", C.c_int32),
+                ("dual2", C.c_int64), ("primal2_last", C.c_int64), ("bad_last", C.c_int64),
+                ("seconds", C.c_double)]
+
+
+class SecSolveResult(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("nlayers", C.c_int32), ("nrows", C.c_int64),
+                ("rows_added", C.c_int64 * SEC_MAX_LAYERS), ("iterations", C.c_int64 * SEC_MAX_LAYERS),
+                ("stop", C.c_int32 * SEC_MAX_LAYERS), ("dual2", C.c_int64 * SEC_MAX_LAYERS),
+                ("dual2_start", C.c_int64), ("best_dual2", C.c_int64), ("certified", C.c_int32),
+                ("components", C.c_int32), ("seconds", C.c_double)]
+
+
 def lib():
     """Loads libf2m.so (raises if it is not built)."""
     global _lib
@@ -119,6 +140,15 @@ def lib():
         L.f2m_solve_batch.argtypes = [p, p, p, C.c_int32, C.POINTER(Opts), p]
         L.f2m_knn_graph.restype = C.c_int
         L.f2m_knn_graph.argtypes = [p, p, i64, C.c_int32, p, p, i64, p]
+        L.f2m_sec_gdp.restype = C.c_int
+        L.f2m_sec_gdp.argtypes = [p, p, i64, C.POINTER(SecRows), p, p, i64, p, i64, C.POINTER(SecResult)]
+        L.f2m_sec_certify.restype = C.c_int
+        L.f2m_sec_certify.argtypes = [p, p, i64, C.POINTER(SecRows), p, p, p]
+        L.f2m_sec_separate.restype = C.c_int
+        L.f2m_sec_separate.argtypes = [p, p, i64, C.POINTER(SecRows), p, p, p, p, p]
+        L.f2m_sec_solve.restype = C.c_int
+        L.f2m_sec_solve.argtypes = [p, p, i64, p, p, C.c_int32, i64, p, i64, C.c_int32, i64,
+                                    C.POINTER(SecSolveResult)]
         L.f2m_result_free.restype = None
         L.f2m_result_free.argtypes = [C.POINTER(Result)]
         L.f2m_status_str.restype = C.c_char_p
@@ -365,6 +395,79 @@ class Context:
                                       _dptr(ev) if m else None, _dptr(ex2) if m else None,
                                       out.ctypes.data_as(C.c_void_p)))
         return dict(primal2=int(out[0]), dual2=int(out[1]), feasible=bool(out[2]), certified=bool(out[3]))
+
+
+    # ---- subtour-elimination rows ----
+    @staticmethod
+    def _rows(row_of, nrows):
+        """f2m_sec_rows from an int32 device tensor [L, n] (or None)."""
+        if row_of is None or row_of.shape[0] == 0:
+            return SecRows(0, 0, 0, None)
+        return SecRows(int(row_of.shape[0]), 0, int(nrows), _dptr(row_of))
+
+    def sec_gdp(self, coords, row_of, nrows, lam, mu, max_iters=100000, trace=True):
+        """GDP with subtour rows on device tensors: lam (int64 [n], Lam_0 in,
+        Lam* out), mu (int64 [nrows], M_0 in, M* out), row_of (int32 [L, n]
+        or None).  Returns the result dict with the trace records."""
+        n = coords.shape[0]
+        rows = self._rows(row_of, nrows)
+        cap = max_iters + 1 if trace else 0
+        tr = np.zeros((max(cap, 1), SEC_TRACE_W), np.int64)
+        res = SecResult()
+        st = lib().f2m_sec_gdp(self._h, _dptr(coords), n, C.byref(rows), _dptr(lam),
+                               _dptr(mu) if nrows else None, int(max_iters),
+                               tr.ctypes.data_as(C.c_void_p) if cap else None, cap, C.byref(res))
+        if st not in (0, -7):
+            self._check(st)
+        out = dict(iterations=res.iterations, kstar=res.kstar, stop=STOP_NAMES.get(res.stop, str(res.stop)),
+                   overflow=bool(res.overflow), dual2=res.dual2, primal2_last=res.primal2_last,
+                   bad_last=res.bad_last, seconds=res.seconds)
+        if cap:
+            recs = []
+            for row in tr[:min(res.iterations, cap)]:
+                r = dict(zip(SEC_TRACE_FIELDS, (int(x) for x in row)))
+                r["hash"] &= (1 << 64) - 1
+                recs.append(r)
+            out["trace"] = recs
+        return out
+
+    def sec_certify(self, coords, row_of, nrows, lam, mu):
+        """Certificate of the trivial x of (Lam, M): dict(primal2, dual2,
+        feasible, tight, certified)."""
+        rows = self._rows(row_of, nrows)
+        out = np.zeros(5, np.int64)
+        self._check(lib().f2m_sec_certify(self._h, _dptr(coords), coords.shape[0], C.byref(rows), _dptr(lam),
+                                          _dptr(mu) if nrows else None, out.ctypes.data_as(C.c_void_p)))
+        return dict(primal2=int(out[0]), dual2=int(out[1]), feasible=bool(out[2]), tight=bool(out[3]),
+                    certified=bool(out[4]))
+
+    def sec_separate(self, coords, row_of, nrows, lam, mu, new_row_of):
+        """New rows of the violated cuts at (Lam, M) into new_row_of (int32
+        [n] device tensor); returns (new rows, components)."""
+        rows = self._rows(row_of, nrows)
+        nn, nc = C.c_int64(0), C.c_int64(0)
+        self._check(lib().f2m_sec_separate(self._h, _dptr(coords), coords.shape[0], C.byref(rows), _dptr(lam),
+                                           _dptr(mu) if nrows else None, _dptr(new_row_of), C.byref(nn),
+                                           C.byref(nc)))
+        return nn.value, nc.value
+
+    def sec_solve(self, coords, lam, row_of, mu, nlayers0=0, nrows0=0, max_rounds=SEC_MAX_LAYERS,
+                  max_iters=100000):
+        """Rounds of separation and GDP (f2m_sec_solve) on device tensors:
+        lam int64 [n] in/out, row_of int32 [SEC_MAX_LAYERS, n], mu int64
+        [cap]; returns the result dict."""
+        res = SecSolveResult()
+        st = lib().f2m_sec_solve(self._h, _dptr(coords), coords.shape[0], _dptr(lam), _dptr(row_of),
+                                 int(nlayers0), int(nrows0), _dptr(mu), int(mu.shape[0]), int(max_rounds),
+                                 int(max_iters), C.byref(res))
+        if st not in (0, -7):
+            self._check(st)
+        r = res.rounds
+        return dict(rounds=r, nlayers=res.nlayers, nrows=res.nrows, rows_added=list(res.rows_added[:r]),
+                    iterations=list(res.iterations[:r]), stop=[STOP_NAMES.get(x, str(x)) for x in res.stop[:r]],
+                    dual2=list(res.dual2[:r]), dual2_start=res.dual2_start, best_dual2=res.best_dual2,
+                    certified=bool(res.certified), components=res.components, seconds=res.seconds,
+                    overflow=st == -7)
 
 
 def knn_graph(ctx, coords, k=10):

@@ -68,6 +68,32 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", s
                     f2m.Result.update_ms_kind.offset, f2m.Opts.degree_b.offset]
 
 
+def test_sec_struct_layout_matches_binding():
+    from paper_2011_08170_amd import f2m
+    probe = r'''
+#include "f2m.h"
+#include <stdio.h>
+#include <stddef.h>
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %d %d\n", sizeof(f2m_sec_rows), offsetof(f2m_sec_rows, row_of),
+ sizeof(f2m_sec_result), offsetof(f2m_sec_result, dual2), offsetof(f2m_sec_result, seconds),
+ sizeof(f2m_sec_solve_result), offsetof(f2m_sec_solve_result, stop), offsetof(f2m_sec_solve_result, dual2),
+ offsetof(f2m_sec_solve_result, certified), offsetof(f2m_sec_solve_result, seconds),
+ F2M_SEC_MAX_LAYERS, F2M_SEC_TRACE_W);return 0;}
+'''
+    import tempfile
+    d = tempfile.mkdtemp()
+    c = os.path.join(d, "p.c")
+    open(c, "w").write(probe)
+    exe = os.path.join(d, "p")
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+    vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    assert vals == [ctypes.sizeof(f2m.SecRows), f2m.SecRows.row_of.offset, ctypes.sizeof(f2m.SecResult),
+                    f2m.SecResult.dual2.offset, f2m.SecResult.seconds.offset, ctypes.sizeof(f2m.SecSolveResult),
+                    f2m.SecSolveResult.stop.offset, f2m.SecSolveResult.dual2.offset,
+                    f2m.SecSolveResult.certified.offset, f2m.SecSolveResult.seconds.offset,
+                    f2m.SEC_MAX_LAYERS, f2m.SEC_TRACE_W]
+
+
 def test_no_gpu_fails_loudly():
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():
