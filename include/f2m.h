@@ -374,6 +374,8 @@ typedef struct f2m_sec_result {
     int64_t primal2_last;         /* 2 c.x of the trivial x at the last iterate */
     int64_t bad_last;             /* bad rows (nodes and subtour rows) at the last iterate */
     double seconds;
+    int64_t pairs_tested;         /* ordered pairs the scans tested with the float filter (the
+                                     culled tiles and sub-tiles excluded), all iterations */
 } f2m_sec_result;
 
 /* GDP with subtour rows from (Lam_0, M_0).

@@ -62,7 +62,8 @@ struct f2m_ctx {
     DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
     // GDP with subtour rows
     DevBuf s_ctrl, s_rowp, s_cnt, s_rptr, s_cur, s_rmem, s_lam0, s_lam1, s_lamb, s_lamp, s_mu0, s_mu1, s_mub, s_pz,
-        s_pc, s_prn, s_ppr, s_pxz, s_pxc, s_xz, s_xc, s_slots, s_trace, s_parent;
+        s_pc, s_prn, s_ppr, s_pxz, s_pxc, s_xz, s_xc, s_slots, s_trace, s_parent, s_pzi, s_pxi, s_seed, s_tileh,
+        s_tpart, s_rseed;
     // warm-start network
     DevBuf m_nbr, m_nbrd, m_sorted, m_temp, m_scale, m_feat, m_w1b, m_w2b, m_z1, m_h1b, m_z2, m_h2, m_y, m_dy, m_g2b,
         m_g2f, m_pre1, m_g1b, m_g1f, m_sq, m_part, m_lam0;
@@ -108,7 +109,8 @@ struct f2m_ctx {
                          &m_temp, &m_scale, &m_feat, &m_w1b, &m_w2b, &m_z1, &m_h1b, &m_z2, &m_h2, &m_y, &m_dy, &m_g2b,
                          &m_g2f, &m_pre1, &m_g1b, &m_g1f, &m_sq, &m_part, &m_lam0, &s_ctrl, &s_rowp, &s_cnt,
                          &s_rptr, &s_cur, &s_rmem, &s_lam0, &s_lam1, &s_lamb, &s_lamp, &s_mu0, &s_mu1, &s_mub, &s_pz,
-                         &s_pc, &s_prn, &s_ppr, &s_pxz, &s_pxc, &s_xz, &s_xc, &s_slots, &s_trace, &s_parent};
+                         &s_pc, &s_prn, &s_ppr, &s_pxz, &s_pxc, &s_xz, &s_xc, &s_slots, &s_trace, &s_parent, &s_pzi,
+                         &s_pxi, &s_seed, &s_tileh, &s_tpart, &s_rseed};
         bufs.assign(std::begin(all), std::end(all));
     }
 };
@@ -1424,6 +1426,7 @@ struct SecSetup {
     int nlayers = 0, L = 1;
     int64_t nrows = 0;
     int32_t *rowp = nullptr, *rptr = nullptr, *rmem = nullptr, *rlayer = nullptr;
+    float *tile_h = nullptr;
     SecCtrl *ctrl = nullptr;
     int64_t *lam[2] = {nullptr, nullptr}, *mu[2] = {nullptr, nullptr}, *lamp = nullptr;
 };
@@ -1477,6 +1480,8 @@ SecSetup sec_setup(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec_row
     ck(ctx, hipMemsetAsync(cur, 0, (Q + 1) * sizeof(int32_t), st), "memset");
     ck(ctx, launch_sec_rows_fill(s.rowp, n, s.L, s.rptr, cur, s.rmem, st), "sec fill");
     ck(ctx, launch_sec_add_mu(s.rptr, s.rmem, s.mu[0], Q, s.lamp, s.ctrl, st), "sec add");
+    s.tile_h = grow<float>(ctx, ctx->s_tileh, ntiles_of(n) * kBoxStride);
+    ck(ctx, launch_sec_tiles(s.lamp, n, s.tile_h, st), "sec tiles");
     return s;
 }
 
@@ -1508,7 +1513,12 @@ SecCtrl sec_loop(f2m_ctx *ctx, SecSetup &s, int64_t max_iters, int64_t *trace_de
     sa.rowp = s.rowp;
     sa.ctrl = s.ctrl;
     sa.slice_len = sh.slice_len;
+    sa.tile_h = s.tile_h;
     sa.pz = grow<int64_t>(ctx, ctx->s_pz, S * 3 * n);
+    sa.pzi = grow<int32_t>(ctx, ctx->s_pzi, S * 3 * n);
+    sa.pxi = grow<int32_t>(ctx, ctx->s_pxi, S * L * 3 * n);
+    sa.tpart = grow<unsigned long long>(ctx, ctx->s_tpart, S * nbn);
+    int32_t *seed = grow<int32_t>(ctx, ctx->s_seed, (1 + L) * 3 * n);
     sa.pc = grow<int32_t>(ctx, ctx->s_pc, S * 2 * n);
     sa.prn = grow<int64_t>(ctx, ctx->s_prn, S * n);
     sa.ppr = grow<int64_t>(ctx, ctx->s_ppr, S * n);
@@ -1519,6 +1529,8 @@ SecCtrl sec_loop(f2m_ctx *ctx, SecSetup &s, int64_t max_iters, int64_t *trace_de
     na.g = s.gh.g;
     na.nslices = S;
     na.pz = sa.pz; na.pc = sa.pc; na.prn = sa.prn; na.ppr = sa.ppr; na.pxz = sa.pxz; na.pxc = sa.pxc;
+    na.pzi = sa.pzi; na.pxi = sa.pxi;
+    na.seed = seed;
     na.rowp = s.rowp;
     na.lam_best = grow<int64_t>(ctx, ctx->s_lamb, n);
     na.lamp = s.lamp;
@@ -1536,14 +1548,19 @@ SecCtrl sec_loop(f2m_ctx *ctx, SecSetup &s, int64_t max_iters, int64_t *trace_de
     ra.xc = na.xc;
     ra.mu_best = grow<int64_t>(ctx, ctx->s_mub, Q + 1);
     ra.lamp = s.lamp;
+    ra.seed = seed;
+    ra.rseed = grow<int2>(ctx, ctx->s_rseed, 3 * (Q + 1));
+    sa.rseed = ra.rseed;
     ra.ctrl = s.ctrl;
     ra.slots = slots + nbn * kSecSlotW;
-    SecControlArgs ca{s.ctrl, n, 0, nbn + nbr, slots, trace_dev};
+    SecControlArgs ca{s.ctrl, n, 0, nbn + nbr, slots, trace_dev, sa.tpart, S * nbn};
     SecCtrl hc;
     constexpr int64_t kChunk = 16;
     for (int64_t k = 0; k <= max_iters;) {
         for (int64_t j = 0; j < kChunk && k <= max_iters; ++j, ++k) {
             sa.mu = s.mu[k & 1];
+            // iteration 0 has no seeds: its scan starts without bounds
+            sa.seed = k > 0 ? seed : nullptr;
             na.k = ra.k = ca.k = k;
             na.lam_in = s.lam[k & 1];
             na.lam_out = s.lam[(k + 1) & 1];
@@ -1552,6 +1569,7 @@ SecCtrl sec_loop(f2m_ctx *ctx, SecSetup &s, int64_t max_iters, int64_t *trace_de
             ck(ctx, launch_sec_scan(sa, (int)L, S, st), "sec scan");
             ck(ctx, launch_sec_node(na, (int)L, st), "sec node");
             ck(ctx, launch_sec_rows(ra, st), "sec rows");
+            ck(ctx, launch_sec_tiles(s.lamp, n, s.tile_h, st), "sec tiles");
             ck(ctx, launch_sec_control(ca, st), "sec control");
         }
         download(ctx, {{s.ctrl, &hc, sizeof(SecCtrl)}}, st);
@@ -1608,6 +1626,7 @@ void sec_separate(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec_rows
     sa.mu = s.mu[0];
     sa.ctrl = s.ctrl;
     sa.slice_len = sec_shape(n).slice_len;
+    sa.tile_h = s.tile_h;
     sa.support = 1;
     sa.parent = parent;
     ck(ctx, launch_sec_scan(sa, s.L, sec_shape(n).slices, st), "sec support");
@@ -2479,6 +2498,7 @@ f2m_status f2m_sec_gdp(f2m_ctx *ctx, const int32_t *xy, int64_t n, const f2m_sec
         r.primal2_last = c.primal2_last;
         r.bad_last = c.node_bad_last + c.row_infeas_last + c.row_loose_last;
         r.seconds = now_s() - t0;
+        r.pairs_tested = (int64_t)c.pairs_tested;
         *out = r;
         return c.overflow ? F2M_ERR_OVERFLOW : F2M_OK;
     } catch (const Fail &f) {

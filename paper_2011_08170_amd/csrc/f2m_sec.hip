@@ -110,6 +110,45 @@ __device__ __forceinline__ void sec_record(unsigned long long (&v)[kRecS], unsig
     }
 }
 
+// max of x over the block, returned to every thread (buf: kSB/64 floats)
+__device__ __forceinline__ float block_max(float x, float *buf)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x = wave_max(x);
+    __syncthreads();
+    if (lane == 0) buf[w] = x;
+    __syncthreads();
+    float r = buf[0];
+    for (int i = 1; i < kSB / 64; ++i) r = fmaxf(r, buf[i]);
+    return r;
+}
+
+// the three smallest (Z, column) of a list, increasing; empty entries are
+// (INT64_MAX, INT32_MAX)
+struct T3 {
+    int64_t z[3];
+    int32_t i[3];
+
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) { z[j] = INT64_MAX; i[j] = INT32_MAX; }
+    }
+    __device__ __forceinline__ static bool less(int64_t za, int32_t ia, int64_t zb, int32_t ib)
+    {
+        return za < zb || (za == zb && ia < ib);
+    }
+    __device__ __forceinline__ void ins(int64_t zz, int32_t u)
+    {
+        if (!less(zz, u, z[2], i[2])) return;
+        z[2] = zz; i[2] = u;
+        if (less(z[2], i[2], z[1], i[1])) { const int64_t a = z[1]; z[1] = z[2]; z[2] = a; const int32_t b = i[1]; i[1] = i[2]; i[2] = b; }
+        if (less(z[1], i[1], z[0], i[0])) { const int64_t a = z[0]; z[0] = z[1]; z[1] = a; const int32_t b = i[0]; i[0] = i[1]; i[1] = b; }
+    }
+};
+
+constexpr int kWin = 1024;   // column tiles tested for culling at a time
+
 template <int L>
 __global__ __launch_bounds__(kSB) void k_sec_scan(SecScanArgs a)
 {
@@ -118,29 +157,36 @@ __global__ __launch_bounds__(kSB) void k_sec_scan(SecScanArgs a)
     __shared__ long long slp[kSB];
     __shared__ int32_t sr[L][kSB];
     __shared__ int32_t so[kSB];
-    const int t = threadIdx.x;
+    __shared__ float redf[kSB / 64];
+    __shared__ unsigned long long redu[kSB / 64];
+    __shared__ unsigned int keep[kWin / 32];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t n = a.g.n;
-    const int64_t p = (int64_t)blockIdx.x * kSB + t;
+    const int64_t rblk = blockIdx.x;
+    const int64_t p = rblk * kSB + t;
     const int64_t sl = blockIdx.y;
     const int64_t c0 = sl * a.slice_len, c1 = min(n, c0 + a.slice_len);
     const float colmax = col_bound(a.g.xy2max, a.ctrl->lamp_bound);
     const bool live = p < n;
 
     Row rw;
-    int64_t nz[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+    T3 nt;
+    nt.clear();
     int32_t cn = 0, cz = 0;
     int64_t rn = 0, pr = 0;
     int32_t rv[L];
     int64_t mv[L];
-    int64_t xz[L][3];
+    T3 xt[L];
     int32_t xn[L], xzr[L];
+    int64_t xb[L];   // bound of the subtour row's third smallest crossing Z (INT64_MAX: none)
     int32_t lab = 0;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         rv[l] = live ? a.rowp[l * n + p] : -1;
         mv[l] = rv[l] >= 0 ? a.mu[rv[l]] : 0;
-        xz[l][0] = xz[l][1] = xz[l][2] = INT64_MAX;
+        xt[l].clear();
         xn[l] = xzr[l] = 0;
+        xb[l] = INT64_MAX;
     }
     if (live) {
         const float4 cv = a.col[p];
@@ -149,8 +195,77 @@ __global__ __launch_bounds__(kSB) void k_sec_scan(SecScanArgs a)
         rw.lamv = a.lamp[p];
         rw.theta = a.support ? 0 : kThetaNone;
         rw.v = p;
-        set_filter(rw, colmax);
         lab = a.g.orig[p];
+        if (!a.support && a.seed) {
+            // Z of (p, u) from global memory
+            auto zpair = [&](int64_t u) {
+                const float4 cu = a.col[u];
+                const int32_t dx = (int32_t)(rw.xv - cu.x), dy = (int32_t)(rw.yv - cu.y);
+                int64_t z = 2 * nint_sqrt((int64_t)dx * dx + (int64_t)dy * dy) - rw.lamv - a.lamp[u];
+#pragma unroll
+                for (int l = 0; l < L; ++l)
+                    if (rv[l] >= 0 && a.rowp[l * n + u] == rv[l]) z += 2 * mv[l];
+                return z;
+            };
+            // each subtour row's bound from its seed edges
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                if (rv[l] < 0) continue;
+                int64_t mx = INT64_MIN;
+                int c3 = 0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int2 e = a.rseed[(int64_t)rv[l] * 3 + j];
+                    if (e.x < 0 || e.y < 0 || e.x >= n || e.y >= n) continue;
+                    const float4 cm = a.col[e.x], cu = a.col[e.y];
+                    const int32_t dx = (int32_t)(cm.x - cu.x), dy = (int32_t)(cm.y - cu.y);
+                    int64_t z = 2 * nint_sqrt((int64_t)dx * dx + (int64_t)dy * dy) - a.lamp[e.x] - a.lamp[e.y];
+#pragma unroll
+                    for (int l2 = 0; l2 < L; ++l2) {
+                        const int32_t r1 = a.rowp[l2 * n + e.x];
+                        if (r1 >= 0 && a.rowp[l2 * n + e.y] == r1) z += 2 * a.mu[r1];
+                    }
+                    mx = z > mx ? z : mx;
+                    ++c3;
+                }
+                if (c3 == 3) xb[l] = mx;
+            }
+            int64_t th = 0;
+            bool full = true;
+            int cnt = 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int64_t u = a.seed[j * n + p];
+                if (u >= 0 && u < n && u != p) {
+                    const int64_t z = zpair(u);
+                    th = z > th ? z : th;
+                    ++cnt;
+                }
+            }
+            full = cnt == 3;
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                if (rv[l] < 0) continue;
+                cnt = 0;
+                int64_t mx = INT64_MIN;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int64_t u = a.seed[((1 + l) * 3 + j) * n + p];
+                    if (u >= 0 && u < n && u != p && a.rowp[l * n + u] != rv[l]) {
+                        const int64_t z = zpair(u);
+                        mx = z > mx ? z : mx;
+                        ++cnt;
+                    }
+                }
+                // the own list's bound or the row's, whichever is smaller
+                const int64_t b = cnt == 3 ? (mx < xb[l] ? mx : xb[l]) : xb[l];
+                if (b == INT64_MAX) full = false;
+                else th = b > th ? b : th;
+            }
+            // three distinct columns of a list bound its third smallest
+            if (full) rw.theta = th < kThetaNone ? th : kThetaNone;
+        }
+        set_filter(rw, colmax);
     } else {
         rw.xv = rw.yv = 0.0f;
         rw.lamv = 0;
@@ -179,17 +294,18 @@ __global__ __launch_bounds__(kSB) void k_sec_scan(SecScanArgs a)
         if (z > rw.theta) return;
         if (z < 0) { ++cn; rn += z; pr += 2 * cst; }
         else if (z == 0) { ++cz; pr += cst; }
-        ins3(nz, z);
-        int64_t th = nz[2];
+        nt.ins(z, (int32_t)u);
+        int64_t th = nt.z[2];
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             if (rv[l] >= 0) {
                 if (sr[l][c] != rv[l]) {
-                    ins3(xz[l], z);
+                    xt[l].ins(z, (int32_t)u);
                     if (z < 0) ++xn[l];
                     else if (z == 0) ++xzr[l];
                 }
-                th = xz[l][2] > th ? xz[l][2] : th;
+                const int64_t b = xt[l].z[2] < xb[l] ? xt[l].z[2] : xb[l];
+                th = b > th ? b : th;
             }
         }
         th = th > 0 ? th : 0;
@@ -197,15 +313,21 @@ __global__ __launch_bounds__(kSB) void k_sec_scan(SecScanArgs a)
         if (th < rw.theta) { rw.theta = th; set_filter(rw, colmax); }
     };
 
-    const int64_t ntl = (c1 - c0 + kSB - 1) / kSB;
-    // the block's own tile first (its rows' nearest columns tighten the
-    // thresholds early), then the rest in order
-    const int64_t own = ((int64_t)blockIdx.x * kSB - c0) / kSB;
-    const int64_t start = ((int64_t)blockIdx.x * kSB >= c0 && own < ntl) ? own : (int64_t)blockIdx.x % max(ntl, (int64_t)1);
-    for (int64_t i = 0; i < ntl; ++i) {
-        int64_t ti = start + i;
-        if (ti >= ntl) ti -= ntl;
-        const int64_t base = c0 + ti * kSB;
+    // the rows' half-radius of the filter: hv = (theta + Lam' + 1) / 2
+    auto hv_row = [&]() { return live ? (float)(0.5 * (double)(rw.theta + rw.lamv + 1)) : -INFINITY; };
+    // boxes of the block's rows (tile rblk) and of this wave's (its two sub-tiles)
+    const float4 rbox = a.g.box[rblk * kBoxStride];
+    float4 wbox;
+    {
+        const float4 b0 = a.g.box[rblk * kBoxStride + 1 + 2 * wave], b1 = a.g.box[rblk * kBoxStride + 2 + 2 * wave];
+        wbox = make_float4(fminf(b0.x, b1.x), fmaxf(b0.y, b1.y), fminf(b0.z, b1.z), fmaxf(b0.w, b1.w));
+    }
+    const unsigned long long lm = __ballot(live);
+    unsigned long long tested = 0;   // wave-uniform
+
+    // every row of the block against column tile gt (global tile index)
+    auto scan_tile = [&](int64_t gt) {
+        const int64_t base = gt * kSB;
         const int64_t cc = base + t;
         __syncthreads();
         if (cc < c1) {
@@ -224,18 +346,68 @@ __global__ __launch_bounds__(kSB) void k_sec_scan(SecScanArgs a)
             for (int l = 0; l < L; ++l) sr[l][t] = -1;
         }
         __syncthreads();
-        for (int g = 0; g < kSB; g += kSGroup) {
-            float m = INFINITY;
+        const float hvw = wave_max(hv_row());
+        for (int s = 0; s < kSubs; ++s) {
+            const int64_t s0 = base + s * kSubCols;
+            if (s0 >= c1) break;
+            if (!may_pass(a.g.box[gt * kBoxStride + 1 + s], wbox, hvw, a.tile_h[gt * kBoxStride + 1 + s])) continue;
+            const int64_t cols = min((int64_t)kSubCols, c1 - s0);
+            // ordered pairs: the wave's rows by the sub-tile's columns, less the diagonal
+            const unsigned long long half = (s >> 1) == wave && gt == rblk
+                                                ? __popcll(lm & ((s & 1) ? 0xffffffff00000000ULL : 0xffffffffULL))
+                                                : 0ULL;
+            tested += (unsigned long long)__popcll(lm) * (unsigned long long)cols - half;
+            for (int g = s * kSubCols; g < (s + 1) * kSubCols; g += kSGroup) {
+                float m = INFINITY;
 #pragma unroll
-            for (int q = 0; q < kSGroup; ++q) m = fminf(m, filter_value(rw, sc[g + q]));
-            if (m <= rw.thr) {
-                for (int q = 0; q < kSGroup; ++q) eval(g + q, base);
+                for (int q = 0; q < kSGroup; ++q) m = fminf(m, filter_value(rw, sc[g + q]));
+                if (m <= rw.thr) {
+                    for (int q = 0; q < kSGroup; ++q) eval(g + q, base);
+                }
             }
+        }
+    };
+
+    const int64_t t0 = c0 / kSB, t1 = (c1 + kSB - 1) / kSB;   // the slice's tiles
+    const bool own_in = rblk >= t0 && rblk < t1;
+    // the block's own tile first: its rows' nearest columns tighten theta
+    if (own_in) scan_tile(rblk);
+    for (int64_t w0 = t0; w0 < t1; w0 += kWin) {
+        const float hvb = block_max(hv_row(), redf);
+        for (int j = t; j < kWin / 32; j += kSB) keep[j] = 0u;
+        __syncthreads();
+        for (int64_t j = t; j < kWin && w0 + j < t1; j += kSB) {
+            const int64_t gt = w0 + j;
+            if (gt != rblk && may_pass(a.g.box[gt * kBoxStride], rbox, hvb, a.tile_h[gt * kBoxStride]))
+                atomicOr(&keep[j >> 5], 1u << (j & 31));
+        }
+        __syncthreads();
+        const int words = (int)((min((int64_t)kWin, t1 - w0) + 31) / 32);
+        for (int wd = 0; wd < words; ++wd) {
+            unsigned int bits = keep[wd];   // the same in every thread
+            while (bits) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                scan_tile(w0 + wd * 32 + b);
+            }
+        }
+    }
+    // pairs tested by the block
+    {
+        if (lane == 0) redu[wave] = tested;
+        __syncthreads();
+        if (t == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < kSB / 64; ++w) tot += redu[w];
+            if (a.tpart) a.tpart[sl * gridDim.x + rblk] = tot;
         }
     }
     if (!live || a.support) return;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) a.pz[(sl * 3 + j) * n + p] = nz[j];
+    for (int j = 0; j < 3; ++j) {
+        a.pz[(sl * 3 + j) * n + p] = nt.z[j];
+        a.pzi[(sl * 3 + j) * n + p] = nt.i[j];
+    }
     a.pc[(sl * 2) * n + p] = cn;
     a.pc[(sl * 2 + 1) * n + p] = cz;
     a.prn[sl * n + p] = rn;
@@ -243,7 +415,10 @@ __global__ __launch_bounds__(kSB) void k_sec_scan(SecScanArgs a)
 #pragma unroll
     for (int l = 0; l < L; ++l) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) a.pxz[((sl * L + l) * 3 + j) * n + p] = xz[l][j];
+        for (int j = 0; j < 3; ++j) {
+            a.pxz[((sl * L + l) * 3 + j) * n + p] = xt[l].z[j];
+            a.pxi[((sl * L + l) * 3 + j) * n + p] = xt[l].i[j];
+        }
         a.pxc[((sl * L + l) * 2) * n + p] = xn[l];
         a.pxc[((sl * L + l) * 2 + 1) * n + p] = xzr[l];
     }
@@ -263,18 +438,19 @@ __global__ __launch_bounds__(kSB) void k_sec_node(SecNodeArgs a)
 #pragma unroll
     for (int i = 0; i < kRecS; ++i) v[i] = 0;
     if (p < n) {
-        int64_t nz[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+        T3 nt;
+        nt.clear();
         int64_t cn = 0, cz = 0, rn = 0, pr = 0;
-        int64_t xz[L][3];
+        T3 xt[L];
         int32_t xn[L], xzr[L];
 #pragma unroll
         for (int l = 0; l < L; ++l) {
-            xz[l][0] = xz[l][1] = xz[l][2] = INT64_MAX;
+            xt[l].clear();
             xn[l] = xzr[l] = 0;
         }
         for (int64_t s = 0; s < a.nslices; ++s) {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) ins3(nz, a.pz[(s * 3 + j) * n + p]);
+            for (int j = 0; j < 3; ++j) nt.ins(a.pz[(s * 3 + j) * n + p], a.pzi[(s * 3 + j) * n + p]);
             cn += a.pc[(s * 2) * n + p];
             cz += a.pc[(s * 2 + 1) * n + p];
             rn += a.prn[s * n + p];
@@ -282,22 +458,28 @@ __global__ __launch_bounds__(kSB) void k_sec_node(SecNodeArgs a)
 #pragma unroll
             for (int l = 0; l < L; ++l) {
 #pragma unroll
-                for (int j = 0; j < 3; ++j) ins3(xz[l], a.pxz[((s * L + l) * 3 + j) * n + p]);
+                for (int j = 0; j < 3; ++j)
+                    xt[l].ins(a.pxz[((s * L + l) * 3 + j) * n + p], a.pxi[((s * L + l) * 3 + j) * n + p]);
                 xn[l] += a.pxc[((s * L + l) * 2) * n + p];
                 xzr[l] += a.pxc[((s * L + l) * 2 + 1) * n + p];
             }
         }
 #pragma unroll
+        for (int j = 0; j < 3; ++j) a.seed[j * n + p] = nt.i[j] == INT32_MAX ? -1 : nt.i[j];
+#pragma unroll
         for (int l = 0; l < L; ++l) {
             if (a.rowp[l * n + p] < 0) continue;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) a.xz[(l * 3 + j) * n + p] = xz[l][j];
+            for (int j = 0; j < 3; ++j) {
+                a.xz[(l * 3 + j) * n + p] = xt[l].z[j];
+                a.seed[((1 + l) * 3 + j) * n + p] = xt[l].i[j] == INT32_MAX ? -1 : xt[l].i[j];
+            }
             a.xc[(l * 2) * n + p] = xn[l];
             a.xc[(l * 2 + 1) * n + p] = xzr[l];
         }
         // eq. 10 on the 2nd and 3rd smallest Z of the degree row (n >= 4)
         const int64_t lamv = a.lam_in[p];
-        const int64_t st = gdp_step(nz[1] + nz[2]);
+        const int64_t st = gdp_step(nt.z[1] + nt.z[2]);
         const int64_t nxt = lamv + st;
         if (copy_best) a.lam_best[p] = a.lam_out[p];
         a.lam_out[p] = nxt;
@@ -306,7 +488,7 @@ __global__ __launch_bounds__(kSB) void k_sec_node(SecNodeArgs a)
         v[0] = (unsigned long long)lamv;
         v[2] = (unsigned long long)rn;
         v[3] = (unsigned long long)pr;
-        v[4] = (nz[1] > 0 || nz[2] < 0) ? 1 : 0;
+        v[4] = (nt.z[1] > 0 || nt.z[2] < 0) ? 1 : 0;
         v[5] = (2 * cn + cz != 4) ? 1 : 0;
         v[8] = (unsigned long long)(st < 0 ? -st : st);
         v[9] = st != 0 ? 1 : 0;
@@ -329,25 +511,49 @@ __global__ __launch_bounds__(kSB) void k_sec_rows(SecRowArgs a)
     if (q < a.nrows) {
         const int64_t l = a.rlayer[q];
         const int32_t e0 = a.rptr[q], e1 = a.rptr[q + 1];
+        // the row's three smallest crossing (Z, edge), the edge (member,
+        // column) packed member-major: values decide the step, edges only
+        // seed the next scan's bound
         int64_t tz[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+        long long te[3] = {-1, -1, -1};
+        auto ins = [&](int64_t z, long long ed) {
+            if (!(z < tz[2] || (z == tz[2] && (unsigned long long)ed < (unsigned long long)te[2]))) return;
+            tz[2] = z; te[2] = ed;
+#pragma unroll
+            for (int j = 2; j > 0; --j) {
+                if (tz[j] < tz[j - 1] || (tz[j] == tz[j - 1] && (unsigned long long)te[j] < (unsigned long long)te[j - 1])) {
+                    const int64_t x = tz[j]; tz[j] = tz[j - 1]; tz[j - 1] = x;
+                    const long long y = te[j]; te[j] = te[j - 1]; te[j - 1] = y;
+                }
+            }
+        };
         long long neg = 0, zero = 0;
         for (int32_t e = e0 + lane; e < e1; e += 64) {
             const int64_t m = a.rmem[e];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) ins3(tz, a.xz[(l * 3 + j) * n + m]);
+            for (int j = 0; j < 3; ++j) {
+                const int32_t u = a.seed[((1 + l) * 3 + j) * n + m];
+                ins(a.xz[(l * 3 + j) * n + m], u < 0 ? -1LL : (long long)(((unsigned long long)m << 32) | (uint32_t)u));
+            }
             neg += a.xc[(l * 2) * n + m];
             zero += a.xc[(l * 2 + 1) * n + m];
         }
         // the wave's three smallest: merge with the partner lane's list at
-        // each distance (a multiset: the merge order does not matter)
+        // each distance (the values are a multiset: the order does not matter)
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-            const long long u0 = __shfl_xor((long long)tz[0], o, 64);
-            const long long u1 = __shfl_xor((long long)tz[1], o, 64);
-            const long long u2 = __shfl_xor((long long)tz[2], o, 64);
-            ins3(tz, u0);
-            ins3(tz, u1);
-            ins3(tz, u2);
+            long long uz[3], ue[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                uz[j] = __shfl_xor((long long)tz[j], o, 64);
+                ue[j] = __shfl_xor(te[j], o, 64);
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) ins(uz[j], ue[j]);
+        }
+        if (lane < 3) {
+            const long long ed = lane == 0 ? te[0] : (lane == 1 ? te[1] : te[2]);
+            a.rseed[q * 3 + lane] = ed < 0 ? make_int2(-1, -1) : make_int2((int32_t)(ed >> 32), (int32_t)(ed & 0xffffffff));
         }
         neg = wave_sum(neg);
         zero = wave_sum(zero);
@@ -401,7 +607,15 @@ __global__ __launch_bounds__(kSB) void k_sec_control(SecControlArgs a)
         for (int i = 0; i < kRecS; ++i) red[w][i] = acc[i];
     }
     __syncthreads();
+    unsigned long long tt = 0;
+    for (int64_t b = threadIdx.x; b < a.ntpart; b += kSB) tt += a.tpart[b];
+    tt = wave_sum(tt);
+    __shared__ unsigned long long redt[kSB / 64];
+    if (lane == 0) redt[w] = tt;
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    for (int q = 1; q < kSB / 64; ++q) tt += redt[q];
+    c->pairs_tested += tt;
     unsigned long long r[kRecS];
 #pragma unroll
     for (int i = 0; i < kRecS; ++i) {
@@ -535,6 +749,20 @@ __global__ void k_sec_bound(SecCtrl *c)
     c->lamp_bound = c->init_lmax + c->nlayers * c->init_mmax;
 }
 
+__global__ __launch_bounds__(kSB) void k_sec_tiles(const int64_t *lamp, int64_t n, float *tile_h)
+{
+    __shared__ float redf[kSB / 64];
+    const int64_t p = (int64_t)blockIdx.x * kSB + threadIdx.x;
+    // the same float the scan's column record holds
+    const float h = p < n ? (float)(0.5 * (double)lamp[p]) : -INFINITY;
+    float hs = h;
+#pragma unroll
+    for (int o = kSubCols / 2; o > 0; o >>= 1) hs = fmaxf(hs, __shfl_xor(hs, o, 64));
+    if ((threadIdx.x & (kSubCols - 1)) == 0) tile_h[blockIdx.x * kBoxStride + 1 + threadIdx.x / kSubCols] = hs;
+    const float hm = block_max(h, redf);
+    if (threadIdx.x == 0) tile_h[blockIdx.x * kBoxStride] = hm;
+}
+
 __global__ __launch_bounds__(kSB) void k_sec_uf_init(int32_t *parent, int64_t n)
 {
     const int64_t v = (int64_t)blockIdx.x * kSB + threadIdx.x;
@@ -634,6 +862,12 @@ hipError_t launch_sec_add_mu(const int32_t *rptr, const int32_t *rmem, const int
         hipLaunchKernelGGL(k_sec_add_mu, dim3(blocks_of(nrows, kSB / 64)), dim3(kSB), 0, st, rptr, rmem, mu, nrows,
                            lamp);
     hipLaunchKernelGGL(k_sec_bound, dim3(1), dim3(1), 0, st, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_sec_tiles(const int64_t *lamp, int64_t n, float *tile_h, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sec_tiles, dim3(blocks_of(n, kSB)), dim3(kSB), 0, st, lamp, n, tile_h);
     return hipGetLastError();
 }
 

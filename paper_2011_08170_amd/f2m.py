@@ -87,7 +87,7 @@ class SecRows(C.Structure):
 class SecResult(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("kstar", C.c_int64), ("stop", C.c_int32), ("overflow", C.c_int32),
                 ("dual2", C.c_int64), ("primal2_last", C.c_int64), ("bad_last", C.c_int64),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("pairs_tested", C.c_int64)]
 
 
 class SecSolveResult(C.Structure):
@@ -421,7 +421,7 @@ class Context:
             self._check(st)
         out = dict(iterations=res.iterations, kstar=res.kstar, stop=STOP_NAMES.get(res.stop, str(res.stop)),
                    overflow=bool(res.overflow), dual2=res.dual2, primal2_last=res.primal2_last,
-                   bad_last=res.bad_last, seconds=res.seconds)
+                   bad_last=res.bad_last, seconds=res.seconds, pairs_tested=res.pairs_tested)
         if cap:
             recs = []
             for row in tr[:min(res.iterations, cap)]:

@@ -75,7 +75,7 @@ def test_sec_struct_layout_matches_binding():
 #include <stdio.h>
 #include <stddef.h>
 int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %d %d\n", sizeof(f2m_sec_rows), offsetof(f2m_sec_rows, row_of),
- sizeof(f2m_sec_result), offsetof(f2m_sec_result, dual2), offsetof(f2m_sec_result, seconds),
+ sizeof(f2m_sec_result), offsetof(f2m_sec_result, dual2), offsetof(f2m_sec_result, pairs_tested),
  sizeof(f2m_sec_solve_result), offsetof(f2m_sec_solve_result, stop), offsetof(f2m_sec_solve_result, dual2),
  offsetof(f2m_sec_solve_result, certified), offsetof(f2m_sec_solve_result, seconds),
  F2M_SEC_MAX_LAYERS, F2M_SEC_TRACE_W);return 0;}
@@ -88,7 +88,7 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %d %d\n", sizeof(
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
     vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     assert vals == [ctypes.sizeof(f2m.SecRows), f2m.SecRows.row_of.offset, ctypes.sizeof(f2m.SecResult),
-                    f2m.SecResult.dual2.offset, f2m.SecResult.seconds.offset, ctypes.sizeof(f2m.SecSolveResult),
+                    f2m.SecResult.dual2.offset, f2m.SecResult.pairs_tested.offset, ctypes.sizeof(f2m.SecSolveResult),
                     f2m.SecSolveResult.stop.offset, f2m.SecSolveResult.dual2.offset,
                     f2m.SecSolveResult.certified.offset, f2m.SecSolveResult.seconds.offset,
                     f2m.SEC_MAX_LAYERS, f2m.SEC_TRACE_W]
