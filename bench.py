@@ -85,6 +85,48 @@ def cpu_baseline(xy, lam, budget_s, iterations):
                       "(the oracle's min-cost flow is dense)" % (done, n, t_used, iterations)}
 
 
+def subtour_leg(ctx, f2m, xy_dev, cold, args):
+    """F2M plus subtour-elimination rows (the extension of Sec. 5) from the
+    certified F2M optimum of the cold solve: one separation (components of
+    its trivial x), then the GDP with those rows for --sec-iters iterations
+    (one untimed run, then `steps` timed runs from the same start)."""
+    import torch
+    n = xy_dev.shape[0]
+    lam0 = torch.from_numpy(np.asarray(cold["lambda2"], np.int64)).cuda()
+    new_row = torch.empty(n, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rows, comps = ctx.sec_separate(xy_dev, None, 0, lam0, None, new_row)
+    torch.cuda.synchronize()
+    sep_s = time.perf_counter() - t0
+    if rows == 0:
+        return {"rows": 0, "components": comps, "note": "the F2M optimum is connected: no subtour row"}
+    row_of = new_row.reshape(1, n)
+    times, g = [], None
+    for i in range(1 + max(1, args.steps)):
+        lam = lam0.clone()
+        mu = torch.zeros(rows, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = ctx.sec_gdp(xy_dev, row_of, rows, lam, mu, max_iters=args.sec_iters, trace=False)
+        torch.cuda.synchronize()
+        if i > 0:
+            times.append(time.perf_counter() - t0)
+        log("subtour GDP run %d: %d iterations, %.3f s" % (i, g["iterations"], time.perf_counter() - t0))
+    it = g["iterations"]
+    per = float(np.mean(times)) / it
+    tested = g["pairs_tested"] / it
+    return {"workload": "F2M + subtour rows from the F2M optimum of the same instance: one separation, "
+                        "then the GDP with those rows, %d iterations at most" % args.sec_iters,
+            "rows": rows, "components": comps, "separation_s": sep_s, "iterations": it, "stop": g["stop"],
+            "seconds": float(np.mean(times)), "ms_per_iteration": 1e3 * per,
+            "dual2_f2m": cold["dual2"], "dual2": g["dual2"], "bound_gain": g["dual2"] / cold["dual2"] - 1.0,
+            "pairs_tested_per_iteration": tested, "pairs_tested_frac": tested / (n * (n - 1.0)),
+            "scan_lane_ops_per_s_over_iteration": OPS_PER_PAIR * tested / per,
+            "note": "the rate divides the scan's algorithmic lane-ops by the whole iteration (scan, node and "
+                    "row steps, control): a lower bound of the scan's own; profiles/ holds its kernel times"}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -116,6 +158,8 @@ def main():
     ap.add_argument("--start", choices=("both", "cold"), default="both",
                     help="both: time the cold start, then the learned warm start (when trained weights exist) and "
                          "the candidate-graph warm start")
+    ap.add_argument("--sec-iters", type=int, default=400,
+                    help="iterations of the subtour-row GDP leg (0: skip the leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -287,6 +331,9 @@ def main():
                              "the complete-graph iterations only")
         graph_out["same_objective"] = graph_out["objective2"] == cold["objective2"]
         graph_out["speedup_time_to_certified"] = cold["time_to_certified_s"] / graph_out["time_to_certified_s"]
+    sec_out = None
+    if args.start == "both" and args.graph == "complete" and args.sec_iters > 0:
+        sec_out = subtour_leg(ctx, f2m, xy_dev, cold_runs[-1], args)
     out = {
         "metric": METRIC,
         "value": cold["value"],
@@ -308,6 +355,7 @@ def main():
     out.update({k: v for k, v in cold.items() if k not in ("value", "ms_per_step")})
     out["warm"] = warm_out
     out["warm_graph"] = graph_out
+    out["subtour"] = sec_out
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
