@@ -714,14 +714,21 @@ __device__ __forceinline__ void rowscan_wave_body(const ScanArgs &a, const int64
                 if (e + 2 < cnt) fetch(e + 2, cnt);
                 // float filter, kGroup columns at a time, into a pass mask
                 unsigned long long pm = 0;
+                // (each column's filter value is computed once; the group's
+                // bits are gathered in 32 bits and placed with one shift)
                 for (int g = 0; g < ncol; g += kGroup) {
+                    float f[kGroup];
                     float m = INFINITY;
 #pragma unroll
-                    for (int q = 0; q < kGroup; ++q) m = fminf(m, filter_value(rw, wc[wave][g + q]));
+                    for (int q = 0; q < kGroup; ++q) {
+                        f[q] = filter_value(rw, wc[wave][g + q]);
+                        m = fminf(m, f[q]);
+                    }
                     if (m <= rw.thr) {
+                        unsigned int gm = 0;
 #pragma unroll
-                        for (int q = 0; q < kGroup; ++q)
-                            pm |= (filter_value(rw, wc[wave][g + q]) <= rw.thr) ? (1ULL << (g + q)) : 0ULL;
+                        for (int q = 0; q < kGroup; ++q) gm |= f[q] <= rw.thr ? (1u << q) : 0u;
+                        pm |= (unsigned long long)gm << g;
                     }
                 }
                 while (pm) {

@@ -357,13 +357,28 @@ __global__ __launch_bounds__(kSB) void k_sec_scan(SecScanArgs a)
                                                 ? __popcll(lm & ((s & 1) ? 0xffffffff00000000ULL : 0xffffffffULL))
                                                 : 0ULL;
             tested += (unsigned long long)__popcll(lm) * (unsigned long long)cols - half;
+            // the sub-tile's columns that pass the filter, as a mask (each
+            // filter value computed once), then their exact evaluation
+            unsigned int pm = 0;
             for (int g = s * kSubCols; g < (s + 1) * kSubCols; g += kSGroup) {
+                float f[kSGroup];
                 float m = INFINITY;
 #pragma unroll
-                for (int q = 0; q < kSGroup; ++q) m = fminf(m, filter_value(rw, sc[g + q]));
-                if (m <= rw.thr) {
-                    for (int q = 0; q < kSGroup; ++q) eval(g + q, base);
+                for (int q = 0; q < kSGroup; ++q) {
+                    f[q] = filter_value(rw, sc[g + q]);
+                    m = fminf(m, f[q]);
                 }
+                if (m <= rw.thr) {
+                    unsigned int gm = 0;
+#pragma unroll
+                    for (int q = 0; q < kSGroup; ++q) gm |= f[q] <= rw.thr ? (1u << q) : 0u;
+                    pm |= gm << (g - s * kSubCols);
+                }
+            }
+            while (pm) {
+                const int q = __ffs(pm) - 1;
+                pm &= pm - 1;
+                eval(s * kSubCols + q, base);
             }
         }
     };
