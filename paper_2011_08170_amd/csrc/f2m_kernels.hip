@@ -1159,17 +1159,23 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
     if (use) {
         // Every column that can matter is in the row's list (see
         // ScanArgs::lst).  A wave's 64 rows (one scan group) have their lists
-        // in one segment per slice, row after row: the wave reads each
-        // segment in chunks, every lane taking entries lane, lane + 64, ...
-        // (their gathers all in flight together) into LDS, then each lane
-        // walks its own row's run there.
+        // in one segment per slice, row after row.  The wave takes each
+        // segment in chunks: every lane marks its own row's run in the chunk,
+        // then the lanes evaluate the chunk's entries lane, lane + 64, ...
+        // against their rows (the gathers and the exact evaluations spread
+        // over the whole wave), and each lane walks its run for the counts
+        // and its four smallest.
         constexpr int kLChunk = 256;
-        __shared__ float2 sxy[kBlock / 64][kLChunk];
-        __shared__ long long slam[kBlock / 64][kLChunk];
+        __shared__ long long sz[kBlock / 64][kLChunk];
         __shared__ int32_t slab[kBlock / 64][kLChunk];
+        __shared__ unsigned char srow[kBlock / 64][kLChunk];
+        __shared__ float2 rxy[kBlock / 64][64];
+        __shared__ long long rlam[kBlock / 64][64];
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int64_t grp = blk * (kBlock / 64) + wave, groups = (n + 63) / 64;
         const float2 xyv = p < n ? reinterpret_cast<const float2 *>(a.col)[2 * p] : make_float2(0.0f, 0.0f);
+        rxy[wave][lane] = xyv;
+        rlam[wave][lane] = lamv;
         for (int64_t sl = 0; sl < a.nslices && grp < groups; ++sl) {
             const int cnt = p < n ? min(max(a.lcnt[sl * n + p], 0), kLW * (kBlock / 64)) : 0;
             const int off = p < n ? a.loff[sl * n + p] : 0;
@@ -1178,21 +1184,25 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
             const int32_t *seg = a.lst + (sl * groups + grp) * kListCap;
             for (int c0 = 0; c0 < total; c0 += kLChunk) {
                 wave_sync();   // the previous chunk's reads are done
+                const int lo = max(off, c0), hi = min(off + cnt, c0 + kLChunk);
+                for (int e = lo; e < hi; ++e) srow[wave][e - c0] = (unsigned char)lane;
+                wave_sync();
 #pragma unroll
                 for (int j = 0; j < kLChunk / 64; ++j) {
                     const int e = c0 + j * 64 + lane;
                     if (e < total) {
                         const int64_t u = seg[e];
-                        sxy[wave][e - c0] = reinterpret_cast<const float2 *>(a.col)[2 * u];
-                        slam[wave][e - c0] = a.lam_in[u];
+                        const int r = srow[wave][e - c0] & 63;
+                        const float2 cxy = reinterpret_cast<const float2 *>(a.col)[2 * u];
+                        sz[wave][e - c0] = exact_z(rxy[wave][r].x, rxy[wave][r].y, rlam[wave][r], cxy.x, cxy.y,
+                                                   a.lam_in[u]);
                         slab[wave][e - c0] = a.g.orig[u];
                     }
                 }
                 wave_sync();
-                const int lo = max(off, c0), hi = min(off + cnt, c0 + kLChunk);
                 for (int e = lo; e < hi; ++e) {
                     const int i = e - c0;
-                    const int64_t z = exact_z(xyv.x, xyv.y, lamv, sxy[wave][i].x, sxy[wave][i].y, slam[wave][i]);
+                    const int64_t z = sz[wave][i];
                     if (z < 0) { ++cn; rn += z; }
                     else if (z == 0) ++cz;
                     top.insert(z, slab[wave][i]);
