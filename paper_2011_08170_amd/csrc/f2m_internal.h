@@ -199,13 +199,16 @@ struct UpdateArgs {
 };
 
 // candidate list entries per row and wave (see ScanArgs::lst); the margin
-// of a build is kListMult times the last max step, allowed once that step
-// is at most 1/16 of iteration 0's and the margin at most half of the last
-// one whose lists overflowed
-constexpr int kLW = 16;
+// D of a build is kListMult times the last max step, cut to half of the
+// last margin whose lists overflowed, and a build is made once that step
+// is at most 1/16 of iteration 0's and D is at least twice the step (lists
+// built with margin D serve while the steps since sum to at most D / 2).
+// Measured at n = 100k: margins of 12 steps keep a list for six
+// iterations, and the lists rarely pass 24 entries per part.
+constexpr int kLW = 24;
 // entries of one 64-row group's list segment: 64 rows x 4 parts x kLW
 constexpr int64_t kListCap = 64 * 4 * kLW;
-constexpr int64_t kListMult = 6;
+constexpr int64_t kListMult = 12;
 
 // Candidate graph (k nearest neighbours, union-symmetrised) in CSR over
 // positions: rowptr[n+1], col (positions, increasing within a row), cost.

@@ -1100,8 +1100,9 @@ __device__ __forceinline__ void control_body(int64_t n, int64_t k, Ctrl *ctrl, i
             if (!ok) {
                 // a build whose lists overflowed caps the later margins
                 if (built && c->list_over) c->list_Dmax = c->list_D / 2;
-                const long long D = kListMult * ms;
-                const bool go = ms * 16 <= c->list_ms0 && (c->list_Dmax == 0 || D <= c->list_Dmax);
+                long long D = kListMult * ms;
+                if (c->list_Dmax > 0 && D > c->list_Dmax) D = c->list_Dmax;
+                const bool go = ms * 16 <= c->list_ms0 && D >= 2 * ms;
                 c->list_D = go ? D : 0;
                 c->list_over = 0;
             }
