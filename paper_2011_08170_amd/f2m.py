@@ -176,18 +176,47 @@ def _np(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
-def _result_dict(res, n, st):
+class _Owner:
+    """Keeps an f2m_result's host arrays alive while numpy views of them
+    exist; the library frees them when the last view goes."""
+
+    def __init__(self, res):
+        self.res = res
+
+    def __del__(self):
+        try:
+            lib().f2m_result_free(C.byref(self.res))
+        except Exception:
+            pass
+
+
+def _view(owner, ptr, ctype, count):
+    """numpy view of `count` entries of a library-owned array (no copy), or
+    a copy when there is no owner (the caller frees the result)."""
+    if not ptr or count <= 0:
+        return np.zeros(0, np.dtype(ctype))
+    buf = (ctype * count).from_address(C.cast(ptr, C.c_void_p).value)
+    if owner is None:
+        return np.frombuffer(buf, dtype=np.dtype(ctype)).copy()
+    buf._owner = owner
+    return np.frombuffer(buf, dtype=np.dtype(ctype))
+
+
+def _result_dict(res, n, st, own=True):
+    """The result as a dict; with own, its arrays are views that keep the
+    result's memory until the last of them goes (else copies)."""
     m = res.n_edges
+    owner = _Owner(res) if own else None
     out = dict(
         status=STATUS[st], certified=bool(res.certified), stop=STOP_NAMES.get(res.stop, "?"),
         iterations=res.iterations, kstar=res.kstar, primal2=res.primal2, dual2=res.dual2,
         dual2_gdp=res.dual2_gdp, finish_paths=res.finish_paths, finish_rounds=res.finish_rounds,
-        lambda2=np.ctypeslib.as_array(res.lambda2, (n,)).copy(),
-        lambda2_gdp=np.ctypeslib.as_array(res.lambda2_gdp, (n,)).copy(),
-        lambda2_last=(np.ctypeslib.as_array(res.lambda2_last, (n,)).copy() if res.lambda2_last else None),
-        edge_u=np.ctypeslib.as_array(res.edge_u, (max(m, 1),))[:m].copy(),
-        edge_v=np.ctypeslib.as_array(res.edge_v, (max(m, 1),))[:m].copy(),
-        edge_x2=np.ctypeslib.as_array(res.edge_x2, (max(m, 1),))[:m].copy(),
+        lambda2=_view(owner, res.lambda2, C.c_int64, n),
+        lambda2_gdp=_view(owner, res.lambda2_gdp, C.c_int64, n),
+        lambda2_last=_view(owner, res.lambda2_last, C.c_int64, n) if res.lambda2_last else None,
+        edge_u=_view(owner, res.edge_u, C.c_int32, m),
+        edge_v=_view(owner, res.edge_v, C.c_int32, m),
+        edge_x2=_view(owner, res.edge_x2, C.c_uint8, m),
         seconds=dict(zip(("setup", "warm", "gdp", "finish", "certify", "total"), list(res.seconds))),
         scan_ms=res.scan_ms, scan_launches=res.scan_launches, scan_rows=res.scan_rows,
         scan_slices=res.scan_slices, scan_pairs=res.scan_pairs,
@@ -305,10 +334,8 @@ class Context:
             ptr = xy.ctypes.data
         res = Result()
         st = self._check(lib().f2m_solve(self._h, ptr, n, C.byref(o), C.byref(res)))
-        try:
-            return _result_dict(res, n, st)
-        finally:
-            lib().f2m_result_free(C.byref(res))
+        # the arrays are views of the result's host memory, freed with the last of them
+        return _result_dict(res, n, st)
 
     def solve_batch(self, coords, offsets, *, max_iters=100000, handoff_div=HANDOFF_DIV, finish="exact", trace=False,
                     chunk=0, scan="culled", lambda2_init=None, slices=0, tuner_cache=None):
@@ -342,7 +369,7 @@ class Context:
         out = []
         try:
             for i in range(k):
-                out.append(_result_dict(arr[i], int(off[i + 1] - off[i]), 0 if arr[i].certified else 1))
+                out.append(_result_dict(arr[i], int(off[i + 1] - off[i]), 0 if arr[i].certified else 1, own=False))
         finally:
             for i in range(k):
                 lib().f2m_result_free(C.byref(arr[i]))
