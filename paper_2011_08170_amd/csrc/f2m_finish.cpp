@@ -951,15 +951,33 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
     r.t_collect = r.t_build = r.t_flow = 0.0;
     double t = secs();
     DoubleCover &g = work->g;
-    g.reset(xy, n, lam0, b);
     PairList &pl = work->pl;
     std::vector<int64_t> &lam = work->lam;
     std::string err;
     pl.clear();
     int64_t slack = 16;
+    // the double cover is reset on another thread while the first
+    // collection runs (the pair source mostly waits for the GPU); the two
+    // touch disjoint state
+    std::exception_ptr reset_err;
+    std::thread resetter([&] {
+        try {
+            g.reset(xy, n, lam0, b);
+        } catch (...) {
+            reset_err = std::current_exception();
+        }
+    });
     src.want_bulk = true;
-    const bool got = src.near(lam0, slack, pl, err);
+    bool got = false;
+    try {
+        got = src.near(lam0, slack, pl, err);
+    } catch (...) {
+        resetter.join();
+        throw;
+    }
+    resetter.join();
     src.want_bulk = false;
+    if (reset_err) std::rethrow_exception(reset_err);
     if (!got) { r.msg = err; return; }
     r.t_collect += secs() - t;
     t = secs();
