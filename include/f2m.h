@@ -387,9 +387,10 @@ typedef struct f2m_sec_result {
  *   iterations 0 .. min(iterations, trace_cap) - 1.
  * Status F2M_OK (also when stopped by cycle or cap: the bound is valid for
  * any iterate), F2M_ERR_OVERFLOW when the multipliers grow past the range
- * (out->overflow set; Lam* and M* are still returned).  A device
- * workspace of about 8 + 72 L words per node (L = nlayers rounded up to 1,
- * 2, 4 or 8) is kept in the context. */
+ * (out->overflow set; Lam* and M* are still returned).  The context keeps
+ * a device workspace of about (60 + 44 L) S + 100 + 60 L bytes per node
+ * (L = nlayers rounded up to 1, 2, 4 or 8; S = column slices, 1 from
+ * n = 262k up, more below so that small instances fill the GPU). */
 f2m_status f2m_sec_gdp(f2m_ctx *ctx, const int32_t *coords_xy, int64_t n, const f2m_sec_rows *rows,
                        int64_t *lambda2, int64_t *mu, int64_t max_iters, int64_t *trace, int64_t trace_cap,
                        f2m_sec_result *out);
