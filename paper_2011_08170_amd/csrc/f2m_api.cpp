@@ -59,7 +59,7 @@ struct f2m_ctx {
     // node degrees b (b-matching rows) by label and by position
     DevBuf deg_label, deg_pos;
     // candidate graph
-    DevBuf knn_nbr, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
+    DevBuf knn_nbr, knn_pp, knn_pd, csr_keys, csr_keys2, csr_deg, csr_rowptr, csr_col, csr_cost, csr_temp, csr_nnz;
     // GDP with subtour rows
     DevBuf s_ctrl, s_rowp, s_cnt, s_rptr, s_cur, s_rmem, s_lam0, s_lam1, s_lamb, s_lamp, s_mu0, s_mu1, s_mub, s_pz,
         s_pc, s_prn, s_ppr, s_pxz, s_pxc, s_xz, s_xc, s_slots, s_trace, s_parent, s_pzi, s_pxi, s_seed, s_tileh,
@@ -101,7 +101,7 @@ struct f2m_ctx {
                          &col, &lam[0], &lam[1], &lam_best, &lam_label, &tile_hmax, &pz, &pi, &pneg, &pzero,
                          &prowneg, &pflag, &z4, &i4, &z4p, &i4p, &seed, &ctrl, &trace, &lst, &lcnt, &loff, &tpart, &slots, &kinds, &slot_u, &slot_v, &slot_x, &eu, &ev, &ex,
                          &btmp, &count, &c_col, &c_lam, &c_tile_hmax, &c_ctrl, &c_deg, &c_cnt, &c_nb, &c_acc,
-                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &deg_label, &deg_pos, &knn_nbr, &csr_keys,
+                         &c_lam_label, &c_eu, &c_ev, &c_ex, &p_pairs, &p_count, &p_keys, &p_keys2, &p_keys3, &p_temp, &p_ucount, &p_costs, &p_neg, &p_deg, &p_start, &p_inc, &p_ucount2, &p_cand, &f_xyp, &f_lam, &deg_label, &deg_pos, &knn_nbr, &knn_pp, &knn_pd, &csr_keys,
                          &csr_keys2, &csr_deg, &csr_rowptr, &csr_col, &csr_cost, &csr_temp, &csr_nnz,
                          &b_xy, &b_orig, &b_pos, &b_col, &b_box, &b_x2m, &b_lam0, &b_lam1, &b_best, &b_lamlabel,
                          &b_thm, &b_pz, &b_pi, &b_pneg, &b_pzero, &b_prn, &b_z4, &b_i4, &b_seed, &b_ctrl, &b_trace,
@@ -757,7 +757,9 @@ Csr build_graph(f2m_ctx *ctx, const GeoHost &gh, int K, hipStream_t st)
     const size_t tb = csr_temp_bytes(n, K);
     void *temp = grow<char>(ctx, ctx->csr_temp, tb);
     ck(ctx, hipMemsetAsync(nnz_dev, 0, sizeof(int64_t), st), "memset");
-    ck(ctx, launch_knn(gh.g, gh.col, K, nbr, nullptr, st), "knn");
+    const int64_t kps = knn_slices(n) * n * K;
+    ck(ctx, launch_knn(gh.g, gh.col, K, nbr, nullptr, grow<int32_t>(ctx, ctx->knn_pp, kps),
+                       grow<int64_t>(ctx, ctx->knn_pd, kps), st), "knn");
     ck(ctx, launch_build_csr(gh.g, gh.xy, n, K, nbr, keys, keys2, deg, rowptr, col, cost, nnz_dev, temp, tb, 2 * nk,
                              st), "csr");
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, nnz_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");
@@ -1077,7 +1079,9 @@ void features_dev(f2m_ctx *ctx, const GeoHost &gh, uint16_t *feat, float *scale_
     uint64_t *sorted = grow<uint64_t>(ctx, ctx->m_sorted, n * kMlpIn);
     const size_t tb = median_temp_bytes(n * kMlpIn);
     void *temp = grow<char>(ctx, ctx->m_temp, tb);
-    ck(ctx, launch_knn(gh.g, gh.col, kMlpIn, nbr, nbrd, st), "knn16");
+    const int64_t kps = knn_slices(n) * n * kMlpIn;
+    ck(ctx, launch_knn(gh.g, gh.col, kMlpIn, nbr, nbrd, grow<int32_t>(ctx, ctx->knn_pp, kps),
+                       grow<int64_t>(ctx, ctx->knn_pd, kps), st), "knn16");
     ck(ctx, launch_features(nbrd, gh.g.orig, n, sorted, temp, tb, scale_dev, feat, st), "features");
 }
 

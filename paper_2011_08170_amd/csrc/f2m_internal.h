@@ -258,8 +258,11 @@ hipError_t launch_ctrl_nblocks(Ctrl *ctrls, const int64_t *nblocks, int64_t nins
 hipError_t launch_count_active(const Ctrl *ctrls, int64_t ninst, int32_t *out, hipStream_t st);
 
 // Launchers (f2m_kernels.hip).  All run on `st`; none synchronises.
-// k nearest neighbours (K in {10, 16}) by (D, label): nbr[p*K + j] positions
-hipError_t launch_knn(const Geo &g, const float4 *col, int K, int32_t *nbr, int64_t *nbr_d, hipStream_t st);
+// k nearest neighbours (K in {10, 16}) by (D, label): nbr[p*K + j] positions;
+// pp / pd: the column slices' lists, knn_slices(n) * n * K entries each
+int64_t knn_slices(int64_t n);
+hipError_t launch_knn(const Geo &g, const float4 *col, int K, int32_t *nbr, int64_t *nbr_d, int32_t *pp,
+                      int64_t *pd, hipStream_t st);
 // CSR of the union-symmetrised graph; returns nnz through nnz_dev
 size_t csr_temp_bytes(int64_t n, int K);
 hipError_t launch_build_csr(const Geo &g, const int32_t *xy, int64_t n, int K, const int32_t *nbr, uint64_t *keys,

@@ -1375,8 +1375,14 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
 // beyond its own rows' bound.  The float distance test keeps every pair with
 // D <= the current K-th smallest exactly (see thrf); insertion is exact in
 // int64 with ties broken by label.
+// With S > 1 column slices (blockIdx.y), every slice scans the block's own
+// tile (so all take the same culling decisions) and every S-th of the
+// surviving tiles; each writes its K smallest to pp / pd [slice][n][K]
+// (positions, D; -1 none) for k_knn_merge.  With S == 1 the block writes
+// nbr / nbr_d itself.
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_t *nbr, int64_t *nbr_d)
+__global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_t *nbr, int64_t *nbr_d, int64_t S,
+                                                int32_t *pp, int64_t *pd)
 {
     __shared__ float2 sc[kTile];
     __shared__ int32_t sl[kTile];
@@ -1478,7 +1484,10 @@ __global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_
     };
 
     // 3. the other tiles: tested in parallel against the block, compacted
-    //    in order; each wave then tests the sub-tiles against its own rows
+    //    in order (this slice takes every S-th); each wave then tests the
+    //    sub-tiles against its own rows
+    const int64_t slc = blockIdx.y;
+    int64_t seen = 0;   // surviving tiles before this chunk of tests
     for (int64_t base = 0; base < ntiles; base += kBlock) {
         const int64_t ti = base + t;
         const bool ok = ti < ntiles && ti != own && near_box(g.box[ti * kBoxStride], rbox, thr_b);
@@ -1495,6 +1504,7 @@ __global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_
         if (ok) tlist[off + __popcll(mk & ((1ULL << lane) - 1ULL))] = (int32_t)ti;
         __syncthreads();
         for (int j = 0; j < total; ++j) {
+            if ((seen + j) % S != slc) continue;
             const int64_t tj = tlist[j];
             load(tj * kTile);
             const int ntile = (int)min((int64_t)kTile, n - tj * kTile);
@@ -1507,13 +1517,61 @@ __global__ __launch_bounds__(kBlock) void k_knn(Geo g, const float4 *col, int32_
                 scan(tj * kTile, sb * kSubCols, min(sb * kSubCols + kSubCols, ntile));
             }
         }
+        seen += total;
     }
     if (valid) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            nbr[p * K + j] = bp[j];
-            if (nbr_d) nbr_d[p * K + j] = bd[j];
+            if (S > 1) {
+                pp[(slc * n + p) * K + j] = bp[j];
+                pd[(slc * n + p) * K + j] = bd[j];
+            } else {
+                nbr[p * K + j] = bp[j];
+                if (nbr_d) nbr_d[p * K + j] = bd[j];
+            }
         }
+    }
+}
+
+// The K smallest (D, label) of a row over the slices' lists of k_knn; the
+// own tile's columns are in every slice's list and are taken once.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_knn_merge(Geo g, int64_t S, const int32_t *pp, const int64_t *pd,
+                                                      int32_t *nbr, int64_t *nbr_d)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t n = g.n;
+    if (p >= n) return;
+    int64_t bd[K];
+    int32_t bl[K], bp[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) { bd[j] = INT64_MAX; bl[j] = kNoIdx; bp[j] = -1; }
+    for (int64_t s = 0; s < S; ++s) {
+        for (int j = 0; j < K; ++j) {
+            const int32_t u = pp[(s * n + p) * K + j];
+            if (u < 0) continue;
+            bool dup = false;
+#pragma unroll
+            for (int q = 0; q < K; ++q) dup = dup || bp[q] == u;
+            if (dup) continue;
+            const int64_t D = pd[(s * n + p) * K + j];
+            const int32_t lu = g.orig[u];
+            if (!(D < bd[K - 1] || (D == bd[K - 1] && lu < bl[K - 1]))) continue;
+            bd[K - 1] = D; bl[K - 1] = lu; bp[K - 1] = u;
+#pragma unroll
+            for (int q = K - 1; q > 0; --q) {
+                if (bd[q] < bd[q - 1] || (bd[q] == bd[q - 1] && bl[q] < bl[q - 1])) {
+                    const int64_t td = bd[q]; bd[q] = bd[q - 1]; bd[q - 1] = td;
+                    const int32_t tl = bl[q]; bl[q] = bl[q - 1]; bl[q - 1] = tl;
+                    const int32_t tp = bp[q]; bp[q] = bp[q - 1]; bp[q - 1] = tp;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        nbr[p * K + j] = bp[j];
+        if (nbr_d) nbr_d[p * K + j] = bd[j];
     }
 }
 
@@ -2362,12 +2420,29 @@ hipError_t launch_graph_step(const GraphStepArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_knn(const Geo &g, const float4 *col, int K, int32_t *nbr, int64_t *nbr_d, hipStream_t st)
+int64_t knn_slices(int64_t n)
+{
+    // enough workgroups for six waves per SIMD of the 256 CUs
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    const int64_t s = (1536 + tiles - 1) / tiles;
+    return s < 1 ? 1 : (s > 8 ? 8 : s);
+}
+
+hipError_t launch_knn(const Geo &g, const float4 *col, int K, int32_t *nbr, int64_t *nbr_d, int32_t *pp,
+                      int64_t *pd, hipStream_t st)
 {
     if (g.n < K + 1) return hipErrorInvalidValue;
+    const int64_t S = knn_slices(g.n);
+    const dim3 grid(blocks_for(g.n, kBlock), (unsigned)S);
     switch (K) {
-    case 10: hipLaunchKernelGGL(k_knn<10>, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, col, nbr, nbr_d); break;
-    case 16: hipLaunchKernelGGL(k_knn<16>, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, col, nbr, nbr_d); break;
+    case 10:
+        hipLaunchKernelGGL(k_knn<10>, grid, dim3(kBlock), 0, st, g, col, nbr, nbr_d, S, pp, pd);
+        if (S > 1) hipLaunchKernelGGL(k_knn_merge<10>, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, S, pp, pd, nbr, nbr_d);
+        break;
+    case 16:
+        hipLaunchKernelGGL(k_knn<16>, grid, dim3(kBlock), 0, st, g, col, nbr, nbr_d, S, pp, pd);
+        if (S > 1) hipLaunchKernelGGL(k_knn_merge<16>, dim3(blocks_for(g.n, kBlock)), dim3(kBlock), 0, st, g, S, pp, pd, nbr, nbr_d);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
