@@ -161,6 +161,7 @@ public:
         });
         A_ = B_ = 0;
         keys_.clear();
+        extra_.clear();
         e_.clear();
         inc_.clear();
         built_ = 0;
@@ -285,6 +286,7 @@ public:
             have_prev = true;
             j = (size_t)(std::lower_bound(keys_.begin() + j, keys_.end(), key) - keys_.begin());
             if (j < keys_.size() && keys_[j] == key) continue;
+            if (std::binary_search(extra_.begin(), extra_.end(), key)) continue;
             fresh_.push_back(key);
             fresh_c_.push_back(costs ? costs[q] : -1);
         }
@@ -311,10 +313,22 @@ public:
             }
             e_.push_back(ed);
         }
-        merged_.resize(keys_.size() + fresh_.size());
-        std::merge(keys_.begin(), keys_.end(), fresh_.begin(), fresh_.end(), merged_.begin());
-        keys_.swap(merged_);
+        merged_.resize(extra_.size() + fresh_.size());
+        std::merge(extra_.begin(), extra_.end(), fresh_.begin(), fresh_.end(), merged_.begin());
+        extra_.swap(merged_);
+        if (extra_.size() * 8 > keys_.size()) {
+            merged_.resize(keys_.size() + extra_.size());
+            std::merge(keys_.begin(), keys_.end(), extra_.begin(), extra_.end(), merged_.begin());
+            keys_.swap(merged_);
+            extra_.clear();
+        }
         build_adjacency();
+    }
+
+    bool has_key(uint64_t key) const
+    {
+        return std::binary_search(keys_.begin(), keys_.end(), key) ||
+               std::binary_search(extra_.begin(), extra_.end(), key);
     }
 
     // Whether some pair of pl that is not a candidate yet has Z < 0 under
@@ -324,7 +338,7 @@ public:
         for (size_t q = 0; q < pl.size(); ++q) {
             const int32_t a = std::min(pl[q].first, pl[q].second), b = std::max(pl[q].first, pl[q].second);
             if (a == b || a < 0 || b >= n_) continue;
-            if (std::binary_search(keys_.begin(), keys_.end(), pair_key(a, b))) continue;
+            if (has_key(pair_key(a, b))) continue;
             int64_t c;
             if (costs) {
                 c = costs[q];
@@ -419,24 +433,38 @@ public:
     }
 
     // the edges with flow, in candidate order
-    void x(std::vector<int32_t> &eu, std::vector<int32_t> &ev, std::vector<uint8_t> &ex2) const
+    void x(std::vector<int32_t> &eu, std::vector<int32_t> &ev, std::vector<uint8_t> &ex2)
     {
-        // every edge is written, the index moves past those with flow
-        const size_t m = e_.size();
-        eu.resize(m);
-        ev.resize(m);
-        ex2.resize(m);
-        size_t k = 0;
-        for (const Edge &ed : e_) {
-            const int f = ed.y[0] + ed.y[1];
-            eu[k] = ed.a;
-            ev[k] = ed.b;
-            ex2[k] = (uint8_t)f;
-            k += f != 0 ? 1 : 0;
-        }
-        eu.resize(k);
-        ev.resize(k);
-        ex2.resize(k);
+        // in ranges of edges on the pool's threads: each range counts its
+        // edges with flow, then writes them from its offset (only those: the
+        // slot after a range's last one is the next range's first)
+        const int64_t m = (int64_t)e_.size();
+        const int T = (int)std::max<int64_t>(1, std::min<int64_t>(threads_, m / 8192));
+        std::vector<int64_t> at(T + 1, 0);
+        auto range = [&](int w, bool write) {
+            const int64_t lo = m * w / T, hi = m * (w + 1) / T;
+            int64_t k = write ? at[w] : 0;
+            for (int64_t i = lo; i < hi; ++i) {
+                const Edge &ed = e_[i];
+                const int f = ed.y[0] + ed.y[1];
+                if (f == 0) continue;
+                if (write) {
+                    eu[k] = ed.a;
+                    ev[k] = ed.b;
+                    ex2[k] = (uint8_t)f;
+                }
+                ++k;
+            }
+            if (!write) at[w + 1] = k;
+        };
+        if (T == 1) range(0, false);
+        else pool_.run(T, [&](int w) { range(w, false); });
+        for (int w = 0; w < T; ++w) at[w + 1] += at[w];
+        eu.resize(at[T]);
+        ev.resize(at[T]);
+        ex2.resize(at[T]);
+        if (T == 1) range(0, true);
+        else pool_.run(T, [&](int w) { range(w, true); });
     }
 
 private:
@@ -893,6 +921,9 @@ private:
     std::vector<int64_t> touched_, cur_;
     std::vector<Item> heap_;
     std::vector<uint64_t> keys_;     // sorted keys (pair_key) of the candidate edges
+    // keys added after keys_ was last merged, sorted: a few pricing rounds
+    // add tens of pairs each, so they wait here instead of rewriting keys_
+    std::vector<uint64_t> extra_;
     std::vector<uint64_t> fresh_, merged_;
     std::vector<int32_t> fresh_c_;
     std::vector<Edge> e_;
