@@ -561,6 +561,8 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
 {
     out.clear();
     src.costs = nullptr;
+    src.keys = nullptr;
+    src.nkeys = 0;
     src.neg = nullptr;
     src.inc_start = nullptr;
     src.inc = nullptr;
@@ -624,8 +626,14 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
         ck(ctx, launch_copy_bytes(inc, ctx->h_inc.dp, (2 * u + 2 * n) * sizeof(int32_t), st), "copy");
     }
     ck(ctx, hipStreamSynchronize(st), "sync");
-    out.resize(u);
-    for (int64_t i = 0; i < u; ++i) out[i] = {(int32_t)(hk[i] >> 32), (int32_t)(hk[i] & 0xffffffffULL)};
+    if (lam_bulk) {
+        // the bulk pairs go to the finish as their sorted keys
+        src.keys = hk;
+        src.nkeys = u;
+    } else {
+        out.resize(u);
+        for (int64_t i = 0; i < u; ++i) out[i] = {(int32_t)(hk[i] >> 32), (int32_t)(hk[i] & 0xffffffffULL)};
+    }
     src.costs = hc;
     src.neg = hn;
     src.inc_start = hs;
@@ -698,6 +706,8 @@ private:
                     // finish computes their costs)
                     out.clear();
                     costs = nullptr;
+                    keys = nullptr;
+                    nkeys = 0;
                     neg = nullptr;
                     inc_start = nullptr;
                     inc = nullptr;

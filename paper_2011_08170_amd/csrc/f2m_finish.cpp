@@ -177,7 +177,9 @@ public:
     // then add() does the work.
     bool add_bulk(const PairList &pl, const PairSource &src)
     {
-        const int64_t m = (int64_t)pl.size();
+        // the pairs come as keys or as the list
+        const uint64_t *sk = src.keys;
+        const int64_t m = sk ? src.nkeys : (int64_t)pl.size();
         if (!e_.empty() || m == 0 || !src.costs || !src.neg || !src.inc_start || !src.inc) return false;
         const int32_t *is = src.inc_start;
         if (is[0] != 0 || (int64_t)is[n_] != 2 * m + kSpare * n_) return false;
@@ -187,9 +189,10 @@ public:
         e_.resize(m);
         parallel_for(m, [&](int64_t lo, int64_t hi) {
             for (int64_t i = lo; i < hi; ++i) {
-                const int32_t a = pl[i].first, b = pl[i].second;
-                if (a < 0 || a >= b || b >= n_ ||
-                    (i > 0 && pair_key(pl[i - 1].first, pl[i - 1].second) >= pair_key(a, b))) {
+                const int32_t a = sk ? (int32_t)(sk[i] >> 32) : pl[i].first;
+                const int32_t b = sk ? (int32_t)(sk[i] & 0xffffffffULL) : pl[i].second;
+                const uint64_t pk = i == 0 ? 0 : (sk ? sk[i - 1] : pair_key(pl[i - 1].first, pl[i - 1].second));
+                if (a < 0 || a >= b || b >= n_ || (i > 0 && pk >= pair_key(a, b))) {
                     ok = false;
                     return;
                 }
@@ -236,9 +239,19 @@ public:
             }
             return false;
         }
-        inc_.assign(src.inc, src.inc + is[n_]);
-        for (int64_t v = 0; v < n_; ++v)
-            if (cp_[n_ + v].ex > 0) src_.push_back(n_ + v);
+        // the lists (copied in ranges) and the nodes with excess (gathered
+        // in ranges, then joined in node order)
+        inc_.resize(is[n_]);
+        parallel_for(is[n_], [&](int64_t lo, int64_t hi) { std::copy(src.inc + lo, src.inc + hi, inc_.begin() + lo); });
+        const int T = (int)std::max<int64_t>(1, std::min<int64_t>(threads_, n_ / 4096));
+        std::vector<std::vector<int64_t>> part(T);
+        auto gather = [&](int w) {
+            for (int64_t v = n_ * w / T; v < n_ * (w + 1) / T; ++v)
+                if (cp_[n_ + v].ex > 0) part[w].push_back(n_ + v);
+        };
+        if (T == 1) gather(0);
+        else pool_.run(T, gather);
+        for (const auto &q : part) src_.insert(src_.end(), q.begin(), q.end());
         built_ = m;
         return true;
     }
@@ -1012,7 +1025,12 @@ void finish_exact(const int32_t *xy, int64_t n, const int64_t *lam0, PairSource 
     if (!got) { r.msg = err; return; }
     r.t_collect += secs() - t;
     t = secs();
-    if (!g.add_bulk(pl, src)) g.add(pl, src.costs);
+    if (!g.add_bulk(pl, src)) {
+        if (pl.empty() && src.keys)
+            for (int64_t i = 0; i < src.nkeys; ++i)
+                pl.emplace_back((int32_t)(src.keys[i] >> 32), (int32_t)(src.keys[i] & 0xffffffffULL));
+        g.add(pl, src.costs);
+    }
     r.t_build += secs() - t;
     for (int round = 0; round < 64; ++round) {
         ++r.rounds;

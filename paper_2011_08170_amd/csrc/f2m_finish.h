@@ -48,6 +48,10 @@ struct PairSource {
     // inc_start[v + 1] - 2), inc_start of n + 1 entries, inc of 2 * pairs +
     // 2 * n entries).
     bool want_bulk = false;
+    // Bulk data, optional: the pairs as sorted keys (u << 32 | v, u < v) in
+    // place of the pair list, which the source may then leave empty
+    const uint64_t *keys = nullptr;
+    int64_t nkeys = 0;
     const uint8_t *neg = nullptr;
     const int32_t *inc_start = nullptr;
     const int32_t *inc = nullptr;

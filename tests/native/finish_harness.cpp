@@ -13,7 +13,9 @@ struct BrutePairs : PairSource {
     const int32_t *xy;
     int64_t n;
     bool bulk = false;   // also supply costs and the bulk data, as the library's GPU source does
+    bool as_keys = false;   // the bulk pairs as sorted keys, the pair list left empty
     std::vector<int32_t> c_, start_, inc_;
+    std::vector<uint64_t> keys_v;
     std::vector<uint8_t> neg_;
     int64_t cost(int64_t u, int64_t v) const
     {
@@ -25,6 +27,8 @@ struct BrutePairs : PairSource {
     void extras(const int64_t *lam, const PairList &out)
     {
         costs = nullptr;
+        keys = nullptr;
+        nkeys = 0;
         neg = nullptr;
         inc_start = nullptr;
         inc = nullptr;
@@ -54,6 +58,12 @@ struct BrutePairs : PairSource {
         neg = neg_.data();
         inc_start = start_.data();
         inc = inc_.data();
+        if (as_keys) {
+            keys_v.clear();
+            for (const auto &p : out) keys_v.push_back(((uint64_t)(uint32_t)p.first << 32) | (uint32_t)p.second);
+            keys = keys_v.data();
+            nkeys = (int64_t)keys_v.size();
+        }
     }
     bool near(const int64_t *lam, int64_t slack, PairList &out, std::string &) override
     {
@@ -74,6 +84,7 @@ struct BrutePairs : PairSource {
                 if (x <= th[u] || x <= th[v]) out.emplace_back((int32_t)u, (int32_t)v);
             }
         extras(lam, out);
+        if (keys) out.clear();   // the pairs went as keys
         return true;
     }
     bool negative(const int64_t *lam, PairList &out, std::string &) override
@@ -107,6 +118,7 @@ extern "C" int64_t finish_cpu(int64_t n, const int32_t *xy, const int64_t *lam0,
     src.xy = xy;
     src.n = n;
     src.bulk = bulk != 0;
+    src.as_keys = bulk == 2;
     FinishResult r;
     if (reuse == 1 && !g_work) g_work = finish_work_create();
     if (reuse == 2 && !g_par) g_par = finish_work_create(4, 1);

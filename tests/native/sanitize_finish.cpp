@@ -1,7 +1,7 @@
 // Host run of the exact finish (f2m_finish.cpp) through the CPU harness,
 // built with AddressSanitizer and UndefinedBehaviorSanitizer: random,
 // tie-heavy and lattice instances, cold and perturbed starts, b-matching
-// degrees, and every workspace mode of the harness (fresh, reused, four
+// degrees, pairs as a list or as keys, and every workspace mode of the harness (fresh, reused, four
 // threads with the chunked tail, one thread).  Exit status 0 when every call
 // returns a solution; the sanitizers abort on the first error they find.
 #include <cstdint>
@@ -44,7 +44,7 @@ int main()
             std::vector<uint8_t> ex(cap);
             int64_t st[4];
             for (int reuse = 0; reuse < 4; ++reuse) {
-                for (int bulk = 0; bulk < 2; ++bulk) {
+                for (int bulk = 0; bulk < 3; ++bulk) {
                     const int64_t m = finish_cpu(n, xy.data(), lam0.data(), lam.data(), cap, eu.data(), ev.data(),
                                                  ex.data(), st, bulk, reuse, b.empty() ? nullptr : b.data());
                     ++calls;

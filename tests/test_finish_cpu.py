@@ -22,9 +22,10 @@ def check(L, xy, lam0):
     assert c["primal2"] == core.exact_opt2(xy)
     assert np.all(eu < ev)
     # the bulk path (costs, initial flow bits and incidence lists from the
-    # source) starts from the same state, so it must end in the same bits;
-    # so must a workspace that served other instances before
-    for bulk, reuse in ((True, False), (True, True), (False, True)):
+    # source; the pairs as a list or, as the GPU source gives them, as keys)
+    # starts from the same state, so it must end in the same bits; so must
+    # a workspace that served other instances before
+    for bulk, reuse in ((True, False), (2, False), (True, True), (2, True), (False, True)):
         got = harness.finish(L, xy, lam0, bulk=bulk, reuse=reuse)
         for a, b in zip((lam, eu, ev, ex), got[:4]):
             assert np.array_equal(a, b), (bulk, reuse)
