@@ -37,6 +37,24 @@ int64_t floor_half(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
 // candidate edge key: (a, b), a < b, in lexicographic order
 uint64_t pair_key(int64_t a, int64_t b) { return ((uint64_t)a << 32) | (uint64_t)b; }
 
+// An allocator whose resize leaves new elements uninitialised (default-
+// initialised): the finish's large arrays are written in full right after
+// they grow, on the pool's threads, so zeroing them first is wasted time.
+template <class T>
+struct NoInit : std::allocator<T> {
+    template <class U>
+    struct rebind { using other = NoInit<U>; };
+    NoInit() = default;
+    template <class U>
+    NoInit(const NoInit<U> &) {}
+    template <class U>
+    void construct(U *p) { ::new (static_cast<void *>(p)) U; }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) { ::new (static_cast<void *>(p)) U(std::forward<A>(a)...); }
+};
+template <class T>
+using RawVec = std::vector<T, NoInit<T>>;
+
 // A fixed set of threads that run one function at a time, fn(worker) for
 // workers 1 .. T-1 while the caller runs fn(0); they stay for the owner's
 // lifetime, so a solve starts no thread.
@@ -933,15 +951,16 @@ private:
     std::vector<int64_t> src_;       // nodes with excess (may hold stale entries)
     std::vector<int64_t> touched_, cur_;
     std::vector<Item> heap_;
-    std::vector<uint64_t> keys_;     // sorted keys (pair_key) of the candidate edges
+    RawVec<uint64_t> keys_;          // sorted keys (pair_key) of the candidate edges
     // keys added after keys_ was last merged, sorted: a few pricing rounds
     // add tens of pairs each, so they wait here instead of rewriting keys_
-    std::vector<uint64_t> extra_;
-    std::vector<uint64_t> fresh_, merged_;
+    RawVec<uint64_t> extra_;
+    std::vector<uint64_t> fresh_;
+    RawVec<uint64_t> merged_;
     std::vector<int32_t> fresh_c_;
-    std::vector<Edge> e_;
+    RawVec<Edge> e_;
     std::vector<int64_t> start_, end_, cap_;   // incident-edge lists (see build_adjacency)
-    std::vector<int32_t> inc_;
+    RawVec<int32_t> inc_;
     int64_t built_ = 0;              // edges covered by the lists
     int32_t stamp_ = 0;              // augmentation pass stamps (Copy::seen)
     std::vector<Frame> frames_;
