@@ -64,6 +64,7 @@ struct Ctrl {
     unsigned long long pairs_kind[3];   // pairs_tested split by the scans' ScanKind
     long long list_uses;   // scans that evaluated the lists only
     long long list_builds; // scans that built lists
+    long long ms_last;     // max |Lam_{k+1} - Lam_k| of the last iteration k
 };
 
 // Blocks of an update launch leave their part of the iteration record in

@@ -899,22 +899,41 @@ struct RowOut {
     float hmax = -INFINITY;
 };
 
+// A row's own data, loaded at the start of a launch (at a clamped position,
+// so the loads are unconditional and travel together with the others).
+struct RowIn {
+    int64_t v;       // label
+    int bv;          // right-hand side of the degree row
+    float2 xy;       // centred coordinates (when the column records are kept)
+    int64_t lprev;   // lam_out on entry: Lam_{k-1}
+};
+
+__device__ __forceinline__ RowIn row_in(const Geo &g, const float4 *col, const int64_t *lam_out, int64_t pc)
+{
+    RowIn r;
+    r.v = g.orig[pc];
+    r.bv = g.b ? (int)g.b[pc] : 2;
+    r.xy = col ? reinterpret_cast<const float2 *>(col)[2 * pc] : make_float2(0.0f, 0.0f);
+    r.lprev = lam_out[pc];
+    return r;
+}
+
 // Step of the row at position p from its merged statistics: eq. 10 on the
 // 2nd and 3rd smallest Z; writes Lam_{k+1} and the per-node outputs.
 // The four smallest go to z4p / i4p by position ([j][n], coalesced) when
 // those are given, and to z4 / i4 by label (4v + j) when those are.
-__device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &top, int64_t cn, int64_t cz,
-                                         int64_t rn, int64_t lamv, bool copy_best, int64_t *lam_out,
+__device__ __forceinline__ void step_row(const Geo &g, int64_t p, const RowIn &ri, const Top4 &top, int64_t cn,
+                                         int64_t cz, int64_t rn, int64_t lamv, bool copy_best, int64_t *lam_out,
                                          int64_t *lam_best, int64_t *z4, int32_t *i4, int32_t *seed,
                                          int32_t *neg, int32_t *zero, int64_t *step, float4 *col, RowOut &o,
                                          int64_t *z4p = nullptr, int32_t *i4p = nullptr)
 {
     const int64_t n = g.n;
-    const int64_t v = g.orig[p];
+    const int64_t v = ri.v;
     // eq. 10 for a row with right-hand side b (Sec. 3): the b-th and
     // (b+1)-th smallest Z (F2M: b = 2, the 2nd and 3rd); the row needs b + 1
     // edges (n >= 4 on the complete graph)
-    const int bv = g.b ? (int)g.b[p] : 2;
+    const int bv = ri.bv;
     // the three candidates are formed from values and then selected (a
     // selected index into the list would put it in scratch memory)
     const int64_t z0 = top.z[0], z1 = top.z[1], z2 = top.z[2], z3 = top.z[3];
@@ -925,16 +944,19 @@ __device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &to
     const bool un1 = z0 > 0 || z1 < 0, un2 = z1 > 0 || z2 < 0, un3 = z2 > 0 || z3 < 0;
     const bool unsat = bv == 1 ? un1 : (bv == 2 ? un2 : un3);
     const int64_t nxt = lamv + st;
-    if (copy_best) lam_best[p] = lam_out[p];
+    if (copy_best) lam_best[p] = ri.lprev;
     lam_out[p] = nxt;
     if (col) {
         // only the (h, q) half changes: the (x, y) half of every record stays
         // untouched, so threads of the same launch may read it (list step)
-        const float2 xy = reinterpret_cast<const float2 *>(col)[2 * p];
-        const float4 cv = col_record(xy.x, xy.y, nxt);
+        const float4 cv = col_record(ri.xy.x, ri.xy.y, nxt);
         reinterpret_cast<float2 *>(col)[2 * p + 1] = make_float2(cv.z, cv.w);
         o.hmax = cv.z;
     }
+    // the seeds' position gathers are issued together (from a clamped label)
+    int32_t sp[kTop];
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) sp[j] = seed ? g.pos[top.id[j] != kNoIdx ? top.id[j] : 0] : 0;
 #pragma unroll
     for (int j = 0; j < kTop; ++j) {
         const bool ok = top.id[j] != kNoIdx;
@@ -946,7 +968,7 @@ __device__ __forceinline__ void step_row(const Geo &g, int64_t p, const Top4 &to
             z4[kTop * v + j] = top.z[j];
             i4[kTop * v + j] = ok ? top.id[j] : -1;
         }
-        if (seed) seed[j * n + p] = ok ? g.pos[top.id[j]] : -1;
+        if (seed) seed[j * n + p] = ok ? sp[j] : -1;
     }
     const int64_t deg2 = 2 * cn + cz;
     if (neg) neg[v] = (int32_t)cn;
@@ -1111,6 +1133,7 @@ __device__ __forceinline__ void control_body(int64_t n, int64_t k, Ctrl *ctrl, i
         c->pairs_kind[kind] += tt;
         c->k_last = k;
         c->dual2_last = dual2;
+        c->ms_last = ms;
         if (stop) {
             c->stop = stop;
             c->kstar = (stop == 3 || stop == 4) ? c->best_k : k;
@@ -1141,22 +1164,30 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
     // update, which evaluates each row's candidate lists itself
     const bool use = a.lists && a.lst && ctrl->list_ok != 0;
     unsigned long long tt = 0;
-    if (!use && a.tpart && threadIdx.x == 0) {
-        // the scan's pairs tested in this block's rows (groups of 64)
+    if (!use && a.tpart) {
+        // the scan's pairs tested in this block's rows (groups of 64), one
+        // count per thread (block_record sums them)
         const int64_t groups = (a.g.n + 63) / 64;
-        for (int64_t s = 0; s < a.nslices; ++s)
-            for (int64_t g = blk * (kBlock / 64); g < min(groups, (blk + 1) * (kBlock / 64)); ++g)
-                tt += a.tpart[s * groups + g];
+        for (int64_t i = threadIdx.x; i < a.nslices * (kBlock / 64); i += kBlock) {
+            const int64_t s = i / (kBlock / 64), g = blk * (kBlock / 64) + i % (kBlock / 64);
+            if (g < groups) tt += a.tpart[s * groups + g];
+        }
     }
     const int64_t n = a.g.n;
     const int64_t p = blk * kBlock + threadIdx.x;
+    const bool inb = p < n;
+    // every load of a row is issued at a clamped position, so that the loads
+    // are unconditional and travel together (a load under a branch waits
+    // for the branch's own)
+    const int64_t pc = inb ? p : 0;
     // Lam_{k-1} sits in lam_out until it is overwritten
     const bool copy_best = k > 0 && ctrl->best_k == k - 1;
+    const RowIn ri = row_in(a.g, a.col, a.lam_out, pc);
+    const int64_t lamv = inb ? a.lam_in[pc] : 0;
     RowOut o;
     Top4 top;
     top.clear();
     int64_t cn = 0, cz = 0, rn = 0;
-    const int64_t lamv = p < n ? a.lam_in[p] : 0;
     if (use) {
         // Every column that can matter is in the row's list (see
         // ScanArgs::lst).  A wave's 64 rows (one scan group) have their lists
@@ -1164,59 +1195,131 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
         // segment in chunks: every lane marks its own row's run in the chunk,
         // then the lanes evaluate the chunk's entries lane, lane + 64, ...
         // against their rows (the gathers and the exact evaluations spread
-        // over the whole wave), and each lane walks its run for the counts
-        // and its four smallest.
+        // over the whole wave, the next chunk's entries loaded meanwhile).
+        // The counts take only entries with Z <= 0 and go to per-row LDS
+        // counters; an entry joins its row's short candidate buffer only if
+        // its Z is at most the row's bound (below), and each lane then
+        // inserts its row's buffer into its four smallest.
+        //
+        // The bound: Z_k(u, v) = Z_{k-1}(u, v) - d_u - d_v with d = Lam_k -
+        // Lam_{k-1} and |d_v| <= the last max step ms, so the four columns
+        // that were smallest in row u at k-1 are all at most B = z4_{k-1}[3]
+        // - d_u + ms at k; a column above B has four smaller ones and is not
+        // among the four smallest (lists are exact, so this holds over the
+        // list too).  A row whose buffer overflows in a chunk walks that
+        // chunk's run instead.
         constexpr int kLChunk = 256;
+        constexpr int kPB = 16;
+        constexpr int kJ = kLChunk / 64;
         __shared__ long long sz[kBlock / 64][kLChunk];
         __shared__ int32_t slab[kBlock / 64][kLChunk];
         __shared__ unsigned char srow[kBlock / 64][kLChunk];
         __shared__ float2 rxy[kBlock / 64][64];
         __shared__ long long rlam[kBlock / 64][64];
+        __shared__ long long rbnd[kBlock / 64][64];
+        __shared__ unsigned long long rneg[kBlock / 64][64];
+        __shared__ unsigned int rcnt[kBlock / 64][64];   // (#neg << 16) + #zero of this chunk
+        __shared__ unsigned int rbc[kBlock / 64][64];    // candidates of this chunk
+        __shared__ unsigned char rbuf[kBlock / 64][64][kPB];
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int64_t grp = blk * (kBlock / 64) + wave, groups = (n + 63) / 64;
-        const float2 xyv = p < n ? reinterpret_cast<const float2 *>(a.col)[2 * p] : make_float2(0.0f, 0.0f);
-        rxy[wave][lane] = xyv;
+        // (without z4p the bound is off; the pointers are chosen first so
+        // that the loads are unconditional)
+        const bool hz = a.z4p != nullptr;
+        const int64_t *zq = hz ? a.z4p + 3 * n : a.lam_in;
+        const int32_t *iq = hz ? a.i4p + 3 * n : a.g.orig;
+        const int32_t i43 = iq[pc];
+        const int64_t z43 = zq[pc];
+        const int rcn0 = a.lcnt[pc], rof0 = a.loff[pc];
+        const long long bnd = (inb && hz && i43 >= 0) ? z43 - (lamv - ri.lprev) + ctrl->ms_last : INT64_MAX;
+        rxy[wave][lane] = ri.xy;
         rlam[wave][lane] = lamv;
+        rbnd[wave][lane] = bnd;
+        rneg[wave][lane] = 0;
+        rcnt[wave][lane] = 0;
+        rbc[wave][lane] = 0;
+        const float2 *col2 = reinterpret_cast<const float2 *>(a.col);
         for (int64_t sl = 0; sl < a.nslices && grp < groups; ++sl) {
-            const int cnt = p < n ? min(max(a.lcnt[sl * n + p], 0), kLW * (kBlock / 64)) : 0;
-            const int off = p < n ? a.loff[sl * n + p] : 0;
+            const int rcn = sl == 0 ? rcn0 : a.lcnt[sl * n + pc], rof = sl == 0 ? rof0 : a.loff[sl * n + pc];
+            const int cnt = inb ? min(max(rcn, 0), kLW * (kBlock / 64)) : 0;
+            const int off = inb ? rof : 0;
             tt += (unsigned long long)cnt;
             const int total = (int)wave_max((long long)(off + cnt));
+            if (total == 0) continue;
             const int32_t *seg = a.lst + (sl * groups + grp) * kListCap;
+            // entries past the end are read at the last one (and not used)
+            int32_t nu[kJ];
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) nu[j] = seg[min(j * 64 + lane, total - 1)];
             for (int c0 = 0; c0 < total; c0 += kLChunk) {
                 wave_sync();   // the previous chunk's reads are done
                 const int lo = max(off, c0), hi = min(off + cnt, c0 + kLChunk);
                 for (int e = lo; e < hi; ++e) srow[wave][e - c0] = (unsigned char)lane;
+                float2 cxy[kJ];
+                int64_t clam[kJ];
+                int32_t clab[kJ];
+#pragma unroll
+                for (int j = 0; j < kJ; ++j) {
+                    const int64_t u = nu[j];
+                    cxy[j] = col2[2 * u];
+                    clam[j] = a.lam_in[u];
+                    clab[j] = a.g.orig[u];
+                    nu[j] = seg[min(c0 + kLChunk + j * 64 + lane, total - 1)];
+                }
                 wave_sync();
 #pragma unroll
-                for (int j = 0; j < kLChunk / 64; ++j) {
+                for (int j = 0; j < kJ; ++j) {
                     const int e = c0 + j * 64 + lane;
                     if (e < total) {
-                        const int64_t u = seg[e];
                         const int r = srow[wave][e - c0] & 63;
-                        const float2 cxy = reinterpret_cast<const float2 *>(a.col)[2 * u];
-                        sz[wave][e - c0] = exact_z(rxy[wave][r].x, rxy[wave][r].y, rlam[wave][r], cxy.x, cxy.y,
-                                                   a.lam_in[u]);
-                        slab[wave][e - c0] = a.g.orig[u];
+                        const float2 rv = rxy[wave][r];
+                        const int64_t z = exact_z(rv.x, rv.y, rlam[wave][r], cxy[j].x, cxy[j].y, clam[j]);
+                        sz[wave][e - c0] = z;
+                        slab[wave][e - c0] = clab[j];
+                        if (z <= 0) {
+                            atomicAdd(&rcnt[wave][r], z < 0 ? 0x10000u : 1u);
+                            if (z < 0) atomicAdd(&rneg[wave][r], (unsigned long long)z);
+                        }
+                        if (z <= rbnd[wave][r]) {
+                            const unsigned q = atomicAdd(&rbc[wave][r], 1u);
+                            if (q < (unsigned)kPB) rbuf[wave][r][q] = (unsigned char)(e - c0);
+                        }
                     }
                 }
                 wave_sync();
-                for (int e = lo; e < hi; ++e) {
-                    const int i = e - c0;
-                    const int64_t z = sz[wave][i];
-                    if (z < 0) { ++cn; rn += z; }
-                    else if (z == 0) ++cz;
-                    top.insert(z, slab[wave][i]);
+                const unsigned cc = rcnt[wave][lane], m = rbc[wave][lane];
+                cn += cc >> 16;
+                cz += cc & 0xffffu;
+                rn += (long long)rneg[wave][lane];
+                rcnt[wave][lane] = 0;
+                rneg[wave][lane] = 0;
+                rbc[wave][lane] = 0;
+                if (m > (unsigned)kPB) {
+                    for (int e = lo; e < hi; ++e) top.insert(sz[wave][e - c0], slab[wave][e - c0]);
+                } else {
+                    for (unsigned q = 0; q < m; ++q) {
+                        const int i = rbuf[wave][lane][q];
+                        top.insert(sz[wave][i], slab[wave][i]);
+                    }
                 }
             }
         }
-    }
-    if (p < n) {
+    } else if (a.nslices == 1 && !a.pflag) {
+        // one partial per row, already in (Z, u) order
+#pragma unroll
+        for (int j = 0; j < kTop; ++j) {
+            top.z[j] = a.pz[j * n + pc];
+            top.id[j] = a.pi[j * n + pc];
+        }
+        cn = a.pneg[pc];
+        cz = a.pzero[pc];
+        rn = a.prowneg[pc];
+    } else if (inb) {
         // slices in groups of four: the group's loads are issued together,
         // then merged (the merge order does not matter: (Z, u) is a total
         // order and the counts are sums)
         constexpr int kG = 4;
-        for (int64_t s0 = 0; !use && s0 < a.nslices; s0 += kG) {
+        for (int64_t s0 = 0; s0 < a.nslices; s0 += kG) {
             int64_t gz[kG][kTop];
             int32_t gi[kG][kTop];
 #pragma unroll
@@ -1239,9 +1342,10 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
 #pragma unroll
                 for (int j = 0; j < kTop; ++j) top.insert(gz[q][j], gi[q][j]);
         }
-        step_row(a.g, p, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
-                 a.neg, a.zero, a.step, a.col, o, a.z4p, a.i4p);
     }
+    if (inb)
+        step_row(a.g, p, ri, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, a.seed,
+                 a.neg, a.zero, a.step, a.col, o, a.z4p, a.i4p);
     block_record(o, a.tile_hmax, blk, a.slots, tt);
 }
 
@@ -1325,25 +1429,42 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
     Top4 top;
     top.clear();
     int64_t cn = 0, cz = 0, rn = 0;
-    int64_t lamv = 0;
-    int32_t rb = 0, re = 0;
-    if (p < n) {
-        lamv = a.lam_in[p];
-        rb = a.csr.rowptr[p];
-        re = a.csr.rowptr[p + 1];
-    }
+    // the row's loads at a clamped position (unconditional, issued together)
+    const bool inb = p < n;
+    const int64_t pc = inb ? p : 0;
+    const RowIn ri = row_in(a.g, nullptr, a.lam_out, pc);
+    const int64_t lamv = inb ? a.lam_in[pc] : 0;
+    const int32_t rb0 = a.csr.rowptr[pc], re0 = a.csr.rowptr[pc + 1];
+    const int32_t rb = inb ? rb0 : 0, re = inb ? re0 : 0;
     if (w0 < n) {
         const int32_t e0 = a.csr.rowptr[w0], e1 = a.csr.rowptr[min(n, w0 + 64)];
+        constexpr int kQ = kGChunk / 64;
         for (int32_t c0 = e0; c0 < e1; c0 += kGChunk) {
             const int32_t cnt = min(kGChunk, e1 - c0);
             wave_sync();   // the previous chunk's reads are done
-#pragma unroll 4
-            for (int i = lane; i < kGChunk; i += 64) {
+            // every lane loads entries lane, lane + 64, ... (past the chunk's
+            // end at its last entry, not used): the column and cost loads go
+            // out together, then all the gathers
+            int32_t cu[kQ], cc[kQ], cb[kQ];
+            int64_t cl[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int32_t i = c0 + min(q * 64 + lane, cnt - 1);
+                cu[q] = a.csr.col[i];
+                cc[q] = a.csr.cost[i];
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                cl[q] = a.lam_in[cu[q]];
+                cb[q] = a.g.orig[cu[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int i = q * 64 + lane;
                 if (i < cnt) {
-                    const int32_t u = a.csr.col[c0 + i];
-                    gcost[wave][i] = a.csr.cost[c0 + i];
-                    glam[wave][i] = a.lam_in[u];
-                    glab[wave][i] = a.g.orig[u];
+                    gcost[wave][i] = cc[q];
+                    glam[wave][i] = cl[q];
+                    glab[wave][i] = cb[q];
                 }
             }
             wave_sync();
@@ -1357,8 +1478,8 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
             }
         }
     }
-    if (p < n)
-        step_row(a.g, p, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, nullptr,
+    if (inb)
+        step_row(a.g, p, ri, top, cn, cz, rn, lamv, copy_best, a.lam_out, a.lam_best, a.z4, a.i4, nullptr,
                  a.neg, a.zero, a.step, nullptr, o, a.z4p, a.i4p);
     block_record(o, nullptr, blockIdx.x, a.slots, 0);
 }
