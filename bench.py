@@ -138,6 +138,11 @@ def cpu_model():
     return "unknown"
 
 
+def _figures(r):
+    """A solve's result without its arrays (scalars and small dicts only)."""
+    return {k: v for k, v in r.items() if not isinstance(v, np.ndarray) and v is not None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,7 +222,12 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
-            runs.append(ctx.solve(xy_dev, scan=args.scan, graph=args.graph, **kw))
+            # every solve returns its whole result in host memory; like a
+            # caller that is done with one result before the next solve, the
+            # bench keeps the arrays of the last solve only
+            r = ctx.solve(xy_dev, scan=args.scan, graph=args.graph, **kw)
+            runs.append(r if i == args.steps - 1 else _figures(r))
+            del r
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         for i, r in enumerate(runs):
@@ -229,7 +239,9 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for i in range(args.steps):
-            timed.append(ctx.solve(xy_dev, time_kernels=True, scan=args.scan, graph=args.graph, **kw))
+            r = ctx.solve(xy_dev, time_kernels=True, scan=args.scan, graph=args.graph, **kw)
+            timed.append(r if i == args.steps - 1 else _figures(r))
+            del r
         torch.cuda.synchronize()
         log("%s: %d solves with kernel events in %.3f s" % (name, args.steps, time.perf_counter() - t1))
         return runs, elapsed, timed

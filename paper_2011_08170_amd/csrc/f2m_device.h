@@ -7,15 +7,27 @@
 namespace f2m {
 
 // nint(sqrt(D)) exactly: the k with (2k-1)^2 <= 4D < (2k+1)^2 (TSPLIB
-// EUC_2D rounding).  sqrtf gives k within one; the loops make it exact.
+// EUC_2D rounding), for 0 <= D < 2^42 (coordinate spans below 2^20 give
+// D < 2^41), from an FP32 value Df of D with relative error at most 2^-23.
+// The hardware square root is within one ulp, so sqrt(Df) is within
+// 2^-23 + 2^-24 + 2^-46 relative of sqrt(D) < 2^21, i.e. within 0.4; adding
+// 1/2 in FP32 rounds by at most 1/8, so trunc(sqrt(Df) + 1/2) is within one
+// of k, and one integer test each way makes it exact (from k - 1 the upward
+// test fires and the downward one does not; from k + 1 only the downward
+// one fires).
+__device__ __forceinline__ int64_t nint_sqrt_f(int64_t D, float Df)
+{
+    int64_t k = (int32_t)(__builtin_amdgcn_sqrtf(Df) + 0.5f);
+    const int64_t d4 = 4 * D;
+    k += (2 * k + 1) * (2 * k + 1) <= d4 ? 1 : 0;
+    k -= (k > 0 && (2 * k - 1) * (2 * k - 1) > d4) ? 1 : 0;
+    return k;
+}
+
+// the same from D alone (the conversion rounds once: relative error 2^-24)
 __device__ __forceinline__ int64_t nint_sqrt(int64_t D)
 {
-    const float f = sqrtf((float)D);
-    int64_t k = (int64_t)(f + 0.5f);
-    const int64_t d4 = 4 * D;
-    while ((2 * k + 1) * (2 * k + 1) <= d4) ++k;
-    while (k > 0 && (2 * k - 1) * (2 * k - 1) > d4) --k;
-    return k;
+    return nint_sqrt_f(D, (float)D);
 }
 
 // dLam = sign(s) * floor((|s| + 2) / 4)

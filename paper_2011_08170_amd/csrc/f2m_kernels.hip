@@ -52,10 +52,12 @@ constexpr int32_t kNoIdx = INT32_MAX;
 __device__ __forceinline__ int64_t exact_z(float xv, float yv, int64_t lamv, float xu, float yu,
                                            int64_t lamu)
 {
-    const int32_t dx = (int32_t)(xv - xu);
-    const int32_t dy = (int32_t)(yv - yu);
+    // the differences are exact (integers below 2^20); fma(fx, fx, fy * fy)
+    // rounds twice, within 2^-23 relative of D
+    const float fx = xv - xu, fy = yv - yu;
+    const int32_t dx = (int32_t)fx, dy = (int32_t)fy;
     const int64_t D = (int64_t)dx * dx + (int64_t)dy * dy;
-    return 2 * nint_sqrt(D) - lamv - lamu;
+    return 2 * nint_sqrt_f(D, fmaf(fx, fx, fy * fy)) - lamv - lamu;
 }
 
 __device__ __forceinline__ bool key_less(int64_t za, int32_t ua, int64_t zb, int32_t ub)

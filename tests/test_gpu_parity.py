@@ -73,6 +73,43 @@ def test_gdp_step_matches_oracle(ctx, name, make):
             assert rec[f] == o["rec"][f], (name, f)
 
 
+def _boundary_pairs(count, seed):
+    """(dx, dy) with 0 <= dx, dy < 2^20 whose length is within 3/4 (in 4 D)
+    of a half-integer: 4 D is within 3 of an odd square, where FP32 alone
+    could round the wrong way."""
+    rng = np.random.default_rng(seed)
+    found = []
+    dy = np.arange(0, 1 << 20, 419, dtype=np.int64)
+    while len(found) < count:
+        dx = rng.integers(1 << 18, 1 << 20, 2048, dtype=np.int64)
+        d4 = 4 * (dx[:, None] ** 2 + dy[None, :] ** 2)
+        o = np.floor(np.sqrt(d4.astype(np.float64))).astype(np.int64) | 1
+        dist = np.minimum(np.abs(d4 - o * o), np.abs(d4 - (o - 2) * (o - 2)))
+        dist = np.minimum(dist, np.abs(d4 - (o + 2) * (o + 2)))
+        ii, jj = np.nonzero(dist <= 3)
+        found += [(int(dx[i]), int(dy[j])) for i, j in zip(ii, jj)]
+    return found[:count]
+
+
+def test_exact_rounding_near_half_integers(ctx):
+    """EUC_2D rounding (the integer cost of eq. 9) at lengths within 3/4 of a
+    half-integer over the full 2^20 span: every Z = 2c at Lam = 0 of five-city
+    instances (the origin and four such offsets; all ten pairs are in the
+    top four) equals 2 nint(sqrt(D)) with nint from math.isqrt (k with
+    (2k-1)^2 <= 4D < (2k+1)^2)."""
+    import math
+    pairs = _boundary_pairs(24, 5)
+    for g in range(0, len(pairs), 4):
+        xy = np.array([(0, 0)] + pairs[g:g + 4], dtype=np.int64)
+        rec, h = gpu_step(ctx, xy, np.zeros(5, np.int64))
+        for v in range(5):
+            assert sorted(h["i4"][v].tolist()) == [u for u in range(5) if u != v]
+            for j in range(4):
+                u = int(h["i4"][v][j])
+                d = int(((xy[v] - xy[u]) ** 2).sum())
+                assert h["z4"][v][j] == 2 * ((math.isqrt(4 * d) + 1) // 2), (xy[v], xy[u])
+
+
 @pytest.mark.parametrize("seed,div,scan", [(1, 0, "culled"), (2, 0, "culled"), (3, 0, "full"), (1, 300, "full"),
                                            (2, 50, "culled")])
 def test_solve_trajectory_c1(ctx, seed, div, scan):
