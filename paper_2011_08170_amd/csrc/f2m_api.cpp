@@ -577,7 +577,7 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
     if (exclude) tb = std::max(tb, exclude_temp_bytes(found));
     void *temp = grow<char>(ctx, ctx->p_temp, tb);
     const bool excl = exclude && nexclude > 0;
-    ck(ctx, launch_sort_unique_pairs(pairs, found, k1, k2, k3, uc, temp, tb, xy_dev,
+    ck(ctx, launch_sort_unique_pairs(pairs, found, n, k1, k2, k3, uc, temp, tb, xy_dev,
                                      (lam_bulk || excl) ? nullptr : cd, st),
        "sort_unique");
     if (excl) {

@@ -299,9 +299,9 @@ hipError_t launch_pair_bulk(const uint64_t *keys, const int64_t *count_dev, int6
                             const int64_t *lam, int64_t n, int32_t *costs, uint8_t *neg, uint64_t *inc_keys,
                             uint64_t *inc_sorted, int32_t *deg, int32_t *start, int32_t *inc, void *temp,
                             size_t temp_bytes, hipStream_t st);
-hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *keys, uint64_t *keys_sorted,
-                                    uint64_t *keys_out, int64_t *count_dev, void *temp, size_t temp_bytes,
-                                    const int32_t *xy, int32_t *costs, hipStream_t st);
+hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, int64_t n, uint64_t *keys,
+                                    uint64_t *keys_sorted, uint64_t *keys_out, int64_t *count_dev, void *temp,
+                                    size_t temp_bytes, const int32_t *xy, int32_t *costs, hipStream_t st);
 // labels: edges of x must be edges of the graph; acc[2] += violations
 hipError_t launch_graph_membership(const Geo &g, const Csr &csr, int64_t m, const int32_t *eu, const int32_t *ev,
                                    unsigned long long *acc, hipStream_t st);

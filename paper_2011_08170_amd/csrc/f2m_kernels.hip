@@ -1698,31 +1698,33 @@ __global__ __launch_bounds__(kBlock) void k_knn_merge(Geo g, int64_t S, const in
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pair_keys(const int32_t *nbr, int64_t nk, int K, uint64_t *keys)
+// undirected edge {p, q} -> (min << bb) | max, bb bits per end (ends below
+// 2^bb, and min < max, so no key has all 2 bb bits set like the filler)
+__global__ __launch_bounds__(kBlock) void k_pair_keys(const int32_t *nbr, int64_t nk, int K, int bb, uint64_t *keys)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nk) return;
     const int32_t qq = nbr[i];
     if (qq < 0) { keys[i] = ~0ULL; return; }   // unfilled slot: sorts last, never used
     const uint64_t p = (uint64_t)(i / K), q = (uint64_t)qq;
-    keys[i] = p < q ? (p << 32) | q : (q << 32) | p;
+    keys[i] = p < q ? (p << bb) | q : (q << bb) | p;
 }
 
 // counts distinct undirected edges per endpoint (keys sorted)
-__global__ __launch_bounds__(kBlock) void k_edge_count(const uint64_t *keys, int64_t nk, int32_t *deg)
+__global__ __launch_bounds__(kBlock) void k_edge_count(const uint64_t *keys, int64_t nk, int bb, int32_t *deg)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nk || keys[i] == ~0ULL || (i > 0 && keys[i] == keys[i - 1])) return;
-    atomicAdd(&deg[keys[i] >> 32], 1);
-    atomicAdd(&deg[keys[i] & 0xffffffffULL], 1);
+    atomicAdd(&deg[keys[i] >> bb], 1);
+    atomicAdd(&deg[keys[i] & ((1ULL << bb) - 1)], 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_edge_fill(const uint64_t *keys, int64_t nk, const int32_t *rowptr,
+__global__ __launch_bounds__(kBlock) void k_edge_fill(const uint64_t *keys, int64_t nk, int bb, const int32_t *rowptr,
                                                       int32_t *cursor, int32_t *col)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nk || keys[i] == ~0ULL || (i > 0 && keys[i] == keys[i - 1])) return;
-    const int32_t a = (int32_t)(keys[i] >> 32), b = (int32_t)(keys[i] & 0xffffffffULL);
+    const int32_t a = (int32_t)(keys[i] >> bb), b = (int32_t)(keys[i] & ((1ULL << bb) - 1));
     col[rowptr[a] + atomicAdd(&cursor[a], 1)] = b;
     col[rowptr[b] + atomicAdd(&cursor[b], 1)] = a;
 }
@@ -1827,10 +1829,21 @@ __global__ __launch_bounds__(kBlock) void k_graph_membership(Geo g, Csr csr, int
     if (lo >= csr.rowptr[pu + 1] || csr.col[lo] != pv) atomicAdd(&acc[2], 1ULL);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pair_to_key(const int2 *pairs, int64_t count, uint64_t *keys)
+// Pair (a, b) -> key (a << bb) | b, with bb bits per end (every end is
+// below 2^bb): the sort then runs over 2 bb bits only.
+__global__ __launch_bounds__(kBlock) void k_pair_to_key(const int2 *pairs, int64_t count, int bb, uint64_t *keys)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < count) keys[i] = ((uint64_t)(uint32_t)pairs[i].x << 32) | (uint64_t)(uint32_t)pairs[i].y;
+    if (i < count) keys[i] = ((uint64_t)(uint32_t)pairs[i].x << bb) | (uint64_t)(uint32_t)pairs[i].y;
+}
+
+// the distinct compact keys (i < *count) back to (a << 32) | b, in place
+__global__ __launch_bounds__(kBlock) void k_key_widen(uint64_t *keys, const int64_t *count, int64_t cap, int bb)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= cap || i >= *count) return;
+    const uint64_t k = keys[i];
+    keys[i] = ((k >> bb) << 32) | (k & ((1ULL << bb) - 1));
 }
 
 // bytes [0, n16 * 16) as 16-byte words, then the tail byte by byte (both
@@ -1860,7 +1873,7 @@ __device__ __forceinline__ int64_t floor_half_d(int64_t x) { return x >= 0 ? x /
 // (b << 32 | i), the incidences to sort; slots past the count get ~0.
 __global__ __launch_bounds__(kBlock) void k_key_info(const uint64_t *keys, const int64_t *count, int64_t cap,
                                                      const int32_t *xy, const int64_t *lam, int32_t *cost,
-                                                     uint8_t *neg, uint64_t *inc_keys)
+                                                     uint8_t *neg, uint64_t *inc_keys, int bi = 32)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= cap) return;
@@ -1879,8 +1892,10 @@ __global__ __launch_bounds__(kBlock) void k_key_info(const uint64_t *keys, const
         neg[i] = (uint8_t)((c - aa - bb < 0 ? 1 : 0) | (c - ab - ba < 0 ? 2 : 0));
     }
     if (inc_keys) {
-        inc_keys[2 * i] = ((uint64_t)a << 32) | (uint64_t)i;
-        inc_keys[2 * i + 1] = ((uint64_t)b << 32) | (uint64_t)i;
+        // (v << bi) | edge, bi bits per edge index (every index is below
+        // 2^bi - 1, so no key equals the all-ones filler of unused slots)
+        inc_keys[2 * i] = ((uint64_t)a << bi) | (uint64_t)i;
+        inc_keys[2 * i + 1] = ((uint64_t)b << bi) | (uint64_t)i;
     }
 }
 
@@ -1888,14 +1903,14 @@ __global__ __launch_bounds__(kBlock) void k_key_info(const uint64_t *keys, const
 // placed with kIncSpare free slots after every node's list: the j-th
 // incidence overall, of node v, lands at j + kIncSpare * v
 constexpr int kIncSpare = 2;
-__global__ __launch_bounds__(kBlock) void k_inc_split(const uint64_t *sorted, const int64_t *count, int32_t *deg,
-                                                      int32_t *inc)
+__global__ __launch_bounds__(kBlock) void k_inc_split(const uint64_t *sorted, const int64_t *count, int bi,
+                                                      int32_t *deg, int32_t *inc)
 {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= 2 * *count) return;
     const uint64_t k = sorted[j];
-    const int64_t v = (int64_t)(k >> 32);
-    inc[j + kIncSpare * v] = (int32_t)(k & 0xffffffffULL);
+    const int64_t v = (int64_t)(k >> bi);
+    inc[j + kIncSpare * v] = (int32_t)(k & ((1ULL << bi) - 1));
     atomicAdd(&deg[v + 1], 1);
 }
 
@@ -2571,11 +2586,31 @@ hipError_t launch_knn(const Geo &g, const float4 *col, int K, int32_t *nbr, int6
     return hipGetLastError();
 }
 
+// Radix sorts of packed keys (the candidate graph's edges, the finish's
+// pairs and incidences): always the one-sweep algorithm (the library's
+// default sorts inputs up to 2^20 keys by block sorts and a dozen or more
+// merge passes, each a launch), over the keys' used bits only.
+using OnesweepSort = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                rocprim::default_config, 0>;
+
+static hipError_t sort_keys(void *temp, size_t &bytes, const uint64_t *in, uint64_t *out, int64_t count, int bits,
+                            hipStream_t st)
+{
+    return rocprim::radix_sort_keys<OnesweepSort>(temp, bytes, in, out, (size_t)count, 0u, (unsigned)bits, st);
+}
+
+// bits of the largest value below `bound` (at least 1)
+static int bits_below(int64_t bound)
+{
+    int b = 1;
+    while (b < 62 && (int64_t(1) << b) < bound) ++b;
+    return b;
+}
+
 size_t csr_temp_bytes(int64_t n, int K)
 {
     size_t a = 0, b = 0;
-    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                            (int)(n * K), 0, 64);
+    (void)sort_keys(nullptr, a, nullptr, nullptr, n * K, 64, nullptr);
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int32_t *)nullptr, (int32_t *)nullptr, (int)(n + 1));
     return a > b ? a : b;
 }
@@ -2585,19 +2620,21 @@ hipError_t launch_build_csr(const Geo &g, const int32_t *xy, int64_t n, int K, c
                             int64_t *nnz_dev, void *temp, size_t temp_bytes, int64_t cap, hipStream_t st)
 {
     const int64_t nk = n * K;
-    hipLaunchKernelGGL(k_pair_keys, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, nbr, nk, K, keys);
+    const int bb = bits_below(n);
+    hipLaunchKernelGGL(k_pair_keys, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, nbr, nk, K, bb, keys);
     size_t tb = temp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, tb, keys, keys_alt, (int)nk, 0, 64, st);
+    hipError_t e = sort_keys(temp, tb, keys, keys_alt, nk, 2 * bb, st);
     if (e != hipSuccess) return e;
     if ((e = hipMemsetAsync(deg, 0, (n + 1) * sizeof(int32_t), st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edge_count, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, keys_alt, nk, deg);
+    hipLaunchKernelGGL(k_edge_count, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, keys_alt, nk, bb, deg);
     tb = temp_bytes;
     e = hipcub::DeviceScan::ExclusiveSum(temp, tb, deg, rowptr, (int)(n + 1), st);
     if (e != hipSuccess) return e;
     if ((e = hipMemcpyAsync(nnz_dev, rowptr + n, sizeof(int32_t), hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
     (void)cap;   // 2*n*K >= nnz always
     if ((e = hipMemsetAsync(deg, 0, (n + 1) * sizeof(int32_t), st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edge_fill, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, keys_alt, nk, rowptr, deg, col);
+    hipLaunchKernelGGL(k_edge_fill, dim3(blocks_for(nk, kBlock)), dim3(kBlock), 0, st, keys_alt, nk, bb, rowptr, deg,
+                       col);
     hipLaunchKernelGGL(k_row_finish, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, xy, g.orig, n, rowptr, col,
                        cost);
     return hipGetLastError();
@@ -2606,25 +2643,28 @@ hipError_t launch_build_csr(const Geo &g, const int32_t *xy, int64_t n, int K, c
 size_t pair_sort_temp_bytes(int64_t count)
 {
     size_t a = 0, b = 0;
-    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr, (int)count, 0,
-                                            64);
+    (void)sort_keys(nullptr, a, nullptr, nullptr, count, 64, nullptr);
     (void)hipcub::DeviceSelect::Unique(nullptr, b, (const uint64_t *)nullptr, (uint64_t *)nullptr,
                                        (int64_t *)nullptr, (int)count);
     return a > b ? a : b;
 }
 
-hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, uint64_t *keys, uint64_t *keys_sorted,
-                                    uint64_t *keys_out, int64_t *count_dev, void *temp, size_t temp_bytes,
-                                    const int32_t *xy, int32_t *costs, hipStream_t st)
+hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, int64_t n, uint64_t *keys,
+                                    uint64_t *keys_sorted, uint64_t *keys_out, int64_t *count_dev, void *temp,
+                                    size_t temp_bytes, const int32_t *xy, int32_t *costs, hipStream_t st)
 {
     if (count <= 0) return hipMemsetAsync(count_dev, 0, sizeof(int64_t), st);
-    hipLaunchKernelGGL(k_pair_to_key, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, pairs, count, keys);
+    // ends are positions below n
+    const int bb = bits_below(n);
+    hipLaunchKernelGGL(k_pair_to_key, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, pairs, count, bb, keys);
     size_t tb = temp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, tb, keys, keys_sorted, (int)count, 0, 64, st);
+    hipError_t e = sort_keys(temp, tb, keys, keys_sorted, count, 2 * bb, st);
     if (e != hipSuccess) return e;
     tb = temp_bytes;
     e = hipcub::DeviceSelect::Unique(temp, tb, keys_sorted, keys_out, count_dev, (int)count, st);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_key_widen, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, keys_out, count_dev, count,
+                       bb);
     if (costs) {
         hipLaunchKernelGGL(k_key_info, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, keys_out, count_dev,
                            count, xy, (const int64_t *)nullptr, costs, (uint8_t *)nullptr, (uint64_t *)nullptr);
@@ -2679,8 +2719,7 @@ hipError_t launch_exclude_keys(const uint64_t *keys, const int64_t *count_dev, i
 size_t pair_bulk_temp_bytes(int64_t count, int64_t n)
 {
     size_t a = 0, b = 0;
-    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                            (int)(2 * count), 0, 64);
+    (void)sort_keys(nullptr, a, nullptr, nullptr, 2 * count, 64, nullptr);
     (void)hipcub::DeviceScan::InclusiveSum(nullptr, b, (const int32_t *)nullptr, (int32_t *)nullptr, (int)(n + 1));
     return a > b ? a : b;
 }
@@ -2691,17 +2730,19 @@ hipError_t launch_pair_bulk(const uint64_t *keys, const int64_t *count_dev, int6
                             size_t temp_bytes, hipStream_t st)
 {
     if (cap <= 0) return hipSuccess;
+    // node below n, edge index below cap (so below 2^bi - 1)
+    const int bv = bits_below(n), bi = bits_below(cap + 1);
     hipLaunchKernelGGL(k_key_info, dim3(blocks_for(cap, kBlock)), dim3(kBlock), 0, st, keys, count_dev, cap, xy, lam,
-                       costs, neg, inc_keys);
+                       costs, neg, inc_keys, bi);
     size_t tb = temp_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, tb, inc_keys, inc_sorted, (int)(2 * cap), 0, 64, st);
+    hipError_t e = sort_keys(temp, tb, inc_keys, inc_sorted, 2 * cap, std::min(64, bv + bi), st);
     if (e != hipSuccess) return e;
     // deg[0] = 0, deg[v + 1] = kIncSpare + incidences of v: its inclusive sum
     // is every list's start including the free slots
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, deg, (int64_t)1, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, deg + 1, n, kIncSpare);
-    hipLaunchKernelGGL(k_inc_split, dim3(blocks_for(2 * cap, kBlock)), dim3(kBlock), 0, st, inc_sorted, count_dev, deg,
-                       inc);
+    hipLaunchKernelGGL(k_inc_split, dim3(blocks_for(2 * cap, kBlock)), dim3(kBlock), 0, st, inc_sorted, count_dev, bi,
+                       deg, inc);
     tb = temp_bytes;
     return hipcub::DeviceScan::InclusiveSum(temp, tb, deg, start, (int)(n + 1), st);
 }
