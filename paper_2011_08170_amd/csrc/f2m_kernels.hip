@@ -1419,9 +1419,17 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
 {
     Ctrl *ctrl = a.ctrl;
     if (ctrl->done) return;
-    __shared__ int32_t gcost[kBlock / 64][kGChunk];
-    __shared__ int32_t glab[kBlock / 64][kGChunk];
-    __shared__ long long glam[kBlock / 64][kGChunk];
+    constexpr int kPB = 16;
+    constexpr int kQ = kGChunk / 64;
+    __shared__ long long sz[kBlock / 64][kGChunk];
+    __shared__ int32_t slab[kBlock / 64][kGChunk];
+    __shared__ unsigned char srow[kBlock / 64][kGChunk];
+    __shared__ long long rlam[kBlock / 64][64];
+    __shared__ long long rbnd[kBlock / 64][64];
+    __shared__ unsigned long long rneg[kBlock / 64][64];
+    __shared__ unsigned int rcnt[kBlock / 64][64];   // (#neg << 16) + #zero of this chunk
+    __shared__ unsigned int rbc[kBlock / 64][64];    // candidates of this chunk
+    __shared__ unsigned short rbuf[kBlock / 64][64][kPB];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n = a.g.n;
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1438,15 +1446,34 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
     const int64_t lamv = inb ? a.lam_in[pc] : 0;
     const int32_t rb0 = a.csr.rowptr[pc], re0 = a.csr.rowptr[pc + 1];
     const int32_t rb = inb ? rb0 : 0, re = inb ? re0 : 0;
+    // The entries of the wave's 64 rows are contiguous: every lane takes
+    // entries lane, lane + 64, ... of a chunk and computes their Z against
+    // their rows; the counts take the entries with Z <= 0 in per-row LDS
+    // counters, and an entry joins its row's short candidate buffer only if
+    // its Z is at most the row's bound B = z4_{k-1}[3] - d_u + ms (the four
+    // columns smallest at k-1 are all at most B at k, as in the complete
+    // graph's list iterations; off on the run's first iteration, where
+    // z4p and lam_out hold nothing of this run).  A row whose buffer
+    // overflows in a chunk walks that chunk's run instead.
+    const bool hz = a.z4p != nullptr && a.k > ctrl->k_first;
+    const int64_t *zq = a.z4p ? a.z4p + 3 * n : a.lam_in;
+    const int32_t *iq = a.z4p ? a.i4p + 3 * n : a.g.orig;
+    const int32_t i43 = iq[pc];
+    const int64_t z43 = zq[pc];
+    rlam[wave][lane] = lamv;
+    rbnd[wave][lane] = (inb && hz && i43 >= 0) ? z43 - (lamv - ri.lprev) + ctrl->ms_last : INT64_MAX;
+    rneg[wave][lane] = 0;
+    rcnt[wave][lane] = 0;
+    rbc[wave][lane] = 0;
     if (w0 < n) {
         const int32_t e0 = a.csr.rowptr[w0], e1 = a.csr.rowptr[min(n, w0 + 64)];
-        constexpr int kQ = kGChunk / 64;
         for (int32_t c0 = e0; c0 < e1; c0 += kGChunk) {
             const int32_t cnt = min(kGChunk, e1 - c0);
             wave_sync();   // the previous chunk's reads are done
-            // every lane loads entries lane, lane + 64, ... (past the chunk's
-            // end at its last entry, not used): the column and cost loads go
-            // out together, then all the gathers
+            const int32_t lo = max(rb, c0), hi = min(re, c0 + cnt);
+            for (int32_t e = lo; e < hi; ++e) srow[wave][e - c0] = (unsigned char)lane;
+            // loads past the chunk's end read its last entry (not used): the
+            // column and cost loads go out together, then all the gathers
             int32_t cu[kQ], cc[kQ], cb[kQ];
             int64_t cl[kQ];
 #pragma unroll
@@ -1460,23 +1487,40 @@ __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
                 cl[q] = a.lam_in[cu[q]];
                 cb[q] = a.g.orig[cu[q]];
             }
+            wave_sync();
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 const int i = q * 64 + lane;
                 if (i < cnt) {
-                    gcost[wave][i] = cc[q];
-                    glam[wave][i] = cl[q];
-                    glab[wave][i] = cb[q];
+                    const int r = srow[wave][i] & 63;
+                    const int64_t z = 2 * (int64_t)cc[q] - rlam[wave][r] - cl[q];   // eq. 9, doubled
+                    sz[wave][i] = z;
+                    slab[wave][i] = cb[q];
+                    if (z <= 0) {
+                        atomicAdd(&rcnt[wave][r], z < 0 ? 0x10000u : 1u);
+                        if (z < 0) atomicAdd(&rneg[wave][r], (unsigned long long)z);
+                    }
+                    if (z <= rbnd[wave][r]) {
+                        const unsigned t = atomicAdd(&rbc[wave][r], 1u);
+                        if (t < (unsigned)kPB) rbuf[wave][r][t] = (unsigned short)i;
+                    }
                 }
             }
             wave_sync();
-            const int32_t lo = max(rb, c0), hi = min(re, c0 + cnt);
-            for (int32_t e = lo; e < hi; ++e) {
-                const int i = e - c0;
-                const int64_t z = 2 * (int64_t)gcost[wave][i] - lamv - glam[wave][i];   // eq. 9, doubled
-                if (z < 0) { ++cn; rn += z; }
-                else if (z == 0) ++cz;
-                top.insert(z, glab[wave][i]);
+            const unsigned ccount = rcnt[wave][lane], m = rbc[wave][lane];
+            cn += ccount >> 16;
+            cz += ccount & 0xffffu;
+            rn += (long long)rneg[wave][lane];
+            rcnt[wave][lane] = 0;
+            rneg[wave][lane] = 0;
+            rbc[wave][lane] = 0;
+            if (m > (unsigned)kPB) {
+                for (int32_t e = lo; e < hi; ++e) top.insert(sz[wave][e - c0], slab[wave][e - c0]);
+            } else {
+                for (unsigned t = 0; t < m; ++t) {
+                    const int i = rbuf[wave][lane][t];
+                    top.insert(sz[wave][i], slab[wave][i]);
+                }
             }
         }
     }
