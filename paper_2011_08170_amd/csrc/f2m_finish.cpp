@@ -37,23 +37,6 @@ int64_t floor_half(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
 // candidate edge key: (a, b), a < b, in lexicographic order
 uint64_t pair_key(int64_t a, int64_t b) { return ((uint64_t)a << 32) | (uint64_t)b; }
 
-// An allocator whose resize leaves new elements uninitialised (default-
-// initialised): the finish's large arrays are written in full right after
-// they grow, on the pool's threads, so zeroing them first is wasted time.
-template <class T>
-struct NoInit : std::allocator<T> {
-    template <class U>
-    struct rebind { using other = NoInit<U>; };
-    NoInit() = default;
-    template <class U>
-    NoInit(const NoInit<U> &) {}
-    template <class U>
-    void construct(U *p) { ::new (static_cast<void *>(p)) U; }
-    template <class U, class... A>
-    void construct(U *p, A &&...a) { ::new (static_cast<void *>(p)) U(std::forward<A>(a)...); }
-};
-template <class T>
-using RawVec = std::vector<T, NoInit<T>>;
 
 // A fixed set of threads that run one function at a time, fn(worker) for
 // workers 1 .. T-1 while the caller runs fn(0); they stay for the owner's
@@ -457,14 +440,17 @@ public:
         parallel_min_ = std::max<int64_t>(1, parallel_min);
     }
 
-    void lam(std::vector<int64_t> &out) const
+    void lam(std::vector<int64_t> &out)
     {
         out.resize(n_);
-        for (int64_t v = 0; v < n_; ++v) out[v] = cp_[v].pot + A_ + cp_[n_ + v].pot + B_;
+        int64_t *o = out.data();
+        parallel_for(n_, [&](int64_t lo, int64_t hi) {
+            for (int64_t v = lo; v < hi; ++v) o[v] = cp_[v].pot + A_ + cp_[n_ + v].pot + B_;
+        });
     }
 
     // the edges with flow, in candidate order
-    void x(std::vector<int32_t> &eu, std::vector<int32_t> &ev, std::vector<uint8_t> &ex2)
+    void x(RawVec<int32_t> &eu, RawVec<int32_t> &ev, RawVec<uint8_t> &ex2)
     {
         // in ranges of edges on the pool's threads: each range counts its
         // edges with flow, then writes them from its offset (only those: the

@@ -19,6 +19,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -63,12 +64,30 @@ struct PairSource {
     virtual bool negative(const int64_t *lam, PairList &out, std::string &err) = 0;
 };
 
+// An allocator whose resize leaves new elements uninitialised (default-
+// initialised): the finish's large arrays and its results are written in
+// full right after they grow, so zeroing them first is wasted time.
+template <class T>
+struct NoInit : std::allocator<T> {
+    template <class U>
+    struct rebind { using other = NoInit<U>; };
+    NoInit() = default;
+    template <class U>
+    NoInit(const NoInit<U> &) {}
+    template <class U>
+    void construct(U *p) { ::new (static_cast<void *>(p)) U; }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) { ::new (static_cast<void *>(p)) U(std::forward<A>(a)...); }
+};
+template <class T>
+using RawVec = std::vector<T, NoInit<T>>;
+
 struct FinishResult {
     bool ok = false;
     std::string msg;
-    std::vector<int64_t> lam;       // Lam = alpha + beta
-    std::vector<int32_t> eu, ev;    // edges of x, eu < ev (no particular order)
-    std::vector<uint8_t> ex2;       // 2x in {1, 2}
+    RawVec<int64_t> lam;            // Lam = alpha + beta
+    RawVec<int32_t> eu, ev;         // edges of x, eu < ev (no particular order)
+    RawVec<uint8_t> ex2;            // 2x in {1, 2}
     int64_t paths = 0;              // unit augmentations
     int64_t rounds = 0;             // pricing rounds
     int64_t phases = 0;             // Dijkstra phases
