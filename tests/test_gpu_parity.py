@@ -122,6 +122,24 @@ def test_solve_trajectory_c1(ctx, seed, div, scan):
     assert np.array_equal(g["lambda2_gdp"], o["lam"])
 
 
+@pytest.mark.parametrize("name,make", [("lattice_ties", lambda: I.lattice_jitter(32, 33, 40, 2, 7)),
+                                       ("duplicates", lambda: I.with_duplicates(1500, 20000, 200, 8))])
+def test_solve_trajectory_ties_with_lists(ctx, name, make):
+    """Tie-heavy instances (jittered lattice; 200 duplicated cities, which
+    run 136 iterations into a cycle stop) through the culled scan with
+    candidate lists: many list entries share a row's bound, so candidate
+    buffers fill up and rows walk their runs instead.  Every record, the
+    stop, k* and Lam* equal the oracle's."""
+    xy = make()
+    o = core.gdp_solve(xy, handoff_div=0)
+    g = ctx.solve(xy, trace=True, finish="none", handoff_div=0)
+    print(name, "list iterations", g["scan_list_uses"], "builds", g["scan_list_builds"], flush=True)
+    assert g["scan_list_uses"] > 0
+    assert g["iterations"] == o["iters"] and g["stop"] == o["stop"] and g["kstar"] == o["kstar"]
+    assert np.array_equal(g["trace"], o["trace"])
+    assert np.array_equal(g["lambda2_gdp"], o["lam"])
+
+
 @pytest.mark.parametrize("name,make", [("square", lambda: I.square4()), ("tri3", lambda: I.triangles(3)),
                                        ("c1", lambda: I.uniform(1000, 100000, 1)),
                                        ("lattice", lambda: I.lattice_jitter(20, 21, 40, 2, 3)),
