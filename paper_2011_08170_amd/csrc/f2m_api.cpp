@@ -592,12 +592,11 @@ void fetch_unique_pairs(f2m_ctx *ctx, const int2 *pairs, int64_t found, const in
     uint8_t *ng = nullptr;
     int32_t *deg = nullptr, *stt = nullptr, *inc = nullptr;
     if (lam_bulk) {
-        // k1, k2 are free again: the incidences sort through them
         ng = grow<uint8_t>(ctx, ctx->p_neg, found);
         deg = grow<int32_t>(ctx, ctx->p_deg, n + 1);
         stt = grow<int32_t>(ctx, ctx->p_start, n + 1);
         inc = grow<int32_t>(ctx, ctx->p_inc, 2 * found + 2 * n);
-        ck(ctx, launch_pair_bulk(k3, uc, found, xy_dev, lam_bulk, n, cd, ng, k1, k2, deg, stt, inc, temp, tb, st),
+        ck(ctx, launch_pair_bulk(k3, uc, found, xy_dev, lam_bulk, n, cd, ng, deg, stt, inc, temp, tb, st),
            "pair_bulk");
     }
     ck(ctx, hipMemcpyAsync(ctx->scratch_host, uc, sizeof(int64_t), hipMemcpyDeviceToHost, st), "copy");

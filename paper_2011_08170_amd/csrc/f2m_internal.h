@@ -296,9 +296,8 @@ hipError_t launch_exclude_keys(const uint64_t *keys, const int64_t *count_dev, i
                                int32_t *costs, void *temp, size_t temp_bytes, hipStream_t st);
 size_t pair_bulk_temp_bytes(int64_t count, int64_t n);
 hipError_t launch_pair_bulk(const uint64_t *keys, const int64_t *count_dev, int64_t cap, const int32_t *xy,
-                            const int64_t *lam, int64_t n, int32_t *costs, uint8_t *neg, uint64_t *inc_keys,
-                            uint64_t *inc_sorted, int32_t *deg, int32_t *start, int32_t *inc, void *temp,
-                            size_t temp_bytes, hipStream_t st);
+                            const int64_t *lam, int64_t n, int32_t *costs, uint8_t *neg, int32_t *deg, int32_t *start,
+                            int32_t *inc, void *temp, size_t temp_bytes, hipStream_t st);
 hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, int64_t n, uint64_t *keys,
                                     uint64_t *keys_sorted, uint64_t *keys_out, int64_t *count_dev, void *temp,
                                     size_t temp_bytes, const int32_t *xy, int32_t *costs, hipStream_t st);

@@ -1910,22 +1910,16 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t count, 
 
 __device__ __forceinline__ int64_t floor_half_d(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
 
-// Per distinct pair key i (labels a << 32 | b, count on the device): the
-// exact cost, and with lam (labels) the bits "arc a'->b'' (bit 0) / b'->a''
-// (bit 1) has negative reduced cost c - alpha_tail - beta_head" for
-// alpha = floor(Lam/2), beta = Lam - alpha; inc_keys gets (a << 32 | i) and
-// (b << 32 | i), the incidences to sort; slots past the count get ~0.
+// Per distinct pair key i (a << 32 | b, count on the device): the exact
+// cost, and with lam the bits "arc a'->b'' (bit 0) / b'->a'' (bit 1) has
+// negative reduced cost c - alpha_tail - beta_head" for alpha = floor(Lam/2),
+// beta = Lam - alpha.
 __global__ __launch_bounds__(kBlock) void k_key_info(const uint64_t *keys, const int64_t *count, int64_t cap,
                                                      const int32_t *xy, const int64_t *lam, int32_t *cost,
-                                                     uint8_t *neg, uint64_t *inc_keys, int bi = 32)
+                                                     uint8_t *neg)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= cap) return;
-    const int64_t u = *count;
-    if (i >= u) {
-        if (inc_keys) { inc_keys[2 * i] = ~0ULL; inc_keys[2 * i + 1] = ~0ULL; }
-        return;
-    }
+    if (i >= cap || i >= *count) return;
     const int64_t a = (int64_t)(keys[i] >> 32), b = (int64_t)(keys[i] & 0xffffffffULL);
     const int64_t dx = (int64_t)xy[2 * a] - xy[2 * b], dy = (int64_t)xy[2 * a + 1] - xy[2 * b + 1];
     const int64_t c = nint_sqrt(dx * dx + dy * dy);
@@ -1935,27 +1929,50 @@ __global__ __launch_bounds__(kBlock) void k_key_info(const uint64_t *keys, const
         const int64_t ba = lam[a] - aa, bb = lam[b] - ab;
         neg[i] = (uint8_t)((c - aa - bb < 0 ? 1 : 0) | (c - ab - ba < 0 ? 2 : 0));
     }
-    if (inc_keys) {
-        // (v << bi) | edge, bi bits per edge index (every index is below
-        // 2^bi - 1, so no key equals the all-ones filler of unused slots)
-        inc_keys[2 * i] = ((uint64_t)a << bi) | (uint64_t)i;
-        inc_keys[2 * i + 1] = ((uint64_t)b << bi) | (uint64_t)i;
-    }
 }
 
-// sorted incidences -> per-node counts added to deg[v + 1] and the edge ids
-// placed with kIncSpare free slots after every node's list: the j-th
-// incidence overall, of node v, lands at j + kIncSpare * v
+// free slots after every node's incidence list (new pairs of pricing rounds
+// are placed there without a rebuild)
 constexpr int kIncSpare = 2;
-__global__ __launch_bounds__(kBlock) void k_inc_split(const uint64_t *sorted, const int64_t *count, int bi,
-                                                      int32_t *deg, int32_t *inc)
+
+// The finish's incidence lists by counting: each distinct pair i < *count
+// adds one to both ends' counts (deg[v + 1]) ...
+__global__ __launch_bounds__(kBlock) void k_inc_count(const uint64_t *keys, const int64_t *count, int64_t cap,
+                                                      int32_t *deg)
 {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= 2 * *count) return;
-    const uint64_t k = sorted[j];
-    const int64_t v = (int64_t)(k >> bi);
-    inc[j + kIncSpare * v] = (int32_t)(k & ((1ULL << bi) - 1));
-    atomicAdd(&deg[v + 1], 1);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= cap || i >= *count) return;
+    const uint64_t k = keys[i];
+    atomicAdd(&deg[(k >> 32) + 1], 1);
+    atomicAdd(&deg[(k & 0xffffffffULL) + 1], 1);
+}
+
+// ... is placed at the next free slot of both ends' lists (in arrival
+// order) ...
+__global__ __launch_bounds__(kBlock) void k_inc_place(const uint64_t *keys, const int64_t *count, int64_t cap,
+                                                      const int32_t *start, int32_t *cursor, int32_t *inc)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= cap || i >= *count) return;
+    const uint64_t k = keys[i];
+    const int64_t a = (int64_t)(k >> 32), b = (int64_t)(k & 0xffffffffULL);
+    inc[start[a] + atomicAdd(&cursor[a], 1)] = (int32_t)i;
+    inc[start[b] + atomicAdd(&cursor[b], 1)] = (int32_t)i;
+}
+
+// ... and every node's list is put in increasing edge order (insertion sort:
+// lists are short).
+__global__ __launch_bounds__(kBlock) void k_inc_order(const int32_t *start, const int32_t *len, int64_t n, int32_t *inc)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    const int32_t s0 = start[v], s1 = s0 + len[v];
+    for (int32_t e = s0 + 1; e < s1; ++e) {
+        const int32_t x = inc[e];
+        int32_t f = e - 1;
+        while (f >= s0 && inc[f] > x) { inc[f + 1] = inc[f]; --f; }
+        inc[f + 1] = x;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_label_degrees(Geo g, Csr csr, int32_t *deg)
@@ -2711,7 +2728,7 @@ hipError_t launch_sort_unique_pairs(const int2 *pairs, int64_t count, int64_t n,
                        bb);
     if (costs) {
         hipLaunchKernelGGL(k_key_info, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, st, keys_out, count_dev,
-                           count, xy, (const int64_t *)nullptr, costs, (uint8_t *)nullptr, (uint64_t *)nullptr);
+                           count, xy, (const int64_t *)nullptr, costs, (uint8_t *)nullptr);
         e = hipGetLastError();
     }
     return e;
@@ -2756,39 +2773,39 @@ hipError_t launch_exclude_keys(const uint64_t *keys, const int64_t *count_dev, i
     hipError_t e = hipcub::DeviceSelect::Flagged(temp, tb, keys, flags, out, out_count, (int)cap, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_key_info, dim3(blocks_for(cap, kBlock)), dim3(kBlock), 0, st, out, out_count, cap, xy,
-                       (const int64_t *)nullptr, costs, (uint8_t *)nullptr, (uint64_t *)nullptr);
+                       (const int64_t *)nullptr, costs, (uint8_t *)nullptr);
     return hipGetLastError();
 }
 
 size_t pair_bulk_temp_bytes(int64_t count, int64_t n)
 {
-    size_t a = 0, b = 0;
-    (void)sort_keys(nullptr, a, nullptr, nullptr, 2 * count, 64, nullptr);
+    (void)count;
+    size_t b = 0;
     (void)hipcub::DeviceScan::InclusiveSum(nullptr, b, (const int32_t *)nullptr, (int32_t *)nullptr, (int)(n + 1));
-    return a > b ? a : b;
+    return b;
 }
 
 hipError_t launch_pair_bulk(const uint64_t *keys, const int64_t *count_dev, int64_t cap, const int32_t *xy,
-                            const int64_t *lam, int64_t n, int32_t *costs, uint8_t *neg, uint64_t *inc_keys,
-                            uint64_t *inc_sorted, int32_t *deg, int32_t *start, int32_t *inc, void *temp,
-                            size_t temp_bytes, hipStream_t st)
+                            const int64_t *lam, int64_t n, int32_t *costs, uint8_t *neg, int32_t *deg, int32_t *start,
+                            int32_t *inc, void *temp, size_t temp_bytes, hipStream_t st)
 {
     if (cap <= 0) return hipSuccess;
-    // node below n, edge index below cap (so below 2^bi - 1)
-    const int bv = bits_below(n), bi = bits_below(cap + 1);
     hipLaunchKernelGGL(k_key_info, dim3(blocks_for(cap, kBlock)), dim3(kBlock), 0, st, keys, count_dev, cap, xy, lam,
-                       costs, neg, inc_keys, bi);
-    size_t tb = temp_bytes;
-    hipError_t e = sort_keys(temp, tb, inc_keys, inc_sorted, 2 * cap, std::min(64, bv + bi), st);
-    if (e != hipSuccess) return e;
+                       costs, neg);
     // deg[0] = 0, deg[v + 1] = kIncSpare + incidences of v: its inclusive sum
     // is every list's start including the free slots
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, st, deg, (int64_t)1, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, deg + 1, n, kIncSpare);
-    hipLaunchKernelGGL(k_inc_split, dim3(blocks_for(2 * cap, kBlock)), dim3(kBlock), 0, st, inc_sorted, count_dev, bi,
+    hipLaunchKernelGGL(k_inc_count, dim3(blocks_for(cap, kBlock)), dim3(kBlock), 0, st, keys, count_dev, cap, deg);
+    size_t tb = temp_bytes;
+    hipError_t e = hipcub::DeviceScan::InclusiveSum(temp, tb, deg, start, (int)(n + 1), st);
+    if (e != hipSuccess) return e;
+    // deg[0 .. n) becomes each list's fill cursor, then its length
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, deg, n, 0);
+    hipLaunchKernelGGL(k_inc_place, dim3(blocks_for(cap, kBlock)), dim3(kBlock), 0, st, keys, count_dev, cap, start,
                        deg, inc);
-    tb = temp_bytes;
-    return hipcub::DeviceScan::InclusiveSum(temp, tb, deg, start, (int)(n + 1), st);
+    hipLaunchKernelGGL(k_inc_order, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, start, deg, n, inc);
+    return hipGetLastError();
 }
 
 hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_sorted, unsigned long long *acc,
