@@ -1413,7 +1413,7 @@ __global__ void k_count_active(const Ctrl *ctrls, int64_t ninst, int32_t *out)
 // lane, lane + 64, ... (coalesced column and cost loads, and all the
 // neighbours' Lam and label gathers of the chunk in flight at once) into the
 // wave's LDS; then each lane walks its own row's entries of the chunk there.
-constexpr int kGChunk = 512;
+constexpr int kGChunk = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_graph_step(GraphStepArgs a)
 {
