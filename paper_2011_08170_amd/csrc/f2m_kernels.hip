@@ -1210,7 +1210,7 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
         // among the four smallest (lists are exact, so this holds over the
         // list too).  A row whose buffer overflows in a chunk walks that
         // chunk's run instead.
-        constexpr int kLChunk = 256;
+        constexpr int kLChunk = 512;
         constexpr int kPB = 16;
         constexpr int kJ = kLChunk / 64;
         __shared__ long long sz[kBlock / 64][kLChunk];
@@ -1222,7 +1222,7 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
         __shared__ unsigned long long rneg[kBlock / 64][64];
         __shared__ unsigned int rcnt[kBlock / 64][64];   // (#neg << 16) + #zero of this chunk
         __shared__ unsigned int rbc[kBlock / 64][64];    // candidates of this chunk
-        __shared__ unsigned char rbuf[kBlock / 64][64][kPB];
+        __shared__ unsigned short rbuf[kBlock / 64][64][kPB];
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int64_t grp = blk * (kBlock / 64) + wave, groups = (n + 63) / 64;
         // (without z4p the bound is off; the pointers are chosen first so
@@ -1284,7 +1284,7 @@ __device__ __forceinline__ void update_body(const UpdateArgs &a, const int64_t k
                         }
                         if (z <= rbnd[wave][r]) {
                             const unsigned q = atomicAdd(&rbc[wave][r], 1u);
-                            if (q < (unsigned)kPB) rbuf[wave][r][q] = (unsigned char)(e - c0);
+                            if (q < (unsigned)kPB) rbuf[wave][r][q] = (unsigned short)(e - c0);
                         }
                     }
                 }
