@@ -277,16 +277,11 @@ hipError_t launch_graph_dual(const Geo &g, const Csr &csr, const int64_t *lam_so
 // max(0, 4th smallest Z of the row) + slack when slack >= 0, else -1)
 hipError_t launch_graph_collect(const Geo &g, const Csr &csr, const int64_t *lam_sorted, int64_t slack,
                                 unsigned long long *count, int2 *out, int64_t cap, hipStream_t st);
-// (lo, hi) node pairs -> sorted distinct keys lo * 2^32 + hi in keys_out;
+// (lo, hi) node pairs, both ends below n -> sorted distinct keys
+// lo * 2^32 + hi in keys_out;
 // the distinct count lands in *count_dev; with costs non-null, costs[i] is
 // the exact cost of keys_out[i] from the coordinates xy (same node order)
 size_t pair_sort_temp_bytes(int64_t count);
-// Bulk candidate data for the exact finish from the distinct keys (count on
-// the device, at most cap): exact costs, the negative-reduced-cost bits of
-// the two arcs under alpha = floor(Lam/2), beta = Lam - alpha (xy and lam
-// in the node order of the keys),
-// and every node's incident pair ids in increasing order, each node's list
-// followed by two free slots, as start[n + 1] (int32) and inc[2 * count + 2 * n]
 // The distinct keys (count on the device, at most cap) that are not in the
 // sorted set ex[nex], compacted into out (count in *out_count), with their
 // exact costs
@@ -294,6 +289,12 @@ size_t exclude_temp_bytes(int64_t count);
 hipError_t launch_exclude_keys(const uint64_t *keys, const int64_t *count_dev, int64_t cap, const uint64_t *ex,
                                int64_t nex, const int32_t *xy, uint8_t *flags, uint64_t *out, int64_t *out_count,
                                int32_t *costs, void *temp, size_t temp_bytes, hipStream_t st);
+// Bulk candidate data for the exact finish from the distinct keys (count on
+// the device, at most cap): exact costs, the negative-reduced-cost bits of
+// the two arcs under alpha = floor(Lam/2), beta = Lam - alpha (xy and lam
+// in the node order of the keys), and every node's incident pair ids in
+// increasing order, each node's list followed by two free slots, as
+// start[n + 1] (int32) and inc[2 * count + 2 * n]; deg[n + 1] is scratch
 size_t pair_bulk_temp_bytes(int64_t count, int64_t n);
 hipError_t launch_pair_bulk(const uint64_t *keys, const int64_t *count_dev, int64_t cap, const int32_t *xy,
                             const int64_t *lam, int64_t n, int32_t *costs, uint8_t *neg, int32_t *deg, int32_t *start,

@@ -2648,9 +2648,9 @@ hipError_t launch_knn(const Geo &g, const float4 *col, int K, int32_t *nbr, int6
 }
 
 // Radix sorts of packed keys (the candidate graph's edges, the finish's
-// pairs and incidences): always the one-sweep algorithm (the library's
-// default sorts inputs up to 2^20 keys by block sorts and a dozen or more
-// merge passes, each a launch), over the keys' used bits only.
+// pairs): always the one-sweep algorithm (the library's default sorts inputs
+// up to 2^20 keys by block sorts and a dozen or more merge passes, each a
+// launch), over the keys' used bits only.
 using OnesweepSort = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
                                                 rocprim::default_config, 0>;
 
